@@ -1,0 +1,260 @@
+/*
+ * amrto.h - C ABI of the MI355X (gfx950) hot path for dynamic-AMR SIMP
+ * topology optimisation (Wang, de Sturler, Paulino, "Dynamic Adaptive Mesh
+ * Refinement for Topology Optimization", arXiv:1009.4975).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Status: every function returns int.  0 = AMRTO_OK; negative values are
+ *   errors; AMRTO_NOT_CONVERGED (+1) is a warning whose outputs hold the last
+ *   iterate.  No exception crosses the ABI.  amrto_last_error() returns a
+ *   per-context message for the most recent failure.
+ * - Memory: pointers named *_dev are device pointers owned by the caller
+ *   (for example torch tensors); pointers named *_host or inside mesh structs
+ *   are host pointers, read during the call only.  The context owns its copies
+ *   of mesh data, its coefficient arrays and its solver workspace.  Hot calls
+ *   (apply, pcg, compliance, filter, oc) allocate nothing.
+ * - Streams: all device work is enqueued on the stream given to
+ *   amrto_create().  Calls are asynchronous except those that return host
+ *   scalars (c_host, change_host, stats), which synchronise the stream.
+ * - Mesh: nodes sit on the finest integer lattice (finest element edge 1; an
+ *   element of level l in a tree with max_level L has edge h = 2^(L-l)).
+ *   DOF vectors are node-major interleaved: dof = 3*node + c (c = x, y, z).
+ *   Element local node a = i + 2j + 4k is the vertex at offset (i, j, k).
+ * - Operator (paper Sec. 6, Eq. (6)-(8), supports handled as identity rows):
+ *       A~ = F T^T K T F + (I - F)
+ *   K = sum_e c_e G_e^T K0 G_e with c_e = (Emin + rho_e^p (E0 - Emin)) h_e
+ *   (Sec. 3, Eq. (2)); T interpolates hanging DOFs from their masters
+ *   (Eq. (6)); F masks out hanging and supported DOFs.  Rows of hanging and
+ *   supported DOFs are the identity.
+ */
+#ifndef AMRTO_H
+#define AMRTO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  AMRTO_OK = 0,
+  AMRTO_NOT_CONVERGED = 1,
+  AMRTO_EINVAL = -1,     /* bad argument, size or mesh table */
+  AMRTO_EHIP = -2,       /* a HIP runtime call failed */
+  AMRTO_ENOMEM = -3,     /* device or host allocation failed */
+  AMRTO_EBREAKDOWN = -4, /* p^T A p <= 0, NaN or Inf inside a Krylov solve */
+  AMRTO_ESTATE = -5      /* call out of order (no mesh, no density, ...) */
+};
+
+/* Precision of the element contraction and of the vectors it reads/writes. */
+enum {
+  AMRTO_FP64 = 0, /* FP64 vectors, FP64 contraction */
+  AMRTO_FP32 = 1, /* FP32 vectors, FP32 contraction */
+  AMRTO_BF16 = 2  /* FP32 vectors, BF16 operands with FP32 accumulation */
+};
+
+enum { AMRTO_PRECOND_JACOBI = 0 };
+enum { AMRTO_FILTER_SENSITIVITY = 0, AMRTO_FILTER_DENSITY = 1 };
+
+typedef struct amrto_ctx amrto_ctx;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`; `hip_stream` (hipStream_t, may be
+ * NULL for the null stream) is used by every later call.  *ctx receives the
+ * handle.  Errors: EINVAL (ctx NULL, bad device), EHIP. */
+int amrto_create(amrto_ctx** ctx, int device, void* hip_stream);
+/* Free all device memory owned by the context.  NULL is accepted. */
+int amrto_destroy(amrto_ctx* ctx);
+/* Message of the most recent error on this context ("" if none).  The string
+ * is owned by the context and valid until the next call on it. */
+const char* amrto_last_error(const amrto_ctx* ctx);
+/* Replace the stream used by later calls. */
+int amrto_set_stream(amrto_ctx* ctx, void* hip_stream);
+
+/* SIMP material law E(rho) = Emin + rho^p (E0 - Emin) (Sec. 3, Eq. (2);
+ * Emin plays the role of the density floor rho_o^p) and Poisson ratio nu,
+ * which fixes the unit-cube element matrix K0.  Defaults: 1, 1e-9, 0.3, 3.
+ * Errors: EINVAL (E0 <= Emin, Emin < 0, nu outside (-1, 0.5), p < 1). */
+int amrto_set_material(amrto_ctx* ctx, double E0, double Emin, double nu, double p);
+
+/* ------------------------------------------------------------------ mesh */
+
+/* A mesh as host arrays (copied by amrto_upload_mesh).
+ * Uniform brick: elem_nodes == NULL; dims gives the element counts, nodes and
+ * elements are numbered lexicographically with x fastest, every element has
+ * h = 1 and there are no hanging nodes (n_hang must be 0).
+ * Octree: elem_nodes[8*e + a] gives the node of local vertex a; elem_level
+ * gives levels (h_e = 2^(max_level - level)); node_xyz gives lattice
+ * coordinates; elements should be in space-filling-curve order for locality.
+ * Hanging nodes (Eq. (6)): hang_node[i] is interpolated as
+ *   u[hang_node[i]] = sum_{k in [hang_ptr[i], hang_ptr[i+1])} hang_w[k] u[hang_master[k]],
+ * masters must not be hanging themselves (chains resolved by the caller).
+ * dof_fixed[3*n + c] != 0 marks a supported DOF (u = 0 there, Eq. (1)). */
+typedef struct {
+  int32_t n_nodes;
+  int32_t n_elems;
+  int32_t dims[3];            /* finest-lattice extents in elements */
+  int32_t max_level;          /* 0 for a uniform brick */
+  const int32_t* node_xyz;    /* [3*n_nodes] or NULL for a uniform brick */
+  const int32_t* elem_nodes;  /* [8*n_elems] or NULL for a uniform brick */
+  const int8_t* elem_level;   /* [n_elems] or NULL (all max_level) */
+  int32_t n_hang;
+  const int32_t* hang_node;   /* [n_hang] */
+  const int32_t* hang_ptr;    /* [n_hang + 1] */
+  const int32_t* hang_master; /* [hang_ptr[n_hang]] */
+  const double* hang_w;       /* [hang_ptr[n_hang]] */
+  const uint8_t* dof_fixed;   /* [3*n_nodes] */
+} amrto_mesh;
+
+/* Copy a mesh to the device, build the element chunks, node tables, the
+ * hanging-node tables and the solver workspace.  Replaces any earlier mesh
+ * (densities must be set again).  Errors: EINVAL (inconsistent sizes, node
+ * indices out of range, a hanging master that is hanging, a chunk whose node
+ * table cannot fit), ENOMEM, EHIP. */
+int amrto_upload_mesh(amrto_ctx* ctx, const amrto_mesh* mesh);
+
+/* Sizes of the uploaded mesh. */
+int amrto_mesh_info(const amrto_ctx* ctx, int32_t* n_nodes, int32_t* n_elems, int32_t* n_chunks);
+
+/* Element densities rho_dev[n_elems] (FP64, caller-owned, read only): computes
+ * c_e (Eq. (2) scaled by h_e), the exact diagonal of A~ (Jacobi, the diagonal
+ * rescaling of Sec. 5) and the FP32 copies used by mixed precision.
+ * Errors: ESTATE (no mesh), EHIP. */
+int amrto_set_density(amrto_ctx* ctx, const double* rho_dev);
+
+/* ------------------------------------------------------------------ operator */
+
+/* y = A~ x over all 3*n_nodes DOFs (Sec. 6, Eq. (8)).  prec = AMRTO_FP64:
+ * x_dev, y_dev are double; AMRTO_FP32 / AMRTO_BF16: float.  x and y must not
+ * alias.  Errors: ESTATE, EINVAL (prec). */
+int amrto_apply(amrto_ctx* ctx, const void* x_dev, void* y_dev, int prec);
+
+/* b = F T^T f: condense a consistent load on all nodes onto unconstrained
+ * DOFs (right-hand side of Eq. (7)) and zero supported/hanging entries. */
+int amrto_project_rhs(amrto_ctx* ctx, const double* f_dev, double* b_dev);
+
+/* u = T u~: recover hanging DOFs from their masters (Eq. (9)); unconstrained
+ * entries are copied.  u_dev and ut_dev may alias. */
+int amrto_recover(amrto_ctx* ctx, const double* ut_dev, double* u_dev);
+
+/* Diagonal of A~ (as used by the Jacobi preconditioner) into diag_dev[3n]. */
+int amrto_get_diag(amrto_ctx* ctx, double* diag_dev);
+
+/* ------------------------------------------------------------------ solve */
+
+typedef struct {
+  double rtol;        /* stop when ||b - A~ u||_2 <= rtol ||b||_2 (default 1e-8) */
+  int32_t max_it;     /* iteration cap of the (inner) CG (default 20000) */
+  int32_t precond;    /* AMRTO_PRECOND_JACOBI */
+  int32_t inner_prec; /* AMRTO_FP64: plain PCG; FP32/BF16: iterative refinement */
+  double inner_rtol;  /* relative tolerance of each inner solve (default 1e-3) */
+  int32_t max_outer;  /* refinement steps cap (default 50) */
+  int32_t check_every;/* iterations between host convergence checks (default 16) */
+  const double* Z_dev;/* optional coarse space, column-major [3n x k] (NULL: none) */
+  int32_t k;          /* columns of Z_dev */
+} amrto_solve_opts;
+
+typedef struct {
+  int32_t iters;       /* total CG iterations (inner iterations summed) */
+  int32_t outer;       /* refinement steps (0 for plain FP64) */
+  double rel_res;      /* true FP64 ||b - A~ u|| / ||b|| at exit */
+  double ms;           /* wall time of the call */
+} amrto_solve_stats;
+
+/* Fill opts with the defaults above. */
+void amrto_solve_opts_default(amrto_solve_opts* opts);
+
+/* Solve A~ u~ = b by Jacobi-preconditioned conjugate gradients (FP64), or by
+ * iterative refinement with an FP64 residual around FP32/BF16 inner PCG.
+ * u_dev: in = initial guess (its hanging and supported entries are ignored),
+ * out = u = T u~ with hanging DOFs recovered (Eq. (9)).  b_dev = F T^T f.
+ * With Z_dev, M^-1 = D^-1 + Z (Z^T A~ Z)^-1 Z^T (an SPD two-level
+ * preconditioner).  Returns NOT_CONVERGED when the cap is reached; EBREAKDOWN
+ * on p^T A p <= 0 or non-finite values. */
+int amrto_pcg(amrto_ctx* ctx, const double* b_dev, double* u_dev,
+              const amrto_solve_opts* opts, amrto_solve_stats* stats);
+
+/* ------------------------------------------------------------------ design */
+
+/* Compliance c = f^T u (Eq. (1)) into *c_host (may be NULL) and, if dc_dev is
+ * not NULL, dc_e = -p rho_e^(p-1) (E0 - Emin) h_e u_e^T K0 u_e (the
+ * self-adjoint sensitivity; Sec. 3).  u_dev: all DOFs, hanging recovered. */
+int amrto_compliance(amrto_ctx* ctx, const double* u_dev, const double* f_dev,
+                     const double* rho_dev, double* c_host, double* dc_dev);
+
+/* Filters of Sec. 6 with H_de = max(rmin - |x_d - x_e|, 0) between element
+ * centres (Eq. (4)) and volume weights (Eq. (5)):
+ *  SENSITIVITY: out_e = sum_d rho_d H V_d in_d / (max(rho_e, 1e-3) sum_d H V_d)
+ *  DENSITY:     out_e = sum_d H V_d in_d / sum_d H V_d
+ * rho_dev is ignored in DENSITY mode.  in/out must not alias. */
+int amrto_filter(amrto_ctx* ctx, int mode, double rmin, const double* in_dev,
+                 const double* rho_dev, double* out_dev);
+
+/* Optimality Criteria step (Sec. 3): rho_new = clamp(rho (-dc/(lam V_e))^eta,
+ * max(rho_min, rho - move), min(1, rho + move)) with lam such that
+ * sum rho_new V_e = volfrac * sum V_e (k-ary search on log lam to relative
+ * width 1e-13).  *change_host (may be NULL) = max |rho_new - rho|;
+ * *lam_host (may be NULL) = lam. */
+int amrto_oc_update(amrto_ctx* ctx, const double* rho_dev, const double* dc_dev,
+                    double volfrac, double move, double eta, double rho_min,
+                    double* rho_new_dev, double* change_host, double* lam_host);
+
+/* ------------------------------------------------------------------ octree (host) */
+
+typedef struct amrto_octree amrto_octree;
+
+/* Plane or line of the lattice: axis a is pinned to at[a] when has[a] != 0. */
+typedef struct {
+  int32_t has[3];
+  int32_t at[3];
+} amrto_region;
+
+/* A tree of base[0] x base[1] x base[2] level-0 leaves, max_level levels. */
+int amrto_octree_create(amrto_octree** t, const int32_t base[3], int32_t max_level);
+int amrto_octree_destroy(amrto_octree* t);
+/* Leaves in Morton order (the order every per-leaf array uses). */
+int32_t amrto_octree_n_leaves(const amrto_octree* t);
+int amrto_octree_leaves(const amrto_octree* t, int8_t* level, int32_t* anchor /*[3n]*/);
+/* Split every leaf with marks[i] != 0 (below max_level) into 8 children. */
+int amrto_octree_refine(amrto_octree* t, const uint8_t* marks);
+/* Level-one closure (Sec. 6): refine leaves that share a face or an edge
+ * with a leaf two or more levels finer, until none remain. */
+int amrto_octree_balance(amrto_octree* t);
+/* One adaptation of Sec. 4 with rho per current leaf: marking (solid if
+ * rho >= rho_s; refine if solid or a solid centre lies within r_amr),
+ * sweep 1 (whole families only), refinement plus closure, sweep 2 (no
+ * level-two incompatibility from a derefinement), derefinement.  rho_new
+ * (caller buffer of at least n_new leaves; query the count with
+ * amrto_octree_adapt_count first) receives transferred densities: children
+ * inherit, parents average.  src_first/src_count (per new leaf) index the old
+ * leaves a new leaf came from (for displacement transfer). */
+int amrto_octree_adapt(amrto_octree* t, const double* rho, double rho_s, double r_amr,
+                       int32_t* n_new);
+int amrto_octree_adapt_result(const amrto_octree* t, double* rho_new, int32_t* src_first,
+                              int32_t* src_count);
+/* Build the finite-element mesh of the current leaves: nodes (Morton or
+ * lexicographic order), connectivity, hanging-node interpolation with chains
+ * resolved (Eq. (6)), supported DOFs from `fixed` regions, and the consistent
+ * load on all nodes: kind 0 = line (edge length / 2 per end), kind 1 = face
+ * (area / 4 per corner), scaled to `total` on component `comp`.
+ * lexicographic != 0 numbers nodes with x fastest (required for a uniform
+ * brick upload). */
+int amrto_octree_build_mesh(amrto_octree* t, int32_t n_fixed, const amrto_region* fixed,
+                            const amrto_region* load_region, int32_t load_kind,
+                            int32_t load_comp, double load_total, int32_t lexicographic);
+int amrto_octree_mesh_sizes(const amrto_octree* t, int32_t* n_nodes, int32_t* n_elems,
+                            int32_t* n_hang, int32_t* n_hang_entries);
+int amrto_octree_mesh_export(const amrto_octree* t, int32_t* node_xyz, int32_t* elem_nodes,
+                             int8_t* elem_level, int32_t* hang_node, int32_t* hang_ptr,
+                             int32_t* hang_master, double* hang_w, uint8_t* dof_fixed,
+                             double* f_load);
+/* Evaluate a nodal field of the previous mesh (kept by adapt) at the nodes
+ * of the current mesh: u_new = trilinear interpolation on the old leaves. */
+int amrto_octree_transfer_nodal(const amrto_octree* t, const double* u_old, double* u_new);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMRTO_H */

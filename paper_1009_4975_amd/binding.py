@@ -1,0 +1,372 @@
+"""ctypes binding of the amrto C ABI (``include/amrto.h``).
+
+Argument marshalling only: device buffers are torch tensors on the HIP device
+(their ``data_ptr()`` is passed through), host arrays are numpy arrays.  Every
+computation happens inside ``libamrto.so``; if the library has not been built
+the loader raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libamrto.so")
+
+FP64, FP32, BF16 = 0, 1, 2
+FILTER_SENSITIVITY, FILTER_DENSITY = 0, 1
+STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EHIP", -3: "ENOMEM", -4: "EBREAKDOWN", -5: "ESTATE"}
+
+_p = C.c_void_p
+_i32p = C.POINTER(C.c_int32)
+
+
+class AmrtoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class MeshStruct(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_elems", C.c_int32), ("dims", C.c_int32 * 3),
+                ("max_level", C.c_int32), ("node_xyz", _p), ("elem_nodes", _p), ("elem_level", _p),
+                ("n_hang", C.c_int32), ("hang_node", _p), ("hang_ptr", _p), ("hang_master", _p),
+                ("hang_w", _p), ("dof_fixed", _p)]
+
+
+class Region(C.Structure):
+    _fields_ = [("has", C.c_int32 * 3), ("at", C.c_int32 * 3)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("max_it", C.c_int32), ("precond", C.c_int32),
+                ("inner_prec", C.c_int32), ("inner_rtol", C.c_double), ("max_outer", C.c_int32),
+                ("check_every", C.c_int32), ("Z_dev", _p), ("k", C.c_int32)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("outer", C.c_int32), ("rel_res", C.c_double), ("ms", C.c_double)]
+
+
+_SIGS = {
+    "amrto_create": (C.c_int, [C.POINTER(_p), C.c_int, _p]),
+    "amrto_destroy": (C.c_int, [_p]),
+    "amrto_last_error": (C.c_char_p, [_p]),
+    "amrto_set_stream": (C.c_int, [_p, _p]),
+    "amrto_set_material": (C.c_int, [_p, C.c_double, C.c_double, C.c_double, C.c_double]),
+    "amrto_upload_mesh": (C.c_int, [_p, C.POINTER(MeshStruct)]),
+    "amrto_mesh_info": (C.c_int, [_p, _i32p, _i32p, _i32p]),
+    "amrto_set_density": (C.c_int, [_p, _p]),
+    "amrto_apply": (C.c_int, [_p, _p, _p, C.c_int]),
+    "amrto_project_rhs": (C.c_int, [_p, _p, _p]),
+    "amrto_recover": (C.c_int, [_p, _p, _p]),
+    "amrto_get_diag": (C.c_int, [_p, _p]),
+    "amrto_solve_opts_default": (None, [C.POINTER(SolveOpts)]),
+    "amrto_pcg": (C.c_int, [_p, _p, _p, C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
+    "amrto_compliance": (C.c_int, [_p, _p, _p, _p, C.POINTER(C.c_double), _p]),
+    "amrto_filter": (C.c_int, [_p, C.c_int, C.c_double, _p, _p, _p]),
+    "amrto_oc_update": (C.c_int, [_p, _p, _p, C.c_double, C.c_double, C.c_double, C.c_double, _p,
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "amrto_octree_create": (C.c_int, [C.POINTER(_p), C.POINTER(C.c_int32), C.c_int32]),
+    "amrto_octree_destroy": (C.c_int, [_p]),
+    "amrto_octree_n_leaves": (C.c_int32, [_p]),
+    "amrto_octree_leaves": (C.c_int, [_p, _p, _p]),
+    "amrto_octree_refine": (C.c_int, [_p, _p]),
+    "amrto_octree_balance": (C.c_int, [_p]),
+    "amrto_octree_adapt": (C.c_int, [_p, _p, C.c_double, C.c_double, _i32p]),
+    "amrto_octree_adapt_result": (C.c_int, [_p, _p, _p, _p]),
+    "amrto_octree_build_mesh": (C.c_int, [_p, C.c_int32, C.POINTER(Region), C.POINTER(Region), C.c_int32,
+                                          C.c_int32, C.c_double, C.c_int32]),
+    "amrto_octree_mesh_sizes": (C.c_int, [_p, _i32p, _i32p, _i32p, _i32p]),
+    "amrto_octree_mesh_export": (C.c_int, [_p] + [_p] * 9),
+    "amrto_octree_transfer_nodal": (C.c_int, [_p, _p, _p]),
+}
+
+_LIB = None
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+def load(path: str = LIB_PATH):
+    """Load libamrto.so (after torch, so both share one HIP runtime)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    import torch  # noqa: F401  (maps torch's HIP runtime first)
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           f"or python -m paper_1009_4975_amd.build")
+    lib = C.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        assert t.flags["C_CONTIGUOUS"]
+        return t.ctypes.data
+    assert t.is_contiguous(), "device buffers must be contiguous"
+    return t.data_ptr()
+
+
+def _dev(t, dtype=None):
+    import torch
+    assert isinstance(t, torch.Tensor) and t.is_cuda, "expected a device tensor"
+    if dtype is not None:
+        assert t.dtype == dtype, f"expected {dtype}, got {t.dtype}"
+    assert t.is_contiguous()
+    return t.data_ptr()
+
+
+# ---------------------------------------------------------------------- mesh
+@dataclass
+class MeshArrays:
+    """Host arrays of a mesh as produced by the octree (``Octree.mesh``)."""
+    dims: tuple
+    max_level: int
+    node_xyz: np.ndarray          # (nn, 3) int32
+    elem_nodes: np.ndarray        # (ne, 8) int32
+    elem_level: np.ndarray        # (ne,) int8
+    hang_node: np.ndarray         # (nh,) int32
+    hang_ptr: np.ndarray          # (nh+1,) int32
+    hang_master: np.ndarray       # int32
+    hang_w: np.ndarray            # float64
+    dof_fixed: np.ndarray         # (3 nn,) uint8
+    f_load: np.ndarray            # (3 nn,) float64
+    uniform: bool = False
+
+    @property
+    def n_nodes(self):
+        return len(self.node_xyz)
+
+    @property
+    def n_elems(self):
+        return len(self.elem_level)
+
+    def struct(self):
+        keep = []
+
+        def arr(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            keep.append(a)
+            return a.ctypes.data
+
+        m = MeshStruct()
+        m.n_nodes = self.n_nodes
+        m.n_elems = self.n_elems
+        m.dims[:] = list(self.dims)
+        m.max_level = self.max_level
+        m.node_xyz = None if self.uniform else arr(self.node_xyz, np.int32)
+        m.elem_nodes = None if self.uniform else arr(self.elem_nodes, np.int32)
+        m.elem_level = arr(self.elem_level, np.int8)
+        m.n_hang = 0 if self.uniform else len(self.hang_node)
+        m.hang_node = arr(self.hang_node, np.int32)
+        m.hang_ptr = arr(self.hang_ptr, np.int32)
+        m.hang_master = arr(self.hang_master, np.int32)
+        m.hang_w = arr(self.hang_w, np.float64)
+        m.dof_fixed = arr(self.dof_fixed, np.uint8)
+        return m, keep
+
+
+def _region(where: dict) -> Region:
+    r = Region()
+    axes = {"x": 0, "y": 1, "z": 2}
+    for k, v in where.items():
+        r.has[axes[k]] = 1
+        r.at[axes[k]] = int(v)
+    return r
+
+
+class Octree:
+    """Host octree (refine, closure, adapt, mesh build) in libamrto.so."""
+
+    def __init__(self, base, max_level):
+        self.lib = load()
+        self.h = _p()
+        b = (C.c_int32 * 3)(*base)
+        self._chk(self.lib.amrto_octree_create(C.byref(self.h), b, int(max_level)))
+        self.base = tuple(base)
+        self.max_level = int(max_level)
+        self.dims = tuple(int(x) << self.max_level for x in base)
+
+    def _chk(self, rc):
+        if rc < 0:
+            raise AmrtoError(rc, "octree call failed")
+        return rc
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.h.value:
+            self.lib.amrto_octree_destroy(self.h)
+            self.h = _p()
+
+    def leaves(self):
+        n = self.lib.amrto_octree_n_leaves(self.h)
+        lv = np.zeros(n, np.int8)
+        an = np.zeros((n, 3), np.int32)
+        self._chk(self.lib.amrto_octree_leaves(self.h, lv.ctypes.data, an.ctypes.data))
+        return lv.astype(np.int64), an.astype(np.int64)
+
+    def refine(self, marks):
+        m = np.ascontiguousarray(np.asarray(marks, dtype=np.uint8))
+        assert len(m) == self.lib.amrto_octree_n_leaves(self.h)
+        self._chk(self.lib.amrto_octree_refine(self.h, m.ctypes.data))
+
+    def balance(self):
+        self._chk(self.lib.amrto_octree_balance(self.h))
+
+    def adapt(self, rho, rho_s=0.5, r_amr=1.5):
+        r = np.ascontiguousarray(rho, dtype=np.float64)
+        assert len(r) == self.lib.amrto_octree_n_leaves(self.h)
+        n = C.c_int32()
+        self._chk(self.lib.amrto_octree_adapt(self.h, r.ctypes.data, rho_s, r_amr, C.byref(n)))
+        out = np.zeros(n.value)
+        self._chk(self.lib.amrto_octree_adapt_result(self.h, out.ctypes.data, None, None))
+        return out
+
+    def build_mesh(self, fixed, load, lexicographic=False) -> MeshArrays:
+        regs = (Region * max(1, len(fixed)))(*[_region(w) for w in fixed])
+        lr = _region(load["where"])
+        kind = 0 if load["kind"] == "line" else 1
+        self._chk(self.lib.amrto_octree_build_mesh(self.h, len(fixed), regs, C.byref(lr), kind,
+                                                   int(load["comp"]), float(load["total"]),
+                                                   1 if lexicographic else 0))
+        nn, ne, nh, nhe = (C.c_int32() for _ in range(4))
+        self._chk(self.lib.amrto_octree_mesh_sizes(self.h, C.byref(nn), C.byref(ne), C.byref(nh), C.byref(nhe)))
+        nn, ne, nh, nhe = nn.value, ne.value, nh.value, nhe.value
+        xyz = np.zeros((nn, 3), np.int32)
+        en = np.zeros((ne, 8), np.int32)
+        lv = np.zeros(ne, np.int8)
+        hn = np.zeros(nh, np.int32)
+        hp = np.zeros(nh + 1, np.int32)
+        hm = np.zeros(nhe, np.int32)
+        hw = np.zeros(nhe, np.float64)
+        fx = np.zeros(3 * nn, np.uint8)
+        fl = np.zeros(3 * nn, np.float64)
+        self._chk(self.lib.amrto_octree_mesh_export(self.h, *[a.ctypes.data for a in (xyz, en, lv, hn, hp, hm, hw,
+                                                                                          fx, fl)]))
+        return MeshArrays(self.dims, self.max_level, xyz, en, lv, hn, hp, hm, hw, fx, fl,
+                          uniform=False)
+
+    def transfer_nodal(self, u_old: np.ndarray, n_new_nodes: int) -> np.ndarray:
+        u_old = np.ascontiguousarray(u_old, dtype=np.float64)
+        out = np.zeros(3 * n_new_nodes)
+        self._chk(self.lib.amrto_octree_transfer_nodal(self.h, u_old.ctypes.data, out.ctypes.data))
+        return out
+
+
+def uniform_mesh(dims, fixed, load) -> MeshArrays:
+    """A uniform brick (implicit connectivity on the device): the octree with
+    one level and lexicographic node numbering supplies supports and loads."""
+    t = Octree(dims, 0)
+    m = t.build_mesh(fixed, load, lexicographic=True)
+    m.uniform = True
+    return m
+
+
+# ---------------------------------------------------------------------- context
+class Context:
+    """A device context: mesh, coefficients, preconditioner and workspace."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.lib = load()
+        self.torch = torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        self.h = _p()
+        rc = self.lib.amrto_create(C.byref(self.h), int(device), _p(stream.cuda_stream))
+        if rc != 0:
+            raise AmrtoError(rc, "amrto_create failed")
+        self.device = device
+        self.mesh: Optional[MeshArrays] = None
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.h.value:
+            self.lib.amrto_destroy(self.h)
+            self.h = _p()
+
+    def _chk(self, rc, allow_not_converged=False):
+        if rc < 0 or (rc > 0 and not allow_not_converged):
+            raise AmrtoError(rc, self.lib.amrto_last_error(self.h).decode())
+        return rc
+
+    def set_material(self, E0=1.0, Emin=1e-9, nu=0.3, p=3.0):
+        self._chk(self.lib.amrto_set_material(self.h, E0, Emin, nu, p))
+
+    def upload_mesh(self, mesh: MeshArrays):
+        s, keep = mesh.struct()
+        self._chk(self.lib.amrto_upload_mesh(self.h, C.byref(s)))
+        del keep
+        self.mesh = mesh
+
+    def info(self):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        self._chk(self.lib.amrto_mesh_info(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return dict(n_nodes=a.value, n_elems=b.value, n_chunks=c.value)
+
+    def set_density(self, rho):
+        self._chk(self.lib.amrto_set_density(self.h, _dev(rho, self.torch.float64)))
+
+    def apply(self, x, y, prec=FP64):
+        dt = self.torch.float64 if prec == FP64 else self.torch.float32
+        self._chk(self.lib.amrto_apply(self.h, _dev(x, dt), _dev(y, dt), int(prec)))
+
+    def project_rhs(self, f, b):
+        self._chk(self.lib.amrto_project_rhs(self.h, _dev(f, self.torch.float64), _dev(b, self.torch.float64)))
+
+    def recover(self, ut, u):
+        self._chk(self.lib.amrto_recover(self.h, _dev(ut, self.torch.float64), _dev(u, self.torch.float64)))
+
+    def diag(self, out):
+        self._chk(self.lib.amrto_get_diag(self.h, _dev(out, self.torch.float64)))
+
+    def pcg(self, b, u, rtol=1e-8, max_it=20000, inner_prec=FP64, inner_rtol=1e-3, max_outer=50,
+            check_every=16, Z=None, k=0, allow_not_converged=False):
+        o = SolveOpts()
+        self.lib.amrto_solve_opts_default(C.byref(o))
+        o.rtol, o.max_it, o.inner_prec, o.inner_rtol = rtol, max_it, inner_prec, inner_rtol
+        o.max_outer, o.check_every = max_outer, check_every
+        if Z is not None:
+            o.Z_dev = _dev(Z, self.torch.float64)
+            o.k = int(k)
+        st = SolveStats()
+        rc = self.lib.amrto_pcg(self.h, _dev(b, self.torch.float64), _dev(u, self.torch.float64), C.byref(o),
+                                C.byref(st))
+        self._chk(rc, allow_not_converged=allow_not_converged)
+        return dict(iters=st.iters, outer=st.outer, rel_res=st.rel_res, ms=st.ms, status=STATUS[rc])
+
+    def compliance(self, u, f, rho=None, dc=None):
+        c = C.c_double()
+        self._chk(self.lib.amrto_compliance(self.h, _dev(u, self.torch.float64), _dev(f, self.torch.float64),
+                                            None if rho is None else _dev(rho, self.torch.float64),
+                                            C.byref(c), None if dc is None else _dev(dc, self.torch.float64)))
+        return c.value
+
+    def sensitivity(self, u, rho, dc):
+        self._chk(self.lib.amrto_compliance(self.h, _dev(u, self.torch.float64), None,
+                                            _dev(rho, self.torch.float64), None, _dev(dc, self.torch.float64)))
+
+    def filter(self, mode, rmin, inp, out, rho=None):
+        self._chk(self.lib.amrto_filter(self.h, int(mode), float(rmin), _dev(inp, self.torch.float64),
+                                        None if rho is None else _dev(rho, self.torch.float64),
+                                        _dev(out, self.torch.float64)))
+
+    def oc_update(self, rho, dc, rho_new, volfrac, move=0.2, eta=0.5, rho_min=1e-3):
+        ch, lam = C.c_double(), C.c_double()
+        self._chk(self.lib.amrto_oc_update(self.h, _dev(rho, self.torch.float64), _dev(dc, self.torch.float64),
+                                           volfrac, move, eta, rho_min, _dev(rho_new, self.torch.float64),
+                                           C.byref(ch), C.byref(lam)))
+        return ch.value, lam.value

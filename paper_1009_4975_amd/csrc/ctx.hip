@@ -1,0 +1,311 @@
+// Context, material, mesh upload and the small host helpers of the amrto
+// library.
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace amrto {
+
+// Unit-cube Q1 element matrix from the index form of linear elasticity,
+//   K[(a,c),(b,d)] = int lam dN_a/dx_c dN_b/dx_d + mu dN_a/dx_d dN_b/dx_c
+//                    + mu delta_cd grad N_a . grad N_b,
+// where each integral of trilinear shape-function products factorises into
+// exact one-dimensional integrals (trilinear displacements: paper Sec. 3).
+void k0_unit_cube(double nu, double* K) {
+  const double lam = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  const double mu = 1.0 / (2.0 * (1.0 + nu));
+  auto one_d = [](int ia, int ib, bool da, bool db) -> double {
+    if (da && db) return ia == ib ? 1.0 : -1.0;
+    if (da) return ia ? 0.5 : -0.5;
+    if (db) return ib ? 0.5 : -0.5;
+    return ia == ib ? 1.0 / 3.0 : 1.0 / 6.0;
+  };
+  auto g = [&](int a, int b, int p, int q) {
+    double v = 1.0;
+    for (int ax = 0; ax < 3; ++ax)
+      v *= one_d((a >> ax) & 1, (b >> ax) & 1, ax == p, ax == q);
+    return v;
+  };
+  for (int a = 0; a < 8; ++a)
+    for (int b = 0; b < 8; ++b)
+      for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < 3; ++d) {
+          double v = lam * g(a, b, c, d) + mu * g(a, b, d, c);
+          if (c == d) v += mu * (g(a, b, 0, 0) + g(a, b, 1, 1) + g(a, b, 2, 2));
+          K[(3 * a + c) * 24 + 3 * b + d] = v;
+        }
+}
+
+uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (uint16_t)(u >> 16);
+}
+
+float bf16_to_f32(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+int grid_for(long n, int threads, int cap) {
+  long g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace amrto
+
+using namespace amrto;
+
+template <typename T>
+static void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+template <typename T>
+static hipError_t dalloc(T*& p, size_t n) {
+  dfree(p);
+  if (n == 0) n = 1;
+  return hipMalloc((void**)&p, n * sizeof(T));
+}
+
+static void free_mesh(amrto_ctx* c) {
+  dfree(c->d_fix); dfree(c->d_level); dfree(c->d_elem_nodes);
+  dfree(c->d_chunk_elem); dfree(c->d_chunk_tab); dfree(c->d_chunk_nreg); dfree(c->d_chunk_trip);
+  dfree(c->d_tab_node); dfree(c->d_tab_slot); dfree(c->d_elem_loc); dfree(c->d_trip_hm);
+  dfree(c->d_trip_w); dfree(c->d_shared_node); dfree(c->d_shared_ptr); dfree(c->d_slot_list);
+  dfree(c->d_hang_node); dfree(c->d_hang_ptr); dfree(c->d_hang_master); dfree(c->d_hang_w);
+  dfree(c->d_mt_node); dfree(c->d_mt_ptr); dfree(c->d_mt_h); dfree(c->d_mt_w);
+  c->n_mt = 0;
+  dfree(c->d_partial); dfree(c->d_nb_ptr); dfree(c->d_nb_idx); dfree(c->d_nb_w);
+  dfree(c->d_coef); dfree(c->d_coef_f); dfree(c->d_dinv); dfree(c->d_dinv_f); dfree(c->d_vol);
+  dfree(c->d_r); dfree(c->d_z); dfree(c->d_p); dfree(c->d_q);
+  dfree(c->f_b); dfree(c->f_x); dfree(c->f_r); dfree(c->f_z); dfree(c->f_p); dfree(c->f_q);
+  dfree(c->d_coarse);
+  c->coarse_k = 0;
+  c->filt_rmin = -1.0;
+  c->has_mesh = false;
+  c->has_density = false;
+}
+
+static int upload_material(amrto_ctx* ctx) {
+  k0_unit_cube(ctx->nu, ctx->K0);
+  float kf[576];
+  uint16_t kb[1152];
+  for (int i = 0; i < 576; ++i) {
+    kf[i] = (float)ctx->K0[i];
+    uint16_t hi = f32_to_bf16_rne(kf[i]);
+    float rem = (float)(ctx->K0[i] - (double)bf16_to_f32(hi));
+    kb[i] = hi;
+    kb[576 + i] = f32_to_bf16_rne(rem);
+  }
+  AMRTO_HIP(hipMemcpyAsync(ctx->d_K0, ctx->K0, sizeof(ctx->K0), hipMemcpyHostToDevice, ctx->stream));
+  AMRTO_HIP(hipMemcpyAsync(ctx->d_K0f, kf, sizeof(kf), hipMemcpyHostToDevice, ctx->stream));
+  AMRTO_HIP(hipMemcpyAsync(ctx->d_K0bf, kb, sizeof(kb), hipMemcpyHostToDevice, ctx->stream));
+  AMRTO_HIP(hipStreamSynchronize(ctx->stream));
+  return AMRTO_OK;
+}
+
+extern "C" {
+
+int amrto_create(amrto_ctx** out, int device, void* stream) {
+  if (!out) return AMRTO_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return AMRTO_EINVAL;
+  amrto_ctx* ctx = new (std::nothrow) amrto_ctx();
+  if (!ctx) return AMRTO_ENOMEM;
+  ctx->device = device;
+  ctx->stream = (hipStream_t)stream;
+  if (hipSetDevice(device) != hipSuccess) { delete ctx; return AMRTO_EHIP; }
+  if (hipMalloc((void**)&ctx->d_K0, 576 * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&ctx->d_K0f, 576 * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&ctx->d_K0bf, 1152 * sizeof(uint16_t)) != hipSuccess ||
+      hipMalloc((void**)&ctx->d_part, 8 * RED_BLOCKS * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&ctx->d_scal, S_COUNT * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&ctx->d_oc, OC_WS * sizeof(double)) != hipSuccess ||
+      hipHostMalloc((void**)&ctx->h_scal, S_COUNT * sizeof(double)) != hipSuccess) {
+    amrto_destroy(ctx);
+    return AMRTO_ENOMEM;
+  }
+  int rc = upload_material(ctx);
+  if (rc != AMRTO_OK) { amrto_destroy(ctx); return rc; }
+  *out = ctx;
+  return AMRTO_OK;
+}
+
+int amrto_destroy(amrto_ctx* ctx) {
+  if (!ctx) return AMRTO_OK;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
+  free_mesh(ctx);
+  dfree(ctx->d_K0); dfree(ctx->d_K0f); dfree(ctx->d_K0bf);
+  dfree(ctx->d_part); dfree(ctx->d_scal); dfree(ctx->d_oc);
+  if (ctx->h_scal) (void)hipHostFree(ctx->h_scal);
+  delete ctx;
+  return AMRTO_OK;
+}
+
+const char* amrto_last_error(const amrto_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : "null context";
+}
+
+int amrto_set_stream(amrto_ctx* ctx, void* stream) {
+  if (!ctx) return AMRTO_EINVAL;
+  ctx->stream = (hipStream_t)stream;
+  return AMRTO_OK;
+}
+
+int amrto_set_material(amrto_ctx* ctx, double E0, double Emin, double nu, double p) {
+  if (!ctx) return AMRTO_EINVAL;
+  if (!(E0 > Emin) || !(Emin >= 0.0) || !(nu > -1.0 && nu < 0.5) || !(p >= 1.0))
+    return ctx->fail(AMRTO_EINVAL, "amrto_set_material: need E0 > Emin >= 0, -1 < nu < 0.5, p >= 1");
+  AMRTO_HIP(hipSetDevice(ctx->device));
+  ctx->E0 = E0; ctx->Emin = Emin; ctx->nu = nu; ctx->p = p;
+  ctx->has_density = false;
+  return upload_material(ctx);
+}
+
+int amrto_upload_mesh(amrto_ctx* ctx, const amrto_mesh* m) {
+  if (!ctx) return AMRTO_EINVAL;
+  if (!m || m->n_nodes <= 0 || m->n_elems <= 0 || !m->dof_fixed)
+    return ctx->fail(AMRTO_EINVAL, "amrto_upload_mesh: empty mesh or missing dof_fixed");
+  AMRTO_HIP(hipSetDevice(ctx->device));
+  AMRTO_HIP(hipStreamSynchronize(ctx->stream));
+  free_mesh(ctx);
+  const bool uni = (m->elem_nodes == nullptr);
+  if (uni) {
+    long nx = m->dims[0], ny = m->dims[1], nz = m->dims[2];
+    if (nx <= 0 || ny <= 0 || nz <= 0 || nx * ny * nz != m->n_elems ||
+        (nx + 1) * (ny + 1) * (nz + 1) != m->n_nodes || m->n_hang != 0)
+      return ctx->fail(AMRTO_EINVAL, "amrto_upload_mesh: uniform brick sizes inconsistent");
+    ctx->nx = (int)nx; ctx->ny = (int)ny; ctx->nz = (int)nz;
+  } else {
+    if (!m->node_xyz) return ctx->fail(AMRTO_EINVAL, "amrto_upload_mesh: octree mesh needs node_xyz");
+    for (long i = 0; i < 8L * m->n_elems; ++i)
+      if (m->elem_nodes[i] < 0 || m->elem_nodes[i] >= m->n_nodes)
+        return ctx->fail(AMRTO_EINVAL, "amrto_upload_mesh: element node index out of range");
+    ctx->nx = m->dims[0]; ctx->ny = m->dims[1]; ctx->nz = m->dims[2];
+  }
+  if (m->max_level < 0 || m->max_level > 16)
+    return ctx->fail(AMRTO_EINVAL, "amrto_upload_mesh: max_level outside [0, 16]");
+  ctx->uniform = uni;
+  ctx->n_nodes = m->n_nodes;
+  ctx->n_elems = m->n_elems;
+  ctx->max_level = m->max_level;
+  const long n3 = 3L * m->n_nodes;
+
+  // supports: one byte per node, bit c for DOF c
+  std::vector<uint8_t> fix(m->n_nodes, 0);
+  for (long i = 0; i < n3; ++i)
+    if (m->dof_fixed[i]) fix[i / 3] |= (uint8_t)(1u << (i % 3));
+  AMRTO_HIP(dalloc(ctx->d_fix, m->n_nodes));
+  AMRTO_HIP(hipMemcpy(ctx->d_fix, fix.data(), fix.size(), hipMemcpyHostToDevice));
+
+  // element levels and volumes
+  std::vector<int8_t> lev(m->n_elems, (int8_t)m->max_level);
+  if (m->elem_level) std::memcpy(lev.data(), m->elem_level, m->n_elems);
+  for (int8_t l : lev)
+    if (l < 0 || l > m->max_level) return ctx->fail(AMRTO_EINVAL, "amrto_upload_mesh: element level out of range");
+  std::vector<double> vol(m->n_elems);
+  for (int e = 0; e < m->n_elems; ++e) {
+    double h = (double)(1 << (m->max_level - lev[e]));
+    vol[e] = h * h * h;
+  }
+  AMRTO_HIP(dalloc(ctx->d_level, m->n_elems));
+  AMRTO_HIP(hipMemcpy(ctx->d_level, lev.data(), lev.size(), hipMemcpyHostToDevice));
+  AMRTO_HIP(dalloc(ctx->d_vol, m->n_elems));
+  AMRTO_HIP(hipMemcpy(ctx->d_vol, vol.data(), vol.size() * sizeof(double), hipMemcpyHostToDevice));
+  ctx->h_level = lev;
+
+  if (!uni) {
+    ctx->h_node_xyz.assign(m->node_xyz, m->node_xyz + n3);
+    ctx->h_elem_nodes.assign(m->elem_nodes, m->elem_nodes + 8L * m->n_elems);
+    AMRTO_HIP(dalloc(ctx->d_elem_nodes, 8L * m->n_elems));
+    AMRTO_HIP(hipMemcpy(ctx->d_elem_nodes, m->elem_nodes, 8L * m->n_elems * sizeof(int32_t), hipMemcpyHostToDevice));
+    int rc = build_chunks(ctx, m);
+    if (rc != AMRTO_OK) return rc;
+  } else {
+    ctx->h_node_xyz.clear();
+    ctx->h_elem_nodes.clear();
+    ctx->n_chunks = 0; ctx->n_hang = 0; ctx->n_shared = 0; ctx->n_slots = 0;
+  }
+
+  // density-dependent arrays and the solver workspace
+  AMRTO_HIP(dalloc(ctx->d_coef, m->n_elems));
+  AMRTO_HIP(dalloc(ctx->d_coef_f, m->n_elems));
+  AMRTO_HIP(dalloc(ctx->d_dinv, n3));
+  AMRTO_HIP(dalloc(ctx->d_dinv_f, n3));
+  AMRTO_HIP(dalloc(ctx->d_r, n3)); AMRTO_HIP(dalloc(ctx->d_z, n3));
+  AMRTO_HIP(dalloc(ctx->d_p, n3)); AMRTO_HIP(dalloc(ctx->d_q, n3));
+  AMRTO_HIP(dalloc(ctx->f_b, n3)); AMRTO_HIP(dalloc(ctx->f_x, n3)); AMRTO_HIP(dalloc(ctx->f_r, n3)); AMRTO_HIP(dalloc(ctx->f_z, n3));
+  AMRTO_HIP(dalloc(ctx->f_p, n3)); AMRTO_HIP(dalloc(ctx->f_q, n3));
+  ctx->has_mesh = true;
+  return AMRTO_OK;
+}
+
+int amrto_mesh_info(const amrto_ctx* ctx, int32_t* n_nodes, int32_t* n_elems, int32_t* n_chunks) {
+  if (!ctx) return AMRTO_EINVAL;
+  if (n_nodes) *n_nodes = ctx->n_nodes;
+  if (n_elems) *n_elems = ctx->n_elems;
+  if (n_chunks) *n_chunks = ctx->n_chunks;
+  return AMRTO_OK;
+}
+
+int amrto_set_density(amrto_ctx* ctx, const double* rho) {
+  if (!ctx) return AMRTO_EINVAL;
+  if (!ctx->has_mesh) return ctx->fail(AMRTO_ESTATE, "amrto_set_density: no mesh uploaded");
+  if (!rho) return ctx->fail(AMRTO_EINVAL, "amrto_set_density: rho is NULL");
+  AMRTO_HIP(hipSetDevice(ctx->device));
+  int rc = launch_set_density(ctx, rho);
+  if (rc) return rc;
+  rc = launch_diag(ctx);
+  if (rc) return rc;
+  ctx->has_density = true;
+  return AMRTO_OK;
+}
+
+int amrto_get_diag(amrto_ctx* ctx, double* diag) {
+  if (!ctx) return AMRTO_EINVAL;
+  if (!ctx->has_density) return ctx->fail(AMRTO_ESTATE, "amrto_get_diag: density not set");
+  if (!diag) return ctx->fail(AMRTO_EINVAL, "amrto_get_diag: NULL buffer");
+  AMRTO_HIP(hipSetDevice(ctx->device));
+  return launch_recip(ctx, ctx->d_dinv, diag, 3L * ctx->n_nodes);
+}
+
+int amrto_apply(amrto_ctx* ctx, const void* x, void* y, int prec) {
+  if (!ctx) return AMRTO_EINVAL;
+  if (!ctx->has_density) return ctx->fail(AMRTO_ESTATE, "amrto_apply: density not set");
+  if (prec != AMRTO_FP64 && prec != AMRTO_FP32 && prec != AMRTO_BF16)
+    return ctx->fail(AMRTO_EINVAL, "amrto_apply: unknown precision");
+  if (!x || !y || x == y) return ctx->fail(AMRTO_EINVAL, "amrto_apply: x and y must be distinct device buffers");
+  AMRTO_HIP(hipSetDevice(ctx->device));
+  return launch_apply(ctx, x, y, prec);
+}
+
+int amrto_project_rhs(amrto_ctx* ctx, const double* f, double* b) {
+  if (!ctx) return AMRTO_EINVAL;
+  if (!ctx->has_mesh) return ctx->fail(AMRTO_ESTATE, "amrto_project_rhs: no mesh");
+  if (!f || !b || f == b) return ctx->fail(AMRTO_EINVAL, "amrto_project_rhs: f and b must be distinct");
+  AMRTO_HIP(hipSetDevice(ctx->device));
+  return launch_project_rhs(ctx, f, b);
+}
+
+int amrto_recover(amrto_ctx* ctx, const double* ut, double* u) {
+  if (!ctx) return AMRTO_EINVAL;
+  if (!ctx->has_mesh) return ctx->fail(AMRTO_ESTATE, "amrto_recover: no mesh");
+  if (!ut || !u) return ctx->fail(AMRTO_EINVAL, "amrto_recover: NULL buffer");
+  AMRTO_HIP(hipSetDevice(ctx->device));
+  return launch_recover(ctx, ut, u);
+}
+
+}  // extern "C"

@@ -1,0 +1,158 @@
+// Internal declarations of the amrto HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "amrto.h"
+
+#define AMRTO_HIP(call)                                                          \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      return ctx->fail(AMRTO_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    }                                                                            \
+  } while (0)
+
+namespace amrto {
+
+// Uniform-brick apply tile: each workgroup owns UT x UT node columns and a
+// range of node layers; it computes the (UT+1)^2 element columns around them
+// (one element per thread) and marches upwards one element layer at a time.
+constexpr int UT = 15;
+constexpr int UE = UT + 1;  // element columns per tile edge
+constexpr int UN = UT + 2;  // node columns per tile edge (with halo)
+
+// Octree apply chunk: a workgroup takes up to CH_MAX consecutive elements and
+// stages the union of their nodes (plus masters of hanging nodes) in LDS.
+constexpr int CH_MAX = 256;
+constexpr int TAB_MAX = 1024;
+
+// Reductions: fixed grid of partial sums; every consumer re-adds them in the
+// same order, so results are deterministic without a separate finalize pass.
+constexpr int RED_BLOCKS = 256;
+constexpr int RED_THREADS = 256;
+constexpr int OC_WS = 2 + 256 * 256 + 64;
+
+template <typename T>
+struct DevArray {
+  T* p = nullptr;
+  size_t n = 0;
+};
+
+// Scalars of a running Krylov solve (device resident).
+enum ScalarSlot {
+  S_RZ0 = 0,   // r.z, double buffered on iteration parity
+  S_RZ1 = 1,
+  S_BB = 2,    // b.b
+  S_DONE = 3,  // 0 running, 1 converged, 2 breakdown
+  S_ITERS = 4, // iterations completed when the flag was raised
+  S_RR = 5,    // last r.r
+  S_COUNT = 8
+};
+
+}  // namespace amrto
+
+struct amrto_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  double E0 = 1.0, Emin = 1e-9, nu = 0.3, p = 3.0;
+  double K0[576];
+  std::string err;
+
+  // mesh
+  bool has_mesh = false, uniform = false, has_density = false;
+  int n_nodes = 0, n_elems = 0, max_level = 0;
+  int nx = 0, ny = 0, nz = 0;
+  int n_chunks = 0, n_shared = 0, n_slots = 0, n_hang = 0;
+  std::vector<int32_t> h_node_xyz;   // octree: lattice coordinates (host copy)
+  std::vector<int8_t> h_level;
+  std::vector<int32_t> h_elem_nodes;
+
+  // device: material
+  double* d_K0 = nullptr;      // 576
+  float* d_K0f = nullptr;      // 576
+  uint16_t* d_K0bf = nullptr;  // 2 x 576 (hi, lo) bf16 bit patterns
+  // device: mesh
+  uint8_t* d_fix = nullptr;        // per node, bit c = DOF c supported
+  int8_t* d_level = nullptr;       // per element
+  int32_t* d_elem_nodes = nullptr; // octree only
+  // octree chunks
+  int32_t* d_chunk_elem = nullptr;   // [n_chunks + 1] element ranges
+  int32_t* d_chunk_tab = nullptr;    // [n_chunks + 1] table ranges
+  int32_t* d_chunk_nreg = nullptr;   // [n_chunks] regular entries per table
+  int32_t* d_chunk_trip = nullptr;   // [n_chunks + 1] hanging triple ranges
+  int32_t* d_tab_node = nullptr;     // global node per table entry
+  int32_t* d_tab_slot = nullptr;     // -1 exclusive, else partial slot
+  uint16_t* d_elem_loc = nullptr;    // [8 n_elems] table index per local vertex
+  uint32_t* d_trip_hm = nullptr;     // (h_loc << 16) | m_loc
+  double* d_trip_w = nullptr;
+  int32_t* d_shared_node = nullptr;  // [n_shared]
+  int32_t* d_shared_ptr = nullptr;   // [n_shared + 1] into d_slot_list
+  int32_t* d_slot_list = nullptr;    // slots of each shared node in chunk order
+  int32_t* d_hang_node = nullptr;    // [n_hang]
+  int32_t* d_hang_ptr = nullptr;     // [n_hang + 1]
+  int32_t* d_hang_master = nullptr;
+  double* d_hang_w = nullptr;
+  int n_mt = 0;                      // masters that receive hanging loads
+  int32_t* d_mt_node = nullptr;      // [n_mt]
+  int32_t* d_mt_ptr = nullptr;       // [n_mt + 1]
+  int32_t* d_mt_h = nullptr;         // hanging node per entry
+  double* d_mt_w = nullptr;          // weight per entry
+  double* d_partial = nullptr;       // [3 n_slots] (double or float view)
+  // filter neighbour lists (octree), rebuilt when rmin changes
+  double filt_rmin = -1.0;
+  int n_sten = 0;
+  int32_t* d_nb_ptr = nullptr;
+  int32_t* d_nb_idx = nullptr;
+  double* d_nb_w = nullptr;
+
+  // device: density dependent
+  double* d_coef = nullptr;   // c_e
+  float* d_coef_f = nullptr;
+  double* d_dinv = nullptr;   // 1 / diag(A~)
+  float* d_dinv_f = nullptr;
+  double* d_vol = nullptr;    // V_e
+
+  // device: solver workspace
+  double* d_r = nullptr; double* d_z = nullptr; double* d_p = nullptr; double* d_q = nullptr;
+  float* f_b = nullptr; float* f_x = nullptr; float* f_r = nullptr; float* f_z = nullptr; float* f_p = nullptr; float* f_q = nullptr;
+  double* d_part = nullptr;   // reduction partials (4 x RED_BLOCKS)
+  double* d_scal = nullptr;   // scalar slots
+  double* h_scal = nullptr;   // pinned mirror
+  double* d_oc = nullptr;     // OC search workspace
+  double* d_coarse = nullptr; // coarse-space workspace
+  int coarse_k = 0;
+
+  int fail(int code, const std::string& msg) {
+    err = msg;
+    return code;
+  }
+};
+
+namespace amrto {
+
+// apply.hip
+int launch_apply(amrto_ctx* ctx, const void* x, void* y, int prec);
+int launch_diag(amrto_ctx* ctx);
+int build_chunks(amrto_ctx* ctx, const amrto_mesh* m);
+// vec.hip
+int launch_set_density(amrto_ctx* ctx, const double* rho);
+int launch_project_rhs(amrto_ctx* ctx, const double* f, double* b);
+int launch_recover(amrto_ctx* ctx, const double* ut, double* u);
+int launch_recip(amrto_ctx* ctx, const double* a, double* b, long n);
+int launch_apply_bf16(amrto_ctx* ctx, const float* x, float* y, const double* stop);
+int apply_stop(amrto_ctx* ctx, const void* x, void* y, int prec, const double* stop);
+void uniform_grid(const amrto_ctx* ctx, int& tiles_x, int& tiles_y, int& zchunk, int& n_tiles, int& grid);
+template <typename VT>
+void reduce_shared(amrto_ctx* ctx, const VT* x, VT* y, const double* stop);
+// helpers
+void k0_unit_cube(double nu, double* K);  // 24 x 24, E = 1
+uint16_t f32_to_bf16_rne(float f);
+float bf16_to_f32(uint16_t h);
+int grid_for(long n, int threads, int cap);
+
+}  // namespace amrto
