@@ -79,6 +79,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-c3", action="store_true", help="skip the uniform 192x96x96 apply measurement")
     ap.add_argument("--profile-only", action="store_true", help="only the timed steps (for profilers)")
+    ap.add_argument("--c3-only", action="store_true", help="only the uniform 192x96x96 apply measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (--gpus 1); multi-GPU runs are not supported.",
@@ -92,6 +93,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     binding.load()
     dev = lambda a, dt=torch.float64: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    if args.c3_only:
+        print(json.dumps(apply_uniform_bandwidth(torch, binding, synth, dev)), flush=True)
+        return
 
     t0 = time.time()
     case, tree, mesh, rho_h = build_c2(binding, synth)

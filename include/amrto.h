@@ -148,9 +148,12 @@ typedef struct {
   double rtol;        /* stop when ||b - A~ u||_2 <= rtol ||b||_2 (default 1e-8) */
   int32_t max_it;     /* iteration cap of the (inner) CG (default 20000) */
   int32_t precond;    /* AMRTO_PRECOND_JACOBI */
-  int32_t inner_prec; /* AMRTO_FP64: plain PCG; FP32/BF16: iterative refinement */
-  double inner_rtol;  /* relative tolerance of each inner solve (default 1e-3) */
-  int32_t max_outer;  /* refinement steps cap (default 50) */
+  int32_t inner_prec; /* AMRTO_FP64: plain PCG; FP32/BF16: mixed precision with
+                         FP64 reliable updates (FP32 vectors, FP32/BF16 operator) */
+  double inner_rtol;  /* mixed precision: factor by which the FP32 recurrence
+                         residual falls between two FP64 reliable updates
+                         (default 1e-2) */
+  int32_t max_outer;  /* reserved (default 1000) */
   int32_t check_every;/* iterations between host convergence checks (default 16) */
   const double* Z_dev;/* optional coarse space, column-major [3n x k] (NULL: none) */
   int32_t k;          /* columns of Z_dev */
@@ -158,7 +161,7 @@ typedef struct {
 
 typedef struct {
   int32_t iters;       /* total CG iterations (inner iterations summed) */
-  int32_t outer;       /* refinement steps (0 for plain FP64) */
+  int32_t outer;       /* FP64 reliable updates (0 for plain FP64) */
   double rel_res;      /* true FP64 ||b - A~ u|| / ||b|| at exit */
   double ms;           /* wall time of the call */
 } amrto_solve_stats;
@@ -167,7 +170,10 @@ typedef struct {
 void amrto_solve_opts_default(amrto_solve_opts* opts);
 
 /* Solve A~ u~ = b by Jacobi-preconditioned conjugate gradients (FP64), or by
- * iterative refinement with an FP64 residual around FP32/BF16 inner PCG.
+ * the same recurrence in FP32 vectors with an FP32 or BF16 element contraction
+ * whose iterate is folded into an FP64 solution with an FP64 true residual
+ * whenever the recurrence residual has fallen by inner_rtol (reliable
+ * updates); convergence is always judged on the FP64 true residual.
  * u_dev: in = initial guess (its hanging and supported entries are ignored),
  * out = u = T u~ with hanging DOFs recovered (Eq. (9)).  b_dev = F T^T f.
  * With Z_dev, M^-1 = D^-1 + Z (Z^T A~ Z)^-1 Z^T (an SPD two-level

@@ -1,0 +1,251 @@
+// Host-side construction of the octree operator chunks.
+//
+// Every unconstrained node is owned by exactly one chunk: the chunk holding
+// the first element (in space-filling-curve order) that touches it, where an
+// element touches a node if the node is one of its vertices or a master of one
+// of its hanging vertices.  A chunk is a run of consecutive elements plus the
+// halo elements that touch its owned nodes from outside the run, so the chunk
+// sees every contribution to its owned rows and can write them directly: the
+// operator needs one pass, no atomics in global memory and no second
+// reduction pass, and it is deterministic.  Each hanging node is owned (for
+// its identity row) by the chunk of the first element having it as a vertex.
+//
+// Node table order inside a chunk: [owned regular | other regular | owned
+// hanging | other hanging]; hanging interpolation is kept as (hanging entry,
+// master entry, weight) triples.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace amrto {
+
+namespace {
+
+template <typename V>
+hipError_t upload(V*& dst, const std::vector<V>& v) {
+  if (dst) (void)hipFree(dst);
+  dst = nullptr;
+  hipError_t e = hipMalloc((void**)&dst, std::max<size_t>(1, v.size()) * sizeof(V));
+  if (e != hipSuccess) return e;
+  if (!v.empty()) e = hipMemcpy(dst, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice);
+  return e;
+}
+
+struct Tables {
+  std::vector<int32_t> chunk_ent{0}, chunk_tab{0}, chunk_trip{0}, chunk_nown, chunk_nreg, chunk_nhown;
+  std::vector<int32_t> ent_elem, tab_node, tab_hbeg;
+  std::vector<uint16_t> ent_loc;
+  std::vector<uint32_t> trip_hm;
+  std::vector<double> trip_w;
+};
+
+}  // namespace
+
+int build_chunks(amrto_ctx* ctx, const amrto_mesh* m) {
+  const int nn = m->n_nodes, ne = m->n_elems;
+  std::vector<int> hidx(nn, -1);
+  for (int i = 0; i < m->n_hang; ++i) {
+    const int h = m->hang_node[i];
+    if (h < 0 || h >= nn || hidx[h] >= 0)
+      return ctx->fail(AMRTO_EINVAL, "amrto_upload_mesh: bad or repeated hanging node");
+    hidx[h] = i;
+  }
+  for (int i = 0; i < m->n_hang; ++i) {
+    const int b = m->hang_ptr[i], e = m->hang_ptr[i + 1];
+    if (e < b || e - b > 16) return ctx->fail(AMRTO_EINVAL, "amrto_upload_mesh: hanging node with bad master count");
+    for (int k = b; k < e; ++k) {
+      const int mm = m->hang_master[k];
+      if (mm < 0 || mm >= nn) return ctx->fail(AMRTO_EINVAL, "amrto_upload_mesh: master out of range");
+      if (hidx[mm] >= 0) return ctx->fail(AMRTO_EINVAL, "amrto_upload_mesh: a master is itself hanging");
+      if (!std::isfinite(m->hang_w[k])) return ctx->fail(AMRTO_EINVAL, "amrto_upload_mesh: bad weight");
+    }
+  }
+  // element -> touched regular nodes (vertices and masters), CSR
+  std::vector<int> tptr(ne + 1, 0), tnode;
+  tnode.reserve(12L * ne);
+  {
+    std::vector<int> tmp;
+    for (int e = 0; e < ne; ++e) {
+      tmp.clear();
+      for (int a = 0; a < 8; ++a) {
+        const int v = m->elem_nodes[8L * e + a];
+        if (hidx[v] < 0) tmp.push_back(v);
+        else
+          for (int k = m->hang_ptr[hidx[v]]; k < m->hang_ptr[hidx[v] + 1]; ++k) tmp.push_back(m->hang_master[k]);
+      }
+      std::sort(tmp.begin(), tmp.end());
+      tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+      tnode.insert(tnode.end(), tmp.begin(), tmp.end());
+      tptr[e + 1] = (int)tnode.size();
+    }
+  }
+  // owner element: first touching element (regular) / first element with it as a vertex (hanging)
+  std::vector<int> owner(nn, ne);
+  for (int e = 0; e < ne; ++e) {
+    for (int k = tptr[e]; k < tptr[e + 1]; ++k) owner[tnode[k]] = std::min(owner[tnode[k]], e);
+    for (int a = 0; a < 8; ++a) {
+      const int v = m->elem_nodes[8L * e + a];
+      if (hidx[v] >= 0) owner[v] = std::min(owner[v], e);
+    }
+  }
+  for (int v = 0; v < nn; ++v)
+    if (owner[v] == ne) return ctx->fail(AMRTO_EINVAL, "amrto_upload_mesh: a node belongs to no element");
+  // node -> touching elements (regular nodes), CSR
+  std::vector<int> nptr(nn + 1, 0), nelem(tnode.size());
+  for (int v : tnode) nptr[v + 1]++;
+  for (int v = 0; v < nn; ++v) nptr[v + 1] += nptr[v];
+  {
+    std::vector<int> fill(nptr.begin(), nptr.end() - 1);
+    for (int e = 0; e < ne; ++e)
+      for (int k = tptr[e]; k < tptr[e + 1]; ++k) nelem[fill[tnode[k]]++] = e;
+  }
+  // owned nodes grouped by owner element
+  std::vector<int> optr(ne + 1, 0), onode(nn);
+  for (int v = 0; v < nn; ++v) optr[owner[v] + 1]++;
+  for (int e = 0; e < ne; ++e) optr[e + 1] += optr[e];
+  {
+    std::vector<int> fill(optr.begin(), optr.end() - 1);
+    for (int v = 0; v < nn; ++v) onode[fill[owner[v]]++] = v;
+  }
+
+  Tables T;
+  std::vector<int> mark_e(ne, -1), loc(nn, -1);
+  int cid = 0;
+  std::vector<int> ents, own_reg, own_h, oth_reg, oth_h;
+  std::vector<int> nstamp(nn, -1);
+  int e0 = 0;
+  while (e0 < ne) {
+    int e1 = std::min(ne, e0 + CH_MAX);
+    while (true) {
+      // gather the chunk for run [e0, e1)
+      ents.clear(); own_reg.clear(); own_h.clear(); oth_reg.clear(); oth_h.clear();
+      const int stamp_id = cid;
+      for (int e = e0; e < e1; ++e) { mark_e[e] = stamp_id; ents.push_back(e); }
+      for (int e = e0; e < e1; ++e)
+        for (int k = optr[e]; k < optr[e + 1]; ++k) {
+          const int v = onode[k];
+          if (hidx[v] >= 0) { own_h.push_back(v); continue; }
+          own_reg.push_back(v);
+          for (int j = nptr[v]; j < nptr[v + 1]; ++j) {
+            const int f = nelem[j];
+            if (mark_e[f] != stamp_id) { mark_e[f] = stamp_id; ents.push_back(f); }
+          }
+        }
+      for (int v : own_reg) nstamp[v] = stamp_id;
+      for (int v : own_h) nstamp[v] = stamp_id;
+      for (int e : ents)
+        for (int a = 0; a < 8; ++a) {
+          const int v = m->elem_nodes[8L * e + a];
+          if (nstamp[v] != stamp_id) {
+            nstamp[v] = stamp_id;
+            (hidx[v] >= 0 ? oth_h : oth_reg).push_back(v);
+          }
+          if (hidx[v] >= 0)
+            for (int k = m->hang_ptr[hidx[v]]; k < m->hang_ptr[hidx[v] + 1]; ++k) {
+              const int mm = m->hang_master[k];
+              if (nstamp[mm] != stamp_id) { nstamp[mm] = stamp_id; oth_reg.push_back(mm); }
+            }
+        }
+      const size_t nt = own_reg.size() + oth_reg.size() + own_h.size() + oth_h.size();
+      if ((nt <= (size_t)TAB_MAX && ents.size() <= (size_t)ENT_MAX) || e1 - e0 == 1) {
+        if (nt > (size_t)TAB_MAX || ents.size() > (size_t)ENT_MAX)
+          return ctx->fail(AMRTO_EINVAL, "amrto_upload_mesh: one element's neighbourhood exceeds a chunk table");
+        break;
+      }
+      ++cid;  // fresh stamps for the retry
+      e1 = e0 + (e1 - e0) / 2;
+    }
+    // commit chunk [e0, e1)
+    int t = 0;
+    for (int v : own_reg) loc[v] = t++;
+    for (int v : oth_reg) loc[v] = t++;
+    const int nreg = t;
+    for (int v : own_h) loc[v] = t++;
+    for (int v : oth_h) loc[v] = t++;
+    std::sort(ents.begin(), ents.end());
+    for (int e : ents) {
+      T.ent_elem.push_back(e);
+      for (int a = 0; a < 8; ++a) T.ent_loc.push_back((uint16_t)loc[m->elem_nodes[8L * e + a]]);
+    }
+    for (int v : own_reg) T.tab_node.push_back(v);
+    for (int v : oth_reg) T.tab_node.push_back(v);
+    for (int v : own_h) T.tab_node.push_back(v);
+    for (int v : oth_h) T.tab_node.push_back(v);
+    T.tab_hbeg.resize(T.tab_node.size(), -1);
+    const int trip0 = (int)T.trip_hm.size();
+    auto add_trips = [&](const std::vector<int>& hs) {
+      for (int h : hs) {
+        T.tab_hbeg[T.chunk_tab.back() + loc[h]] = (int)T.trip_hm.size() - trip0;
+        for (int k = m->hang_ptr[hidx[h]]; k < m->hang_ptr[hidx[h] + 1]; ++k) {
+          T.trip_hm.push_back(((uint32_t)loc[h] << 16) | (uint32_t)loc[m->hang_master[k]]);
+          T.trip_w.push_back(m->hang_w[k]);
+        }
+      }
+    };
+    add_trips(own_h);
+    add_trips(oth_h);
+    T.chunk_nown.push_back((int)own_reg.size());
+    T.chunk_nreg.push_back(nreg);
+    T.chunk_nhown.push_back((int)own_h.size());
+    T.chunk_ent.push_back((int)T.ent_elem.size());
+    T.chunk_tab.push_back((int)T.tab_node.size());
+    T.chunk_trip.push_back((int)T.trip_hm.size());
+    ++cid;
+    e0 = e1;
+  }
+  const int nc = (int)T.chunk_nown.size();
+  AMRTO_HIP(upload(ctx->d_chunk_ent, T.chunk_ent));
+  AMRTO_HIP(upload(ctx->d_chunk_tab, T.chunk_tab));
+  AMRTO_HIP(upload(ctx->d_chunk_trip, T.chunk_trip));
+  AMRTO_HIP(upload(ctx->d_chunk_nown, T.chunk_nown));
+  AMRTO_HIP(upload(ctx->d_chunk_nreg, T.chunk_nreg));
+  AMRTO_HIP(upload(ctx->d_chunk_nhown, T.chunk_nhown));
+  AMRTO_HIP(upload(ctx->d_ent_elem, T.ent_elem));
+  AMRTO_HIP(upload(ctx->d_ent_loc, T.ent_loc));
+  AMRTO_HIP(upload(ctx->d_tab_node, T.tab_node));
+  AMRTO_HIP(upload(ctx->d_trip_hm, T.trip_hm));
+  AMRTO_HIP(upload(ctx->d_trip_w, T.trip_w));
+  AMRTO_HIP(upload(ctx->d_tab_hbeg, T.tab_hbeg));
+
+  // hanging lists (recovery, masks) and the transpose used for loads
+  std::vector<int> hang_node(m->hang_node, m->hang_node + m->n_hang);
+  std::vector<int> hang_ptr(m->hang_ptr, m->hang_ptr + m->n_hang + 1);
+  const int nhe = m->n_hang ? m->hang_ptr[m->n_hang] : 0;
+  std::vector<int> hang_master(m->hang_master, m->hang_master + nhe);
+  std::vector<double> hang_w(m->hang_w, m->hang_w + nhe);
+  std::vector<int> mt_count(nn, 0);
+  for (int k = 0; k < nhe; ++k) mt_count[hang_master[k]]++;
+  std::vector<int> mt_node, mt_ptr{0}, mt_h, mt_pos(nn, -1);
+  std::vector<double> mt_w;
+  for (int v = 0; v < nn; ++v)
+    if (mt_count[v] > 0) {
+      mt_pos[v] = mt_ptr.back();
+      mt_node.push_back(v);
+      mt_ptr.push_back(mt_ptr.back() + mt_count[v]);
+    }
+  mt_h.resize(mt_ptr.back());
+  mt_w.resize(mt_ptr.back());
+  for (int i = 0; i < m->n_hang; ++i)
+    for (int k = hang_ptr[i]; k < hang_ptr[i + 1]; ++k) {
+      const int mm = hang_master[k];
+      mt_h[mt_pos[mm]] = hang_node[i];
+      mt_w[mt_pos[mm]] = hang_w[k];
+      mt_pos[mm]++;
+    }
+  AMRTO_HIP(upload(ctx->d_hang_node, hang_node));
+  AMRTO_HIP(upload(ctx->d_hang_ptr, hang_ptr));
+  AMRTO_HIP(upload(ctx->d_hang_master, hang_master));
+  AMRTO_HIP(upload(ctx->d_hang_w, hang_w));
+  AMRTO_HIP(upload(ctx->d_mt_node, mt_node));
+  AMRTO_HIP(upload(ctx->d_mt_ptr, mt_ptr));
+  AMRTO_HIP(upload(ctx->d_mt_h, mt_h));
+  AMRTO_HIP(upload(ctx->d_mt_w, mt_w));
+  ctx->n_mt = (int)mt_node.size();
+  ctx->n_chunks = nc;
+  ctx->n_entries = (int)T.ent_elem.size();
+  ctx->n_hang = m->n_hang;
+  return AMRTO_OK;
+}
+
+}  // namespace amrto

@@ -79,15 +79,17 @@ static hipError_t dalloc(T*& p, size_t n) {
 
 static void free_mesh(amrto_ctx* c) {
   dfree(c->d_fix); dfree(c->d_level); dfree(c->d_elem_nodes);
-  dfree(c->d_chunk_elem); dfree(c->d_chunk_tab); dfree(c->d_chunk_nreg); dfree(c->d_chunk_trip);
-  dfree(c->d_tab_node); dfree(c->d_tab_slot); dfree(c->d_elem_loc); dfree(c->d_trip_hm);
-  dfree(c->d_trip_w); dfree(c->d_shared_node); dfree(c->d_shared_ptr); dfree(c->d_slot_list);
+  dfree(c->d_chunk_ent); dfree(c->d_chunk_tab); dfree(c->d_chunk_trip); dfree(c->d_chunk_nown);
+  dfree(c->d_chunk_nreg); dfree(c->d_chunk_nhown); dfree(c->d_ent_elem); dfree(c->d_ent_loc);
+  dfree(c->d_tab_node); dfree(c->d_trip_hm); dfree(c->d_trip_w); dfree(c->d_tab_hbeg);
   dfree(c->d_hang_node); dfree(c->d_hang_ptr); dfree(c->d_hang_master); dfree(c->d_hang_w);
   dfree(c->d_mt_node); dfree(c->d_mt_ptr); dfree(c->d_mt_h); dfree(c->d_mt_w);
   c->n_mt = 0;
-  dfree(c->d_partial); dfree(c->d_nb_ptr); dfree(c->d_nb_idx); dfree(c->d_nb_w);
+  dfree(c->d_nb_ptr); dfree(c->d_nb_idx); dfree(c->d_nb_w);
   dfree(c->d_coef); dfree(c->d_coef_f); dfree(c->d_dinv); dfree(c->d_dinv_f); dfree(c->d_vol);
-  dfree(c->d_r); dfree(c->d_z); dfree(c->d_p); dfree(c->d_q);
+  dfree(c->d_r); dfree(c->d_z); dfree(c->d_p); dfree(c->d_q); dfree(c->d_p2); dfree(c->f_p2);
+  dfree(c->d_partpq);
+  c->n_partpq = 0;
   dfree(c->f_b); dfree(c->f_x); dfree(c->f_r); dfree(c->f_z); dfree(c->f_p); dfree(c->f_q);
   dfree(c->d_coarse);
   c->coarse_k = 0;
@@ -110,6 +112,24 @@ static int upload_material(amrto_ctx* ctx) {
   AMRTO_HIP(hipMemcpyAsync(ctx->d_K0, ctx->K0, sizeof(ctx->K0), hipMemcpyHostToDevice, ctx->stream));
   AMRTO_HIP(hipMemcpyAsync(ctx->d_K0f, kf, sizeof(kf), hipMemcpyHostToDevice, ctx->stream));
   AMRTO_HIP(hipMemcpyAsync(ctx->d_K0bf, kb, sizeof(kb), hipMemcpyHostToDevice, ctx->stream));
+  // K0 in the basis of per-component Walsh-Hadamard modes W (W W^T = 8 I):
+  // B = W K0 W^T / 64 is block diagonal; block S couples the modes
+  // (c, t = S ^ (1 << c)), c = 0, 1, 2, so K0 = W^T B W.
+  static double kbd[72];
+  static float kbf[72];
+  auto wsign = [](int t, int n) { return (__builtin_popcount(t & n) & 1) ? -1.0 : 1.0; };
+  for (int S = 0; S < 8; ++S)
+    for (int c = 0; c < 3; ++c)
+      for (int d = 0; d < 3; ++d) {
+        const int t = S ^ (1 << c), tp = S ^ (1 << d);
+        double v = 0.0;
+        for (int n = 0; n < 8; ++n)
+          for (int m = 0; m < 8; ++m) v += wsign(t, n) * ctx->K0[(3 * n + c) * 24 + 3 * m + d] * wsign(tp, m);
+        kbd[9 * S + 3 * c + d] = v / 64.0;
+        kbf[9 * S + 3 * c + d] = (float)(v / 64.0);
+      }
+  AMRTO_HIP(hipMemcpyAsync(ctx->d_Kb, kbd, sizeof(kbd), hipMemcpyHostToDevice, ctx->stream));
+  AMRTO_HIP(hipMemcpyAsync(ctx->d_Kbf, kbf, sizeof(kbf), hipMemcpyHostToDevice, ctx->stream));
   AMRTO_HIP(hipStreamSynchronize(ctx->stream));
   return AMRTO_OK;
 }
@@ -129,6 +149,8 @@ int amrto_create(amrto_ctx** out, int device, void* stream) {
   if (hipMalloc((void**)&ctx->d_K0, 576 * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&ctx->d_K0f, 576 * sizeof(float)) != hipSuccess ||
       hipMalloc((void**)&ctx->d_K0bf, 1152 * sizeof(uint16_t)) != hipSuccess ||
+      hipMalloc((void**)&ctx->d_Kb, 72 * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&ctx->d_Kbf, 72 * sizeof(float)) != hipSuccess ||
       hipMalloc((void**)&ctx->d_part, 8 * RED_BLOCKS * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&ctx->d_scal, S_COUNT * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&ctx->d_oc, OC_WS * sizeof(double)) != hipSuccess ||
@@ -148,7 +170,7 @@ int amrto_destroy(amrto_ctx* ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   else (void)hipDeviceSynchronize();
   free_mesh(ctx);
-  dfree(ctx->d_K0); dfree(ctx->d_K0f); dfree(ctx->d_K0bf);
+  dfree(ctx->d_K0); dfree(ctx->d_K0f); dfree(ctx->d_K0bf); dfree(ctx->d_Kb); dfree(ctx->d_Kbf);
   dfree(ctx->d_part); dfree(ctx->d_scal); dfree(ctx->d_oc);
   if (ctx->h_scal) (void)hipHostFree(ctx->h_scal);
   delete ctx;
@@ -237,7 +259,7 @@ int amrto_upload_mesh(amrto_ctx* ctx, const amrto_mesh* m) {
   } else {
     ctx->h_node_xyz.clear();
     ctx->h_elem_nodes.clear();
-    ctx->n_chunks = 0; ctx->n_hang = 0; ctx->n_shared = 0; ctx->n_slots = 0;
+    ctx->n_chunks = 0; ctx->n_hang = 0; ctx->n_entries = 0;
   }
 
   // density-dependent arrays and the solver workspace
@@ -246,7 +268,10 @@ int amrto_upload_mesh(amrto_ctx* ctx, const amrto_mesh* m) {
   AMRTO_HIP(dalloc(ctx->d_dinv, n3));
   AMRTO_HIP(dalloc(ctx->d_dinv_f, n3));
   AMRTO_HIP(dalloc(ctx->d_r, n3)); AMRTO_HIP(dalloc(ctx->d_z, n3));
-  AMRTO_HIP(dalloc(ctx->d_p, n3)); AMRTO_HIP(dalloc(ctx->d_q, n3));
+  AMRTO_HIP(dalloc(ctx->d_p, n3)); AMRTO_HIP(dalloc(ctx->d_q, n3)); AMRTO_HIP(dalloc(ctx->d_p2, n3));
+  AMRTO_HIP(dalloc(ctx->f_p2, n3));
+  ctx->n_partpq = apply_blocks(ctx);
+  AMRTO_HIP(dalloc(ctx->d_partpq, ctx->n_partpq));
   AMRTO_HIP(dalloc(ctx->f_b, n3)); AMRTO_HIP(dalloc(ctx->f_x, n3)); AMRTO_HIP(dalloc(ctx->f_r, n3)); AMRTO_HIP(dalloc(ctx->f_z, n3));
   AMRTO_HIP(dalloc(ctx->f_p, n3)); AMRTO_HIP(dalloc(ctx->f_q, n3));
   ctx->has_mesh = true;

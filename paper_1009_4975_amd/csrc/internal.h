@@ -26,9 +26,11 @@ constexpr int UT = 15;
 constexpr int UE = UT + 1;  // element columns per tile edge
 constexpr int UN = UT + 2;  // node columns per tile edge (with halo)
 
-// Octree apply chunk: a workgroup takes up to CH_MAX consecutive elements and
-// stages the union of their nodes (plus masters of hanging nodes) in LDS.
-constexpr int CH_MAX = 256;
+// Octree operator chunk: a run of at most CH_MAX consecutive elements plus
+// the halo elements around its owned nodes (at most ENT_MAX in all); its node
+// table (at most TAB_MAX entries) is staged in LDS.
+constexpr int CH_MAX = 128;
+constexpr int ENT_MAX = 512;
 constexpr int TAB_MAX = 1024;
 
 // Reductions: fixed grid of partial sums; every consumer re-adds them in the
@@ -54,6 +56,16 @@ enum ScalarSlot {
   S_COUNT = 8
 };
 
+// Arguments of a fused conjugate-gradient step (see kernels.h).
+struct CgArgs {
+  double* scal;
+  const double* part_in;  // r.z and r.r partials of the previous update
+  double* part_out;       // p.q partials written by this pass
+  int part_base;          // first slot of this kernel in part_out
+  int it;
+  double tol2;
+};
+
 }  // namespace amrto
 
 struct amrto_ctx {
@@ -67,7 +79,7 @@ struct amrto_ctx {
   bool has_mesh = false, uniform = false, has_density = false;
   int n_nodes = 0, n_elems = 0, max_level = 0;
   int nx = 0, ny = 0, nz = 0;
-  int n_chunks = 0, n_shared = 0, n_slots = 0, n_hang = 0;
+  int n_chunks = 0, n_hang = 0;
   std::vector<int32_t> h_node_xyz;   // octree: lattice coordinates (host copy)
   std::vector<int8_t> h_level;
   std::vector<int32_t> h_elem_nodes;
@@ -76,23 +88,26 @@ struct amrto_ctx {
   double* d_K0 = nullptr;      // 576
   float* d_K0f = nullptr;      // 576
   uint16_t* d_K0bf = nullptr;  // 2 x 576 (hi, lo) bf16 bit patterns
+  double* d_Kb = nullptr;      // 72: K0 in mirror-symmetry blocks
+  float* d_Kbf = nullptr;      // 72
   // device: mesh
   uint8_t* d_fix = nullptr;        // per node, bit c = DOF c supported
   int8_t* d_level = nullptr;       // per element
   int32_t* d_elem_nodes = nullptr; // octree only
-  // octree chunks
-  int32_t* d_chunk_elem = nullptr;   // [n_chunks + 1] element ranges
+  // octree node-owner chunks (chunks.hip)
+  int n_entries = 0;                 // chunk elements including halo elements
+  int32_t* d_chunk_ent = nullptr;    // [n_chunks + 1] entry ranges
   int32_t* d_chunk_tab = nullptr;    // [n_chunks + 1] table ranges
-  int32_t* d_chunk_nreg = nullptr;   // [n_chunks] regular entries per table
   int32_t* d_chunk_trip = nullptr;   // [n_chunks + 1] hanging triple ranges
+  int32_t* d_chunk_nown = nullptr;   // [n_chunks] owned regular table entries
+  int32_t* d_chunk_nreg = nullptr;   // [n_chunks] regular table entries
+  int32_t* d_chunk_nhown = nullptr;  // [n_chunks] owned hanging table entries
+  int32_t* d_ent_elem = nullptr;     // element of each entry
+  uint16_t* d_ent_loc = nullptr;     // [8 n_entries] table index per local vertex
   int32_t* d_tab_node = nullptr;     // global node per table entry
-  int32_t* d_tab_slot = nullptr;     // -1 exclusive, else partial slot
-  uint16_t* d_elem_loc = nullptr;    // [8 n_elems] table index per local vertex
   uint32_t* d_trip_hm = nullptr;     // (h_loc << 16) | m_loc
   double* d_trip_w = nullptr;
-  int32_t* d_shared_node = nullptr;  // [n_shared]
-  int32_t* d_shared_ptr = nullptr;   // [n_shared + 1] into d_slot_list
-  int32_t* d_slot_list = nullptr;    // slots of each shared node in chunk order
+  int32_t* d_tab_hbeg = nullptr;     // per table entry: first triple of a hanging entry
   int32_t* d_hang_node = nullptr;    // [n_hang]
   int32_t* d_hang_ptr = nullptr;     // [n_hang + 1]
   int32_t* d_hang_master = nullptr;
@@ -102,7 +117,6 @@ struct amrto_ctx {
   int32_t* d_mt_ptr = nullptr;       // [n_mt + 1]
   int32_t* d_mt_h = nullptr;         // hanging node per entry
   double* d_mt_w = nullptr;          // weight per entry
-  double* d_partial = nullptr;       // [3 n_slots] (double or float view)
   // filter neighbour lists (octree), rebuilt when rmin changes
   double filt_rmin = -1.0;
   int n_sten = 0;
@@ -119,6 +133,9 @@ struct amrto_ctx {
 
   // device: solver workspace
   double* d_r = nullptr; double* d_z = nullptr; double* d_p = nullptr; double* d_q = nullptr;
+  double* d_p2 = nullptr; float* f_p2 = nullptr;
+  double* d_partpq = nullptr; // p.q partials of the fused operator passes
+  int n_partpq = 0;
   float* f_b = nullptr; float* f_x = nullptr; float* f_r = nullptr; float* f_z = nullptr; float* f_p = nullptr; float* f_q = nullptr;
   double* d_part = nullptr;   // reduction partials (4 x RED_BLOCKS)
   double* d_scal = nullptr;   // scalar slots
@@ -146,9 +163,10 @@ int launch_recover(amrto_ctx* ctx, const double* ut, double* u);
 int launch_recip(amrto_ctx* ctx, const double* a, double* b, long n);
 int launch_apply_bf16(amrto_ctx* ctx, const float* x, float* y, const double* stop);
 int apply_stop(amrto_ctx* ctx, const void* x, void* y, int prec, const double* stop);
+int apply_fused(amrto_ctx* ctx, const void* z, const void* pold, void* pnew, void* q, int prec, const CgArgs& cg);
+int apply_blocks(const amrto_ctx* ctx);
 void uniform_grid(const amrto_ctx* ctx, int& tiles_x, int& tiles_y, int& zchunk, int& n_tiles, int& grid);
-template <typename VT>
-void reduce_shared(amrto_ctx* ctx, const VT* x, VT* y, const double* stop);
+
 // helpers
 void k0_unit_cube(double nu, double* K);  // 24 x 24, E = 1
 uint16_t f32_to_bf16_rne(float f);
