@@ -153,10 +153,9 @@ typedef struct {
   double inner_rtol;  /* mixed precision: factor by which the FP32 recurrence
                          residual falls between two FP64 reliable updates
                          (default 1e-2) */
-  int32_t max_outer;  /* reserved (default 1000) */
   int32_t check_every;/* iterations between host convergence checks (default 16) */
-  const double* Z_dev;/* optional coarse space, column-major [3n x k] (NULL: none) */
-  int32_t k;          /* columns of Z_dev */
+  int32_t use_coarse; /* 1 (default): add the coarse correction set by
+                         amrto_coarse_setup, when one is set; 0: Jacobi only */
 } amrto_solve_opts;
 
 typedef struct {
@@ -176,7 +175,7 @@ void amrto_solve_opts_default(amrto_solve_opts* opts);
  * updates); convergence is always judged on the FP64 true residual.
  * u_dev: in = initial guess (its hanging and supported entries are ignored),
  * out = u = T u~ with hanging DOFs recovered (Eq. (9)).  b_dev = F T^T f.
- * With Z_dev, M^-1 = D^-1 + Z (Z^T A~ Z)^-1 Z^T (an SPD two-level
+ * With a coarse space, M^-1 = D^-1 + Z (Z^T A~ Z)^-1 Z^T (an SPD two-level
  * preconditioner).  Returns NOT_CONVERGED when the cap is reached; EBREAKDOWN
  * on p^T A p <= 0 or non-finite values. */
 int amrto_pcg(amrto_ctx* ctx, const double* b_dev, double* u_dev,
@@ -206,6 +205,89 @@ int amrto_filter(amrto_ctx* ctx, int mode, double rmin, const double* in_dev,
 int amrto_oc_update(amrto_ctx* ctx, const double* rho_dev, const double* dc_dev,
                     double volfrac, double move, double eta, double rho_min,
                     double* rho_new_dev, double* change_host, double* lam_host);
+
+/* Zero the supported and hanging entries of a DOF vector x_dev[3n] in place
+ * (the entries whose rows of A~ are the identity with zero right-hand side). */
+int amrto_mask(amrto_ctx* ctx, double* x_dev);
+
+/* ------------------------------------------------------------------ learned warm start
+ * (not in the paper, whose solves start from the previous displacement,
+ * Sec. 5: a network's prediction of the displacement change refines that
+ * start, and a Galerkin coarse space accelerates the Jacobi-PCG; the plain
+ * solve judges every result) */
+
+/* Two-level preconditioner M^-1 = D^-1 + Z (Z^T A~ Z)^-1 Z^T used by
+ * amrto_pcg while set (SPD for any Z, so CG stays valid).  The lattice box is
+ * split into rx x ry x rz equal regions; column (f, g, c) of Z is component
+ * c of field f on the nodes of region g, zero elsewhere.  The fields are, in
+ * this order: with affine != 0, the four affine fields (1,1,1), (x,y,z),
+ * (y,z,x), (z,x,y) (centred coordinates; per region they span the rigid
+ * motions and the constant strains), then the n_fields caller fields
+ * (fields_host: host array of device pointers to 3n FP64 vectors; copied).
+ * Every field is masked (zero on supported and hanging DOFs).  k = 3 rx ry rz
+ * (4 affine + n_fields) <= 96.  Z^T A~ Z is formed by k operator applications
+ * and factorised on the host, dropping columns whose pivot falls below 1e-12
+ * of the largest (*k_kept receives the rank kept; may be NULL).  Needs the
+ * density set; amrto_set_density drops the coarse space.
+ * Errors: EINVAL (bad sizes, k > 96), ESTATE, EHIP. */
+int amrto_coarse_setup(amrto_ctx* ctx, int32_t affine, const double* const* fields_host, int32_t n_fields,
+                       int32_t rx, int32_t ry, int32_t rz, int32_t* k_kept);
+/* Stop using the coarse space (plain Jacobi again). */
+int amrto_coarse_clear(amrto_ctx* ctx);
+/* x0 = base + sum_j a_j v_j with a minimising the energy 1/2 x^T A~ x - b^T x
+ * (base_dev may be NULL: zero), so x0 is never worse in the energy norm than
+ * base or any single v_j.  vecs_host: host array of n (1..8) device pointers;
+ * base and the vectors should be masked.  coef_host (may be NULL) receives a.
+ * x0_dev must not alias base or the vectors. */
+int amrto_energy_combine(amrto_ctx* ctx, const double* b_dev, const double* base_dev,
+                         const double* const* vecs_host, int32_t n, double* x0_dev, double* coef_host);
+
+/* Mesh -> regular grid with nodes every `cell` lattice units (cell divides
+ * every extent; gx = nx / cell etc.), node-major arrays (z, y, x) of
+ * (gz+1)(gy+1)(gx+1) values, FP32:
+ *   rho_grid = exact volume average of rho over each grid node's dual cell
+ *              (the box of edge `cell` centred at the node, clipped to the domain);
+ *   u_grid (3 components one after the other) = u_scale times the FE
+ *              displacement u - u_ref (u_ref may be NULL), trilinear on the
+ *              element holding the grid node.
+ * Either output may be NULL.  The transfer tables are built on the first call
+ * for a given cell (host work, then cached with the mesh). */
+int amrto_grid_from_mesh(amrto_ctx* ctx, int32_t cell, const double* rho_dev, const double* u_dev,
+                         const double* u_ref_dev, double u_scale, float* rho_grid_dev, float* u_grid_dev);
+/* u_dev[3n] = scale times the trilinear interpolation of u_grid (layout as
+ * above) at every mesh node (hanging nodes included; a solve ignores them). */
+int amrto_grid_to_mesh(amrto_ctx* ctx, int32_t cell, const float* u_grid_dev, double scale, double* u_dev);
+
+/* A fully convolutional network on a gx x gy x gz grid: n_layers 3x3x3
+ * convolutions (stride 1, zero padding), channels[0..n_layers], ReLU between
+ * layers, FP32; with skip_from >= 0 the output adds the input channels
+ * [skip_from, skip_from + channels[n_layers]) (a residual connection).
+ * Parameters are stored layer by layer as w (Cout, Cin, 3, 3, 3) then b
+ * (Cout); initial weights are He-normal, N(0, 2 / (27 Cin)), drawn as
+ * Box-Muller pairs of SplitMix64 outputs of (seed XOR counter); biases zero.
+ * Work is enqueued on hip_stream.  Buffers are allocated here only. */
+typedef struct amrto_net amrto_net;
+int amrto_net_create(amrto_net** net, int device, void* hip_stream, int32_t n_layers, const int32_t* channels,
+                     int32_t skip_from, int32_t gx, int32_t gy, int32_t gz, int32_t max_batch, uint64_t seed);
+int amrto_net_destroy(amrto_net* net);
+const char* amrto_net_last_error(const amrto_net* net);
+int amrto_net_n_params(const amrto_net* net, int64_t* n);
+/* host copies of all parameters / of the gradients of the last backward */
+int amrto_net_get_params(const amrto_net* net, float* host);
+int amrto_net_set_params(amrto_net* net, const float* host);
+int amrto_net_get_grads(const amrto_net* net, float* host);
+/* in_dev (batch, C0, gz, gy, gx) -> out_dev (batch, C_last, gz, gy, gx) (out may be NULL);
+ * activations are kept for the next backward */
+int amrto_net_forward(amrto_net* net, const float* in_dev, int32_t batch, float* out_dev);
+/* gradients of all parameters (overwritten) from dL/dout of the last forward;
+ * din_dev (may be NULL) receives dL/din */
+int amrto_net_backward(amrto_net* net, const float* dout_dev, float* din_dev);
+/* masked mean squared error over n values (mask_dev may be NULL): *loss_host
+ * (may be NULL) and dpred_dev = dL/dpred */
+int amrto_net_mse(amrto_net* net, const float* pred_dev, const float* target_dev, const uint8_t* mask_dev,
+                  int64_t n, float* dpred_dev, double* loss_host);
+/* one Adam step (step t >= 1, bias-corrected) on all parameters */
+int amrto_net_adam(amrto_net* net, float lr, float beta1, float beta2, float eps, int32_t t);
 
 /* ------------------------------------------------------------------ octree (host) */
 

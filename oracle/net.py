@@ -1,4 +1,5 @@
-"""Reference 3-D convolutional network for the learned warm start.
+"""Reference 3-D convolutional network for the learned warm start (test
+infrastructure; nothing in the product path imports this module).
 
 The learned part is not in the paper: a small fully convolutional network
 maps per-cell inputs (density, previous displacement, coordinates) on a
@@ -58,9 +59,10 @@ def init_params(channels, seed):
     return params
 
 
-def forward(params, x):
-    """Conv layers with ReLU between them (none after the last); returns the
-    output and the per-layer inputs needed by backward."""
+def forward(params, x, skip_from=None):
+    """Conv layers with ReLU between them (none after the last); with
+    skip_from, the output adds input channels [skip_from, skip_from + C_out).
+    Returns the output and the per-layer inputs needed by backward."""
     acts = [x]
     h = x
     for k, (w, b) in enumerate(params):
@@ -68,10 +70,13 @@ def forward(params, x):
         if k + 1 < len(params):
             h = relu(h)
         acts.append(h)
+    if skip_from is not None:
+        h = h + x[:, skip_from:skip_from + h.shape[1]]
     return h, acts
 
 
-def backward(params, acts, dout):
+def backward(params, acts, dout, skip_from=None, return_dx=False):
+    """Parameter gradients (and, with return_dx, the input gradient)."""
     grads = [None] * len(params)
     g = dout
     for k in range(len(params) - 1, -1, -1):
@@ -81,7 +86,12 @@ def backward(params, acts, dout):
         dx, dw, db = conv3d_backward(acts[k], w, g)
         grads[k] = (dw, db)
         g = dx
-    return grads
+    if not return_dx:
+        return grads
+    if skip_from is not None:
+        g = g.copy()
+        g[:, skip_from:skip_from + dout.shape[1]] += dout
+    return grads, g
 
 
 def mse(pred, target, mask):

@@ -44,8 +44,8 @@ class Region(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_it", C.c_int32), ("precond", C.c_int32),
-                ("inner_prec", C.c_int32), ("inner_rtol", C.c_double), ("max_outer", C.c_int32),
-                ("check_every", C.c_int32), ("Z_dev", _p), ("k", C.c_int32)]
+                ("inner_prec", C.c_int32), ("inner_rtol", C.c_double), ("check_every", C.c_int32),
+                ("use_coarse", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -71,6 +71,25 @@ _SIGS = {
     "amrto_filter": (C.c_int, [_p, C.c_int, C.c_double, _p, _p, _p]),
     "amrto_oc_update": (C.c_int, [_p, _p, _p, C.c_double, C.c_double, C.c_double, C.c_double, _p,
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "amrto_mask": (C.c_int, [_p, _p]),
+    "amrto_coarse_setup": (C.c_int, [_p, C.c_int32, C.POINTER(_p), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                     _i32p]),
+    "amrto_coarse_clear": (C.c_int, [_p]),
+    "amrto_energy_combine": (C.c_int, [_p, _p, _p, C.POINTER(_p), C.c_int32, _p, C.POINTER(C.c_double)]),
+    "amrto_grid_from_mesh": (C.c_int, [_p, C.c_int32, _p, _p, _p, C.c_double, _p, _p]),
+    "amrto_grid_to_mesh": (C.c_int, [_p, C.c_int32, _p, C.c_double, _p]),
+    "amrto_net_create": (C.c_int, [C.POINTER(_p), C.c_int, _p, C.c_int32, _i32p, C.c_int32, C.c_int32,
+                                   C.c_int32, C.c_int32, C.c_int32, C.c_uint64]),
+    "amrto_net_destroy": (C.c_int, [_p]),
+    "amrto_net_last_error": (C.c_char_p, [_p]),
+    "amrto_net_n_params": (C.c_int, [_p, C.POINTER(C.c_int64)]),
+    "amrto_net_get_params": (C.c_int, [_p, _p]),
+    "amrto_net_set_params": (C.c_int, [_p, _p]),
+    "amrto_net_get_grads": (C.c_int, [_p, _p]),
+    "amrto_net_forward": (C.c_int, [_p, _p, C.c_int32, _p]),
+    "amrto_net_backward": (C.c_int, [_p, _p, _p]),
+    "amrto_net_mse": (C.c_int, [_p, _p, _p, _p, C.c_int64, _p, C.POINTER(C.c_double)]),
+    "amrto_net_adam": (C.c_int, [_p, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32]),
     "amrto_octree_create": (C.c_int, [C.POINTER(_p), C.POINTER(C.c_int32), C.c_int32]),
     "amrto_octree_destroy": (C.c_int, [_p]),
     "amrto_octree_n_leaves": (C.c_int32, [_p]),
@@ -333,15 +352,12 @@ class Context:
     def diag(self, out):
         self._chk(self.lib.amrto_get_diag(self.h, _dev(out, self.torch.float64)))
 
-    def pcg(self, b, u, rtol=1e-8, max_it=20000, inner_prec=FP64, inner_rtol=1e-3, max_outer=50,
-            check_every=16, Z=None, k=0, allow_not_converged=False):
+    def pcg(self, b, u, rtol=1e-8, max_it=20000, inner_prec=FP64, inner_rtol=1e-3, check_every=16,
+            use_coarse=True, allow_not_converged=False):
         o = SolveOpts()
         self.lib.amrto_solve_opts_default(C.byref(o))
         o.rtol, o.max_it, o.inner_prec, o.inner_rtol = rtol, max_it, inner_prec, inner_rtol
-        o.max_outer, o.check_every = max_outer, check_every
-        if Z is not None:
-            o.Z_dev = _dev(Z, self.torch.float64)
-            o.k = int(k)
+        o.check_every, o.use_coarse = check_every, int(bool(use_coarse))
         st = SolveStats()
         rc = self.lib.amrto_pcg(self.h, _dev(b, self.torch.float64), _dev(u, self.torch.float64), C.byref(o),
                                 C.byref(st))
@@ -370,3 +386,104 @@ class Context:
                                            volfrac, move, eta, rho_min, _dev(rho_new, self.torch.float64),
                                            C.byref(ch), C.byref(lam)))
         return ch.value, lam.value
+
+    def mask(self, x):
+        self._chk(self.lib.amrto_mask(self.h, _dev(x, self.torch.float64)))
+
+    def coarse_setup(self, fields, rx, ry, rz, affine=False):
+        """fields: sequence of float64 device vectors (3n); returns the rank kept."""
+        n = len(fields)
+        arr = (_p * max(n, 1))(*[_dev(f, self.torch.float64) for f in fields])
+        kept = C.c_int32()
+        self._chk(self.lib.amrto_coarse_setup(self.h, int(bool(affine)), arr, n, int(rx), int(ry), int(rz),
+                                              C.byref(kept)))
+        return kept.value
+
+    def coarse_clear(self):
+        self._chk(self.lib.amrto_coarse_clear(self.h))
+
+    def energy_combine(self, b, vecs, x0, base=None):
+        n = len(vecs)
+        f64 = self.torch.float64
+        arr = (_p * n)(*[_dev(v, f64) for v in vecs])
+        coef = (C.c_double * n)()
+        self._chk(self.lib.amrto_energy_combine(self.h, _dev(b, f64), None if base is None else _dev(base, f64),
+                                                arr, n, _dev(x0, f64), coef))
+        return list(coef)
+
+    def grid_from_mesh(self, cell, rho=None, u=None, rho_grid=None, u_grid=None, u_scale=1.0, u_ref=None):
+        f64, f32 = self.torch.float64, self.torch.float32
+        self._chk(self.lib.amrto_grid_from_mesh(
+            self.h, int(cell), None if rho is None else _dev(rho, f64), None if u is None else _dev(u, f64),
+            None if u_ref is None else _dev(u_ref, f64), float(u_scale),
+            None if rho_grid is None else _dev(rho_grid, f32), None if u_grid is None else _dev(u_grid, f32)))
+
+    def grid_to_mesh(self, cell, u_grid, u, scale=1.0):
+        self._chk(self.lib.amrto_grid_to_mesh(self.h, int(cell), _dev(u_grid, self.torch.float32), float(scale),
+                                              _dev(u, self.torch.float64)))
+
+
+class Net:
+    """3x3x3 convolution stack on a regular grid, trained by the library's kernels."""
+
+    def __init__(self, channels, grid, max_batch=1, seed=0, skip_from=-1, device=0, stream=None):
+        self.lib = load()
+        import torch
+        self.torch = torch
+        self.channels = [int(c) for c in channels]
+        self.grid = tuple(int(g) for g in grid)  # (gx, gy, gz)
+        ch = (C.c_int32 * len(self.channels))(*self.channels)
+        h = _p()
+        st = stream if stream is not None else torch.cuda.current_stream(device).cuda_stream
+        rc = self.lib.amrto_net_create(C.byref(h), int(device), st, len(self.channels) - 1, ch, int(skip_from),
+                                       *self.grid, int(max_batch), int(seed))
+        if rc != 0:
+            raise AmrtoError(rc, "amrto_net_create failed")
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.lib.amrto_net_destroy(self.h)
+            self.h = None
+
+    def _chk(self, rc):
+        if rc != 0:
+            raise AmrtoError(rc, self.lib.amrto_net_last_error(self.h).decode())
+
+    def n_params(self):
+        n = C.c_int64()
+        self._chk(self.lib.amrto_net_n_params(self.h, C.byref(n)))
+        return n.value
+
+    def get_params(self):
+        out = np.empty(self.n_params(), np.float32)
+        self._chk(self.lib.amrto_net_get_params(self.h, out.ctypes.data))
+        return out
+
+    def set_params(self, flat):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        assert a.size == self.n_params()
+        self._chk(self.lib.amrto_net_set_params(self.h, a.ctypes.data))
+
+    def get_grads(self):
+        out = np.empty(self.n_params(), np.float32)
+        self._chk(self.lib.amrto_net_get_grads(self.h, out.ctypes.data))
+        return out
+
+    def forward(self, x, out):
+        self._chk(self.lib.amrto_net_forward(self.h, _dev(x, self.torch.float32), int(x.shape[0]),
+                                             _dev(out, self.torch.float32)))
+
+    def backward(self, dout, din=None):
+        self._chk(self.lib.amrto_net_backward(self.h, _dev(dout, self.torch.float32),
+                                              None if din is None else _dev(din, self.torch.float32)))
+
+    def mse(self, pred, target, dpred, mask=None):
+        loss = C.c_double()
+        self._chk(self.lib.amrto_net_mse(self.h, _dev(pred, self.torch.float32), _dev(target, self.torch.float32),
+                                         None if mask is None else _dev(mask, self.torch.uint8), int(pred.numel()),
+                                         _dev(dpred, self.torch.float32), C.byref(loss)))
+        return loss.value
+
+    def adam(self, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._chk(self.lib.amrto_net_adam(self.h, lr, beta1, beta2, eps, int(t)))

@@ -91,8 +91,12 @@ static void free_mesh(amrto_ctx* c) {
   dfree(c->d_partpq);
   c->n_partpq = 0;
   dfree(c->f_b); dfree(c->f_x); dfree(c->f_r); dfree(c->f_z); dfree(c->f_p); dfree(c->f_q);
-  dfree(c->d_coarse);
+  dfree(c->d_cf); dfree(c->d_region); dfree(c->d_cpart); dfree(c->d_cinv);
+  dfree(c->d_node_xyz); dfree(c->d_cell_ptr); dfree(c->d_cell_elem); dfree(c->d_cell_w);
+  dfree(c->d_gn_node); dfree(c->d_gn_w);
   c->coarse_k = 0;
+  c->coarse_cap = 0;
+  c->grid_cell = 0;
   c->filt_rmin = -1.0;
   c->has_mesh = false;
   c->has_density = false;
@@ -291,6 +295,7 @@ int amrto_set_density(amrto_ctx* ctx, const double* rho) {
   if (!ctx->has_mesh) return ctx->fail(AMRTO_ESTATE, "amrto_set_density: no mesh uploaded");
   if (!rho) return ctx->fail(AMRTO_EINVAL, "amrto_set_density: rho is NULL");
   AMRTO_HIP(hipSetDevice(ctx->device));
+  ctx->coarse_k = 0;  // Z^T A~ Z depends on the density
   int rc = launch_set_density(ctx, rho);
   if (rc) return rc;
   rc = launch_diag(ctx);

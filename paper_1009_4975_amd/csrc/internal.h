@@ -38,6 +38,7 @@ constexpr int TAB_MAX = 1024;
 constexpr int RED_BLOCKS = 256;
 constexpr int RED_THREADS = 256;
 constexpr int OC_WS = 2 + 256 * 256 + 64;
+constexpr int COARSE_KMAX = 96;  // coarse-space columns
 
 template <typename T>
 struct DevArray {
@@ -141,8 +142,20 @@ struct amrto_ctx {
   double* d_scal = nullptr;   // scalar slots
   double* h_scal = nullptr;   // pinned mirror
   double* d_oc = nullptr;     // OC search workspace
-  double* d_coarse = nullptr; // coarse-space workspace
-  int coarse_k = 0;
+  // coarse space (coarse.hip)
+  int coarse_k = 0, coarse_nf = 0, coarse_R = 0, coarse_cap = 0;
+  double* d_cf = nullptr;      // n_fields x 3n fields (masked)
+  uint8_t* d_region = nullptr; // region of each node
+  double* d_cpart = nullptr;   // COARSE_KMAX x RED_BLOCKS partials
+  double* d_cinv = nullptr;    // E^-1 (k x k)
+  // mesh <-> grid transfers (net.hip)
+  int grid_cell = 0;
+  int32_t* d_node_xyz = nullptr;
+  int32_t* d_cell_ptr = nullptr;   // [cells + 1] elements overlapping each grid cell
+  int32_t* d_cell_elem = nullptr;
+  double* d_cell_w = nullptr;      // overlap volume / cell volume
+  int32_t* d_gn_node = nullptr;    // [8 grid nodes] mesh nodes interpolated at each grid node
+  float* d_gn_w = nullptr;         // [8 grid nodes] their trilinear weights
 
   int fail(int code, const std::string& msg) {
     err = msg;
@@ -161,7 +174,9 @@ int launch_set_density(amrto_ctx* ctx, const double* rho);
 int launch_project_rhs(amrto_ctx* ctx, const double* f, double* b);
 int launch_recover(amrto_ctx* ctx, const double* ut, double* u);
 int launch_recip(amrto_ctx* ctx, const double* a, double* b, long n);
-int launch_apply_bf16(amrto_ctx* ctx, const float* x, float* y, const double* stop);
+int mask_vector(amrto_ctx* ctx, double* x);
+int mask_vector_n(amrto_ctx* ctx, double* x, int count);
+int launch_zt(amrto_ctx* ctx, const double* v);
 int apply_stop(amrto_ctx* ctx, const void* x, void* y, int prec, const double* stop);
 int apply_fused(amrto_ctx* ctx, const void* z, const void* pold, void* pnew, void* q, int prec, const CgArgs& cg);
 int apply_blocks(const amrto_ctx* ctx);

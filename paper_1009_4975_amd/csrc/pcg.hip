@@ -116,6 +116,102 @@ __global__ __launch_bounds__(256) void k_cg_update(VT* __restrict__ x, VT* __res
   }
 }
 
+// partials of Z^T v: part[j * RED_BLOCKS + block]
+template <typename VT>
+__global__ __launch_bounds__(256) void k_zt_part(const double* __restrict__ F, int nf, const uint8_t* __restrict__ region,
+                                                 int R, const VT* __restrict__ v, long n3, double* __restrict__ part) {
+  __shared__ double acc[COARSE_KMAX];
+  const int k = 3 * nf * R;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) acc[j] = 0.0;
+  __syncthreads();
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n3; i += (long)gridDim.x * blockDim.x) {
+    const double vi = (double)v[i];
+    if (vi == 0.0) continue;
+    const int g = region[i / 3], c = (int)(i % 3);
+    for (int f = 0; f < nf; ++f) atomicAdd(&acc[(f * R + g) * 3 + c], F[(long)f * n3 + i] * vi);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < k; j += blockDim.x) part[(long)j * RED_BLOCKS + blockIdx.x] = acc[j];
+}
+
+
+// Coarse-corrected variant of the update pass: x += alpha p, r -= alpha q and
+// partials of Z^T r (z is formed afterwards by k_coarse_z).
+template <typename VT>
+__global__ __launch_bounds__(256) void k_cg_update_coarse(VT* __restrict__ x, VT* __restrict__ r,
+                                                          const VT* __restrict__ p, const VT* __restrict__ q, long n,
+                                                          const double* __restrict__ part_pq, int n_pq,
+                                                          double* __restrict__ scal, int it, const double* __restrict__ F,
+                                                          int nf, const uint8_t* __restrict__ region, int R,
+                                                          double* __restrict__ part_z) {
+  if (scal[S_DONE] != 0.0) return;
+  __shared__ double sh[8];
+  __shared__ double acc[COARSE_KMAX];
+  const int k = 3 * nf * R;
+  const double pq = sum_partials(part_pq, n_pq, sh);
+  const double rz = scal[S_RZ0 + (it & 1)];
+  if (!(pq > 0.0) || !(pq < 1e300) || !(rz == rz)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_DONE] = 2.0;
+    return;
+  }
+  for (int j = threadIdx.x; j < k; j += blockDim.x) acc[j] = 0.0;
+  __syncthreads();
+  const VT alpha = (VT)(rz / pq);
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    const VT ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    if (ri != (VT)0) {
+      const int g = region[i / 3], c = (int)(i % 3);
+      for (int f = 0; f < nf; ++f) atomicAdd(&acc[(f * R + g) * 3 + c], F[(long)f * n + i] * (double)ri);
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < k; j += blockDim.x) part_z[(long)j * RED_BLOCKS + blockIdx.x] = acc[j];
+}
+
+// z = D^-1 r + Z E^-1 (Z^T r); partials r.z, r.r
+template <typename VT>
+__global__ __launch_bounds__(256) void k_coarse_z(const VT* __restrict__ r, VT* __restrict__ z,
+                                                  const VT* __restrict__ dinv, long n, const double* __restrict__ part_z,
+                                                  const double* __restrict__ Einv, const double* __restrict__ F, int nf,
+                                                  const uint8_t* __restrict__ region, int R,
+                                                  double* __restrict__ part, const double* __restrict__ stop) {
+  if (stop && *stop != 0.0) return;
+  __shared__ double sh[8];
+  __shared__ double ct[COARSE_KMAX], cz[COARSE_KMAX];
+  const int k = 3 * nf * R;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < RED_BLOCKS; ++b) s += part_z[(long)j * RED_BLOCKS + b];
+    ct[j] = s;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < k; ++i) s += Einv[j * k + i] * ct[i];
+    cz[j] = s;
+  }
+  __syncthreads();
+  double srz = 0.0, srr = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const VT ri = r[i];
+    double zi = (double)dinv[i] * (double)ri;
+    const int g = region[i / 3], c = (int)(i % 3);
+    // the fields are zero on supported and hanging DOFs, so z stays zero there
+    for (int f = 0; f < nf; ++f) zi += F[(long)f * n + i] * cz[(f * R + g) * 3 + c];
+    z[i] = (VT)zi;
+    srz += (double)ri * zi;
+    srr += (double)ri * (double)ri;
+  }
+  srz = block_sum(srz, sh);
+  srr = block_sum(srr, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = srz;
+    part[RED_BLOCKS + blockIdx.x] = srr;
+  }
+}
+
 // r = b - q in FP64 and partials r.r, b.b (true residual)
 __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ b, const double* __restrict__ q,
                                                   double* __restrict__ r, long n, double* __restrict__ part) {
@@ -165,6 +261,44 @@ struct Vecs {
 static Vecs<double> vecs64(amrto_ctx* c) { return {c->d_r, c->d_z, c->d_p, c->d_p2, c->d_q, c->d_dinv}; }
 static Vecs<float> vecs32(amrto_ctx* c) { return {c->f_r, c->f_z, c->f_p, c->f_p2, c->f_q, c->d_dinv_f}; }
 
+// with a coarse space: z = D^-1 r + Z E^-1 Z^T r for the initial residual
+// (overwrites the r.z and r.r partials of k_init; b.b stays)
+template <typename VT>
+static void coarse_init(amrto_ctx* ctx, const Vecs<VT>& v) {
+  if (ctx->coarse_k <= 0) return;
+  const long n3 = 3L * ctx->n_nodes;
+  hipLaunchKernelGGL(k_zt_part<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, ctx->d_cf, ctx->coarse_nf,
+                     ctx->d_region, ctx->coarse_R, v.r, n3, ctx->d_cpart);
+  hipLaunchKernelGGL(k_coarse_z<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, v.r, v.z, v.dinv, n3, ctx->d_cpart,
+                     ctx->d_cinv, ctx->d_cf, ctx->coarse_nf, ctx->d_region, ctx->coarse_R, ctx->d_part,
+                     (const double*)nullptr);
+}
+
+int launch_zt(amrto_ctx* ctx, const double* v) {
+  hipLaunchKernelGGL(k_zt_part<double>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, ctx->d_cf, ctx->coarse_nf,
+                     ctx->d_region, ctx->coarse_R, v, 3L * ctx->n_nodes, ctx->d_cpart);
+  AMRTO_HIP(hipGetLastError());
+  return AMRTO_OK;
+}
+
+int mask_vector_n(amrto_ctx* ctx, double* x, int count) {
+  for (int i = 0; i < count; ++i) {
+    int rc = mask_vector(ctx, x + 3L * ctx->n_nodes * i);
+    if (rc) return rc;
+  }
+  return AMRTO_OK;
+}
+
+int mask_vector(amrto_ctx* ctx, double* x) {
+  const long n3 = 3L * ctx->n_nodes;
+  hipLaunchKernelGGL(k_mask<double>, dim3((n3 + 255) / 256), dim3(256), 0, ctx->stream, x, ctx->d_fix, n3);
+  if (ctx->n_hang)
+    hipLaunchKernelGGL(k_mask_hanging<double>, dim3((3L * ctx->n_hang + 255) / 256), dim3(256), 0, ctx->stream, x,
+                       ctx->d_hang_node, ctx->n_hang);
+  AMRTO_HIP(hipGetLastError());
+  return AMRTO_OK;
+}
+
 static int read_scalars(amrto_ctx* ctx) {
   AMRTO_HIP(hipMemcpyAsync(ctx->h_scal, ctx->d_scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   AMRTO_HIP(hipStreamSynchronize(ctx->stream));
@@ -181,8 +315,17 @@ static int enqueue_iters(amrto_ctx* ctx, const Vecs<VT>& v, VT* x, int prec, dou
     CgArgs cg{ctx->d_scal, ctx->d_part, ctx->d_partpq, 0, it, tol2};
     int rc = apply_fused(ctx, v.z, pold, pnew, v.q, prec, cg);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_cg_update<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew, v.q, v.dinv, v.z,
-                       n3, ctx->d_partpq, ctx->n_partpq, ctx->d_scal, it, ctx->d_part);
+    if (ctx->coarse_k > 0) {
+      hipLaunchKernelGGL(k_cg_update_coarse<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew, v.q, n3,
+                         ctx->d_partpq, ctx->n_partpq, ctx->d_scal, it, ctx->d_cf, ctx->coarse_nf, ctx->d_region,
+                         ctx->coarse_R, ctx->d_cpart);
+      hipLaunchKernelGGL(k_coarse_z<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, v.r, v.z, v.dinv, n3,
+                         ctx->d_cpart, ctx->d_cinv, ctx->d_cf, ctx->coarse_nf, ctx->d_region, ctx->coarse_R,
+                         ctx->d_part, ctx->d_scal + S_DONE);
+    } else {
+      hipLaunchKernelGGL(k_cg_update<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew, v.q, v.dinv,
+                         v.z, n3, ctx->d_partpq, ctx->n_partpq, ctx->d_scal, it, ctx->d_part);
+    }
   }
   AMRTO_HIP(hipGetLastError());
   return AMRTO_OK;
@@ -203,6 +346,7 @@ static int cg_fp64(amrto_ctx* ctx, const double* b, double* x, double rtol, int 
   if (rc) return rc;
   hipLaunchKernelGGL((k_init<double, double>), dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, b, v.q, v.r, v.z, v.dinv,
                      n3, ctx->d_part);
+  coarse_init<double>(ctx, v);
   hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(256), 0, ctx->stream, ctx->d_part, ctx->d_scal, tol2, 0);
   AMRTO_HIP(hipGetLastError());
   int it = 0;
@@ -272,6 +416,7 @@ static int cg_mixed(amrto_ctx* ctx, const double* b, double* x, int prec, double
       // r32 = r64, z32 = D^-1 r32; r.z, r.r partials for the next operator pass
       hipLaunchKernelGGL((k_init<float, double>), dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, ctx->d_r,
                          (const double*)nullptr, v.r, v.z, v.dinv, n3, ctx->d_part);
+      coarse_init<float>(ctx, v);
       // the recurrence measures its residual against b.b
       hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, ctx->stream, ctx->d_scal, (int)S_BB, bb);
       if (*updates == 0) {
@@ -313,6 +458,14 @@ using namespace amrto;
 
 extern "C" {
 
+int amrto_mask(amrto_ctx* ctx, double* x) {
+  if (!ctx) return AMRTO_EINVAL;
+  if (!ctx->has_mesh) return ctx->fail(AMRTO_ESTATE, "amrto_mask: no mesh");
+  if (!x) return ctx->fail(AMRTO_EINVAL, "amrto_mask: NULL buffer");
+  AMRTO_HIP(hipSetDevice(ctx->device));
+  return mask_vector(ctx, x);
+}
+
 void amrto_solve_opts_default(amrto_solve_opts* o) {
   if (!o) return;
   o->rtol = 1e-8;
@@ -320,10 +473,8 @@ void amrto_solve_opts_default(amrto_solve_opts* o) {
   o->precond = AMRTO_PRECOND_JACOBI;
   o->inner_prec = AMRTO_FP64;
   o->inner_rtol = 1e-2;
-  o->max_outer = 1000;
   o->check_every = 16;
-  o->Z_dev = nullptr;
-  o->k = 0;
+  o->use_coarse = 1;
 }
 
 int amrto_pcg(amrto_ctx* ctx, const double* b, double* u, const amrto_solve_opts* opts_in,
@@ -334,13 +485,19 @@ int amrto_pcg(amrto_ctx* ctx, const double* b, double* u, const amrto_solve_opts
   amrto_solve_opts o;
   amrto_solve_opts_default(&o);
   if (opts_in) o = *opts_in;
-  if (!(o.rtol > 0.0) || o.max_it < 0 || o.check_every < 1 || o.max_outer < 1 || !(o.inner_rtol > 0.0) ||
+  if (!(o.rtol > 0.0) || o.max_it < 0 || o.check_every < 1 || !(o.inner_rtol > 0.0) ||
       !(o.inner_rtol < 1.0))
     return ctx->fail(AMRTO_EINVAL, "amrto_pcg: bad options");
   if (o.inner_prec != AMRTO_FP64 && o.inner_prec != AMRTO_FP32 && o.inner_prec != AMRTO_BF16)
     return ctx->fail(AMRTO_EINVAL, "amrto_pcg: unknown inner precision");
   if (o.precond != AMRTO_PRECOND_JACOBI) return ctx->fail(AMRTO_EINVAL, "amrto_pcg: unknown preconditioner");
   AMRTO_HIP(hipSetDevice(ctx->device));
+  // the solve loops read the coarse space from the context
+  struct CoarseOff {
+    amrto_ctx* c; int k;
+    ~CoarseOff() { c->coarse_k = k; }
+  } coarse_guard{ctx, ctx->coarse_k};
+  if (!o.use_coarse) ctx->coarse_k = 0;
   const auto t0 = std::chrono::steady_clock::now();
   int iters = 0, outer = 0, status;
   double rel = 0.0;

@@ -1,0 +1,256 @@
+"""Learned warm start and coarse correction on the GPU.
+
+Network layers, loss and Adam against the CPU reference network (FP32 kernels
+vs FP64 reference: relative 1e-5 on activations, 1e-4 on gradients, which sum
+up to 27 Cin V products); grid transfers against the reference transfers;
+the energy-optimal combination against the oracle's system; the two-level
+preconditioner against the oracle's direct solution.  The network's
+predictions themselves are parity unpinned: the plain solve judges them, and
+the gain test checks that they cut iterations.
+"""
+import numpy as np
+import pytest
+
+import cases
+import synth
+from oracle import grid as ogrid, net as onet, system as osys
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(a, dt=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def split_params(flat, channels):
+    out, off = [], 0
+    for ci, co in zip(channels[:-1], channels[1:]):
+        w = flat[off:off + co * ci * 27].reshape(co, ci, 3, 3, 3).astype(np.float64)
+        off += co * ci * 27
+        b = flat[off:off + co].astype(np.float64)
+        off += co
+        out.append((w, b))
+    assert off == len(flat)
+    return out
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+# ---------------------------------------------------------------------- network
+@pytest.mark.parametrize("skip", [None, 1])
+def test_net_forward_backward_match_reference(skip):
+    from paper_1009_4975_amd import binding
+    ch = [4, 8, 6, 3]
+    gx, gy, gz = 7, 5, 6
+    B = 2
+    net = binding.Net(ch, (gx, gy, gz), max_batch=3, seed=5, skip_from=-1 if skip is None else skip)
+    params = split_params(net.get_params(), ch)
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(B, 4, gz, gy, gx)).astype(np.float32)
+    xd = dev(x, torch.float32)
+    out = torch.empty(B, 3, gz, gy, gx, dtype=torch.float32, device="cuda")
+    net.forward(xd, out)
+    want, acts = onet.forward(params, x.astype(np.float64), skip_from=skip)
+    assert rel(host(out), want) < 1e-5
+    g = rng.normal(size=want.shape).astype(np.float32)
+    din = torch.empty_like(xd)
+    net.backward(dev(g, torch.float32), din)
+    grads, dx = onet.backward(params, acts, g.astype(np.float64), skip_from=skip, return_dx=True)
+    got = split_params(net.get_grads(), ch)
+    for (gw, gb), (ww, wb) in zip(got, grads):
+        assert rel(gw, ww) < 1e-4
+        assert rel(gb, wb) < 1e-4
+    assert rel(host(din), dx) < 1e-5
+
+
+def test_net_init_seeded_he_normal():
+    from paper_1009_4975_amd import binding
+    ch = [8, 32, 3]
+    a = binding.Net(ch, (4, 4, 4), seed=7).get_params()
+    b = binding.Net(ch, (4, 4, 4), seed=7).get_params()
+    c = binding.Net(ch, (4, 4, 4), seed=8).get_params()
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+    (w0, b0), (w1, b1) = split_params(a, ch)
+    assert np.all(b0 == 0) and np.all(b1 == 0)
+    sd = np.sqrt(2.0 / (27 * 8))
+    assert abs(w0.std() / sd - 1) < 0.05 and abs(w0.mean()) < 0.05 * sd
+
+
+def test_mse_and_adam_match_reference():
+    from paper_1009_4975_amd import binding
+    ch = [2, 3]
+    net = binding.Net(ch, (5, 4, 3), max_batch=1, seed=1)
+    rng = np.random.default_rng(2)
+    n = 3 * 3 * 4 * 5
+    pred = rng.normal(size=n).astype(np.float32)
+    tgt = rng.normal(size=n).astype(np.float32)
+    mask = (rng.random(n) < 0.7).astype(np.uint8)
+    dp = torch.empty(n, dtype=torch.float32, device="cuda")
+    loss = net.mse(dev(pred, torch.float32), dev(tgt, torch.float32), dp, mask=dev(mask, torch.uint8))
+    wl, wg = onet.mse(pred.astype(np.float64), tgt.astype(np.float64), mask.astype(bool))
+    assert loss == pytest.approx(wl, rel=1e-12)
+    assert rel(host(dp), wg) < 1e-6
+    # two Adam steps from the library's own gradients
+    p = net.get_params().astype(np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    x = dev(rng.normal(size=(1, 2, 3, 4, 5)), torch.float32)
+    out = torch.empty(1, 3, 3, 4, 5, dtype=torch.float32, device="cuda")
+    for t in (1, 2):
+        net.forward(x, out)
+        net.backward(dev(rng.normal(size=(1, 3, 3, 4, 5)), torch.float32))
+        g = net.get_grads().astype(np.float64)
+        net.adam(1e-2, t)
+        p, m, v = onet.adam(p, g, m, v, t, 1e-2)
+        assert np.abs(net.get_params() - p).max() < 1e-6
+
+
+# ---------------------------------------------------------------------- grid transfers
+def _transfer_case(kind):
+    if kind == "uniform":
+        pair = cases.uniform_pair((6, 3, 9))
+        return pair, [1, 3]
+    pair = cases.octree_pair((4, 2, 2), 2)
+    return pair, [1, 2, 4]
+
+
+@pytest.mark.parametrize("kind", ["uniform", "octree"])
+def test_grid_transfers_match_reference(kind):
+    from paper_1009_4975_amd import binding
+    pair, cells = _transfer_case(kind)
+    o = pair.orc
+    rng = np.random.default_rng(3)
+    rho_o = rng.random(o.n_elems)
+    u_o = (o.Tn @ rng.normal(size=(o.n_nodes, 3))).ravel()  # hanging values follow Eq. (6)
+    ctx = binding.Context(0)
+    ctx.upload_mesh(pair.lib_mesh)
+    nx, ny, nz = o.dims
+    for cell in cells:
+        G = (nz // cell + 1, ny // cell + 1, nx // cell + 1)
+        rg = torch.empty(G, dtype=torch.float32, device="cuda")
+        ug = torch.empty((3,) + G, dtype=torch.float32, device="cuda")
+        ctx.grid_from_mesh(cell, rho=dev(pair.to_lib_elems(rho_o)), u=dev(pair.to_lib_nodes(u_o)), u_scale=0.5,
+                           rho_grid=rg, u_grid=ug)
+        assert rel(host(rg), ogrid.grid_density(o, rho_o, cell)) < 1e-6
+        assert rel(host(ug), ogrid.grid_sample(o, u_o, cell, 0.5)) < 1e-6
+        g_in = rng.normal(size=(3,) + G).astype(np.float32)
+        um = torch.empty(3 * o.n_nodes, dtype=torch.float64, device="cuda")
+        ctx.grid_to_mesh(cell, dev(g_in, torch.float32), um, scale=2.0)
+        want = ogrid.grid_interp(g_in.astype(np.float64), cell, pair.lib_mesh.node_xyz, 2.0)
+        assert rel(host(um), want) < 1e-12
+
+
+# ---------------------------------------------------------------------- energy combination, coarse space
+@pytest.fixture(scope="module")
+def c1_small():
+    from paper_1009_4975_amd import binding
+    dims = (16, 8, 8)
+    pair = cases.uniform_pair(dims)
+    rho = cases.c1_density(dims)
+    sysm = cases.oracle_system(pair, rho)
+    ut = osys.solve_direct(sysm)
+    ctx = binding.Context(0)
+    ctx.upload_mesh(pair.lib_mesh)
+    ctx.set_density(dev(rho))
+    return pair, rho, sysm, ut, ctx
+
+
+def test_energy_combine_is_energy_optimal(c1_small):
+    pair, rho, sysm, ut, ctx = c1_small
+    rng = np.random.default_rng(4)
+    free = sysm.free
+    v1 = np.where(free, ut * (1 + 0.1 * rng.normal(size=ut.shape)), 0.0)
+    v2 = np.where(free, rng.normal(size=ut.shape) * np.abs(ut).max(), 0.0)
+    V = np.stack([v1, v2], axis=1)
+    G = V.T @ (sysm.A @ V)
+    a_want = np.linalg.solve(G, V.T @ sysm.b)
+    x0 = torch.empty(len(ut), dtype=torch.float64, device="cuda")
+    coef = ctx.energy_combine(dev(sysm.b), [dev(v1), dev(v2)], x0)
+    assert np.allclose(coef, a_want, rtol=1e-9, atol=1e-12)
+    assert rel(host(x0), V @ a_want) < 1e-10
+
+
+def test_coarse_pcg_matches_direct_and_cuts_iterations(c1_small):
+    from paper_1009_4975_amd import binding
+    pair, rho, sysm, ut, ctx = c1_small
+    b = dev(sysm.b)
+    u_ref = osys.recover(sysm, ut)
+
+    def solve(**kw):
+        u = torch.zeros(len(ut), dtype=torch.float64, device="cuda")
+        st = ctx.pcg(b, u, rtol=1e-12, **kw)
+        return host(u), st
+
+    u0, st0 = solve()
+    # exact solution as the field: it lies in range(Z)
+    ctx.coarse_setup([dev(ut)], 2, 1, 1)
+    u1, st1 = solve()
+    # a poor (random) coarse space: still an SPD preconditioner
+    rng = np.random.default_rng(5)
+    kept = ctx.coarse_setup([dev(rng.normal(size=len(ut))), dev(rng.normal(size=len(ut)))], 2, 2, 2)
+    assert kept == 48
+    u2, st2 = solve()
+    u3, st3 = solve(inner_prec=binding.FP32)
+    u4, st4 = solve(use_coarse=False)
+    for u in (u0, u1, u2, u3, u4):
+        assert rel(u, u_ref) < 1e-8
+    assert st1["iters"] < st0["iters"]
+    # plain Jacobi again (iteration counts move by a step or two with the LDS accumulation order)
+    assert abs(st4["iters"] - st0["iters"]) <= 2
+    # a new density drops the coarse space
+    ctx.set_density(dev(rho))
+    _, st5 = solve()
+    assert abs(st5["iters"] - st0["iters"]) <= 2
+
+
+def test_coarse_setup_drops_dependent_columns(c1_small):
+    pair, rho, sysm, ut, ctx = c1_small
+    f = np.where(sysm.free, ut, 0.0)
+    kept = ctx.coarse_setup([dev(f), dev(2 * f), dev(np.zeros_like(f))], 1, 1, 1)
+    assert kept == 3
+    ctx.set_density(dev(rho))
+
+
+# ---------------------------------------------------------------------- learned gain
+def test_learned_warm_start_and_coarse_space_gain():
+    """Small adaptive bridge run: train on iterations 1-10, then compare the
+    solves of iterations 11-15 with the plain warm start (previous solution).
+    The network must fit its training pairs better than the no-change
+    prediction; the learned start with the affine coarse space must reach the
+    same designs in fewer iterations."""
+    from paper_1009_4975_amd.learned import LearnedWarmStart
+    from paper_1009_4975_amd.simp import AdaptiveSIMP
+    base, L = (8, 4, 4), 2
+    dims = tuple(x << L for x in base)
+    fixed, load = synth.bridge_bc(*dims)
+    plain = AdaptiveSIMP(base, L, fixed, load, rtol=1e-8)
+    lrn = AdaptiveSIMP(base, L, fixed, load, rtol=1e-8)
+    ws = LearnedWarmStart(dims, cell=2, hidden=8, layers=3, epochs=150, regions=(2, 2, 2), coarse="affine")
+    for _ in range(10):
+        rp = plain.step()
+        rl = lrn.step(warm_start=ws.collect_before, after_solve=ws.collect_after)
+        # same solves (LDS accumulation order may move the count by one or two)
+        assert abs(rl["iters"] - rp["iters"]) <= max(2, rp["iters"] // 20)
+    assert ws.n_pairs == 9
+    base_loss = ws.baseline_loss()
+    final = ws.train()
+    assert final < 0.5 * base_loss
+    it_plain = it_lrn = 0
+    for _ in range(5):
+        rp = plain.step()
+        rl = lrn.step(warm_start=ws.warm_start)
+        assert ws.last["kept"] > 0
+        assert rl["rel_res"] <= 1e-8 and rp["rel_res"] <= 1e-8
+        assert rl["compliance"] == pytest.approx(rp["compliance"], rel=1e-5)
+        it_plain += rp["iters"]
+        it_lrn += rl["iters"]
+    assert it_lrn < 0.85 * it_plain
