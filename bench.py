@@ -20,6 +20,7 @@ oracle on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
@@ -33,7 +34,37 @@ sys.path.insert(0, ROOT)
 
 METRIC = "K(ρ)u=f solve ms to 1e-8 rel-res; stiffness-apply GB/s; learned+mixed vs FP64"
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
+FP64_PEAK_TFLOPS = 78.6  # FP64 vector: 256 CUs x 2.4 GHz x 128 flop/clk
+APPLY_SOURCES = ("paper_1009_4975_amd/csrc/apply.hip", "paper_1009_4975_amd/csrc/kernels.h",
+                 "paper_1009_4975_amd/csrc/internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_octree_c2_traffic.txt")
+
+
+def apply_source_hash():
+    h = hashlib.sha1()
+    for rel in APPLY_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the octree FP64 apply from the committed counter
+    summary, or None when the kernel sources changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != apply_source_hash():
+        return None
+    try:
+        return float(kv["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -80,6 +111,8 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the uniform 192x96x96 apply measurement")
     ap.add_argument("--profile-only", action="store_true", help="only the timed steps (for profilers)")
     ap.add_argument("--c3-only", action="store_true", help="only the uniform 192x96x96 apply measurement")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the C2 apply loop and a copy kernel of known size (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (--gpus 1); multi-GPU runs are not supported.",
@@ -115,6 +148,18 @@ def main():
     ctx.project_rhs(f, b)
 
     precs = {"fp64": binding.FP64, "fp32": binding.FP32, "bf16": binding.BF16}
+    if args.roofline_only:
+        x = torch.randn_like(f)
+        y = torch.empty_like(f)
+        ms = event_time(torch, lambda: ctx.apply(x, y, binding.FP64), 50)
+        log(f"[bench] C2 FP64 apply: {ms * 1e3:.2f} us/launch")
+        # calibration: a plain device copy of 256 MiB (reads and writes 268,435,456 bytes each)
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        c = torch.empty_like(a)
+        ms_c = event_time(torch, lambda: c.copy_(a), 10)
+        log(f"[bench] copy 256 MiB: {ms_c * 1e3:.1f} us ({2 * a.numel() * 8 / ms_c / 1e6:.0f} GB/s)")
+        log(f"[bench] apply source hash {apply_source_hash()}")
+        return
 
     def solve(name):
         u.zero_()
@@ -171,10 +216,12 @@ def main():
     ne, nn = mesh.n_elems, mesh.n_nodes
     flops = 1152.0 * ne
     log(f"[bench] C2 FP64 apply: {apply_ms * 1e3:.2f} us/launch ({flops / apply_ms / 1e9:.2f} TFLOP/s)")
-    roofline = dict(bound="mfma", achieved=round(flops / (apply_ms * 1e-3) / 1e12, 4), peak=FP64_PEAK_TFLOPS,
+    traffic = measured_traffic()
+    roofline = dict(bound="alu", achieved=round(flops / (apply_ms * 1e-3) / 1e12, 4), peak=FP64_PEAK_TFLOPS,
                     unit="TFLOP/s", frac=round(flops / (apply_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 5),
-                    traffic=None, kernel="octree FP64 stiffness apply (chunk kernel + shared-node pass)",
-                    per_launch_us=round(apply_ms * 1e3, 3), flop_per_element=1152, elements=ne)
+                    traffic=traffic, kernel="octree FP64 stiffness apply (k_apply_chunks, FP64)",
+                    per_launch_us=round(apply_ms * 1e3, 3), flop_per_element=1152, elements=ne,
+                    traffic_unit="bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)")
 
     # --- uniform 192x96x96 apply bandwidth
     c3 = None
