@@ -224,8 +224,8 @@ int amrto_mask(amrto_ctx* ctx, double* x_dev);
  * (y,z,x), (z,x,y) (centred coordinates; per region they span the rigid
  * motions and the constant strains), then the n_fields caller fields
  * (fields_host: host array of device pointers to 3n FP64 vectors; copied).
- * Every field is masked (zero on supported and hanging DOFs).  k = 3 rx ry rz
- * (4 affine + n_fields) <= 96.  Z^T A~ Z is formed by k operator applications
+ * Every field is masked (zero on supported and hanging DOFs).  At most 8
+ * fields in all, and k = 3 rx ry rz (4 affine + n_fields) <= 96.  Z^T A~ Z is formed by k operator applications
  * and factorised on the host, dropping columns whose pivot falls below 1e-12
  * of the largest (*k_kept receives the rank kept; may be NULL).  Needs the
  * density set; amrto_set_density drops the coarse space.

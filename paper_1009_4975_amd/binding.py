@@ -226,9 +226,12 @@ class Octree:
         return rc
 
     def __del__(self):
-        if getattr(self, "h", None) and self.h.value:
-            self.lib.amrto_octree_destroy(self.h)
-            self.h = _p()
+        try:
+            if getattr(self, "h", None) and self.h.value:
+                self.lib.amrto_octree_destroy(self.h)
+                self.h = _p()
+        except Exception:  # interpreter shutdown: ctypes may already be gone
+            pass
 
     def leaves(self):
         n = self.lib.amrto_octree_n_leaves(self.h)
@@ -313,9 +316,12 @@ class Context:
         self.mesh: Optional[MeshArrays] = None
 
     def __del__(self):
-        if getattr(self, "h", None) and self.h.value:
-            self.lib.amrto_destroy(self.h)
-            self.h = _p()
+        try:
+            if getattr(self, "h", None) and self.h.value:
+                self.lib.amrto_destroy(self.h)
+                self.h = _p()
+        except Exception:  # interpreter shutdown: ctypes may already be gone
+            pass
 
     def _chk(self, rc, allow_not_converged=False):
         if rc < 0 or (rc > 0 and not allow_not_converged):
@@ -442,9 +448,12 @@ class Net:
         self.h = h
 
     def __del__(self):
-        if getattr(self, "h", None):
-            self.lib.amrto_net_destroy(self.h)
-            self.h = None
+        try:
+            if getattr(self, "h", None):
+                self.lib.amrto_net_destroy(self.h)
+                self.h = None
+        except Exception:  # interpreter shutdown: ctypes may already be gone
+            pass
 
     def _chk(self, rc):
         if rc != 0:

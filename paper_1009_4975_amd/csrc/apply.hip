@@ -307,19 +307,47 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, CgA
   const int t0 = ca.chunk_tab[c], nt = ca.chunk_tab[c + 1] - t0;
   const int nown = ca.chunk_nown[c], nreg = ca.chunk_nreg[c], nhown = ca.chunk_nhown[c];
   const int h0 = ca.chunk_trip[c], nh = ca.chunk_trip[c + 1] - h0;
-  for (int i = tid; i < nt * 3; i += 256) {
-    const int t = i / 3, comp = i % 3;
-    VT v = 0;
-    if (t < nreg) {
-      const long g = 3L * ca.tab_node[t0 + t] + comp;
-      const uint8_t f = fix[g / 3];
-      VT xv = X[g];
-      if (FUSED && !first) xv += vbeta * PO[g];
-      v = ((f >> comp) & 1) ? (VT)0 : xv;
-    }
-    xs[i] = v;
-    ys[i] = 0.0;
+  // Table nodes t = tid + 256 r (r < NPT): global node, support bits and the
+  // staged values are loaded in one batch (no dependent round trips per
+  // component), and the indices stay in registers for the store phase.
+  constexpr int NPT = TAB_MAX / 256;
+  int gn[NPT];
+  uint8_t fb[NPT];
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) {
+    const int t = tid + 256 * r;
+    gn[r] = t < nt ? ca.tab_node[t0 + t] : -1;
   }
+  // entry metadata of the element loop, prefetched under the staging latency
+  constexpr int EPT = ENT_MAX / 256;
+  uint4 lvp[EPT];
+  int eel[EPT];
+#pragma unroll
+  for (int r = 0; r < EPT; ++r) {
+    const int en = tid + 256 * r;
+    eel[r] = en < nent ? ca.ent_elem[n0 + en] : 0;
+    lvp[r] = en < nent ? *reinterpret_cast<const uint4*>(ca.ent_loc + 8L * (n0 + en)) : make_uint4(0, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) {
+    const int t = tid + 256 * r;
+    fb[r] = 0;
+    if (t < nreg) {
+      const long g = 3L * gn[r];
+      const uint8_t f = fix[gn[r]];
+      fb[r] = f;
+      VT v0 = X[g], v1 = X[g + 1], v2 = X[g + 2];
+      if (FUSED && !first) {
+        v0 += vbeta * PO[g];
+        v1 += vbeta * PO[g + 1];
+        v2 += vbeta * PO[g + 2];
+      }
+      xs[3 * t + 0] = (f & 1) ? (VT)0 : v0;
+      xs[3 * t + 1] = (f & 2) ? (VT)0 : v1;
+      xs[3 * t + 2] = (f & 4) ? (VT)0 : v2;
+    }
+  }
+  for (int i = tid; i < nt * 3; i += 256) ys[i] = 0.0;
   if (PREC == P_BF16)
     for (int i = tid; i < nent * 8; i += 256) lsm[i] = ca.ent_loc[8L * n0 + i];
   __shared__ VT sB[PREC == P_F64 ? 72 : 1];  // FP64 block constants as LDS broadcasts
@@ -335,12 +363,18 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, CgA
   __syncthreads();
   if (PREC != P_BF16) {
     const VT* Bs = PREC == P_F64 ? (const VT*)sB : (const VT*)a.kb;
-    for (int en = tid; en < nent; en += 256) {
+    VT cep[EPT];
+#pragma unroll
+    for (int r = 0; r < EPT; ++r) cep[r] = coef[eel[r]];
+#pragma unroll
+    for (int r = 0; r < EPT; ++r) {
+      const int en = tid + 256 * r;
+      if (en >= nent) break;
       int loc[8];
-      const uint4 lv = *reinterpret_cast<const uint4*>(ca.ent_loc + 8L * (n0 + en));
+      const uint4 lv = lvp[r];
       loc[0] = lv.x & 0xffff; loc[1] = lv.x >> 16; loc[2] = lv.y & 0xffff; loc[3] = lv.y >> 16;
       loc[4] = lv.z & 0xffff; loc[5] = lv.z >> 16; loc[6] = lv.w & 0xffff; loc[7] = lv.w >> 16;
-      const VT ce = coef[ca.ent_elem[n0 + en]];
+      const VT ce = cep[r];
       VT u[24], out[24];
 #pragma unroll
       for (int aa = 0; aa < 8; ++aa) {
@@ -394,31 +428,35 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, CgA
   }
   __syncthreads();
   double dot = 0.0;
-  for (int i = tid; i < (nown + nhown) * 3; i += 256) {
-    int t = i / 3;
-    const int comp = i % 3;
-    const bool hang = t >= nown;
-    if (hang) t = nreg + (t - nown);
-    const long g = 3L * ca.tab_node[t0 + t] + comp;
-    if (hang) {  // identity row; in a solve the hanging entries stay zero
-      if (FUSED) {
-        PN[g] = 0;
-        Y[g] = 0;
-      } else {
-        Y[g] = X[g];
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) {
+    const int t = tid + 256 * r;
+    const bool own_reg = t < nown, own_hang = t >= nreg && t < nreg + nhown;
+    if (!own_reg && !own_hang) continue;
+    const long g = 3L * gn[r];
+    if (own_hang) {  // identity row; in a solve the hanging entries stay zero
+      for (int comp = 0; comp < 3; ++comp) {
+        if (FUSED) {
+          PN[g + comp] = 0;
+          Y[g + comp] = 0;
+        } else {
+          Y[g + comp] = X[g + comp];
+        }
       }
       continue;
     }
-    const VT acc = (VT)ys[t * 3 + comp];
-    const bool fixed = (fix[g / 3] >> comp) & 1;
-    if (FUSED) {
-      const VT pn = xs[t * 3 + comp];
-      const VT q = fixed ? (VT)0 : acc;
-      PN[g] = pn;
-      Y[g] = q;
-      dot += (double)pn * (double)q;
-    } else {
-      Y[g] = fixed ? X[g] : acc;
+    for (int comp = 0; comp < 3; ++comp) {
+      const VT acc = (VT)ys[t * 3 + comp];
+      const bool fixed = (fb[r] >> comp) & 1;
+      if (FUSED) {
+        const VT pn = xs[t * 3 + comp];
+        const VT q = fixed ? (VT)0 : acc;
+        PN[g + comp] = pn;
+        Y[g + comp] = q;
+        dot += (double)pn * (double)q;
+      } else {
+        Y[g + comp] = fixed ? X[g + comp] : acc;
+      }
     }
   }
   if (FUSED) {
@@ -469,31 +507,41 @@ __global__ __launch_bounds__(256) void k_diag_chunks(double* __restrict__ dinv, 
   const int h0 = ca.chunk_trip[c], nh = ca.chunk_trip[c + 1] - h0;
   for (int i = tid; i < nt * 3; i += 256) ds[i] = 0.0;
   __syncthreads();
+  // vertex aa of an entry maps to the masters [kb, ke) of its hanging table
+  // entry, or to itself (kb = -1) when regular
+  auto range = [&](int l, int& kb, int& ke) {
+    if (l < nreg) {
+      kb = -1; ke = 0;
+    } else {
+      kb = ca.tab_hbeg[t0 + l];
+      ke = l + 1 < nt ? ca.tab_hbeg[t0 + l + 1] : nh;
+    }
+  };
   for (int en = tid; en < nent; en += 256) {
-    int ent_m[64], ent_a[64];
-    double ent_w[64];
-    int ne = 0;
+    int loc[8];
+    const uint4 lv = *reinterpret_cast<const uint4*>(ca.ent_loc + 8L * (n0 + en));
+    loc[0] = lv.x & 0xffff; loc[1] = lv.x >> 16; loc[2] = lv.y & 0xffff; loc[3] = lv.y >> 16;
+    loc[4] = lv.z & 0xffff; loc[5] = lv.z >> 16; loc[6] = lv.w & 0xffff; loc[7] = lv.w >> 16;
+    const double ce = coef[ca.ent_elem[n0 + en]];
     for (int aa = 0; aa < 8; ++aa) {
-      const int l = ca.ent_loc[8L * (n0 + en) + aa];
-      if (l < nreg) {
-        ent_m[ne] = l; ent_a[ne] = aa; ent_w[ne] = 1.0; ++ne;
-      } else {
-        for (int k = 0; k < nh && ne < 64; ++k) {
-          const uint32_t hm = ca.trip_hm[h0 + k];
-          if ((int)(hm >> 16) == l) {
-            ent_m[ne] = hm & 0xffff; ent_a[ne] = aa; ent_w[ne] = ca.trip_w[h0 + k]; ++ne;
+      int ka, kae;
+      range(loc[aa], ka, kae);
+      for (int k = ka; k < (ka < 0 ? 0 : kae); ++k) {
+        const int ma = ka < 0 ? loc[aa] : (int)(ca.trip_hm[h0 + k] & 0xffff);
+        const double wa = ka < 0 ? 1.0 : ca.trip_w[h0 + k];
+        if (ma >= nown) continue;  // only owned rows are written
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int bb = 0; bb < 8; ++bb) {
+          int kb, kbe;
+          range(loc[bb], kb, kbe);
+          for (int j = kb; j < (kb < 0 ? 0 : kbe); ++j) {
+            const int mb = kb < 0 ? loc[bb] : (int)(ca.trip_hm[h0 + j] & 0xffff);
+            if (mb != ma) continue;
+            const double w = wa * (kb < 0 ? 1.0 : ca.trip_w[h0 + j]);
+            for (int cc = 0; cc < 3; ++cc) acc[cc] += w * K0[(3 * aa + cc) * 24 + 3 * bb + cc];
           }
         }
-      }
-    }
-    const double ce = coef[ca.ent_elem[n0 + en]];
-    for (int p = 0; p < ne; ++p) {
-      if (ent_m[p] >= nown) continue;  // only owned rows are written
-      for (int q = 0; q < ne; ++q) {
-        if (ent_m[p] != ent_m[q]) continue;
-        const double w = ce * ent_w[p] * ent_w[q];
-        for (int cc = 0; cc < 3; ++cc)
-          atomicAdd(&ds[ent_m[p] * 3 + cc], w * K0[(3 * ent_a[p] + cc) * 24 + 3 * ent_a[q] + cc]);
+        for (int cc = 0; cc < 3; ++cc) atomicAdd(&ds[ma * 3 + cc], ce * acc[cc]);
       }
     }
   }

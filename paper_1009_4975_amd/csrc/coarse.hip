@@ -80,14 +80,16 @@ __global__ __launch_bounds__(256) void k_axpy_set(double a, const double* __rest
   x[i] = first ? a * v[i] : fma(a, v[i], x[i]);
 }
 
-// E[i k + j] = sum over blocks of part[i RED_BLOCKS + block] (fixed order)
+// E[i k + j] = sum over blocks of part[block k + i]; one block per row i
+// (deterministic tree)
 __global__ __launch_bounds__(256) void k_gram_column(const double* __restrict__ part, int k, int j,
                                                      double* __restrict__ E) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= k) return;
-  double s = 0.0;
-  for (int b = 0; b < RED_BLOCKS; ++b) s += part[(long)i * RED_BLOCKS + b];
-  E[(long)i * k + j] = s;
+  __shared__ double sh[8];
+  const int i = blockIdx.x;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < RED_BLOCKS; b += blockDim.x) v += part[(long)b * k + i];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) E[(long)i * k + j] = v;
 }
 
 __global__ __launch_bounds__(256) void k_dot2_part(const double* __restrict__ a, const double* __restrict__ b, long n,
@@ -159,9 +161,10 @@ int amrto_coarse_setup(amrto_ctx* ctx, int32_t affine, const double* const* fiel
   const int nf = (affine ? 4 : 0) + n_fields;
   const int R = rx * ry * rz;
   const int k = 3 * nf * R;
-  if (n_fields < 0 || (n_fields > 0 && !fields) || nf < 1 || rx < 1 || ry < 1 || rz < 1 || R > 255 ||
-      k > COARSE_KMAX)
-    return ctx->fail(AMRTO_EINVAL, "amrto_coarse_setup: need 1 <= 3 (4 affine + n_fields) rx ry rz <= 96");
+  if (n_fields < 0 || (n_fields > 0 && !fields) || nf < 1 || nf > COARSE_NFMAX || rx < 1 || ry < 1 || rz < 1 ||
+      R > 255 || k > COARSE_KMAX)
+    return ctx->fail(AMRTO_EINVAL,
+                     "amrto_coarse_setup: need at most 8 fields and 1 <= 3 (4 affine + n_fields) rx ry rz <= 96");
   AMRTO_HIP(hipSetDevice(ctx->device));
   ctx->coarse_k = 0;  // no coarse space unless this setup completes
   const long n3 = 3L * ctx->n_nodes;
@@ -198,6 +201,8 @@ int amrto_coarse_setup(amrto_ctx* ctx, int32_t affine, const double* const* fiel
                      rx, ry, rz, ctx->d_region);
   if (!ctx->d_cpart) AMRTO_HIP(hipMalloc((void**)&ctx->d_cpart, COARSE_KMAX * RED_BLOCKS * sizeof(double)));
   if (!ctx->d_cinv) AMRTO_HIP(hipMalloc((void**)&ctx->d_cinv, COARSE_KMAX * COARSE_KMAX * sizeof(double)));
+  if (!ctx->d_cz) AMRTO_HIP(hipMalloc((void**)&ctx->d_cz, COARSE_KMAX * sizeof(double)));
+  if (!ctx->d_ct) AMRTO_HIP(hipMalloc((void**)&ctx->d_ct, COARSE_KMAX * sizeof(double)));
   // E[:, j] = Z^T A~ z_j, gathered on the device (d_cinv holds E until the inverse replaces it)
   const int g1 = (int)((n3 + 255) / 256);
   for (int j = 0; j < k; ++j) {
@@ -208,7 +213,7 @@ int amrto_coarse_setup(amrto_ctx* ctx, int32_t affine, const double* const* fiel
     if (rc) return rc;
     rc = launch_zt(ctx, ctx->d_q);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_gram_column, dim3(1), dim3(128), 0, ctx->stream, ctx->d_cpart, k, j, ctx->d_cinv);
+    hipLaunchKernelGGL(k_gram_column, dim3(k), dim3(256), 0, ctx->stream, ctx->d_cpart, k, j, ctx->d_cinv);
   }
   std::vector<double> E((long)k * k);
   AMRTO_HIP(hipMemcpyAsync(E.data(), ctx->d_cinv, E.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));

@@ -39,6 +39,7 @@ constexpr int RED_BLOCKS = 256;
 constexpr int RED_THREADS = 256;
 constexpr int OC_WS = 2 + 256 * 256 + 64;
 constexpr int COARSE_KMAX = 96;  // coarse-space columns
+constexpr int COARSE_NFMAX = 8;  // coarse-space fields (4 affine + caller fields)
 
 template <typename T>
 struct DevArray {
@@ -146,8 +147,10 @@ struct amrto_ctx {
   int coarse_k = 0, coarse_nf = 0, coarse_R = 0, coarse_cap = 0;
   double* d_cf = nullptr;      // n_fields x 3n fields (masked)
   uint8_t* d_region = nullptr; // region of each node
-  double* d_cpart = nullptr;   // COARSE_KMAX x RED_BLOCKS partials
+  double* d_cpart = nullptr;   // RED_BLOCKS x COARSE_KMAX partials (block-major)
   double* d_cinv = nullptr;    // E^-1 (k x k)
+  double* d_ct = nullptr;      // Z^T r of the current iteration
+  double* d_cz = nullptr;      // E^-1 Z^T r
   // mesh <-> grid transfers (net.hip)
   int grid_cell = 0;
   int32_t* d_node_xyz = nullptr;

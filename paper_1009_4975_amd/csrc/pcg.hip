@@ -116,7 +116,97 @@ __global__ __launch_bounds__(256) void k_cg_update(VT* __restrict__ x, VT* __res
   }
 }
 
-// partials of Z^T v: part[j * RED_BLOCKS + block]
+// ------------------------------------------------------------------ coarse space
+// Z^T v per block.  Each block takes a contiguous DOF range and walks it in
+// steps of the block size, so a thread's DOFs stay in one region for long
+// stretches: the thread keeps 3 nf running sums in registers for its current
+// region and adds them to the block's LDS accumulator only when its region
+// changes and at the end (then, when the whole wavefront is in one region,
+// after a wavefront reduction).  Fields beyond COARSE_NFMAX are rejected at
+// set-up, so the register sums have a fixed size.
+struct ZtAcc {
+  double s[COARSE_NFMAX][3];
+  int g;
+};
+
+__device__ __forceinline__ void zt_clear(ZtAcc& a, int g) {
+#pragma unroll
+  for (int f = 0; f < COARSE_NFMAX; ++f)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.s[f][c] = 0.0;
+  a.g = g;
+}
+
+__device__ __forceinline__ void zt_flush_lane(ZtAcc& a, double* acc, int nf, int R) {
+  if (a.g < 0) return;
+#pragma unroll
+  for (int f = 0; f < COARSE_NFMAX; ++f)
+    if (f < nf)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        if (a.s[f][c] != 0.0) atomicAdd(&acc[(f * R + a.g) * 3 + c], a.s[f][c]);
+}
+
+// add v F_f[i] (f < nf) for DOF i of component c in region g; fv holds the
+// field values, loaded by the caller ahead of the arithmetic
+__device__ __forceinline__ void zt_add(ZtAcc& a, double* acc, const double (&fv)[COARSE_NFMAX], int nf, int R, int g,
+                                       int c, double vi) {
+  if (g != a.g) {
+    zt_flush_lane(a, acc, nf, R);
+    zt_clear(a, g);
+  }
+#pragma unroll
+  for (int f = 0; f < COARSE_NFMAX; ++f) {
+    const double v = fv[f] * vi;
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) a.s[f][cc] += cc == c ? v : 0.0;
+  }
+}
+
+__device__ __forceinline__ void load_fields(double (&fv)[COARSE_NFMAX], const double* __restrict__ F, int nf, long n3,
+                                            long i) {
+#pragma unroll
+  for (int f = 0; f < COARSE_NFMAX; ++f) fv[f] = f < nf ? F[(long)f * n3 + i] : 0.0;
+}
+
+// End of the block's range.  When every thread's sums belong to the region of
+// the block's first DOF (the usual case), they are transposed through LDS and
+// each of the 3 nf columns is summed by one thread in thread order (no atomics,
+// deterministic); otherwise each thread adds its own sums atomically.
+__device__ __forceinline__ void zt_flush(ZtAcc& a, double* acc, int nf, int R, int g_first,
+                                         double (*red)[256]) {
+  const bool uniform = __syncthreads_and(a.g == g_first || a.g < 0);
+  if (!uniform) {
+    zt_flush_lane(a, acc, nf, R);
+    return;
+  }
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int f = 0; f < COARSE_NFMAX; ++f)
+    if (f < nf)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) red[f * 3 + c][t] = a.g < 0 ? 0.0 : a.s[f][c];
+  __syncthreads();
+  if (t < 3 * nf) {
+    double s = 0.0;
+#pragma unroll 8
+    for (int u = 0; u < 256; ++u) s += red[t][u];
+    acc[((t / 3) * R + g_first) * 3 + t % 3] += s;  // one writer per column; earlier flushes are done
+  }
+}
+
+// block b's DOF range [lo, hi)
+__device__ __forceinline__ void block_range(long n, long& lo, long& hi) {
+  const long per = (n + gridDim.x - 1) / gridDim.x;
+  lo = blockIdx.x * per;
+  hi = lo + per < n ? lo + per : n;
+}
+
+// Write this block's Z^T v partials (block-major: part[block k + j]).
+__device__ __forceinline__ void zt_store(const double* acc, int k, double* __restrict__ part) {
+  for (int j = threadIdx.x; j < k; j += blockDim.x) part[(long)blockIdx.x * k + j] = acc[j];
+}
+
 template <typename VT>
 __global__ __launch_bounds__(256) void k_zt_part(const double* __restrict__ F, int nf, const uint8_t* __restrict__ region,
                                                  int R, const VT* __restrict__ v, long n3, double* __restrict__ part) {
@@ -124,19 +214,26 @@ __global__ __launch_bounds__(256) void k_zt_part(const double* __restrict__ F, i
   const int k = 3 * nf * R;
   for (int j = threadIdx.x; j < k; j += blockDim.x) acc[j] = 0.0;
   __syncthreads();
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n3; i += (long)gridDim.x * blockDim.x) {
+  __shared__ double red[COARSE_NFMAX * 3][256];
+  long lo, hi;
+  block_range(n3, lo, hi);
+  ZtAcc a;
+  zt_clear(a, -1);
+#pragma unroll 2
+  for (long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    double fv[COARSE_NFMAX];
+    load_fields(fv, F, nf, n3, i);
     const double vi = (double)v[i];
-    if (vi == 0.0) continue;
-    const int g = region[i / 3], c = (int)(i % 3);
-    for (int f = 0; f < nf; ++f) atomicAdd(&acc[(f * R + g) * 3 + c], F[(long)f * n3 + i] * vi);
+    const int g = region[i / 3];
+    zt_add(a, acc, fv, nf, R, g, (int)(i % 3), vi);
   }
+  zt_flush(a, acc, nf, R, lo < hi ? region[lo / 3] : 0, red);
   __syncthreads();
-  for (int j = threadIdx.x; j < k; j += blockDim.x) part[(long)j * RED_BLOCKS + blockIdx.x] = acc[j];
+  zt_store(acc, k, part);
 }
 
-
 // Coarse-corrected variant of the update pass: x += alpha p, r -= alpha q and
-// partials of Z^T r (z is formed afterwards by k_coarse_z).
+// the block partials of Z^T r (then k_coarse_sum, k_coarse_cz, k_coarse_z).
 template <typename VT>
 __global__ __launch_bounds__(256) void k_cg_update_coarse(VT* __restrict__ x, VT* __restrict__ r,
                                                           const VT* __restrict__ p, const VT* __restrict__ q, long n,
@@ -156,42 +253,75 @@ __global__ __launch_bounds__(256) void k_cg_update_coarse(VT* __restrict__ x, VT
   }
   for (int j = threadIdx.x; j < k; j += blockDim.x) acc[j] = 0.0;
   __syncthreads();
+  __shared__ double red[COARSE_NFMAX * 3][256];
   const VT alpha = (VT)(rz / pq);
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    x[i] += alpha * p[i];
-    const VT ri = r[i] - alpha * q[i];
-    r[i] = ri;
-    if (ri != (VT)0) {
-      const int g = region[i / 3], c = (int)(i % 3);
-      for (int f = 0; f < nf; ++f) atomicAdd(&acc[(f * R + g) * 3 + c], F[(long)f * n + i] * (double)ri);
-    }
+  long lo, hi;
+  block_range(n, lo, hi);
+  ZtAcc a;
+  zt_clear(a, -1);
+#pragma unroll 2
+  for (long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    double fv[COARSE_NFMAX];
+    load_fields(fv, F, nf, n, i);
+    const VT pi = p[i], qi = q[i], ri = r[i], xi = x[i];
+    const int g = region[i / 3];
+    x[i] = xi + alpha * pi;
+    const VT rv = ri - alpha * qi;
+    r[i] = rv;
+    zt_add(a, acc, fv, nf, R, g, (int)(i % 3), (double)rv);
   }
+  zt_flush(a, acc, nf, R, lo < hi ? region[lo / 3] : 0, red);
   __syncthreads();
-  for (int j = threadIdx.x; j < k; j += blockDim.x) part_z[(long)j * RED_BLOCKS + blockIdx.x] = acc[j];
+  zt_store(acc, k, part_z);
 }
 
-// z = D^-1 r + Z E^-1 (Z^T r); partials r.z, r.r
+// ct[j] = sum_b part[b k + j]: one block per coarse column, fixed-tree sum
+// (deterministic).
+__global__ __launch_bounds__(256) void k_coarse_sum(const double* __restrict__ part, int k, int nblk,
+                                                    double* __restrict__ ct, const double* __restrict__ stop) {
+  if (stop && *stop != 0.0) return;
+  __shared__ double sh[8];
+  const int j = blockIdx.x;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) v += part[(long)b * k + j];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) ct[j] = v;
+}
+
+// cz = E^-1 ct in one block: thread j walks column j of the symmetric E^-1
+// (row i of E^-1 is read coalesced across threads).
+__global__ __launch_bounds__(128) void k_coarse_cz(const double* __restrict__ ct_g, int k,
+                                                   const double* __restrict__ Einv, double* __restrict__ cz,
+                                                   const double* __restrict__ stop) {
+  if (stop && *stop != 0.0) return;
+  __shared__ double ct[COARSE_KMAX];
+  for (int i = threadIdx.x; i < k; i += blockDim.x) ct[i] = ct_g[i];
+  __syncthreads();
+  const int j = threadIdx.x;
+  if (j >= k) return;
+  double s0 = 0.0, s1 = 0.0;
+  int i = 0;
+#pragma unroll 4
+  for (; i + 1 < k; i += 2) {
+    s0 += Einv[(long)i * k + j] * ct[i];
+    s1 += Einv[(long)(i + 1) * k + j] * ct[i + 1];
+  }
+  if (i < k) s0 += Einv[(long)i * k + j] * ct[i];
+  cz[j] = s0 + s1;
+}
+
+// z = D^-1 r + Z cz; partials r.z, r.r
 template <typename VT>
 __global__ __launch_bounds__(256) void k_coarse_z(const VT* __restrict__ r, VT* __restrict__ z,
-                                                  const VT* __restrict__ dinv, long n, const double* __restrict__ part_z,
-                                                  const double* __restrict__ Einv, const double* __restrict__ F, int nf,
+                                                  const VT* __restrict__ dinv, long n, const double* __restrict__ cz_g,
+                                                  const double* __restrict__ F, int nf,
                                                   const uint8_t* __restrict__ region, int R,
                                                   double* __restrict__ part, const double* __restrict__ stop) {
   if (stop && *stop != 0.0) return;
   __shared__ double sh[8];
-  __shared__ double ct[COARSE_KMAX], cz[COARSE_KMAX];
+  __shared__ double cz[COARSE_KMAX];
   const int k = 3 * nf * R;
-  for (int j = threadIdx.x; j < k; j += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < RED_BLOCKS; ++b) s += part_z[(long)j * RED_BLOCKS + b];
-    ct[j] = s;
-  }
-  __syncthreads();
-  for (int j = threadIdx.x; j < k; j += blockDim.x) {
-    double s = 0.0;
-    for (int i = 0; i < k; ++i) s += Einv[j * k + i] * ct[i];
-    cz[j] = s;
-  }
+  for (int j = threadIdx.x; j < k; j += blockDim.x) cz[j] = cz_g[j];
   __syncthreads();
   double srz = 0.0, srr = 0.0;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -269,9 +399,12 @@ static void coarse_init(amrto_ctx* ctx, const Vecs<VT>& v) {
   const long n3 = 3L * ctx->n_nodes;
   hipLaunchKernelGGL(k_zt_part<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, ctx->d_cf, ctx->coarse_nf,
                      ctx->d_region, ctx->coarse_R, v.r, n3, ctx->d_cpart);
-  hipLaunchKernelGGL(k_coarse_z<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, v.r, v.z, v.dinv, n3, ctx->d_cpart,
-                     ctx->d_cinv, ctx->d_cf, ctx->coarse_nf, ctx->d_region, ctx->coarse_R, ctx->d_part,
-                     (const double*)nullptr);
+  hipLaunchKernelGGL(k_coarse_sum, dim3(ctx->coarse_k), dim3(256), 0, ctx->stream, ctx->d_cpart, ctx->coarse_k,
+                     RED_BLOCKS, ctx->d_ct, (const double*)nullptr);
+  hipLaunchKernelGGL(k_coarse_cz, dim3(1), dim3(128), 0, ctx->stream, (const double*)ctx->d_ct, ctx->coarse_k,
+                     (const double*)ctx->d_cinv, ctx->d_cz, (const double*)nullptr);
+  hipLaunchKernelGGL(k_coarse_z<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, v.r, v.z, v.dinv, n3, ctx->d_cz,
+                     ctx->d_cf, ctx->coarse_nf, ctx->d_region, ctx->coarse_R, ctx->d_part, (const double*)nullptr);
 }
 
 int launch_zt(amrto_ctx* ctx, const double* v) {
@@ -319,8 +452,12 @@ static int enqueue_iters(amrto_ctx* ctx, const Vecs<VT>& v, VT* x, int prec, dou
       hipLaunchKernelGGL(k_cg_update_coarse<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew, v.q, n3,
                          ctx->d_partpq, ctx->n_partpq, ctx->d_scal, it, ctx->d_cf, ctx->coarse_nf, ctx->d_region,
                          ctx->coarse_R, ctx->d_cpart);
+      hipLaunchKernelGGL(k_coarse_sum, dim3(ctx->coarse_k), dim3(256), 0, ctx->stream, ctx->d_cpart,
+                         ctx->coarse_k, RED_BLOCKS, ctx->d_ct, ctx->d_scal + S_DONE);
+      hipLaunchKernelGGL(k_coarse_cz, dim3(1), dim3(128), 0, ctx->stream, (const double*)ctx->d_ct, ctx->coarse_k,
+                         (const double*)ctx->d_cinv, ctx->d_cz, ctx->d_scal + S_DONE);
       hipLaunchKernelGGL(k_coarse_z<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, v.r, v.z, v.dinv, n3,
-                         ctx->d_cpart, ctx->d_cinv, ctx->d_cf, ctx->coarse_nf, ctx->d_region, ctx->coarse_R,
+                         ctx->d_cz, ctx->d_cf, ctx->coarse_nf, ctx->d_region, ctx->coarse_R,
                          ctx->d_part, ctx->d_scal + S_DONE);
     } else {
       hipLaunchKernelGGL(k_cg_update<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew, v.q, v.dinv,
