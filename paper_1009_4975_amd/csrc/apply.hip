@@ -283,30 +283,26 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, CgA
   __shared__ double ys[TAB_MAX * 3];  // FP64 LDS accumulators (see k_apply_uniform)
   __shared__ uint16_t lsm[PREC == P_BF16 ? ENT_MAX * 8 : 1];
   __shared__ double sh[8];
-  double beta = 0.0;
-  if (FUSED) {
-    if (!cg_prologue(cg, beta, sh)) return;
-  } else if (a.stop && *a.stop != 0.0) {
-    return;
-  }
+  __shared__ uint32_t trip_hm_s[TRIP_MAX];
+  __shared__ double trip_w_s[TRIP_MAX];
+  __shared__ int hbeg_s[TAB_MAX];
   const int tid = threadIdx.x;
   const int c = xcd_remap(blockIdx.x, gridDim.x);
-  if (c >= ca.n_chunks) {
-    if (FUSED && tid == 0) cg.part_out[cg.part_base + blockIdx.x] = 0.0;
-    return;
-  }
+  if (!FUSED && a.stop && *a.stop != 0.0) return;
+  const bool have = c < ca.n_chunks;
+  const int cc = have ? c : 0;
   const VT* __restrict__ X = (const VT*)a.x;
   const VT* __restrict__ PO = (const VT*)a.pold;
   VT* __restrict__ Y = (VT*)a.y;
   VT* __restrict__ PN = (VT*)a.pnew;
   const VT* __restrict__ coef = (const VT*)a.coef;
   const uint8_t* __restrict__ fix = a.fix;
-  const VT vbeta = (VT)beta;
-  const bool first = FUSED && cg.it == 0;
-  const int n0 = ca.chunk_ent[c], nent = ca.chunk_ent[c + 1] - n0;
-  const int t0 = ca.chunk_tab[c], nt = ca.chunk_tab[c + 1] - t0;
-  const int nown = ca.chunk_nown[c], nreg = ca.chunk_nreg[c], nhown = ca.chunk_nhown[c];
-  const int h0 = ca.chunk_trip[c], nh = ca.chunk_trip[c + 1] - h0;
+  const int n0 = ca.chunk_ent[cc], nent = have ? ca.chunk_ent[cc + 1] - n0 : 0;
+  const int t0 = ca.chunk_tab[cc], nt = have ? ca.chunk_tab[cc + 1] - t0 : 0;
+  const int nown = ca.chunk_nown[cc], nreg = ca.chunk_nreg[cc], nhown = ca.chunk_nhown[cc];
+  const int h0 = ca.chunk_trip[cc], nh = have ? ca.chunk_trip[cc + 1] - h0 : 0;
+  // Every index this block needs is requested before the CG prologue (which
+  // waits on the previous pass's partial sums), so those round trips overlap.
   // Table nodes t = tid + 256 r (r < NPT): global node, support bits and the
   // staged values are loaded in one batch (no dependent round trips per
   // component), and the indices stay in registers for the store phase.
@@ -328,6 +324,25 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, CgA
     eel[r] = en < nent ? ca.ent_elem[n0 + en] : 0;
     lvp[r] = en < nent ? *reinterpret_cast<const uint4*>(ca.ent_loc + 8L * (n0 + en)) : make_uint4(0, 0, 0, 0);
   }
+  // hanging triples and per-entry triple ranges into LDS
+  for (int k = tid; k < nh; k += 256) {
+    trip_hm_s[k] = ca.trip_hm[h0 + k];
+    trip_w_s[k] = ca.trip_w[h0 + k];
+  }
+  for (int t = nreg + tid; t < nt; t += 256) hbeg_s[t - nreg] = ca.tab_hbeg[t0 + t];
+  double beta = 0.0;
+  if (FUSED) {
+    if (!cg_prologue(cg, beta, sh)) return;
+  }
+  if (!have) {
+    if (FUSED && tid == 0) cg.part_out[cg.part_base + blockIdx.x] = 0.0;
+    return;
+  }
+  const VT vbeta = (VT)beta;
+  const bool first = FUSED && cg.it == 0;
+  VT cep[EPT];
+#pragma unroll
+  for (int r = 0; r < EPT; ++r) cep[r] = coef[eel[r]];
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
     const int t = tid + 256 * r;
@@ -355,17 +370,14 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, CgA
   __syncthreads();
   for (int i = tid; i < (nt - nreg) * 3; i += 256) {  // x_h = sum_m w_hm x_m  (Eq. (6))
     const int t = nreg + i / 3, comp = i % 3;
-    const int kb = ca.tab_hbeg[t0 + t], ke = t + 1 < nt ? ca.tab_hbeg[t0 + t + 1] : nh;
+    const int kb = hbeg_s[t - nreg], ke = t + 1 < nt ? hbeg_s[t + 1 - nreg] : nh;
     double v = 0.0;
-    for (int k = kb; k < ke; ++k) v += ca.trip_w[h0 + k] * (double)xs[(ca.trip_hm[h0 + k] & 0xffff) * 3 + comp];
+    for (int k = kb; k < ke; ++k) v += trip_w_s[k] * (double)xs[(trip_hm_s[k] & 0xffff) * 3 + comp];
     xs[t * 3 + comp] = (VT)v;
   }
   __syncthreads();
   if (PREC != P_BF16) {
     const VT* Bs = PREC == P_F64 ? (const VT*)sB : (const VT*)a.kb;
-    VT cep[EPT];
-#pragma unroll
-    for (int r = 0; r < EPT; ++r) cep[r] = coef[eel[r]];
 #pragma unroll
     for (int r = 0; r < EPT; ++r) {
       const int en = tid + 256 * r;
@@ -423,8 +435,8 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, CgA
   __syncthreads();
   for (int i = tid; i < nh * 3; i += 256) {  // y_m += w_hm y_h  (P^T of Eq. (7))
     const int k = i / 3, comp = i % 3;
-    const uint32_t hm = ca.trip_hm[h0 + k];
-    atomicAdd(&ys[(hm & 0xffff) * 3 + comp], ca.trip_w[h0 + k] * ys[(hm >> 16) * 3 + comp]);
+    const uint32_t hm = trip_hm_s[k];
+    atomicAdd(&ys[(hm & 0xffff) * 3 + comp], trip_w_s[k] * ys[(hm >> 16) * 3 + comp]);
   }
   __syncthreads();
   double dot = 0.0;

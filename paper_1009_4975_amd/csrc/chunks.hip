@@ -148,8 +148,12 @@ int build_chunks(amrto_ctx* ctx, const amrto_mesh* m) {
             }
         }
       const size_t nt = own_reg.size() + oth_reg.size() + own_h.size() + oth_h.size();
-      if ((nt <= (size_t)TAB_MAX && ents.size() <= (size_t)ENT_MAX) || e1 - e0 == 1) {
-        if (nt > (size_t)TAB_MAX || ents.size() > (size_t)ENT_MAX)
+      size_t ntrip = 0;
+      for (int v : own_h) ntrip += m->hang_ptr[hidx[v] + 1] - m->hang_ptr[hidx[v]];
+      for (int v : oth_h) ntrip += m->hang_ptr[hidx[v] + 1] - m->hang_ptr[hidx[v]];
+      const bool fits = nt <= (size_t)TAB_MAX && ents.size() <= (size_t)ENT_MAX && ntrip <= (size_t)TRIP_MAX;
+      if (fits || e1 - e0 == 1) {
+        if (!fits)
           return ctx->fail(AMRTO_EINVAL, "amrto_upload_mesh: one element's neighbourhood exceeds a chunk table");
         break;
       }

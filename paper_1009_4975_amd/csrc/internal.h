@@ -28,10 +28,12 @@ constexpr int UN = UT + 2;  // node columns per tile edge (with halo)
 
 // Octree operator chunk: a run of at most CH_MAX consecutive elements plus
 // the halo elements around its owned nodes (at most ENT_MAX in all); its node
-// table (at most TAB_MAX entries) is staged in LDS.
+// table (at most TAB_MAX entries) and hanging triples (at most TRIP_MAX) are
+// staged in LDS.
 constexpr int CH_MAX = 128;
 constexpr int ENT_MAX = 512;
 constexpr int TAB_MAX = 1024;
+constexpr int TRIP_MAX = 1024;  // hanging (node, master, weight) triples per chunk
 
 // Reductions: fixed grid of partial sums; every consumer re-adds them in the
 // same order, so results are deterministic without a separate finalize pass.
