@@ -160,7 +160,8 @@ typedef struct {
 
 typedef struct {
   int32_t iters;       /* total CG iterations (inner iterations summed) */
-  int32_t outer;       /* FP64 reliable updates (0 for plain FP64) */
+  int32_t outer;       /* FP64 reliable updates (mixed) or residual-replacement
+                          restarts (plain FP64) */
   double rel_res;      /* true FP64 ||b - A~ u|| / ||b|| at exit */
   double ms;           /* wall time of the call */
 } amrto_solve_stats;
@@ -168,7 +169,10 @@ typedef struct {
 /* Fill opts with the defaults above. */
 void amrto_solve_opts_default(amrto_solve_opts* opts);
 
-/* Solve A~ u~ = b by Jacobi-preconditioned conjugate gradients (FP64), or by
+/* Solve A~ u~ = b by Jacobi-preconditioned conjugate gradients (FP64; when the
+ * recurrence residual converges but the true residual does not, CG restarts
+ * from the iterate with r = b - A~ u, up to 8 times while each restart halves
+ * the true residual), or by
  * the same recurrence in FP32 vectors with an FP32 or BF16 element contraction
  * whose iterate is folded into an FP64 solution with an FP64 true residual
  * whenever the recurrence residual has fallen by inner_rtol (reliable

@@ -13,6 +13,7 @@
 // solve makes the rest of an enqueued batch return at once.
 #include <chrono>
 #include <cmath>
+#include <string>
 
 #include "kernels.h"
 
@@ -469,8 +470,8 @@ static int enqueue_iters(amrto_ctx* ctx, const Vecs<VT>& v, VT* x, int prec, dou
 }
 
 // Plain FP64 Jacobi-PCG from x (masked).  *iters = iterations performed.
-static int cg_fp64(amrto_ctx* ctx, const double* b, double* x, double rtol, int max_it, int check_every,
-                   int* iters) {
+static int cg_fp64_run(amrto_ctx* ctx, const double* b, double* x, double rtol, int max_it, int check_every,
+                       int* iters) {
   const long n3 = 3L * ctx->n_nodes;
   const int g1 = (int)((n3 + 255) / 256);
   Vecs<double> v = vecs64(ctx);
@@ -520,6 +521,40 @@ static int true_residual(amrto_ctx* ctx, const double* b, const double* x, doubl
   return AMRTO_OK;
 }
 
+// Plain FP64 PCG judged on the true residual.  Over long solves the
+// recurrence residual of CG drifts away from b - A~ x (the attainable
+// accuracy of the method); when the recurrence claims convergence but the
+// true residual is still above the target, the search restarts from the
+// current iterate with r = b - A~ x (residual replacement), as long as that
+// keeps paying off (at most 8 restarts, each must halve the true residual).
+static int cg_fp64(amrto_ctx* ctx, const double* b, double* x, double rtol, int max_it, int check_every,
+                   int* iters, int* restarts, double* rel_out) {
+  int total = 0, status = AMRTO_NOT_CONVERGED;
+  double best = 1e300;
+  *restarts = 0;
+  while (true) {
+    int it = 0;
+    status = cg_fp64_run(ctx, b, x, rtol, max_it - total, check_every, &it);
+    total += it;
+    if (status < 0 && status != AMRTO_EBREAKDOWN) return status;
+    double rr, bb;
+    int rc = true_residual(ctx, b, x, &rr, &bb);
+    if (rc) return rc;
+    const double rel = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+    *rel_out = rel;
+    if (status != AMRTO_OK) break;  // breakdown or iteration cap
+    if (rel <= rtol) break;
+    if (*restarts >= 8 || !(rel < 0.5 * best) || total >= max_it) {
+      status = AMRTO_NOT_CONVERGED;
+      break;
+    }
+    best = rel;
+    ++*restarts;
+  }
+  *iters = total;
+  return status;
+}
+
 // Mixed precision: the CG recurrence runs in FP32 vectors with an FP32 or
 // BF16 operator on d = A~^-1 r0; whenever the recurrence residual has dropped
 // by `delta` since the last reliable update (or claims convergence), the FP32
@@ -544,6 +579,7 @@ static int cg_mixed(amrto_ctx* ctx, const double* b, double* x, int prec, double
   int it = 0;
   int status = AMRTO_NOT_CONVERGED;
   double rr_ref = rr;  // true r.r at the last reliable update
+  int stalls = 0;
   bool restart_scalars = true;
   while (true) {
     if (!(rr == rr) || rr > 1e300) { status = AMRTO_EBREAKDOWN; break; }
@@ -579,9 +615,13 @@ static int cg_mixed(amrto_ctx* ctx, const double* b, double* x, int prec, double
       hipLaunchKernelGGL(k_accumulate, dim3(g1), dim3(256), 0, ctx->stream, x, d, n3);
       rc = true_residual(ctx, b, x, &rr, &bb);
       if (rc) return rc;
+      // at the FP64 floor of the true residual the cycles stop paying off:
+      // three updates in a row that fail to halve it end the solve
+      stalls = (rr > 0.25 * rr_ref) ? stalls + 1 : 0;
       rr_ref = rr;
       ++*updates;
       restart_scalars = true;
+      if (stalls >= 3 && !(rr <= tol2 * bb)) break;
     }
   }
   *iters = it;
@@ -639,12 +679,8 @@ int amrto_pcg(amrto_ctx* ctx, const double* b, double* u, const amrto_solve_opts
   int iters = 0, outer = 0, status;
   double rel = 0.0;
   if (o.inner_prec == AMRTO_FP64) {
-    status = cg_fp64(ctx, b, u, o.rtol, o.max_it, o.check_every, &iters);
+    status = cg_fp64(ctx, b, u, o.rtol, o.max_it, o.check_every, &iters, &outer, &rel);
     if (status < 0 && status != AMRTO_EBREAKDOWN) return status;
-    double rr, bb;
-    int rc = true_residual(ctx, b, u, &rr, &bb);
-    if (rc) return rc;
-    rel = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
   } else {
     status = cg_mixed(ctx, b, u, o.inner_prec, o.rtol, o.max_it, o.check_every, o.inner_rtol, &iters, &outer, &rel);
     if (status < 0 && status != AMRTO_EBREAKDOWN) return status;
@@ -660,7 +696,10 @@ int amrto_pcg(amrto_ctx* ctx, const double* b, double* u, const amrto_solve_opts
     stats->ms = ms;
   }
   if (status == AMRTO_EBREAKDOWN) return ctx->fail(AMRTO_EBREAKDOWN, "amrto_pcg: breakdown (p^T A p <= 0 or non-finite)");
-  if (status == AMRTO_NOT_CONVERGED) ctx->err = "amrto_pcg: iteration cap reached";
+  if (status == AMRTO_NOT_CONVERGED)
+    ctx->err = iters >= o.max_it ? "amrto_pcg: iteration cap reached"
+                                 : "amrto_pcg: true residual " + std::to_string(rel) +
+                                       " stagnated above rtol (FP64 attainable accuracy)";
   return status;
 }
 
