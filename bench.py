@@ -111,6 +111,8 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the uniform 192x96x96 apply measurement")
     ap.add_argument("--profile-only", action="store_true", help="only the timed steps (for profilers)")
     ap.add_argument("--c3-only", action="store_true", help="only the uniform 192x96x96 apply measurement")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 50-iteration adaptive SIMP run")
+    ap.add_argument("--c4-only", action="store_true", help="only the 50-iteration adaptive SIMP run")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the C2 apply loop and a copy kernel of known size (for counter runs)")
     args = ap.parse_args()
@@ -128,6 +130,9 @@ def main():
     dev = lambda a, dt=torch.float64: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
     if args.c3_only:
         print(json.dumps(apply_uniform_bandwidth(torch, binding, synth, dev)), flush=True)
+        return
+    if args.c4_only:
+        print(json.dumps(c4_simp(torch, binding, synth)), flush=True)
         return
 
     t0 = time.time()
@@ -228,6 +233,11 @@ def main():
     if not args.no_c3:
         c3 = apply_uniform_bandwidth(torch, binding, synth, dev)
 
+    # --- 50-iteration adaptive SIMP run: plain vs coarse-corrected vs learned
+    c4 = None
+    if not args.no_c4:
+        c4 = c4_simp(torch, binding, synth)
+
     # --- CPU oracle on a bounded sample
     cpu = None
     if not args.no_cpu:
@@ -243,7 +253,7 @@ def main():
                    "hanging_nodes": int(len(mesh.hang_node)), "chunks": info["n_chunks"], "solver": solver,
                    "rtol": 1e-8, "E0": 1.0, "Emin": 1e-9, "nu": 0.3, "p": 3.0},
         "solve_iters": int(np.median(iters)), "solve_rel_res": float(max(rel)),
-        "solve_variants": variants, "roofline": roofline, "apply_uniform_192x96x96": c3,
+        "solve_variants": variants, "roofline": roofline, "apply_uniform_192x96x96": c3, "simp_adaptive_bridge": c4,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -285,6 +295,62 @@ def apply_uniform_bandwidth(torch, binding, synth, dev):
             f"({100 * gbs / HBM_PEAK_GBS:.1f}% of HBM), {res[name]['TFLOPs']} TFLOP/s")
         del xs, ys
     return res
+
+
+def c4_simp(torch, binding, synth):
+    """The adaptive bridge: 32x16x16 base leaves, 2 refinement levels (finest
+    128x64x64), volume fraction 0.25, filter radius 1.5, OC, adapt every 5
+    iterations, 50 iterations.  Variants differ only in how iterations 11-50
+    solve: plain (previous solution as the start, Jacobi-PCG), the affine
+    coarse space, and the learned start (network trained on iterations 1-10)
+    with the coarse space; each in FP64 and with FP32 inner solves."""
+    from paper_1009_4975_amd.learned import LearnedWarmStart
+    from paper_1009_4975_amd.simp import AdaptiveSIMP
+    case = synth.c4()
+    ex = case.extra
+    n_train = ex["train_iters"]
+    out = {}
+    for name, prec, mode in (("plain_fp64", binding.FP64, None), ("plain_fp32", binding.FP32, None),
+                             ("coarse_fp64", binding.FP64, "coarse"), ("learned_coarse_fp64", binding.FP64, "learned"),
+                             ("learned_coarse_fp32", binding.FP32, "learned")):
+        t0 = time.perf_counter()
+        sim = AdaptiveSIMP(case.base, case.max_level, case.fixed, case.load, volfrac=ex["volfrac"],
+                           rho_init=ex["rho_init"], rmin=ex["rmin"], rho_solid=ex["rho_solid"], r_amr=ex["r_amr"],
+                           adapt_every=ex["adapt_every"], rtol=1e-8, inner_prec=prec, inner_rtol=1e-2)
+        ws = LearnedWarmStart(case.dims, cell=2, hidden=8, layers=3, epochs=100, seed=ex["net_seed"],
+                              regions=(2, 2, 2)) if mode else None
+        recs, train_ms = [], 0.0
+        for k in range(ex["iters"]):
+            if mode == "learned" and k < n_train:
+                r = sim.step(warm_start=ws.collect_before, after_solve=ws.collect_after)
+            elif mode and k >= n_train:
+                if mode == "learned" and not ws.trained:
+                    ws.train()
+                    train_ms = ws.train_ms
+                r = sim.step(warm_start=(lambda s: ws.warm_start(s, use_net=(mode == "learned"))))
+            else:
+                r = sim.step()
+            recs.append(r)
+        torch.cuda.synchronize()
+        late = recs[n_train:]
+        out[name] = dict(
+            iters_11_50=int(sum(r["iters"] for r in late)),
+            solve_ms_11_50=round(sum(r["solve_ms"] for r in late), 1),
+            warm_and_coarse_setup_ms_11_50=round(sum(r["warm_ms"] for r in late), 1),
+            train_ms=round(train_ms, 1),
+            step_ms_total=round(sum(r["step_ms"] for r in recs), 1),
+            wall_s=round(time.perf_counter() - t0, 2),
+            final_compliance=recs[-1]["compliance"], max_rel_res=max(r["rel_res"] for r in recs),
+            dofs_min_max=[min(r["dofs"] for r in recs), max(r["dofs"] for r in recs)],
+            elements_final=recs[-1]["n_elems"])
+        log(f"[bench] C4 {name}: iterations 11-50 {out[name]['iters_11_50']} PCG its, "
+            f"{out[name]['solve_ms_11_50']} ms solve + {out[name]['warm_and_coarse_setup_ms_11_50']} ms set-up, "
+            f"train {train_ms:.0f} ms, compliance {recs[-1]['compliance']:.6e}, DOFs {out[name]['dofs_min_max']}")
+    base = out["plain_fp64"]
+    for k, v in out.items():
+        v["time_vs_plain_fp64"] = round((v["solve_ms_11_50"] + v["warm_and_coarse_setup_ms_11_50"] + v["train_ms"]) /
+                                        (base["solve_ms_11_50"] + base["warm_and_coarse_setup_ms_11_50"]), 4)
+    return out
 
 
 def cpu_baseline(synth, case, tree, mesh, rho_h, gpu_iters):

@@ -32,10 +32,13 @@ __global__ __launch_bounds__(256) void k_node_region(const int32_t* __restrict__
   region[v] = (uint8_t)((gz * ry + gy) * rx + gx);
 }
 
-// affine fields 0..3: (1,1,1), (x,y,z), (y,z,x), (z,x,y) with coordinates
-// centred on the node's region and scaled by the largest extent
+// Affine fields 0..3: (1,1,1), (x,y,z), (y,z,x), (z,x,y) with coordinates
+// centred on the node's region and scaled by the largest extent, rounded to
+// FP32 once: geo[v] = (dx, dy, dz, region | mask << 8) is what the solve
+// kernels read, and the stored fields are made from the same values.
 __global__ __launch_bounds__(256) void k_affine_fields(const int32_t* __restrict__ xyz, int n_nodes, int nx, int ny,
-                                                       int nz, int rx, int ry, int rz, double* __restrict__ F) {
+                                                       int nz, int rx, int ry, int rz, const uint8_t* __restrict__ cmask,
+                                                       float4* __restrict__ geo, double* __restrict__ F) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n_nodes) return;
   int px, py, pz;
@@ -46,15 +49,28 @@ __global__ __launch_bounds__(256) void k_affine_fields(const int32_t* __restrict
   }
   const int gx = min(px * rx / nx, rx - 1), gy = min(py * ry / ny, ry - 1), gz = min(pz * rz / nz, rz - 1);
   const double s = 1.0 / max(nx, max(ny, nz));
-  const double c[3] = {(px - (gx + 0.5) * nx / rx) * s, (py - (gy + 0.5) * ny / ry) * s,
-                       (pz - (gz + 0.5) * nz / rz) * s};
+  const float c[3] = {(float)((px - (gx + 0.5) * nx / rx) * s), (float)((py - (gy + 0.5) * ny / ry) * s),
+                      (float)((pz - (gz + 0.5) * nz / rz) * s)};
+  const int g = (gz * ry + gy) * rx + gx;
+  geo[v] = make_float4(c[0], c[1], c[2], __int_as_float(g | ((int)cmask[v] << 8)));
   const long n3 = 3L * n_nodes;
   for (int d = 0; d < 3; ++d) {
     F[3L * v + d] = 1.0;
-    F[n3 + 3L * v + d] = c[d];
-    F[2 * n3 + 3L * v + d] = c[(d + 1) % 3];
-    F[3 * n3 + 3L * v + d] = c[(d + 2) % 3];
+    F[n3 + 3L * v + d] = (double)c[d];
+    F[2 * n3 + 3L * v + d] = (double)c[(d + 1) % 3];
+    F[3 * n3 + 3L * v + d] = (double)c[(d + 2) % 3];
   }
+}
+
+// cmask[v] = supported components of node v, all three for hanging nodes
+__global__ __launch_bounds__(256) void k_cmask(const uint8_t* __restrict__ fix, int n_nodes, uint8_t* __restrict__ cmask) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n_nodes) cmask[v] = fix[v] & 7;
+}
+__global__ __launch_bounds__(256) void k_cmask_hanging(const int32_t* __restrict__ hang, int n_hang,
+                                                       uint8_t* __restrict__ cmask) {
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h < n_hang) cmask[hang[h]] = 7;
 }
 
 // r = b - q
@@ -182,17 +198,25 @@ int amrto_coarse_setup(amrto_ctx* ctx, int32_t affine, const double* const* fiel
   }
   const int32_t* xyz = ctx->uniform ? nullptr : ctx->d_node_xyz;
   const int gn = (ctx->n_nodes + 255) / 256;
-  if (affine)
-    hipLaunchKernelGGL(k_affine_fields, dim3(gn), dim3(256), 0, ctx->stream, xyz, ctx->n_nodes, ctx->nx, ctx->ny,
-                       ctx->nz, rx, ry, rz, ctx->d_cf);
   for (int f = 0; f < n_fields; ++f) {
     if (!fields[f]) return ctx->fail(AMRTO_EINVAL, "amrto_coarse_setup: null field");
     AMRTO_HIP(hipMemcpyAsync(ctx->d_cf + (long)(nf - n_fields + f) * n3, fields[f], n3 * sizeof(double),
                              hipMemcpyDeviceToDevice, ctx->stream));
   }
   if (!ctx->d_region) AMRTO_HIP(hipMalloc((void**)&ctx->d_region, ctx->n_nodes));
+  if (!ctx->d_cmask) AMRTO_HIP(hipMalloc((void**)&ctx->d_cmask, ctx->n_nodes));
+  hipLaunchKernelGGL(k_cmask, dim3(gn), dim3(256), 0, ctx->stream, ctx->d_fix, ctx->n_nodes, ctx->d_cmask);
+  if (ctx->n_hang)
+    hipLaunchKernelGGL(k_cmask_hanging, dim3((ctx->n_hang + 255) / 256), dim3(256), 0, ctx->stream, ctx->d_hang_node,
+                       ctx->n_hang, ctx->d_cmask);
   ctx->coarse_nf = nf;
   ctx->coarse_R = R;
+  ctx->coarse_affine_only = (affine && n_fields == 0) ? 1 : 0;
+  if (affine) {
+    if (!ctx->d_cgeo) AMRTO_HIP(hipMalloc((void**)&ctx->d_cgeo, ctx->n_nodes * sizeof(float4)));
+    hipLaunchKernelGGL(k_affine_fields, dim3(gn), dim3(256), 0, ctx->stream, xyz, ctx->n_nodes, ctx->nx, ctx->ny,
+                       ctx->nz, rx, ry, rz, (const uint8_t*)ctx->d_cmask, ctx->d_cgeo, ctx->d_cf);
+  }
   {
     int rc = mask_vector_n(ctx, ctx->d_cf, nf);
     if (rc) return rc;

@@ -147,6 +147,9 @@ struct amrto_ctx {
   double* d_oc = nullptr;     // OC search workspace
   // coarse space (coarse.hip)
   int coarse_k = 0, coarse_nf = 0, coarse_R = 0, coarse_cap = 0;
+  int coarse_affine_only = 0;   // fields generated on the fly by the solve kernels
+  uint8_t* d_cmask = nullptr;   // per node: bit c = DOF c supported or hanging
+  float4* d_cgeo = nullptr;     // affine space: per node (dx, dy, dz, region | mask << 8)
   double* d_cf = nullptr;      // n_fields x 3n fields (masked)
   uint8_t* d_region = nullptr; // region of each node
   double* d_cpart = nullptr;   // RED_BLOCKS x COARSE_KMAX partials (block-major)

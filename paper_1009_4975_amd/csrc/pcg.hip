@@ -118,13 +118,50 @@ __global__ __launch_bounds__(256) void k_cg_update(VT* __restrict__ x, VT* __res
 }
 
 // ------------------------------------------------------------------ coarse space
+// The coarse space Z: column (f, g, c) is component c of field f on the nodes
+// of region g.  Fields are either stored (F, nf x 3n, masked) or, for the
+// affine space alone, formed on the fly from a 16-byte node descriptor (FP32
+// offsets from the region centre, region, support/hanging bits) instead of
+// 96 bytes of stored fields.  The stored fields Z^T A Z was formed from are
+// made from the same FP32 offsets, so both views of Z agree exactly.
+struct CoarseArgs {
+  const double* F;
+  int nf, R;
+  const uint8_t* region;
+  const float4* geo;      // affine space: per node (dx, dy, dz, region | mask << 8); NULL: stored fields
+};
+
+// field values of DOF i into fv; returns the DOF's region
+__device__ __forceinline__ int coarse_fields(const CoarseArgs& a, long i, long n3, double (&fv)[COARSE_NFMAX]) {
+  const int ii = (int)i, v = ii / 3, c = ii - 3 * v;
+  if (!a.geo) {
+#pragma unroll
+    for (int f = 0; f < COARSE_NFMAX; ++f) fv[f] = f < a.nf ? a.F[(long)f * n3 + i] : 0.0;
+    return a.region[v];
+  }
+  const float4 q = a.geo[v];
+  const int w = __float_as_int(q.w);
+  const double on = ((w >> (8 + c)) & 1) ? 0.0 : 1.0;
+  const double d[3] = {(double)q.x, (double)q.y, (double)q.z};
+  fv[0] = on;
+  fv[1] = on * d[c];
+  fv[2] = on * d[c == 2 ? 0 : c + 1];
+  fv[3] = on * d[c == 0 ? 2 : c - 1];
+#pragma unroll
+  for (int f = 4; f < COARSE_NFMAX; ++f) fv[f] = 0.0;
+  return w & 0xff;
+}
+
+__device__ __forceinline__ int coarse_region(const CoarseArgs& a, int v) {
+  return a.geo ? (__float_as_int(a.geo[v].w) & 0xff) : a.region[v];
+}
+
 // Z^T v per block.  Each block takes a contiguous DOF range and walks it in
 // steps of the block size, so a thread's DOFs stay in one region for long
 // stretches: the thread keeps 3 nf running sums in registers for its current
 // region and adds them to the block's LDS accumulator only when its region
-// changes and at the end (then, when the whole wavefront is in one region,
-// after a wavefront reduction).  Fields beyond COARSE_NFMAX are rejected at
-// set-up, so the register sums have a fixed size.
+// changes and at the end.  Fields beyond COARSE_NFMAX are rejected at set-up,
+// so the register sums have a fixed size.
 struct ZtAcc {
   double s[COARSE_NFMAX][3];
   int g;
@@ -148,8 +185,7 @@ __device__ __forceinline__ void zt_flush_lane(ZtAcc& a, double* acc, int nf, int
         if (a.s[f][c] != 0.0) atomicAdd(&acc[(f * R + a.g) * 3 + c], a.s[f][c]);
 }
 
-// add v F_f[i] (f < nf) for DOF i of component c in region g; fv holds the
-// field values, loaded by the caller ahead of the arithmetic
+// add vi F_f[i] (f < nf) for DOF i of component c in region g
 __device__ __forceinline__ void zt_add(ZtAcc& a, double* acc, const double (&fv)[COARSE_NFMAX], int nf, int R, int g,
                                        int c, double vi) {
   if (g != a.g) {
@@ -162,12 +198,6 @@ __device__ __forceinline__ void zt_add(ZtAcc& a, double* acc, const double (&fv)
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) a.s[f][cc] += cc == c ? v : 0.0;
   }
-}
-
-__device__ __forceinline__ void load_fields(double (&fv)[COARSE_NFMAX], const double* __restrict__ F, int nf, long n3,
-                                            long i) {
-#pragma unroll
-  for (int f = 0; f < COARSE_NFMAX; ++f) fv[f] = f < nf ? F[(long)f * n3 + i] : 0.0;
 }
 
 // End of the block's range.  When every thread's sums belong to the region of
@@ -209,13 +239,13 @@ __device__ __forceinline__ void zt_store(const double* acc, int k, double* __res
 }
 
 template <typename VT>
-__global__ __launch_bounds__(256) void k_zt_part(const double* __restrict__ F, int nf, const uint8_t* __restrict__ region,
-                                                 int R, const VT* __restrict__ v, long n3, double* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_zt_part(CoarseArgs ca, const VT* __restrict__ v, long n3,
+                                                 double* __restrict__ part) {
   __shared__ double acc[COARSE_KMAX];
-  const int k = 3 * nf * R;
+  __shared__ double red[COARSE_NFMAX * 3][256];
+  const int nf = ca.nf, R = ca.R, k = 3 * nf * R;
   for (int j = threadIdx.x; j < k; j += blockDim.x) acc[j] = 0.0;
   __syncthreads();
-  __shared__ double red[COARSE_NFMAX * 3][256];
   long lo, hi;
   block_range(n3, lo, hi);
   ZtAcc a;
@@ -223,12 +253,10 @@ __global__ __launch_bounds__(256) void k_zt_part(const double* __restrict__ F, i
 #pragma unroll 2
   for (long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     double fv[COARSE_NFMAX];
-    load_fields(fv, F, nf, n3, i);
-    const double vi = (double)v[i];
-    const int g = region[i / 3];
-    zt_add(a, acc, fv, nf, R, g, (int)(i % 3), vi);
+    const int g = coarse_fields(ca, i, n3, fv);
+    zt_add(a, acc, fv, nf, R, g, (int)(i % 3), (double)v[i]);
   }
-  zt_flush(a, acc, nf, R, lo < hi ? region[lo / 3] : 0, red);
+  zt_flush(a, acc, nf, R, lo < hi ? coarse_region(ca, (int)(lo / 3)) : 0, red);
   __syncthreads();
   zt_store(acc, k, part);
 }
@@ -239,13 +267,13 @@ template <typename VT>
 __global__ __launch_bounds__(256) void k_cg_update_coarse(VT* __restrict__ x, VT* __restrict__ r,
                                                           const VT* __restrict__ p, const VT* __restrict__ q, long n,
                                                           const double* __restrict__ part_pq, int n_pq,
-                                                          double* __restrict__ scal, int it, const double* __restrict__ F,
-                                                          int nf, const uint8_t* __restrict__ region, int R,
+                                                          double* __restrict__ scal, int it, CoarseArgs ca,
                                                           double* __restrict__ part_z) {
   if (scal[S_DONE] != 0.0) return;
   __shared__ double sh[8];
   __shared__ double acc[COARSE_KMAX];
-  const int k = 3 * nf * R;
+  __shared__ double red[COARSE_NFMAX * 3][256];
+  const int nf = ca.nf, R = ca.R, k = 3 * nf * R;
   const double pq = sum_partials(part_pq, n_pq, sh);
   const double rz = scal[S_RZ0 + (it & 1)];
   if (!(pq > 0.0) || !(pq < 1e300) || !(rz == rz)) {
@@ -254,7 +282,6 @@ __global__ __launch_bounds__(256) void k_cg_update_coarse(VT* __restrict__ x, VT
   }
   for (int j = threadIdx.x; j < k; j += blockDim.x) acc[j] = 0.0;
   __syncthreads();
-  __shared__ double red[COARSE_NFMAX * 3][256];
   const VT alpha = (VT)(rz / pq);
   long lo, hi;
   block_range(n, lo, hi);
@@ -263,15 +290,14 @@ __global__ __launch_bounds__(256) void k_cg_update_coarse(VT* __restrict__ x, VT
 #pragma unroll 2
   for (long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     double fv[COARSE_NFMAX];
-    load_fields(fv, F, nf, n, i);
+    const int g = coarse_fields(ca, i, n, fv);
     const VT pi = p[i], qi = q[i], ri = r[i], xi = x[i];
-    const int g = region[i / 3];
     x[i] = xi + alpha * pi;
     const VT rv = ri - alpha * qi;
     r[i] = rv;
     zt_add(a, acc, fv, nf, R, g, (int)(i % 3), (double)rv);
   }
-  zt_flush(a, acc, nf, R, lo < hi ? region[lo / 3] : 0, red);
+  zt_flush(a, acc, nf, R, lo < hi ? coarse_region(ca, (int)(lo / 3)) : 0, red);
   __syncthreads();
   zt_store(acc, k, part_z);
 }
@@ -315,22 +341,25 @@ __global__ __launch_bounds__(128) void k_coarse_cz(const double* __restrict__ ct
 template <typename VT>
 __global__ __launch_bounds__(256) void k_coarse_z(const VT* __restrict__ r, VT* __restrict__ z,
                                                   const VT* __restrict__ dinv, long n, const double* __restrict__ cz_g,
-                                                  const double* __restrict__ F, int nf,
-                                                  const uint8_t* __restrict__ region, int R,
-                                                  double* __restrict__ part, const double* __restrict__ stop) {
+                                                  CoarseArgs ca, double* __restrict__ part,
+                                                  const double* __restrict__ stop) {
   if (stop && *stop != 0.0) return;
   __shared__ double sh[8];
   __shared__ double cz[COARSE_KMAX];
-  const int k = 3 * nf * R;
+  const int nf = ca.nf, R = ca.R, k = 3 * nf * R;
   for (int j = threadIdx.x; j < k; j += blockDim.x) cz[j] = cz_g[j];
   __syncthreads();
   double srz = 0.0, srr = 0.0;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double fv[COARSE_NFMAX];
+    const int g = coarse_fields(ca, i, n, fv);
+    const int c = (int)(i % 3);
     const VT ri = r[i];
     double zi = (double)dinv[i] * (double)ri;
-    const int g = region[i / 3], c = (int)(i % 3);
     // the fields are zero on supported and hanging DOFs, so z stays zero there
-    for (int f = 0; f < nf; ++f) zi += F[(long)f * n + i] * cz[(f * R + g) * 3 + c];
+#pragma unroll
+    for (int f = 0; f < COARSE_NFMAX; ++f)
+      if (f < nf) zi += fv[f] * cz[(f * R + g) * 3 + c];
     z[i] = (VT)zi;
     srz += (double)ri * zi;
     srr += (double)ri * (double)ri;
@@ -392,25 +421,32 @@ struct Vecs {
 static Vecs<double> vecs64(amrto_ctx* c) { return {c->d_r, c->d_z, c->d_p, c->d_p2, c->d_q, c->d_dinv}; }
 static Vecs<float> vecs32(amrto_ctx* c) { return {c->f_r, c->f_z, c->f_p, c->f_p2, c->f_q, c->d_dinv_f}; }
 
+static CoarseArgs coarse_args(const amrto_ctx* ctx) {
+  CoarseArgs a;
+  a.F = ctx->d_cf; a.nf = ctx->coarse_nf; a.R = ctx->coarse_R; a.region = ctx->d_region;
+  a.geo = ctx->coarse_affine_only ? ctx->d_cgeo : nullptr;
+  return a;
+}
+
 // with a coarse space: z = D^-1 r + Z E^-1 Z^T r for the initial residual
 // (overwrites the r.z and r.r partials of k_init; b.b stays)
 template <typename VT>
 static void coarse_init(amrto_ctx* ctx, const Vecs<VT>& v) {
   if (ctx->coarse_k <= 0) return;
   const long n3 = 3L * ctx->n_nodes;
-  hipLaunchKernelGGL(k_zt_part<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, ctx->d_cf, ctx->coarse_nf,
-                     ctx->d_region, ctx->coarse_R, v.r, n3, ctx->d_cpart);
+  hipLaunchKernelGGL(k_zt_part<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, coarse_args(ctx), v.r, n3,
+                     ctx->d_cpart);
   hipLaunchKernelGGL(k_coarse_sum, dim3(ctx->coarse_k), dim3(256), 0, ctx->stream, ctx->d_cpart, ctx->coarse_k,
                      RED_BLOCKS, ctx->d_ct, (const double*)nullptr);
   hipLaunchKernelGGL(k_coarse_cz, dim3(1), dim3(128), 0, ctx->stream, (const double*)ctx->d_ct, ctx->coarse_k,
                      (const double*)ctx->d_cinv, ctx->d_cz, (const double*)nullptr);
   hipLaunchKernelGGL(k_coarse_z<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, v.r, v.z, v.dinv, n3, ctx->d_cz,
-                     ctx->d_cf, ctx->coarse_nf, ctx->d_region, ctx->coarse_R, ctx->d_part, (const double*)nullptr);
+                     coarse_args(ctx), ctx->d_part, (const double*)nullptr);
 }
 
 int launch_zt(amrto_ctx* ctx, const double* v) {
-  hipLaunchKernelGGL(k_zt_part<double>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, ctx->d_cf, ctx->coarse_nf,
-                     ctx->d_region, ctx->coarse_R, v, 3L * ctx->n_nodes, ctx->d_cpart);
+  hipLaunchKernelGGL(k_zt_part<double>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, coarse_args(ctx), v,
+                     3L * ctx->n_nodes, ctx->d_cpart);
   AMRTO_HIP(hipGetLastError());
   return AMRTO_OK;
 }
@@ -451,14 +487,13 @@ static int enqueue_iters(amrto_ctx* ctx, const Vecs<VT>& v, VT* x, int prec, dou
     if (rc) return rc;
     if (ctx->coarse_k > 0) {
       hipLaunchKernelGGL(k_cg_update_coarse<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew, v.q, n3,
-                         ctx->d_partpq, ctx->n_partpq, ctx->d_scal, it, ctx->d_cf, ctx->coarse_nf, ctx->d_region,
-                         ctx->coarse_R, ctx->d_cpart);
+                         ctx->d_partpq, ctx->n_partpq, ctx->d_scal, it, coarse_args(ctx), ctx->d_cpart);
       hipLaunchKernelGGL(k_coarse_sum, dim3(ctx->coarse_k), dim3(256), 0, ctx->stream, ctx->d_cpart,
                          ctx->coarse_k, RED_BLOCKS, ctx->d_ct, ctx->d_scal + S_DONE);
       hipLaunchKernelGGL(k_coarse_cz, dim3(1), dim3(128), 0, ctx->stream, (const double*)ctx->d_ct, ctx->coarse_k,
                          (const double*)ctx->d_cinv, ctx->d_cz, ctx->d_scal + S_DONE);
       hipLaunchKernelGGL(k_coarse_z<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, v.r, v.z, v.dinv, n3,
-                         ctx->d_cz, ctx->d_cf, ctx->coarse_nf, ctx->d_region, ctx->coarse_R,
+                         ctx->d_cz, coarse_args(ctx),
                          ctx->d_part, ctx->d_scal + S_DONE);
     } else {
       hipLaunchKernelGGL(k_cg_update<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew, v.q, v.dinv,
