@@ -46,10 +46,12 @@ struct UArgs {
   const double* stop;
 };
 
+// workgroups per CU the uniform kernels are compiled for (register budget:
+// 4 -> 128 VGPRs, 2 -> 256)
 template <int PREC>
-struct Occ { static constexpr int blocks = 2; };
+struct Occ { static constexpr int blocks = 4; };
 template <>
-struct Occ<1> { static constexpr int blocks = 3; };
+struct Occ<0> { static constexpr int blocks = 2; };
 
 // ------------------------------------------------------------------ uniform brick
 // Output rows accumulate in FP64 LDS for every precision: ds_add_f64 runs at
@@ -104,34 +106,60 @@ __global__ __launch_bounds__(256, Occ<PREC>::blocks) void k_apply_uniform(UArgs 
     gxy[s] = 3 * (gx + sx * gy) + c;
     own[s] = (in && li >= 1 && li <= UT && lj >= 1 && lj <= UT) ? ((lj - 1) * UT + li - 1) * 3 + c : -1;
   }
-  // support bits of the last four layers, 4 bits per layer (one per slot),
-  // so the store phase needs no dependent global read
+  // support bits of the last four staged layers, 4 bits per layer (one per
+  // slot), so the store phase needs no dependent global read
   uint32_t fring = 0;
-  auto load = [&](VT (&R)[LSLOTS], int k) {
-    uint32_t fb = 0;
+  // A layer in flight: raw loads only.  Masking and the beta update happen
+  // at stage time two layers later, so nothing waits on these loads early.
+  // The BF16 body sits at the register limit of its occupancy: there the
+  // masking stays at load time (fewer live registers), which measured faster.
+  constexpr bool DEFER = PREC != P_BF16;
+  struct Slot {
+    VT x[LSLOTS];
+    VT po[(FUSED && DEFER) ? LSLOTS : 1];
+    uint8_t f[DEFER ? LSLOTS : 1];
+    uint32_t fb;
+  };
+  auto load = [&](Slot& R, int k) {
+    R.fb = 0;
 #pragma unroll
     for (int s = 0; s < LSLOTS; ++s) {
-      VT v = 0;
+      R.x[s] = 0;
+      if (DEFER) R.f[s] = 0;
+      if (FUSED && DEFER) R.po[s] = 0;
       if ((inside >> s) & 1) {
         const long g = gxy[s] + sxy3 * k;
         const uint8_t f = fix[g / 3];
         VT xv = X[g];
-        if (FUSED && !first) xv += vbeta * PO[g];
-        const bool fx = (f >> (gxy[s] % 3)) & 1;
-        fb |= (uint32_t)fx << s;
-        v = fx ? (VT)0 : xv;
+        if (DEFER) {
+          R.f[s] = f;
+          R.x[s] = xv;
+          if (FUSED && !first) R.po[s] = PO[g];
+        } else {
+          if (FUSED && !first) xv += vbeta * PO[g];
+          const bool fx = (f >> ((tid + 256 * s) % 3)) & 1;
+          R.fb |= (uint32_t)fx << s;
+          R.x[s] = fx ? (VT)0 : xv;
+        }
       }
-      R[s] = v;
     }
-    const int sh4 = 4 * (k % NBUF);
-    fring = (fring & ~(0xfu << sh4)) | (fb << sh4);
   };
-  auto stage = [&](const VT (&R)[LSLOTS], int k) {
+  auto stage = [&](const Slot& R, int k) {
+    uint32_t fb = DEFER ? 0u : R.fb;
 #pragma unroll
     for (int s = 0; s < LSLOTS; ++s) {
       const int idx = tid + 256 * s;
-      if (idx < UN * UN * 3) xs[k % NBUF][idx] = R[s];
+      VT v = R.x[s];
+      if (DEFER) {
+        if (FUSED && !first) v += vbeta * R.po[s];
+        const bool fx = (R.f[s] >> (idx % 3)) & 1;
+        fb |= (uint32_t)fx << s;
+        v = fx ? (VT)0 : v;
+      }
+      if (idx < UN * UN * 3) xs[k % NBUF][idx] = v;
     }
+    const int sh4 = 4 * (k % NBUF);
+    fring = (fring & ~(0xfu << sh4)) | (fb << sh4);
   };
   double dot = 0.0;
   auto store = [&](int k) {
@@ -157,12 +185,12 @@ __global__ __launch_bounds__(256, Occ<PREC>::blocks) void k_apply_uniform(UArgs 
   for (int idx = tid; idx < UT * UT * 3; idx += 256) { ys[0][idx] = 0; ys[1][idx] = 0; ys[2][idx] = 0; }
   const int kbeg = max(z0 - 1, 0);
   const int kend = min(z1 - 1, nz - 1);
-  VT Rn[LSLOTS], Rf[LSLOTS];  // layer k+2 (staged this iteration), layer k+3 (in flight)
-  load(Rn, kbeg);
-  stage(Rn, kbeg);
-  load(Rn, kbeg + 1);
-  stage(Rn, kbeg + 1);
-  if (kbeg + 2 <= nz) load(Rn, kbeg + 2);
+  Slot Ra, Rb;  // ping-pong: one set is staged two layers after it was requested
+  load(Ra, kbeg);
+  stage(Ra, kbeg);
+  load(Ra, kbeg + 1);
+  stage(Ra, kbeg + 1);
+  if (kbeg + 2 <= nz) load(Ra, kbeg + 2);
 
   // element-side state
   const int i = tid % UE, j = tid / UE;
@@ -182,8 +210,10 @@ __global__ __launch_bounds__(256, Occ<PREC>::blocks) void k_apply_uniform(UArgs 
   VT ce_next = (PREC != P_BF16 && ev_valu) ? coef[eoff + nxy * kbeg] : (VT)0;
   __syncthreads();
 
-  for (int k = kbeg; k <= kend; ++k) {
-    if (k + 3 <= nz) load(Rf, k + 3);
+  // one layer: request layer k + 3 into Rfly, contract elements of layer k,
+  // stage layer k + 2 from Rnext, barrier, write the finished node layer k
+  auto layer_step = [&](int k, Slot& Rnext, Slot& Rfly) {
+    if (k + 3 <= nz) load(Rfly, k + 3);
     const VT* bot = xs[k % NBUF];
     const VT* top = xs[(k + 1) % NBUF];
     if (PREC != P_BF16) {
@@ -247,11 +277,22 @@ __global__ __launch_bounds__(256, Occ<PREC>::blocks) void k_apply_uniform(UArgs 
         }
       }
     }
-    if (k + 2 <= nz) stage(Rn, k + 2);
+    if (k + 2 <= nz) stage(Rnext, k + 2);
     __syncthreads();
     if (k >= z0) store(k);
-#pragma unroll
-    for (int s = 0; s < LSLOTS; ++s) Rn[s] = Rf[s];
+  };
+  // FP64: two register sets alternate so no copy waits on loads in flight;
+  // for the FP32 and BF16 bodies the doubled loop measured slower.
+  if (PREC == P_F64) {
+    for (int k = kbeg; k <= kend; k += 2) {
+      layer_step(k, Ra, Rb);
+      if (k + 1 <= kend) layer_step(k + 1, Rb, Ra);
+    }
+  } else {
+    for (int k = kbeg; k <= kend; ++k) {
+      layer_step(k, Ra, Rb);
+      Ra = Rb;
+    }
   }
   if (kend + 1 < z1 && kend + 1 >= z0) store(kend + 1);
   if (FUSED) {
