@@ -11,11 +11,15 @@ of the per-iteration hot path on that mesh:
     filter (r = 1.5) -> OC update
 
 ``value`` is the mean wall time of the solve inside the timed steps (ms,
-lower is better) for the solver variant used (--solver).  Also reported:
-the per-variant solve times (plain FP64 PCG, FP32 and BF16 inner solves with
-FP64 refinement), the stiffness-apply roofline of the dominant kernel, the
-uniform 192x96x96 stiffness-apply bandwidth in FP64/FP32/BF16 and the CPU
-oracle on a bounded sample.
+lower is better) for the solver variant used (--solver; "best" takes the
+fastest variant that reaches 1e-8 in an untimed survey).  Variants: plain
+FP64 PCG; FP32 and BF16 inner solves with FP64 reliable updates; each of the
+first two with the affine coarse space, whose set-up (k = 96 operator
+applications on the new density) is counted inside the solve time.  Also
+reported: the stiffness-apply roofline of the dominant kernel, the uniform
+192x96x96 stiffness-apply bandwidth in FP64/FP32/BF16, the 50-iteration
+adaptive SIMP run (plain vs coarse vs learned) and the CPU oracle on a bounded
+sample.
 """
 from __future__ import annotations
 
@@ -106,7 +110,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--solver", choices=["fp64", "fp32", "bf16", "best"], default="best")
+    ap.add_argument("--solver", choices=["fp64", "fp32", "bf16", "fp64+coarse", "fp32+coarse", "best"],
+                    default="best")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-c3", action="store_true", help="skip the uniform 192x96x96 apply measurement")
     ap.add_argument("--profile-only", action="store_true", help="only the timed steps (for profilers)")
@@ -167,19 +172,32 @@ def main():
         return
 
     def solve(name):
+        """One solve from zero; with "+coarse" the affine coarse space (2x2x2
+        regions, 96 columns) is built first and its set-up counts in ms."""
         u.zero_()
-        return ctx.pcg(b, u, rtol=1e-8, inner_prec=precs[name], inner_rtol=1e-2 if name != "fp64" else 1e-3,
-                       max_it=50000)
+        prec = precs[name.split("+")[0]]
+        t0 = time.perf_counter()
+        if name.endswith("+coarse"):
+            ctx.coarse_setup([], 2, 2, 2, affine=True)
+        torch.cuda.synchronize()
+        setup_ms = (time.perf_counter() - t0) * 1e3
+        st = ctx.pcg(b, u, rtol=1e-8, inner_prec=prec, inner_rtol=1e-2, max_it=50000)
+        st["ms"] += setup_ms
+        st["setup_ms"] = setup_ms
+        if name.endswith("+coarse"):
+            ctx.coarse_clear()
+        return st
 
     # --- solver variants (untimed survey, picks the fastest that reaches 1e-8)
     variants = {}
     if not args.profile_only:
-        for name in ("fp64", "fp32", "bf16"):
+        for name in ("fp64", "fp32", "bf16", "fp64+coarse", "fp32+coarse"):
             solve(name)
             runs = [solve(name) for _ in range(2)]
             ms = min(r["ms"] for r in runs)
             variants[name] = dict(ms=round(ms, 3), iters=runs[-1]["iters"], outer=runs[-1]["outer"],
-                                  rel_res=runs[-1]["rel_res"], status=runs[-1]["status"])
+                                  rel_res=runs[-1]["rel_res"], status=runs[-1]["status"],
+                                  setup_ms=round(runs[-1]["setup_ms"], 3))
             log(f"[bench] solve {name}: {ms:.2f} ms, iters {runs[-1]['iters']}, outer {runs[-1]['outer']}, "
                 f"rel_res {runs[-1]['rel_res']:.2e}")
     if args.solver == "best":
@@ -247,7 +265,7 @@ def main():
         "metric": METRIC, "value": round(float(np.mean(solve_ms)), 3), "unit": "ms", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64"}[solver], "data": "synthetic",
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64"}[solver.split("+")[0]], "data": "synthetic",
         "config": {"workload": "octree cantilever 16x8x8 base leaves, 3 refinement levels, band-refined and "
                                "2:1 balanced", "elements": ne, "nodes": nn, "dofs": 3 * nn,
                    "hanging_nodes": int(len(mesh.hang_node)), "chunks": info["n_chunks"], "solver": solver,

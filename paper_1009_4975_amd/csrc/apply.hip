@@ -340,7 +340,9 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, CgA
   const uint8_t* __restrict__ fix = a.fix;
   const int n0 = ca.chunk_ent[cc], nent = have ? ca.chunk_ent[cc + 1] - n0 : 0;
   const int t0 = ca.chunk_tab[cc], nt = have ? ca.chunk_tab[cc + 1] - t0 : 0;
-  const int nown = ca.chunk_nown[cc], nreg = ca.chunk_nreg[cc], nhown = ca.chunk_nhown[cc];
+  // surplus workgroups (the grid is rounded up to a multiple of 8) own nothing
+  const int nown = have ? ca.chunk_nown[cc] : 0, nreg = have ? ca.chunk_nreg[cc] : 0;
+  const int nhown = have ? ca.chunk_nhown[cc] : 0;
   const int h0 = ca.chunk_trip[cc], nh = have ? ca.chunk_trip[cc + 1] - h0 : 0;
   // Every index this block needs is requested before the CG prologue (which
   // waits on the previous pass's partial sums), so those round trips overlap.
@@ -371,6 +373,29 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, CgA
     trip_w_s[k] = ca.trip_w[h0 + k];
   }
   for (int t = nreg + tid; t < nt; t += 256) hbeg_s[t - nreg] = ca.tab_hbeg[t0 + t];
+  // raw vector values of the regular table nodes, also requested before the
+  // prologue; beta is applied once the prologue has it
+  const bool first = FUSED && cg.it == 0;
+  VT xv[NPT][3], pv[FUSED ? NPT : 1][3];
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) {
+    const int t = tid + 256 * r;
+    fb[r] = 0;
+#pragma unroll
+    for (int c3 = 0; c3 < 3; ++c3) {
+      xv[r][c3] = 0;
+      if (FUSED) pv[r][c3] = 0;
+    }
+    if (t < nreg && gn[r] >= 0) {
+      const long g = 3L * gn[r];
+      fb[r] = fix[gn[r]];
+#pragma unroll
+      for (int c3 = 0; c3 < 3; ++c3) {
+        xv[r][c3] = X[g + c3];
+        if (FUSED && !first) pv[r][c3] = PO[g + c3];
+      }
+    }
+  }
   double beta = 0.0;
   if (FUSED) {
     if (!cg_prologue(cg, beta, sh)) return;
@@ -380,27 +405,19 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, CgA
     return;
   }
   const VT vbeta = (VT)beta;
-  const bool first = FUSED && cg.it == 0;
   VT cep[EPT];
 #pragma unroll
   for (int r = 0; r < EPT; ++r) cep[r] = coef[eel[r]];
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
     const int t = tid + 256 * r;
-    fb[r] = 0;
     if (t < nreg) {
-      const long g = 3L * gn[r];
-      const uint8_t f = fix[gn[r]];
-      fb[r] = f;
-      VT v0 = X[g], v1 = X[g + 1], v2 = X[g + 2];
-      if (FUSED && !first) {
-        v0 += vbeta * PO[g];
-        v1 += vbeta * PO[g + 1];
-        v2 += vbeta * PO[g + 2];
+#pragma unroll
+      for (int c3 = 0; c3 < 3; ++c3) {
+        VT v = xv[r][c3];
+        if (FUSED && !first) v += vbeta * pv[r][c3];
+        xs[3 * t + c3] = ((fb[r] >> c3) & 1) ? (VT)0 : v;
       }
-      xs[3 * t + 0] = (f & 1) ? (VT)0 : v0;
-      xs[3 * t + 1] = (f & 2) ? (VT)0 : v1;
-      xs[3 * t + 2] = (f & 4) ? (VT)0 : v2;
     }
   }
   for (int i = tid; i < nt * 3; i += 256) ys[i] = 0.0;

@@ -37,7 +37,7 @@ constexpr int TRIP_MAX = 1024;  // hanging (node, master, weight) triples per ch
 
 // Reductions: fixed grid of partial sums; every consumer re-adds them in the
 // same order, so results are deterministic without a separate finalize pass.
-constexpr int RED_BLOCKS = 256;
+constexpr int RED_BLOCKS = 512;
 constexpr int RED_THREADS = 256;
 constexpr int OC_WS = 2 + 256 * 256 + 64;
 constexpr int COARSE_KMAX = 96;  // coarse-space columns
