@@ -44,6 +44,12 @@ struct UArgs {
   const void* kb;    // FP64/FP32: 72 block constants; BF16: K0 hi/lo bits
   int nx, ny, nz, tiles_x, tiles_y, zchunk, n_tiles;
   const double* stop;
+  // fused octree pass with the affine coarse space: x holds r and the staged
+  // direction is p = (D^-1 r + Z cz) + beta p_old
+  const void* dinv = nullptr;
+  const float4* geo = nullptr;
+  const double* cz = nullptr;
+  int coarse_R = 0;
 };
 
 // workgroups per CU the uniform kernels are compiled for (register budget:
@@ -318,7 +324,7 @@ struct ChunkArgs {
   int n_chunks;
 };
 
-template <typename VT, int PREC, bool FUSED>
+template <typename VT, int PREC, bool FUSED, bool COARSE = false>
 __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, CgArgs cg) {
   __shared__ VT xs[TAB_MAX * 3];
   __shared__ double ys[TAB_MAX * 3];  // FP64 LDS accumulators (see k_apply_uniform)
@@ -376,7 +382,11 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, CgA
   // raw vector values of the regular table nodes, also requested before the
   // prologue; beta is applied once the prologue has it
   const bool first = FUSED && cg.it == 0;
-  VT xv[NPT][3], pv[FUSED ? NPT : 1][3];
+  VT xv[NPT][3], pv[FUSED ? NPT : 1][3], dv[COARSE ? NPT : 1][3];
+  float4 gv[COARSE ? NPT : 1];
+  __shared__ double czs[COARSE ? COARSE_KMAX : 1];
+  if (COARSE)
+    for (int j = tid; j < 12 * a.coarse_R; j += 256) czs[j] = a.cz[j];
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
     const int t = tid + 256 * r;
@@ -385,7 +395,9 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, CgA
     for (int c3 = 0; c3 < 3; ++c3) {
       xv[r][c3] = 0;
       if (FUSED) pv[r][c3] = 0;
+      if (COARSE) dv[r][c3] = 0;
     }
+    if (COARSE) gv[r] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (t < nreg && gn[r] >= 0) {
       const long g = 3L * gn[r];
       fb[r] = fix[gn[r]];
@@ -393,7 +405,9 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, CgA
       for (int c3 = 0; c3 < 3; ++c3) {
         xv[r][c3] = X[g + c3];
         if (FUSED && !first) pv[r][c3] = PO[g + c3];
+        if (COARSE) dv[r][c3] = ((const VT*)a.dinv)[g + c3];
       }
+      if (COARSE) gv[r] = a.geo[gn[r]];
     }
   }
   double beta = 0.0;
@@ -415,6 +429,18 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, CgA
 #pragma unroll
       for (int c3 = 0; c3 < 3; ++c3) {
         VT v = xv[r][c3];
+        if (COARSE) {
+          // z = D^-1 r + Z cz with the affine fields of this node (zero on
+          // supported and hanging DOFs, where r and the fields vanish)
+          const int w = __float_as_int(gv[r].w), gr = w & 0xff;
+          const double on = ((w >> (8 + c3)) & 1) ? 0.0 : 1.0;
+          const double d[3] = {(double)gv[r].x, (double)gv[r].y, (double)gv[r].z};
+          const int R = a.coarse_R;
+          const double zc = czs[gr * 3 + c3] + d[c3] * czs[(R + gr) * 3 + c3] +
+                            d[c3 == 2 ? 0 : c3 + 1] * czs[(2 * R + gr) * 3 + c3] +
+                            d[c3 == 0 ? 2 : c3 - 1] * czs[(3 * R + gr) * 3 + c3];
+          v = (VT)((double)dv[r][c3] * (double)v + on * zc);
+        }
         if (FUSED && !first) v += vbeta * pv[r][c3];
         xs[3 * t + c3] = ((fb[r] >> c3) & 1) ? (VT)0 : v;
       }
@@ -720,6 +746,35 @@ int apply_fused(amrto_ctx* ctx, const void* z, const void* pold, void* pnew, voi
   if (prec == AMRTO_FP64) return launch_t<double, P_F64, true>(ctx, a, cg);
   if (prec == AMRTO_FP32) return launch_t<float, P_F32, true>(ctx, a, cg);
   return launch_t<float, P_BF16, true>(ctx, a, cg);
+}
+
+// Fused octree pass with the affine coarse space folded into the staging
+// (no separate z pass): p = (D^-1 r + Z cz) + beta p_old, q = A~ p.
+int apply_fused_coarse(amrto_ctx* ctx, const void* r, const void* dinv, const void* pold, void* pnew, void* q,
+                       int prec, const CgArgs& cg) {
+  if (ctx->uniform || !ctx->coarse_affine_only || ctx->coarse_k <= 0)
+    return ctx->fail(AMRTO_ESTATE, "apply_fused_coarse: needs an octree mesh and an affine coarse space");
+  UArgs a = base_args(ctx, prec);
+  a.x = r;
+  a.pold = pold;
+  a.pnew = pnew;
+  a.y = q;
+  a.dinv = dinv;
+  a.geo = ctx->d_cgeo;
+  a.cz = ctx->d_cz;
+  a.coarse_R = ctx->coarse_R;
+  const dim3 grid(apply_blocks(ctx));
+  if (prec == AMRTO_FP64)
+    hipLaunchKernelGGL((k_apply_chunks<double, P_F64, true, true>), grid, dim3(256), 0, ctx->stream, a,
+                       chunk_args(ctx), cg);
+  else if (prec == AMRTO_FP32)
+    hipLaunchKernelGGL((k_apply_chunks<float, P_F32, true, true>), grid, dim3(256), 0, ctx->stream, a,
+                       chunk_args(ctx), cg);
+  else
+    hipLaunchKernelGGL((k_apply_chunks<float, P_BF16, true, true>), grid, dim3(256), 0, ctx->stream, a,
+                       chunk_args(ctx), cg);
+  AMRTO_HIP(hipGetLastError());
+  return AMRTO_OK;
 }
 
 int launch_diag(amrto_ctx* ctx) {

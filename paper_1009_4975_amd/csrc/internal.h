@@ -57,7 +57,9 @@ enum ScalarSlot {
   S_DONE = 3,  // 0 running, 1 converged, 2 breakdown
   S_ITERS = 4, // iterations completed when the flag was raised
   S_RR = 5,    // last r.r
-  S_COUNT = 8
+  // 6, 7: true residual r.r and b.b
+  S_CTZ = 8,   // coarse space: ct^T E^-1 ct, the coarse part of r.z
+  S_COUNT = 10
 };
 
 // Arguments of a fused conjugate-gradient step (see kernels.h).
@@ -68,6 +70,7 @@ struct CgArgs {
   int part_base;          // first slot of this kernel in part_out
   int it;
   double tol2;
+  int coarse = 0;         // r.z = partial sums + scal[S_CTZ]
 };
 
 }  // namespace amrto
@@ -187,6 +190,8 @@ int mask_vector_n(amrto_ctx* ctx, double* x, int count);
 int launch_zt(amrto_ctx* ctx, const double* v);
 int apply_stop(amrto_ctx* ctx, const void* x, void* y, int prec, const double* stop);
 int apply_fused(amrto_ctx* ctx, const void* z, const void* pold, void* pnew, void* q, int prec, const CgArgs& cg);
+int apply_fused_coarse(amrto_ctx* ctx, const void* r, const void* dinv, const void* pold, void* pnew, void* q,
+                       int prec, const CgArgs& cg);
 int apply_blocks(const amrto_ctx* ctx);
 void uniform_grid(const amrto_ctx* ctx, int& tiles_x, int& tiles_y, int& zchunk, int& n_tiles, int& grid);
 

@@ -154,7 +154,8 @@ __device__ __forceinline__ void mfma_tile_bf16(const bf16x8 (&a)[2][2], const fl
 
 __device__ __forceinline__ bool cg_prologue(const CgArgs& cg, double& beta, double* sh) {
   if (cg.scal[S_DONE] != 0.0) return false;
-  const double rz = sum_partials(cg.part_in, RED_BLOCKS, sh);
+  double rz = sum_partials(cg.part_in, RED_BLOCKS, sh);
+  if (cg.coarse) rz += cg.scal[S_CTZ];
   const double rr = sum_partials(cg.part_in + RED_BLOCKS, RED_BLOCKS, sh);
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   if (!(rz == rz) || !(rr == rr) || rr > 1e300 || rz > 1e300) {

@@ -68,9 +68,10 @@ __global__ __launch_bounds__(256) void k_init(const BT* __restrict__ b, const BT
 
 // bb_mode 0: b.b from the partials; 1: keep scal[S_BB] (set by the caller)
 __global__ __launch_bounds__(256) void k_init_scalars(const double* __restrict__ part, double* __restrict__ scal,
-                                                      double tol2, int keep_bb) {
+                                                      double tol2, int keep_bb, int add_ctz) {
   __shared__ double sh[8];
-  const double rz = sum_partials(part, RED_BLOCKS, sh);
+  double rz = sum_partials(part, RED_BLOCKS, sh);
+  if (add_ctz) rz += scal[S_CTZ];
   const double rr = sum_partials(part + RED_BLOCKS, RED_BLOCKS, sh);
   const double bb = sum_partials(part + 2 * RED_BLOCKS, RED_BLOCKS, sh);
   if (threadIdx.x == 0) {
@@ -261,14 +262,17 @@ __global__ __launch_bounds__(256) void k_zt_part(CoarseArgs ca, const VT* __rest
   zt_store(acc, k, part);
 }
 
-// Coarse-corrected variant of the update pass: x += alpha p, r -= alpha q and
-// the block partials of Z^T r (then k_coarse_sum, k_coarse_cz, k_coarse_z).
+// Coarse-corrected variant of the update pass: x += alpha p, r -= alpha q,
+// the block partials of Z^T r, and partials of r^T D^-1 r and r^T r (then
+// k_coarse_sum and k_coarse_cz; z is formed by k_coarse_z or, on octree
+// meshes with the affine space, inside the next operator pass).
 template <typename VT>
 __global__ __launch_bounds__(256) void k_cg_update_coarse(VT* __restrict__ x, VT* __restrict__ r,
-                                                          const VT* __restrict__ p, const VT* __restrict__ q, long n,
+                                                          const VT* __restrict__ p, const VT* __restrict__ q,
+                                                          const VT* __restrict__ dinv, long n,
                                                           const double* __restrict__ part_pq, int n_pq,
                                                           double* __restrict__ scal, int it, CoarseArgs ca,
-                                                          double* __restrict__ part_z) {
+                                                          double* __restrict__ part_z, double* __restrict__ part) {
   if (scal[S_DONE] != 0.0) return;
   __shared__ double sh[8];
   __shared__ double acc[COARSE_KMAX];
@@ -287,19 +291,28 @@ __global__ __launch_bounds__(256) void k_cg_update_coarse(VT* __restrict__ x, VT
   block_range(n, lo, hi);
   ZtAcc a;
   zt_clear(a, -1);
+  double srz = 0.0, srr = 0.0;
 #pragma unroll 2
   for (long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     double fv[COARSE_NFMAX];
     const int g = coarse_fields(ca, i, n, fv);
-    const VT pi = p[i], qi = q[i], ri = r[i], xi = x[i];
+    const VT pi = p[i], qi = q[i], ri = r[i], xi = x[i], di = dinv[i];
     x[i] = xi + alpha * pi;
     const VT rv = ri - alpha * qi;
     r[i] = rv;
+    srz += (double)rv * (double)di * (double)rv;
+    srr += (double)rv * (double)rv;
     zt_add(a, acc, fv, nf, R, g, (int)(i % 3), (double)rv);
   }
   zt_flush(a, acc, nf, R, lo < hi ? coarse_region(ca, (int)(lo / 3)) : 0, red);
   __syncthreads();
   zt_store(acc, k, part_z);
+  srz = block_sum(srz, sh);
+  srr = block_sum(srr, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = srz;
+    part[RED_BLOCKS + blockIdx.x] = srr;
+  }
 }
 
 // ct[j] = sum_b part[b k + j]: one block per coarse column, fixed-tree sum
@@ -316,25 +329,34 @@ __global__ __launch_bounds__(256) void k_coarse_sum(const double* __restrict__ p
 }
 
 // cz = E^-1 ct in one block: thread j walks column j of the symmetric E^-1
-// (row i of E^-1 is read coalesced across threads).
+// (row i of E^-1 is read coalesced across threads); ct^T cz is summed in
+// column order (deterministic).  (Copying E^-1 into LDS first measured slower.)
 __global__ __launch_bounds__(128) void k_coarse_cz(const double* __restrict__ ct_g, int k,
                                                    const double* __restrict__ Einv, double* __restrict__ cz,
-                                                   const double* __restrict__ stop) {
+                                                   double* __restrict__ ctz, const double* __restrict__ stop) {
   if (stop && *stop != 0.0) return;
-  __shared__ double ct[COARSE_KMAX];
+  __shared__ double ct[COARSE_KMAX], prod[COARSE_KMAX];
   for (int i = threadIdx.x; i < k; i += blockDim.x) ct[i] = ct_g[i];
   __syncthreads();
   const int j = threadIdx.x;
-  if (j >= k) return;
-  double s0 = 0.0, s1 = 0.0;
-  int i = 0;
+  if (j < k) {
+    double s0 = 0.0, s1 = 0.0;
+    int i = 0;
 #pragma unroll 4
-  for (; i + 1 < k; i += 2) {
-    s0 += Einv[(long)i * k + j] * ct[i];
-    s1 += Einv[(long)(i + 1) * k + j] * ct[i + 1];
+    for (; i + 1 < k; i += 2) {
+      s0 += Einv[(long)i * k + j] * ct[i];
+      s1 += Einv[(long)(i + 1) * k + j] * ct[i + 1];
+    }
+    if (i < k) s0 += Einv[(long)i * k + j] * ct[i];
+    cz[j] = s0 + s1;
+    prod[j] = ct[j] * (s0 + s1);
   }
-  if (i < k) s0 += Einv[(long)i * k + j] * ct[i];
-  cz[j] = s0 + s1;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < k; ++i) t += prod[i];
+    *ctz = t;
+  }
 }
 
 // z = D^-1 r + Z cz; partials r.z, r.r
@@ -428,8 +450,16 @@ static CoarseArgs coarse_args(const amrto_ctx* ctx) {
   return a;
 }
 
-// with a coarse space: z = D^-1 r + Z E^-1 Z^T r for the initial residual
-// (overwrites the r.z and r.r partials of k_init; b.b stays)
+// The affine coarse space on an octree mesh is folded into the operator pass
+// (z = D^-1 r + Z cz formed while staging; r.z = r^T D^-1 r + ct^T cz).
+static bool coarse_fused(const amrto_ctx* ctx) {
+  return ctx->coarse_k > 0 && !ctx->uniform && ctx->coarse_affine_only;
+}
+
+// with a coarse space: cz = E^-1 Z^T r for the initial residual and either
+// z = D^-1 r + Z cz (overwriting the r.z and r.r partials of k_init; b.b
+// stays) or, in the fused form, ct^T cz in its scalar slot (the partials of
+// k_init already are r^T D^-1 r and r^T r)
 template <typename VT>
 static void coarse_init(amrto_ctx* ctx, const Vecs<VT>& v) {
   if (ctx->coarse_k <= 0) return;
@@ -439,9 +469,10 @@ static void coarse_init(amrto_ctx* ctx, const Vecs<VT>& v) {
   hipLaunchKernelGGL(k_coarse_sum, dim3(ctx->coarse_k), dim3(256), 0, ctx->stream, ctx->d_cpart, ctx->coarse_k,
                      RED_BLOCKS, ctx->d_ct, (const double*)nullptr);
   hipLaunchKernelGGL(k_coarse_cz, dim3(1), dim3(128), 0, ctx->stream, (const double*)ctx->d_ct, ctx->coarse_k,
-                     (const double*)ctx->d_cinv, ctx->d_cz, (const double*)nullptr);
-  hipLaunchKernelGGL(k_coarse_z<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, v.r, v.z, v.dinv, n3, ctx->d_cz,
-                     coarse_args(ctx), ctx->d_part, (const double*)nullptr);
+                     (const double*)ctx->d_cinv, ctx->d_cz, ctx->d_scal + S_CTZ, (const double*)nullptr);
+  if (!coarse_fused(ctx))
+    hipLaunchKernelGGL(k_coarse_z<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, v.r, v.z, v.dinv, n3, ctx->d_cz,
+                       coarse_args(ctx), ctx->d_part, (const double*)nullptr);
 }
 
 int launch_zt(amrto_ctx* ctx, const double* v) {
@@ -479,22 +510,25 @@ static int read_scalars(amrto_ctx* ctx) {
 template <typename VT>
 static int enqueue_iters(amrto_ctx* ctx, const Vecs<VT>& v, VT* x, int prec, double tol2, int it0, int count) {
   const long n3 = 3L * ctx->n_nodes;
+  const bool fused = coarse_fused(ctx);
   for (int it = it0; it < it0 + count; ++it) {
     VT* pnew = (it & 1) ? v.p1 : v.p0;
     VT* pold = (it & 1) ? v.p0 : v.p1;
-    CgArgs cg{ctx->d_scal, ctx->d_part, ctx->d_partpq, 0, it, tol2};
-    int rc = apply_fused(ctx, v.z, pold, pnew, v.q, prec, cg);
+    CgArgs cg{ctx->d_scal, ctx->d_part, ctx->d_partpq, 0, it, tol2, fused ? 1 : 0};
+    int rc = fused ? apply_fused_coarse(ctx, v.r, v.dinv, pold, pnew, v.q, prec, cg)
+                   : apply_fused(ctx, v.z, pold, pnew, v.q, prec, cg);
     if (rc) return rc;
     if (ctx->coarse_k > 0) {
-      hipLaunchKernelGGL(k_cg_update_coarse<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew, v.q, n3,
-                         ctx->d_partpq, ctx->n_partpq, ctx->d_scal, it, coarse_args(ctx), ctx->d_cpart);
+      hipLaunchKernelGGL(k_cg_update_coarse<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew, v.q,
+                         v.dinv, n3, ctx->d_partpq, ctx->n_partpq, ctx->d_scal, it, coarse_args(ctx), ctx->d_cpart,
+                         ctx->d_part);
       hipLaunchKernelGGL(k_coarse_sum, dim3(ctx->coarse_k), dim3(256), 0, ctx->stream, ctx->d_cpart,
                          ctx->coarse_k, RED_BLOCKS, ctx->d_ct, ctx->d_scal + S_DONE);
       hipLaunchKernelGGL(k_coarse_cz, dim3(1), dim3(128), 0, ctx->stream, (const double*)ctx->d_ct, ctx->coarse_k,
-                         (const double*)ctx->d_cinv, ctx->d_cz, ctx->d_scal + S_DONE);
-      hipLaunchKernelGGL(k_coarse_z<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, v.r, v.z, v.dinv, n3,
-                         ctx->d_cz, coarse_args(ctx),
-                         ctx->d_part, ctx->d_scal + S_DONE);
+                         (const double*)ctx->d_cinv, ctx->d_cz, ctx->d_scal + S_CTZ, ctx->d_scal + S_DONE);
+      if (!fused)
+        hipLaunchKernelGGL(k_coarse_z<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, v.r, v.z, v.dinv, n3,
+                           ctx->d_cz, coarse_args(ctx), ctx->d_part, ctx->d_scal + S_DONE);
     } else {
       hipLaunchKernelGGL(k_cg_update<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew, v.q, v.dinv,
                          v.z, n3, ctx->d_partpq, ctx->n_partpq, ctx->d_scal, it, ctx->d_part);
@@ -520,7 +554,8 @@ static int cg_fp64_run(amrto_ctx* ctx, const double* b, double* x, double rtol, 
   hipLaunchKernelGGL((k_init<double, double>), dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, b, v.q, v.r, v.z, v.dinv,
                      n3, ctx->d_part);
   coarse_init<double>(ctx, v);
-  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(256), 0, ctx->stream, ctx->d_part, ctx->d_scal, tol2, 0);
+  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(256), 0, ctx->stream, ctx->d_part, ctx->d_scal, tol2, 0,
+                     coarse_fused(ctx) ? 1 : 0);
   AMRTO_HIP(hipGetLastError());
   int it = 0;
   int status = AMRTO_NOT_CONVERGED;
@@ -628,7 +663,8 @@ static int cg_mixed(amrto_ctx* ctx, const double* b, double* x, int prec, double
       // the recurrence measures its residual against b.b
       hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, ctx->stream, ctx->d_scal, (int)S_BB, bb);
       if (*updates == 0) {
-        hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(256), 0, ctx->stream, ctx->d_part, ctx->d_scal, 0.0, 1);
+        hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(256), 0, ctx->stream, ctx->d_part, ctx->d_scal, 0.0, 1,
+                           coarse_fused(ctx) ? 1 : 0);
       } else {
         // continue the recurrence (same search direction): clear the stop flag
         hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, ctx->stream, ctx->d_scal, (int)S_DONE, 0.0);
