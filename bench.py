@@ -329,7 +329,8 @@ def c4_simp(torch, binding, synth):
     n_train = ex["train_iters"]
     out = {}
     for name, prec, mode in (("plain_fp64", binding.FP64, None), ("plain_fp32", binding.FP32, None),
-                             ("coarse_fp64", binding.FP64, "coarse"), ("learned_coarse_fp64", binding.FP64, "learned"),
+                             ("coarse_fp64", binding.FP64, "coarse"), ("coarse_fp32", binding.FP32, "coarse"),
+                             ("learned_coarse_fp64", binding.FP64, "learned"),
                              ("learned_coarse_fp32", binding.FP32, "learned")):
         t0 = time.perf_counter()
         sim = AdaptiveSIMP(case.base, case.max_level, case.fixed, case.load, volfrac=ex["volfrac"],

@@ -229,11 +229,11 @@ int amrto_mask(amrto_ctx* ctx, double* x_dev);
  * motions and the constant strains), then the n_fields caller fields
  * (fields_host: host array of device pointers to 3n FP64 vectors; copied).
  * Every field is masked (zero on supported and hanging DOFs).  At most 8
- * fields in all, and k = 3 rx ry rz (4 affine + n_fields) <= 96.  Z^T A~ Z is formed by k operator applications
+ * fields in all, and k = 3 rx ry rz (4 affine + n_fields) <= 384.  Z^T A~ Z is formed by k operator applications
  * and factorised on the host, dropping columns whose pivot falls below 1e-12
  * of the largest (*k_kept receives the rank kept; may be NULL).  Needs the
  * density set; amrto_set_density drops the coarse space.
- * Errors: EINVAL (bad sizes, k > 96), ESTATE, EHIP. */
+ * Errors: EINVAL (bad sizes, k > 384), ESTATE, EHIP. */
 int amrto_coarse_setup(amrto_ctx* ctx, int32_t affine, const double* const* fields_host, int32_t n_fields,
                        int32_t rx, int32_t ry, int32_t rz, int32_t* k_kept);
 /* Stop using the coarse space (plain Jacobi again). */

@@ -180,7 +180,7 @@ int amrto_coarse_setup(amrto_ctx* ctx, int32_t affine, const double* const* fiel
   if (n_fields < 0 || (n_fields > 0 && !fields) || nf < 1 || nf > COARSE_NFMAX || rx < 1 || ry < 1 || rz < 1 ||
       R > 255 || k > COARSE_KMAX)
     return ctx->fail(AMRTO_EINVAL,
-                     "amrto_coarse_setup: need at most 8 fields and 1 <= 3 (4 affine + n_fields) rx ry rz <= 96");
+                     "amrto_coarse_setup: need at most 8 fields and 1 <= 3 (4 affine + n_fields) rx ry rz <= 384");
   AMRTO_HIP(hipSetDevice(ctx->device));
   ctx->coarse_k = 0;  // no coarse space unless this setup completes
   const long n3 = 3L * ctx->n_nodes;

@@ -40,7 +40,7 @@ constexpr int TRIP_MAX = 1024;  // hanging (node, master, weight) triples per ch
 constexpr int RED_BLOCKS = 512;
 constexpr int RED_THREADS = 256;
 constexpr int OC_WS = 2 + 256 * 256 + 64;
-constexpr int COARSE_KMAX = 96;  // coarse-space columns
+constexpr int COARSE_KMAX = 384;  // coarse-space columns
 constexpr int COARSE_NFMAX = 8;  // coarse-space fields (4 affine + caller fields)
 
 template <typename T>

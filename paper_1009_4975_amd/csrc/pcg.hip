@@ -331,7 +331,7 @@ __global__ __launch_bounds__(256) void k_coarse_sum(const double* __restrict__ p
 // cz = E^-1 ct in one block: thread j walks column j of the symmetric E^-1
 // (row i of E^-1 is read coalesced across threads); ct^T cz is summed in
 // column order (deterministic).  (Copying E^-1 into LDS first measured slower.)
-__global__ __launch_bounds__(128) void k_coarse_cz(const double* __restrict__ ct_g, int k,
+__global__ __launch_bounds__(COARSE_KMAX) void k_coarse_cz(const double* __restrict__ ct_g, int k,
                                                    const double* __restrict__ Einv, double* __restrict__ cz,
                                                    double* __restrict__ ctz, const double* __restrict__ stop) {
   if (stop && *stop != 0.0) return;
@@ -450,6 +450,9 @@ static CoarseArgs coarse_args(const amrto_ctx* ctx) {
   return a;
 }
 
+// one thread per coarse column, whole wavefronts
+static int cz_threads(const amrto_ctx* ctx) { return ((ctx->coarse_k + 63) / 64) * 64; }
+
 // The affine coarse space on an octree mesh is folded into the operator pass
 // (z = D^-1 r + Z cz formed while staging; r.z = r^T D^-1 r + ct^T cz).
 static bool coarse_fused(const amrto_ctx* ctx) {
@@ -468,7 +471,7 @@ static void coarse_init(amrto_ctx* ctx, const Vecs<VT>& v) {
                      ctx->d_cpart);
   hipLaunchKernelGGL(k_coarse_sum, dim3(ctx->coarse_k), dim3(256), 0, ctx->stream, ctx->d_cpart, ctx->coarse_k,
                      RED_BLOCKS, ctx->d_ct, (const double*)nullptr);
-  hipLaunchKernelGGL(k_coarse_cz, dim3(1), dim3(128), 0, ctx->stream, (const double*)ctx->d_ct, ctx->coarse_k,
+  hipLaunchKernelGGL(k_coarse_cz, dim3(1), dim3(cz_threads(ctx)), 0, ctx->stream, (const double*)ctx->d_ct, ctx->coarse_k,
                      (const double*)ctx->d_cinv, ctx->d_cz, ctx->d_scal + S_CTZ, (const double*)nullptr);
   if (!coarse_fused(ctx))
     hipLaunchKernelGGL(k_coarse_z<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, v.r, v.z, v.dinv, n3, ctx->d_cz,
@@ -524,7 +527,7 @@ static int enqueue_iters(amrto_ctx* ctx, const Vecs<VT>& v, VT* x, int prec, dou
                          ctx->d_part);
       hipLaunchKernelGGL(k_coarse_sum, dim3(ctx->coarse_k), dim3(256), 0, ctx->stream, ctx->d_cpart,
                          ctx->coarse_k, RED_BLOCKS, ctx->d_ct, ctx->d_scal + S_DONE);
-      hipLaunchKernelGGL(k_coarse_cz, dim3(1), dim3(128), 0, ctx->stream, (const double*)ctx->d_ct, ctx->coarse_k,
+      hipLaunchKernelGGL(k_coarse_cz, dim3(1), dim3(cz_threads(ctx)), 0, ctx->stream, (const double*)ctx->d_ct, ctx->coarse_k,
                          (const double*)ctx->d_cinv, ctx->d_cz, ctx->d_scal + S_CTZ, ctx->d_scal + S_DONE);
       if (!fused)
         hipLaunchKernelGGL(k_coarse_z<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, v.r, v.z, v.dinv, n3,
