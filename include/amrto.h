@@ -233,7 +233,8 @@ int amrto_mask(amrto_ctx* ctx, double* x_dev);
  * and factorised on the host, dropping columns whose pivot falls below 1e-12
  * of the largest (*k_kept receives the rank kept; may be NULL).  Needs the
  * density set; amrto_set_density drops the coarse space.
- * Errors: EINVAL (bad sizes, k > 384), ESTATE, EHIP. */
+ * Errors: EINVAL (bad sizes, k > 384, a field with non-finite values; the
+ * solve then runs without a coarse space), ESTATE, EHIP. */
 int amrto_coarse_setup(amrto_ctx* ctx, int32_t affine, const double* const* fields_host, int32_t n_fields,
                        int32_t rx, int32_t ry, int32_t rz, int32_t* k_kept);
 /* Stop using the coarse space (plain Jacobi again). */
@@ -242,7 +243,8 @@ int amrto_coarse_clear(amrto_ctx* ctx);
  * (base_dev may be NULL: zero), so x0 is never worse in the energy norm than
  * base or any single v_j.  vecs_host: host array of n (1..8) device pointers;
  * base and the vectors should be masked.  coef_host (may be NULL) receives a.
- * x0_dev must not alias base or the vectors. */
+ * x0_dev must not alias base or the vectors.  EINVAL if a vector or the base
+ * residual is not finite (x0 is then left untouched). */
 int amrto_energy_combine(amrto_ctx* ctx, const double* b_dev, const double* base_dev,
                          const double* const* vecs_host, int32_t n, double* x0_dev, double* coef_host);
 

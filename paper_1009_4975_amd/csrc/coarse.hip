@@ -242,6 +242,8 @@ int amrto_coarse_setup(amrto_ctx* ctx, int32_t affine, const double* const* fiel
   std::vector<double> E((long)k * k);
   AMRTO_HIP(hipMemcpyAsync(E.data(), ctx->d_cinv, E.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   AMRTO_HIP(hipStreamSynchronize(ctx->stream));
+  for (double e : E)
+    if (!std::isfinite(e)) return ctx->fail(AMRTO_EINVAL, "amrto_coarse_setup: a coarse field is not finite");
   std::vector<double> inv;
   const int kept = spd_inverse(E, k, inv);
   AMRTO_HIP(hipMemcpy(ctx->d_cinv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -297,6 +299,12 @@ int amrto_energy_combine(amrto_ctx* ctx, const double* b, const double* base, co
     }
     int rc2 = dot(vecs_host[j], res, &rhs[j]);
     if (rc2) return rc2;
+  }
+  for (int i = 0; i < n; ++i) {
+    if (!std::isfinite(rhs[i])) return ctx->fail(AMRTO_EINVAL, "amrto_energy_combine: a vector is not finite");
+    for (int j = 0; j < n; ++j)
+      if (!std::isfinite(G[i * n + j]))
+        return ctx->fail(AMRTO_EINVAL, "amrto_energy_combine: a vector is not finite");
   }
   std::vector<double> inv;
   spd_inverse(G, n, inv);

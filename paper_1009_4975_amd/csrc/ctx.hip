@@ -217,6 +217,11 @@ int amrto_upload_mesh(amrto_ctx* ctx, const amrto_mesh* m) {
     ctx->nx = (int)nx; ctx->ny = (int)ny; ctx->nz = (int)nz;
   } else {
     if (!m->node_xyz) return ctx->fail(AMRTO_EINVAL, "amrto_upload_mesh: octree mesh needs node_xyz");
+    if (m->dims[0] <= 0 || m->dims[1] <= 0 || m->dims[2] <= 0)
+      return ctx->fail(AMRTO_EINVAL, "amrto_upload_mesh: octree mesh needs positive lattice extents");
+    for (long i = 0; i < 3L * m->n_nodes; ++i)
+      if (m->node_xyz[i] < 0 || m->node_xyz[i] > m->dims[i % 3])
+        return ctx->fail(AMRTO_EINVAL, "amrto_upload_mesh: node coordinate outside the lattice box");
     for (long i = 0; i < 8L * m->n_elems; ++i)
       if (m->elem_nodes[i] < 0 || m->elem_nodes[i] >= m->n_nodes)
         return ctx->fail(AMRTO_EINVAL, "amrto_upload_mesh: element node index out of range");

@@ -133,14 +133,21 @@ class LearnedWarmStart:
         coarse = self.coarse if coarse is None else (None if coarse is False else coarse)
         uprev = sim.u
         sim.ctx.mask(uprev)  # the solve ignores these entries of its initial guess anyway
-        coef, kept, d = [], 0, None
+        coef, kept, d, fallback = [], 0, None, None
         if use_net:
             d = self.predict(sim)
             x0 = torch.empty_like(uprev)
-            coef = sim.ctx.energy_combine(sim.b, [d], x0, base=uprev)
-            sim.u = x0
+            try:
+                coef = sim.ctx.energy_combine(sim.b, [d], x0, base=uprev)
+                sim.u = x0
+            except binding.AmrtoError as err:  # e.g. a non-finite prediction: keep u_prev
+                fallback, d = str(err), None
         if coarse:
             extra = [d] if (coarse == "affine+pred" and d is not None) else []
-            kept = sim.ctx.coarse_setup(extra, *self.regions, affine=True)
+            try:
+                kept = sim.ctx.coarse_setup(extra, *self.regions, affine=True)
+            except binding.AmrtoError as err:  # plain Jacobi-PCG then
+                sim.ctx.coarse_clear()
+                fallback = str(err)
         torch.cuda.synchronize(self.dev)
-        self.last = dict(coef=coef, kept=kept, ms=1e3 * (time.perf_counter() - t0))
+        self.last = dict(coef=coef, kept=kept, fallback=fallback, ms=1e3 * (time.perf_counter() - t0))
