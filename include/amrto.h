@@ -156,6 +156,9 @@ typedef struct {
   int32_t check_every;/* iterations between host convergence checks (default 16) */
   int32_t use_coarse; /* 1 (default): add the coarse correction set by
                          amrto_coarse_setup, when one is set; 0: Jacobi only */
+  int32_t fallback_fp64; /* 1 (default): a mixed solve that breaks down or
+                         stalls above rtol continues as plain FP64 PCG from
+                         its iterate (from zero if that is not finite) */
 } amrto_solve_opts;
 
 typedef struct {
@@ -164,6 +167,7 @@ typedef struct {
                           restarts (plain FP64) */
   double rel_res;      /* true FP64 ||b - A~ u|| / ||b|| at exit */
   double ms;           /* wall time of the call */
+  int32_t fell_back;   /* 1 if a mixed solve was finished by plain FP64 PCG */
 } amrto_solve_stats;
 
 /* Fill opts with the defaults above. */
@@ -282,6 +286,10 @@ int amrto_net_n_params(const amrto_net* net, int64_t* n);
 int amrto_net_get_params(const amrto_net* net, float* host);
 int amrto_net_set_params(amrto_net* net, const float* host);
 int amrto_net_get_grads(const amrto_net* net, float* host);
+/* host copies of the Adam first and second moments (n_params each), for a
+ * checkpoint; set rejects non-finite moments and negative second moments */
+int amrto_net_get_adam(const amrto_net* net, float* m_host, float* v_host);
+int amrto_net_set_adam(amrto_net* net, const float* m_host, const float* v_host);
 /* in_dev (batch, C0, gz, gy, gx) -> out_dev (batch, C_last, gz, gy, gx) (out may be NULL);
  * activations are kept for the next backward */
 int amrto_net_forward(amrto_net* net, const float* in_dev, int32_t batch, float* out_dev);

@@ -45,11 +45,12 @@ class Region(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_it", C.c_int32), ("precond", C.c_int32),
                 ("inner_prec", C.c_int32), ("inner_rtol", C.c_double), ("check_every", C.c_int32),
-                ("use_coarse", C.c_int32)]
+                ("use_coarse", C.c_int32), ("fallback_fp64", C.c_int32)]
 
 
 class SolveStats(C.Structure):
-    _fields_ = [("iters", C.c_int32), ("outer", C.c_int32), ("rel_res", C.c_double), ("ms", C.c_double)]
+    _fields_ = [("iters", C.c_int32), ("outer", C.c_int32), ("rel_res", C.c_double), ("ms", C.c_double),
+                ("fell_back", C.c_int32)]
 
 
 _SIGS = {
@@ -86,6 +87,8 @@ _SIGS = {
     "amrto_net_get_params": (C.c_int, [_p, _p]),
     "amrto_net_set_params": (C.c_int, [_p, _p]),
     "amrto_net_get_grads": (C.c_int, [_p, _p]),
+    "amrto_net_get_adam": (C.c_int, [_p, _p, _p]),
+    "amrto_net_set_adam": (C.c_int, [_p, _p, _p]),
     "amrto_net_forward": (C.c_int, [_p, _p, C.c_int32, _p]),
     "amrto_net_backward": (C.c_int, [_p, _p, _p]),
     "amrto_net_mse": (C.c_int, [_p, _p, _p, _p, C.c_int64, _p, C.POINTER(C.c_double)]),
@@ -359,16 +362,18 @@ class Context:
         self._chk(self.lib.amrto_get_diag(self.h, _dev(out, self.torch.float64)))
 
     def pcg(self, b, u, rtol=1e-8, max_it=20000, inner_prec=FP64, inner_rtol=1e-3, check_every=16,
-            use_coarse=True, allow_not_converged=False):
+            use_coarse=True, fallback_fp64=True, allow_not_converged=False):
         o = SolveOpts()
         self.lib.amrto_solve_opts_default(C.byref(o))
         o.rtol, o.max_it, o.inner_prec, o.inner_rtol = rtol, max_it, inner_prec, inner_rtol
         o.check_every, o.use_coarse = check_every, int(bool(use_coarse))
+        o.fallback_fp64 = int(bool(fallback_fp64))
         st = SolveStats()
         rc = self.lib.amrto_pcg(self.h, _dev(b, self.torch.float64), _dev(u, self.torch.float64), C.byref(o),
                                 C.byref(st))
         self._chk(rc, allow_not_converged=allow_not_converged)
-        return dict(iters=st.iters, outer=st.outer, rel_res=st.rel_res, ms=st.ms, status=STATUS[rc])
+        return dict(iters=st.iters, outer=st.outer, rel_res=st.rel_res, ms=st.ms, status=STATUS[rc],
+                    fell_back=bool(st.fell_back))
 
     def compliance(self, u, f, rho=None, dc=None):
         c = C.c_double()
@@ -478,6 +483,19 @@ class Net:
         out = np.empty(self.n_params(), np.float32)
         self._chk(self.lib.amrto_net_get_grads(self.h, out.ctypes.data))
         return out
+
+    def get_adam(self):
+        """Adam moments (m, v) as host arrays."""
+        m = np.empty(self.n_params(), np.float32)
+        v = np.empty_like(m)
+        self._chk(self.lib.amrto_net_get_adam(self.h, m.ctypes.data, v.ctypes.data))
+        return m, v
+
+    def set_adam(self, m, v):
+        m = np.ascontiguousarray(m, dtype=np.float32)
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        assert m.size == v.size == self.n_params()
+        self._chk(self.lib.amrto_net_set_adam(self.h, m.ctypes.data, v.ctypes.data))
 
     def forward(self, x, out):
         self._chk(self.lib.amrto_net_forward(self.h, _dev(x, self.torch.float32), int(x.shape[0]),

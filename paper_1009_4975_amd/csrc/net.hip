@@ -354,6 +354,27 @@ int amrto_net_get_grads(const amrto_net* net, float* host) {
   return hipMemcpy(host, net->d_grads, net->n_params * 4, hipMemcpyDeviceToHost) == hipSuccess ? AMRTO_OK : AMRTO_EHIP;
 }
 
+int amrto_net_get_adam(const amrto_net* net, float* m_host, float* v_host) {
+  if (!net || !m_host || !v_host) return AMRTO_EINVAL;
+  const size_t bytes = net->n_params * 4;
+  return hipMemcpy(m_host, net->d_m, bytes, hipMemcpyDeviceToHost) == hipSuccess &&
+                 hipMemcpy(v_host, net->d_v, bytes, hipMemcpyDeviceToHost) == hipSuccess
+             ? AMRTO_OK
+             : AMRTO_EHIP;
+}
+
+int amrto_net_set_adam(amrto_net* net, const float* m_host, const float* v_host) {
+  if (!net || !m_host || !v_host) return AMRTO_EINVAL;
+  for (int64_t i = 0; i < net->n_params; ++i)
+    if (!std::isfinite(m_host[i]) || !std::isfinite(v_host[i]) || v_host[i] < 0.f)
+      return net->fail(AMRTO_EINVAL, "amrto_net_set_adam: moments must be finite, second moments >= 0");
+  const size_t bytes = net->n_params * 4;
+  return hipMemcpy(net->d_m, m_host, bytes, hipMemcpyHostToDevice) == hipSuccess &&
+                 hipMemcpy(net->d_v, v_host, bytes, hipMemcpyHostToDevice) == hipSuccess
+             ? AMRTO_OK
+             : AMRTO_EHIP;
+}
+
 int amrto_net_forward(amrto_net* net, const float* in, int32_t batch, float* out) {
   if (!net || !in || batch < 1 || batch > net->max_batch) return net ? net->fail(AMRTO_EINVAL, "amrto_net_forward: bad arguments") : AMRTO_EINVAL;
   NET_HIP(hipSetDevice(net->device));

@@ -726,6 +726,7 @@ void amrto_solve_opts_default(amrto_solve_opts* o) {
   o->inner_rtol = 1e-2;
   o->check_every = 16;
   o->use_coarse = 1;
+  o->fallback_fp64 = 1;
 }
 
 int amrto_pcg(amrto_ctx* ctx, const double* b, double* u, const amrto_solve_opts* opts_in,
@@ -750,7 +751,7 @@ int amrto_pcg(amrto_ctx* ctx, const double* b, double* u, const amrto_solve_opts
   } coarse_guard{ctx, ctx->coarse_k};
   if (!o.use_coarse) ctx->coarse_k = 0;
   const auto t0 = std::chrono::steady_clock::now();
-  int iters = 0, outer = 0, status;
+  int iters = 0, outer = 0, status, fell_back = 0;
   double rel = 0.0;
   if (o.inner_prec == AMRTO_FP64) {
     status = cg_fp64(ctx, b, u, o.rtol, o.max_it, o.check_every, &iters, &outer, &rel);
@@ -758,6 +759,17 @@ int amrto_pcg(amrto_ctx* ctx, const double* b, double* u, const amrto_solve_opts
   } else {
     status = cg_mixed(ctx, b, u, o.inner_prec, o.rtol, o.max_it, o.check_every, o.inner_rtol, &iters, &outer, &rel);
     if (status < 0 && status != AMRTO_EBREAKDOWN) return status;
+    if (status != AMRTO_OK && o.fallback_fp64 && iters < o.max_it) {
+      // the plain FP64 solve takes over (and judges), from the mixed iterate
+      if (!(rel == rel) || rel > 1e300)
+        hipLaunchKernelGGL(k_fill<double>, dim3((int)((3L * ctx->n_nodes + 255) / 256)), dim3(256), 0, ctx->stream, u,
+                           3L * ctx->n_nodes);
+      int it2 = 0, restarts = 0;
+      status = cg_fp64(ctx, b, u, o.rtol, o.max_it - iters, o.check_every, &it2, &restarts, &rel);
+      if (status < 0 && status != AMRTO_EBREAKDOWN) return status;
+      iters += it2;
+      fell_back = 1;
+    }
   }
   int rc = launch_recover(ctx, u, u);
   if (rc) return rc;
@@ -768,6 +780,7 @@ int amrto_pcg(amrto_ctx* ctx, const double* b, double* u, const amrto_solve_opts
     stats->outer = outer;
     stats->rel_res = rel;
     stats->ms = ms;
+    stats->fell_back = fell_back;
   }
   if (status == AMRTO_EBREAKDOWN) return ctx->fail(AMRTO_EBREAKDOWN, "amrto_pcg: breakdown (p^T A p <= 0 or non-finite)");
   if (status == AMRTO_NOT_CONVERGED)

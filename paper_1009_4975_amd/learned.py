@@ -25,6 +25,7 @@ from __future__ import annotations
 
 import time
 
+import numpy as np
 import torch
 
 from . import binding
@@ -61,6 +62,7 @@ class LearnedWarmStart:
         self.coarse = coarse
         self._uref = None
         self.trained = False
+        self.adam_t = 0  # Adam steps taken (bias correction continues across train calls)
         self.loss_history = []
         self.last = {}
         self._scale = None
@@ -99,11 +101,12 @@ class LearnedWarmStart:
         epochs = self.epochs if epochs is None else epochs
         t0 = time.perf_counter()
         X, Y, out, dout = self.X[:n], self.Y[:n], self.out[:n], self.dout[:n]
-        for t in range(1, epochs + 1):
+        for _ in range(epochs):
             self.net.forward(X, out)
             loss = self.net.mse(out, Y, dout)
             self.net.backward(dout)
-            self.net.adam(self.lr, t)
+            self.adam_t += 1
+            self.net.adam(self.lr, self.adam_t)
             self.loss_history.append(loss)
         torch.cuda.synchronize(self.dev)
         self.trained = True
@@ -115,6 +118,27 @@ class LearnedWarmStart:
         n = self.n_pairs
         zero = torch.zeros_like(self.Y[:n])
         return self.net.mse(zero, self.Y[:n], self.dout[:n])
+
+    # ------------------------------------------------------------------ checkpoint
+    def state_dict(self):
+        n = self.n_pairs
+        m, v = self.net.get_adam()
+        return {"params": self.net.get_params(), "adam_m": m, "adam_v": v, "adam_t": np.int64(self.adam_t),
+                "n_pairs": np.int64(n), "X": self.X[:n].cpu().numpy(), "Y": self.Y[:n].cpu().numpy(),
+                "trained": np.int8(self.trained), "loss_history": np.asarray(self.loss_history, np.float64)}
+
+    def load_state_dict(self, st):
+        n = int(st["n_pairs"])
+        if n > self.max_pairs or tuple(st["X"].shape[1:]) != tuple(self.X.shape[1:]):
+            raise ValueError("checkpoint is for another grid or pair capacity")
+        self.net.set_params(st["params"])
+        self.net.set_adam(st["adam_m"], st["adam_v"])
+        self.adam_t = int(st["adam_t"])
+        self.n_pairs = n
+        self.X[:n].copy_(torch.from_numpy(np.asarray(st["X"], np.float32)))
+        self.Y[:n].copy_(torch.from_numpy(np.asarray(st["Y"], np.float32)))
+        self.trained = bool(st["trained"])
+        self.loss_history = [float(x) for x in st["loss_history"]]
 
     # ------------------------------------------------------------------ use
     def predict(self, sim):

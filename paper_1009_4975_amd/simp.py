@@ -12,6 +12,7 @@ mesh changes.
 """
 from __future__ import annotations
 
+import json
 import time
 
 import numpy as np
@@ -24,7 +25,8 @@ from .binding import FILTER_SENSITIVITY, FP64
 class AdaptiveSIMP:
     def __init__(self, base, max_level, fixed, load, volfrac=0.25, rho_init=0.25, rmin=1.5, move=0.2, eta=0.5,
                  rho_min=1e-3, rho_solid=0.5, r_amr=1.5, adapt_every=5, rtol=1e-8, inner_prec=FP64,
-                 inner_rtol=1e-2, max_it=100000, device=0):
+                 inner_rtol=1e-2, max_it=100000, device=0, metrics_path=None):
+        self.base, self.max_level = tuple(int(b) for b in base), int(max_level)
         self.tree = binding.Octree(base, max_level)
         self.ctx = binding.Context(device)
         self.dev = torch.device("cuda", device)
@@ -35,6 +37,7 @@ class AdaptiveSIMP:
         self.it = 0
         self.compliance = None
         self.mesh_version = 0
+        self.metrics_path = metrics_path
         n = self.tree.lib.amrto_octree_n_leaves(self.tree.h)
         self._set_mesh(np.full(n, rho_init), None)
 
@@ -54,6 +57,15 @@ class AdaptiveSIMP:
         self.u = (torch.zeros_like(self.f) if u_host is None
                   else torch.tensor(u_host, dtype=torch.float64, device=d))
         self.mesh_version += 1
+        # per-mesh counts for the metrics log
+        lv = mesh.elem_level.astype(np.int64)
+        self.elem_volume = np.ldexp(1.0, 3 * (self.max_level - lv))  # leaf edge 2^(L - level) lattice units
+        hang = np.zeros(3 * mesh.n_nodes, bool)
+        hang[(3 * mesh.hang_node[:, None] + np.arange(3)).ravel()] = True
+        fixed = mesh.dof_fixed.astype(bool)
+        self.mesh_counts = dict(elems_per_level=np.bincount(lv, minlength=self.max_level + 1).tolist(),
+                                dofs_all=3 * mesh.n_nodes, dofs_hanging=int(hang.sum()),
+                                dofs_fixed=int((fixed & ~hang).sum()), dofs_free=int((~fixed & ~hang).sum()))
 
     def adapt(self):
         """One mesh adaptation (Sec. 4); rho and u are transferred."""
@@ -96,6 +108,95 @@ class AdaptiveSIMP:
         info = self.ctx.info()
         rec.update(n_elems=info["n_elems"], n_nodes=info["n_nodes"], dofs=3 * info["n_nodes"],
                    iters=st["iters"], outer=st["outer"], rel_res=st["rel_res"], solve_ms=st["ms"],
+                   fell_back=st["fell_back"],
                    warm_ms=1e3 * (t2 - t1), adapt_ms=1e3 * (t1 - t0), design_ms=1e3 * (t4 - t3),
                    step_ms=1e3 * (t4 - t0), compliance=c, change=change, lam=lam)
+        if self.metrics_path is not None:
+            self.log_metrics(rec)
         return rec
+
+    def log_metrics(self, rec):
+        """Append one JSON line: the step record, the volume fraction of the
+        new design, elements per level and the DOF counts of the mesh."""
+        rho = self.rho.cpu().numpy()
+        line = dict(rec, volume=float(rho @ self.elem_volume / self.elem_volume.sum()), **self.mesh_counts)
+        with open(self.metrics_path, "a") as fh:
+            fh.write(json.dumps(line) + "\n")
+
+    # ------------------------------------------------------------------ checkpoint
+    def state_dict(self):
+        """Host arrays that restart the run at the next iteration: the leaf set
+        (levels and anchors in Morton order), rho per leaf, u on the mesh nodes,
+        the iteration counter and the last compliance."""
+        levels, anchors = self.tree.leaves()
+        return {"base": np.array(self.base, np.int32), "max_level": np.int32(self.max_level),
+                "leaf_level": levels, "leaf_anchor": anchors, "rho": self.rho.cpu().numpy(),
+                "u": self.u.cpu().numpy(), "it": np.int64(self.it),
+                "compliance": np.float64(np.nan if self.compliance is None else self.compliance)}
+
+    def load_state_dict(self, st):
+        """Rebuild the tree from the saved leaf set (refining every leaf that
+        is a strict ancestor of a saved leaf, level by level), then the mesh,
+        rho and u.  The leaf set was 2:1 balanced when saved, so no closure is
+        needed, and the same leaves give the same node numbering."""
+        if tuple(int(b) for b in st["base"]) != self.base or int(st["max_level"]) != self.max_level:
+            raise ValueError("checkpoint is for another base grid or level count")
+        lv_s = np.asarray(st["leaf_level"], np.int64)
+        self.tree = rebuild_tree(self.base, self.max_level, lv_s, st["leaf_anchor"])
+        rho, u = np.asarray(st["rho"], np.float64), np.asarray(st["u"], np.float64)
+        if len(rho) != len(lv_s):
+            raise ValueError("checkpoint rho does not match its leaf set")
+        self._set_mesh(rho, None)
+        if len(u) != self.f.numel():
+            raise ValueError("checkpoint u does not match the mesh of its leaf set")
+        self.u.copy_(torch.from_numpy(u))
+        self.it = int(st["it"])
+        c = float(st["compliance"])
+        self.compliance = None if np.isnan(c) else c
+
+
+def rebuild_tree(base, max_level, levels, anchors):
+    """Octree whose leaves are exactly (levels, anchors) (anchors in units of
+    the finest lattice): every leaf that is a strict ancestor of a wanted leaf
+    is refined, one level per pass."""
+    lv_s = np.asarray(levels, np.int64)
+    an_s = np.asarray(anchors, np.int64).reshape(-1, 3)
+    L = int(max_level)
+    ancestors = set()
+    for lev, a in zip(lv_s, an_s):
+        for l in range(int(lev)):
+            size = 1 << (L - l)
+            ancestors.add((l, *(int(x) for x in a // size * size)))
+    tree = binding.Octree(base, L)
+    for _ in range(L + 1):
+        lv, an = tree.leaves()
+        marks = np.array([(int(l), *(int(x) for x in a)) in ancestors for l, a in zip(lv, an)], np.uint8)
+        if not marks.any():
+            break
+        tree.refine(marks)
+    lv, an = tree.leaves()
+    if not (np.array_equal(lv, lv_s) and np.array_equal(an, an_s)):
+        raise ValueError("leaf set is not a tree of this base grid")
+    return tree
+
+
+def save_checkpoint(path, sim, learned=None):
+    """One .npz (plain arrays, no pickled objects) with the SIMP state and,
+    optionally, the learned warm start (weights, Adam moments, training pairs)."""
+    arrays = {"sim/" + k: v for k, v in sim.state_dict().items()}
+    if learned is not None:
+        arrays.update({"net/" + k: v for k, v in learned.state_dict().items()})
+    with open(path, "wb") as fh:
+        np.savez(fh, **arrays)
+
+
+def load_checkpoint(path, sim, learned=None):
+    """Restore what save_checkpoint wrote into objects built with the same
+    configuration."""
+    with np.load(path, allow_pickle=False) as z:
+        sim.load_state_dict({k[4:]: z[k] for k in z.files if k.startswith("sim/")})
+        if learned is not None:
+            net = {k[4:]: z[k] for k in z.files if k.startswith("net/")}
+            if not net:
+                raise ValueError("checkpoint holds no learned state")
+            learned.load_state_dict(net)

@@ -63,6 +63,24 @@ def test_nonfinite_rhs_is_breakdown(small, prec):
     assert st["rel_res"] <= 1e-8
 
 
+def test_stalled_mixed_solve_falls_back_to_fp64(small):
+    """inner_rtol 0.9: every reliable update cuts the true residual by about
+    0.9, which the stall rule counts as no progress, so the mixed solve stops
+    after three updates; plain FP64 PCG then finishes from its iterate."""
+    from paper_1009_4975_amd import binding
+    pair, rho, ctx, b = small
+    ref = torch.zeros_like(b)
+    st0 = ctx.pcg(b, ref, rtol=1e-10)
+    assert not st0["fell_back"]
+    u = torch.zeros_like(b)
+    st = ctx.pcg(b, u, rtol=1e-10, inner_prec=binding.FP32, inner_rtol=0.9)
+    assert st["status"] == "OK" and st["fell_back"] and st["rel_res"] <= 1e-10
+    assert torch.allclose(u, ref, rtol=0, atol=1e-8 * ref.abs().max().item())
+    st = ctx.pcg(b, torch.zeros_like(b), rtol=1e-10, inner_prec=binding.FP32, inner_rtol=0.9, fallback_fp64=False,
+                 allow_not_converged=True)
+    assert st["status"] == "NOT_CONVERGED" and not st["fell_back"] and st["rel_res"] > 1e-10
+
+
 def test_calls_out_of_order(small):
     from paper_1009_4975_amd import binding
     pair, rho, _, b = small
