@@ -327,11 +327,11 @@ int amrto_octree_balance(amrto_octree* t);
 /* One adaptation of Sec. 4 with rho per current leaf: marking (solid if
  * rho >= rho_s; refine if solid or a solid centre lies within r_amr),
  * sweep 1 (whole families only), refinement plus closure, sweep 2 (no
- * level-two incompatibility from a derefinement), derefinement.  rho_new
- * (caller buffer of at least n_new leaves; query the count with
- * amrto_octree_adapt_count first) receives transferred densities: children
- * inherit, parents average.  src_first/src_count (per new leaf) index the old
- * leaves a new leaf came from (for displacement transfer). */
+ * level-two incompatibility from a derefinement), derefinement.  *n_new
+ * receives the new leaf count; amrto_octree_adapt_result then fills rho_new
+ * (caller buffer of n_new values) with transferred densities: children
+ * inherit, parents average.  src_first and src_count are not filled (pass
+ * NULL): displacements move through amrto_octree_transfer_nodal. */
 int amrto_octree_adapt(amrto_octree* t, const double* rho, double rho_s, double r_amr,
                        int32_t* n_new);
 int amrto_octree_adapt_result(const amrto_octree* t, double* rho_new, int32_t* src_first,
