@@ -6,12 +6,12 @@
 //
 // Two data paths, both writing every output row exactly once (deterministic,
 // no atomics in global memory):
-//  * uniform brick: implicit connectivity.  A workgroup owns a UT x UT block
-//    of node columns over a range of node layers, computes the surrounding
-//    (UT+1)^2 element columns (one element per thread, or one 16-element MFMA
-//    tile per wave row) and marches upwards one element layer at a time.
-//    Node layers rotate through four LDS buffers and are fetched three layers
-//    ahead into registers; one barrier per layer.
+//  * uniform brick: implicit connectivity, workgroups march upwards through
+//    a range of node layers of a block of node columns.  FP64 and FP32: one
+//    thread per node column, output rows summed in registers (z), across
+//    lanes (x) and through LDS (y), no atomics (k_apply_brick).  BF16: one
+//    16-element MFMA tile per wave row, rows accumulated in LDS
+//    (k_apply_uniform).
 //  * octree: node-owner chunks (chunks.hip).  A chunk stages its node table
 //    (vertices plus masters of hanging vertices) in LDS, interpolates hanging
 //    values x_h = P x_m, runs its run of elements plus the halo elements around
@@ -75,7 +75,8 @@ __global__ __launch_bounds__(256, Occ<PREC>::blocks) void k_apply_uniform(UArgs 
     return;
   }
   const int tid = threadIdx.x;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int ntp = (a.n_tiles + 7) & ~7;
+  const int tile = (int)blockIdx.x < ntp ? xcd_remap(blockIdx.x, ntp) : a.n_tiles;
   if (tile >= a.n_tiles) {
     if (FUSED && tid == 0) cg.part_out[cg.part_base + blockIdx.x] = 0.0;
     return;
@@ -301,6 +302,345 @@ __global__ __launch_bounds__(256, Occ<PREC>::blocks) void k_apply_uniform(UArgs 
     }
   }
   if (kend + 1 < z1 && kend + 1 >= z0) store(kend + 1);
+  if (FUSED) {
+    dot = block_sum(dot, sh);
+    if (tid == 0) cg.part_out[cg.part_base + blockIdx.x] = dot;
+  }
+}
+
+// ------------------------------------------------------------------ uniform brick, node-owner form
+// FP64 and FP32.  One thread per node column of a 16 x 16 tile; the thread's
+// element column is the one whose lower corner is its node.  Marching up one
+// element layer per step, every output row is summed without atomics:
+//  * z: an element's top-face outputs stay in the thread's registers and are
+//    added to the next element's bottom-face outputs (same node layer);
+//  * x: the contributions to the right-hand node move one lane up with DPP
+//    (rows of 16 lanes are rows of the tile);
+//  * y: the contributions to the node column above go through LDS.
+// The element contraction works in the Walsh-Hadamard mode basis and reuses
+// transforms along z: the forward transform of a node layer factors into an
+// x-y part (computed once per layer, carried to the next element) and a z
+// butterfly; the inverse is linear, so the top-face outputs of element k-1
+// are carried in mode form and added before one x-y inverse per layer.  The
+// block matrix is applied through its eight distinct entries (cube symmetry:
+// 33 multiply-adds instead of 72, the element coefficient folded into the
+// eight constants).  One barrier per layer.
+template <typename VT>
+struct BrickK {
+  VT c[8];  // a - b, b, d, e, f, g, h - i, i
+};
+
+constexpr int DPP_ROW_SHL1 = 0x101;  // lane l reads lane l + 1 of its row of 16
+constexpr int DPP_ROW_SHR1 = 0x111;  // lane l reads lane l - 1 of its row of 16
+
+// row shifts; lanes whose source falls outside their row read zero
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// 4-point Walsh-Hadamard transform over the x and y bits of a face:
+// (u00, u10, u01, u11) -> modes (0, x, y, xy); its own inverse up to 1/4.
+template <typename T>
+__device__ __forceinline__ void wht4(T (&u)[4]) {
+  const T a0 = u[0] + u[1], a1 = u[0] - u[1], b0 = u[2] + u[3], b1 = u[2] - u[3];
+  u[0] = a0 + b0;
+  u[1] = a1 + b1;
+  u[2] = a0 - b0;
+  u[3] = a1 - b1;
+}
+
+// o = s B w with the block pattern of the cube (w, o: modes [c][t], t bits
+// x, y, z); k[] already scaled by the element coefficient.  Translation modes
+// (t = 0) give zero rows and columns.
+template <typename T>
+__device__ __forceinline__ void brick_blocks(const T (&k)[8], const T (&w)[3][8], T (&o)[3][8]) {
+  const T AB = k[0], B = k[1], D = k[2], E = k[3], F = k[4], G = k[5], HI = k[6], I = k[7];
+  o[0][0] = 0;
+  o[1][0] = 0;
+  o[2][0] = 0;
+  {  // S = 0: modes (0,1) (1,2) (2,4)
+    const T v0 = w[0][1], v1 = w[1][2], v2 = w[2][4];
+    const T bt = B * (v0 + v1 + v2);
+    o[0][1] = AB * v0 + bt;
+    o[1][2] = AB * v1 + bt;
+    o[2][4] = AB * v2 + bt;
+  }
+  {  // S = 7: modes (0,6) (1,5) (2,3)
+    const T v0 = w[0][6], v1 = w[1][5], v2 = w[2][3];
+    const T it = I * (v0 + v1 + v2);
+    o[0][6] = HI * v0 + it;
+    o[1][5] = HI * v1 + it;
+    o[2][3] = HI * v2 + it;
+  }
+  {  // S = 1: (1,3) (2,5)
+    const T v1 = w[1][3], v2 = w[2][5];
+    o[1][3] = D * v1 + E * v2;
+    o[2][5] = E * v1 + D * v2;
+  }
+  {  // S = 2: (0,3) (2,6)
+    const T v0 = w[0][3], v2 = w[2][6];
+    o[0][3] = D * v0 + E * v2;
+    o[2][6] = E * v0 + D * v2;
+  }
+  {  // S = 4: (0,5) (1,6)
+    const T v0 = w[0][5], v1 = w[1][6];
+    o[0][5] = D * v0 + E * v1;
+    o[1][6] = E * v0 + D * v1;
+  }
+  {  // S = 3: (0,2) (1,1) | (2,7)
+    const T s = F * (w[0][2] + w[1][1]);
+    o[0][2] = s;
+    o[1][1] = s;
+    o[2][7] = G * w[2][7];
+  }
+  {  // S = 5: (0,4) (2,1) | (1,7)
+    const T s = F * (w[0][4] + w[2][1]);
+    o[0][4] = s;
+    o[2][1] = s;
+    o[1][7] = G * w[1][7];
+  }
+  {  // S = 6: (1,4) (2,2) | (0,7)
+    const T s = F * (w[1][4] + w[2][2]);
+    o[1][4] = s;
+    o[2][2] = s;
+    o[0][7] = G * w[0][7];
+  }
+}
+
+#ifndef AMRTO_BRICK_NS
+#define AMRTO_BRICK_NS 3
+#endif
+
+#ifndef AMRTO_BRICK_OCC64
+#define AMRTO_BRICK_OCC64 2
+#endif
+// workgroups per CU the brick kernel is compiled for
+template <typename VT>
+struct BrickOcc { static constexpr int blocks = 4; };
+template <>
+struct BrickOcc<double> { static constexpr int blocks = AMRTO_BRICK_OCC64; };
+
+template <typename VT, bool FUSED>
+__global__ __launch_bounds__(256, BrickOcc<VT>::blocks) void k_apply_brick(UArgs a, BrickK<VT> kc, CgArgs cg) {
+  __shared__ VT xs[4][3][BT * BT];  // staged node layers L & 3 (masked; fused: p)
+  __shared__ VT sb[2][3][BT * BT];  // partial sums for the node column above
+  __shared__ double sh[8];
+  double beta = 0.0;
+  if (FUSED) {
+    if (!cg_prologue(cg, beta, sh)) return;
+  } else if (a.stop && *a.stop != 0.0) {
+    return;
+  }
+  const int tid = threadIdx.x;
+  // the grid may exceed the tile count (it is shared with the BF16 kernel):
+  // spread the tiles over all eight XCDs, surplus workgroups at the end
+  const int ntp = (a.n_tiles + 7) & ~7;
+  const int tile = (int)blockIdx.x < ntp ? xcd_remap(blockIdx.x, ntp) : a.n_tiles;
+  if (tile >= a.n_tiles) {
+    if (FUSED && tid == 0) cg.part_out[cg.part_base + blockIdx.x] = 0.0;
+    return;
+  }
+  const VT* __restrict__ X = (const VT*)a.x;
+  const VT* __restrict__ PO = (const VT*)a.pold;
+  VT* __restrict__ Y = (VT*)a.y;
+  VT* __restrict__ PN = (VT*)a.pnew;
+  const VT* __restrict__ coef = (const VT*)a.coef;
+  const uint8_t* __restrict__ fix = a.fix;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  // z-chunks vary fastest: the chunks of one column of tiles share an XCD
+  const int nzc = (nz + 1 + a.zchunk - 1) / a.zchunk;
+  const int tz = tile % nzc;
+  const int txy = tile / nzc;
+  const int tx = txy % a.tiles_x, ty = txy / a.tiles_x;
+  const int i = tid & (BT - 1), j = tid >> 4;
+  const int gx = tx * BO - 1 + i, gy = ty * BO - 1 + j;
+  const bool nv = gx >= 0 && gx <= nx && gy >= 0 && gy <= ny;
+  const bool ev = i < BT - 1 && j < BT - 1 && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+  const bool owned = nv && i >= 1 && i <= BO && j >= 1 && j <= BO;
+  // per-lane offsets within a layer (32-bit: 3 n_nodes < 2^31 is checked at
+  // upload); per-layer offsets are uniform
+  const int nid = nv ? gx + (nx + 1) * gy : 0;
+  const int eid = ev ? gx + nx * gy : 0;
+  const long sxy = (long)(nx + 1) * (ny + 1);
+  const long nxy = (long)nx * ny;
+  const int z0 = tz * a.zchunk;
+  const int z1 = min(z0 + a.zchunk, nz + 1);
+  const VT vbeta = (VT)beta;
+  const bool first = FUSED && cg.it == 0;
+  const int up = min(tid + BT, BT * BT - 1);  // node column above (row 15: unused)
+  const int dn = max(tid - BT, 0);            // node column below (row 0: unused)
+
+  // raw loads of node layer L and the coefficient of element layer L.  The
+  // loads are unconditional (addresses clamped into the arrays) and the
+  // validity is applied when the layer is staged, so a load in flight is
+  // never merged with a default value (which would force a wait).
+  struct Slot {
+    VT x[3];
+    VT po[FUSED ? 3 : 1];
+    VT ce;
+    uint32_t f;
+  };
+  auto load = [&](Slot& R, int L) {
+    const long Lc = min(L, nz);
+    const VT* xl = X + 3 * sxy * Lc;
+    R.f = fix[sxy * Lc + nid];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) R.x[c] = xl[3 * nid + c];
+    if (FUSED) {
+      const VT* pl = PO + 3 * sxy * Lc;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) R.po[c] = pl[3 * nid + c];
+    }
+    R.ce = coef[nxy * min(L, nz - 1) + eid];
+  };
+  // what stays in registers of a staged layer: support bits and the
+  // coefficient of the element above it (the values themselves are in LDS)
+  struct Lay {
+    VT ce;
+    uint32_t f;
+  };
+  // Stage layer L: masked values (fused: p = z + beta p_old) into LDS.  Rows
+  // known at this point are written now: the search direction p (fused) and
+  // the identity rows of supported DOFs (plain apply).
+  auto stage = [&](const Slot& R, int L, Lay& out) {
+    const bool in = nv && L <= nz;
+    out.f = in ? R.f : 0u;
+    out.ce = (ev && L < nz) ? R.ce : (VT)0;
+    const bool mine = owned && L >= z0 && L < z1;
+    const long g = 3 * sxy * L + 3 * nid;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const bool fx = (out.f >> c) & 1;
+      VT v = in ? R.x[c] : (VT)0;
+      if (!FUSED && mine && fx) Y[g + c] = v;
+      if (FUSED && !first) v += vbeta * (in ? R.po[c] : (VT)0);
+      v = fx ? (VT)0 : v;
+      if (FUSED && mine) PN[g + c] = v;
+      xs[L & 3][c][tid] = v;
+    }
+  };
+  // x-y modes of a staged layer: own column, right (DPP), above (LDS), above-right
+  auto face_modes = [&](int L, VT (&m)[3][4]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const VT v00 = xs[L & 3][c][tid];
+      const VT v01 = xs[L & 3][c][up];
+      m[c][0] = v00;
+      m[c][1] = dpp_mov<DPP_ROW_SHL1>(v00);
+      m[c][2] = v01;
+      m[c][3] = dpp_mov<DPP_ROW_SHL1>(v01);
+      wht4(m[c]);
+    }
+  };
+
+  const int kbeg = max(z0 - 1, 0);
+  const int kend = z1 - 1;
+  // layer L lives in register set (L - kbeg) % NS while loading and staged;
+  // it is requested NS - 1 steps before it is staged
+  constexpr int NS = AMRTO_BRICK_NS;
+  Slot S0, S1, S2, S3;
+  Lay L0, L1, L2, L3;
+  VT fb[3][4], carry[3][4];
+  load(S0, kbeg);
+  load(S1, kbeg + 1);
+  stage(S0, kbeg, L0);
+  stage(S1, kbeg + 1, L1);
+  load(S2, kbeg + 2);
+  if (NS == 3) {
+    load(S0, kbeg + 3);
+  } else {
+    load(S3, kbeg + 3);
+    load(S0, kbeg + 4);
+  }
+  __syncthreads();
+  face_modes(kbeg, fb);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) carry[c][t] = 0;
+  double dot = 0.0;
+
+  // element layer k: contract with the staged layers k (lp) and k + 1, stage
+  // layer k + 2 from Rst into ln, request layer k + NS + 1 into Rld, finish
+  // node layer k
+  auto step = [&](int k, Slot& Rld, Slot& Rst, const Lay& lp, Lay& ln) {
+    VT ft[3][4];
+    face_modes(k + 1, ft);
+    VT w[3][8];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        w[c][t] = fb[c][t] + ft[c][t];
+        w[c][t + 4] = fb[c][t] - ft[c][t];
+        fb[c][t] = ft[c][t];
+      }
+    VT ks[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ks[q] = lp.ce * kc.c[q];
+    VT o[3][8];
+    brick_blocks<VT>(ks, w, o);
+    VT c00[3], c10[3], c01[3], c11[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      VT m[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        m[t] = o[c][t] + o[c][t + 4] + carry[c][t];
+        carry[c][t] = o[c][t] - o[c][t + 4];
+      }
+      wht4(m);
+      c00[c] = m[0];
+      c10[c] = m[1];
+      c01[c] = m[2];
+      c11[c] = m[3];
+    }
+    VT s0[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      s0[c] = c00[c] + dpp_mov<DPP_ROW_SHR1>(c10[c]);
+      sb[k & 1][c][tid] = c01[c] + dpp_mov<DPP_ROW_SHR1>(c11[c]);
+    }
+    if (k + 2 <= nz) stage(Rst, k + 2, ln);
+    load(Rld, k + 1 + NS);
+    __syncthreads();
+    if (owned && k >= z0) {
+      VT* yl = Y + 3 * sxy * k;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const VT tot = s0[c] + (j >= 1 ? sb[k & 1][c][dn] : (VT)0);
+        const bool fx = (lp.f >> c) & 1;
+        if (FUSED) {
+          const VT q = fx ? (VT)0 : tot;
+          yl[3 * nid + c] = q;
+          dot += (double)xs[k & 3][c][tid] * (double)q;
+        } else if (!fx) {
+          yl[3 * nid + c] = tot;
+        }
+      }
+    }
+  };
+  if (NS == 3) {
+    for (int k = kbeg; k <= kend; k += 3) {
+      step(k, S1, S2, L0, L2);
+      if (k + 1 <= kend) step(k + 1, S2, S0, L1, L0);
+      if (k + 2 <= kend) step(k + 2, S0, S1, L2, L1);
+    }
+  } else {
+    for (int k = kbeg; k <= kend; k += 4) {
+      step(k, S1, S2, L0, L2);
+      if (k + 1 <= kend) step(k + 1, S2, S3, L1, L3);
+      if (k + 2 <= kend) step(k + 2, S3, S0, L2, L0);
+      if (k + 3 <= kend) step(k + 3, S0, S1, L3, L1);
+    }
+  }
   if (FUSED) {
     dot = block_sum(dot, sh);
     if (tid == 0) cg.part_out[cg.part_base + blockIdx.x] = dot;
@@ -682,11 +1022,29 @@ void uniform_grid(const amrto_ctx* ctx, int& tiles_x, int& tiles_y, int& zchunk,
   grid = ((n_tiles + 7) / 8) * 8;
 }
 
+#ifndef AMRTO_BRICK_WANT
+#define AMRTO_BRICK_WANT 1024
+#endif
+
+void brick_grid(const amrto_ctx* ctx, int& tiles_x, int& tiles_y, int& zchunk, int& n_tiles) {
+  tiles_x = (ctx->nx + 1 + BO - 1) / BO;
+  tiles_y = (ctx->ny + 1 + BO - 1) / BO;
+  const int layers = ctx->nz + 1;
+  int nzc = std::max(1, AMRTO_BRICK_WANT / std::max(1, tiles_x * tiles_y));
+  zchunk = std::max(4, (layers + nzc - 1) / nzc);
+  nzc = (layers + zchunk - 1) / zchunk;
+  n_tiles = tiles_x * tiles_y * nzc;
+}
+
+// Both uniform kernels run on one grid (the larger of their tile counts,
+// rounded to a multiple of 8), so the partial sums of p.q always fill the
+// same slots whatever the precision; surplus workgroups write zeros.
 int apply_blocks(const amrto_ctx* ctx) {
   if (ctx->uniform) {
-    int tx, ty, zc, nt, grid;
+    int tx, ty, zc, nt, grid, nb;
     uniform_grid(ctx, tx, ty, zc, nt, grid);
-    return grid;
+    brick_grid(ctx, tx, ty, zc, nb);
+    return ((std::max(nt, nb) + 7) / 8) * 8;
   }
   return ((ctx->n_chunks + 7) / 8) * 8;
 }
@@ -695,11 +1053,21 @@ template <typename VT, int PREC, bool FUSED>
 static int launch_t(amrto_ctx* ctx, const UArgs& ua, const CgArgs& cg) {
   if (ctx->uniform) {
     int tx, ty, zc, nt, grid;
-    uniform_grid(ctx, tx, ty, zc, nt, grid);
     UArgs a = ua;
     a.nx = ctx->nx; a.ny = ctx->ny; a.nz = ctx->nz;
-    a.tiles_x = tx; a.tiles_y = ty; a.zchunk = zc; a.n_tiles = nt;
-    hipLaunchKernelGGL((k_apply_uniform<VT, PREC, FUSED>), dim3(grid), dim3(256), 0, ctx->stream, a, cg);
+    if constexpr (PREC == P_BF16) {
+      uniform_grid(ctx, tx, ty, zc, nt, grid);
+      grid = apply_blocks(ctx);
+      a.tiles_x = tx; a.tiles_y = ty; a.zchunk = zc; a.n_tiles = nt;
+      hipLaunchKernelGGL((k_apply_uniform<VT, PREC, FUSED>), dim3(grid), dim3(256), 0, ctx->stream, a, cg);
+    } else {
+      brick_grid(ctx, tx, ty, zc, nt);
+      grid = apply_blocks(ctx);
+      a.tiles_x = tx; a.tiles_y = ty; a.zchunk = zc; a.n_tiles = nt;
+      BrickK<VT> kc;
+      for (int q = 0; q < 8; ++q) kc.c[q] = (VT)ctx->bk[q];
+      hipLaunchKernelGGL((k_apply_brick<VT, FUSED>), dim3(grid), dim3(256), 0, ctx->stream, a, kc, cg);
+    }
   } else {
     hipLaunchKernelGGL((k_apply_chunks<VT, PREC, FUSED>), dim3(apply_blocks(ctx)), dim3(256), 0, ctx->stream, ua,
                        chunk_args(ctx), cg);

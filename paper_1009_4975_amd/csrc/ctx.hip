@@ -1,5 +1,6 @@
 // Context, material, mesh upload and the small host helpers of the amrto
 // library.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -132,6 +133,24 @@ static int upload_material(amrto_ctx* ctx) {
         kbd[9 * S + 3 * c + d] = v / 64.0;
         kbf[9 * S + 3 * c + d] = (float)(v / 64.0);
       }
+  // For a cube of an isotropic material the blocks have a fixed pattern
+  // (zero modes, equal entries) with eight distinct values:
+  //   B0 = [[a b b][b a b][b b a]]  B7 = [[h i i][i h i][i i h]]
+  //   B1 = [[0 0 0][0 d e][0 e d]]  B2 = [[d 0 e][0 0 0][e 0 d]]  B4 = [[d e 0][e d 0][0 0 0]]
+  //   B3 = [[f f 0][f f 0][0 0 g]]  B5 = [[f 0 f][0 g 0][f 0 f]]  B6 = [[g 0 0][0 f f][0 f f]]
+  {
+    const double a = kbd[0], b = kbd[1], d = kbd[9 + 4], e = kbd[9 + 5], f = kbd[27], g = kbd[27 + 8],
+                 h = kbd[63], i = kbd[64];
+    const double pat[8][9] = {{a, b, b, b, a, b, b, b, a}, {0, 0, 0, 0, d, e, 0, e, d}, {d, 0, e, 0, 0, 0, e, 0, d},
+                              {f, f, 0, f, f, 0, 0, 0, g}, {d, e, 0, e, d, 0, 0, 0, 0}, {f, 0, f, 0, g, 0, f, 0, f},
+                              {g, 0, 0, 0, f, f, 0, f, f}, {h, i, i, i, h, i, i, i, h}};
+    double big = 0.0, dev = 0.0;
+    for (int k = 0; k < 72; ++k) big = std::max(big, std::fabs(kbd[k]));
+    for (int k = 0; k < 72; ++k) dev = std::max(dev, std::fabs(kbd[k] - pat[k / 9][k % 9]));
+    if (!(dev <= 1e-12 * big)) return ctx->fail(AMRTO_EINVAL, "element matrix lost its cube symmetry (material constants?)");
+    const double bk[8] = {a - b, b, d, e, f, g, h - i, i};
+    std::memcpy(ctx->bk, bk, sizeof bk);
+  }
   AMRTO_HIP(hipMemcpyAsync(ctx->d_Kb, kbd, sizeof(kbd), hipMemcpyHostToDevice, ctx->stream));
   AMRTO_HIP(hipMemcpyAsync(ctx->d_Kbf, kbf, sizeof(kbf), hipMemcpyHostToDevice, ctx->stream));
   AMRTO_HIP(hipStreamSynchronize(ctx->stream));

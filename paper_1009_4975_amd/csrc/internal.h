@@ -25,6 +25,10 @@ namespace amrto {
 constexpr int UT = 15;
 constexpr int UE = UT + 1;  // element columns per tile edge
 constexpr int UN = UT + 2;  // node columns per tile edge (with halo)
+// Brick kernel tile: 16 x 16 node columns per workgroup (one per thread),
+// 15 x 15 element columns, 14 x 14 owned node columns.
+constexpr int BT = 16;
+constexpr int BO = BT - 2;
 
 // Octree operator chunk: a run of at most CH_MAX consecutive elements plus
 // the halo elements around its owned nodes (at most ENT_MAX in all); its node
@@ -80,6 +84,9 @@ struct amrto_ctx {
   hipStream_t stream = nullptr;
   double E0 = 1.0, Emin = 1e-9, nu = 0.3, p = 3.0;
   double K0[576];
+  // the eight distinct entries of the mirror-symmetry blocks (brick kernel):
+  // a - b, b, d, e, f, g, h - i, i (see k_apply_brick)
+  double bk[8];
   std::string err;
 
   // mesh

@@ -35,7 +35,7 @@ def make_ctx(pair, rho_oracle):
     return ctx
 
 
-UNIFORM_DIMS = [(4, 3, 2), (20, 9, 7), (31, 16, 13), (24, 12, 12)]
+UNIFORM_DIMS = [(1, 1, 1), (4, 3, 2), (20, 9, 7), (31, 16, 13), (13, 27, 5), (24, 12, 12)]
 
 
 @pytest.fixture(scope="module", params=["uniform", "octree"])
