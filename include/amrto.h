@@ -112,7 +112,7 @@ typedef struct {
  * hanging-node tables and the solver workspace.  Replaces any earlier mesh
  * (densities must be set again).  Errors: EINVAL (inconsistent sizes, node
  * indices out of range, a hanging master that is hanging, a chunk whose node
- * table cannot fit), ENOMEM, EHIP. */
+ * table cannot fit, 3 n_nodes or 8 n_elems not below 2^31), ENOMEM, EHIP. */
 int amrto_upload_mesh(amrto_ctx* ctx, const amrto_mesh* mesh);
 
 /* Sizes of the uploaded mesh. */

@@ -414,9 +414,14 @@ __device__ __forceinline__ void brick_blocks(const T (&k)[8], const T (&w)[3][8]
   }
 }
 
-#ifndef AMRTO_BRICK_NS
-#define AMRTO_BRICK_NS 3
+#ifndef AMRTO_BRICK_Z
+#define AMRTO_BRICK_Z 10
 #endif
+constexpr int BZ = AMRTO_BRICK_Z;  // node layers per workgroup
+#ifndef AMRTO_BRICK_PD
+#define AMRTO_BRICK_PD 2
+#endif
+constexpr int BPD = AMRTO_BRICK_PD;  // prefetch distance in layers
 
 #ifndef AMRTO_BRICK_OCC64
 #define AMRTO_BRICK_OCC64 2
@@ -500,9 +505,10 @@ __global__ __launch_bounds__(256, BrickOcc<VT>::blocks) void k_apply_brick(UArgs
     }
     R.ce = coef[nxy * min(L, nz - 1) + eid];
   };
-  // what stays in registers of a staged layer: support bits and the
-  // coefficient of the element above it (the values themselves are in LDS)
+  // a staged layer in registers: masked values (fused: p), support bits and
+  // the coefficient of the element above it
   struct Lay {
+    VT v[3];
     VT ce;
     uint32_t f;
   };
@@ -523,14 +529,15 @@ __global__ __launch_bounds__(256, BrickOcc<VT>::blocks) void k_apply_brick(UArgs
       if (FUSED && !first) v += vbeta * (in ? R.po[c] : (VT)0);
       v = fx ? (VT)0 : v;
       if (FUSED && mine) PN[g + c] = v;
+      out.v[c] = v;
       xs[L & 3][c][tid] = v;
     }
   };
   // x-y modes of a staged layer: own column, right (DPP), above (LDS), above-right
-  auto face_modes = [&](int L, VT (&m)[3][4]) {
+  auto face_modes = [&](const Lay& l, int L, VT (&m)[3][4]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const VT v00 = xs[L & 3][c][tid];
+      const VT v00 = l.v[c];
       const VT v01 = xs[L & 3][c][up];
       m[c][0] = v00;
       m[c][1] = dpp_mov<DPP_ROW_SHL1>(v00);
@@ -542,37 +549,34 @@ __global__ __launch_bounds__(256, BrickOcc<VT>::blocks) void k_apply_brick(UArgs
 
   const int kbeg = max(z0 - 1, 0);
   const int kend = z1 - 1;
-  // layer L lives in register set (L - kbeg) % NS while loading and staged;
-  // it is requested NS - 1 steps before it is staged
-  constexpr int NS = AMRTO_BRICK_NS;
-  Slot S0, S1, S2, S3;
-  Lay L0, L1, L2, L3;
+  // layer L is loaded into register set (L - kbeg) % NSL, BPD steps before
+  // it is staged (into staged set (L - kbeg) % 3).  The march is unrolled
+  // completely (at most BZ + 1 steps), so no value in flight crosses a loop
+  // back-edge (where register copies would wait for it).
+  constexpr int NSL = BPD + 1;
+  Slot S[NSL];
+  Lay Ls[3];
   VT fb[3][4], carry[3][4];
-  load(S0, kbeg);
-  load(S1, kbeg + 1);
-  stage(S0, kbeg, L0);
-  stage(S1, kbeg + 1, L1);
-  load(S2, kbeg + 2);
-  if (NS == 3) {
-    load(S0, kbeg + 3);
-  } else {
-    load(S3, kbeg + 3);
-    load(S0, kbeg + 4);
-  }
+  load(S[0], kbeg);
+  load(S[1 % NSL], kbeg + 1);
+  stage(S[0], kbeg, Ls[0]);
+  stage(S[1 % NSL], kbeg + 1, Ls[1]);
+#pragma unroll
+  for (int q = 2; q < 2 + BPD; ++q) load(S[q % NSL], kbeg + q);
   __syncthreads();
-  face_modes(kbeg, fb);
+  face_modes(Ls[0], kbeg, fb);
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int t = 0; t < 4; ++t) carry[c][t] = 0;
   double dot = 0.0;
 
-  // element layer k: contract with the staged layers k (lp) and k + 1, stage
-  // layer k + 2 from Rst into ln, request layer k + NS + 1 into Rld, finish
+  // element layer k: contract with the staged layers k (lp) and k + 1 (lc), stage
+  // layer k + 2 from Rst into ln, request layer k + 2 + BPD into Rld, finish
   // node layer k
-  auto step = [&](int k, Slot& Rld, Slot& Rst, const Lay& lp, Lay& ln) {
+  auto step = [&](int k, Slot& Rld, Slot& Rst, const Lay& lp, const Lay& lc, Lay& ln) {
     VT ft[3][4];
-    face_modes(k + 1, ft);
+    face_modes(lc, k + 1, ft);
     VT w[3][8];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -609,7 +613,7 @@ __global__ __launch_bounds__(256, BrickOcc<VT>::blocks) void k_apply_brick(UArgs
       sb[k & 1][c][tid] = c01[c] + dpp_mov<DPP_ROW_SHR1>(c11[c]);
     }
     if (k + 2 <= nz) stage(Rst, k + 2, ln);
-    load(Rld, k + 1 + NS);
+    load(Rld, k + 2 + BPD);
     __syncthreads();
     if (owned && k >= z0) {
       VT* yl = Y + 3 * sxy * k;
@@ -620,26 +624,18 @@ __global__ __launch_bounds__(256, BrickOcc<VT>::blocks) void k_apply_brick(UArgs
         if (FUSED) {
           const VT q = fx ? (VT)0 : tot;
           yl[3 * nid + c] = q;
-          dot += (double)xs[k & 3][c][tid] * (double)q;
+          dot += (double)lp.v[c] * (double)q;
         } else if (!fx) {
           yl[3 * nid + c] = tot;
         }
       }
     }
   };
-  if (NS == 3) {
-    for (int k = kbeg; k <= kend; k += 3) {
-      step(k, S1, S2, L0, L2);
-      if (k + 1 <= kend) step(k + 1, S2, S0, L1, L0);
-      if (k + 2 <= kend) step(k + 2, S0, S1, L2, L1);
-    }
-  } else {
-    for (int k = kbeg; k <= kend; k += 4) {
-      step(k, S1, S2, L0, L2);
-      if (k + 1 <= kend) step(k + 1, S2, S3, L1, L3);
-      if (k + 2 <= kend) step(k + 2, S3, S0, L2, L0);
-      if (k + 3 <= kend) step(k + 3, S0, S1, L3, L1);
-    }
+#pragma unroll
+  for (int st = 0; st <= BZ; ++st) {
+    const int k = kbeg + st;
+    if (k > kend) break;
+    step(k, S[(st + 2 + BPD) % NSL], S[(st + 2) % NSL], Ls[st % 3], Ls[(st + 1) % 3], Ls[(st + 2) % 3]);
   }
   if (FUSED) {
     dot = block_sum(dot, sh);
@@ -1022,18 +1018,11 @@ void uniform_grid(const amrto_ctx* ctx, int& tiles_x, int& tiles_y, int& zchunk,
   grid = ((n_tiles + 7) / 8) * 8;
 }
 
-#ifndef AMRTO_BRICK_WANT
-#define AMRTO_BRICK_WANT 1024
-#endif
-
 void brick_grid(const amrto_ctx* ctx, int& tiles_x, int& tiles_y, int& zchunk, int& n_tiles) {
   tiles_x = (ctx->nx + 1 + BO - 1) / BO;
   tiles_y = (ctx->ny + 1 + BO - 1) / BO;
-  const int layers = ctx->nz + 1;
-  int nzc = std::max(1, AMRTO_BRICK_WANT / std::max(1, tiles_x * tiles_y));
-  zchunk = std::max(4, (layers + nzc - 1) / nzc);
-  nzc = (layers + zchunk - 1) / zchunk;
-  n_tiles = tiles_x * tiles_y * nzc;
+  zchunk = BZ;  // the kernel's march is unrolled for exactly this many layers
+  n_tiles = tiles_x * tiles_y * ((ctx->nz + 1 + BZ - 1) / BZ);
 }
 
 // Both uniform kernels run on one grid (the larger of their tile counts,

@@ -224,6 +224,9 @@ int amrto_upload_mesh(amrto_ctx* ctx, const amrto_mesh* m) {
   if (!ctx) return AMRTO_EINVAL;
   if (!m || m->n_nodes <= 0 || m->n_elems <= 0 || !m->dof_fixed)
     return ctx->fail(AMRTO_EINVAL, "amrto_upload_mesh: empty mesh or missing dof_fixed");
+  // kernels index DOFs with 32-bit per-lane offsets
+  if (3L * m->n_nodes > 2147483647L || 8L * m->n_elems > 2147483647L)
+    return ctx->fail(AMRTO_EINVAL, "amrto_upload_mesh: mesh too large (3 n_nodes and 8 n_elems must be < 2^31)");
   AMRTO_HIP(hipSetDevice(ctx->device));
   AMRTO_HIP(hipStreamSynchronize(ctx->stream));
   free_mesh(ctx);
