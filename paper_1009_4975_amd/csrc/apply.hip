@@ -11,7 +11,7 @@
 //    thread per node column, output rows summed in registers (z), across
 //    lanes (x) and through LDS (y), no atomics (k_apply_brick).  BF16: one
 //    16-element MFMA tile per wave row, rows accumulated in LDS
-//    (k_apply_uniform).
+//    (k_apply_uniform_bf16).
 //  * octree: node-owner chunks (chunks.hip).  A chunk stages its node table
 //    (vertices plus masters of hanging vertices) in LDS, interpolates hanging
 //    values x_h = P x_m, runs its run of elements plus the halo elements around
@@ -52,19 +52,15 @@ struct UArgs {
   int coarse_R = 0;
 };
 
-// workgroups per CU the uniform kernels are compiled for (register budget:
-// 4 -> 128 VGPRs, 2 -> 256)
-template <int PREC>
-struct Occ { static constexpr int blocks = 4; };
-template <>
-struct Occ<0> { static constexpr int blocks = 2; };
-
-// ------------------------------------------------------------------ uniform brick
-// Output rows accumulate in FP64 LDS for every precision: ds_add_f64 runs at
-// full rate on gfx950 while FP32 LDS atomics were measured to stall the
-// waves on LDS issue (two orders of magnitude more LDS wait cycles).
-template <typename VT, int PREC, bool FUSED>
-__global__ __launch_bounds__(256, Occ<PREC>::blocks) void k_apply_uniform(UArgs a, CgArgs cg) {
+// ------------------------------------------------------------------ uniform brick, BF16 on the matrix cores
+// One 16-element MFMA tile per wave row; a workgroup covers UE x UE element
+// columns around UT x UT owned node columns and marches upwards.  Node layers
+// rotate through four LDS buffers and are fetched three layers ahead; output
+// rows accumulate in FP64 LDS (ds_add_f64 runs at full rate on gfx950, FP32
+// LDS atomics were measured to stall the waves on LDS issue).
+template <bool FUSED>
+__global__ __launch_bounds__(256, 4) void k_apply_uniform_bf16(UArgs a, CgArgs cg) {
+  using VT = float;
   __shared__ VT xs[NBUF][UN * UN * 3];
   __shared__ double ys[3][UT * UT * 3];
   __shared__ double sh[8];
@@ -116,15 +112,9 @@ __global__ __launch_bounds__(256, Occ<PREC>::blocks) void k_apply_uniform(UArgs 
   // support bits of the last four staged layers, 4 bits per layer (one per
   // slot), so the store phase needs no dependent global read
   uint32_t fring = 0;
-  // A layer in flight: raw loads only.  Masking and the beta update happen
-  // at stage time two layers later, so nothing waits on these loads early.
-  // The BF16 body sits at the register limit of its occupancy: there the
-  // masking stays at load time (fewer live registers), which measured faster.
-  constexpr bool DEFER = PREC != P_BF16;
+  // a layer in flight, masked (and beta-updated) at load time
   struct Slot {
     VT x[LSLOTS];
-    VT po[(FUSED && DEFER) ? LSLOTS : 1];
-    uint8_t f[DEFER ? LSLOTS : 1];
     uint32_t fb;
   };
   auto load = [&](Slot& R, int k) {
@@ -132,41 +122,25 @@ __global__ __launch_bounds__(256, Occ<PREC>::blocks) void k_apply_uniform(UArgs 
 #pragma unroll
     for (int s = 0; s < LSLOTS; ++s) {
       R.x[s] = 0;
-      if (DEFER) R.f[s] = 0;
-      if (FUSED && DEFER) R.po[s] = 0;
       if ((inside >> s) & 1) {
         const long g = gxy[s] + sxy3 * k;
         const uint8_t f = fix[g / 3];
         VT xv = X[g];
-        if (DEFER) {
-          R.f[s] = f;
-          R.x[s] = xv;
-          if (FUSED && !first) R.po[s] = PO[g];
-        } else {
-          if (FUSED && !first) xv += vbeta * PO[g];
-          const bool fx = (f >> ((tid + 256 * s) % 3)) & 1;
-          R.fb |= (uint32_t)fx << s;
-          R.x[s] = fx ? (VT)0 : xv;
-        }
+        if (FUSED && !first) xv += vbeta * PO[g];
+        const bool fx = (f >> ((tid + 256 * s) % 3)) & 1;
+        R.fb |= (uint32_t)fx << s;
+        R.x[s] = fx ? (VT)0 : xv;
       }
     }
   };
   auto stage = [&](const Slot& R, int k) {
-    uint32_t fb = DEFER ? 0u : R.fb;
 #pragma unroll
     for (int s = 0; s < LSLOTS; ++s) {
       const int idx = tid + 256 * s;
-      VT v = R.x[s];
-      if (DEFER) {
-        if (FUSED && !first) v += vbeta * R.po[s];
-        const bool fx = (R.f[s] >> (idx % 3)) & 1;
-        fb |= (uint32_t)fx << s;
-        v = fx ? (VT)0 : v;
-      }
-      if (idx < UN * UN * 3) xs[k % NBUF][idx] = v;
+      if (idx < UN * UN * 3) xs[k % NBUF][idx] = R.x[s];
     }
     const int sh4 = 4 * (k % NBUF);
-    fring = (fring & ~(0xfu << sh4)) | (fb << sh4);
+    fring = (fring & ~(0xfu << sh4)) | (R.fb << sh4);
   };
   double dot = 0.0;
   auto store = [&](int k) {
@@ -192,29 +166,17 @@ __global__ __launch_bounds__(256, Occ<PREC>::blocks) void k_apply_uniform(UArgs 
   for (int idx = tid; idx < UT * UT * 3; idx += 256) { ys[0][idx] = 0; ys[1][idx] = 0; ys[2][idx] = 0; }
   const int kbeg = max(z0 - 1, 0);
   const int kend = min(z1 - 1, nz - 1);
-  Slot Ra, Rb;  // ping-pong: one set is staged two layers after it was requested
+  Slot Ra, Rb;
   load(Ra, kbeg);
   stage(Ra, kbeg);
   load(Ra, kbeg + 1);
   stage(Ra, kbeg + 1);
   if (kbeg + 2 <= nz) load(Ra, kbeg + 2);
 
-  // element-side state
-  const int i = tid % UE, j = tid / UE;
   const int lane = tid & 63, wave = tid >> 6;
   const int n16 = lane & 15, q4 = lane >> 4;
   bf16x8 ka[2][2];
-  if (PREC == P_BF16) load_k0_bf16((const uint16_t*)a.kb, ka);
-  // FP64 block constants (144 SGPRs) do not fit the scalar file: keep them
-  // in LDS and read them as broadcasts instead of pinning 144 VGPRs.
-  __shared__ VT sB[PREC == P_F64 ? 72 : 1];
-  if (PREC == P_F64 && tid < 72) sB[tid] = ((const VT*)a.kb)[tid];
-  const VT* Bs = PREC == P_F64 ? (const VT*)sB : (const VT*)a.kb;
-  const int exv = ox - 1 + i, eyv = oy - 1 + j;
-  const bool ev_valu = exv >= 0 && exv < nx && eyv >= 0 && eyv < ny;
-  const long eoff = ev_valu ? exv + (long)nx * eyv : 0;
-  const long nxy = (long)nx * ny;
-  VT ce_next = (PREC != P_BF16 && ev_valu) ? coef[eoff + nxy * kbeg] : (VT)0;
+  load_k0_bf16((const uint16_t*)a.kb, ka);
   __syncthreads();
 
   // one layer: request layer k + 3 into Rfly, contract elements of layer k,
@@ -223,83 +185,46 @@ __global__ __launch_bounds__(256, Occ<PREC>::blocks) void k_apply_uniform(UArgs 
     if (k + 3 <= nz) load(Rfly, k + 3);
     const VT* bot = xs[k % NBUF];
     const VT* top = xs[(k + 1) % NBUF];
-    if (PREC != P_BF16) {
-      const VT ce = ce_next;
-      if (ev_valu && k + 1 <= kend) ce_next = coef[eoff + nxy * (k + 1)];
-      if (ev_valu) {
-        VT u[24], out[24];
-#pragma unroll
-        for (int aa = 0; aa < 8; ++aa) {
-          const VT* src = (aa >> 2) ? top : bot;
-          const int l = ((j + ((aa >> 1) & 1)) * UN + i + (aa & 1)) * 3;
-          u[3 * aa + 0] = src[l + 0];
-          u[3 * aa + 1] = src[l + 1];
-          u[3 * aa + 2] = src[l + 2];
-        }
-        contract_sym<VT>(Bs, u, out, ce);
-#pragma unroll
-        for (int aa = 0; aa < 8; ++aa) {
-          const int li = i + (aa & 1) - 1, lj = j + ((aa >> 1) & 1) - 1;
-          const int layer = k + (aa >> 2);
-          if (li >= 0 && li < UT && lj >= 0 && lj < UT && layer >= z0 && layer < z1) {
-            double* dst = &ys[layer % 3][(lj * UT + li) * 3];
-            atomicAdd(dst + 0, (double)out[3 * aa + 0]);
-            atomicAdd(dst + 1, (double)out[3 * aa + 1]);
-            atomicAdd(dst + 2, (double)out[3 * aa + 2]);
-          }
-        }
-      }
-    } else {
 #pragma unroll 1
-      for (int row = 0; row < 4; ++row) {
-        const int jj = 4 * wave + row, ii = n16;
-        const int ex = ox - 1 + ii, ey = oy - 1 + jj;
-        const bool ev = ex >= 0 && ex < nx && ey >= 0 && ey < ny;
-        const float ce = ev ? (float)coef[ex + (long)nx * (ey + (long)ny * k)] : 0.f;
-        float u[24];
+    for (int row = 0; row < 4; ++row) {
+      const int jj = 4 * wave + row, ii = n16;
+      const int ex = ox - 1 + ii, ey = oy - 1 + jj;
+      const bool ev = ex >= 0 && ex < nx && ey >= 0 && ey < ny;
+      const float ce = ev ? (float)coef[ex + (long)nx * (ey + (long)ny * k)] : 0.f;
+      float u[24];
 #pragma unroll
-        for (int aa = 0; aa < 8; ++aa) {
-          const VT* src = (aa >> 2) ? top : bot;
-          const int l = ((jj + ((aa >> 1) & 1)) * UN + ii + (aa & 1)) * 3;
-          u[3 * aa + 0] = (float)src[l + 0];
-          u[3 * aa + 1] = (float)src[l + 1];
-          u[3 * aa + 2] = (float)src[l + 2];
-        }
-        f32x4 d0, d1;
-        mfma_tile_bf16(ka, u, q4, d0, d1);
-        if (ev) {
+      for (int aa = 0; aa < 8; ++aa) {
+        const VT* src = (aa >> 2) ? top : bot;
+        const int l = ((jj + ((aa >> 1) & 1)) * UN + ii + (aa & 1)) * 3;
+        u[3 * aa + 0] = src[l + 0];
+        u[3 * aa + 1] = src[l + 1];
+        u[3 * aa + 2] = src[l + 2];
+      }
+      f32x4 d0, d1;
+      mfma_tile_bf16(ka, u, q4, d0, d1);
+      if (ev) {
 #pragma unroll
-          for (int t = 0; t < 2; ++t)
+        for (int t = 0; t < 2; ++t)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int R = 16 * t + 4 * q4 + r;
-              if (R < 24) {
-                const int aa = R / 3, c = R % 3;
-                const int li = ii + (aa & 1) - 1, lj = jj + ((aa >> 1) & 1) - 1;
-                const int layer = k + (aa >> 2);
-                if (li >= 0 && li < UT && lj >= 0 && lj < UT && layer >= z0 && layer < z1)
-                  atomicAdd(&ys[layer % 3][(lj * UT + li) * 3 + c], (double)(ce * (t ? d1[r] : d0[r])));
-              }
+          for (int r = 0; r < 4; ++r) {
+            const int R = 16 * t + 4 * q4 + r;
+            if (R < 24) {
+              const int aa = R / 3, c = R % 3;
+              const int li = ii + (aa & 1) - 1, lj = jj + ((aa >> 1) & 1) - 1;
+              const int layer = k + (aa >> 2);
+              if (li >= 0 && li < UT && lj >= 0 && lj < UT && layer >= z0 && layer < z1)
+                atomicAdd(&ys[layer % 3][(lj * UT + li) * 3 + c], (double)(ce * (t ? d1[r] : d0[r])));
             }
-        }
+          }
       }
     }
     if (k + 2 <= nz) stage(Rnext, k + 2);
     __syncthreads();
     if (k >= z0) store(k);
   };
-  // FP64: two register sets alternate so no copy waits on loads in flight;
-  // for the FP32 and BF16 bodies the doubled loop measured slower.
-  if (PREC == P_F64) {
-    for (int k = kbeg; k <= kend; k += 2) {
-      layer_step(k, Ra, Rb);
-      if (k + 1 <= kend) layer_step(k + 1, Rb, Ra);
-    }
-  } else {
-    for (int k = kbeg; k <= kend; ++k) {
-      layer_step(k, Ra, Rb);
-      Ra = Rb;
-    }
+  for (int k = kbeg; k <= kend; ++k) {
+    layer_step(k, Ra, Rb);
+    Ra = Rb;
   }
   if (kend + 1 < z1 && kend + 1 >= z0) store(kend + 1);
   if (FUSED) {
@@ -414,10 +339,13 @@ __device__ __forceinline__ void brick_blocks(const T (&k)[8], const T (&w)[3][8]
   }
 }
 
-#ifndef AMRTO_BRICK_Z
-#define AMRTO_BRICK_Z 10
-#endif
-constexpr int BZ = AMRTO_BRICK_Z;  // node layers per workgroup
+// node layers per workgroup (the march is unrolled for exactly this many):
+// FP64 runs two workgroups per CU and gains from longer chunks (fewer
+// repeated layers); FP32 runs four and from more workgroups
+template <typename VT>
+struct BrickZ { static constexpr int layers = 10; };
+template <>
+struct BrickZ<double> { static constexpr int layers = 20; };
 #ifndef AMRTO_BRICK_PD
 #define AMRTO_BRICK_PD 2
 #endif
@@ -428,14 +356,14 @@ constexpr int BPD = AMRTO_BRICK_PD;  // prefetch distance in layers
 #endif
 // workgroups per CU the brick kernel is compiled for
 template <typename VT>
-struct BrickOcc { static constexpr int blocks = 4; };
+struct BrickOcc { static constexpr int blocks = 4 * 256 / BTHREADS; };
 template <>
-struct BrickOcc<double> { static constexpr int blocks = AMRTO_BRICK_OCC64; };
+struct BrickOcc<double> { static constexpr int blocks = AMRTO_BRICK_OCC64 * 256 / BTHREADS; };
 
 template <typename VT, bool FUSED>
-__global__ __launch_bounds__(256, BrickOcc<VT>::blocks) void k_apply_brick(UArgs a, BrickK<VT> kc, CgArgs cg) {
-  __shared__ VT xs[4][3][BT * BT];  // staged node layers L & 3 (masked; fused: p)
-  __shared__ VT sb[2][3][BT * BT];  // partial sums for the node column above
+__global__ __launch_bounds__(BTHREADS, BrickOcc<VT>::blocks) void k_apply_brick(UArgs a, BrickK<VT> kc, CgArgs cg) {
+  __shared__ VT xs[4][3][BTHREADS];  // staged node layers L & 3 (masked; fused: p)
+  __shared__ VT sb[2][3][BTHREADS];  // partial sums for the node column above
   __shared__ double sh[8];
   double beta = 0.0;
   if (FUSED) {
@@ -460,26 +388,27 @@ __global__ __launch_bounds__(256, BrickOcc<VT>::blocks) void k_apply_brick(UArgs
   const uint8_t* __restrict__ fix = a.fix;
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   // z-chunks vary fastest: the chunks of one column of tiles share an XCD
-  const int nzc = (nz + 1 + a.zchunk - 1) / a.zchunk;
+  constexpr int BZ = BrickZ<VT>::layers;
+  const int nzc = (nz + 1 + BZ - 1) / BZ;
   const int tz = tile % nzc;
   const int txy = tile / nzc;
   const int tx = txy % a.tiles_x, ty = txy / a.tiles_x;
   const int i = tid & (BT - 1), j = tid >> 4;
-  const int gx = tx * BO - 1 + i, gy = ty * BO - 1 + j;
+  const int gx = tx * BO - 1 + i, gy = ty * BOY - 1 + j;
   const bool nv = gx >= 0 && gx <= nx && gy >= 0 && gy <= ny;
-  const bool ev = i < BT - 1 && j < BT - 1 && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-  const bool owned = nv && i >= 1 && i <= BO && j >= 1 && j <= BO;
+  const bool ev = i < BT - 1 && j < BTY - 1 && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+  const bool owned = nv && i >= 1 && i <= BO && j >= 1 && j <= BOY;
   // per-lane offsets within a layer (32-bit: 3 n_nodes < 2^31 is checked at
   // upload); per-layer offsets are uniform
   const int nid = nv ? gx + (nx + 1) * gy : 0;
   const int eid = ev ? gx + nx * gy : 0;
   const long sxy = (long)(nx + 1) * (ny + 1);
   const long nxy = (long)nx * ny;
-  const int z0 = tz * a.zchunk;
-  const int z1 = min(z0 + a.zchunk, nz + 1);
+  const int z0 = tz * BZ;
+  const int z1 = min(z0 + BZ, nz + 1);
   const VT vbeta = (VT)beta;
   const bool first = FUSED && cg.it == 0;
-  const int up = min(tid + BT, BT * BT - 1);  // node column above (row 15: unused)
+  const int up = min(tid + BT, BTHREADS - 1);  // node column above (top row: unused)
   const int dn = max(tid - BT, 0);            // node column below (row 0: unused)
 
   // raw loads of node layer L and the coefficient of element layer L.  The
@@ -565,26 +494,26 @@ __global__ __launch_bounds__(256, BrickOcc<VT>::blocks) void k_apply_brick(UArgs
   for (int q = 2; q < 2 + BPD; ++q) load(S[q % NSL], kbeg + q);
   __syncthreads();
   face_modes(Ls[0], kbeg, fb);
+  VT fn[3][4];  // x-y modes of the next layer to contract (k + 1)
+  face_modes(Ls[1], kbeg + 1, fn);
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int t = 0; t < 4; ++t) carry[c][t] = 0;
   double dot = 0.0;
 
-  // element layer k: contract with the staged layers k (lp) and k + 1 (lc), stage
-  // layer k + 2 from Rst into ln, request layer k + 2 + BPD into Rld, finish
-  // node layer k
-  auto step = [&](int k, Slot& Rld, Slot& Rst, const Lay& lp, const Lay& lc, Lay& ln) {
-    VT ft[3][4];
-    face_modes(lc, k + 1, ft);
+  // element layer k: contract with the staged layers k (modes fb) and k + 1
+  // (modes fn), stage layer k + 2 from Rst into ln, request layer k + 2 + BPD
+  // into Rld, finish node layer k and take the modes of layer k + 2
+  auto step = [&](int k, Slot& Rld, Slot& Rst, const Lay& lp, Lay& ln) {
     VT w[3][8];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        w[c][t] = fb[c][t] + ft[c][t];
-        w[c][t + 4] = fb[c][t] - ft[c][t];
-        fb[c][t] = ft[c][t];
+        w[c][t] = fb[c][t] + fn[c][t];
+        w[c][t + 4] = fb[c][t] - fn[c][t];
+        fb[c][t] = fn[c][t];
       }
     VT ks[8];
 #pragma unroll
@@ -615,6 +544,8 @@ __global__ __launch_bounds__(256, BrickOcc<VT>::blocks) void k_apply_brick(UArgs
     if (k + 2 <= nz) stage(Rst, k + 2, ln);
     load(Rld, k + 2 + BPD);
     __syncthreads();
+    // the next layer's modes first: its LDS reads overlap the partial sums'
+    if (k < kend) face_modes(ln, k + 2, fn);
     if (owned && k >= z0) {
       VT* yl = Y + 3 * sxy * k;
 #pragma unroll
@@ -635,7 +566,7 @@ __global__ __launch_bounds__(256, BrickOcc<VT>::blocks) void k_apply_brick(UArgs
   for (int st = 0; st <= BZ; ++st) {
     const int k = kbeg + st;
     if (k > kend) break;
-    step(k, S[(st + 2 + BPD) % NSL], S[(st + 2) % NSL], Ls[st % 3], Ls[(st + 1) % 3], Ls[(st + 2) % 3]);
+    step(k, S[(st + 2 + BPD) % NSL], S[(st + 2) % NSL], Ls[st % 3], Ls[(st + 2) % 3]);
   }
   if (FUSED) {
     dot = block_sum(dot, sh);
@@ -663,7 +594,7 @@ struct ChunkArgs {
 template <typename VT, int PREC, bool FUSED, bool COARSE = false>
 __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, CgArgs cg) {
   __shared__ VT xs[TAB_MAX * 3];
-  __shared__ double ys[TAB_MAX * 3];  // FP64 LDS accumulators (see k_apply_uniform)
+  __shared__ double ys[TAB_MAX * 3];  // FP64 LDS accumulators (see k_apply_uniform_bf16)
   __shared__ uint16_t lsm[PREC == P_BF16 ? ENT_MAX * 8 : 1];
   __shared__ double sh[8];
   __shared__ uint32_t trip_hm_s[TRIP_MAX];
@@ -1018,10 +949,11 @@ void uniform_grid(const amrto_ctx* ctx, int& tiles_x, int& tiles_y, int& zchunk,
   grid = ((n_tiles + 7) / 8) * 8;
 }
 
-void brick_grid(const amrto_ctx* ctx, int& tiles_x, int& tiles_y, int& zchunk, int& n_tiles) {
+template <typename VT>
+static void brick_grid(const amrto_ctx* ctx, int& tiles_x, int& tiles_y, int& n_tiles) {
+  constexpr int BZ = BrickZ<VT>::layers;
   tiles_x = (ctx->nx + 1 + BO - 1) / BO;
-  tiles_y = (ctx->ny + 1 + BO - 1) / BO;
-  zchunk = BZ;  // the kernel's march is unrolled for exactly this many layers
+  tiles_y = (ctx->ny + 1 + BOY - 1) / BOY;
   n_tiles = tiles_x * tiles_y * ((ctx->nz + 1 + BZ - 1) / BZ);
 }
 
@@ -1030,10 +962,11 @@ void brick_grid(const amrto_ctx* ctx, int& tiles_x, int& tiles_y, int& zchunk, i
 // same slots whatever the precision; surplus workgroups write zeros.
 int apply_blocks(const amrto_ctx* ctx) {
   if (ctx->uniform) {
-    int tx, ty, zc, nt, grid, nb;
+    int tx, ty, zc, nt, grid, nb64, nb32;
     uniform_grid(ctx, tx, ty, zc, nt, grid);
-    brick_grid(ctx, tx, ty, zc, nb);
-    return ((std::max(nt, nb) + 7) / 8) * 8;
+    brick_grid<double>(ctx, tx, ty, nb64);
+    brick_grid<float>(ctx, tx, ty, nb32);
+    return ((std::max(nt, std::max(nb64, nb32)) + 7) / 8) * 8;
   }
   return ((ctx->n_chunks + 7) / 8) * 8;
 }
@@ -1048,14 +981,14 @@ static int launch_t(amrto_ctx* ctx, const UArgs& ua, const CgArgs& cg) {
       uniform_grid(ctx, tx, ty, zc, nt, grid);
       grid = apply_blocks(ctx);
       a.tiles_x = tx; a.tiles_y = ty; a.zchunk = zc; a.n_tiles = nt;
-      hipLaunchKernelGGL((k_apply_uniform<VT, PREC, FUSED>), dim3(grid), dim3(256), 0, ctx->stream, a, cg);
+      hipLaunchKernelGGL((k_apply_uniform_bf16<FUSED>), dim3(grid), dim3(256), 0, ctx->stream, a, cg);
     } else {
-      brick_grid(ctx, tx, ty, zc, nt);
+      brick_grid<VT>(ctx, tx, ty, nt);
       grid = apply_blocks(ctx);
-      a.tiles_x = tx; a.tiles_y = ty; a.zchunk = zc; a.n_tiles = nt;
+      a.tiles_x = tx; a.tiles_y = ty; a.zchunk = BrickZ<VT>::layers; a.n_tiles = nt;
       BrickK<VT> kc;
       for (int q = 0; q < 8; ++q) kc.c[q] = (VT)ctx->bk[q];
-      hipLaunchKernelGGL((k_apply_brick<VT, FUSED>), dim3(grid), dim3(256), 0, ctx->stream, a, kc, cg);
+      hipLaunchKernelGGL((k_apply_brick<VT, FUSED>), dim3(grid), dim3(BTHREADS), 0, ctx->stream, a, kc, cg);
     }
   } else {
     hipLaunchKernelGGL((k_apply_chunks<VT, PREC, FUSED>), dim3(apply_blocks(ctx)), dim3(256), 0, ctx->stream, ua,

@@ -25,10 +25,16 @@ namespace amrto {
 constexpr int UT = 15;
 constexpr int UE = UT + 1;  // element columns per tile edge
 constexpr int UN = UT + 2;  // node columns per tile edge (with halo)
-// Brick kernel tile: 16 x 16 node columns per workgroup (one per thread),
-// 15 x 15 element columns, 14 x 14 owned node columns.
+// Brick kernel tile: 16 x BTY node columns per workgroup (one per thread),
+// 15 x (BTY - 1) element columns, 14 x (BTY - 2) owned node columns.
+#ifndef AMRTO_BRICK_TY
+#define AMRTO_BRICK_TY 16
+#endif
 constexpr int BT = 16;
 constexpr int BO = BT - 2;
+constexpr int BTY = AMRTO_BRICK_TY;
+constexpr int BOY = BTY - 2;
+constexpr int BTHREADS = BT * BTY;
 
 // Octree operator chunk: a run of at most CH_MAX consecutive elements plus
 // the halo elements around its owned nodes (at most ENT_MAX in all); its node
