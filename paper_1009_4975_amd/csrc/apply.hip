@@ -41,7 +41,7 @@ struct UArgs {
   void* pnew;        // fused: new search direction
   const void* coef;
   const uint8_t* fix;
-  const void* kb;    // FP64/FP32: 72 block constants; BF16: K0 hi/lo bits
+  const void* kb;    // BF16: K0 hi/lo bits
   int nx, ny, nz, tiles_x, tiles_y, zchunk, n_tiles;
   const double* stop;
   // fused octree pass with the affine coarse space: x holds r and the staged
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256, 4) void k_apply_uniform_bf16(UArgs a, CgArgs c
   using VT = float;
   __shared__ VT xs[NBUF][UN * UN * 3];
   __shared__ double ys[3][UT * UT * 3];
-  __shared__ double sh[8];
+  __shared__ double sh[16];
   double beta = 0.0;
   if (FUSED) {
     if (!cg_prologue(cg, beta, sh)) return;
@@ -351,6 +351,26 @@ struct BrickZ<double> { static constexpr int layers = 20; };
 #endif
 constexpr int BPD = AMRTO_BRICK_PD;  // prefetch distance in layers
 
+// y = c K0 u for one element: mode transform, the eight-constant block
+// product (k already scaled by c), inverse transform
+template <typename T>
+__device__ __forceinline__ void contract_brick(const T (&k)[8], const T (&u)[24], T (&y)[24]) {
+  T w[3][8], o[3][8];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int n = 0; n < 8; ++n) w[c][n] = u[3 * n + c];
+    wht8(w[c]);
+  }
+  brick_blocks<T>(k, w, o);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    wht8(o[c]);
+#pragma unroll
+    for (int n = 0; n < 8; ++n) y[3 * n + c] = o[c][n];
+  }
+}
+
 #ifndef AMRTO_BRICK_OCC64
 #define AMRTO_BRICK_OCC64 2
 #endif
@@ -364,7 +384,7 @@ template <typename VT, bool FUSED>
 __global__ __launch_bounds__(BTHREADS, BrickOcc<VT>::blocks) void k_apply_brick(UArgs a, BrickK<VT> kc, CgArgs cg) {
   __shared__ VT xs[4][3][BTHREADS];  // staged node layers L & 3 (masked; fused: p)
   __shared__ VT sb[2][3][BTHREADS];  // partial sums for the node column above
-  __shared__ double sh[8];
+  __shared__ double sh[16];
   double beta = 0.0;
   if (FUSED) {
     if (!cg_prologue(cg, beta, sh)) return;
@@ -592,11 +612,11 @@ struct ChunkArgs {
 };
 
 template <typename VT, int PREC, bool FUSED, bool COARSE = false>
-__global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, CgArgs cg) {
+__global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, BrickK<VT> kc, CgArgs cg) {
   __shared__ VT xs[TAB_MAX * 3];
   __shared__ double ys[TAB_MAX * 3];  // FP64 LDS accumulators (see k_apply_uniform_bf16)
   __shared__ uint16_t lsm[PREC == P_BF16 ? ENT_MAX * 8 : 1];
-  __shared__ double sh[8];
+  __shared__ double sh[16];
   __shared__ uint32_t trip_hm_s[TRIP_MAX];
   __shared__ double trip_w_s[TRIP_MAX];
   __shared__ int hbeg_s[TAB_MAX];
@@ -716,8 +736,6 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, CgA
   for (int i = tid; i < nt * 3; i += 256) ys[i] = 0.0;
   if (PREC == P_BF16)
     for (int i = tid; i < nent * 8; i += 256) lsm[i] = ca.ent_loc[8L * n0 + i];
-  __shared__ VT sB[PREC == P_F64 ? 72 : 1];  // FP64 block constants as LDS broadcasts
-  if (PREC == P_F64 && tid < 72) sB[tid] = ((const VT*)a.kb)[tid];
   __syncthreads();
   for (int i = tid; i < (nt - nreg) * 3; i += 256) {  // x_h = sum_m w_hm x_m  (Eq. (6))
     const int t = nreg + i / 3, comp = i % 3;
@@ -728,7 +746,6 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, CgA
   }
   __syncthreads();
   if (PREC != P_BF16) {
-    const VT* Bs = PREC == P_F64 ? (const VT*)sB : (const VT*)a.kb;
 #pragma unroll
     for (int r = 0; r < EPT; ++r) {
       const int en = tid + 256 * r;
@@ -745,7 +762,10 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, CgA
         u[3 * aa + 1] = xs[loc[aa] * 3 + 1];
         u[3 * aa + 2] = xs[loc[aa] * 3 + 2];
       }
-      contract_sym<VT>(Bs, u, out, ce);
+      VT ks[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) ks[q] = ce * kc.c[q];
+      contract_brick<VT>(ks, u, out);
 #pragma unroll
       for (int aa = 0; aa < 8; ++aa) {
         atomicAdd(&ys[loc[aa] * 3 + 0], (double)out[3 * aa + 0]);
@@ -926,6 +946,13 @@ __global__ void k_to_float(const double* __restrict__ a, float* __restrict__ b, 
 }
 
 // ------------------------------------------------------------------ host side
+template <typename VT>
+static BrickK<VT> brick_k(const amrto_ctx* ctx) {
+  BrickK<VT> kc;
+  for (int q = 0; q < 8; ++q) kc.c[q] = (VT)ctx->bk[q];
+  return kc;
+}
+
 static ChunkArgs chunk_args(amrto_ctx* ctx) {
   ChunkArgs a;
   a.chunk_ent = ctx->d_chunk_ent; a.chunk_tab = ctx->d_chunk_tab; a.chunk_trip = ctx->d_chunk_trip;
@@ -986,13 +1013,12 @@ static int launch_t(amrto_ctx* ctx, const UArgs& ua, const CgArgs& cg) {
       brick_grid<VT>(ctx, tx, ty, nt);
       grid = apply_blocks(ctx);
       a.tiles_x = tx; a.tiles_y = ty; a.zchunk = BrickZ<VT>::layers; a.n_tiles = nt;
-      BrickK<VT> kc;
-      for (int q = 0; q < 8; ++q) kc.c[q] = (VT)ctx->bk[q];
-      hipLaunchKernelGGL((k_apply_brick<VT, FUSED>), dim3(grid), dim3(BTHREADS), 0, ctx->stream, a, kc, cg);
+      hipLaunchKernelGGL((k_apply_brick<VT, FUSED>), dim3(grid), dim3(BTHREADS), 0, ctx->stream, a, brick_k<VT>(ctx),
+                         cg);
     }
   } else {
     hipLaunchKernelGGL((k_apply_chunks<VT, PREC, FUSED>), dim3(apply_blocks(ctx)), dim3(256), 0, ctx->stream, ua,
-                       chunk_args(ctx), cg);
+                       chunk_args(ctx), brick_k<VT>(ctx), cg);
   }
   AMRTO_HIP(hipGetLastError());
   return AMRTO_OK;
@@ -1002,13 +1028,8 @@ static UArgs base_args(amrto_ctx* ctx, int prec) {
   UArgs a;
   std::memset(&a, 0, sizeof a);
   a.fix = ctx->d_fix;
-  if (prec == AMRTO_FP64) {
-    a.coef = ctx->d_coef;
-    a.kb = ctx->d_Kb;
-  } else {
-    a.coef = ctx->d_coef_f;
-    a.kb = prec == AMRTO_FP32 ? (const void*)ctx->d_Kbf : (const void*)ctx->d_K0bf;
-  }
+  a.coef = prec == AMRTO_FP64 ? (const void*)ctx->d_coef : (const void*)ctx->d_coef_f;
+  a.kb = prec == AMRTO_BF16 ? (const void*)ctx->d_K0bf : nullptr;  // FP64/FP32 take the eight block constants
   return a;
 }
 
@@ -1056,13 +1077,13 @@ int apply_fused_coarse(amrto_ctx* ctx, const void* r, const void* dinv, const vo
   const dim3 grid(apply_blocks(ctx));
   if (prec == AMRTO_FP64)
     hipLaunchKernelGGL((k_apply_chunks<double, P_F64, true, true>), grid, dim3(256), 0, ctx->stream, a,
-                       chunk_args(ctx), cg);
+                       chunk_args(ctx), brick_k<double>(ctx), cg);
   else if (prec == AMRTO_FP32)
     hipLaunchKernelGGL((k_apply_chunks<float, P_F32, true, true>), grid, dim3(256), 0, ctx->stream, a,
-                       chunk_args(ctx), cg);
+                       chunk_args(ctx), brick_k<float>(ctx), cg);
   else
     hipLaunchKernelGGL((k_apply_chunks<float, P_BF16, true, true>), grid, dim3(256), 0, ctx->stream, a,
-                       chunk_args(ctx), cg);
+                       chunk_args(ctx), brick_k<float>(ctx), cg);
   AMRTO_HIP(hipGetLastError());
   return AMRTO_OK;
 }

@@ -120,8 +120,7 @@ static int upload_material(amrto_ctx* ctx) {
   // K0 in the basis of per-component Walsh-Hadamard modes W (W W^T = 8 I):
   // B = W K0 W^T / 64 is block diagonal; block S couples the modes
   // (c, t = S ^ (1 << c)), c = 0, 1, 2, so K0 = W^T B W.
-  static double kbd[72];
-  static float kbf[72];
+  double kbd[72];
   auto wsign = [](int t, int n) { return (__builtin_popcount(t & n) & 1) ? -1.0 : 1.0; };
   for (int S = 0; S < 8; ++S)
     for (int c = 0; c < 3; ++c)
@@ -131,7 +130,6 @@ static int upload_material(amrto_ctx* ctx) {
         for (int n = 0; n < 8; ++n)
           for (int m = 0; m < 8; ++m) v += wsign(t, n) * ctx->K0[(3 * n + c) * 24 + 3 * m + d] * wsign(tp, m);
         kbd[9 * S + 3 * c + d] = v / 64.0;
-        kbf[9 * S + 3 * c + d] = (float)(v / 64.0);
       }
   // For a cube of an isotropic material the blocks have a fixed pattern
   // (zero modes, equal entries) with eight distinct values:
@@ -151,8 +149,6 @@ static int upload_material(amrto_ctx* ctx) {
     const double bk[8] = {a - b, b, d, e, f, g, h - i, i};
     std::memcpy(ctx->bk, bk, sizeof bk);
   }
-  AMRTO_HIP(hipMemcpyAsync(ctx->d_Kb, kbd, sizeof(kbd), hipMemcpyHostToDevice, ctx->stream));
-  AMRTO_HIP(hipMemcpyAsync(ctx->d_Kbf, kbf, sizeof(kbf), hipMemcpyHostToDevice, ctx->stream));
   AMRTO_HIP(hipStreamSynchronize(ctx->stream));
   return AMRTO_OK;
 }
@@ -172,8 +168,6 @@ int amrto_create(amrto_ctx** out, int device, void* stream) {
   if (hipMalloc((void**)&ctx->d_K0, 576 * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&ctx->d_K0f, 576 * sizeof(float)) != hipSuccess ||
       hipMalloc((void**)&ctx->d_K0bf, 1152 * sizeof(uint16_t)) != hipSuccess ||
-      hipMalloc((void**)&ctx->d_Kb, 72 * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&ctx->d_Kbf, 72 * sizeof(float)) != hipSuccess ||
       hipMalloc((void**)&ctx->d_part, 8 * RED_BLOCKS * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&ctx->d_scal, S_COUNT * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&ctx->d_oc, OC_WS * sizeof(double)) != hipSuccess ||
@@ -193,7 +187,7 @@ int amrto_destroy(amrto_ctx* ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   else (void)hipDeviceSynchronize();
   free_mesh(ctx);
-  dfree(ctx->d_K0); dfree(ctx->d_K0f); dfree(ctx->d_K0bf); dfree(ctx->d_Kb); dfree(ctx->d_Kbf);
+  dfree(ctx->d_K0); dfree(ctx->d_K0f); dfree(ctx->d_K0bf);
   dfree(ctx->d_part); dfree(ctx->d_scal); dfree(ctx->d_oc);
   if (ctx->h_scal) (void)hipHostFree(ctx->h_scal);
   delete ctx;

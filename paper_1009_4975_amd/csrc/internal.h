@@ -108,8 +108,6 @@ struct amrto_ctx {
   double* d_K0 = nullptr;      // 576
   float* d_K0f = nullptr;      // 576
   uint16_t* d_K0bf = nullptr;  // 2 x 576 (hi, lo) bf16 bit patterns
-  double* d_Kb = nullptr;      // 72: K0 in mirror-symmetry blocks
-  float* d_Kbf = nullptr;      // 72
   // device: mesh
   uint8_t* d_fix = nullptr;        // per node, bit c = DOF c supported
   int8_t* d_level = nullptr;       // per element

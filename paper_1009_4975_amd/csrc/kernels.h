@@ -38,6 +38,27 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
   return block_sum(v, sh);
 }
 
+// two block sums with one exchange (sh holds 2 x waves entries); each sum
+// uses the same fixed tree as block_sum
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+  if (lane == 0) {
+    sh[w] = a;
+    sh[nw + w] = b;
+  }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+  for (int i = 0; i < nw; ++i) {
+    sa += sh[i];
+    sb += sh[nw + i];
+  }
+  __syncthreads();
+  a = sa;
+  b = sb;
+}
+
 // ------------------------------------------------------------------ element contraction
 // K0 commutes with the three mirror maps of the cube (node flip combined with
 // a sign change of the mirrored displacement component).  In the basis of
@@ -45,7 +66,7 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
 // it is block diagonal: the three modes (c, t = S ^ (1 << c)), c = 0, 1, 2,
 // sharing the mirror character S form one 3x3 block B_S (8 blocks; rigid
 // translations t = 0 fall in zero rows).  So K0 u = W^T B W u costs two
-// transforms (add/sub only) and 72 FMAs instead of 576.
+// transforms (add/sub only) and a few multiply-adds (apply.hip: brick_blocks).
 template <typename T>
 __device__ __forceinline__ void wht8(T (&v)[8]) {
 #pragma unroll
@@ -57,32 +78,6 @@ __device__ __forceinline__ void wht8(T (&v)[8]) {
         v[j] = a + b;
         v[j + h] = a - b;
       }
-}
-
-// y = s * K0 u with Bs = 8 blocks x 9 entries (row-major, already / 64)
-template <typename T>
-__device__ __forceinline__ void contract_sym(const T* __restrict__ Bs, const T (&u)[24], T (&y)[24], T s) {
-  T w[3][8];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-#pragma unroll
-    for (int n = 0; n < 8; ++n) w[c][n] = u[3 * n + c];
-    wht8(w[c]);
-  }
-  T o[3][8];
-#pragma unroll
-  for (int S = 0; S < 8; ++S) {
-    const T v0 = w[0][S ^ 1], v1 = w[1][S ^ 2], v2 = w[2][S ^ 4];
-    o[0][S ^ 1] = s * (Bs[9 * S + 0] * v0 + Bs[9 * S + 1] * v1 + Bs[9 * S + 2] * v2);
-    o[1][S ^ 2] = s * (Bs[9 * S + 3] * v0 + Bs[9 * S + 4] * v1 + Bs[9 * S + 5] * v2);
-    o[2][S ^ 4] = s * (Bs[9 * S + 6] * v0 + Bs[9 * S + 7] * v1 + Bs[9 * S + 8] * v2);
-  }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    wht8(o[c]);
-#pragma unroll
-    for (int n = 0; n < 8; ++n) y[3 * n + c] = o[c][n];
-  }
 }
 
 // ------------------------------------------------------------------ BF16 MFMA tile
@@ -154,9 +149,13 @@ __device__ __forceinline__ void mfma_tile_bf16(const bf16x8 (&a)[2][2], const fl
 
 __device__ __forceinline__ bool cg_prologue(const CgArgs& cg, double& beta, double* sh) {
   if (cg.scal[S_DONE] != 0.0) return false;
-  double rz = sum_partials(cg.part_in, RED_BLOCKS, sh);
+  double rz = 0.0, rr = 0.0;
+  for (int i = threadIdx.x; i < RED_BLOCKS; i += blockDim.x) {
+    rz += cg.part_in[i];
+    rr += cg.part_in[RED_BLOCKS + i];
+  }
+  block_sum2(rz, rr, sh);
   if (cg.coarse) rz += cg.scal[S_CTZ];
-  const double rr = sum_partials(cg.part_in + RED_BLOCKS, RED_BLOCKS, sh);
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   if (!(rz == rz) || !(rr == rr) || rr > 1e300 || rz > 1e300) {
     if (lead) cg.scal[S_DONE] = 2.0;

@@ -110,8 +110,7 @@ __global__ __launch_bounds__(256) void k_cg_update(VT* __restrict__ x, VT* __res
     srz += (double)ri * (double)zi;
     srr += (double)ri * (double)ri;
   }
-  srz = block_sum(srz, sh);
-  srr = block_sum(srr, sh);
+  block_sum2(srz, srr, sh);
   if (threadIdx.x == 0) {
     part[blockIdx.x] = srz;
     part[RED_BLOCKS + blockIdx.x] = srr;
@@ -307,8 +306,7 @@ __global__ __launch_bounds__(256) void k_cg_update_coarse(VT* __restrict__ x, VT
   zt_flush(a, acc, nf, R, lo < hi ? coarse_region(ca, (int)(lo / 3)) : 0, red);
   __syncthreads();
   zt_store(acc, k, part_z);
-  srz = block_sum(srz, sh);
-  srr = block_sum(srr, sh);
+  block_sum2(srz, srr, sh);
   if (threadIdx.x == 0) {
     part[blockIdx.x] = srz;
     part[RED_BLOCKS + blockIdx.x] = srr;
@@ -386,8 +384,7 @@ __global__ __launch_bounds__(256) void k_coarse_z(const VT* __restrict__ r, VT* 
     srz += (double)ri * zi;
     srr += (double)ri * (double)ri;
   }
-  srz = block_sum(srz, sh);
-  srr = block_sum(srr, sh);
+  block_sum2(srz, srr, sh);
   if (threadIdx.x == 0) {
     part[blockIdx.x] = srz;
     part[RED_BLOCKS + blockIdx.x] = srr;
