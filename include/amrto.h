@@ -159,6 +159,12 @@ typedef struct {
   int32_t fallback_fp64; /* 1 (default): a mixed solve that breaks down or
                          stalls above rtol continues as plain FP64 PCG from
                          its iterate (from zero if that is not finite) */
+  int32_t single_reduction; /* 1: plain FP64 Jacobi-PCG on an octree mesh runs
+                         the one-reduction recurrences of Chronopoulos and
+                         Gear (one pass per iteration, same iterates in exact
+                         arithmetic); 0 (default): two passes, which measured
+                         faster on the octree cantilever (the one pass carries
+                         the update's gathers and is as long as both) */
 } amrto_solve_opts;
 
 typedef struct {

@@ -45,7 +45,7 @@ class Region(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_it", C.c_int32), ("precond", C.c_int32),
                 ("inner_prec", C.c_int32), ("inner_rtol", C.c_double), ("check_every", C.c_int32),
-                ("use_coarse", C.c_int32), ("fallback_fp64", C.c_int32)]
+                ("use_coarse", C.c_int32), ("fallback_fp64", C.c_int32), ("single_reduction", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -362,12 +362,13 @@ class Context:
         self._chk(self.lib.amrto_get_diag(self.h, _dev(out, self.torch.float64)))
 
     def pcg(self, b, u, rtol=1e-8, max_it=20000, inner_prec=FP64, inner_rtol=1e-3, check_every=16,
-            use_coarse=True, fallback_fp64=True, allow_not_converged=False):
+            use_coarse=True, fallback_fp64=True, single_reduction=False, allow_not_converged=False):
         o = SolveOpts()
         self.lib.amrto_solve_opts_default(C.byref(o))
         o.rtol, o.max_it, o.inner_prec, o.inner_rtol = rtol, max_it, inner_prec, inner_rtol
         o.check_every, o.use_coarse = check_every, int(bool(use_coarse))
         o.fallback_fp64 = int(bool(fallback_fp64))
+        o.single_reduction = int(bool(single_reduction))
         st = SolveStats()
         rc = self.lib.amrto_pcg(self.h, _dev(b, self.torch.float64), _dev(u, self.torch.float64), C.byref(o),
                                 C.byref(st))

@@ -250,127 +250,6 @@ __global__ __launch_bounds__(256, 4) void k_apply_uniform_bf16(UArgs a, CgArgs c
 // block matrix is applied through its eight distinct entries (cube symmetry:
 // 33 multiply-adds instead of 72, the element coefficient folded into the
 // eight constants).  One barrier per layer.
-template <typename VT>
-struct BrickK {
-  VT c[8];  // a - b, b, d, e, f, g, h - i, i
-};
-
-constexpr int DPP_ROW_SHL1 = 0x101;  // lane l reads lane l + 1 of its row of 16
-constexpr int DPP_ROW_SHR1 = 0x111;  // lane l reads lane l - 1 of its row of 16
-
-// row shifts; lanes whose source falls outside their row read zero
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double v) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
-  return __hiloint2double(hi, lo);
-}
-template <int CTRL>
-__device__ __forceinline__ float dpp_mov(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
-}
-
-// 4-point Walsh-Hadamard transform over the x and y bits of a face:
-// (u00, u10, u01, u11) -> modes (0, x, y, xy); its own inverse up to 1/4.
-template <typename T>
-__device__ __forceinline__ void wht4(T (&u)[4]) {
-  const T a0 = u[0] + u[1], a1 = u[0] - u[1], b0 = u[2] + u[3], b1 = u[2] - u[3];
-  u[0] = a0 + b0;
-  u[1] = a1 + b1;
-  u[2] = a0 - b0;
-  u[3] = a1 - b1;
-}
-
-// o = s B w with the block pattern of the cube (w, o: modes [c][t], t bits
-// x, y, z); k[] already scaled by the element coefficient.  Translation modes
-// (t = 0) give zero rows and columns.
-template <typename T>
-__device__ __forceinline__ void brick_blocks(const T (&k)[8], const T (&w)[3][8], T (&o)[3][8]) {
-  const T AB = k[0], B = k[1], D = k[2], E = k[3], F = k[4], G = k[5], HI = k[6], I = k[7];
-  o[0][0] = 0;
-  o[1][0] = 0;
-  o[2][0] = 0;
-  {  // S = 0: modes (0,1) (1,2) (2,4)
-    const T v0 = w[0][1], v1 = w[1][2], v2 = w[2][4];
-    const T bt = B * (v0 + v1 + v2);
-    o[0][1] = AB * v0 + bt;
-    o[1][2] = AB * v1 + bt;
-    o[2][4] = AB * v2 + bt;
-  }
-  {  // S = 7: modes (0,6) (1,5) (2,3)
-    const T v0 = w[0][6], v1 = w[1][5], v2 = w[2][3];
-    const T it = I * (v0 + v1 + v2);
-    o[0][6] = HI * v0 + it;
-    o[1][5] = HI * v1 + it;
-    o[2][3] = HI * v2 + it;
-  }
-  {  // S = 1: (1,3) (2,5)
-    const T v1 = w[1][3], v2 = w[2][5];
-    o[1][3] = D * v1 + E * v2;
-    o[2][5] = E * v1 + D * v2;
-  }
-  {  // S = 2: (0,3) (2,6)
-    const T v0 = w[0][3], v2 = w[2][6];
-    o[0][3] = D * v0 + E * v2;
-    o[2][6] = E * v0 + D * v2;
-  }
-  {  // S = 4: (0,5) (1,6)
-    const T v0 = w[0][5], v1 = w[1][6];
-    o[0][5] = D * v0 + E * v1;
-    o[1][6] = E * v0 + D * v1;
-  }
-  {  // S = 3: (0,2) (1,1) | (2,7)
-    const T s = F * (w[0][2] + w[1][1]);
-    o[0][2] = s;
-    o[1][1] = s;
-    o[2][7] = G * w[2][7];
-  }
-  {  // S = 5: (0,4) (2,1) | (1,7)
-    const T s = F * (w[0][4] + w[2][1]);
-    o[0][4] = s;
-    o[2][1] = s;
-    o[1][7] = G * w[1][7];
-  }
-  {  // S = 6: (1,4) (2,2) | (0,7)
-    const T s = F * (w[1][4] + w[2][2]);
-    o[1][4] = s;
-    o[2][2] = s;
-    o[0][7] = G * w[0][7];
-  }
-}
-
-// node layers per workgroup (the march is unrolled for exactly this many):
-// FP64 runs two workgroups per CU and gains from longer chunks (fewer
-// repeated layers); FP32 runs four and from more workgroups
-template <typename VT>
-struct BrickZ { static constexpr int layers = 10; };
-template <>
-struct BrickZ<double> { static constexpr int layers = 20; };
-#ifndef AMRTO_BRICK_PD
-#define AMRTO_BRICK_PD 2
-#endif
-constexpr int BPD = AMRTO_BRICK_PD;  // prefetch distance in layers
-
-// y = c K0 u for one element: mode transform, the eight-constant block
-// product (k already scaled by c), inverse transform
-template <typename T>
-__device__ __forceinline__ void contract_brick(const T (&k)[8], const T (&u)[24], T (&y)[24]) {
-  T w[3][8], o[3][8];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-#pragma unroll
-    for (int n = 0; n < 8; ++n) w[c][n] = u[3 * n + c];
-    wht8(w[c]);
-  }
-  brick_blocks<T>(k, w, o);
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    wht8(o[c]);
-#pragma unroll
-    for (int n = 0; n < 8; ++n) y[3 * n + c] = o[c][n];
-  }
-}
-
 #ifndef AMRTO_BRICK_OCC64
 #define AMRTO_BRICK_OCC64 2
 #endif
@@ -595,21 +474,6 @@ __global__ __launch_bounds__(BTHREADS, BrickOcc<VT>::blocks) void k_apply_brick(
 }
 
 // ------------------------------------------------------------------ octree chunks
-struct ChunkArgs {
-  const int32_t* chunk_ent;   // [n_chunks + 1] entry ranges
-  const int32_t* chunk_tab;   // [n_chunks + 1] table ranges
-  const int32_t* chunk_trip;  // [n_chunks + 1] hanging triple ranges
-  const int32_t* chunk_nown;  // owned regular entries (table prefix)
-  const int32_t* chunk_nreg;  // regular entries
-  const int32_t* chunk_nhown; // owned hanging entries (after the regular ones)
-  const int32_t* ent_elem;
-  const uint16_t* ent_loc;
-  const int32_t* tab_node;
-  const uint32_t* trip_hm;
-  const double* trip_w;
-  const int32_t* tab_hbeg;    // hanging entries: first triple (chunk-relative)
-  int n_chunks;
-};
 
 template <typename VT, int PREC, bool FUSED, bool COARSE = false>
 __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, BrickK<VT> kc, CgArgs cg) {
@@ -946,23 +810,6 @@ __global__ void k_to_float(const double* __restrict__ a, float* __restrict__ b, 
 }
 
 // ------------------------------------------------------------------ host side
-template <typename VT>
-static BrickK<VT> brick_k(const amrto_ctx* ctx) {
-  BrickK<VT> kc;
-  for (int q = 0; q < 8; ++q) kc.c[q] = (VT)ctx->bk[q];
-  return kc;
-}
-
-static ChunkArgs chunk_args(amrto_ctx* ctx) {
-  ChunkArgs a;
-  a.chunk_ent = ctx->d_chunk_ent; a.chunk_tab = ctx->d_chunk_tab; a.chunk_trip = ctx->d_chunk_trip;
-  a.chunk_nown = ctx->d_chunk_nown; a.chunk_nreg = ctx->d_chunk_nreg; a.chunk_nhown = ctx->d_chunk_nhown;
-  a.ent_elem = ctx->d_ent_elem; a.ent_loc = ctx->d_ent_loc; a.tab_node = ctx->d_tab_node;
-  a.trip_hm = ctx->d_trip_hm; a.trip_w = ctx->d_trip_w; a.tab_hbeg = ctx->d_tab_hbeg;
-  a.n_chunks = ctx->n_chunks;
-  return a;
-}
-
 void uniform_grid(const amrto_ctx* ctx, int& tiles_x, int& tiles_y, int& zchunk, int& n_tiles, int& grid) {
   tiles_x = (ctx->nx + 1 + UT - 1) / UT;
   tiles_y = (ctx->ny + 1 + UT - 1) / UT;

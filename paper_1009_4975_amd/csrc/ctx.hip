@@ -90,6 +90,8 @@ static void free_mesh(amrto_ctx* c) {
   dfree(c->d_coef); dfree(c->d_coef_f); dfree(c->d_dinv); dfree(c->d_dinv_f); dfree(c->d_vol);
   dfree(c->d_r); dfree(c->d_z); dfree(c->d_p); dfree(c->d_q); dfree(c->d_p2); dfree(c->f_p2);
   dfree(c->d_partpq);
+  dfree(c->d_cg1_r2); dfree(c->d_cg1_w); dfree(c->d_cg1_w2); dfree(c->d_cg1_s); dfree(c->d_cg1_s2);
+  dfree(c->d_cg1_part);
   c->n_partpq = 0;
   dfree(c->f_b); dfree(c->f_x); dfree(c->f_r); dfree(c->f_z); dfree(c->f_p); dfree(c->f_q);
   dfree(c->d_cf); dfree(c->d_region); dfree(c->d_cpart); dfree(c->d_cinv); dfree(c->d_cz); dfree(c->d_ct); dfree(c->d_cmask); dfree(c->d_cgeo);
@@ -297,6 +299,11 @@ int amrto_upload_mesh(amrto_ctx* ctx, const amrto_mesh* m) {
   AMRTO_HIP(dalloc(ctx->f_p2, n3));
   ctx->n_partpq = apply_blocks(ctx);
   AMRTO_HIP(dalloc(ctx->d_partpq, ctx->n_partpq));
+  if (!uni) {
+    AMRTO_HIP(dalloc(ctx->d_cg1_r2, n3)); AMRTO_HIP(dalloc(ctx->d_cg1_w, n3)); AMRTO_HIP(dalloc(ctx->d_cg1_w2, n3));
+    AMRTO_HIP(dalloc(ctx->d_cg1_s, n3)); AMRTO_HIP(dalloc(ctx->d_cg1_s2, n3));
+    AMRTO_HIP(dalloc(ctx->d_cg1_part, 6L * cg1_parts(ctx)));
+  }
   AMRTO_HIP(dalloc(ctx->f_b, n3)); AMRTO_HIP(dalloc(ctx->f_x, n3)); AMRTO_HIP(dalloc(ctx->f_r, n3)); AMRTO_HIP(dalloc(ctx->f_z, n3));
   AMRTO_HIP(dalloc(ctx->f_p, n3)); AMRTO_HIP(dalloc(ctx->f_q, n3));
   ctx->has_mesh = true;

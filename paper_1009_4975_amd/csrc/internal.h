@@ -40,10 +40,13 @@ constexpr int BTHREADS = BT * BTY;
 // the halo elements around its owned nodes (at most ENT_MAX in all); its node
 // table (at most TAB_MAX entries) and hanging triples (at most TRIP_MAX) are
 // staged in LDS.
-constexpr int CH_MAX = 128;
-constexpr int ENT_MAX = 512;
-constexpr int TAB_MAX = 1024;
-constexpr int TRIP_MAX = 1024;  // hanging (node, master, weight) triples per chunk
+#ifndef AMRTO_CH_MAX
+#define AMRTO_CH_MAX 128
+#endif
+constexpr int CH_MAX = AMRTO_CH_MAX;
+constexpr int ENT_MAX = 4 * CH_MAX;
+constexpr int TAB_MAX = 8 * CH_MAX;
+constexpr int TRIP_MAX = 8 * CH_MAX;  // hanging (node, master, weight) triples per chunk
 
 // Reductions: fixed grid of partial sums; every consumer re-adds them in the
 // same order, so results are deterministic without a separate finalize pass.
@@ -69,7 +72,9 @@ enum ScalarSlot {
   S_RR = 5,    // last r.r
   // 6, 7: true residual r.r and b.b
   S_CTZ = 8,   // coarse space: ct^T E^-1 ct, the coarse part of r.z
-  S_COUNT = 10
+  S_AL0 = 9,   // single-reduction CG: alpha, double buffered on iteration parity
+  S_AL1 = 10,
+  S_COUNT = 12
 };
 
 // Arguments of a fused conjugate-gradient step (see kernels.h).
@@ -153,6 +158,10 @@ struct amrto_ctx {
   double* d_r = nullptr; double* d_z = nullptr; double* d_p = nullptr; double* d_q = nullptr;
   double* d_p2 = nullptr; float* f_p2 = nullptr;
   double* d_partpq = nullptr; // p.q partials of the fused operator passes
+  // single-reduction CG on octree meshes: second r buffer, w and s pairs, and
+  // the gamma / delta / r.r partials of two passes
+  double* d_cg1_r2 = nullptr; double* d_cg1_w = nullptr; double* d_cg1_w2 = nullptr;
+  double* d_cg1_s = nullptr; double* d_cg1_s2 = nullptr; double* d_cg1_part = nullptr;
   int n_partpq = 0;
   float* f_b = nullptr; float* f_x = nullptr; float* f_r = nullptr; float* f_z = nullptr; float* f_p = nullptr; float* f_q = nullptr;
   double* d_part = nullptr;   // reduction partials (4 x RED_BLOCKS)
@@ -201,6 +210,10 @@ int mask_vector_n(amrto_ctx* ctx, double* x, int count);
 int launch_zt(amrto_ctx* ctx, const double* v);
 int apply_stop(amrto_ctx* ctx, const void* x, void* y, int prec, const double* stop);
 int apply_fused(amrto_ctx* ctx, const void* z, const void* pold, void* pnew, void* q, int prec, const CgArgs& cg);
+bool cg1_available(const amrto_ctx* ctx);
+int cg1_parts(const amrto_ctx* ctx);
+int cg1_init(amrto_ctx* ctx);
+int cg1_enqueue(amrto_ctx* ctx, double* x, double tol2, int it0, int count);
 int apply_fused_coarse(amrto_ctx* ctx, const void* r, const void* dinv, const void* pold, void* pnew, void* q,
                        int prec, const CgArgs& cg);
 int apply_blocks(const amrto_ctx* ctx);

@@ -540,7 +540,7 @@ static int enqueue_iters(amrto_ctx* ctx, const Vecs<VT>& v, VT* x, int prec, dou
 
 // Plain FP64 Jacobi-PCG from x (masked).  *iters = iterations performed.
 static int cg_fp64_run(amrto_ctx* ctx, const double* b, double* x, double rtol, int max_it, int check_every,
-                       int* iters) {
+                       bool one_reduction, int* iters) {
   const long n3 = 3L * ctx->n_nodes;
   const int g1 = (int)((n3 + 255) / 256);
   Vecs<double> v = vecs64(ctx);
@@ -557,6 +557,13 @@ static int cg_fp64_run(amrto_ctx* ctx, const double* b, double* x, double rtol, 
   hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(256), 0, ctx->stream, ctx->d_part, ctx->d_scal, tol2, 0,
                      coarse_fused(ctx) ? 1 : 0);
   AMRTO_HIP(hipGetLastError());
+  // one reduction per iteration where the recurrences allow it (octree mesh,
+  // Jacobi preconditioner)
+  const bool one = one_reduction && ctx->coarse_k <= 0 && cg1_available(ctx);
+  if (one) {
+    rc = cg1_init(ctx);
+    if (rc) return rc;
+  }
   int it = 0;
   int status = AMRTO_NOT_CONVERGED;
   while (true) {
@@ -567,7 +574,7 @@ static int cg_fp64_run(amrto_ctx* ctx, const double* b, double* x, double rtol, 
     if (done == 2.0) { status = AMRTO_EBREAKDOWN; break; }
     if (it >= max_it) break;
     const int batch = std::min(check_every, max_it - it);
-    rc = enqueue_iters<double>(ctx, v, x, AMRTO_FP64, tol2, it, batch);
+    rc = one ? cg1_enqueue(ctx, x, tol2, it, batch) : enqueue_iters<double>(ctx, v, x, AMRTO_FP64, tol2, it, batch);
     if (rc) return rc;
     it += batch;
   }
@@ -598,13 +605,13 @@ static int true_residual(amrto_ctx* ctx, const double* b, const double* x, doubl
 // current iterate with r = b - A~ x (residual replacement), as long as that
 // keeps paying off (at most 8 restarts, each must halve the true residual).
 static int cg_fp64(amrto_ctx* ctx, const double* b, double* x, double rtol, int max_it, int check_every,
-                   int* iters, int* restarts, double* rel_out) {
+                   bool one_reduction, int* iters, int* restarts, double* rel_out) {
   int total = 0, status = AMRTO_NOT_CONVERGED;
   double best = 1e300;
   *restarts = 0;
   while (true) {
     int it = 0;
-    status = cg_fp64_run(ctx, b, x, rtol, max_it - total, check_every, &it);
+    status = cg_fp64_run(ctx, b, x, rtol, max_it - total, check_every, one_reduction, &it);
     total += it;
     if (status < 0 && status != AMRTO_EBREAKDOWN) return status;
     double rr, bb;
@@ -724,6 +731,7 @@ void amrto_solve_opts_default(amrto_solve_opts* o) {
   o->check_every = 16;
   o->use_coarse = 1;
   o->fallback_fp64 = 1;
+  o->single_reduction = 0;
 }
 
 int amrto_pcg(amrto_ctx* ctx, const double* b, double* u, const amrto_solve_opts* opts_in,
@@ -751,7 +759,7 @@ int amrto_pcg(amrto_ctx* ctx, const double* b, double* u, const amrto_solve_opts
   int iters = 0, outer = 0, status, fell_back = 0;
   double rel = 0.0;
   if (o.inner_prec == AMRTO_FP64) {
-    status = cg_fp64(ctx, b, u, o.rtol, o.max_it, o.check_every, &iters, &outer, &rel);
+    status = cg_fp64(ctx, b, u, o.rtol, o.max_it, o.check_every, o.single_reduction != 0, &iters, &outer, &rel);
     if (status < 0 && status != AMRTO_EBREAKDOWN) return status;
   } else {
     status = cg_mixed(ctx, b, u, o.inner_prec, o.rtol, o.max_it, o.check_every, o.inner_rtol, &iters, &outer, &rel);
@@ -762,7 +770,8 @@ int amrto_pcg(amrto_ctx* ctx, const double* b, double* u, const amrto_solve_opts
         hipLaunchKernelGGL(k_fill<double>, dim3((int)((3L * ctx->n_nodes + 255) / 256)), dim3(256), 0, ctx->stream, u,
                            3L * ctx->n_nodes);
       int it2 = 0, restarts = 0;
-      status = cg_fp64(ctx, b, u, o.rtol, o.max_it - iters, o.check_every, &it2, &restarts, &rel);
+      status = cg_fp64(ctx, b, u, o.rtol, o.max_it - iters, o.check_every, o.single_reduction != 0, &it2, &restarts,
+                       &rel);
       if (status < 0 && status != AMRTO_EBREAKDOWN) return status;
       iters += it2;
       fell_back = 1;

@@ -143,6 +143,32 @@ def test_pcg_octree_matches_oracle(lib):
     assert np.linalg.norm(got - want) <= 1e-8 * np.linalg.norm(want)
 
 
+@pytest.mark.parametrize("single", [True, False])
+def test_pcg_octree_one_and_two_reduction_forms(lib, single):
+    """The one-reduction recurrences (Chronopoulos-Gear) and the two-pass form
+    reach the direct solution; their iteration counts agree closely (same
+    iterates in exact arithmetic), from a zero and from a nonzero start."""
+    p = cases.octree_pair((4, 2, 2), 2, width=0.2)
+    rho = cases.centre_density(p, p.case["field"])
+    ctx = make_ctx(p, rho)
+    s = cases.oracle_system(p, rho)
+    want = p.to_lib_nodes(osys.recover(s, osys.solve_direct(s)))
+    b = torch.empty(3 * p.orc.n_nodes, dtype=torch.float64, device="cuda")
+    ctx.project_rhs(dev(p.lib_mesh.f_load), b)
+    its = {}
+    for form in (single, not single):
+        for start in ("zero", "half"):
+            u = torch.zeros_like(b) if start == "zero" else dev(0.5 * want)
+            st = ctx.pcg(b, u, rtol=1e-12, single_reduction=form)
+            assert st["status"] == "OK" and st["rel_res"] <= 1e-12
+            got = host(u)
+            assert np.linalg.norm(got - want) <= 1e-8 * np.linalg.norm(want)
+            its[form, start] = st["iters"]
+    for start in ("zero", "half"):
+        a, b2 = its[True, start], its[False, start]
+        assert abs(a - b2) <= max(3, 0.05 * b2), its
+
+
 @pytest.mark.parametrize("inner", [1, 2])
 def test_mixed_precision_refinement(pair_rho, inner):
     p, rho = pair_rho
