@@ -93,6 +93,21 @@ __global__ __launch_bounds__(256) void k_cg_update(VT* __restrict__ x, VT* __res
                                                    double* __restrict__ part) {
   if (scal[S_DONE] != 0.0) return;
   __shared__ double sh[8];
+  // the first UPT entries of this thread are requested before the p.q
+  // partials are reduced (alpha is not needed to load them)
+  constexpr int UPT = 4;
+  const long i0 = blockIdx.x * (long)blockDim.x + threadIdx.x, stride = (long)gridDim.x * blockDim.x;
+  VT xv[UPT], pv[UPT], rv[UPT], qv[UPT], dv[UPT];
+#pragma unroll
+  for (int u = 0; u < UPT; ++u) {
+    const long i = i0 + u * stride;
+    const bool in = i < n;
+    xv[u] = in ? x[i] : (VT)0;
+    pv[u] = in ? p[i] : (VT)0;
+    rv[u] = in ? r[i] : (VT)0;
+    qv[u] = in ? q[i] : (VT)0;
+    dv[u] = in ? dinv[i] : (VT)0;
+  }
   const double pq = sum_partials(part_pq, n_pq, sh);
   const double rz = scal[S_RZ0 + (it & 1)];
   if (!(pq > 0.0) || !(pq < 1e300) || !(rz == rz)) {
@@ -101,7 +116,20 @@ __global__ __launch_bounds__(256) void k_cg_update(VT* __restrict__ x, VT* __res
   }
   const VT alpha = (VT)(rz / pq);
   double srz = 0.0, srr = 0.0;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+#pragma unroll
+  for (int u = 0; u < UPT; ++u) {
+    const long i = i0 + u * stride;
+    if (i < n) {
+      x[i] = xv[u] + alpha * pv[u];
+      const VT ri = rv[u] - alpha * qv[u];
+      const VT zi = dv[u] * ri;
+      r[i] = ri;
+      z[i] = zi;
+      srz += (double)ri * (double)zi;
+      srr += (double)ri * (double)ri;
+    }
+  }
+  for (long i = i0 + UPT * stride; i < n; i += stride) {
     x[i] += alpha * p[i];
     const VT ri = r[i] - alpha * q[i];
     const VT zi = dinv[i] * ri;
@@ -277,6 +305,22 @@ __global__ __launch_bounds__(256) void k_cg_update_coarse(VT* __restrict__ x, VT
   __shared__ double acc[COARSE_KMAX];
   __shared__ double red[COARSE_NFMAX * 3][256];
   const int nf = ca.nf, R = ca.R, k = 3 * nf * R;
+  long lo, hi;
+  block_range(n, lo, hi);
+  // the first UPT entries of this thread are requested before the p.q
+  // partials are reduced (alpha is not needed to load them)
+  constexpr int UPT = 2;
+  VT pv0[UPT], qv0[UPT], rv0[UPT], xv0[UPT], dv0[UPT];
+#pragma unroll
+  for (int u = 0; u < UPT; ++u) {
+    const long i = lo + threadIdx.x + u * (long)blockDim.x;
+    const bool in = i < hi;
+    pv0[u] = in ? p[i] : (VT)0;
+    qv0[u] = in ? q[i] : (VT)0;
+    rv0[u] = in ? r[i] : (VT)0;
+    xv0[u] = in ? x[i] : (VT)0;
+    dv0[u] = in ? dinv[i] : (VT)0;
+  }
   const double pq = sum_partials(part_pq, n_pq, sh);
   const double rz = scal[S_RZ0 + (it & 1)];
   if (!(pq > 0.0) || !(pq < 1e300) || !(rz == rz)) {
@@ -286,13 +330,25 @@ __global__ __launch_bounds__(256) void k_cg_update_coarse(VT* __restrict__ x, VT
   for (int j = threadIdx.x; j < k; j += blockDim.x) acc[j] = 0.0;
   __syncthreads();
   const VT alpha = (VT)(rz / pq);
-  long lo, hi;
-  block_range(n, lo, hi);
   ZtAcc a;
   zt_clear(a, -1);
   double srz = 0.0, srr = 0.0;
+  long i = lo + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < UPT; ++u, i += blockDim.x) {
+    if (i < hi) {
+      double fv[COARSE_NFMAX];
+      const int g = coarse_fields(ca, i, n, fv);
+      x[i] = xv0[u] + alpha * pv0[u];
+      const VT rv = rv0[u] - alpha * qv0[u];
+      r[i] = rv;
+      srz += (double)rv * (double)dv0[u] * (double)rv;
+      srr += (double)rv * (double)rv;
+      zt_add(a, acc, fv, nf, R, g, (int)(i % 3), (double)rv);
+    }
+  }
 #pragma unroll 2
-  for (long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+  for (; i < hi; i += blockDim.x) {
     double fv[COARSE_NFMAX];
     const int g = coarse_fields(ca, i, n, fv);
     const VT pi = p[i], qi = q[i], ri = r[i], xi = x[i], di = dinv[i];
