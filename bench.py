@@ -181,7 +181,7 @@ def main():
             ctx.coarse_setup([], 2, 2, 2, affine=True)
         torch.cuda.synchronize()
         setup_ms = (time.perf_counter() - t0) * 1e3
-        st = ctx.pcg(b, u, rtol=1e-8, inner_prec=prec, inner_rtol=1e-2, max_it=50000)
+        st = ctx.pcg(b, u, rtol=1e-8, inner_prec=prec, inner_rtol=0.1, max_it=50000)
         st["ms"] += setup_ms
         st["setup_ms"] = setup_ms
         if name.endswith("+coarse"):
@@ -335,7 +335,7 @@ def c4_simp(torch, binding, synth):
         t0 = time.perf_counter()
         sim = AdaptiveSIMP(case.base, case.max_level, case.fixed, case.load, volfrac=ex["volfrac"],
                            rho_init=ex["rho_init"], rmin=ex["rmin"], rho_solid=ex["rho_solid"], r_amr=ex["r_amr"],
-                           adapt_every=ex["adapt_every"], rtol=1e-8, inner_prec=prec, inner_rtol=1e-2)
+                           adapt_every=ex["adapt_every"], rtol=1e-8, inner_prec=prec, inner_rtol=0.1)
         ws = LearnedWarmStart(case.dims, cell=2, hidden=8, layers=3, epochs=100, seed=ex["net_seed"],
                               regions=(2, 2, 2)) if mode else None
         recs, train_ms = [], 0.0

@@ -152,7 +152,8 @@ typedef struct {
                          FP64 reliable updates (FP32 vectors, FP32/BF16 operator) */
   double inner_rtol;  /* mixed precision: factor by which the FP32 recurrence
                          residual falls between two FP64 reliable updates
-                         (default 1e-2) */
+                         (default 0.1; a recurrence that levels off above its
+                         target for 2048 iterations is updated anyway) */
   int32_t check_every;/* iterations between host convergence checks (default 16) */
   int32_t use_coarse; /* 1 (default): add the coarse correction set by
                          amrto_coarse_setup, when one is set; 0: Jacobi only */

@@ -15,7 +15,7 @@ from . import binding
 class ComplianceProblem:
     """A mesh, its load and solver settings on one device context."""
 
-    def __init__(self, mesh: "binding.MeshArrays", rtol=1e-10, inner_prec=binding.FP64, inner_rtol=1e-2,
+    def __init__(self, mesh: "binding.MeshArrays", rtol=1e-10, inner_prec=binding.FP64, inner_rtol=0.1,
                  max_it=100000, device=0):
         self.ctx = binding.Context(device)
         self.ctx.upload_mesh(mesh)

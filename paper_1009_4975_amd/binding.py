@@ -361,7 +361,7 @@ class Context:
     def diag(self, out):
         self._chk(self.lib.amrto_get_diag(self.h, _dev(out, self.torch.float64)))
 
-    def pcg(self, b, u, rtol=1e-8, max_it=20000, inner_prec=FP64, inner_rtol=1e-3, check_every=16,
+    def pcg(self, b, u, rtol=1e-8, max_it=20000, inner_prec=FP64, inner_rtol=0.1, check_every=16,
             use_coarse=True, fallback_fp64=True, single_reduction=False, allow_not_converged=False):
         o = SolveOpts()
         self.lib.amrto_solve_opts_default(C.byref(o))

@@ -561,6 +561,9 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
       if (COARSE) gv[r] = a.geo[gn[r]];
     }
   }
+  VT cep[EPT];
+#pragma unroll
+  for (int r = 0; r < EPT; ++r) cep[r] = coef[eel[r]];
   double beta = 0.0;
   if (FUSED) {
     if (!cg_prologue(cg, beta, sh)) return;
@@ -570,9 +573,6 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
     return;
   }
   const VT vbeta = (VT)beta;
-  VT cep[EPT];
-#pragma unroll
-  for (int r = 0; r < EPT; ++r) cep[r] = coef[eel[r]];
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
     const int t = tid + 256 * r;

@@ -160,6 +160,9 @@ __global__ __launch_bounds__(256) void k_cg1_chunks(Cg1Vecs<VT> v, ChunkArgs ca,
       }
     }
   }
+  VT cep[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) cep[q] = v.coef[eel[q]];
   // scalars of iteration j from the partials of the previous pass
   if (g.scal[S_DONE] != 0.0) return;
   double gam = 0.0, del = 0.0, rho = 0.0;
@@ -207,9 +210,6 @@ __global__ __launch_bounds__(256) void k_cg1_chunks(Cg1Vecs<VT> v, ChunkArgs ca,
     return;
   }
   const VT va = (VT)alpha, vb = (VT)beta;
-  VT cep[EPT];
-#pragma unroll
-  for (int q = 0; q < EPT; ++q) cep[q] = v.coef[eel[q]];
   // s_j, r_{j+1} and u_{j+1} = M r_{j+1} on every regular table node
 #pragma unroll
   for (int q = 0; q < NPT; ++q) {

@@ -25,7 +25,7 @@ from .binding import FILTER_SENSITIVITY, FP64
 class AdaptiveSIMP:
     def __init__(self, base, max_level, fixed, load, volfrac=0.25, rho_init=0.25, rmin=1.5, move=0.2, eta=0.5,
                  rho_min=1e-3, rho_solid=0.5, r_amr=1.5, adapt_every=5, rtol=1e-8, inner_prec=FP64,
-                 inner_rtol=1e-2, max_it=100000, device=0, metrics_path=None):
+                 inner_rtol=0.1, max_it=100000, device=0, metrics_path=None):
         self.base, self.max_level = tuple(int(b) for b in base), int(max_level)
         self.tree = binding.Octree(base, max_level)
         self.ctx = binding.Context(device)
