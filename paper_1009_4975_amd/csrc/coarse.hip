@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void k_gram_column(const double* __restrict__ 
   __shared__ double sh[8];
   const int i = blockIdx.x;
   double v = 0.0;
-  for (int b = threadIdx.x; b < RED_BLOCKS; b += blockDim.x) v += part[(long)b * k + i];
+  for (int b = threadIdx.x; b < RED_BLOCKS; b += blockDim.x) v += part[(long)i * RED_BLOCKS + b];
   v = block_sum(v, sh);
   if (threadIdx.x == 0) E[(long)i * k + j] = v;
 }

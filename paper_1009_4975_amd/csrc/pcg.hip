@@ -261,9 +261,10 @@ __device__ __forceinline__ void block_range(long n, long& lo, long& hi) {
   hi = lo + per < n ? lo + per : n;
 }
 
-// Write this block's Z^T v partials (block-major: part[block k + j]).
+// Write this block's Z^T v partials (column-major: part[j nblk + block], so
+// the column sums read them coalesced).
 __device__ __forceinline__ void zt_store(const double* acc, int k, double* __restrict__ part) {
-  for (int j = threadIdx.x; j < k; j += blockDim.x) part[(long)blockIdx.x * k + j] = acc[j];
+  for (int j = threadIdx.x; j < k; j += blockDim.x) part[(long)j * gridDim.x + blockIdx.x] = acc[j];
 }
 
 template <typename VT>
@@ -369,7 +370,7 @@ __global__ __launch_bounds__(256) void k_cg_update_coarse(VT* __restrict__ x, VT
   }
 }
 
-// ct[j] = sum_b part[b k + j]: one block per coarse column, fixed-tree sum
+// ct[j] = sum_b part[j nblk + b]: one block per coarse column, fixed-tree sum
 // (deterministic).
 __global__ __launch_bounds__(256) void k_coarse_sum(const double* __restrict__ part, int k, int nblk,
                                                     double* __restrict__ ct, const double* __restrict__ stop) {
@@ -377,33 +378,35 @@ __global__ __launch_bounds__(256) void k_coarse_sum(const double* __restrict__ p
   __shared__ double sh[8];
   const int j = blockIdx.x;
   double v = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) v += part[(long)b * k + j];
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) v += part[(long)j * nblk + b];
   v = block_sum(v, sh);
   if (threadIdx.x == 0) ct[j] = v;
 }
 
-// cz = E^-1 ct in one block: thread j walks column j of the symmetric E^-1
-// (row i of E^-1 is read coalesced across threads); ct^T cz is summed in
-// column order (deterministic).  (Copying E^-1 into LDS first measured slower.)
-__global__ __launch_bounds__(COARSE_KMAX) void k_coarse_cz(const double* __restrict__ ct_g, int k,
-                                                   const double* __restrict__ Einv, double* __restrict__ cz,
-                                                   double* __restrict__ ctz, const double* __restrict__ stop) {
+// cz = E^-1 ct in one block of G x kp threads: thread (g, j) sums the rows
+// i = g, g + G, ... of column j of the symmetric E^-1 (each row read coalesced
+// across j), so all of E^-1 is requested at once; the G group sums are added
+// in group order and ct^T cz in column order (deterministic).
+__global__ __launch_bounds__(1024) void k_coarse_cz(const double* __restrict__ ct_g, int k,
+                                                    const double* __restrict__ Einv, double* __restrict__ cz,
+                                                    double* __restrict__ ctz, const double* __restrict__ stop) {
   if (stop && *stop != 0.0) return;
-  __shared__ double ct[COARSE_KMAX], prod[COARSE_KMAX];
+  __shared__ double ct[COARSE_KMAX], prod[COARSE_KMAX], grp[1024];
+  const int kp = ((k + 63) / 64) * 64, G = (int)blockDim.x / kp;
   for (int i = threadIdx.x; i < k; i += blockDim.x) ct[i] = ct_g[i];
   __syncthreads();
-  const int j = threadIdx.x;
-  if (j < k) {
-    double s0 = 0.0, s1 = 0.0;
-    int i = 0;
-#pragma unroll 4
-    for (; i + 1 < k; i += 2) {
-      s0 += Einv[(long)i * k + j] * ct[i];
-      s1 += Einv[(long)(i + 1) * k + j] * ct[i + 1];
-    }
-    if (i < k) s0 += Einv[(long)i * k + j] * ct[i];
-    cz[j] = s0 + s1;
-    prod[j] = ct[j] * (s0 + s1);
+  const int j = threadIdx.x % kp, g = threadIdx.x / kp;
+  if (j < k && g < G) {
+    double s = 0.0;
+    for (int i = g; i < k; i += G) s += Einv[(long)i * k + j] * ct[i];
+    grp[g * kp + j] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < k) {
+    double s = 0.0;
+    for (int q = 0; q < G; ++q) s += grp[q * kp + threadIdx.x];
+    cz[threadIdx.x] = s;
+    prod[threadIdx.x] = ct[threadIdx.x] * s;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -503,8 +506,12 @@ static CoarseArgs coarse_args(const amrto_ctx* ctx) {
   return a;
 }
 
-// one thread per coarse column, whole wavefronts
-static int cz_threads(const amrto_ctx* ctx) { return ((ctx->coarse_k + 63) / 64) * 64; }
+// G groups of kp threads (kp = columns rounded to whole wavefronts), G as
+// large as 1024 threads allow
+static int cz_threads(const amrto_ctx* ctx) {
+  const int kp = ((ctx->coarse_k + 63) / 64) * 64;
+  return (1024 / kp) * kp;
+}
 
 // The affine coarse space on an octree mesh is folded into the operator pass
 // (z = D^-1 r + Z cz formed while staging; r.z = r^T D^-1 r + ct^T cz).
