@@ -12,6 +12,7 @@
 // the same decision without a finalize launch, and a converged or broken
 // solve makes the rest of an enqueued batch return at once.
 #include <chrono>
+#include <cstdio>
 #include <cmath>
 #include <string>
 
@@ -871,10 +872,15 @@ int amrto_pcg(amrto_ctx* ctx, const double* b, double* u, const amrto_solve_opts
     stats->fell_back = fell_back;
   }
   if (status == AMRTO_EBREAKDOWN) return ctx->fail(AMRTO_EBREAKDOWN, "amrto_pcg: breakdown (p^T A p <= 0 or non-finite)");
-  if (status == AMRTO_NOT_CONVERGED)
-    ctx->err = iters >= o.max_it ? "amrto_pcg: iteration cap reached"
-                                 : "amrto_pcg: true residual " + std::to_string(rel) +
-                                       " stagnated above rtol (FP64 attainable accuracy)";
+  if (status == AMRTO_NOT_CONVERGED) {
+    char msg[160];
+    if (iters >= o.max_it)
+      std::snprintf(msg, sizeof msg, "amrto_pcg: iteration cap reached (relative residual %.3e)", rel);
+    else
+      std::snprintf(msg, sizeof msg,
+                    "amrto_pcg: true relative residual %.3e stagnated above rtol (FP64 attainable accuracy)", rel);
+    ctx->err = msg;
+  }
   return status;
 }
 

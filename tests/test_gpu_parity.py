@@ -63,6 +63,51 @@ def test_apply_uniform_fp64(lib, dims):
     assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
 
 
+# seeded random boxes for the brick kernel's tile, halo and z-chunk edges:
+# thin slabs (one element across), exact multiples of the 14-column tile,
+# one past a multiple, and chunk counts that leave a short last chunk
+RANDOM_DIMS = [(1, 29, 3), (29, 1, 22), (14, 13, 41), (15, 29, 1), (2, 2, 21), (37, 5, 9)]
+
+
+@pytest.mark.parametrize("dims", RANDOM_DIMS)
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 5e-6)])
+def test_apply_uniform_edge_shapes(lib, dims, prec, tol):
+    p = cases.uniform_pair(dims)
+    rng = np.random.default_rng(sum(dims))
+    rho = rng.uniform(0.01, 1.0, p.orc.n_elems)
+    ctx = make_ctx(p, rho)
+    x = rng.uniform(-1, 1, 3 * p.orc.n_nodes)
+    dt = torch.float64 if prec == 0 else torch.float32
+    y = torch.empty(3 * p.orc.n_nodes, dtype=dt, device="cuda")
+    ctx.apply(dev(x, dt), y, prec=prec)
+    xr = x if prec == 0 else x.astype(np.float32).astype(np.float64)
+    want = osys.apply_constrained(p.orc, osys.elem_coeff(p.orc, rho), p.fixed, xr)
+    assert np.max(np.abs(host(y) - want)) <= tol * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("dims", [(29, 1, 22), (1, 17, 2), (14, 13, 21)])
+def test_pcg_uniform_edge_shapes_match_direct(lib, dims):
+    """The fused CG pass of the brick kernel (p = z + beta p staged, q = A p,
+    partial p.q) on shapes that exercise every tile and chunk edge."""
+    p = cases.uniform_pair(dims, bc="bridge")
+    rho = np.random.default_rng(3).uniform(0.05, 1.0, p.orc.n_elems)
+    ctx = make_ctx(p, rho)
+    s = cases.oracle_system(p, rho)
+    want = osys.recover(s, osys.solve_direct(s))
+    b = torch.empty(3 * p.orc.n_nodes, dtype=torch.float64, device="cuda")
+    ctx.project_rhs(dev(p.lib_mesh.f_load), b)
+    u = torch.zeros_like(b)
+    # 1e-10: a slab one element thick bends like a plate and its FP64 floor
+    # lies above 1e-12
+    st = ctx.pcg(b, u, rtol=1e-10, max_it=50000)
+    assert st["status"] == "OK"
+    got = host(u)
+    free = np.where(s.free, got, 0.0)
+    r = s.b - s.A @ free
+    assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(s.b)
+    assert np.linalg.norm(got - want) <= 1e-5 * np.linalg.norm(want)
+
+
 @pytest.mark.parametrize("prec,tol", [(1, 5e-6), (2, 1e-2)])
 def test_apply_reduced_precision(pair_rho, prec, tol):
     p, rho = pair_rho
