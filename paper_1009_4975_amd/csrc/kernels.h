@@ -176,10 +176,13 @@ __device__ __forceinline__ void brick_blocks(const T (&k)[8], const T (&w)[3][8]
 // node layers per workgroup (the march is unrolled for exactly this many):
 // FP64 runs two workgroups per CU and gains from longer chunks (fewer
 // repeated layers); FP32 runs four and from more workgroups
+#ifndef AMRTO_BRICK_Z64
+#define AMRTO_BRICK_Z64 20
+#endif
 template <typename VT>
 struct BrickZ { static constexpr int layers = 10; };
 template <>
-struct BrickZ<double> { static constexpr int layers = 20; };
+struct BrickZ<double> { static constexpr int layers = AMRTO_BRICK_Z64; };
 #ifndef AMRTO_BRICK_PD
 #define AMRTO_BRICK_PD 2
 #endif
