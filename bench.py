@@ -110,7 +110,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--solver", choices=["fp64", "fp32", "bf16", "fp64+coarse", "fp32+coarse", "best"],
+    ap.add_argument("--solver", choices=["fp64", "fp32", "bf16", "fp64+coarse", "fp32+coarse", "fp64+block3",
+                                         "fp32+block3", "best"],
                     default="best")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-c3", action="store_true", help="skip the uniform 192x96x96 apply measurement")
@@ -173,7 +174,9 @@ def main():
 
     def solve(name):
         """One solve from zero; with "+coarse" the affine coarse space (2x2x2
-        regions, 96 columns) is built first and its set-up counts in ms."""
+        regions, 96 columns) is built first and its set-up counts in ms; with
+        "+block3" the 3x3 node-block Jacobi preconditioner (its inverse blocks
+        are formed on the first solve after a density change, inside ms)."""
         u.zero_()
         prec = precs[name.split("+")[0]]
         t0 = time.perf_counter()
@@ -181,7 +184,8 @@ def main():
             ctx.coarse_setup([], 2, 2, 2, affine=True)
         torch.cuda.synchronize()
         setup_ms = (time.perf_counter() - t0) * 1e3
-        st = ctx.pcg(b, u, rtol=1e-8, inner_prec=prec, inner_rtol=0.1, max_it=50000)
+        pc = binding.BLOCK3 if name.endswith("+block3") else binding.JACOBI
+        st = ctx.pcg(b, u, rtol=1e-8, inner_prec=prec, inner_rtol=0.1, max_it=50000, precond=pc)
         st["ms"] += setup_ms
         st["setup_ms"] = setup_ms
         if name.endswith("+coarse"):
@@ -191,7 +195,7 @@ def main():
     # --- solver variants (untimed survey, picks the fastest that reaches 1e-8)
     variants = {}
     if not args.profile_only:
-        for name in ("fp64", "fp32", "bf16", "fp64+coarse", "fp32+coarse"):
+        for name in ("fp64", "fp32", "bf16", "fp64+coarse", "fp32+coarse", "fp64+block3", "fp32+block3"):
             solve(name)
             runs = [solve(name) for _ in range(2)]
             ms = min(r["ms"] for r in runs)
@@ -319,9 +323,10 @@ def c4_simp(torch, binding, synth):
     """The adaptive bridge: 32x16x16 base leaves, 2 refinement levels (finest
     128x64x64), volume fraction 0.25, filter radius 1.5, OC, adapt every 5
     iterations, 50 iterations.  Variants differ only in how iterations 11-50
-    solve: plain (previous solution as the start, Jacobi-PCG), the affine
-    coarse space, and the learned start (network trained on iterations 1-10)
-    with the coarse space; each in FP64 and with FP32 inner solves."""
+    solve: plain (previous solution as the start, Jacobi-PCG), plain with the
+    3x3 node-block Jacobi preconditioner, the affine coarse space, and the
+    learned start (network trained on iterations 1-10) with the coarse space;
+    each in FP64 and with FP32 inner solves."""
     from paper_1009_4975_amd.learned import LearnedWarmStart
     from paper_1009_4975_amd.simp import AdaptiveSIMP
     case = synth.c4()
@@ -329,13 +334,17 @@ def c4_simp(torch, binding, synth):
     n_train = ex["train_iters"]
     out = {}
     for name, prec, mode in (("plain_fp64", binding.FP64, None), ("plain_fp32", binding.FP32, None),
+                             ("block3_fp64", binding.FP64, "block3"), ("block3_fp32", binding.FP32, "block3"),
                              ("coarse_fp64", binding.FP64, "coarse"), ("coarse_fp32", binding.FP32, "coarse"),
                              ("learned_coarse_fp64", binding.FP64, "learned"),
                              ("learned_coarse_fp32", binding.FP32, "learned")):
         t0 = time.perf_counter()
         sim = AdaptiveSIMP(case.base, case.max_level, case.fixed, case.load, volfrac=ex["volfrac"],
                            rho_init=ex["rho_init"], rmin=ex["rmin"], rho_solid=ex["rho_solid"], r_amr=ex["r_amr"],
-                           adapt_every=ex["adapt_every"], rtol=1e-8, inner_prec=prec, inner_rtol=0.1)
+                           adapt_every=ex["adapt_every"], rtol=1e-8, inner_prec=prec, inner_rtol=0.1,
+                           precond=binding.BLOCK3 if mode == "block3" else binding.JACOBI)
+        if mode == "block3":
+            mode = None  # a plain run apart from the preconditioner
         ws = LearnedWarmStart(case.dims, cell=2, hidden=8, layers=3, epochs=100, seed=ex["net_seed"],
                               regions=(2, 2, 2)) if mode else None
         recs, train_ms = [], 0.0

@@ -54,7 +54,10 @@ enum {
   AMRTO_BF16 = 2  /* FP32 vectors, BF16 operands with FP32 accumulation */
 };
 
-enum { AMRTO_PRECOND_JACOBI = 0 };
+/* Preconditioners of amrto_pcg: JACOBI = the exact diagonal of A~ (the
+ * diagonal rescaling of Sec. 5); BLOCK3 = the 3x3 node blocks of A~ (all
+ * components of a node), solves without a coarse space. */
+enum { AMRTO_PRECOND_JACOBI = 0, AMRTO_PRECOND_BLOCK3 = 1 };
 enum { AMRTO_FILTER_SENSITIVITY = 0, AMRTO_FILTER_DENSITY = 1 };
 
 typedef struct amrto_ctx amrto_ctx;
@@ -142,12 +145,19 @@ int amrto_recover(amrto_ctx* ctx, const double* ut_dev, double* u_dev);
 /* Diagonal of A~ (as used by the Jacobi preconditioner) into diag_dev[3n]. */
 int amrto_get_diag(amrto_ctx* ctx, double* diag_dev);
 
+/* The 3x3 node blocks of A~ (as used by the block-Jacobi preconditioner,
+ * before inversion) into blocks_dev[9n], row-major per node: supported
+ * components carry identity rows and columns, hanging nodes the identity.
+ * Errors: ESTATE (no density), EINVAL. */
+int amrto_get_block_diag(amrto_ctx* ctx, double* blocks_dev);
+
 /* ------------------------------------------------------------------ solve */
 
 typedef struct {
   double rtol;        /* stop when ||b - A~ u||_2 <= rtol ||b||_2 (default 1e-8) */
   int32_t max_it;     /* iteration cap of the (inner) CG (default 20000) */
-  int32_t precond;    /* AMRTO_PRECOND_JACOBI */
+  int32_t precond;    /* AMRTO_PRECOND_JACOBI (default) or AMRTO_PRECOND_BLOCK3
+                         (any precision, no coarse space, two-pass form) */
   int32_t inner_prec; /* AMRTO_FP64: plain PCG; FP32/BF16: mixed precision with
                          FP64 reliable updates (FP32 vectors, FP32/BF16 operator) */
   double inner_rtol;  /* mixed precision: factor by which the FP32 recurrence

@@ -18,6 +18,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libamrto.so")
 
 FP64, FP32, BF16 = 0, 1, 2
+JACOBI, BLOCK3 = 0, 1  # preconditioners of Context.pcg
 FILTER_SENSITIVITY, FILTER_DENSITY = 0, 1
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EHIP", -3: "ENOMEM", -4: "EBREAKDOWN", -5: "ESTATE"}
 
@@ -66,6 +67,7 @@ _SIGS = {
     "amrto_project_rhs": (C.c_int, [_p, _p, _p]),
     "amrto_recover": (C.c_int, [_p, _p, _p]),
     "amrto_get_diag": (C.c_int, [_p, _p]),
+    "amrto_get_block_diag": (C.c_int, [_p, _p]),
     "amrto_solve_opts_default": (None, [C.POINTER(SolveOpts)]),
     "amrto_pcg": (C.c_int, [_p, _p, _p, C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
     "amrto_compliance": (C.c_int, [_p, _p, _p, _p, C.POINTER(C.c_double), _p]),
@@ -361,11 +363,17 @@ class Context:
     def diag(self, out):
         self._chk(self.lib.amrto_get_diag(self.h, _dev(out, self.torch.float64)))
 
+    def block_diag(self, out):
+        """3x3 node blocks of A~ into out (9 n_nodes float64, row-major per node)."""
+        self._chk(self.lib.amrto_get_block_diag(self.h, _dev(out, self.torch.float64)))
+
     def pcg(self, b, u, rtol=1e-8, max_it=20000, inner_prec=FP64, inner_rtol=0.1, check_every=16,
-            use_coarse=True, fallback_fp64=True, single_reduction=False, allow_not_converged=False):
+            use_coarse=True, fallback_fp64=True, single_reduction=False, precond=JACOBI,
+            allow_not_converged=False):
         o = SolveOpts()
         self.lib.amrto_solve_opts_default(C.byref(o))
         o.rtol, o.max_it, o.inner_prec, o.inner_rtol = rtol, max_it, inner_prec, inner_rtol
+        o.precond = int(precond)
         o.check_every, o.use_coarse = check_every, int(bool(use_coarse))
         o.fallback_fp64 = int(bool(fallback_fp64))
         o.single_reduction = int(bool(single_reduction))

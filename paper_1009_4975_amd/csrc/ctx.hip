@@ -92,6 +92,8 @@ static void free_mesh(amrto_ctx* c) {
   dfree(c->d_partpq);
   dfree(c->d_cg1_r2); dfree(c->d_cg1_w); dfree(c->d_cg1_w2); dfree(c->d_cg1_s); dfree(c->d_cg1_s2);
   dfree(c->d_cg1_part);
+  dfree(c->d_binv); dfree(c->d_binv_f);
+  c->binv_valid = false;
   c->n_partpq = 0;
   dfree(c->f_b); dfree(c->f_x); dfree(c->f_r); dfree(c->f_z); dfree(c->f_p); dfree(c->f_q);
   dfree(c->d_cf); dfree(c->d_region); dfree(c->d_cpart); dfree(c->d_cinv); dfree(c->d_cz); dfree(c->d_ct); dfree(c->d_cmask); dfree(c->d_cgeo);
@@ -299,6 +301,7 @@ int amrto_upload_mesh(amrto_ctx* ctx, const amrto_mesh* m) {
   AMRTO_HIP(dalloc(ctx->f_p2, n3));
   ctx->n_partpq = apply_blocks(ctx);
   AMRTO_HIP(dalloc(ctx->d_partpq, ctx->n_partpq));
+  AMRTO_HIP(dalloc(ctx->d_binv, 6L * m->n_nodes)); AMRTO_HIP(dalloc(ctx->d_binv_f, 6L * m->n_nodes));
   if (!uni) {
     AMRTO_HIP(dalloc(ctx->d_cg1_r2, n3)); AMRTO_HIP(dalloc(ctx->d_cg1_w, n3)); AMRTO_HIP(dalloc(ctx->d_cg1_w2, n3));
     AMRTO_HIP(dalloc(ctx->d_cg1_s, n3)); AMRTO_HIP(dalloc(ctx->d_cg1_s2, n3));
@@ -321,6 +324,7 @@ int amrto_mesh_info(const amrto_ctx* ctx, int32_t* n_nodes, int32_t* n_elems, in
 int amrto_set_density(amrto_ctx* ctx, const double* rho) {
   if (!ctx) return AMRTO_EINVAL;
   if (!ctx->has_mesh) return ctx->fail(AMRTO_ESTATE, "amrto_set_density: no mesh uploaded");
+  ctx->binv_valid = false;
   if (!rho) return ctx->fail(AMRTO_EINVAL, "amrto_set_density: rho is NULL");
   AMRTO_HIP(hipSetDevice(ctx->device));
   ctx->coarse_k = 0;  // Z^T A~ Z depends on the density

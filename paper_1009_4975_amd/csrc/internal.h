@@ -162,6 +162,11 @@ struct amrto_ctx {
   // the gamma / delta / r.r partials of two passes
   double* d_cg1_r2 = nullptr; double* d_cg1_w = nullptr; double* d_cg1_w2 = nullptr;
   double* d_cg1_s = nullptr; double* d_cg1_s2 = nullptr; double* d_cg1_part = nullptr;
+  // block-Jacobi: inverse 3x3 node blocks (6 entries per node), computed on
+  // the first block-Jacobi solve after a density change
+  double* d_binv = nullptr;
+  float* d_binv_f = nullptr;
+  bool binv_valid = false;
   int n_partpq = 0;
   float* f_b = nullptr; float* f_x = nullptr; float* f_r = nullptr; float* f_z = nullptr; float* f_p = nullptr; float* f_q = nullptr;
   double* d_part = nullptr;   // reduction partials (4 x RED_BLOCKS)
@@ -210,6 +215,11 @@ int mask_vector_n(amrto_ctx* ctx, double* x, int count);
 int launch_zt(amrto_ctx* ctx, const double* v);
 int apply_stop(amrto_ctx* ctx, const void* x, void* y, int prec, const double* stop);
 int apply_fused(amrto_ctx* ctx, const void* z, const void* pold, void* pnew, void* q, int prec, const CgArgs& cg);
+int block3_setup(amrto_ctx* ctx);
+template <typename VT, typename BT>
+int block3_init(amrto_ctx* ctx, const BT* b, const BT* q, VT* r, VT* z);
+template <typename VT>
+int block3_update(amrto_ctx* ctx, VT* x, VT* r, const VT* p, const VT* q, VT* z, int it);
 bool cg1_available(const amrto_ctx* ctx);
 int cg1_parts(const amrto_ctx* ctx);
 int cg1_init(amrto_ctx* ctx);

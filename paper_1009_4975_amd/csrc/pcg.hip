@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cmath>
 #include <string>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -572,7 +573,8 @@ static int read_scalars(amrto_ctx* ctx) {
 
 // enqueue CG iterations [it0, it0 + count) on the current r, z (and p from it0 - 1)
 template <typename VT>
-static int enqueue_iters(amrto_ctx* ctx, const Vecs<VT>& v, VT* x, int prec, double tol2, int it0, int count) {
+static int enqueue_iters(amrto_ctx* ctx, const Vecs<VT>& v, VT* x, int prec, double tol2, int it0, int count,
+                         bool block3 = false) {
   const long n3 = 3L * ctx->n_nodes;
   const bool fused = coarse_fused(ctx);
   for (int it = it0; it < it0 + count; ++it) {
@@ -593,6 +595,9 @@ static int enqueue_iters(amrto_ctx* ctx, const Vecs<VT>& v, VT* x, int prec, dou
       if (!fused)
         hipLaunchKernelGGL(k_coarse_z<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, v.r, v.z, v.dinv, n3,
                            ctx->d_cz, coarse_args(ctx), ctx->d_part, ctx->d_scal + S_DONE);
+    } else if (block3) {
+      rc = block3_update<VT>(ctx, x, v.r, pnew, v.q, v.z, it);
+      if (rc) return rc;
     } else {
       hipLaunchKernelGGL(k_cg_update<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew, v.q, v.dinv,
                          v.z, n3, ctx->d_partpq, ctx->n_partpq, ctx->d_scal, it, ctx->d_part);
@@ -604,7 +609,7 @@ static int enqueue_iters(amrto_ctx* ctx, const Vecs<VT>& v, VT* x, int prec, dou
 
 // Plain FP64 Jacobi-PCG from x (masked).  *iters = iterations performed.
 static int cg_fp64_run(amrto_ctx* ctx, const double* b, double* x, double rtol, int max_it, int check_every,
-                       bool one_reduction, int* iters) {
+                       bool one_reduction, bool block3, int* iters) {
   const long n3 = 3L * ctx->n_nodes;
   const int g1 = (int)((n3 + 255) / 256);
   Vecs<double> v = vecs64(ctx);
@@ -615,15 +620,21 @@ static int cg_fp64_run(amrto_ctx* ctx, const double* b, double* x, double rtol, 
                        ctx->d_hang_node, ctx->n_hang);
   int rc = apply_stop(ctx, x, v.q, AMRTO_FP64, nullptr);
   if (rc) return rc;
-  hipLaunchKernelGGL((k_init<double, double>), dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, b, v.q, v.r, v.z, v.dinv,
-                     n3, ctx->d_part);
+  if (block3) {
+    rc = block3_setup(ctx);
+    if (!rc) rc = block3_init<double, double>(ctx, b, v.q, v.r, v.z);
+    if (rc) return rc;
+  } else {
+    hipLaunchKernelGGL((k_init<double, double>), dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, b, v.q, v.r, v.z,
+                       v.dinv, n3, ctx->d_part);
+  }
   coarse_init<double>(ctx, v);
   hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(256), 0, ctx->stream, ctx->d_part, ctx->d_scal, tol2, 0,
                      coarse_fused(ctx) ? 1 : 0);
   AMRTO_HIP(hipGetLastError());
   // one reduction per iteration where the recurrences allow it (octree mesh,
   // Jacobi preconditioner)
-  const bool one = one_reduction && ctx->coarse_k <= 0 && cg1_available(ctx);
+  const bool one = one_reduction && !block3 && ctx->coarse_k <= 0 && cg1_available(ctx);
   if (one) {
     rc = cg1_init(ctx);
     if (rc) return rc;
@@ -638,7 +649,8 @@ static int cg_fp64_run(amrto_ctx* ctx, const double* b, double* x, double rtol, 
     if (done == 2.0) { status = AMRTO_EBREAKDOWN; break; }
     if (it >= max_it) break;
     const int batch = std::min(check_every, max_it - it);
-    rc = one ? cg1_enqueue(ctx, x, tol2, it, batch) : enqueue_iters<double>(ctx, v, x, AMRTO_FP64, tol2, it, batch);
+    rc = one ? cg1_enqueue(ctx, x, tol2, it, batch)
+             : enqueue_iters<double>(ctx, v, x, AMRTO_FP64, tol2, it, batch, block3);
     if (rc) return rc;
     it += batch;
   }
@@ -669,13 +681,13 @@ static int true_residual(amrto_ctx* ctx, const double* b, const double* x, doubl
 // current iterate with r = b - A~ x (residual replacement), as long as that
 // keeps paying off (at most 8 restarts, each must halve the true residual).
 static int cg_fp64(amrto_ctx* ctx, const double* b, double* x, double rtol, int max_it, int check_every,
-                   bool one_reduction, int* iters, int* restarts, double* rel_out) {
+                   bool one_reduction, bool block3, int* iters, int* restarts, double* rel_out) {
   int total = 0, status = AMRTO_NOT_CONVERGED;
   double best = 1e300;
   *restarts = 0;
   while (true) {
     int it = 0;
-    status = cg_fp64_run(ctx, b, x, rtol, max_it - total, check_every, one_reduction, &it);
+    status = cg_fp64_run(ctx, b, x, rtol, max_it - total, check_every, one_reduction, block3, &it);
     total += it;
     if (status < 0 && status != AMRTO_EBREAKDOWN) return status;
     double rr, bb;
@@ -702,7 +714,7 @@ static int cg_fp64(amrto_ctx* ctx, const double* b, double* x, double rtol, int 
 // correction is added to the FP64 iterate, the true FP64 residual replaces the
 // recurrence residual and the search continues with the same direction p.
 static int cg_mixed(amrto_ctx* ctx, const double* b, double* x, int prec, double rtol, int max_it,
-                    int check_every, double delta, int* iters, int* updates, double* rel_out) {
+                    int check_every, double delta, bool block3, int* iters, int* updates, double* rel_out) {
   const long n3 = 3L * ctx->n_nodes;
   const int g1 = (int)((n3 + 255) / 256);
   Vecs<float> v = vecs32(ctx);
@@ -733,9 +745,14 @@ static int cg_mixed(amrto_ctx* ctx, const double* b, double* x, int prec, double
     if (rr <= tol2 * bb) { status = AMRTO_OK; break; }
     if (it >= max_it) break;
     if (restart_scalars) {
-      // r32 = r64, z32 = D^-1 r32; r.z, r.r partials for the next operator pass
-      hipLaunchKernelGGL((k_init<float, double>), dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, ctx->d_r,
-                         (const double*)nullptr, v.r, v.z, v.dinv, n3, ctx->d_part);
+      // r32 = r64, z32 = M^-1 r32; r.z, r.r partials for the next operator pass
+      if (block3) {
+        rc = block3_init<float, double>(ctx, ctx->d_r, (const double*)nullptr, v.r, v.z);
+        if (rc) return rc;
+      } else {
+        hipLaunchKernelGGL((k_init<float, double>), dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, ctx->d_r,
+                           (const double*)nullptr, v.r, v.z, v.dinv, n3, ctx->d_part);
+      }
       coarse_init<float>(ctx, v);
       // the recurrence measures its residual against b.b
       hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, ctx->stream, ctx->d_scal, (int)S_BB, bb);
@@ -751,7 +768,7 @@ static int cg_mixed(amrto_ctx* ctx, const double* b, double* x, int prec, double
     const int batch = std::min(check_every, max_it - it);
     // the recurrence stops itself when its own residual reaches delta^2 rr_ref
     const double tol_in = std::max(std::sqrt(delta * delta * rr_ref / bb), 0.5 * rtol);
-    rc = enqueue_iters<float>(ctx, v, d, prec, tol_in * tol_in, it, batch);
+    rc = enqueue_iters<float>(ctx, v, d, prec, tol_in * tol_in, it, batch, block3);
     if (rc) return rc;
     rc = read_scalars(ctx);
     if (rc) return rc;
@@ -830,7 +847,11 @@ int amrto_pcg(amrto_ctx* ctx, const double* b, double* u, const amrto_solve_opts
     return ctx->fail(AMRTO_EINVAL, "amrto_pcg: bad options");
   if (o.inner_prec != AMRTO_FP64 && o.inner_prec != AMRTO_FP32 && o.inner_prec != AMRTO_BF16)
     return ctx->fail(AMRTO_EINVAL, "amrto_pcg: unknown inner precision");
-  if (o.precond != AMRTO_PRECOND_JACOBI) return ctx->fail(AMRTO_EINVAL, "amrto_pcg: unknown preconditioner");
+  if (o.precond != AMRTO_PRECOND_JACOBI && o.precond != AMRTO_PRECOND_BLOCK3)
+    return ctx->fail(AMRTO_EINVAL, "amrto_pcg: unknown preconditioner");
+  const bool block3 = o.precond == AMRTO_PRECOND_BLOCK3;
+  if (block3 && o.use_coarse && ctx->coarse_k > 0)
+    return ctx->fail(AMRTO_EINVAL, "amrto_pcg: block-Jacobi takes solves without a coarse space");
   AMRTO_HIP(hipSetDevice(ctx->device));
   // the solve loops read the coarse space from the context
   struct CoarseOff {
@@ -842,10 +863,16 @@ int amrto_pcg(amrto_ctx* ctx, const double* b, double* u, const amrto_solve_opts
   int iters = 0, outer = 0, status, fell_back = 0;
   double rel = 0.0;
   if (o.inner_prec == AMRTO_FP64) {
-    status = cg_fp64(ctx, b, u, o.rtol, o.max_it, o.check_every, o.single_reduction != 0, &iters, &outer, &rel);
+    status = cg_fp64(ctx, b, u, o.rtol, o.max_it, o.check_every, o.single_reduction != 0, block3, &iters, &outer,
+                     &rel);
     if (status < 0 && status != AMRTO_EBREAKDOWN) return status;
   } else {
-    status = cg_mixed(ctx, b, u, o.inner_prec, o.rtol, o.max_it, o.check_every, o.inner_rtol, &iters, &outer, &rel);
+    if (block3) {
+      const int rc = block3_setup(ctx);
+      if (rc) return rc;
+    }
+    status = cg_mixed(ctx, b, u, o.inner_prec, o.rtol, o.max_it, o.check_every, o.inner_rtol, block3, &iters,
+                      &outer, &rel);
     if (status < 0 && status != AMRTO_EBREAKDOWN) return status;
     if (status != AMRTO_OK && o.fallback_fp64 && iters < o.max_it) {
       // the plain FP64 solve takes over (and judges), from the mixed iterate
@@ -853,8 +880,8 @@ int amrto_pcg(amrto_ctx* ctx, const double* b, double* u, const amrto_solve_opts
         hipLaunchKernelGGL(k_fill<double>, dim3((int)((3L * ctx->n_nodes + 255) / 256)), dim3(256), 0, ctx->stream, u,
                            3L * ctx->n_nodes);
       int it2 = 0, restarts = 0;
-      status = cg_fp64(ctx, b, u, o.rtol, o.max_it - iters, o.check_every, o.single_reduction != 0, &it2, &restarts,
-                       &rel);
+      status = cg_fp64(ctx, b, u, o.rtol, o.max_it - iters, o.check_every, o.single_reduction != 0, block3, &it2,
+                       &restarts, &rel);
       if (status < 0 && status != AMRTO_EBREAKDOWN) return status;
       iters += it2;
       fell_back = 1;

@@ -25,7 +25,7 @@ from .binding import FILTER_SENSITIVITY, FP64
 class AdaptiveSIMP:
     def __init__(self, base, max_level, fixed, load, volfrac=0.25, rho_init=0.25, rmin=1.5, move=0.2, eta=0.5,
                  rho_min=1e-3, rho_solid=0.5, r_amr=1.5, adapt_every=5, rtol=1e-8, inner_prec=FP64,
-                 inner_rtol=0.1, max_it=100000, device=0, metrics_path=None):
+                 inner_rtol=0.1, max_it=100000, device=0, metrics_path=None, precond=binding.JACOBI):
         self.base, self.max_level = tuple(int(b) for b in base), int(max_level)
         self.tree = binding.Octree(base, max_level)
         self.ctx = binding.Context(device)
@@ -34,6 +34,7 @@ class AdaptiveSIMP:
         self.volfrac, self.rmin, self.move, self.eta, self.rho_min = volfrac, rmin, move, eta, rho_min
         self.rho_solid, self.r_amr, self.adapt_every = rho_solid, r_amr, adapt_every
         self.rtol, self.inner_prec, self.inner_rtol, self.max_it = rtol, inner_prec, inner_rtol, max_it
+        self.precond = precond
         self.it = 0
         self.compliance = None
         self.mesh_version = 0
@@ -93,7 +94,7 @@ class AdaptiveSIMP:
         torch.cuda.synchronize(self.dev)
         t2 = time.perf_counter()
         st = self.ctx.pcg(self.b, self.u, rtol=self.rtol, max_it=self.max_it, inner_prec=self.inner_prec,
-                          inner_rtol=self.inner_rtol)
+                          inner_rtol=self.inner_rtol, precond=self.precond)
         if after_solve is not None:
             after_solve(self)
         t3 = time.perf_counter()

@@ -214,6 +214,60 @@ def test_pcg_octree_one_and_two_reduction_forms(lib, single):
         assert abs(a - b2) <= max(3, 0.05 * b2), its
 
 
+def test_block_diag_matches_assembled_operator(pair_rho):
+    """The 3x3 node blocks of A~ against the oracle's assembled A~ (hanging
+    and supported rows and columns as identity)."""
+    p, rho = pair_rho
+    ctx = make_ctx(p, rho)
+    s = cases.oracle_system(p, rho)
+    n = p.orc.n_nodes
+    out = torch.empty(9 * n, dtype=torch.float64, device="cuda")
+    ctx.block_diag(out)
+    got = host(out).reshape(n, 3, 3)
+    A = s.A.tocsr()
+    want = np.zeros((n, 3, 3))
+    for c in range(3):
+        for d in range(3):
+            want[:, c, d] = np.asarray(A[np.arange(c, 3 * n, 3), :][:, np.arange(d, 3 * n, 3)].diagonal()).ravel()
+    lib_want = want[p.perm]  # library node i is oracle node perm[i]
+    assert np.max(np.abs(got - lib_want)) <= 1e-12 * np.max(np.abs(lib_want))
+
+
+@pytest.mark.parametrize("kind", ["uniform", "octree"])
+def test_block_jacobi_pcg_matches_direct(lib, kind):
+    """Block-Jacobi PCG reaches the direct solution in fewer iterations than
+    Jacobi on the bridge (uniform) and the band-refined cantilever (octree)."""
+    from paper_1009_4975_amd import binding
+    if kind == "uniform":
+        p = cases.uniform_pair((16, 8, 8), bc="bridge")
+        rho = np.random.default_rng(4).uniform(0.01, 1.0, p.orc.n_elems)
+    else:
+        p = cases.octree_pair((4, 2, 2), 2, width=0.2)
+        rho = cases.centre_density(p, p.case["field"])
+    ctx = make_ctx(p, rho)
+    s = cases.oracle_system(p, rho)
+    want = p.to_lib_nodes(osys.recover(s, osys.solve_direct(s)))
+    b = torch.empty(3 * p.orc.n_nodes, dtype=torch.float64, device="cuda")
+    ctx.project_rhs(dev(p.lib_mesh.f_load), b)
+    its = {}
+    for pc in (binding.JACOBI, binding.BLOCK3):
+        u = torch.zeros_like(b)
+        st = ctx.pcg(b, u, rtol=1e-12, max_it=50000, precond=pc)
+        assert st["status"] == "OK"
+        assert np.linalg.norm(host(u) - want) <= 1e-8 * np.linalg.norm(want)
+        its[pc] = st["iters"]
+    assert its[binding.BLOCK3] < its[binding.JACOBI], its
+    # mixed precision with the FP32 copy of the inverse blocks
+    u = torch.zeros_like(b)
+    st = ctx.pcg(b, u, rtol=1e-10, max_it=50000, precond=binding.BLOCK3, inner_prec=binding.FP32)
+    assert st["status"] == "OK" and st["rel_res"] <= 1e-10
+    assert np.linalg.norm(host(u) - want) <= 1e-6 * np.linalg.norm(want)
+    with pytest.raises(binding.AmrtoError):  # the coarse space keeps the scalar diagonal
+        ctx.coarse_setup([], 1, 1, 1, affine=True)
+        ctx.pcg(b, torch.zeros_like(b), precond=binding.BLOCK3)
+    ctx.coarse_clear()
+
+
 @pytest.mark.parametrize("inner", [1, 2])
 def test_mixed_precision_refinement(pair_rho, inner):
     p, rho = pair_rho
