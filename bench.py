@@ -105,13 +105,18 @@ def event_time(torch, fn, reps):
     return s.elapsed_time(e) / reps
 
 
+# solve variants: inner precision, then "+coarse" (affine coarse space) and/or
+# "+block3" (3x3 node-block Jacobi in place of the scalar diagonal)
+SOLVERS = ("fp64", "fp32", "bf16", "fp64+coarse", "fp32+coarse", "fp64+block3", "fp32+block3",
+           "fp64+coarse+block3", "fp32+coarse+block3")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--solver", choices=["fp64", "fp32", "bf16", "fp64+coarse", "fp32+coarse", "fp64+block3",
-                                         "fp32+block3", "best"],
+    ap.add_argument("--solver", choices=[*SOLVERS, "best"],
                     default="best")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-c3", action="store_true", help="skip the uniform 192x96x96 apply measurement")
@@ -180,22 +185,23 @@ def main():
         u.zero_()
         prec = precs[name.split("+")[0]]
         t0 = time.perf_counter()
-        if name.endswith("+coarse"):
+        coarse = "+coarse" in name
+        if coarse:
             ctx.coarse_setup([], 2, 2, 2, affine=True)
         torch.cuda.synchronize()
         setup_ms = (time.perf_counter() - t0) * 1e3
-        pc = binding.BLOCK3 if name.endswith("+block3") else binding.JACOBI
+        pc = binding.BLOCK3 if "+block3" in name else binding.JACOBI
         st = ctx.pcg(b, u, rtol=1e-8, inner_prec=prec, inner_rtol=0.1, max_it=50000, precond=pc)
         st["ms"] += setup_ms
         st["setup_ms"] = setup_ms
-        if name.endswith("+coarse"):
+        if coarse:
             ctx.coarse_clear()
         return st
 
     # --- solver variants (untimed survey, picks the fastest that reaches 1e-8)
     variants = {}
     if not args.profile_only:
-        for name in ("fp64", "fp32", "bf16", "fp64+coarse", "fp32+coarse", "fp64+block3", "fp32+block3"):
+        for name in SOLVERS:
             solve(name)
             runs = [solve(name) for _ in range(2)]
             ms = min(r["ms"] for r in runs)
@@ -336,15 +342,17 @@ def c4_simp(torch, binding, synth):
     for name, prec, mode in (("plain_fp64", binding.FP64, None), ("plain_fp32", binding.FP32, None),
                              ("block3_fp64", binding.FP64, "block3"), ("block3_fp32", binding.FP32, "block3"),
                              ("coarse_fp64", binding.FP64, "coarse"), ("coarse_fp32", binding.FP32, "coarse"),
+                             ("coarse_block3_fp64", binding.FP64, "coarse+block3"),
+                             ("coarse_block3_fp32", binding.FP32, "coarse+block3"),
                              ("learned_coarse_fp64", binding.FP64, "learned"),
                              ("learned_coarse_fp32", binding.FP32, "learned")):
         t0 = time.perf_counter()
         sim = AdaptiveSIMP(case.base, case.max_level, case.fixed, case.load, volfrac=ex["volfrac"],
                            rho_init=ex["rho_init"], rmin=ex["rmin"], rho_solid=ex["rho_solid"], r_amr=ex["r_amr"],
                            adapt_every=ex["adapt_every"], rtol=1e-8, inner_prec=prec, inner_rtol=0.1,
-                           precond=binding.BLOCK3 if mode == "block3" else binding.JACOBI)
-        if mode == "block3":
-            mode = None  # a plain run apart from the preconditioner
+                           precond=binding.BLOCK3 if (mode or "").endswith("block3") else binding.JACOBI)
+        # the node-block preconditioner changes nothing else in a run
+        mode = {"block3": None, "coarse+block3": "coarse"}.get(mode, mode)
         ws = LearnedWarmStart(case.dims, cell=2, hidden=8, layers=3, epochs=100, seed=ex["net_seed"],
                               regions=(2, 2, 2)) if mode else None
         recs, train_ms = [], 0.0

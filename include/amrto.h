@@ -56,7 +56,8 @@ enum {
 
 /* Preconditioners of amrto_pcg: JACOBI = the exact diagonal of A~ (the
  * diagonal rescaling of Sec. 5); BLOCK3 = the 3x3 node blocks of A~ (all
- * components of a node), solves without a coarse space. */
+ * components of a node), alone or, on an octree mesh, added to the affine
+ * coarse space (M^-1 = B^-1 + Z E^-1 Z^T). */
 enum { AMRTO_PRECOND_JACOBI = 0, AMRTO_PRECOND_BLOCK3 = 1 };
 enum { AMRTO_FILTER_SENSITIVITY = 0, AMRTO_FILTER_DENSITY = 1 };
 
@@ -157,7 +158,9 @@ typedef struct {
   double rtol;        /* stop when ||b - A~ u||_2 <= rtol ||b||_2 (default 1e-8) */
   int32_t max_it;     /* iteration cap of the (inner) CG (default 20000) */
   int32_t precond;    /* AMRTO_PRECOND_JACOBI (default) or AMRTO_PRECOND_BLOCK3
-                         (any precision, no coarse space, two-pass form) */
+                         (any precision, two-pass form; with a coarse space
+                         only the affine one on an octree mesh: EINVAL
+                         otherwise) */
   int32_t inner_prec; /* AMRTO_FP64: plain PCG; FP32/BF16: mixed precision with
                          FP64 reliable updates (FP32 vectors, FP32/BF16 operator) */
   double inner_rtol;  /* mixed precision: factor by which the FP32 recurrence

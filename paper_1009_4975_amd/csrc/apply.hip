@@ -45,7 +45,8 @@ struct UArgs {
   int nx, ny, nz, tiles_x, tiles_y, zchunk, n_tiles;
   const double* stop;
   // fused octree pass with the affine coarse space: x holds r and the staged
-  // direction is p = (D^-1 r + Z cz) + beta p_old
+  // direction is p = (M r + Z cz) + beta p_old; dinv holds M (the Jacobi
+  // diagonal, or the inverse 3x3 node blocks)
   const void* dinv = nullptr;
   const float4* geo = nullptr;
   const double* cz = nullptr;
@@ -475,7 +476,9 @@ __global__ __launch_bounds__(BTHREADS, BrickOcc<VT>::blocks) void k_apply_brick(
 
 // ------------------------------------------------------------------ octree chunks
 
-template <typename VT, int PREC, bool FUSED, bool COARSE = false>
+// COARSE: 0 plain; 1 stage p from z = D^-1 r + Z cz; 2 the same with the
+// inverse 3x3 node blocks (six entries per node in a.dinv) in place of D^-1
+template <typename VT, int PREC, bool FUSED, int COARSE = 0>
 __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, BrickK<VT> kc, CgArgs cg) {
   __shared__ VT xs[TAB_MAX * 3];
   __shared__ double ys[TAB_MAX * 3];  // FP64 LDS accumulators (see k_apply_uniform_bf16)
@@ -533,7 +536,8 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   // raw vector values of the regular table nodes, also requested before the
   // prologue; beta is applied once the prologue has it
   const bool first = FUSED && cg.it == 0;
-  VT xv[NPT][3], pv[FUSED ? NPT : 1][3], dv[COARSE ? NPT : 1][3];
+  constexpr int DW = COARSE == 2 ? 6 : 3;
+  VT xv[NPT][3], pv[FUSED ? NPT : 1][3], dv[COARSE ? NPT : 1][DW];
   float4 gv[COARSE ? NPT : 1];
   __shared__ double czs[COARSE ? COARSE_KMAX : 1];
   if (COARSE)
@@ -546,8 +550,10 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
     for (int c3 = 0; c3 < 3; ++c3) {
       xv[r][c3] = 0;
       if (FUSED) pv[r][c3] = 0;
-      if (COARSE) dv[r][c3] = 0;
     }
+#pragma unroll
+    for (int k = 0; k < DW; ++k)
+      if (COARSE) dv[r][k] = 0;
     if (COARSE) gv[r] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (t < nreg && gn[r] >= 0) {
       const long g = 3L * gn[r];
@@ -556,8 +562,10 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
       for (int c3 = 0; c3 < 3; ++c3) {
         xv[r][c3] = X[g + c3];
         if (FUSED && !first) pv[r][c3] = PO[g + c3];
-        if (COARSE) dv[r][c3] = ((const VT*)a.dinv)[g + c3];
       }
+#pragma unroll
+      for (int k = 0; k < DW; ++k)
+        if (COARSE) dv[r][k] = ((const VT*)a.dinv)[(long)DW * gn[r] + k];
       if (COARSE) gv[r] = a.geo[gn[r]];
     }
   }
@@ -577,6 +585,8 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   for (int r = 0; r < NPT; ++r) {
     const int t = tid + 256 * r;
     if (t < nreg) {
+      VT zb[3];
+      if (COARSE == 2) block_apply<VT>(dv[r], xv[r], zb);
 #pragma unroll
       for (int c3 = 0; c3 < 3; ++c3) {
         VT v = xv[r][c3];
@@ -590,7 +600,8 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
           const double zc = czs[gr * 3 + c3] + d[c3] * czs[(R + gr) * 3 + c3] +
                             d[c3 == 2 ? 0 : c3 + 1] * czs[(2 * R + gr) * 3 + c3] +
                             d[c3 == 0 ? 2 : c3 - 1] * czs[(3 * R + gr) * 3 + c3];
-          v = (VT)((double)dv[r][c3] * (double)v + on * zc);
+          const double zl = COARSE == 2 ? (double)zb[c3] : (double)dv[r][c3] * (double)v;
+          v = (VT)(zl + on * zc);
         }
         if (FUSED && !first) v += vbeta * pv[r][c3];
         xs[3 * t + c3] = ((fb[r] >> c3) & 1) ? (VT)0 : v;
@@ -907,9 +918,11 @@ int apply_fused(amrto_ctx* ctx, const void* z, const void* pold, void* pnew, voi
 }
 
 // Fused octree pass with the affine coarse space folded into the staging
-// (no separate z pass): p = (D^-1 r + Z cz) + beta p_old, q = A~ p.
-int apply_fused_coarse(amrto_ctx* ctx, const void* r, const void* dinv, const void* pold, void* pnew, void* q,
-                       int prec, const CgArgs& cg) {
+// (no separate z pass): p = (M r + Z cz) + beta p_old, q = A~ p, with M the
+// Jacobi diagonal D^-1 (minv: 3 per node) or the inverse node blocks (block3:
+// 6 per node).
+int apply_fused_coarse(amrto_ctx* ctx, const void* r, const void* minv, const void* pold, void* pnew, void* q,
+                       int prec, const CgArgs& cg, bool block3) {
   if (ctx->uniform || !ctx->coarse_affine_only || ctx->coarse_k <= 0)
     return ctx->fail(AMRTO_ESTATE, "apply_fused_coarse: needs an octree mesh and an affine coarse space");
   UArgs a = base_args(ctx, prec);
@@ -917,20 +930,34 @@ int apply_fused_coarse(amrto_ctx* ctx, const void* r, const void* dinv, const vo
   a.pold = pold;
   a.pnew = pnew;
   a.y = q;
-  a.dinv = dinv;
+  a.dinv = minv;
   a.geo = ctx->d_cgeo;
   a.cz = ctx->d_cz;
   a.coarse_R = ctx->coarse_R;
   const dim3 grid(apply_blocks(ctx));
-  if (prec == AMRTO_FP64)
-    hipLaunchKernelGGL((k_apply_chunks<double, P_F64, true, true>), grid, dim3(256), 0, ctx->stream, a,
-                       chunk_args(ctx), brick_k<double>(ctx), cg);
-  else if (prec == AMRTO_FP32)
-    hipLaunchKernelGGL((k_apply_chunks<float, P_F32, true, true>), grid, dim3(256), 0, ctx->stream, a,
-                       chunk_args(ctx), brick_k<float>(ctx), cg);
-  else
-    hipLaunchKernelGGL((k_apply_chunks<float, P_BF16, true, true>), grid, dim3(256), 0, ctx->stream, a,
-                       chunk_args(ctx), brick_k<float>(ctx), cg);
+  const ChunkArgs ch = chunk_args(ctx);
+  if (prec == AMRTO_FP64) {
+    if (block3)
+      hipLaunchKernelGGL((k_apply_chunks<double, P_F64, true, 2>), grid, dim3(256), 0, ctx->stream, a, ch,
+                         brick_k<double>(ctx), cg);
+    else
+      hipLaunchKernelGGL((k_apply_chunks<double, P_F64, true, 1>), grid, dim3(256), 0, ctx->stream, a, ch,
+                         brick_k<double>(ctx), cg);
+  } else if (prec == AMRTO_FP32) {
+    if (block3)
+      hipLaunchKernelGGL((k_apply_chunks<float, P_F32, true, 2>), grid, dim3(256), 0, ctx->stream, a, ch,
+                         brick_k<float>(ctx), cg);
+    else
+      hipLaunchKernelGGL((k_apply_chunks<float, P_F32, true, 1>), grid, dim3(256), 0, ctx->stream, a, ch,
+                         brick_k<float>(ctx), cg);
+  } else {
+    if (block3)
+      hipLaunchKernelGGL((k_apply_chunks<float, P_BF16, true, 2>), grid, dim3(256), 0, ctx->stream, a, ch,
+                         brick_k<float>(ctx), cg);
+    else
+      hipLaunchKernelGGL((k_apply_chunks<float, P_BF16, true, 1>), grid, dim3(256), 0, ctx->stream, a, ch,
+                         brick_k<float>(ctx), cg);
+  }
   AMRTO_HIP(hipGetLastError());
   return AMRTO_OK;
 }

@@ -150,14 +150,6 @@ __global__ __launch_bounds__(256) void k_block_chunks(const double* __restrict__
   }
 }
 
-// z = B^-1 r for one node from the six stored entries
-template <typename VT>
-__device__ __forceinline__ void block_apply(const VT* __restrict__ bi, const VT (&r)[3], VT (&z)[3]) {
-  z[0] = bi[0] * r[0] + bi[3] * r[1] + bi[4] * r[2];
-  z[1] = bi[3] * r[0] + bi[1] * r[1] + bi[5] * r[2];
-  z[2] = bi[4] * r[0] + bi[5] * r[1] + bi[2] * r[2];
-}
-
 // r = b - q (q may be NULL), z = B^-1 r; partials r.z, r.r, b.b (one thread per node)
 template <typename VT, typename BT>
 __global__ __launch_bounds__(256) void k_init_b3(const BT* __restrict__ b, const BT* __restrict__ q,

@@ -224,8 +224,8 @@ bool cg1_available(const amrto_ctx* ctx);
 int cg1_parts(const amrto_ctx* ctx);
 int cg1_init(amrto_ctx* ctx);
 int cg1_enqueue(amrto_ctx* ctx, double* x, double tol2, int it0, int count);
-int apply_fused_coarse(amrto_ctx* ctx, const void* r, const void* dinv, const void* pold, void* pnew, void* q,
-                       int prec, const CgArgs& cg);
+int apply_fused_coarse(amrto_ctx* ctx, const void* r, const void* minv, const void* pold, void* pnew, void* q,
+                       int prec, const CgArgs& cg, bool block3 = false);
 int apply_blocks(const amrto_ctx* ctx);
 void uniform_grid(const amrto_ctx* ctx, int& tiles_x, int& tiles_y, int& zchunk, int& n_tiles, int& grid);
 

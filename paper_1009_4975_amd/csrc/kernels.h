@@ -304,6 +304,18 @@ __device__ __forceinline__ void mfma_tile_bf16(const bf16x8 (&a)[2][2], const fl
   d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][0], bl, d1, 0, 0, 0);
 }
 
+// ------------------------------------------------------------------ block-Jacobi
+
+// Inverse 3x3 node blocks are stored as six entries per node:
+// (B00, B11, B22, B01, B02, B12) of the symmetric inverse.
+// z = B^-1 r for one node from the six stored entries
+template <typename VT>
+__device__ __forceinline__ void block_apply(const VT* __restrict__ bi, const VT (&r)[3], VT (&z)[3]) {
+  z[0] = bi[0] * r[0] + bi[3] * r[1] + bi[4] * r[2];
+  z[1] = bi[3] * r[0] + bi[1] * r[1] + bi[5] * r[2];
+  z[2] = bi[4] * r[0] + bi[5] * r[1] + bi[2] * r[2];
+}
+
 // ------------------------------------------------------------------ fused CG step
 // Start of a fused CG iteration (every block computes the same values from
 // the same partial sums): convergence test on r.r, then beta = rz_i / rz_{i-1}

@@ -372,6 +372,64 @@ __global__ __launch_bounds__(256) void k_cg_update_coarse(VT* __restrict__ x, VT
   }
 }
 
+// The same pass with the block-Jacobi preconditioner (inverse 3x3 node
+// blocks): one node per step, since r^T B^-1 r needs a node's three
+// components together.
+template <typename VT>
+__global__ __launch_bounds__(256) void k_cg_update_coarse_b3(VT* __restrict__ x, VT* __restrict__ r,
+                                                             const VT* __restrict__ p, const VT* __restrict__ q,
+                                                             const VT* __restrict__ binv, long nn,
+                                                             const double* __restrict__ part_pq, int n_pq,
+                                                             double* __restrict__ scal, int it, CoarseArgs ca,
+                                                             double* __restrict__ part_z, double* __restrict__ part) {
+  if (scal[S_DONE] != 0.0) return;
+  __shared__ double sh[8];
+  __shared__ double acc[COARSE_KMAX];
+  __shared__ double red[COARSE_NFMAX * 3][256];
+  const int nf = ca.nf, R = ca.R, k = 3 * nf * R;
+  const long n3 = 3 * nn;
+  long lo, hi;
+  block_range(nn, lo, hi);
+  const double pq = sum_partials(part_pq, n_pq, sh);
+  const double rz = scal[S_RZ0 + (it & 1)];
+  if (!(pq > 0.0) || !(pq < 1e300) || !(rz == rz)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_DONE] = 2.0;
+    return;
+  }
+  for (int j = threadIdx.x; j < k; j += blockDim.x) acc[j] = 0.0;
+  __syncthreads();
+  const VT alpha = (VT)(rz / pq);
+  ZtAcc a;
+  zt_clear(a, -1);
+  double srz = 0.0, srr = 0.0;
+  for (long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    VT rv[3], zv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      x[3 * i + c] += alpha * p[3 * i + c];
+      rv[c] = r[3 * i + c] - alpha * q[3 * i + c];
+      r[3 * i + c] = rv[c];
+    }
+    block_apply<VT>(binv + 6 * i, rv, zv);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      srz += (double)rv[c] * (double)zv[c];
+      srr += (double)rv[c] * (double)rv[c];
+      double fv[COARSE_NFMAX];
+      const int g = coarse_fields(ca, 3 * i + c, n3, fv);
+      zt_add(a, acc, fv, nf, R, g, c, (double)rv[c]);
+    }
+  }
+  zt_flush(a, acc, nf, R, lo < hi ? coarse_region(ca, (int)lo) : 0, red);
+  __syncthreads();
+  zt_store(acc, k, part_z);
+  block_sum2(srz, srr, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = srz;
+    part[RED_BLOCKS + blockIdx.x] = srr;
+  }
+}
+
 // ct[j] = sum_b part[j nblk + b]: one block per coarse column, fixed-tree sum
 // (deterministic).
 __global__ __launch_bounds__(256) void k_coarse_sum(const double* __restrict__ part, int k, int nblk,
@@ -581,13 +639,24 @@ static int enqueue_iters(amrto_ctx* ctx, const Vecs<VT>& v, VT* x, int prec, dou
     VT* pnew = (it & 1) ? v.p1 : v.p0;
     VT* pold = (it & 1) ? v.p0 : v.p1;
     CgArgs cg{ctx->d_scal, ctx->d_part, ctx->d_partpq, 0, it, tol2, fused ? 1 : 0};
-    int rc = fused ? apply_fused_coarse(ctx, v.r, v.dinv, pold, pnew, v.q, prec, cg)
+    const VT* binv = nullptr;
+    if (block3) {
+      if constexpr (std::is_same<VT, double>::value) binv = ctx->d_binv;
+      else binv = ctx->d_binv_f;
+    }
+    int rc = fused ? apply_fused_coarse(ctx, v.r, block3 ? (const void*)binv : (const void*)v.dinv, pold, pnew, v.q,
+                                        prec, cg, block3)
                    : apply_fused(ctx, v.z, pold, pnew, v.q, prec, cg);
     if (rc) return rc;
     if (ctx->coarse_k > 0) {
-      hipLaunchKernelGGL(k_cg_update_coarse<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew, v.q,
-                         v.dinv, n3, ctx->d_partpq, ctx->n_partpq, ctx->d_scal, it, coarse_args(ctx), ctx->d_cpart,
-                         ctx->d_part);
+      if (block3)  // coarse_fused holds (checked in amrto_pcg)
+        hipLaunchKernelGGL(k_cg_update_coarse_b3<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew,
+                           v.q, binv, (long)ctx->n_nodes, ctx->d_partpq, ctx->n_partpq, ctx->d_scal, it,
+                           coarse_args(ctx), ctx->d_cpart, ctx->d_part);
+      else
+        hipLaunchKernelGGL(k_cg_update_coarse<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew, v.q,
+                           v.dinv, n3, ctx->d_partpq, ctx->n_partpq, ctx->d_scal, it, coarse_args(ctx),
+                           ctx->d_cpart, ctx->d_part);
       hipLaunchKernelGGL(k_coarse_sum, dim3(ctx->coarse_k), dim3(256), 0, ctx->stream, ctx->d_cpart,
                          ctx->coarse_k, RED_BLOCKS, ctx->d_ct, ctx->d_scal + S_DONE);
       hipLaunchKernelGGL(k_coarse_cz, dim3(1), dim3(cz_threads(ctx)), 0, ctx->stream, (const double*)ctx->d_ct, ctx->coarse_k,
@@ -850,8 +919,9 @@ int amrto_pcg(amrto_ctx* ctx, const double* b, double* u, const amrto_solve_opts
   if (o.precond != AMRTO_PRECOND_JACOBI && o.precond != AMRTO_PRECOND_BLOCK3)
     return ctx->fail(AMRTO_EINVAL, "amrto_pcg: unknown preconditioner");
   const bool block3 = o.precond == AMRTO_PRECOND_BLOCK3;
-  if (block3 && o.use_coarse && ctx->coarse_k > 0)
-    return ctx->fail(AMRTO_EINVAL, "amrto_pcg: block-Jacobi takes solves without a coarse space");
+  if (block3 && o.use_coarse && ctx->coarse_k > 0 && !coarse_fused(ctx))
+    return ctx->fail(AMRTO_EINVAL,
+                     "amrto_pcg: block-Jacobi with a coarse space needs an octree mesh and the affine space");
   AMRTO_HIP(hipSetDevice(ctx->device));
   // the solve loops read the coarse space from the context
   struct CoarseOff {

@@ -262,9 +262,26 @@ def test_block_jacobi_pcg_matches_direct(lib, kind):
     st = ctx.pcg(b, u, rtol=1e-10, max_it=50000, precond=binding.BLOCK3, inner_prec=binding.FP32)
     assert st["status"] == "OK" and st["rel_res"] <= 1e-10
     assert np.linalg.norm(host(u) - want) <= 1e-6 * np.linalg.norm(want)
-    with pytest.raises(binding.AmrtoError):  # the coarse space keeps the scalar diagonal
-        ctx.coarse_setup([], 1, 1, 1, affine=True)
-        ctx.pcg(b, torch.zeros_like(b), precond=binding.BLOCK3)
+    ctx.coarse_setup([], 1, 1, 1, affine=True)
+    if kind == "uniform":
+        # the uniform brick path keeps a scalar diagonal beside a coarse space
+        with pytest.raises(binding.AmrtoError):
+            ctx.pcg(b, torch.zeros_like(b), precond=binding.BLOCK3)
+    else:
+        # octree: M^-1 = B^-1 + Z E^-1 Z^T, folded into the operator pass
+        its_c = {}
+        for pc in (binding.JACOBI, binding.BLOCK3):
+            u = torch.zeros_like(b)
+            st = ctx.pcg(b, u, rtol=1e-12, max_it=50000, precond=pc)
+            assert st["status"] == "OK"
+            assert np.linalg.norm(host(u) - want) <= 1e-8 * np.linalg.norm(want)
+            its_c[pc] = st["iters"]
+        assert its_c[binding.BLOCK3] < its[binding.BLOCK3], (its, its_c)
+        assert its_c[binding.BLOCK3] <= its_c[binding.JACOBI], its_c
+        u = torch.zeros_like(b)
+        st = ctx.pcg(b, u, rtol=1e-10, max_it=50000, precond=binding.BLOCK3, inner_prec=binding.FP32)
+        assert st["status"] == "OK" and st["rel_res"] <= 1e-10
+        assert np.linalg.norm(host(u) - want) <= 1e-6 * np.linalg.norm(want)
     ctx.coarse_clear()
 
 
