@@ -441,7 +441,10 @@ __global__ __launch_bounds__(BTHREADS, BrickOcc<VT>::blocks) void k_apply_brick(
       s0[c] = c00[c] + dpp_mov<DPP_ROW_SHR1>(c10[c]);
       sb[k & 1][c][tid] = c01[c] + dpp_mov<DPP_ROW_SHR1>(c11[c]);
     }
-    if (k + 2 <= nz) stage(Rst, k + 2, ln);
+    // layers above the mesh are staged too (as zeros): their modes meet a zero
+    // coefficient in the top element layer, and zero times stale LDS or
+    // register contents is not zero when those bits are Inf or NaN
+    stage(Rst, k + 2, ln);
     load(Rld, k + 2 + BPD);
     __syncthreads();
     // the next layer's modes first: its LDS reads overlap the partial sums'
