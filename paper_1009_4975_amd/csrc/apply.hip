@@ -51,6 +51,12 @@ struct UArgs {
   const float4* geo = nullptr;
   const double* cz = nullptr;
   int coarse_R = 0;
+  // recurrence form: cz = E^-1 ct is formed by every block from ct, and the
+  // pass writes, per block, Z^T q over its owned nodes (column j at
+  // zq_part[j nblocks + block]); NULL: cz is read, no partials
+  double* zq_part = nullptr;
+  const double* einv = nullptr;
+  const double* ct = nullptr;
 };
 
 // ------------------------------------------------------------------ uniform brick, BF16 on the matrix cores
@@ -543,8 +549,49 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   VT xv[NPT][3], pv[FUSED ? NPT : 1][3], dv[COARSE ? NPT : 1][DW];
   float4 gv[COARSE ? NPT : 1];
   __shared__ double czs[COARSE ? COARSE_KMAX : 1];
-  if (COARSE)
+  CgArgs cgb = cg;
+  if (COARSE && a.zq_part) {
+    // recurrence form: cz = E^-1 ct (E^-1 symmetric: column j read as row
+    // j), two groups of kk threads over the even and odd rows, added in group
+    // order; then r.z adds ct^T cz in the prologue.  Up to 96 columns (eight
+    // regions) the loads go out in two batches of 24; more take a plain loop.
+    const int kk = 12 * a.coarse_R;
+    const int jj = tid % kk, g = tid / kk;
+    double s = 0.0;
+    if (kk <= 96) {
+      for (int i = tid; i < kk; i += 256) ys[256 + i] = a.ct[i];
+      __syncthreads();
+      if (g < 2) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          double e[24];
+#pragma unroll
+          for (int u = 0; u < 24; ++u) e[u] = a.einv[(long)min(g + 2 * (24 * h + u), kk - 1) * kk + jj];
+#pragma unroll
+          for (int u = 0; u < 24; ++u) {
+            const int i = g + 2 * (24 * h + u);
+            if (i < kk) s += e[u] * ys[256 + i];
+          }
+        }
+      }
+      ys[tid] = s;
+      __syncthreads();
+      if (tid < kk) czs[tid] = ys[tid] + ys[kk + tid];
+    } else {
+      for (int j = tid; j < kk; j += 256) {
+        double v = 0.0;
+#pragma unroll 16
+        for (int i = 0; i < kk; ++i) v += a.einv[(long)i * kk + j] * a.ct[i];
+        czs[j] = v;
+      }
+    }
+    __syncthreads();
+    cgb.cct = a.ct;
+    cgb.ccz = czs;
+    cgb.ck = kk;
+  } else if (COARSE) {
     for (int j = tid; j < 12 * a.coarse_R; j += 256) czs[j] = a.cz[j];
+  }
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
     const int t = tid + 256 * r;
@@ -577,10 +624,12 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   for (int r = 0; r < EPT; ++r) cep[r] = coef[eel[r]];
   double beta = 0.0;
   if (FUSED) {
-    if (!cg_prologue(cg, beta, sh)) return;
+    if (!cg_prologue(cgb, beta, sh)) return;
   }
   if (!have) {
     if (FUSED && tid == 0) cg.part_out[cg.part_base + blockIdx.x] = 0.0;
+    if (COARSE && a.zq_part)
+      for (int j = tid; j < 12 * a.coarse_R; j += 256) a.zq_part[(long)j * gridDim.x + blockIdx.x] = 0.0;
     return;
   }
   const VT vbeta = (VT)beta;
@@ -689,9 +738,13 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   }
   __syncthreads();
   double dot = 0.0;
+  VT qk[COARSE ? NPT : 1][3];  // q of the owned regular nodes (coarse recurrence)
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
     const int t = tid + 256 * r;
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp)
+      if (COARSE) qk[r][comp] = 0;
     const bool own_reg = t < nown, own_hang = t >= nreg && t < nreg + nhown;
     if (!own_reg && !own_hang) continue;
     const long g = 3L * gn[r];
@@ -715,6 +768,7 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
         PN[g + comp] = pn;
         Y[g + comp] = q;
         dot += (double)pn * (double)q;
+        if (COARSE) qk[r][comp] = q;
       } else {
         Y[g + comp] = fixed ? X[g + comp] : acc;
       }
@@ -723,6 +777,70 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   if (FUSED) {
     dot = block_sum(dot, sh);
     if (tid == 0) cg.part_out[cg.part_base + blockIdx.x] = dot;
+  }
+  if (COARSE && a.zq_part) {
+    // Z^T q over the owned regular nodes, one region present at a time (a
+    // bitmask; usually one region): sums per thread in node order, then
+    // through LDS (ys is free here) 16 partial sums per column and one final
+    // sum per column, all in fixed order (deterministic).  Columns of absent
+    // regions are zero.
+    __shared__ double zred[12][16];
+    __shared__ uint32_t gmask_s[4];
+    static_assert(TAB_MAX * 3 >= 12 * 256, "the Z^T q columns are staged in ys");
+    const int R = a.coarse_R, kk = 12 * R, lane = tid & 63, wv = tid >> 6;
+    uint32_t m = 0;
+#pragma unroll
+    for (int r = 0; r < NPT; ++r)
+      if (tid + 256 * r < nown) m |= 1u << (__float_as_int(gv[r].w) & 31);
+    for (int off = 32; off > 0; off >>= 1) m |= (uint32_t)__shfl_xor((int)m, off, 64);
+    if (lane == 0) gmask_s[wv] = m;
+    for (int j = tid; j < kk; j += 256) czs[j] = 0.0;
+    __syncthreads();
+    m = gmask_s[0] | gmask_s[1] | gmask_s[2] | gmask_s[3];
+    for (; m; m &= m - 1) {
+      const int g = __ffs((int)m) - 1;
+      double s[4][3];
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int c3 = 0; c3 < 3; ++c3) s[f][c3] = 0.0;
+#pragma unroll
+      for (int r = 0; r < NPT; ++r) {
+        const int w = __float_as_int(gv[r].w);
+        if (tid + 256 * r < nown && (w & 0xff) == g) {
+          const double d[3] = {(double)gv[r].x, (double)gv[r].y, (double)gv[r].z};
+#pragma unroll
+          for (int c3 = 0; c3 < 3; ++c3) {
+            const double qc = ((w >> (8 + c3)) & 1) ? 0.0 : (double)qk[r][c3];
+            s[0][c3] += qc;
+            s[1][c3] += qc * d[c3];
+            s[2][c3] += qc * d[c3 == 2 ? 0 : c3 + 1];
+            s[3][c3] += qc * d[c3 == 0 ? 2 : c3 - 1];
+          }
+        }
+      }
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int c3 = 0; c3 < 3; ++c3) ys[(f * 3 + c3) * 256 + tid] = s[f][c3];
+      __syncthreads();
+      if (tid < 192) {
+        const int u = tid >> 4, sub = tid & 15;
+        double v = 0.0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v += ys[u * 256 + i * 16 + sub];
+        zred[u][sub] = v;
+      }
+      __syncthreads();
+      if (tid < 12) {
+        double v = 0.0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v += zred[tid][i];
+        czs[((tid / 3) * R + g) * 3 + tid % 3] = v;
+      }
+    }
+    __syncthreads();
+    for (int j = tid; j < kk; j += 256) a.zq_part[(long)j * gridDim.x + blockIdx.x] = czs[j];
   }
 }
 
@@ -925,7 +1043,7 @@ int apply_fused(amrto_ctx* ctx, const void* z, const void* pold, void* pnew, voi
 // Jacobi diagonal D^-1 (minv: 3 per node) or the inverse node blocks (block3:
 // 6 per node).
 int apply_fused_coarse(amrto_ctx* ctx, const void* r, const void* minv, const void* pold, void* pnew, void* q,
-                       int prec, const CgArgs& cg, bool block3) {
+                       int prec, const CgArgs& cg, bool block3, double* zq_part) {
   if (ctx->uniform || !ctx->coarse_affine_only || ctx->coarse_k <= 0)
     return ctx->fail(AMRTO_ESTATE, "apply_fused_coarse: needs an octree mesh and an affine coarse space");
   UArgs a = base_args(ctx, prec);
@@ -937,6 +1055,9 @@ int apply_fused_coarse(amrto_ctx* ctx, const void* r, const void* minv, const vo
   a.geo = ctx->d_cgeo;
   a.cz = ctx->d_cz;
   a.coarse_R = ctx->coarse_R;
+  a.zq_part = zq_part;
+  a.einv = ctx->d_cinv;
+  a.ct = ctx->d_ct;
   const dim3 grid(apply_blocks(ctx));
   const ChunkArgs ch = chunk_args(ctx);
   if (prec == AMRTO_FP64) {

@@ -212,6 +212,17 @@ int amrto_coarse_setup(amrto_ctx* ctx, int32_t affine, const double* const* fiel
   ctx->coarse_nf = nf;
   ctx->coarse_R = R;
   ctx->coarse_affine_only = (affine && n_fields == 0) ? 1 : 0;
+  if (!ctx->uniform && ctx->coarse_affine_only) {
+    // partials of Z^T q per operator-pass block (recurrence form)
+    const long need = (long)k * apply_blocks(ctx);
+    if (need > ctx->cq_cap) {
+      if (ctx->d_cqpart) (void)hipFree(ctx->d_cqpart);
+      ctx->d_cqpart = nullptr;
+      ctx->cq_cap = 0;
+      AMRTO_HIP(hipMalloc((void**)&ctx->d_cqpart, need * sizeof(double)));
+      ctx->cq_cap = need;
+    }
+  }
   if (affine) {
     if (!ctx->d_cgeo) AMRTO_HIP(hipMalloc((void**)&ctx->d_cgeo, ctx->n_nodes * sizeof(float4)));
     hipLaunchKernelGGL(k_affine_fields, dim3(gn), dim3(256), 0, ctx->stream, xyz, ctx->n_nodes, ctx->nx, ctx->ny,

@@ -86,6 +86,11 @@ struct CgArgs {
   int it;
   double tol2;
   int coarse = 0;         // r.z = partial sums + scal[S_CTZ]
+  // coarse space in recurrence form: r.z = partial sums + ct^T cz, formed
+  // from the ck entries of ct and cz (the block's own copy) by every block
+  const double* cct = nullptr;
+  const double* ccz = nullptr;
+  int ck = 0;
 };
 
 }  // namespace amrto
@@ -184,6 +189,12 @@ struct amrto_ctx {
   double* d_cinv = nullptr;    // E^-1 (k x k)
   double* d_ct = nullptr;      // Z^T r of the current iteration
   double* d_cz = nullptr;      // E^-1 Z^T r
+  // recurrence form (octree, affine space): per operator-pass block, the
+  // partials of Z^T q (k x blocks, column-major)
+  double* d_cqpart = nullptr;
+  long cq_cap = 0;
+  int coarse_exact_it = 0;      // iteration at which ct was last formed from r
+  bool coarse_fresh = false;    // ct was just formed from r (coarse_init)
   // mesh <-> grid transfers (net.hip)
   int grid_cell = 0;
   int32_t* d_node_xyz = nullptr;
@@ -225,7 +236,7 @@ int cg1_parts(const amrto_ctx* ctx);
 int cg1_init(amrto_ctx* ctx);
 int cg1_enqueue(amrto_ctx* ctx, double* x, double tol2, int it0, int count);
 int apply_fused_coarse(amrto_ctx* ctx, const void* r, const void* minv, const void* pold, void* pnew, void* q,
-                       int prec, const CgArgs& cg, bool block3 = false);
+                       int prec, const CgArgs& cg, bool block3 = false, double* zq_part = nullptr);
 int apply_blocks(const amrto_ctx* ctx);
 void uniform_grid(const amrto_ctx* ctx, int& tiles_x, int& tiles_y, int& zchunk, int& n_tiles, int& grid);
 

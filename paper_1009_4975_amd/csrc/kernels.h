@@ -329,6 +329,7 @@ __device__ __forceinline__ bool cg_prologue(const CgArgs& cg, double& beta, doub
     rz += cg.part_in[i];
     rr += cg.part_in[RED_BLOCKS + i];
   }
+  for (int i = threadIdx.x; i < cg.ck; i += blockDim.x) rz += cg.cct[i] * cg.ccz[i];
   block_sum2(rz, rr, sh);
   if (cg.coarse) rz += cg.scal[S_CTZ];
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;

@@ -430,6 +430,99 @@ __global__ __launch_bounds__(256) void k_cg_update_coarse_b3(VT* __restrict__ x,
   }
 }
 
+#ifndef AMRTO_COARSE_REC
+#define AMRTO_COARSE_REC 1
+#endif
+constexpr int CT_REFRESH = 64;
+
+// Update pass of the coarse-space solve in recurrence form (octree mesh,
+// affine space; the operator pass formed the per-block partials of Z^T q and
+// forms cz = E^-1 ct itself).  Blocks below RED_BLOCKS: x += alpha p,
+// r -= alpha q and the partials of r^T M r and r^T r, one node per step (M =
+// the Jacobi diagonal, 3 entries per node, or with B3 the inverse node blocks,
+// 6 entries).  Block RED_BLOCKS + j: ct[j] -= alpha (Z^T q)_j, so that
+// ct = Z^T r holds for the new r up to rounding (ct is formed from r again
+// every CT_REFRESH iterations).
+template <typename VT, bool B3>
+__global__ __launch_bounds__(256) void k_cg_update_rec(VT* __restrict__ x, VT* __restrict__ r,
+                                                       const VT* __restrict__ p, const VT* __restrict__ q,
+                                                       const VT* __restrict__ minv, long nn,
+                                                       const double* __restrict__ part_pq, int n_pq,
+                                                       double* __restrict__ scal, int it,
+                                                       const double* __restrict__ qpart, int nb,
+                                                       double* __restrict__ ct, double* __restrict__ part) {
+  if (scal[S_DONE] != 0.0) return;
+  __shared__ double sh[16];
+  constexpr int MW = B3 ? 6 : 3;
+  const bool col = blockIdx.x >= RED_BLOCKS;
+  const int j = (int)blockIdx.x - RED_BLOCKS;
+  const long i0 = blockIdx.x * (long)blockDim.x + threadIdx.x, stride = (long)RED_BLOCKS * blockDim.x;
+  // first node of this thread, and the column sums, requested before the
+  // p.q partials are reduced
+  VT xv[3], pv[3], rv[3], qv[3], mv[MW];
+  const bool in0 = !col && i0 < nn;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    xv[c] = in0 ? x[3 * i0 + c] : (VT)0;
+    pv[c] = in0 ? p[3 * i0 + c] : (VT)0;
+    rv[c] = in0 ? r[3 * i0 + c] : (VT)0;
+    qv[c] = in0 ? q[3 * i0 + c] : (VT)0;
+  }
+#pragma unroll
+  for (int c = 0; c < MW; ++c) mv[c] = in0 ? minv[MW * i0 + c] : (VT)0;
+  double s1 = 0.0;
+  if (col)
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s1 += qpart[(long)j * nb + b];
+  const double pq = sum_partials(part_pq, n_pq, sh);
+  const double rz = scal[S_RZ0 + (it & 1)];
+  if (!(pq > 0.0) || !(pq < 1e300) || !(rz == rz)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_DONE] = 2.0;
+    return;
+  }
+  const VT alpha = (VT)(rz / pq);
+  if (col) {
+    s1 = block_sum(s1, sh);
+    if (threadIdx.x == 0) ct[j] -= (double)alpha * s1;
+    return;
+  }
+  double srz = 0.0, srr = 0.0;
+  for (long i = i0; i < nn; i += stride) {
+    if (i != i0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        xv[c] = x[3 * i + c];
+        pv[c] = p[3 * i + c];
+        rv[c] = r[3 * i + c];
+        qv[c] = q[3 * i + c];
+      }
+#pragma unroll
+      for (int c = 0; c < MW; ++c) mv[c] = minv[MW * i + c];
+    }
+    VT rn[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      x[3 * i + c] = xv[c] + alpha * pv[c];
+      rn[c] = rv[c] - alpha * qv[c];
+      r[3 * i + c] = rn[c];
+      srr += (double)rn[c] * (double)rn[c];
+    }
+    if (B3) {
+      VT zn[3];
+      block_apply<VT>(mv, rn, zn);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) srz += (double)rn[c] * (double)zn[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) srz += (double)rn[c] * (double)mv[c] * (double)rn[c];
+    }
+  }
+  block_sum2(srz, srr, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = srz;
+    part[RED_BLOCKS + blockIdx.x] = srr;
+  }
+}
+
 // ct[j] = sum_b part[j nblk + b]: one block per coarse column, fixed-tree sum
 // (deterministic).
 __global__ __launch_bounds__(256) void k_coarse_sum(const double* __restrict__ part, int k, int nblk,
@@ -583,9 +676,19 @@ static bool coarse_fused(const amrto_ctx* ctx) {
 // z = D^-1 r + Z cz (overwriting the r.z and r.r partials of k_init; b.b
 // stays) or, in the fused form, ct^T cz in its scalar slot (the partials of
 // k_init already are r^T D^-1 r and r^T r)
+// ct = Z^T r formed from r
+template <typename VT>
+static void coarse_ct(amrto_ctx* ctx, const VT* r, const double* stop) {
+  hipLaunchKernelGGL(k_zt_part<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, coarse_args(ctx), r,
+                     3L * ctx->n_nodes, ctx->d_cpart);
+  hipLaunchKernelGGL(k_coarse_sum, dim3(ctx->coarse_k), dim3(256), 0, ctx->stream, ctx->d_cpart, ctx->coarse_k,
+                     RED_BLOCKS, ctx->d_ct, stop);
+}
+
 template <typename VT>
 static void coarse_init(amrto_ctx* ctx, const Vecs<VT>& v) {
   if (ctx->coarse_k <= 0) return;
+  ctx->coarse_fresh = true;
   const long n3 = 3L * ctx->n_nodes;
   hipLaunchKernelGGL(k_zt_part<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, coarse_args(ctx), v.r, n3,
                      ctx->d_cpart);
@@ -635,20 +738,43 @@ static int enqueue_iters(amrto_ctx* ctx, const Vecs<VT>& v, VT* x, int prec, dou
                          bool block3 = false) {
   const long n3 = 3L * ctx->n_nodes;
   const bool fused = coarse_fused(ctx);
+  const bool rec = fused && AMRTO_COARSE_REC && ctx->d_cqpart;
+  if (rec) {
+    // ct follows r by a recurrence; every CT_REFRESH iterations it is formed
+    // from r again, so rounding cannot accumulate without bound
+    if (ctx->coarse_fresh) {
+      ctx->coarse_fresh = false;
+      ctx->coarse_exact_it = it0;
+    } else if (it0 - ctx->coarse_exact_it >= CT_REFRESH) {
+      coarse_ct(ctx, v.r, ctx->d_scal + S_DONE);
+      ctx->coarse_exact_it = it0;
+    }
+  }
   for (int it = it0; it < it0 + count; ++it) {
     VT* pnew = (it & 1) ? v.p1 : v.p0;
     VT* pold = (it & 1) ? v.p0 : v.p1;
-    CgArgs cg{ctx->d_scal, ctx->d_part, ctx->d_partpq, 0, it, tol2, fused ? 1 : 0};
+    CgArgs cg{ctx->d_scal, ctx->d_part, ctx->d_partpq, 0, it, tol2, (fused && !rec) ? 1 : 0};
     const VT* binv = nullptr;
     if (block3) {
       if constexpr (std::is_same<VT, double>::value) binv = ctx->d_binv;
       else binv = ctx->d_binv_f;
     }
     int rc = fused ? apply_fused_coarse(ctx, v.r, block3 ? (const void*)binv : (const void*)v.dinv, pold, pnew, v.q,
-                                        prec, cg, block3)
+                                        prec, cg, block3, rec ? ctx->d_cqpart : nullptr)
                    : apply_fused(ctx, v.z, pold, pnew, v.q, prec, cg);
     if (rc) return rc;
-    if (ctx->coarse_k > 0) {
+    if (rec) {
+      const int nb = apply_blocks(ctx);
+      if (block3)
+        hipLaunchKernelGGL((k_cg_update_rec<VT, true>), dim3(RED_BLOCKS + ctx->coarse_k), dim3(256), 0, ctx->stream,
+                           x, v.r, pnew, v.q, binv, (long)ctx->n_nodes, ctx->d_partpq, ctx->n_partpq, ctx->d_scal,
+                           it, (const double*)ctx->d_cqpart, nb, ctx->d_ct, ctx->d_part);
+      else
+        hipLaunchKernelGGL((k_cg_update_rec<VT, false>), dim3(RED_BLOCKS + ctx->coarse_k), dim3(256), 0,
+                           ctx->stream, x, v.r, pnew, v.q, (const VT*)v.dinv, (long)ctx->n_nodes, ctx->d_partpq,
+                           ctx->n_partpq, ctx->d_scal, it, (const double*)ctx->d_cqpart, nb, ctx->d_ct,
+                           ctx->d_part);
+    } else if (ctx->coarse_k > 0) {
       if (block3)  // coarse_fused holds (checked in amrto_pcg)
         hipLaunchKernelGGL(k_cg_update_coarse_b3<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew,
                            v.q, binv, (long)ctx->n_nodes, ctx->d_partpq, ctx->n_partpq, ctx->d_scal, it,
