@@ -51,9 +51,10 @@ struct UArgs {
   const float4* geo = nullptr;
   const double* cz = nullptr;
   int coarse_R = 0;
-  // recurrence form: cz = E^-1 ct is formed by every block from ct, and the
-  // pass writes, per block, Z^T q over its owned nodes (column j at
-  // zq_part[j nblocks + block]); NULL: cz is read, no partials
+  // recurrence form: the pass writes, per block, Z^T q over its owned nodes
+  // and E^-1 Z^T q (column j at zq_part[j nblocks + block], E^-1 Z^T q after
+  // the first k columns), and r.z takes ct^T cz from ct and cz; NULL: r.z
+  // takes its coarse part from the scalar slot, no partials
   double* zq_part = nullptr;
   const double* einv = nullptr;
   const double* ct = nullptr;
@@ -548,50 +549,6 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   constexpr int DW = COARSE == 2 ? 6 : 3;
   VT xv[NPT][3], pv[FUSED ? NPT : 1][3], dv[COARSE ? NPT : 1][DW];
   float4 gv[COARSE ? NPT : 1];
-  __shared__ double czs[COARSE ? COARSE_KMAX : 1];
-  CgArgs cgb = cg;
-  if (COARSE && a.zq_part) {
-    // recurrence form: cz = E^-1 ct (E^-1 symmetric: column j read as row
-    // j), two groups of kk threads over the even and odd rows, added in group
-    // order; then r.z adds ct^T cz in the prologue.  Up to 96 columns (eight
-    // regions) the loads go out in two batches of 24; more take a plain loop.
-    const int kk = 12 * a.coarse_R;
-    const int jj = tid % kk, g = tid / kk;
-    double s = 0.0;
-    if (kk <= 96) {
-      for (int i = tid; i < kk; i += 256) ys[256 + i] = a.ct[i];
-      __syncthreads();
-      if (g < 2) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          double e[24];
-#pragma unroll
-          for (int u = 0; u < 24; ++u) e[u] = a.einv[(long)min(g + 2 * (24 * h + u), kk - 1) * kk + jj];
-#pragma unroll
-          for (int u = 0; u < 24; ++u) {
-            const int i = g + 2 * (24 * h + u);
-            if (i < kk) s += e[u] * ys[256 + i];
-          }
-        }
-      }
-      ys[tid] = s;
-      __syncthreads();
-      if (tid < kk) czs[tid] = ys[tid] + ys[kk + tid];
-    } else {
-      for (int j = tid; j < kk; j += 256) {
-        double v = 0.0;
-#pragma unroll 16
-        for (int i = 0; i < kk; ++i) v += a.einv[(long)i * kk + j] * a.ct[i];
-        czs[j] = v;
-      }
-    }
-    __syncthreads();
-    cgb.cct = a.ct;
-    cgb.ccz = czs;
-    cgb.ck = kk;
-  } else if (COARSE) {
-    for (int j = tid; j < 12 * a.coarse_R; j += 256) czs[j] = a.cz[j];
-  }
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
     const int t = tid + 256 * r;
@@ -622,6 +579,16 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   VT cep[EPT];
 #pragma unroll
   for (int r = 0; r < EPT; ++r) cep[r] = coef[eel[r]];
+  __shared__ double czs[COARSE ? COARSE_KMAX : 1];
+  CgArgs cgb = cg;
+  if (COARSE) {
+    for (int j = tid; j < 12 * a.coarse_R; j += 256) czs[j] = a.cz[j];
+    if (a.zq_part) {  // recurrence form: r.z adds ct^T cz in the prologue
+      cgb.cct = a.ct;
+      cgb.ccz = a.cz;
+      cgb.ck = 12 * a.coarse_R;
+    }
+  }
   double beta = 0.0;
   if (FUSED) {
     if (!cg_prologue(cgb, beta, sh)) return;
@@ -629,7 +596,7 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   if (!have) {
     if (FUSED && tid == 0) cg.part_out[cg.part_base + blockIdx.x] = 0.0;
     if (COARSE && a.zq_part)
-      for (int j = tid; j < 12 * a.coarse_R; j += 256) a.zq_part[(long)j * gridDim.x + blockIdx.x] = 0.0;
+      for (int j = tid; j < 24 * a.coarse_R; j += 256) a.zq_part[(long)j * gridDim.x + blockIdx.x] = 0.0;
     return;
   }
   const VT vbeta = (VT)beta;
@@ -840,7 +807,23 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
       }
     }
     __syncthreads();
-    for (int j = tid; j < kk; j += 256) a.zq_part[(long)j * gridDim.x + blockIdx.x] = czs[j];
+    // E^-1 Z^T q over the nonzero columns (twelve per region present; E^-1
+    // symmetric, so column i serves as row i), the twelve loads of a region
+    // issued together
+    const uint32_t mall = gmask_s[0] | gmask_s[1] | gmask_s[2] | gmask_s[3];
+    for (int j = tid; j < kk; j += 256) {
+      double wj = 0.0;
+      for (uint32_t mm = mall; mm; mm &= mm - 1) {
+        const int g = __ffs((int)mm) - 1;
+        double e[12];
+#pragma unroll
+        for (int u = 0; u < 12; ++u) e[u] = a.einv[(long)(((u / 3) * R + g) * 3 + u % 3) * kk + j];
+#pragma unroll
+        for (int u = 0; u < 12; ++u) wj += e[u] * czs[((u / 3) * R + g) * 3 + u % 3];
+      }
+      a.zq_part[(long)j * gridDim.x + blockIdx.x] = czs[j];
+      a.zq_part[(long)(kk + j) * gridDim.x + blockIdx.x] = wj;
+    }
   }
 }
 

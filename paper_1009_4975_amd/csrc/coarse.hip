@@ -213,8 +213,8 @@ int amrto_coarse_setup(amrto_ctx* ctx, int32_t affine, const double* const* fiel
   ctx->coarse_R = R;
   ctx->coarse_affine_only = (affine && n_fields == 0) ? 1 : 0;
   if (!ctx->uniform && ctx->coarse_affine_only) {
-    // partials of Z^T q per operator-pass block (recurrence form)
-    const long need = (long)k * apply_blocks(ctx);
+    // partials of Z^T q and E^-1 Z^T q per operator-pass block (recurrence form)
+    const long need = 2L * k * apply_blocks(ctx);
     if (need > ctx->cq_cap) {
       if (ctx->d_cqpart) (void)hipFree(ctx->d_cqpart);
       ctx->d_cqpart = nullptr;

@@ -87,7 +87,7 @@ struct CgArgs {
   double tol2;
   int coarse = 0;         // r.z = partial sums + scal[S_CTZ]
   // coarse space in recurrence form: r.z = partial sums + ct^T cz, formed
-  // from the ck entries of ct and cz (the block's own copy) by every block
+  // from the ck entries of ct and cz by every block
   const double* cct = nullptr;
   const double* ccz = nullptr;
   int ck = 0;
@@ -190,11 +190,11 @@ struct amrto_ctx {
   double* d_ct = nullptr;      // Z^T r of the current iteration
   double* d_cz = nullptr;      // E^-1 Z^T r
   // recurrence form (octree, affine space): per operator-pass block, the
-  // partials of Z^T q (k x blocks, column-major)
+  // partials of Z^T q and E^-1 Z^T q (2 k x blocks, column-major)
   double* d_cqpart = nullptr;
   long cq_cap = 0;
-  int coarse_exact_it = 0;      // iteration at which ct was last formed from r
-  bool coarse_fresh = false;    // ct was just formed from r (coarse_init)
+  int coarse_exact_it = 0;      // iteration at which ct, cz were last formed from r
+  bool coarse_fresh = false;    // ct, cz were just formed from r (coarse_init)
   // mesh <-> grid transfers (net.hip)
   int grid_cell = 0;
   int32_t* d_node_xyz = nullptr;

@@ -437,20 +437,21 @@ constexpr int CT_REFRESH = 64;
 
 // Update pass of the coarse-space solve in recurrence form (octree mesh,
 // affine space; the operator pass formed the per-block partials of Z^T q and
-// forms cz = E^-1 ct itself).  Blocks below RED_BLOCKS: x += alpha p,
-// r -= alpha q and the partials of r^T M r and r^T r, one node per step (M =
-// the Jacobi diagonal, 3 entries per node, or with B3 the inverse node blocks,
-// 6 entries).  Block RED_BLOCKS + j: ct[j] -= alpha (Z^T q)_j, so that
-// ct = Z^T r holds for the new r up to rounding (ct is formed from r again
-// every CT_REFRESH iterations).
+// E^-1 Z^T q).  Blocks below RED_BLOCKS: x += alpha p, r -= alpha q and the
+// partials of r^T M r and r^T r, one node per step (M = the Jacobi diagonal,
+// 3 entries per node, or with B3 the inverse node blocks, 6 entries).  Block
+// RED_BLOCKS + j: ct[j] -= alpha (Z^T q)_j and cz[j] -= alpha (E^-1 Z^T q)_j,
+// so that ct = Z^T r and cz = E^-1 ct hold for the new r up to rounding (both
+// are formed from r again every CT_REFRESH iterations).
 template <typename VT, bool B3>
 __global__ __launch_bounds__(256) void k_cg_update_rec(VT* __restrict__ x, VT* __restrict__ r,
                                                        const VT* __restrict__ p, const VT* __restrict__ q,
                                                        const VT* __restrict__ minv, long nn,
                                                        const double* __restrict__ part_pq, int n_pq,
                                                        double* __restrict__ scal, int it,
-                                                       const double* __restrict__ qpart, int nb,
-                                                       double* __restrict__ ct, double* __restrict__ part) {
+                                                       const double* __restrict__ qpart, int nb, int kk,
+                                                       double* __restrict__ ct, double* __restrict__ cz,
+                                                       double* __restrict__ part) {
   if (scal[S_DONE] != 0.0) return;
   __shared__ double sh[16];
   constexpr int MW = B3 ? 6 : 3;
@@ -470,9 +471,12 @@ __global__ __launch_bounds__(256) void k_cg_update_rec(VT* __restrict__ x, VT* _
   }
 #pragma unroll
   for (int c = 0; c < MW; ++c) mv[c] = in0 ? minv[MW * i0 + c] : (VT)0;
-  double s1 = 0.0;
+  double s1 = 0.0, s2 = 0.0;
   if (col)
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) s1 += qpart[(long)j * nb + b];
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+      s1 += qpart[(long)j * nb + b];
+      s2 += qpart[(long)(kk + j) * nb + b];
+    }
   const double pq = sum_partials(part_pq, n_pq, sh);
   const double rz = scal[S_RZ0 + (it & 1)];
   if (!(pq > 0.0) || !(pq < 1e300) || !(rz == rz)) {
@@ -481,8 +485,11 @@ __global__ __launch_bounds__(256) void k_cg_update_rec(VT* __restrict__ x, VT* _
   }
   const VT alpha = (VT)(rz / pq);
   if (col) {
-    s1 = block_sum(s1, sh);
-    if (threadIdx.x == 0) ct[j] -= (double)alpha * s1;
+    block_sum2(s1, s2, sh);
+    if (threadIdx.x == 0) {
+      ct[j] -= (double)alpha * s1;
+      cz[j] -= (double)alpha * s2;
+    }
     return;
   }
   double srz = 0.0, srr = 0.0;
@@ -676,13 +683,15 @@ static bool coarse_fused(const amrto_ctx* ctx) {
 // z = D^-1 r + Z cz (overwriting the r.z and r.r partials of k_init; b.b
 // stays) or, in the fused form, ct^T cz in its scalar slot (the partials of
 // k_init already are r^T D^-1 r and r^T r)
-// ct = Z^T r formed from r
+// ct = Z^T r and cz = E^-1 ct (and ct^T cz) formed from r
 template <typename VT>
-static void coarse_ct(amrto_ctx* ctx, const VT* r, const double* stop) {
+static void coarse_exact(amrto_ctx* ctx, const VT* r, const double* stop) {
   hipLaunchKernelGGL(k_zt_part<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, coarse_args(ctx), r,
                      3L * ctx->n_nodes, ctx->d_cpart);
   hipLaunchKernelGGL(k_coarse_sum, dim3(ctx->coarse_k), dim3(256), 0, ctx->stream, ctx->d_cpart, ctx->coarse_k,
                      RED_BLOCKS, ctx->d_ct, stop);
+  hipLaunchKernelGGL(k_coarse_cz, dim3(1), dim3(cz_threads(ctx)), 0, ctx->stream, (const double*)ctx->d_ct,
+                     ctx->coarse_k, (const double*)ctx->d_cinv, ctx->d_cz, ctx->d_scal + S_CTZ, stop);
 }
 
 template <typename VT>
@@ -740,13 +749,13 @@ static int enqueue_iters(amrto_ctx* ctx, const Vecs<VT>& v, VT* x, int prec, dou
   const bool fused = coarse_fused(ctx);
   const bool rec = fused && AMRTO_COARSE_REC && ctx->d_cqpart;
   if (rec) {
-    // ct follows r by a recurrence; every CT_REFRESH iterations it is formed
-    // from r again, so rounding cannot accumulate without bound
+    // ct and cz follow r by recurrences; every CT_REFRESH iterations they are
+    // formed from r again, so rounding cannot accumulate without bound
     if (ctx->coarse_fresh) {
       ctx->coarse_fresh = false;
       ctx->coarse_exact_it = it0;
     } else if (it0 - ctx->coarse_exact_it >= CT_REFRESH) {
-      coarse_ct(ctx, v.r, ctx->d_scal + S_DONE);
+      coarse_exact(ctx, v.r, ctx->d_scal + S_DONE);
       ctx->coarse_exact_it = it0;
     }
   }
@@ -768,12 +777,13 @@ static int enqueue_iters(amrto_ctx* ctx, const Vecs<VT>& v, VT* x, int prec, dou
       if (block3)
         hipLaunchKernelGGL((k_cg_update_rec<VT, true>), dim3(RED_BLOCKS + ctx->coarse_k), dim3(256), 0, ctx->stream,
                            x, v.r, pnew, v.q, binv, (long)ctx->n_nodes, ctx->d_partpq, ctx->n_partpq, ctx->d_scal,
-                           it, (const double*)ctx->d_cqpart, nb, ctx->d_ct, ctx->d_part);
+                           it, (const double*)ctx->d_cqpart, nb, ctx->coarse_k, ctx->d_ct, ctx->d_cz,
+                           ctx->d_part);
       else
         hipLaunchKernelGGL((k_cg_update_rec<VT, false>), dim3(RED_BLOCKS + ctx->coarse_k), dim3(256), 0,
                            ctx->stream, x, v.r, pnew, v.q, (const VT*)v.dinv, (long)ctx->n_nodes, ctx->d_partpq,
-                           ctx->n_partpq, ctx->d_scal, it, (const double*)ctx->d_cqpart, nb, ctx->d_ct,
-                           ctx->d_part);
+                           ctx->n_partpq, ctx->d_scal, it, (const double*)ctx->d_cqpart, nb, ctx->coarse_k,
+                           ctx->d_ct, ctx->d_cz, ctx->d_part);
     } else if (ctx->coarse_k > 0) {
       if (block3)  // coarse_fused holds (checked in amrto_pcg)
         hipLaunchKernelGGL(k_cg_update_coarse_b3<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew,
