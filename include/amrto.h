@@ -253,16 +253,24 @@ int amrto_mask(amrto_ctx* ctx, double* x_dev);
  * motions and the constant strains), then the n_fields caller fields
  * (fields_host: host array of device pointers to 3n FP64 vectors; copied).
  * Every field is masked (zero on supported and hanging DOFs).  At most 8
- * fields in all, and k = 3 rx ry rz (4 affine + n_fields) <= 384.  Z^T A~ Z is formed by k operator applications
- * and factorised on the host, dropping columns whose pivot falls below 1e-12
- * of the largest (*k_kept receives the rank kept; may be NULL).  Needs the
- * density set; amrto_set_density drops the coarse space.
+ * fields in all, and k = 3 rx ry rz (4 affine + n_fields) <= 384.  Z^T A~ Z is
+ * formed on the device (for the affine space alone on an octree mesh in one
+ * pass over the chunks: each forms A~ z_j for the columns whose region meets
+ * it; otherwise by k operator applications) and factorised on the host,
+ * dropping columns whose pivot falls below 1e-12 of the largest (*k_kept
+ * receives the rank kept; may be NULL).  Needs the density set;
+ * amrto_set_density drops the coarse space.
  * Errors: EINVAL (bad sizes, k > 384, a field with non-finite values; the
  * solve then runs without a coarse space), ESTATE, EHIP. */
 int amrto_coarse_setup(amrto_ctx* ctx, int32_t affine, const double* const* fields_host, int32_t n_fields,
                        int32_t rx, int32_t ry, int32_t rz, int32_t* k_kept);
 /* Stop using the coarse space (plain Jacobi again). */
 int amrto_coarse_clear(amrto_ctx* ctx);
+/* The Gram matrix E = Z^T A~ Z of the current coarse space as formed (before
+ * factorisation) into E_host (row-major k x k; cap = its length in doubles),
+ * *k = the coarse dimension.  Errors: ESTATE (no coarse space), EINVAL
+ * (cap < k^2 or NULL arguments). */
+int amrto_coarse_gram(amrto_ctx* ctx, double* E_host, int64_t cap, int32_t* k);
 /* x0 = base + sum_j a_j v_j with a minimising the energy 1/2 x^T A~ x - b^T x
  * (base_dev may be NULL: zero), so x0 is never worse in the energy norm than
  * base or any single v_j.  vecs_host: host array of n (1..8) device pointers;

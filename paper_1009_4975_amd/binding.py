@@ -78,6 +78,7 @@ _SIGS = {
     "amrto_coarse_setup": (C.c_int, [_p, C.c_int32, C.POINTER(_p), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                      _i32p]),
     "amrto_coarse_clear": (C.c_int, [_p]),
+    "amrto_coarse_gram": (C.c_int, [_p, _p, C.c_int64, _i32p]),
     "amrto_energy_combine": (C.c_int, [_p, _p, _p, C.POINTER(_p), C.c_int32, _p, C.POINTER(C.c_double)]),
     "amrto_grid_from_mesh": (C.c_int, [_p, C.c_int32, _p, _p, _p, C.c_double, _p, _p]),
     "amrto_grid_to_mesh": (C.c_int, [_p, C.c_int32, _p, C.c_double, _p]),
@@ -421,6 +422,14 @@ class Context:
 
     def coarse_clear(self):
         self._chk(self.lib.amrto_coarse_clear(self.h))
+
+    def coarse_gram(self):
+        """The Gram matrix Z^T A~ Z of the current coarse space (k x k numpy array)."""
+        k = C.c_int32()
+        cap = 384 * 384
+        buf = np.empty(cap, np.float64)
+        self._chk(self.lib.amrto_coarse_gram(self.h, buf.ctypes.data_as(_p), cap, C.byref(k)))
+        return buf[: k.value * k.value].reshape(k.value, k.value).copy()
 
     def energy_combine(self, b, vecs, x0, base=None):
         n = len(vecs)

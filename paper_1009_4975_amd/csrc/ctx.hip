@@ -97,7 +97,8 @@ static void free_mesh(amrto_ctx* c) {
   c->n_partpq = 0;
   dfree(c->f_b); dfree(c->f_x); dfree(c->f_r); dfree(c->f_z); dfree(c->f_p); dfree(c->f_q);
   dfree(c->d_cf); dfree(c->d_region); dfree(c->d_cpart); dfree(c->d_cinv); dfree(c->d_cz); dfree(c->d_ct);
-  dfree(c->d_cqpart); c->cq_cap = 0; dfree(c->d_cmask); dfree(c->d_cgeo);
+  dfree(c->d_cqpart); c->cq_cap = 0;
+  dfree(c->d_gram_mask); c->gram_mask_cap = 0; dfree(c->d_gram); c->gram_cap = 0; dfree(c->d_cmask); dfree(c->d_cgeo);
   dfree(c->d_node_xyz); dfree(c->d_cell_ptr); dfree(c->d_cell_elem); dfree(c->d_cell_w);
   dfree(c->d_gn_node); dfree(c->d_gn_w);
   c->coarse_k = 0;

@@ -187,12 +187,19 @@ struct amrto_ctx {
   uint8_t* d_region = nullptr; // region of each node
   double* d_cpart = nullptr;   // RED_BLOCKS x COARSE_KMAX partials (block-major)
   double* d_cinv = nullptr;    // E^-1 (k x k)
+  std::vector<double> h_gram;  // E as formed (host copy)
   double* d_ct = nullptr;      // Z^T r of the current iteration
   double* d_cz = nullptr;      // E^-1 Z^T r
   // recurrence form (octree, affine space): per operator-pass block, the
   // partials of Z^T q and E^-1 Z^T q (2 k x blocks, column-major)
   double* d_cqpart = nullptr;
   long cq_cap = 0;
+  // Gram matrix on octree meshes (coarse.hip): region masks per chunk, and
+  // tiles + tile offsets + per-pair tile lists
+  uint32_t* d_gram_mask = nullptr;
+  long gram_mask_cap = 0;
+  void* d_gram = nullptr;
+  size_t gram_cap = 0;
   int coarse_exact_it = 0;      // iteration at which ct, cz were last formed from r
   bool coarse_fresh = false;    // ct, cz were just formed from r (coarse_init)
   // mesh <-> grid transfers (net.hip)

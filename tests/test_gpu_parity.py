@@ -352,3 +352,63 @@ def test_oc_update(pair_rho, volfrac):
         assert got @ p.to_lib_elems(vol) == pytest.approx(volfrac * vol.sum(), rel=1e-11)
     else:
         assert got @ p.to_lib_elems(vol) == pytest.approx(floor, rel=1e-12)
+
+
+def _affine_z(lm, dims, regions):
+    """Z of the affine coarse space in library node order, from its definition:
+    region g of a node from its lattice position, offsets from the region
+    centre scaled by the largest extent and rounded to FP32 once, fields
+    1, d_c, d_(c+1), d_(c+2) for component c, zero on supported and hanging
+    DOFs; column (f, g, c) at (f R + g) 3 + c."""
+    import scipy.sparse as sp
+    rx, ry, rz = regions
+    R = rx * ry * rz
+    n = np.asarray(dims, np.int64)
+    p = np.asarray(lm.node_xyz, np.int64)
+    gd = np.minimum(p * np.array([rx, ry, rz]) // n, np.array([rx, ry, rz]) - 1)
+    g = (gd[:, 2] * ry + gd[:, 1]) * rx + gd[:, 0]
+    s = 1.0 / n.max()
+    d = ((p - (gd + 0.5) * n / np.array([rx, ry, rz])) * s).astype(np.float32).astype(np.float64)
+    off = np.asarray(lm.dof_fixed, bool).reshape(-1, 3).copy()
+    off[np.asarray(lm.hang_node, np.int64)] = True
+    rows, cols, vals = [], [], []
+    nn = len(p)
+    for f in range(4):
+        for c in range(3):
+            val = np.ones(nn) if f == 0 else d[:, (c + f - 1) % 3]
+            keep = ~off[:, c] & (val != 0)
+            v = np.nonzero(keep)[0]
+            rows.append(3 * v + c)
+            cols.append((f * R + g[v]) * 3 + c)
+            vals.append(val[v])
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(3 * nn, 12 * R))
+
+
+@pytest.mark.parametrize("kind,regions", [("octree", (2, 2, 2)), ("octree", (3, 1, 2)), ("octree", (1, 1, 1)),
+                                          ("uniform", (2, 2, 2))])
+def test_coarse_gram_matches_oracle(lib, kind, regions):
+    """E = Z^T A~ Z as the library forms it (one pass over the chunks on an
+    octree mesh, k operator applications on the brick) against Z^T A~ Z with
+    the oracle's assembled operator."""
+    if kind == "uniform":
+        p = cases.uniform_pair((12, 6, 6), bc="bridge")
+        rho = np.random.default_rng(5).uniform(0.01, 1.0, p.orc.n_elems)
+        nx, ny, nz = p.lib_mesh.dims
+        v = np.arange(p.orc.n_nodes)
+        implicit = np.stack([v % (nx + 1), (v // (nx + 1)) % (ny + 1), v // ((nx + 1) * (ny + 1))], 1)
+        assert np.array_equal(np.asarray(p.lib_mesh.node_xyz), implicit)
+    else:
+        p = cases.octree_pair((4, 2, 2), 2, width=0.2)
+        rho = cases.centre_density(p, p.case["field"])
+    ctx = make_ctx(p, rho)
+    ctx.coarse_setup([], *regions, affine=True)
+    E = ctx.coarse_gram()
+    s = cases.oracle_system(p, rho)
+    idx = (3 * p.perm[:, None] + np.arange(3)).ravel()
+    A = s.A[idx][:, idx]
+    Z = _affine_z(p.lib_mesh, p.lib_mesh.dims, regions)
+    want = (Z.T @ (A @ Z)).toarray()
+    assert E.shape == want.shape
+    assert np.max(np.abs(E - want)) <= 1e-12 * np.max(np.abs(want))
+    ctx.coarse_clear()
