@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--solver", choices=[*SOLVERS, "best"],
                     default="best")
+    ap.add_argument("--regions", default="3,2,2",
+                    help="coarse-space regions rx,ry,rz of the octree solves (12 rx ry rz columns)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-c3", action="store_true", help="skip the uniform 192x96x96 apply measurement")
     ap.add_argument("--profile-only", action="store_true", help="only the timed steps (for profilers)")
@@ -177,9 +179,11 @@ def main():
         log(f"[bench] apply source hash {apply_source_hash()}")
         return
 
+    regions = tuple(int(r) for r in args.regions.split(","))
+
     def solve(name):
-        """One solve from zero; with "+coarse" the affine coarse space (2x2x2
-        regions, 96 columns) is built first and its set-up counts in ms; with
+        """One solve from zero; with "+coarse" the affine coarse space (--regions,
+        12 columns per region) is built first and its set-up counts in ms; with
         "+block3" the 3x3 node-block Jacobi preconditioner (its inverse blocks
         are formed on the first solve after a density change, inside ms)."""
         u.zero_()
@@ -187,7 +191,7 @@ def main():
         t0 = time.perf_counter()
         coarse = "+coarse" in name
         if coarse:
-            ctx.coarse_setup([], 2, 2, 2, affine=True)
+            ctx.coarse_setup([], *regions, affine=True)
         torch.cuda.synchronize()
         setup_ms = (time.perf_counter() - t0) * 1e3
         pc = binding.BLOCK3 if "+block3" in name else binding.JACOBI
@@ -279,7 +283,7 @@ def main():
         "config": {"workload": "octree cantilever 16x8x8 base leaves, 3 refinement levels, band-refined and "
                                "2:1 balanced", "elements": ne, "nodes": nn, "dofs": 3 * nn,
                    "hanging_nodes": int(len(mesh.hang_node)), "chunks": info["n_chunks"], "solver": solver,
-                   "rtol": 1e-8, "E0": 1.0, "Emin": 1e-9, "nu": 0.3, "p": 3.0},
+                   "coarse_regions": list(regions) if "+coarse" in solver else None, "rtol": 1e-8, "E0": 1.0, "Emin": 1e-9, "nu": 0.3, "p": 3.0},
         "solve_iters": int(np.median(iters)), "solve_rel_res": float(max(rel)),
         "solve_variants": variants, "roofline": roofline, "apply_uniform_192x96x96": c3, "simp_adaptive_bridge": c4,
         "cpu_baseline": cpu,
