@@ -630,7 +630,29 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   for (int i = tid; i < nt * 3; i += 256) ys[i] = 0.0;
   if (PREC == P_BF16)
     for (int i = tid; i < nent * 8; i += 256) lsm[i] = ca.ent_loc[8L * n0 + i];
+  // recurrence form: the regions of the owned regular nodes (a bitmask), and
+  // the E^-1 columns of the first one requested now, under the element loop
+  __shared__ uint32_t gmask_s[4];
+  uint32_t mall = 0;
+  int g0 = 0;
+  double e0[COARSE ? 12 : 1];
+  if (COARSE && a.zq_part) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int r = 0; r < NPT; ++r)
+      if (tid + 256 * r < nown) m |= 1u << (__float_as_int(gv[r].w) & 31);
+    for (int off = 32; off > 0; off >>= 1) m |= (uint32_t)__shfl_xor((int)m, off, 64);
+    if ((tid & 63) == 0) gmask_s[tid >> 6] = m;
+  }
   __syncthreads();
+  if (COARSE && a.zq_part) {
+    mall = gmask_s[0] | gmask_s[1] | gmask_s[2] | gmask_s[3];
+    g0 = mall ? __ffs((int)mall) - 1 : 0;
+    const int R = a.coarse_R, kk = 12 * R;
+#pragma unroll
+    for (int u = 0; u < 12; ++u)
+      e0[u] = (mall && tid < kk) ? a.einv[(long)(((u / 3) * R + g0) * 3 + u % 3) * kk + tid] : 0.0;
+  }
   for (int i = tid; i < (nt - nreg) * 3; i += 256) {  // x_h = sum_m w_hm x_m  (Eq. (6))
     const int t = nreg + i / 3, comp = i % 3;
     const int kb = hbeg_s[t - nreg], ke = t + 1 < nt ? hbeg_s[t + 1 - nreg] : nh;
@@ -752,19 +774,11 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
     // sum per column, all in fixed order (deterministic).  Columns of absent
     // regions are zero.
     __shared__ double zred[12][16];
-    __shared__ uint32_t gmask_s[4];
     static_assert(TAB_MAX * 3 >= 12 * 256, "the Z^T q columns are staged in ys");
-    const int R = a.coarse_R, kk = 12 * R, lane = tid & 63, wv = tid >> 6;
-    uint32_t m = 0;
-#pragma unroll
-    for (int r = 0; r < NPT; ++r)
-      if (tid + 256 * r < nown) m |= 1u << (__float_as_int(gv[r].w) & 31);
-    for (int off = 32; off > 0; off >>= 1) m |= (uint32_t)__shfl_xor((int)m, off, 64);
-    if (lane == 0) gmask_s[wv] = m;
+    const int R = a.coarse_R, kk = 12 * R;
     for (int j = tid; j < kk; j += 256) czs[j] = 0.0;
     __syncthreads();
-    m = gmask_s[0] | gmask_s[1] | gmask_s[2] | gmask_s[3];
-    for (; m; m &= m - 1) {
+    for (uint32_t m = mall; m; m &= m - 1) {
       const int g = __ffs((int)m) - 1;
       double s[4][3];
 #pragma unroll
@@ -809,15 +823,15 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
     __syncthreads();
     // E^-1 Z^T q over the nonzero columns (twelve per region present; E^-1
     // symmetric, so column i serves as row i), the twelve loads of a region
-    // issued together
-    const uint32_t mall = gmask_s[0] | gmask_s[1] | gmask_s[2] | gmask_s[3];
+    // issued together (those of the first region are already in e0)
     for (int j = tid; j < kk; j += 256) {
       double wj = 0.0;
       for (uint32_t mm = mall; mm; mm &= mm - 1) {
         const int g = __ffs((int)mm) - 1;
         double e[12];
 #pragma unroll
-        for (int u = 0; u < 12; ++u) e[u] = a.einv[(long)(((u / 3) * R + g) * 3 + u % 3) * kk + j];
+        for (int u = 0; u < 12; ++u)
+          e[u] = (g == g0 && j == tid) ? e0[u] : a.einv[(long)(((u / 3) * R + g) * 3 + u % 3) * kk + j];
 #pragma unroll
         for (int u = 0; u < 12; ++u) wj += e[u] * czs[((u / 3) * R + g) * 3 + u % 3];
       }
@@ -860,6 +874,10 @@ __global__ __launch_bounds__(256) void k_diag_chunks(double* __restrict__ dinv, 
                                                      const uint8_t* __restrict__ fix, const double* __restrict__ K0,
                                                      ChunkArgs ca) {
   __shared__ double ds[TAB_MAX * 3];
+  __shared__ uint32_t trip_hm_s[TRIP_MAX];
+  __shared__ double trip_w_s[TRIP_MAX];
+  __shared__ int hbeg_s[TAB_MAX];
+  __shared__ double K0s[576];
   const int c = blockIdx.x;
   if (c >= ca.n_chunks) return;
   const int tid = threadIdx.x;
@@ -868,6 +886,13 @@ __global__ __launch_bounds__(256) void k_diag_chunks(double* __restrict__ dinv, 
   const int nown = ca.chunk_nown[c], nreg = ca.chunk_nreg[c], nhown = ca.chunk_nhown[c];
   const int h0 = ca.chunk_trip[c], nh = ca.chunk_trip[c + 1] - h0;
   for (int i = tid; i < nt * 3; i += 256) ds[i] = 0.0;
+  // the chunk's hanging triples and per-entry triple ranges, and K0, in LDS
+  for (int k = tid; k < nh; k += 256) {
+    trip_hm_s[k] = ca.trip_hm[h0 + k];
+    trip_w_s[k] = ca.trip_w[h0 + k];
+  }
+  for (int t = nreg + tid; t < nt; t += 256) hbeg_s[t - nreg] = ca.tab_hbeg[t0 + t];
+  for (int i = tid; i < 576; i += 256) K0s[i] = K0[i];
   __syncthreads();
   // vertex aa of an entry maps to the masters [kb, ke) of its hanging table
   // entry, or to itself (kb = -1) when regular
@@ -875,8 +900,8 @@ __global__ __launch_bounds__(256) void k_diag_chunks(double* __restrict__ dinv, 
     if (l < nreg) {
       kb = -1; ke = 0;
     } else {
-      kb = ca.tab_hbeg[t0 + l];
-      ke = l + 1 < nt ? ca.tab_hbeg[t0 + l + 1] : nh;
+      kb = hbeg_s[l - nreg];
+      ke = l + 1 < nt ? hbeg_s[l + 1 - nreg] : nh;
     }
   };
   for (int en = tid; en < nent; en += 256) {
@@ -889,18 +914,18 @@ __global__ __launch_bounds__(256) void k_diag_chunks(double* __restrict__ dinv, 
       int ka, kae;
       range(loc[aa], ka, kae);
       for (int k = ka; k < (ka < 0 ? 0 : kae); ++k) {
-        const int ma = ka < 0 ? loc[aa] : (int)(ca.trip_hm[h0 + k] & 0xffff);
-        const double wa = ka < 0 ? 1.0 : ca.trip_w[h0 + k];
+        const int ma = ka < 0 ? loc[aa] : (int)(trip_hm_s[k] & 0xffff);
+        const double wa = ka < 0 ? 1.0 : trip_w_s[k];
         if (ma >= nown) continue;  // only owned rows are written
         double acc[3] = {0.0, 0.0, 0.0};
         for (int bb = 0; bb < 8; ++bb) {
           int kb, kbe;
           range(loc[bb], kb, kbe);
           for (int j = kb; j < (kb < 0 ? 0 : kbe); ++j) {
-            const int mb = kb < 0 ? loc[bb] : (int)(ca.trip_hm[h0 + j] & 0xffff);
+            const int mb = kb < 0 ? loc[bb] : (int)(trip_hm_s[j] & 0xffff);
             if (mb != ma) continue;
-            const double w = wa * (kb < 0 ? 1.0 : ca.trip_w[h0 + j]);
-            for (int cc = 0; cc < 3; ++cc) acc[cc] += w * K0[(3 * aa + cc) * 24 + 3 * bb + cc];
+            const double w = wa * (kb < 0 ? 1.0 : trip_w_s[j]);
+            for (int cc = 0; cc < 3; ++cc) acc[cc] += w * K0s[(3 * aa + cc) * 24 + 3 * bb + cc];
           }
         }
         for (int cc = 0; cc < 3; ++cc) atomicAdd(&ds[ma * 3 + cc], ce * acc[cc]);

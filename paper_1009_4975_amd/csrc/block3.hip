@@ -81,14 +81,19 @@ __global__ __launch_bounds__(256) void k_block_uniform(const double* __restrict_
   finish_block<INV>(B, fix[node], out + (INV ? 6 : 9) * node);
 }
 
-// octree: per chunk, as the exact diagonal (k_diag_chunks) with all nine
-// component pairs; owned rows are finished and written
+// octree: per chunk, as the exact diagonal (k_diag_chunks) with the six
+// component pairs of the symmetric block (00, 11, 22, 01, 02, 12); owned rows
+// are finished and written
 template <bool INV>
 __global__ __launch_bounds__(256) void k_block_chunks(const double* __restrict__ coef,
                                                       const uint8_t* __restrict__ fix,
                                                       const double* __restrict__ K0, double* __restrict__ out,
                                                       ChunkArgs ca) {
-  __shared__ double ds[TAB_MAX * 9];
+  __shared__ double ds[TAB_MAX * 6];
+  __shared__ uint32_t trip_hm_s[TRIP_MAX];
+  __shared__ double trip_w_s[TRIP_MAX];
+  __shared__ int hbeg_s[TAB_MAX];
+  __shared__ double K0s[576];
   const int c = blockIdx.x;
   if (c >= ca.n_chunks) return;
   const int tid = threadIdx.x;
@@ -96,15 +101,22 @@ __global__ __launch_bounds__(256) void k_block_chunks(const double* __restrict__
   const int t0 = ca.chunk_tab[c], nt = ca.chunk_tab[c + 1] - t0;
   const int nown = ca.chunk_nown[c], nreg = ca.chunk_nreg[c], nhown = ca.chunk_nhown[c];
   const int h0 = ca.chunk_trip[c], nh = ca.chunk_trip[c + 1] - h0;
-  for (int i = tid; i < nt * 9; i += 256) ds[i] = 0.0;
+  for (int i = tid; i < nt * 6; i += 256) ds[i] = 0.0;
+  // the chunk's hanging triples and per-entry triple ranges, and K0, in LDS
+  for (int k = tid; k < nh; k += 256) {
+    trip_hm_s[k] = ca.trip_hm[h0 + k];
+    trip_w_s[k] = ca.trip_w[h0 + k];
+  }
+  for (int t = nreg + tid; t < nt; t += 256) hbeg_s[t - nreg] = ca.tab_hbeg[t0 + t];
+  for (int i = tid; i < 576; i += 256) K0s[i] = K0[i];
   __syncthreads();
   auto range = [&](int l, int& kb, int& ke) {
     if (l < nreg) {
       kb = -1;
       ke = 0;
     } else {
-      kb = ca.tab_hbeg[t0 + l];
-      ke = l + 1 < nt ? ca.tab_hbeg[t0 + l + 1] : nh;
+      kb = hbeg_s[l - nreg];
+      ke = l + 1 < nt ? hbeg_s[l + 1 - nreg] : nh;
     }
   };
   for (int en = tid; en < nent; en += 256) {
@@ -117,22 +129,27 @@ __global__ __launch_bounds__(256) void k_block_chunks(const double* __restrict__
       int ka, kae;
       range(loc[aa], ka, kae);
       for (int k = ka; k < (ka < 0 ? 0 : kae); ++k) {
-        const int ma = ka < 0 ? loc[aa] : (int)(ca.trip_hm[h0 + k] & 0xffff);
-        const double wa = ka < 0 ? 1.0 : ca.trip_w[h0 + k];
+        const int ma = ka < 0 ? loc[aa] : (int)(trip_hm_s[k] & 0xffff);
+        const double wa = ka < 0 ? 1.0 : trip_w_s[k];
         if (ma >= nown) continue;  // only owned rows are written
-        double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        double acc[6] = {0, 0, 0, 0, 0, 0};
         for (int bb = 0; bb < 8; ++bb) {
           int kb, kbe;
           range(loc[bb], kb, kbe);
           for (int j = kb; j < (kb < 0 ? 0 : kbe); ++j) {
-            const int mb = kb < 0 ? loc[bb] : (int)(ca.trip_hm[h0 + j] & 0xffff);
+            const int mb = kb < 0 ? loc[bb] : (int)(trip_hm_s[j] & 0xffff);
             if (mb != ma) continue;
-            const double w = wa * (kb < 0 ? 1.0 : ca.trip_w[h0 + j]);
-            for (int cc = 0; cc < 3; ++cc)
-              for (int dd = 0; dd < 3; ++dd) acc[3 * cc + dd] += w * K0[(3 * aa + cc) * 24 + 3 * bb + dd];
+            const double w = wa * (kb < 0 ? 1.0 : trip_w_s[j]);
+            const double* kr = K0s + 3 * aa * 24 + 3 * bb;
+            acc[0] += w * kr[0];
+            acc[1] += w * kr[24 + 1];
+            acc[2] += w * kr[48 + 2];
+            acc[3] += w * kr[1];
+            acc[4] += w * kr[2];
+            acc[5] += w * kr[24 + 2];
           }
         }
-        for (int q = 0; q < 9; ++q) atomicAdd(&ds[ma * 9 + q], ce * acc[q]);
+        for (int q = 0; q < 6; ++q) atomicAdd(&ds[ma * 6 + q], ce * acc[q]);
       }
     }
   }
@@ -145,7 +162,11 @@ __global__ __launch_bounds__(256) void k_block_chunks(const double* __restrict__
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
-      for (int dd = 0; dd < 3; ++dd) B[cc][dd] = hang ? (cc == dd ? 1.0 : 0.0) : ds[tt * 9 + 3 * cc + dd];
+      for (int dd = 0; dd < 3; ++dd) {
+        // pair (cc, dd) in the order 00, 11, 22, 01, 02, 12
+        const int q = cc == dd ? cc : (cc + dd + 2);
+        B[cc][dd] = hang ? (cc == dd ? 1.0 : 0.0) : ds[tt * 6 + q];
+      }
     finish_block<INV>(B, hang ? 0u : (uint32_t)fix[node], out + (INV ? 6 : 9) * node);
   }
 }

@@ -148,11 +148,15 @@ __device__ __forceinline__ double affine_value(int f, int c, const double (&d)[3
 // element products, P^T), then reduces Z^T (A~ z_j) over its owned regular
 // nodes per row region (fixed order: per-thread sums, 16 partials per row,
 // one sum per row).  The results go to 12 x 12 tiles (row region, column
-// region) at the block's tile offset, rows i = f' 3 + c', columns f 3 + cc.
+// region) at the chunk's tile offset, rows i = f' 3 + c', columns f 3 + cc.
+// The twelve columns of a region are split over `split` blocks per chunk
+// (block b: chunk b mod n_chunks, columns (b / n_chunks) + split m), so that
+// chunks met by many regions do not set the launch's length alone.
 __global__ __launch_bounds__(256) void k_gram_chunks(ChunkArgs ca, BrickK<double> kc, const double* __restrict__ coef,
                                                      const uint8_t* __restrict__ fix, const float4* __restrict__ geo,
                                                      const uint32_t* __restrict__ mask,
-                                                     const int32_t* __restrict__ tile_off, double* __restrict__ tiles) {
+                                                     const int32_t* __restrict__ tile_off, double* __restrict__ tiles,
+                                                     int split) {
   __shared__ double xs[TAB_MAX * 3];
   __shared__ double ys[TAB_MAX * 3];
   __shared__ uint32_t trip_hm_s[TRIP_MAX];
@@ -160,8 +164,8 @@ __global__ __launch_bounds__(256) void k_gram_chunks(ChunkArgs ca, BrickK<double
   __shared__ int hbeg_s[TAB_MAX];
   __shared__ double zred[12][16];
   static_assert(TAB_MAX * 3 >= 12 * 256, "the row sums are staged in xs");
-  const int tid = threadIdx.x, c = blockIdx.x;
-  if (c >= ca.n_chunks) return;
+  const int tid = threadIdx.x, c = blockIdx.x % ca.n_chunks, col0 = blockIdx.x / ca.n_chunks;
+  if (col0 >= split) return;
   const int n0 = ca.chunk_ent[c], nent = ca.chunk_ent[c + 1] - n0;
   const int t0 = ca.chunk_tab[c], nt = ca.chunk_tab[c + 1] - t0;
   const int nown = ca.chunk_nown[c], nreg = ca.chunk_nreg[c];
@@ -200,7 +204,7 @@ __global__ __launch_bounds__(256) void k_gram_chunks(ChunkArgs ca, BrickK<double
   int jc = 0;  // column region rank
   for (uint32_t mj = mt; mj; mj &= mj - 1, ++jc) {
     const int gj = __ffs((int)mj) - 1;
-    for (int col = 0; col < 12; ++col) {
+    for (int col = col0; col < 12; col += split) {
       const int f = col / 3, cc = col % 3;
       // z_j on the regular table nodes (zero on supported components)
 #pragma unroll
@@ -452,9 +456,11 @@ static int gram_chunks(amrto_ctx* ctx, int R, double* E_dev) {
   if (ntile)
     AMRTO_HIP(hipMemcpyAsync(d_ptile, ptile.data(), ptile.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                              ctx->stream));
-  hipLaunchKernelGGL(k_gram_chunks, dim3(nc), dim3(256), 0, ctx->stream, chunk_args(ctx), brick_k<double>(ctx),
-                     (const double*)ctx->d_coef, (const uint8_t*)ctx->d_fix, (const float4*)ctx->d_cgeo,
-                     (const uint32_t*)ctx->d_gram_mask, (const int32_t*)d_toff, tiles);
+  constexpr int GRAM_SPLIT = 12;  // one column of each region per block
+  hipLaunchKernelGGL(k_gram_chunks, dim3(nc * GRAM_SPLIT), dim3(256), 0, ctx->stream, chunk_args(ctx),
+                     brick_k<double>(ctx), (const double*)ctx->d_coef, (const uint8_t*)ctx->d_fix,
+                     (const float4*)ctx->d_cgeo, (const uint32_t*)ctx->d_gram_mask, (const int32_t*)d_toff, tiles,
+                     GRAM_SPLIT);
   hipLaunchKernelGGL(k_gram_reduce, dim3(R * R), dim3(256), 0, ctx->stream, (const double*)tiles,
                      (const int32_t*)d_pptr, (const int32_t*)d_ptile, R, E_dev);
   AMRTO_HIP(hipGetLastError());
