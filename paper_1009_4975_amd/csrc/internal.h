@@ -52,7 +52,8 @@ constexpr int TRIP_MAX = 8 * CH_MAX;  // hanging (node, master, weight) triples 
 // same order, so results are deterministic without a separate finalize pass.
 constexpr int RED_BLOCKS = 512;
 constexpr int RED_THREADS = 256;
-constexpr int OC_WS = 2 + 256 * 256 + 64;
+constexpr int OC_WS = 2 + 1024 * 256 + 256 + 64;  // OC search: bracket, 1024 blocks x 256 partial
+                                                   // volumes, 256 candidate volumes
 constexpr int COARSE_KMAX = 384;  // coarse-space columns
 constexpr int COARSE_NFMAX = 8;  // coarse-space fields (4 affine + caller fields)
 

@@ -137,7 +137,9 @@ __global__ __launch_bounds__(256) void k_filter_csr(
 
 // ------------------------------------------------------------------ OC
 constexpr int OC_K = 256;      // candidates per pass
-constexpr int OC_BLOCKS = 256;
+constexpr int OC_BLOCKS = 1024;
+constexpr int OC_TILE = 64;   // elements per block and step of the volume pass
+constexpr int OC_VOL = 2 + OC_BLOCKS * OC_K;
 
 __device__ __forceinline__ double oc_new(double rho, double g, double lam, double eta, double move, double rmin) {
   const double b = g / lam;
@@ -146,7 +148,8 @@ __device__ __forceinline__ double oc_new(double rho, double g, double lam, doubl
   return fmin(fmax(rho * f, lo), hi);
 }
 
-// ws layout: [0] log lo, [1] log hi, [2..] partial volumes OC_BLOCKS x OC_K
+// ws layout: [0] log lo, [1] log hi, [2..] partial volumes OC_K x nblocks
+// (candidate-major), then OC_K candidate volumes at OC_VOL
 __global__ __launch_bounds__(OC_K) void k_oc_volumes(
     const double* __restrict__ rho, const double* __restrict__ dc, const double* __restrict__ vol, int n,
     double eta, double move, double rmin, double* __restrict__ ws) {
@@ -155,27 +158,35 @@ __global__ __launch_bounds__(OC_K) void k_oc_volumes(
   const int j = threadIdx.x;
   const double lam = exp(llo + (lhi - llo) * (double)j / (double)(OC_K - 1));
   double acc = 0.0;
-  for (int base = blockIdx.x * OC_K; base < n; base += gridDim.x * OC_K) {
+  for (int base = blockIdx.x * OC_TILE; base < n; base += gridDim.x * OC_TILE) {
     const int e = base + j;
     __syncthreads();
-    if (e < n) {
+    if (j < OC_TILE && e < n) {
       s_rho[j] = rho[e];
       s_v[j] = vol[e];
       s_g[j] = fmax(-dc[e], 0.0) / vol[e];
     }
     __syncthreads();
-    const int m = min(OC_K, n - base);
+    const int m = min(OC_TILE, n - base);
     for (int t = 0; t < m; ++t) acc += oc_new(s_rho[t], s_g[t], lam, eta, move, rmin) * s_v[t];
   }
-  ws[2 + blockIdx.x * OC_K + j] = acc;
+  ws[2 + (long)j * gridDim.x + blockIdx.x] = acc;
 }
 
-__global__ __launch_bounds__(OC_K) void k_oc_bracket(double* __restrict__ ws, int nblocks, double v0) {
+// volume of candidate j = blockIdx.x: its nblocks partials in a fixed tree
+__global__ __launch_bounds__(256) void k_oc_candsum(double* __restrict__ ws, int nblocks) {
+  __shared__ double sh[8];
+  const int j = blockIdx.x;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += ws[2 + (long)j * nblocks + b];
+  v = block_sum_t(v, sh);
+  if (threadIdx.x == 0) ws[OC_VOL + j] = v;
+}
+
+__global__ __launch_bounds__(OC_K) void k_oc_bracket(double* __restrict__ ws, double v0) {
   __shared__ double s_vol[OC_K];
   const int j = threadIdx.x;
-  double v = 0.0;
-  for (int b = 0; b < nblocks; ++b) v += ws[2 + b * OC_K + j];
-  s_vol[j] = v;
+  s_vol[j] = ws[OC_VOL + j];
   __syncthreads();
   if (j == 0) {
     const double llo = ws[0], lhi = ws[1];
@@ -386,7 +397,7 @@ int amrto_oc_update(amrto_ctx* ctx, const double* rho, const double* dc, double 
     vtot += h * h * h;
   }
   const double v0 = volfrac * vtot;
-  const int nblk = std::min(OC_BLOCKS, (ne + OC_K - 1) / OC_K);
+  const int nblk = std::min(OC_BLOCKS, (ne + OC_TILE - 1) / OC_TILE);
   double* ws = ctx->d_oc;
   // log(lam) in [log 1e-300, log 1e300]; each pass narrows it 255-fold
   hipLaunchKernelGGL(k_init_bracket, dim3(1), dim3(1), 0, ctx->stream, ws, std::log(1e-300), std::log(1e300));
@@ -394,7 +405,8 @@ int amrto_oc_update(amrto_ctx* ctx, const double* rho, const double* dc, double 
   while (width > 1e-14) {
     hipLaunchKernelGGL(k_oc_volumes, dim3(nblk), dim3(OC_K), 0, ctx->stream, rho, dc, ctx->d_vol, ne, eta, move,
                        rho_min, ws);
-    hipLaunchKernelGGL(k_oc_bracket, dim3(1), dim3(OC_K), 0, ctx->stream, ws, nblk, v0);
+    hipLaunchKernelGGL(k_oc_candsum, dim3(OC_K), dim3(256), 0, ctx->stream, ws, nblk);
+    hipLaunchKernelGGL(k_oc_bracket, dim3(1), dim3(OC_K), 0, ctx->stream, ws, v0);
     width /= (OC_K - 1);
   }
   const int g = std::min(256, (ne + 255) / 256);
