@@ -120,6 +120,8 @@ def main():
                     default="best")
     ap.add_argument("--regions", default="3,2,2",
                     help="coarse-space regions rx,ry,rz of the octree solves (12 rx ry rz columns)")
+    ap.add_argument("--c4-regions", default="3,2,2",
+                    help="coarse-space regions of the adaptive SIMP run's coarse variants")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-c3", action="store_true", help="skip the uniform 192x96x96 apply measurement")
     ap.add_argument("--profile-only", action="store_true", help="only the timed steps (for profilers)")
@@ -145,7 +147,8 @@ def main():
         print(json.dumps(apply_uniform_bandwidth(torch, binding, synth, dev)), flush=True)
         return
     if args.c4_only:
-        print(json.dumps(c4_simp(torch, binding, synth)), flush=True)
+        print(json.dumps(c4_simp(torch, binding, synth, tuple(int(r) for r in args.c4_regions.split(",")))),
+              flush=True)
         return
 
     t0 = time.time()
@@ -179,6 +182,7 @@ def main():
         log(f"[bench] apply source hash {apply_source_hash()}")
         return
 
+    c4_regions = tuple(int(r) for r in args.c4_regions.split(","))
     regions = tuple(int(r) for r in args.regions.split(","))
 
     def solve(name):
@@ -268,7 +272,7 @@ def main():
     # --- 50-iteration adaptive SIMP run: plain vs coarse-corrected vs learned
     c4 = None
     if not args.no_c4:
-        c4 = c4_simp(torch, binding, synth)
+        c4 = c4_simp(torch, binding, synth, c4_regions)
 
     # --- CPU oracle on a bounded sample
     cpu = None
@@ -329,7 +333,7 @@ def apply_uniform_bandwidth(torch, binding, synth, dev):
     return res
 
 
-def c4_simp(torch, binding, synth):
+def c4_simp(torch, binding, synth, regions=(2, 2, 2)):
     """The adaptive bridge: 32x16x16 base leaves, 2 refinement levels (finest
     128x64x64), volume fraction 0.25, filter radius 1.5, OC, adapt every 5
     iterations, 50 iterations.  Variants differ only in how iterations 11-50
@@ -358,7 +362,7 @@ def c4_simp(torch, binding, synth):
         # the node-block preconditioner changes nothing else in a run
         mode = {"block3": None, "coarse+block3": "coarse"}.get(mode, mode)
         ws = LearnedWarmStart(case.dims, cell=2, hidden=8, layers=3, epochs=100, seed=ex["net_seed"],
-                              regions=(2, 2, 2)) if mode else None
+                              regions=tuple(regions)) if mode else None
         recs, train_ms = [], 0.0
         for k in range(ex["iters"]):
             if mode == "learned" and k < n_train:

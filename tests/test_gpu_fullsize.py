@@ -2,7 +2,9 @@
 benchmark times, judged by the oracle through what it can afford there:
 
 * C2 (octree cantilever, 61,028 elements, 255,636 DOFs): the GPU solutions
-  (plain FP64 and mixed FP32/BF16 with FP64 reliable updates) are checked
+  (plain FP64, mixed FP32/BF16 with FP64 reliable updates, and the timed
+  configuration: FP32 inner, 3x3 node-block Jacobi and the affine coarse
+  space on 3x2x2 regions in recurrence form; FP64 with the coarse space) are checked
   by the oracle's own element-by-element operator: relative residual of the
   constrained system, compliance f.u equal to u^T K u, and sensitivities of
   sampled elements recomputed one by one from the same u.
@@ -54,7 +56,7 @@ def c2():
     return pair, rho_o, ctx
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "fp32+coarse+block3", "fp64+coarse"])
 def test_c2_solve_judged_by_oracle_operator(c2, prec):
     from paper_1009_4975_amd import binding
     pair, rho_o, ctx = c2
@@ -64,8 +66,15 @@ def test_c2_solve_judged_by_oracle_operator(c2, prec):
     b = torch.empty_like(f)
     ctx.project_rhs(f, b)
     u = torch.zeros_like(f)
-    st = ctx.pcg(b, u, rtol=1e-8, inner_prec={"fp64": binding.FP64, "fp32": binding.FP32, "bf16": binding.BF16}[prec],
-                 inner_rtol=1e-2, max_it=50000)
+    inner = {"fp64": binding.FP64, "fp32": binding.FP32, "bf16": binding.BF16}[prec.split("+")[0]]
+    if "+coarse" in prec:  # as bench.py times it
+        ctx.coarse_setup([], 3, 2, 2, affine=True)
+        st = ctx.pcg(b, u, rtol=1e-8, inner_prec=inner, inner_rtol=0.1, max_it=50000,
+                     precond=binding.BLOCK3 if "+block3" in prec else binding.JACOBI)
+        ctx.coarse_clear()
+        assert st["iters"] < 1000  # the plain solve takes about 2200
+    else:
+        st = ctx.pcg(b, u, rtol=1e-8, inner_prec=inner, inner_rtol=1e-2, max_it=50000)
     assert st["rel_res"] <= 1e-8
     # back to oracle node order; the oracle forms A~ u element by element
     u_o = np.empty(3 * o.n_nodes)
