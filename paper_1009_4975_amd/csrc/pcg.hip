@@ -674,7 +674,9 @@ static int cz_threads(const amrto_ctx* ctx) {
 }
 
 // The affine coarse space on an octree mesh is folded into the operator pass
-// (z = D^-1 r + Z cz formed while staging; r.z = r^T D^-1 r + ct^T cz).
+// (z = M1 r + Z cz formed while staging, M1 the Jacobi diagonal or the inverse
+// node blocks; r.z = r^T M1 r + ct^T cz), in the recurrence form of
+// k_cg_update_rec unless built with AMRTO_COARSE_REC=0.
 static bool coarse_fused(const amrto_ctx* ctx) {
   return ctx->coarse_k > 0 && !ctx->uniform && ctx->coarse_affine_only;
 }
