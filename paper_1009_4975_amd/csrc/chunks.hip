@@ -109,14 +109,98 @@ int build_chunks(amrto_ctx* ctx, const amrto_mesh* m) {
     for (int v = 0; v < nn; ++v) onode[fill[owner[v]]++] = v;
   }
 
+  // Chunk boundaries.  The operator pass of a chunk takes a fixed time plus
+  // time in proportion to its entries and, at half that rate, its hanging
+  // triples (measured on the octree cantilever), and a launch lasts as long
+  // as its heaviest chunk.  Runs of consecutive elements are therefore grown
+  // one element at a time (the entry set and node table followed
+  // incrementally) while the tables fit and that cost stays under a cap; the
+  // cap is the smallest (bisection) that keeps the number of chunks at most
+  // what runs of CH_MAX elements give, rounded up to a multiple of 8 (the
+  // launch grid is rounded so anyway).  Light runs may exceed CH_MAX
+  // elements, up to RUN_MAX, as long as their tables fit.
+  constexpr double W_TRIP = 0.5, W_FIX = 390.0;  // cost per entry = 1
+  constexpr int RUN_MAX = 4 * CH_MAX;
+  std::vector<int> mk_e(ne, -1), mk_n(nn, -1);
+  std::vector<std::pair<int, int>> jr_e, jr_n;  // (index, previous stamp) of one element's additions
+  int stamp = 0;
+  auto plan = [&](double cap, int run_max, long limit, std::vector<int>* ends) -> long {
+    long count = 0;
+    int b = 0;
+    while (b < ne) {
+      const int s = stamp++;
+      long n_ent = 0, n_tab = 0, n_trip = 0;
+      auto add_node = [&](int v) {
+        if (mk_n[v] == s) return;
+        jr_n.push_back({v, mk_n[v]});
+        mk_n[v] = s;
+        ++n_tab;
+        if (hidx[v] >= 0) n_trip += m->hang_ptr[hidx[v] + 1] - m->hang_ptr[hidx[v]];
+      };
+      auto add_ent = [&](int f) {
+        if (mk_e[f] == s) return;
+        jr_e.push_back({f, mk_e[f]});
+        mk_e[f] = s;
+        ++n_ent;
+        for (int a = 0; a < 8; ++a) {
+          const int v = m->elem_nodes[8L * f + a];
+          add_node(v);
+          if (hidx[v] >= 0)
+            for (int k = m->hang_ptr[hidx[v]]; k < m->hang_ptr[hidx[v] + 1]; ++k) add_node(m->hang_master[k]);
+        }
+      };
+      int e = b;
+      while (e < ne && e - b < run_max) {
+        jr_e.clear();
+        jr_n.clear();
+        const long se = n_ent, st = n_tab, sh = n_trip;
+        add_ent(e);
+        for (int k = optr[e]; k < optr[e + 1]; ++k) {
+          const int v = onode[k];
+          if (hidx[v] >= 0) continue;
+          for (int j = nptr[v]; j < nptr[v + 1]; ++j) add_ent(nelem[j]);
+        }
+        const bool fits = n_tab <= TAB_MAX && n_ent <= ENT_MAX && n_trip <= TRIP_MAX;
+        if (!fits || (e > b && W_FIX + n_ent + W_TRIP * n_trip > cap)) {
+          for (const auto& p : jr_e) mk_e[p.first] = p.second;
+          for (const auto& p : jr_n) mk_n[p.first] = p.second;
+          n_ent = se;
+          n_tab = st;
+          n_trip = sh;
+          if (e == b) ++e;  // one element alone does not fit: reported when the chunk is built
+          break;
+        }
+        ++e;
+      }
+      if (ends) ends->push_back(e);
+      if (++count > limit) return count;
+      b = e;
+    }
+    return count;
+  };
+  const long n_fixed = plan(1e300, CH_MAX, ne, nullptr);
+  const long target = (n_fixed + 7) / 8 * 8;
+  double lo = W_FIX, hi = W_FIX + ENT_MAX + W_TRIP * TRIP_MAX + 1.0;
+  const bool balanced = plan(hi, RUN_MAX, target, nullptr) <= target;
+  for (int it = 0; balanced && it < 14 && hi - lo > 0.5; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (plan(mid, RUN_MAX, target, nullptr) <= target) hi = mid;
+    else lo = mid;
+  }
+  std::vector<int> ends;
+  if (balanced) plan(hi, RUN_MAX, ne, &ends);
+  else plan(1e300, CH_MAX, ne, &ends);
+
   Tables T;
   std::vector<int> mark_e(ne, -1), loc(nn, -1);
   int cid = 0;
   std::vector<int> ents, own_reg, own_h, oth_reg, oth_h;
   std::vector<int> nstamp(nn, -1);
   int e0 = 0;
+  size_t run = 0;
   while (e0 < ne) {
-    int e1 = std::min(ne, e0 + CH_MAX);
+    while (run < ends.size() && ends[run] <= e0) ++run;
+    int e1 = run < ends.size() ? ends[run] : ne;
     while (true) {
       // gather the chunk for run [e0, e1)
       ents.clear(); own_reg.clear(); own_h.clear(); oth_reg.clear(); oth_h.clear();
