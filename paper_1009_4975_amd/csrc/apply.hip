@@ -631,11 +631,11 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   if (PREC == P_BF16)
     for (int i = tid; i < nent * 8; i += 256) lsm[i] = ca.ent_loc[8L * n0 + i];
   // recurrence form: the regions of the owned regular nodes (a bitmask), and
-  // the E^-1 columns of the first one requested now, under the element loop
+  // the E^-1 columns of the first two requested now, under the element loop
   __shared__ uint32_t gmask_s[4];
   uint32_t mall = 0;
-  int g0 = 0;
-  double e0[COARSE ? 12 : 1];
+  int g0 = -1, g1 = -1;
+  double e0[COARSE ? 24 : 1];
   if (COARSE && a.zq_part) {
     uint32_t m = 0;
 #pragma unroll
@@ -647,11 +647,15 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   __syncthreads();
   if (COARSE && a.zq_part) {
     mall = gmask_s[0] | gmask_s[1] | gmask_s[2] | gmask_s[3];
-    g0 = mall ? __ffs((int)mall) - 1 : 0;
+    const uint32_t m1 = mall & (mall - 1);
+    g0 = mall ? __ffs((int)mall) - 1 : -1;
+    g1 = m1 ? __ffs((int)m1) - 1 : -1;
     const int R = a.coarse_R, kk = 12 * R;
 #pragma unroll
-    for (int u = 0; u < 12; ++u)
-      e0[u] = (mall && tid < kk) ? a.einv[(long)(((u / 3) * R + g0) * 3 + u % 3) * kk + tid] : 0.0;
+    for (int u = 0; u < 24; ++u) {
+      const int g = u < 12 ? g0 : g1, v = u % 12;
+      e0[u] = (g >= 0 && tid < kk) ? a.einv[(long)(((v / 3) * R + g) * 3 + v % 3) * kk + tid] : 0.0;
+    }
   }
   for (int i = tid; i < (nt - nreg) * 3; i += 256) {  // x_h = sum_m w_hm x_m  (Eq. (6))
     const int t = nreg + i / 3, comp = i % 3;
@@ -768,72 +772,105 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
     if (tid == 0) cg.part_out[cg.part_base + blockIdx.x] = dot;
   }
   if (COARSE && a.zq_part) {
-    // Z^T q over the owned regular nodes, one region present at a time (a
-    // bitmask; usually one region): sums per thread in node order, then
-    // through LDS (ys is free here) 16 partial sums per column and one final
-    // sum per column, all in fixed order (deterministic).  Columns of absent
-    // regions are zero.
+    // Z^T q over the owned regular nodes.  The first region present (a
+    // bitmask; the only one in most chunks) is summed in fixed order: sums
+    // per thread in node order, then through LDS (ys is free here) 16 partial
+    // sums per column and one final sum per column.  Entries of the other
+    // regions (the chunks cut by a region boundary) add their contributions
+    // to their columns with LDS atomics, all in one step, as the element
+    // contributions to ys are added.  Columns of absent regions are zero.
     __shared__ double zred[12][16];
     static_assert(TAB_MAX * 3 >= 12 * 256, "the Z^T q columns are staged in ys");
     const int R = a.coarse_R, kk = 12 * R;
     for (int j = tid; j < kk; j += 256) czs[j] = 0.0;
-    __syncthreads();
-    for (uint32_t m = mall; m; m &= m - 1) {
-      const int g = __ffs((int)m) - 1;
-      double s[4][3];
+    double s[4][3];
 #pragma unroll
-      for (int f = 0; f < 4; ++f)
+    for (int f = 0; f < 4; ++f)
 #pragma unroll
-        for (int c3 = 0; c3 < 3; ++c3) s[f][c3] = 0.0;
+      for (int c3 = 0; c3 < 3; ++c3) s[f][c3] = 0.0;
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+      const int w = __float_as_int(gv[r].w);
+      if (tid + 256 * r < nown && (w & 0xff) == g0) {
+        const double d[3] = {(double)gv[r].x, (double)gv[r].y, (double)gv[r].z};
+#pragma unroll
+        for (int c3 = 0; c3 < 3; ++c3) {
+          const double qc = ((w >> (8 + c3)) & 1) ? 0.0 : (double)qk[r][c3];
+          s[0][c3] += qc;
+          s[1][c3] += qc * d[c3];
+          s[2][c3] += qc * d[c3 == 2 ? 0 : c3 + 1];
+          s[3][c3] += qc * d[c3 == 0 ? 2 : c3 - 1];
+        }
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int c3 = 0; c3 < 3; ++c3) ys[(f * 3 + c3) * 256 + tid] = s[f][c3];
+    __syncthreads();  // also orders the zeroing of czs before the atomics below
+    if (mall & (mall - 1)) {
 #pragma unroll
       for (int r = 0; r < NPT; ++r) {
-        const int w = __float_as_int(gv[r].w);
-        if (tid + 256 * r < nown && (w & 0xff) == g) {
+        const int w = __float_as_int(gv[r].w), g = w & 0xff;
+        if (tid + 256 * r < nown && g != g0) {
           const double d[3] = {(double)gv[r].x, (double)gv[r].y, (double)gv[r].z};
 #pragma unroll
           for (int c3 = 0; c3 < 3; ++c3) {
             const double qc = ((w >> (8 + c3)) & 1) ? 0.0 : (double)qk[r][c3];
-            s[0][c3] += qc;
-            s[1][c3] += qc * d[c3];
-            s[2][c3] += qc * d[c3 == 2 ? 0 : c3 + 1];
-            s[3][c3] += qc * d[c3 == 0 ? 2 : c3 - 1];
+            if (qc == 0.0) continue;
+            atomicAdd(&czs[g * 3 + c3], qc);
+            atomicAdd(&czs[(R + g) * 3 + c3], qc * d[c3]);
+            atomicAdd(&czs[(2 * R + g) * 3 + c3], qc * d[c3 == 2 ? 0 : c3 + 1]);
+            atomicAdd(&czs[(3 * R + g) * 3 + c3], qc * d[c3 == 0 ? 2 : c3 - 1]);
           }
         }
       }
+    }
+    if (tid < 192) {
+      const int u = tid >> 4, sub = tid & 15;
+      double v = 0.0;
 #pragma unroll
-      for (int f = 0; f < 4; ++f)
+      for (int i = 0; i < 16; ++i) v += ys[u * 256 + i * 16 + sub];
+      zred[u][sub] = v;
+    }
+    __syncthreads();
+    if (tid < 12 && g0 >= 0) {
+      double v = 0.0;
 #pragma unroll
-        for (int c3 = 0; c3 < 3; ++c3) ys[(f * 3 + c3) * 256 + tid] = s[f][c3];
-      __syncthreads();
-      if (tid < 192) {
-        const int u = tid >> 4, sub = tid & 15;
-        double v = 0.0;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) v += ys[u * 256 + i * 16 + sub];
-        zred[u][sub] = v;
-      }
-      __syncthreads();
-      if (tid < 12) {
-        double v = 0.0;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) v += zred[tid][i];
-        czs[((tid / 3) * R + g) * 3 + tid % 3] = v;
-      }
+      for (int i = 0; i < 16; ++i) v += zred[tid][i];
+      czs[((tid / 3) * R + g0) * 3 + tid % 3] = v;
     }
     __syncthreads();
     // E^-1 Z^T q over the nonzero columns (twelve per region present; E^-1
-    // symmetric, so column i serves as row i), the twelve loads of a region
-    // issued together (those of the first region are already in e0)
+    // symmetric, so column i serves as row i): those of the first two regions
+    // are in e0 (for j = tid), the others are loaded two regions at a time
     for (int j = tid; j < kk; j += 256) {
       double wj = 0.0;
-      for (uint32_t mm = mall; mm; mm &= mm - 1) {
-        const int g = __ffs((int)mm) - 1;
-        double e[12];
+      uint32_t rest = mall;
+      if (j == tid) {
 #pragma unroll
-        for (int u = 0; u < 12; ++u)
-          e[u] = (g == g0 && j == tid) ? e0[u] : a.einv[(long)(((u / 3) * R + g) * 3 + u % 3) * kk + j];
+        for (int u = 0; u < 24; ++u) {
+          const int g = u < 12 ? g0 : g1, v = u % 12;
+          if (g >= 0) wj += e0[u] * czs[((v / 3) * R + g) * 3 + v % 3];
+        }
+        rest &= ~((g0 >= 0 ? 1u << g0 : 0u) | (g1 >= 0 ? 1u << g1 : 0u));
+      }
+      while (rest) {
+        const int ga = __ffs((int)rest) - 1;
+        rest &= rest - 1;
+        const int gb = rest ? __ffs((int)rest) - 1 : -1;
+        if (gb >= 0) rest &= rest - 1;
+        double e[24];
 #pragma unroll
-        for (int u = 0; u < 12; ++u) wj += e[u] * czs[((u / 3) * R + g) * 3 + u % 3];
+        for (int u = 0; u < 24; ++u) {
+          const int g = u < 12 ? ga : gb, v = u % 12;
+          e[u] = g >= 0 ? a.einv[(long)(((v / 3) * R + g) * 3 + v % 3) * kk + j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 24; ++u) {
+          const int g = u < 12 ? ga : gb, v = u % 12;
+          if (g >= 0) wj += e[u] * czs[((v / 3) * R + g) * 3 + v % 3];
+        }
       }
       a.zq_part[(long)j * gridDim.x + blockIdx.x] = czs[j];
       a.zq_part[(long)(kk + j) * gridDim.x + blockIdx.x] = wj;
