@@ -508,24 +508,26 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   VT* __restrict__ PN = (VT*)a.pnew;
   const VT* __restrict__ coef = (const VT*)a.coef;
   const uint8_t* __restrict__ fix = a.fix;
-  const int n0 = ca.chunk_ent[cc], nent = have ? ca.chunk_ent[cc + 1] - n0 : 0;
-  const int t0 = ca.chunk_tab[cc], nt = have ? ca.chunk_tab[cc + 1] - t0 : 0;
   // surplus workgroups (the grid is rounded up to a multiple of 8) own nothing
-  const int nown = have ? ca.chunk_nown[cc] : 0, nreg = have ? ca.chunk_nreg[cc] : 0;
-  const int nhown = have ? ca.chunk_nhown[cc] : 0;
-  const int h0 = ca.chunk_trip[cc], nh = have ? ca.chunk_trip[cc + 1] - h0 : 0;
+  const ChunkDims cd = chunk_dims(ca, cc, have);
+  const int n0 = cd.n0, nent = cd.nent, t0 = cd.t0, nt = cd.nt, h0 = cd.h0, nh = cd.nh;
+  const int nown = cd.nown, nreg = cd.nreg, nhown = cd.nhown;
   // Every index this block needs is requested before the CG prologue (which
-  // waits on the previous pass's partial sums), so those round trips overlap.
-  // Table nodes t = tid + 256 r (r < NPT): global node, support bits and the
-  // staged values are loaded in one batch (no dependent round trips per
-  // component), and the indices stay in registers for the store phase.
+  // waits on the previous pass's partial sums), so those round trips overlap;
+  // the table and entry slots are read whole (the chunk's slots sit at fixed
+  // strides, zero padded), so these loads go out with the count loads rather
+  // than after them.  Table nodes t = tid + 256 r (r < NPT): global node,
+  // support bits and the staged values are loaded in one batch (no dependent
+  // round trips per component), and the indices stay in registers for the
+  // store phase.
   constexpr int NPT = TAB_MAX / 256;
   int gn[NPT];
   uint8_t fb[NPT];
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
     const int t = tid + 256 * r;
-    gn[r] = t < nt ? ca.tab_node[t0 + t] : -1;
+    const int g = ca.tab_node[t0 + t];
+    gn[r] = t < nt ? g : -1;
   }
   // entry metadata of the element loop, prefetched under the staging latency
   constexpr int EPT = ENT_MAX / 256;
@@ -534,15 +536,22 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
 #pragma unroll
   for (int r = 0; r < EPT; ++r) {
     const int en = tid + 256 * r;
-    eel[r] = en < nent ? ca.ent_elem[n0 + en] : 0;
-    lvp[r] = en < nent ? *reinterpret_cast<const uint4*>(ca.ent_loc + 8L * (n0 + en)) : make_uint4(0, 0, 0, 0);
+    eel[r] = ca.ent_elem[n0 + en];
+    lvp[r] = *reinterpret_cast<const uint4*>(ca.ent_loc + 8L * (n0 + en));
   }
-  // hanging triples and per-entry triple ranges into LDS
-  for (int k = tid; k < nh; k += 256) {
-    trip_hm_s[k] = ca.trip_hm[h0 + k];
-    trip_w_s[k] = ca.trip_w[h0 + k];
+  // hanging triples and per-entry triple ranges, whole slots; written to LDS
+  // once the vector values below are requested
+  constexpr int HPT = TRIP_MAX / 256;
+  uint32_t thm[HPT];
+  double tw[HPT];
+  int hbr[NPT];
+#pragma unroll
+  for (int q = 0; q < HPT; ++q) {
+    thm[q] = ca.trip_hm[h0 + tid + 256 * q];
+    tw[q] = ca.trip_w[h0 + tid + 256 * q];
   }
-  for (int t = nreg + tid; t < nt; t += 256) hbeg_s[t - nreg] = ca.tab_hbeg[t0 + t];
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) hbr[r] = ca.tab_hbeg[t0 + tid + 256 * r];
   // raw vector values of the regular table nodes, also requested before the
   // prologue; beta is applied once the prologue has it
   const bool first = FUSED && cg.it == 0;
@@ -579,6 +588,16 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   VT cep[EPT];
 #pragma unroll
   for (int r = 0; r < EPT; ++r) cep[r] = coef[eel[r]];
+#pragma unroll
+  for (int q = 0; q < HPT; ++q) {
+    trip_hm_s[tid + 256 * q] = thm[q];
+    trip_w_s[tid + 256 * q] = tw[q];
+  }
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) {
+    const int t = tid + 256 * r;
+    if (t >= nreg && t < nt) hbeg_s[t - nreg] = hbr[r];
+  }
   __shared__ double czs[COARSE ? COARSE_KMAX : 1];
   CgArgs cgb = cg;
   if (COARSE) {
@@ -918,10 +937,9 @@ __global__ __launch_bounds__(256) void k_diag_chunks(double* __restrict__ dinv, 
   const int c = blockIdx.x;
   if (c >= ca.n_chunks) return;
   const int tid = threadIdx.x;
-  const int n0 = ca.chunk_ent[c], nent = ca.chunk_ent[c + 1] - n0;
-  const int t0 = ca.chunk_tab[c], nt = ca.chunk_tab[c + 1] - t0;
-  const int nown = ca.chunk_nown[c], nreg = ca.chunk_nreg[c], nhown = ca.chunk_nhown[c];
-  const int h0 = ca.chunk_trip[c], nh = ca.chunk_trip[c + 1] - h0;
+  const ChunkDims cd = chunk_dims(ca, c);
+  const int n0 = cd.n0, nent = cd.nent, t0 = cd.t0, nt = cd.nt, h0 = cd.h0, nh = cd.nh;
+  const int nown = cd.nown, nreg = cd.nreg, nhown = cd.nhown;
   for (int i = tid; i < nt * 3; i += 256) ds[i] = 0.0;
   // the chunk's hanging triples and per-entry triple ranges, and K0, in LDS
   for (int k = tid; k < nh; k += 256) {

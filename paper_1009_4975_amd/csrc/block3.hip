@@ -97,10 +97,9 @@ __global__ __launch_bounds__(256) void k_block_chunks(const double* __restrict__
   const int c = blockIdx.x;
   if (c >= ca.n_chunks) return;
   const int tid = threadIdx.x;
-  const int n0 = ca.chunk_ent[c], nent = ca.chunk_ent[c + 1] - n0;
-  const int t0 = ca.chunk_tab[c], nt = ca.chunk_tab[c + 1] - t0;
-  const int nown = ca.chunk_nown[c], nreg = ca.chunk_nreg[c], nhown = ca.chunk_nhown[c];
-  const int h0 = ca.chunk_trip[c], nh = ca.chunk_trip[c + 1] - h0;
+  const ChunkDims cd = chunk_dims(ca, c);
+  const int n0 = cd.n0, nent = cd.nent, t0 = cd.t0, nt = cd.nt, h0 = cd.h0, nh = cd.nh;
+  const int nown = cd.nown, nreg = cd.nreg, nhown = cd.nhown;
   for (int i = tid; i < nt * 6; i += 256) ds[i] = 0.0;
   // the chunk's hanging triples and per-entry triple ranges, and K0, in LDS
   for (int k = tid; k < nh; k += 256) {

@@ -97,11 +97,9 @@ __global__ __launch_bounds__(256) void k_cg1_chunks(Cg1Vecs<VT> v, ChunkArgs ca,
   const int c = xcd_remap(blockIdx.x, gridDim.x);
   const bool have = c < ca.n_chunks;
   const int cc = have ? c : 0;
-  const int n0 = ca.chunk_ent[cc], nent = have ? ca.chunk_ent[cc + 1] - n0 : 0;
-  const int t0 = ca.chunk_tab[cc], nt = have ? ca.chunk_tab[cc + 1] - t0 : 0;
-  const int nown = have ? ca.chunk_nown[cc] : 0, nreg = have ? ca.chunk_nreg[cc] : 0;
-  const int nhown = have ? ca.chunk_nhown[cc] : 0;
-  const int h0 = ca.chunk_trip[cc], nh = have ? ca.chunk_trip[cc + 1] - h0 : 0;
+  const ChunkDims cd = chunk_dims(ca, cc, have);
+  const int n0 = cd.n0, nent = cd.nent, t0 = cd.t0, nt = cd.nt, h0 = cd.h0, nh = cd.nh;
+  const int nown = cd.nown, nreg = cd.nreg, nhown = cd.nhown;
   const bool first = g.it == 0;
   // every index and vector value is requested before the reduction of the
   // previous pass's partials (which waits on memory), as in k_apply_chunks

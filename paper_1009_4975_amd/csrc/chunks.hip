@@ -33,7 +33,7 @@ hipError_t upload(V*& dst, const std::vector<V>& v) {
 }
 
 struct Tables {
-  std::vector<int32_t> chunk_ent{0}, chunk_tab{0}, chunk_trip{0}, chunk_nown, chunk_nreg, chunk_nhown;
+  std::vector<int32_t> chunk_cnt;  // 8 per chunk
   std::vector<int32_t> ent_elem, tab_node, tab_hbeg;
   std::vector<uint16_t> ent_loc;
   std::vector<uint32_t> trip_hm;
@@ -198,6 +198,7 @@ int build_chunks(amrto_ctx* ctx, const amrto_mesh* m) {
   std::vector<int> nstamp(nn, -1);
   int e0 = 0;
   size_t run = 0;
+  long n_real_entries = 0;
   while (e0 < ne) {
     while (run < ends.size() && ends[run] <= e0) ++run;
     int e1 = run < ends.size() ? ends[run] : ne;
@@ -252,43 +253,48 @@ int build_chunks(amrto_ctx* ctx, const amrto_mesh* m) {
     for (int v : own_h) loc[v] = t++;
     for (int v : oth_h) loc[v] = t++;
     std::sort(ents.begin(), ents.end());
-    for (int e : ents) {
-      T.ent_elem.push_back(e);
-      for (int a = 0; a < 8; ++a) T.ent_loc.push_back((uint16_t)loc[m->elem_nodes[8L * e + a]]);
+    // this chunk's slots at fixed strides, zero padded (kc = chunks so far)
+    const size_t kc = T.chunk_cnt.size() / 8;
+    const size_t eb = kc * ENT_MAX, tb = kc * TAB_MAX, hb = kc * TRIP_MAX;
+    T.ent_elem.resize(eb + ENT_MAX, 0);
+    T.ent_loc.resize(8 * (eb + ENT_MAX), 0);
+    T.tab_node.resize(tb + TAB_MAX, 0);
+    T.tab_hbeg.resize(tb + TAB_MAX, 0);
+    T.trip_hm.resize(hb + TRIP_MAX, 0);
+    T.trip_w.resize(hb + TRIP_MAX, 0.0);
+    for (size_t i = 0; i < ents.size(); ++i) {
+      const int e = ents[i];
+      T.ent_elem[eb + i] = e;
+      for (int a = 0; a < 8; ++a) T.ent_loc[8 * (eb + i) + a] = (uint16_t)loc[m->elem_nodes[8L * e + a]];
     }
-    for (int v : own_reg) T.tab_node.push_back(v);
-    for (int v : oth_reg) T.tab_node.push_back(v);
-    for (int v : own_h) T.tab_node.push_back(v);
-    for (int v : oth_h) T.tab_node.push_back(v);
-    T.tab_hbeg.resize(T.tab_node.size(), -1);
-    const int trip0 = (int)T.trip_hm.size();
+    {
+      size_t i = tb;
+      for (int v : own_reg) T.tab_node[i++] = v;
+      for (int v : oth_reg) T.tab_node[i++] = v;
+      for (int v : own_h) T.tab_node[i++] = v;
+      for (int v : oth_h) T.tab_node[i++] = v;
+    }
+    int ntrip = 0;
     auto add_trips = [&](const std::vector<int>& hs) {
       for (int h : hs) {
-        T.tab_hbeg[T.chunk_tab.back() + loc[h]] = (int)T.trip_hm.size() - trip0;
+        T.tab_hbeg[tb + loc[h]] = ntrip;
         for (int k = m->hang_ptr[hidx[h]]; k < m->hang_ptr[hidx[h] + 1]; ++k) {
-          T.trip_hm.push_back(((uint32_t)loc[h] << 16) | (uint32_t)loc[m->hang_master[k]]);
-          T.trip_w.push_back(m->hang_w[k]);
+          T.trip_hm[hb + ntrip] = ((uint32_t)loc[h] << 16) | (uint32_t)loc[m->hang_master[k]];
+          T.trip_w[hb + ntrip] = m->hang_w[k];
+          ++ntrip;
         }
       }
     };
     add_trips(own_h);
     add_trips(oth_h);
-    T.chunk_nown.push_back((int)own_reg.size());
-    T.chunk_nreg.push_back(nreg);
-    T.chunk_nhown.push_back((int)own_h.size());
-    T.chunk_ent.push_back((int)T.ent_elem.size());
-    T.chunk_tab.push_back((int)T.tab_node.size());
-    T.chunk_trip.push_back((int)T.trip_hm.size());
+    const int cnt[8] = {(int)ents.size(), t, ntrip, (int)own_reg.size(), nreg, (int)own_h.size(), 0, 0};
+    T.chunk_cnt.insert(T.chunk_cnt.end(), cnt, cnt + 8);
+    n_real_entries += (long)ents.size();
     ++cid;
     e0 = e1;
   }
-  const int nc = (int)T.chunk_nown.size();
-  AMRTO_HIP(upload(ctx->d_chunk_ent, T.chunk_ent));
-  AMRTO_HIP(upload(ctx->d_chunk_tab, T.chunk_tab));
-  AMRTO_HIP(upload(ctx->d_chunk_trip, T.chunk_trip));
-  AMRTO_HIP(upload(ctx->d_chunk_nown, T.chunk_nown));
-  AMRTO_HIP(upload(ctx->d_chunk_nreg, T.chunk_nreg));
-  AMRTO_HIP(upload(ctx->d_chunk_nhown, T.chunk_nhown));
+  const int nc = (int)(T.chunk_cnt.size() / 8);
+  AMRTO_HIP(upload(ctx->d_chunk_cnt, T.chunk_cnt));
   AMRTO_HIP(upload(ctx->d_ent_elem, T.ent_elem));
   AMRTO_HIP(upload(ctx->d_ent_loc, T.ent_loc));
   AMRTO_HIP(upload(ctx->d_tab_node, T.tab_node));
@@ -331,7 +337,7 @@ int build_chunks(amrto_ctx* ctx, const amrto_mesh* m) {
   AMRTO_HIP(upload(ctx->d_mt_w, mt_w));
   ctx->n_mt = (int)mt_node.size();
   ctx->n_chunks = nc;
-  ctx->n_entries = (int)T.ent_elem.size();
+  ctx->n_entries = (int)n_real_entries;
   ctx->n_hang = m->n_hang;
   return AMRTO_OK;
 }

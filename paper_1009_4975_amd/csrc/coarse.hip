@@ -120,7 +120,8 @@ __global__ __launch_bounds__(256) void k_gram_masks(ChunkArgs ca, const float4* 
   if (c >= ca.n_chunks) return;
   if (threadIdx.x == 0) m[0] = m[1] = 0u;
   __syncthreads();
-  const int t0 = ca.chunk_tab[c], nreg = ca.chunk_nreg[c], nown = ca.chunk_nown[c];
+  const ChunkDims cd = chunk_dims(ca, c);
+  const int t0 = cd.t0, nreg = cd.nreg, nown = cd.nown;
   uint32_t mt = 0, mo = 0;
   for (int t = threadIdx.x; t < nreg; t += blockDim.x) {
     const uint32_t bit = 1u << (__float_as_int(geo[ca.tab_node[t0 + t]].w) & 31);
@@ -166,10 +167,9 @@ __global__ __launch_bounds__(256) void k_gram_chunks(ChunkArgs ca, BrickK<double
   static_assert(TAB_MAX * 3 >= 12 * 256, "the row sums are staged in xs");
   const int tid = threadIdx.x, c = blockIdx.x % ca.n_chunks, col0 = blockIdx.x / ca.n_chunks;
   if (col0 >= split) return;
-  const int n0 = ca.chunk_ent[c], nent = ca.chunk_ent[c + 1] - n0;
-  const int t0 = ca.chunk_tab[c], nt = ca.chunk_tab[c + 1] - t0;
-  const int nown = ca.chunk_nown[c], nreg = ca.chunk_nreg[c];
-  const int h0 = ca.chunk_trip[c], nh = ca.chunk_trip[c + 1] - h0;
+  const ChunkDims cd = chunk_dims(ca, c);
+  const int n0 = cd.n0, nent = cd.nent, t0 = cd.t0, nt = cd.nt, h0 = cd.h0, nh = cd.nh;
+  const int nown = cd.nown, nreg = cd.nreg;
   const uint32_t mt = mask[2 * c], mo = mask[2 * c + 1];
   if (!mt || !mo) return;  // no tiles
   const int nct = __popc(mt);

@@ -80,8 +80,7 @@ static hipError_t dalloc(T*& p, size_t n) {
 
 static void free_mesh(amrto_ctx* c) {
   dfree(c->d_fix); dfree(c->d_level); dfree(c->d_elem_nodes);
-  dfree(c->d_chunk_ent); dfree(c->d_chunk_tab); dfree(c->d_chunk_trip); dfree(c->d_chunk_nown);
-  dfree(c->d_chunk_nreg); dfree(c->d_chunk_nhown); dfree(c->d_ent_elem); dfree(c->d_ent_loc);
+  dfree(c->d_chunk_cnt); dfree(c->d_ent_elem); dfree(c->d_ent_loc);
   dfree(c->d_tab_node); dfree(c->d_trip_hm); dfree(c->d_trip_w); dfree(c->d_tab_hbeg);
   dfree(c->d_hang_node); dfree(c->d_hang_ptr); dfree(c->d_hang_master); dfree(c->d_hang_w);
   dfree(c->d_mt_node); dfree(c->d_mt_ptr); dfree(c->d_mt_h); dfree(c->d_mt_w);

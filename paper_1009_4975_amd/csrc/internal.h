@@ -125,14 +125,10 @@ struct amrto_ctx {
   int32_t* d_elem_nodes = nullptr; // octree only
   // octree node-owner chunks (chunks.hip)
   int n_entries = 0;                 // chunk elements including halo elements
-  int32_t* d_chunk_ent = nullptr;    // [n_chunks + 1] entry ranges
-  int32_t* d_chunk_tab = nullptr;    // [n_chunks + 1] table ranges
-  int32_t* d_chunk_trip = nullptr;   // [n_chunks + 1] hanging triple ranges
-  int32_t* d_chunk_nown = nullptr;   // [n_chunks] owned regular table entries
-  int32_t* d_chunk_nreg = nullptr;   // [n_chunks] regular table entries
-  int32_t* d_chunk_nhown = nullptr;  // [n_chunks] owned hanging table entries
+  int32_t* d_chunk_cnt = nullptr;    // [8 n_chunks] entries, table, triples, owned regular, regular, owned hanging
+  // per chunk at fixed strides (ENT_MAX, TAB_MAX, TRIP_MAX), zero padded:
   int32_t* d_ent_elem = nullptr;     // element of each entry
-  uint16_t* d_ent_loc = nullptr;     // [8 n_entries] table index per local vertex
+  uint16_t* d_ent_loc = nullptr;     // [8 per entry] table index per local vertex
   int32_t* d_tab_node = nullptr;     // global node per table entry
   uint32_t* d_trip_hm = nullptr;     // (h_loc << 16) | m_loc
   double* d_trip_w = nullptr;

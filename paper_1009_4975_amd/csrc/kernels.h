@@ -210,13 +210,12 @@ __device__ __forceinline__ void contract_brick(const T (&k)[8], const T (&u)[24]
 
 
 // ------------------------------------------------------------------ octree chunk tables
+// Chunk c's entries, table and hanging triples sit at fixed strides (c
+// ENT_MAX, c TAB_MAX, c TRIP_MAX; the tails are padded with zeros), so their
+// addresses follow from c alone and a kernel can request them together with
+// the chunk's counts instead of after them.
 struct ChunkArgs {
-  const int32_t* chunk_ent;   // [n_chunks + 1] entry ranges
-  const int32_t* chunk_tab;   // [n_chunks + 1] table ranges
-  const int32_t* chunk_trip;  // [n_chunks + 1] hanging triple ranges
-  const int32_t* chunk_nown;  // owned regular entries (table prefix)
-  const int32_t* chunk_nreg;  // regular entries
-  const int32_t* chunk_nhown; // owned hanging entries (after the regular ones)
+  const int4* chunk_cnt;      // [2 n_chunks]: (entries, table, triples, owned regular), (regular, owned hanging, -, -)
   const int32_t* ent_elem;
   const uint16_t* ent_loc;
   const int32_t* tab_node;
@@ -225,6 +224,26 @@ struct ChunkArgs {
   const int32_t* tab_hbeg;    // hanging entries: first triple (chunk-relative)
   int n_chunks;
 };
+
+struct ChunkDims {
+  int n0, nent, t0, nt, h0, nh, nown, nreg, nhown;
+};
+
+// bases and counts of chunk c (counts zero for a surplus workgroup, have = false)
+__device__ __forceinline__ ChunkDims chunk_dims(const ChunkArgs& ca, int c, bool have = true) {
+  ChunkDims d;
+  d.n0 = c * ENT_MAX;
+  d.t0 = c * TAB_MAX;
+  d.h0 = c * TRIP_MAX;
+  const int4 a = ca.chunk_cnt[2 * c], b = ca.chunk_cnt[2 * c + 1];
+  d.nent = have ? a.x : 0;
+  d.nt = have ? a.y : 0;
+  d.nh = have ? a.z : 0;
+  d.nown = have ? a.w : 0;
+  d.nreg = have ? b.x : 0;
+  d.nhown = have ? b.y : 0;
+  return d;
+}
 
 template <typename VT>
 inline BrickK<VT> brick_k(const amrto_ctx* ctx) {
@@ -235,8 +254,7 @@ inline BrickK<VT> brick_k(const amrto_ctx* ctx) {
 
 inline ChunkArgs chunk_args(amrto_ctx* ctx) {
   ChunkArgs a;
-  a.chunk_ent = ctx->d_chunk_ent; a.chunk_tab = ctx->d_chunk_tab; a.chunk_trip = ctx->d_chunk_trip;
-  a.chunk_nown = ctx->d_chunk_nown; a.chunk_nreg = ctx->d_chunk_nreg; a.chunk_nhown = ctx->d_chunk_nhown;
+  a.chunk_cnt = (const int4*)ctx->d_chunk_cnt;
   a.ent_elem = ctx->d_ent_elem; a.ent_loc = ctx->d_ent_loc; a.tab_node = ctx->d_tab_node;
   a.trip_hm = ctx->d_trip_hm; a.trip_w = ctx->d_trip_w; a.tab_hbeg = ctx->d_tab_hbeg;
   a.n_chunks = ctx->n_chunks;
