@@ -513,13 +513,14 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   const int n0 = cd.n0, nent = cd.nent, t0 = cd.t0, nt = cd.nt, h0 = cd.h0, nh = cd.nh;
   const int nown = cd.nown, nreg = cd.nreg, nhown = cd.nhown;
   // Every index this block needs is requested before the CG prologue (which
-  // waits on the previous pass's partial sums), so those round trips overlap;
-  // the table and entry slots are read whole (the chunk's slots sit at fixed
-  // strides, zero padded), so these loads go out with the count loads rather
-  // than after them.  Table nodes t = tid + 256 r (r < NPT): global node,
-  // support bits and the staged values are loaded in one batch (no dependent
-  // round trips per component), and the indices stay in registers for the
-  // store phase.
+  // waits on the previous pass's partial sums), so those round trips overlap.
+  // The node-table slot is read whole (the chunk's slots sit at fixed strides,
+  // zero padded), so it goes out with the count loads rather than after them:
+  // the staged vector values depend on it.  Entries and hanging triples are
+  // needed later and are read only up to their counts.  Table nodes
+  // t = tid + 256 r (r < NPT): global node, support bits and the staged values
+  // are loaded in one batch (no dependent round trips per component), and the
+  // indices stay in registers for the store phase.
   constexpr int NPT = TAB_MAX / 256;
   int gn[NPT];
   uint8_t fb[NPT];
@@ -536,8 +537,12 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
 #pragma unroll
   for (int r = 0; r < EPT; ++r) {
     const int en = tid + 256 * r;
-    eel[r] = ca.ent_elem[n0 + en];
-    lvp[r] = *reinterpret_cast<const uint4*>(ca.ent_loc + 8L * (n0 + en));
+    eel[r] = 0;
+    lvp[r] = make_uint4(0u, 0u, 0u, 0u);
+    if (en < nent) {
+      eel[r] = ca.ent_elem[n0 + en];
+      lvp[r] = *reinterpret_cast<const uint4*>(ca.ent_loc + 8L * (n0 + en));
+    }
   }
   // hanging triples and per-entry triple ranges, whole slots; written to LDS
   // once the vector values below are requested
@@ -547,11 +552,18 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   int hbr[NPT];
 #pragma unroll
   for (int q = 0; q < HPT; ++q) {
-    thm[q] = ca.trip_hm[h0 + tid + 256 * q];
-    tw[q] = ca.trip_w[h0 + tid + 256 * q];
+    thm[q] = 0u;
+    tw[q] = 0.0;
+    if (tid + 256 * q < nh) {
+      thm[q] = ca.trip_hm[h0 + tid + 256 * q];
+      tw[q] = ca.trip_w[h0 + tid + 256 * q];
+    }
   }
 #pragma unroll
-  for (int r = 0; r < NPT; ++r) hbr[r] = ca.tab_hbeg[t0 + tid + 256 * r];
+  for (int r = 0; r < NPT; ++r) {
+    const int t = tid + 256 * r;
+    hbr[r] = (t >= nreg && t < nt) ? ca.tab_hbeg[t0 + t] : 0;
+  }
   // raw vector values of the regular table nodes, also requested before the
   // prologue; beta is applied once the prologue has it
   const bool first = FUSED && cg.it == 0;
