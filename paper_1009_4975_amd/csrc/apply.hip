@@ -488,8 +488,15 @@ __global__ __launch_bounds__(BTHREADS, BrickOcc<VT>::blocks) void k_apply_brick(
 
 // COARSE: 0 plain; 1 stage p from z = D^-1 r + Z cz; 2 the same with the
 // inverse 3x3 node blocks (six entries per node in a.dinv) in place of D^-1
+// Threads per workgroup of the octree operator pass.  The LDS of a chunk
+// allows two workgroups per CU; with 512 threads that is four waves per SIMD
+// (twice the latency hiding of 256, and half the per-thread staging, element
+// and store work), which needs at most 128 VGPRs: the FP64 and BF16
+// coarse-space variants need more and keep 256.
+constexpr int chunk_threads(int prec, int coarse) { return (coarse && prec != P_F32) ? 256 : 512; }
+
 template <typename VT, int PREC, bool FUSED, int COARSE = 0>
-__global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, BrickK<VT> kc, CgArgs cg) {
+__global__ __launch_bounds__(chunk_threads(PREC, COARSE)) void k_apply_chunks(UArgs a, ChunkArgs ca, BrickK<VT> kc, CgArgs cg) {
   __shared__ VT xs[TAB_MAX * 3];
   __shared__ double ys[TAB_MAX * 3];  // FP64 LDS accumulators (see k_apply_uniform_bf16)
   __shared__ uint16_t lsm[PREC == P_BF16 ? ENT_MAX * 8 : 1];
@@ -497,6 +504,8 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   __shared__ uint32_t trip_hm_s[TRIP_MAX];
   __shared__ double trip_w_s[TRIP_MAX];
   __shared__ int hbeg_s[TAB_MAX];
+  constexpr int NT = chunk_threads(PREC, COARSE);
+  static_assert(NT == 256 || NT == 512, "chunk workgroups have 256 or 512 threads");
   const int tid = threadIdx.x;
   const int c = xcd_remap(blockIdx.x, gridDim.x);
   if (!FUSED && a.stop && *a.stop != 0.0) return;
@@ -518,25 +527,25 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   // zero padded), so it goes out with the count loads rather than after them:
   // the staged vector values depend on it.  Entries and hanging triples are
   // needed later and are read only up to their counts.  Table nodes
-  // t = tid + 256 r (r < NPT): global node, support bits and the staged values
+  // t = tid + NT r (r < NPT): global node, support bits and the staged values
   // are loaded in one batch (no dependent round trips per component), and the
   // indices stay in registers for the store phase.
-  constexpr int NPT = TAB_MAX / 256;
+  constexpr int NPT = TAB_MAX / NT;
   int gn[NPT];
   uint8_t fb[NPT];
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
-    const int t = tid + 256 * r;
+    const int t = tid + NT * r;
     const int g = ca.tab_node[t0 + t];
     gn[r] = t < nt ? g : -1;
   }
   // entry metadata of the element loop, prefetched under the staging latency
-  constexpr int EPT = ENT_MAX / 256;
+  constexpr int EPT = ENT_MAX / NT;
   uint4 lvp[EPT];
   int eel[EPT];
 #pragma unroll
   for (int r = 0; r < EPT; ++r) {
-    const int en = tid + 256 * r;
+    const int en = tid + NT * r;
     eel[r] = 0;
     lvp[r] = make_uint4(0u, 0u, 0u, 0u);
     if (en < nent) {
@@ -546,7 +555,7 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   }
   // hanging triples and per-entry triple ranges, whole slots; written to LDS
   // once the vector values below are requested
-  constexpr int HPT = TRIP_MAX / 256;
+  constexpr int HPT = TRIP_MAX / NT;
   uint32_t thm[HPT];
   double tw[HPT];
   int hbr[NPT];
@@ -554,14 +563,14 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   for (int q = 0; q < HPT; ++q) {
     thm[q] = 0u;
     tw[q] = 0.0;
-    if (tid + 256 * q < nh) {
-      thm[q] = ca.trip_hm[h0 + tid + 256 * q];
-      tw[q] = ca.trip_w[h0 + tid + 256 * q];
+    if (tid + NT * q < nh) {
+      thm[q] = ca.trip_hm[h0 + tid + NT * q];
+      tw[q] = ca.trip_w[h0 + tid + NT * q];
     }
   }
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
-    const int t = tid + 256 * r;
+    const int t = tid + NT * r;
     hbr[r] = (t >= nreg && t < nt) ? ca.tab_hbeg[t0 + t] : 0;
   }
   // raw vector values of the regular table nodes, also requested before the
@@ -572,7 +581,7 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   float4 gv[COARSE ? NPT : 1];
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
-    const int t = tid + 256 * r;
+    const int t = tid + NT * r;
     fb[r] = 0;
 #pragma unroll
     for (int c3 = 0; c3 < 3; ++c3) {
@@ -602,18 +611,18 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   for (int r = 0; r < EPT; ++r) cep[r] = coef[eel[r]];
 #pragma unroll
   for (int q = 0; q < HPT; ++q) {
-    trip_hm_s[tid + 256 * q] = thm[q];
-    trip_w_s[tid + 256 * q] = tw[q];
+    trip_hm_s[tid + NT * q] = thm[q];
+    trip_w_s[tid + NT * q] = tw[q];
   }
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
-    const int t = tid + 256 * r;
+    const int t = tid + NT * r;
     if (t >= nreg && t < nt) hbeg_s[t - nreg] = hbr[r];
   }
   __shared__ double czs[COARSE ? COARSE_KMAX : 1];
   CgArgs cgb = cg;
   if (COARSE) {
-    for (int j = tid; j < 12 * a.coarse_R; j += 256) czs[j] = a.cz[j];
+    for (int j = tid; j < 12 * a.coarse_R; j += NT) czs[j] = a.cz[j];
     if (a.zq_part) {  // recurrence form: r.z adds ct^T cz in the prologue
       cgb.cct = a.ct;
       cgb.ccz = a.cz;
@@ -627,13 +636,13 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   if (!have) {
     if (FUSED && tid == 0) cg.part_out[cg.part_base + blockIdx.x] = 0.0;
     if (COARSE && a.zq_part)
-      for (int j = tid; j < 24 * a.coarse_R; j += 256) a.zq_part[(long)j * gridDim.x + blockIdx.x] = 0.0;
+      for (int j = tid; j < 24 * a.coarse_R; j += NT) a.zq_part[(long)j * gridDim.x + blockIdx.x] = 0.0;
     return;
   }
   const VT vbeta = (VT)beta;
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
-    const int t = tid + 256 * r;
+    const int t = tid + NT * r;
     if (t < nreg) {
       VT zb[3];
       if (COARSE == 2) block_apply<VT>(dv[r], xv[r], zb);
@@ -658,12 +667,12 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
       }
     }
   }
-  for (int i = tid; i < nt * 3; i += 256) ys[i] = 0.0;
+  for (int i = tid; i < nt * 3; i += NT) ys[i] = 0.0;
   if (PREC == P_BF16)
-    for (int i = tid; i < nent * 8; i += 256) lsm[i] = ca.ent_loc[8L * n0 + i];
+    for (int i = tid; i < nent * 8; i += NT) lsm[i] = ca.ent_loc[8L * n0 + i];
   // recurrence form: the regions of the owned regular nodes (a bitmask), and
   // the E^-1 columns of the first two requested now, under the element loop
-  __shared__ uint32_t gmask_s[4];
+  __shared__ uint32_t gmask_s[NT / 64];
   uint32_t mall = 0;
   int g0 = -1, g1 = -1;
   double e0[COARSE ? 24 : 1];
@@ -671,13 +680,14 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
     uint32_t m = 0;
 #pragma unroll
     for (int r = 0; r < NPT; ++r)
-      if (tid + 256 * r < nown) m |= 1u << (__float_as_int(gv[r].w) & 31);
+      if (tid + NT * r < nown) m |= 1u << (__float_as_int(gv[r].w) & 31);
     for (int off = 32; off > 0; off >>= 1) m |= (uint32_t)__shfl_xor((int)m, off, 64);
     if ((tid & 63) == 0) gmask_s[tid >> 6] = m;
   }
   __syncthreads();
   if (COARSE && a.zq_part) {
-    mall = gmask_s[0] | gmask_s[1] | gmask_s[2] | gmask_s[3];
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) mall |= gmask_s[w];
     const uint32_t m1 = mall & (mall - 1);
     g0 = mall ? __ffs((int)mall) - 1 : -1;
     g1 = m1 ? __ffs((int)m1) - 1 : -1;
@@ -688,7 +698,7 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
       e0[u] = (g >= 0 && tid < kk) ? a.einv[(long)(((v / 3) * R + g) * 3 + v % 3) * kk + tid] : 0.0;
     }
   }
-  for (int i = tid; i < (nt - nreg) * 3; i += 256) {  // x_h = sum_m w_hm x_m  (Eq. (6))
+  for (int i = tid; i < (nt - nreg) * 3; i += NT) {  // x_h = sum_m w_hm x_m  (Eq. (6))
     const int t = nreg + i / 3, comp = i % 3;
     const int kb = hbeg_s[t - nreg], ke = t + 1 < nt ? hbeg_s[t + 1 - nreg] : nh;
     double v = 0.0;
@@ -699,7 +709,7 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   if (PREC != P_BF16) {
 #pragma unroll
     for (int r = 0; r < EPT; ++r) {
-      const int en = tid + 256 * r;
+      const int en = tid + NT * r;
       if (en >= nent) break;
       int loc[8];
       const uint4 lv = lvp[r];
@@ -729,7 +739,7 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
     load_k0_bf16((const uint16_t*)a.kb, ka);
     const int lane = tid & 63, wave = tid >> 6;
     const int n16 = lane & 15, q4 = lane >> 4;
-    for (int tb = 16 * wave; tb < nent; tb += 64) {
+    for (int tb = 16 * wave; tb < nent; tb += 16 * (NT / 64)) {
       const int en = tb + n16;
       const bool ev = en < nent;
       float u[24];
@@ -755,7 +765,7 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
     }
   }
   __syncthreads();
-  for (int i = tid; i < nh * 3; i += 256) {  // y_m += w_hm y_h  (P^T of Eq. (7))
+  for (int i = tid; i < nh * 3; i += NT) {  // y_m += w_hm y_h  (P^T of Eq. (7))
     const int k = i / 3, comp = i % 3;
     const uint32_t hm = trip_hm_s[k];
     atomicAdd(&ys[(hm & 0xffff) * 3 + comp], trip_w_s[k] * ys[(hm >> 16) * 3 + comp]);
@@ -765,7 +775,7 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
   VT qk[COARSE ? NPT : 1][3];  // q of the owned regular nodes (coarse recurrence)
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
-    const int t = tid + 256 * r;
+    const int t = tid + NT * r;
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp)
       if (COARSE) qk[r][comp] = 0;
@@ -813,7 +823,7 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
     __shared__ double zred[12][16];
     static_assert(TAB_MAX * 3 >= 12 * 256, "the Z^T q columns are staged in ys");
     const int R = a.coarse_R, kk = 12 * R;
-    for (int j = tid; j < kk; j += 256) czs[j] = 0.0;
+    for (int j = tid; j < kk; j += NT) czs[j] = 0.0;
     double s[4][3];
 #pragma unroll
     for (int f = 0; f < 4; ++f)
@@ -822,7 +832,7 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
 #pragma unroll
     for (int r = 0; r < NPT; ++r) {
       const int w = __float_as_int(gv[r].w);
-      if (tid + 256 * r < nown && (w & 0xff) == g0) {
+      if (tid + NT * r < nown && (w & 0xff) == g0) {
         const double d[3] = {(double)gv[r].x, (double)gv[r].y, (double)gv[r].z};
 #pragma unroll
         for (int c3 = 0; c3 < 3; ++c3) {
@@ -834,16 +844,31 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
         }
       }
     }
+    if (NT > 256) {  // fold the upper threads' sums onto threads 0-255 (fixed order)
+      if (tid >= 256)
 #pragma unroll
-    for (int f = 0; f < 4; ++f)
+        for (int f = 0; f < 4; ++f)
 #pragma unroll
-      for (int c3 = 0; c3 < 3; ++c3) ys[(f * 3 + c3) * 256 + tid] = s[f][c3];
+          for (int c3 = 0; c3 < 3; ++c3) ys[(f * 3 + c3) * 256 + tid - 256] = s[f][c3];
+      __syncthreads();
+      if (tid < 256)
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+          for (int c3 = 0; c3 < 3; ++c3) s[f][c3] += ys[(f * 3 + c3) * 256 + tid];
+      __syncthreads();
+    }
+    if (tid < 256)
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int c3 = 0; c3 < 3; ++c3) ys[(f * 3 + c3) * 256 + tid] = s[f][c3];
     __syncthreads();  // also orders the zeroing of czs before the atomics below
     if (mall & (mall - 1)) {
 #pragma unroll
       for (int r = 0; r < NPT; ++r) {
         const int w = __float_as_int(gv[r].w), g = w & 0xff;
-        if (tid + 256 * r < nown && g != g0) {
+        if (tid + NT * r < nown && g != g0) {
           const double d[3] = {(double)gv[r].x, (double)gv[r].y, (double)gv[r].z};
 #pragma unroll
           for (int c3 = 0; c3 < 3; ++c3) {
@@ -875,7 +900,7 @@ __global__ __launch_bounds__(256) void k_apply_chunks(UArgs a, ChunkArgs ca, Bri
     // E^-1 Z^T q over the nonzero columns (twelve per region present; E^-1
     // symmetric, so column i serves as row i): those of the first two regions
     // are in e0 (for j = tid), the others are loaded two regions at a time
-    for (int j = tid; j < kk; j += 256) {
+    for (int j = tid; j < kk; j += NT) {
       double wj = 0.0;
       uint32_t rest = mall;
       if (j == tid) {
@@ -1071,7 +1096,7 @@ static int launch_t(amrto_ctx* ctx, const UArgs& ua, const CgArgs& cg) {
                          cg);
     }
   } else {
-    hipLaunchKernelGGL((k_apply_chunks<VT, PREC, FUSED>), dim3(apply_blocks(ctx)), dim3(256), 0, ctx->stream, ua,
+    hipLaunchKernelGGL((k_apply_chunks<VT, PREC, FUSED>), dim3(apply_blocks(ctx)), dim3(chunk_threads(PREC, 0)), 0, ctx->stream, ua,
                        chunk_args(ctx), brick_k<VT>(ctx), cg);
   }
   AMRTO_HIP(hipGetLastError());
@@ -1137,24 +1162,24 @@ int apply_fused_coarse(amrto_ctx* ctx, const void* r, const void* minv, const vo
   const ChunkArgs ch = chunk_args(ctx);
   if (prec == AMRTO_FP64) {
     if (block3)
-      hipLaunchKernelGGL((k_apply_chunks<double, P_F64, true, 2>), grid, dim3(256), 0, ctx->stream, a, ch,
+      hipLaunchKernelGGL((k_apply_chunks<double, P_F64, true, 2>), grid, dim3(chunk_threads(P_F64, 2)), 0, ctx->stream, a, ch,
                          brick_k<double>(ctx), cg);
     else
-      hipLaunchKernelGGL((k_apply_chunks<double, P_F64, true, 1>), grid, dim3(256), 0, ctx->stream, a, ch,
+      hipLaunchKernelGGL((k_apply_chunks<double, P_F64, true, 1>), grid, dim3(chunk_threads(P_F64, 1)), 0, ctx->stream, a, ch,
                          brick_k<double>(ctx), cg);
   } else if (prec == AMRTO_FP32) {
     if (block3)
-      hipLaunchKernelGGL((k_apply_chunks<float, P_F32, true, 2>), grid, dim3(256), 0, ctx->stream, a, ch,
+      hipLaunchKernelGGL((k_apply_chunks<float, P_F32, true, 2>), grid, dim3(chunk_threads(P_F32, 2)), 0, ctx->stream, a, ch,
                          brick_k<float>(ctx), cg);
     else
-      hipLaunchKernelGGL((k_apply_chunks<float, P_F32, true, 1>), grid, dim3(256), 0, ctx->stream, a, ch,
+      hipLaunchKernelGGL((k_apply_chunks<float, P_F32, true, 1>), grid, dim3(chunk_threads(P_F32, 1)), 0, ctx->stream, a, ch,
                          brick_k<float>(ctx), cg);
   } else {
     if (block3)
-      hipLaunchKernelGGL((k_apply_chunks<float, P_BF16, true, 2>), grid, dim3(256), 0, ctx->stream, a, ch,
+      hipLaunchKernelGGL((k_apply_chunks<float, P_BF16, true, 2>), grid, dim3(chunk_threads(P_BF16, 2)), 0, ctx->stream, a, ch,
                          brick_k<float>(ctx), cg);
     else
-      hipLaunchKernelGGL((k_apply_chunks<float, P_BF16, true, 1>), grid, dim3(256), 0, ctx->stream, a, ch,
+      hipLaunchKernelGGL((k_apply_chunks<float, P_BF16, true, 1>), grid, dim3(chunk_threads(P_BF16, 1)), 0, ctx->stream, a, ch,
                          brick_k<float>(ctx), cg);
   }
   AMRTO_HIP(hipGetLastError());
