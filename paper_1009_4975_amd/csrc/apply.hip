@@ -963,7 +963,7 @@ __global__ __launch_bounds__(256) void k_diag_uniform(
 // the diagonal of T^T K T including the cross terms that hanging vertices
 // create.  Owned rows are inverted and written (identity for supported and
 // hanging rows).
-__global__ __launch_bounds__(256) void k_diag_chunks(double* __restrict__ dinv, const double* __restrict__ coef,
+__global__ __launch_bounds__(512) void k_diag_chunks(double* __restrict__ dinv, const double* __restrict__ coef,
                                                      const uint8_t* __restrict__ fix, const double* __restrict__ K0,
                                                      ChunkArgs ca) {
   __shared__ double ds[TAB_MAX * 3];
@@ -973,18 +973,19 @@ __global__ __launch_bounds__(256) void k_diag_chunks(double* __restrict__ dinv, 
   __shared__ double K0s[576];
   const int c = blockIdx.x;
   if (c >= ca.n_chunks) return;
+  constexpr int DT = 512;
   const int tid = threadIdx.x;
   const ChunkDims cd = chunk_dims(ca, c);
   const int n0 = cd.n0, nent = cd.nent, t0 = cd.t0, nt = cd.nt, h0 = cd.h0, nh = cd.nh;
   const int nown = cd.nown, nreg = cd.nreg, nhown = cd.nhown;
-  for (int i = tid; i < nt * 3; i += 256) ds[i] = 0.0;
+  for (int i = tid; i < nt * 3; i += DT) ds[i] = 0.0;
   // the chunk's hanging triples and per-entry triple ranges, and K0, in LDS
-  for (int k = tid; k < nh; k += 256) {
+  for (int k = tid; k < nh; k += DT) {
     trip_hm_s[k] = ca.trip_hm[h0 + k];
     trip_w_s[k] = ca.trip_w[h0 + k];
   }
-  for (int t = nreg + tid; t < nt; t += 256) hbeg_s[t - nreg] = ca.tab_hbeg[t0 + t];
-  for (int i = tid; i < 576; i += 256) K0s[i] = K0[i];
+  for (int t = nreg + tid; t < nt; t += DT) hbeg_s[t - nreg] = ca.tab_hbeg[t0 + t];
+  for (int i = tid; i < 576; i += DT) K0s[i] = K0[i];
   __syncthreads();
   // vertex aa of an entry maps to the masters [kb, ke) of its hanging table
   // entry, or to itself (kb = -1) when regular
@@ -996,13 +997,16 @@ __global__ __launch_bounds__(256) void k_diag_chunks(double* __restrict__ dinv, 
       ke = l + 1 < nt ? hbeg_s[l + 1 - nreg] : nh;
     }
   };
-  for (int en = tid; en < nent; en += 256) {
+  // one work item per (entry, vertex): the few entries that touch hanging
+  // nodes carry most of the work, so it is spread over the threads by vertex
+  for (int it = tid; it < nent * 8; it += DT) {
+    const int en = it >> 3, aa = it & 7;
     int loc[8];
     const uint4 lv = *reinterpret_cast<const uint4*>(ca.ent_loc + 8L * (n0 + en));
     loc[0] = lv.x & 0xffff; loc[1] = lv.x >> 16; loc[2] = lv.y & 0xffff; loc[3] = lv.y >> 16;
     loc[4] = lv.z & 0xffff; loc[5] = lv.z >> 16; loc[6] = lv.w & 0xffff; loc[7] = lv.w >> 16;
     const double ce = coef[ca.ent_elem[n0 + en]];
-    for (int aa = 0; aa < 8; ++aa) {
+    {
       int ka, kae;
       range(loc[aa], ka, kae);
       for (int k = ka; k < (ka < 0 ? 0 : kae); ++k) {
@@ -1025,7 +1029,7 @@ __global__ __launch_bounds__(256) void k_diag_chunks(double* __restrict__ dinv, 
     }
   }
   __syncthreads();
-  for (int i = tid; i < (nown + nhown) * 3; i += 256) {
+  for (int i = tid; i < (nown + nhown) * 3; i += DT) {
     int t = i / 3;
     const int comp = i % 3;
     const bool hang = t >= nown;
@@ -1193,7 +1197,7 @@ int launch_diag(amrto_ctx* ctx) {
     hipLaunchKernelGGL(k_diag_uniform, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, ctx->d_coef,
                        ctx->d_fix, ctx->K0[0], ctx->d_dinv, ctx->nx, ctx->ny, ctx->nz);
   } else {
-    hipLaunchKernelGGL(k_diag_chunks, dim3(ctx->n_chunks), dim3(256), 0, ctx->stream, ctx->d_dinv, ctx->d_coef,
+    hipLaunchKernelGGL(k_diag_chunks, dim3(ctx->n_chunks), dim3(512), 0, ctx->stream, ctx->d_dinv, ctx->d_coef,
                        ctx->d_fix, ctx->d_K0, chunk_args(ctx));
   }
   hipLaunchKernelGGL(k_to_float, dim3((n3 + 255) / 256), dim3(256), 0, ctx->stream, ctx->d_dinv,

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_block_uniform(const double* __restrict_
 // component pairs of the symmetric block (00, 11, 22, 01, 02, 12); owned rows
 // are finished and written
 template <bool INV>
-__global__ __launch_bounds__(256) void k_block_chunks(const double* __restrict__ coef,
+__global__ __launch_bounds__(512) void k_block_chunks(const double* __restrict__ coef,
                                                       const uint8_t* __restrict__ fix,
                                                       const double* __restrict__ K0, double* __restrict__ out,
                                                       ChunkArgs ca) {
@@ -96,18 +96,19 @@ __global__ __launch_bounds__(256) void k_block_chunks(const double* __restrict__
   __shared__ double K0s[576];
   const int c = blockIdx.x;
   if (c >= ca.n_chunks) return;
+  constexpr int DT = 512;
   const int tid = threadIdx.x;
   const ChunkDims cd = chunk_dims(ca, c);
   const int n0 = cd.n0, nent = cd.nent, t0 = cd.t0, nt = cd.nt, h0 = cd.h0, nh = cd.nh;
   const int nown = cd.nown, nreg = cd.nreg, nhown = cd.nhown;
-  for (int i = tid; i < nt * 6; i += 256) ds[i] = 0.0;
+  for (int i = tid; i < nt * 6; i += DT) ds[i] = 0.0;
   // the chunk's hanging triples and per-entry triple ranges, and K0, in LDS
-  for (int k = tid; k < nh; k += 256) {
+  for (int k = tid; k < nh; k += DT) {
     trip_hm_s[k] = ca.trip_hm[h0 + k];
     trip_w_s[k] = ca.trip_w[h0 + k];
   }
-  for (int t = nreg + tid; t < nt; t += 256) hbeg_s[t - nreg] = ca.tab_hbeg[t0 + t];
-  for (int i = tid; i < 576; i += 256) K0s[i] = K0[i];
+  for (int t = nreg + tid; t < nt; t += DT) hbeg_s[t - nreg] = ca.tab_hbeg[t0 + t];
+  for (int i = tid; i < 576; i += DT) K0s[i] = K0[i];
   __syncthreads();
   auto range = [&](int l, int& kb, int& ke) {
     if (l < nreg) {
@@ -118,13 +119,16 @@ __global__ __launch_bounds__(256) void k_block_chunks(const double* __restrict__
       ke = l + 1 < nt ? hbeg_s[l + 1 - nreg] : nh;
     }
   };
-  for (int en = tid; en < nent; en += 256) {
+  // one work item per (entry, vertex): the few entries that touch hanging
+  // nodes carry most of the work, so it is spread over the threads by vertex
+  for (int it = tid; it < nent * 8; it += DT) {
+    const int en = it >> 3, aa = it & 7;
     int loc[8];
     const uint4 lv = *reinterpret_cast<const uint4*>(ca.ent_loc + 8L * (n0 + en));
     loc[0] = lv.x & 0xffff; loc[1] = lv.x >> 16; loc[2] = lv.y & 0xffff; loc[3] = lv.y >> 16;
     loc[4] = lv.z & 0xffff; loc[5] = lv.z >> 16; loc[6] = lv.w & 0xffff; loc[7] = lv.w >> 16;
     const double ce = coef[ca.ent_elem[n0 + en]];
-    for (int aa = 0; aa < 8; ++aa) {
+    {
       int ka, kae;
       range(loc[aa], ka, kae);
       for (int k = ka; k < (ka < 0 ? 0 : kae); ++k) {
@@ -153,7 +157,7 @@ __global__ __launch_bounds__(256) void k_block_chunks(const double* __restrict__
     }
   }
   __syncthreads();
-  for (int t = tid; t < nown + nhown; t += 256) {
+  for (int t = tid; t < nown + nhown; t += DT) {
     const bool hang = t >= nown;
     const int tt = hang ? nreg + (t - nown) : t;
     const long node = ca.tab_node[t0 + tt];
@@ -252,7 +256,7 @@ static int launch_blocks(amrto_ctx* ctx, double* out) {
     hipLaunchKernelGGL(k_block_uniform<INV>, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, ctx->d_coef,
                        ctx->d_fix, ctx->d_K0, out, ctx->nx, ctx->ny, ctx->nz);
   } else {
-    hipLaunchKernelGGL(k_block_chunks<INV>, dim3(ctx->n_chunks), dim3(256), 0, ctx->stream, ctx->d_coef, ctx->d_fix,
+    hipLaunchKernelGGL(k_block_chunks<INV>, dim3(ctx->n_chunks), dim3(512), 0, ctx->stream, ctx->d_coef, ctx->d_fix,
                        ctx->d_K0, out, chunk_args(ctx));
   }
   AMRTO_HIP(hipGetLastError());
