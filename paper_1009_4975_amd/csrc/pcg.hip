@@ -93,7 +93,9 @@ __global__ __launch_bounds__(256) void k_cg_update(VT* __restrict__ x, VT* __res
                                                    VT* __restrict__ z, long n, const double* __restrict__ part_pq,
                                                    int n_pq, double* __restrict__ scal, int it,
                                                    double* __restrict__ part) {
-  if (scal[S_DONE] != 0.0) return;
+  // a finished solve stores nothing; the flag is read with the loads below
+  // and tested once they are requested (one round trip instead of two)
+  const double done = scal[S_DONE];
   __shared__ double sh[8];
   // the first UPT entries of this thread are requested before the p.q
   // partials are reduced (alpha is not needed to load them)
@@ -111,6 +113,7 @@ __global__ __launch_bounds__(256) void k_cg_update(VT* __restrict__ x, VT* __res
     dv[u] = in ? dinv[i] : (VT)0;
   }
   const double pq = sum_partials(part_pq, n_pq, sh);
+  if (done != 0.0) return;
   const double rz = scal[S_RZ0 + (it & 1)];
   if (!(pq > 0.0) || !(pq < 1e300) || !(rz == rz)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_DONE] = 2.0;
@@ -303,7 +306,9 @@ __global__ __launch_bounds__(256) void k_cg_update_coarse(VT* __restrict__ x, VT
                                                           const double* __restrict__ part_pq, int n_pq,
                                                           double* __restrict__ scal, int it, CoarseArgs ca,
                                                           double* __restrict__ part_z, double* __restrict__ part) {
-  if (scal[S_DONE] != 0.0) return;
+  // a finished solve stores nothing; the flag is read with the loads below
+  // and tested once they are requested (one round trip instead of two)
+  const double done = scal[S_DONE];
   __shared__ double sh[8];
   __shared__ double acc[COARSE_KMAX];
   __shared__ double red[COARSE_NFMAX * 3][256];
@@ -325,6 +330,7 @@ __global__ __launch_bounds__(256) void k_cg_update_coarse(VT* __restrict__ x, VT
     dv0[u] = in ? dinv[i] : (VT)0;
   }
   const double pq = sum_partials(part_pq, n_pq, sh);
+  if (done != 0.0) return;
   const double rz = scal[S_RZ0 + (it & 1)];
   if (!(pq > 0.0) || !(pq < 1e300) || !(rz == rz)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_DONE] = 2.0;
@@ -382,7 +388,9 @@ __global__ __launch_bounds__(256) void k_cg_update_coarse_b3(VT* __restrict__ x,
                                                              const double* __restrict__ part_pq, int n_pq,
                                                              double* __restrict__ scal, int it, CoarseArgs ca,
                                                              double* __restrict__ part_z, double* __restrict__ part) {
-  if (scal[S_DONE] != 0.0) return;
+  // a finished solve stores nothing; the flag is read with the loads below
+  // and tested once they are requested (one round trip instead of two)
+  const double done = scal[S_DONE];
   __shared__ double sh[8];
   __shared__ double acc[COARSE_KMAX];
   __shared__ double red[COARSE_NFMAX * 3][256];
@@ -391,6 +399,7 @@ __global__ __launch_bounds__(256) void k_cg_update_coarse_b3(VT* __restrict__ x,
   long lo, hi;
   block_range(nn, lo, hi);
   const double pq = sum_partials(part_pq, n_pq, sh);
+  if (done != 0.0) return;
   const double rz = scal[S_RZ0 + (it & 1)];
   if (!(pq > 0.0) || !(pq < 1e300) || !(rz == rz)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_DONE] = 2.0;
@@ -452,7 +461,9 @@ __global__ __launch_bounds__(256) void k_cg_update_rec(VT* __restrict__ x, VT* _
                                                        const double* __restrict__ qpart, int nb, int kk,
                                                        double* __restrict__ ct, double* __restrict__ cz,
                                                        double* __restrict__ part) {
-  if (scal[S_DONE] != 0.0) return;
+  // a finished solve stores nothing; the flag is read with the loads below
+  // and tested once they are requested (one round trip instead of two)
+  const double done = scal[S_DONE];
   __shared__ double sh[16];
   constexpr int MW = B3 ? 6 : 3;
   const bool col = blockIdx.x >= RED_BLOCKS;
@@ -478,6 +489,7 @@ __global__ __launch_bounds__(256) void k_cg_update_rec(VT* __restrict__ x, VT* _
       s2 += qpart[(long)(kk + j) * nb + b];
     }
   const double pq = sum_partials(part_pq, n_pq, sh);
+  if (done != 0.0) return;
   const double rz = scal[S_RZ0 + (it & 1)];
   if (!(pq > 0.0) || !(pq < 1e300) || !(rz == rz)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_DONE] = 2.0;
