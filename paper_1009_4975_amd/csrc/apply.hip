@@ -681,7 +681,7 @@ __global__ __launch_bounds__(chunk_threads(PREC, COARSE)) void k_apply_chunks(UA
 #pragma unroll
     for (int r = 0; r < NPT; ++r)
       if (tid + NT * r < nown) m |= 1u << (__float_as_int(gv[r].w) & 31);
-    for (int off = 32; off > 0; off >>= 1) m |= (uint32_t)__shfl_xor((int)m, off, 64);
+    m = wave_or(m);
     if ((tid & 63) == 0) gmask_s[tid >> 6] = m;
   }
   __syncthreads();

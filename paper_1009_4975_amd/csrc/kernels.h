@@ -39,6 +39,22 @@ __device__ __forceinline__ double wave_sum(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// bitwise OR over the wave, same DPP steps; every lane gets the result
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+}
+
+__device__ __forceinline__ uint32_t wave_or(uint32_t m) {
+  m |= dpp_u32<0xb1, 0xf>(m);
+  m |= dpp_u32<0x4e, 0xf>(m);
+  m |= dpp_u32<0x141, 0xf>(m);
+  m |= dpp_u32<0x140, 0xf>(m);
+  m |= dpp_u32<0x142, 0xa>(m);
+  m |= dpp_u32<0x143, 0xc>(m);
+  return (uint32_t)__builtin_amdgcn_readlane((int)m, 63);
+}
+
 // deterministic block sum (fixed tree); every thread gets the result
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   v = wave_sum(v);
@@ -360,7 +376,9 @@ __device__ __forceinline__ void block_apply(const VT* __restrict__ bi, const VT 
 // stopped (converged, breakdown, or already flagged).
 
 __device__ __forceinline__ bool cg_prologue(const CgArgs& cg, double& beta, double* sh) {
-  if (cg.scal[S_DONE] != 0.0) return false;
+  // the finished flag is read with the partial sums and tested after them
+  // (uniform over the block; nothing is stored before the test)
+  const double done = cg.scal[S_DONE];
   double rz = 0.0, rr = 0.0;
   for (int i = threadIdx.x; i < RED_BLOCKS; i += blockDim.x) {
     rz += cg.part_in[i];
@@ -368,6 +386,7 @@ __device__ __forceinline__ bool cg_prologue(const CgArgs& cg, double& beta, doub
   }
   for (int i = threadIdx.x; i < cg.ck; i += blockDim.x) rz += cg.cct[i] * cg.ccz[i];
   block_sum2(rz, rr, sh);
+  if (done != 0.0) return false;
   if (cg.coarse) rz += cg.scal[S_CTZ];
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   if (!(rz == rz) || !(rr == rr) || rr > 1e300 || rz > 1e300) {
