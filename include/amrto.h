@@ -167,7 +167,10 @@ typedef struct {
                          residual falls between two FP64 reliable updates
                          (default 0.1; a recurrence that levels off above its
                          target for 2048 iterations is updated anyway) */
-  int32_t check_every;/* iterations between host convergence checks (default 16) */
+  int32_t check_every;/* shortest run of iterations between host convergence
+                          checks (default 16); runs grow to at most 8x this
+                          while the residual's convergence rate says the
+                          target is further away */
   int32_t use_coarse; /* 1 (default): add the coarse correction set by
                          amrto_coarse_setup, when one is set; 0: Jacobi only */
   int32_t fallback_fp64; /* 1 (default): a mixed solve that breaks down or

@@ -826,6 +826,25 @@ static int enqueue_iters(amrto_ctx* ctx, const Vecs<VT>& v, VT* x, int prec, dou
   return AMRTO_OK;
 }
 
+// Iterations to enqueue before the next host check.  Every check drains the
+// stream (the device idles until the next batch is queued), and every
+// iteration queued past convergence is a pair of launches that return at
+// once.  So: check_every while nothing is known; then 3/4 of the iterations
+// the residual still needs to reach `target`, at the faster of its mean rate
+// since rr0 (its iterations ago) and its rate over the last batch (log r.r
+// falls about linearly in CG), between check_every and 8 check_every.
+static int next_batch(double rr0, double rr_prev, double rr, int its, int last, double target, int check_every,
+                      int left) {
+  int n = check_every;
+  if (its > 0 && last > 0 && rr0 > 0.0 && rr_prev > 0.0 && target > 0.0 && rr > target && rr < rr0) {
+    double rate = std::log(rr / rr0) / its;
+    if (rr < rr_prev) rate = std::min(rate, std::log(rr / rr_prev) / last);
+    const double need = std::log(target / rr) / rate;
+    n = (int)std::min(8.0 * check_every, std::max((double)check_every, 0.75 * need));
+  }
+  return std::max(1, std::min(n, left));
+}
+
 // Plain FP64 Jacobi-PCG from x (masked).  *iters = iterations performed.
 static int cg_fp64_run(amrto_ctx* ctx, const double* b, double* x, double rtol, int max_it, int check_every,
                        bool one_reduction, bool block3, int* iters) {
@@ -858,8 +877,9 @@ static int cg_fp64_run(amrto_ctx* ctx, const double* b, double* x, double rtol, 
     rc = cg1_init(ctx);
     if (rc) return rc;
   }
-  int it = 0;
+  int it = 0, last = 0;
   int status = AMRTO_NOT_CONVERGED;
+  double rr0 = 0.0, rr_prev = 0.0;
   while (true) {
     rc = read_scalars(ctx);
     if (rc) return rc;
@@ -867,11 +887,15 @@ static int cg_fp64_run(amrto_ctx* ctx, const double* b, double* x, double rtol, 
     if (done == 1.0) { status = AMRTO_OK; break; }
     if (done == 2.0) { status = AMRTO_EBREAKDOWN; break; }
     if (it >= max_it) break;
-    const int batch = std::min(check_every, max_it - it);
+    const double rr = ctx->h_scal[S_RR];
+    if (it == 0) rr0 = rr;
+    const int batch = next_batch(rr0, rr_prev, rr, it, last, tol2 * ctx->h_scal[S_BB], check_every, max_it - it);
+    rr_prev = rr;
     rc = one ? cg1_enqueue(ctx, x, tol2, it, batch)
              : enqueue_iters<double>(ctx, v, x, AMRTO_FP64, tol2, it, batch, block3);
     if (rc) return rc;
     it += batch;
+    last = batch;
   }
   *iters = status == AMRTO_NOT_CONVERGED ? it : (int)ctx->h_scal[S_ITERS];
   return status;
@@ -959,6 +983,10 @@ static int cg_mixed(amrto_ctx* ctx, const double* b, double* x, int prec, double
   constexpr int STALL_WIN = 2048;
   double rr_rec_best = 1e300;
   int since_gain = 0;
+  // this cycle (since the last reliable update): r.r at its start, at the
+  // last two checks, its iterations and the last batch
+  double cyc_rr0 = rr, cyc_prev = 0.0, cyc_rr = rr;
+  int cyc_its = 0, cyc_last = 0;
   while (true) {
     if (!(rr == rr) || rr > 1e300) { status = AMRTO_EBREAKDOWN; break; }
     if (rr <= tol2 * bb) { status = AMRTO_OK; break; }
@@ -983,10 +1011,14 @@ static int cg_mixed(amrto_ctx* ctx, const double* b, double* x, int prec, double
         hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, ctx->stream, ctx->d_scal, (int)S_DONE, 0.0);
       }
       restart_scalars = false;
+      cyc_rr0 = cyc_rr = rr;
+      cyc_prev = 0.0;
+      cyc_its = cyc_last = 0;
     }
-    const int batch = std::min(check_every, max_it - it);
     // the recurrence stops itself when its own residual reaches delta^2 rr_ref
     const double tol_in = std::max(std::sqrt(delta * delta * rr_ref / bb), 0.5 * rtol);
+    const int batch = next_batch(cyc_rr0, cyc_prev, cyc_rr, cyc_its, cyc_last, tol_in * tol_in * bb, check_every,
+                                 max_it - it);
     rc = enqueue_iters<float>(ctx, v, d, prec, tol_in * tol_in, it, batch, block3);
     if (rc) return rc;
     rc = read_scalars(ctx);
@@ -997,6 +1029,10 @@ static int cg_mixed(amrto_ctx* ctx, const double* b, double* x, int prec, double
     bool stagnant = false;
     if (done == 0.0) {
       const double rr_rec = ctx->h_scal[S_RR];
+      cyc_prev = cyc_rr;
+      cyc_rr = rr_rec;
+      cyc_its += batch;
+      cyc_last = batch;
       if (rr_rec < 0.25 * rr_rec_best) {
         rr_rec_best = rr_rec;
         since_gain = 0;
