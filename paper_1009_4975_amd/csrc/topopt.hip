@@ -153,22 +153,28 @@ __device__ __forceinline__ double oc_new(double rho, double g, double lam, doubl
 __global__ __launch_bounds__(OC_K) void k_oc_volumes(
     const double* __restrict__ rho, const double* __restrict__ dc, const double* __restrict__ vol, int n,
     double eta, double move, double rmin, double* __restrict__ ws) {
-  __shared__ double s_rho[OC_K], s_g[OC_K], s_v[OC_K];
+  // rho (g / lam)^eta = (rho g^eta) lam^-eta: the powers are taken once per
+  // element (as a tile is staged) and once per candidate, so a pair costs a
+  // product, the move limits and the volume product
+  __shared__ double s_rg[OC_TILE], s_lo[OC_TILE], s_hi[OC_TILE], s_v[OC_TILE];
   const double llo = ws[0], lhi = ws[1];
   const int j = threadIdx.x;
   const double lam = exp(llo + (lhi - llo) * (double)j / (double)(OC_K - 1));
+  const double ilam = eta == 0.5 ? 1.0 / sqrt(lam) : pow(lam, -eta);
   double acc = 0.0;
   for (int base = blockIdx.x * OC_TILE; base < n; base += gridDim.x * OC_TILE) {
     const int e = base + j;
     __syncthreads();
     if (j < OC_TILE && e < n) {
-      s_rho[j] = rho[e];
+      const double r = rho[e], g = fmax(-dc[e], 0.0) / vol[e];
+      s_rg[j] = r * (eta == 0.5 ? sqrt(g) : pow(g, eta));
+      s_lo[j] = fmax(rmin, r - move);
+      s_hi[j] = fmin(1.0, r + move);
       s_v[j] = vol[e];
-      s_g[j] = fmax(-dc[e], 0.0) / vol[e];
     }
     __syncthreads();
     const int m = min(OC_TILE, n - base);
-    for (int t = 0; t < m; ++t) acc += oc_new(s_rho[t], s_g[t], lam, eta, move, rmin) * s_v[t];
+    for (int t = 0; t < m; ++t) acc += fmin(fmax(s_rg[t] * ilam, s_lo[t]), s_hi[t]) * s_v[t];
   }
   ws[2 + (long)j * gridDim.x + blockIdx.x] = acc;
 }
