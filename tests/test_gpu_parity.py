@@ -188,6 +188,37 @@ def test_pcg_octree_matches_oracle(lib):
     assert np.linalg.norm(got - want) <= 1e-8 * np.linalg.norm(want)
 
 
+@pytest.mark.parametrize("kind", ["fp64", "fp32+coarse+block3"])
+def test_pcg_result_independent_of_check_interval(lib, kind):
+    """How often the host checks convergence (batches sized from the
+    residual's rate, between check_every and 8 check_every) changes only when
+    the enqueued iterations stop, not what they compute: every interval
+    reaches the direct solution with about the same number of iterations."""
+    from paper_1009_4975_amd import binding
+    p = cases.octree_pair((4, 2, 2), 2, width=0.2)
+    rho = cases.centre_density(p, p.case["field"])
+    ctx = make_ctx(p, rho)
+    s = cases.oracle_system(p, rho)
+    want = p.to_lib_nodes(osys.recover(s, osys.solve_direct(s)))
+    b = torch.empty(3 * p.orc.n_nodes, dtype=torch.float64, device="cuda")
+    ctx.project_rhs(dev(p.lib_mesh.f_load), b)
+    mixed = kind != "fp64"
+    its = {}
+    for ce in (1, 16, 200):
+        u = torch.zeros_like(b)
+        if mixed:
+            ctx.coarse_setup([], 2, 1, 1, affine=True)
+            st = ctx.pcg(b, u, rtol=1e-10, inner_prec=binding.FP32, precond=binding.BLOCK3, check_every=ce)
+            ctx.coarse_clear()
+        else:
+            st = ctx.pcg(b, u, rtol=1e-10, check_every=ce)
+        assert st["status"] == "OK" and st["rel_res"] <= 1e-10, (ce, st)
+        got = host(u)
+        assert np.linalg.norm(got - want) <= 1e-8 * np.linalg.norm(want), ce
+        its[ce] = st["iters"]
+    assert max(its.values()) - min(its.values()) <= max(3, 0.05 * its[16]), its
+
+
 @pytest.mark.parametrize("single", [True, False])
 def test_pcg_octree_one_and_two_reduction_forms(lib, single):
     """The one-reduction recurrences (Chronopoulos-Gear) and the two-pass form
