@@ -491,9 +491,9 @@ __global__ __launch_bounds__(BTHREADS, BrickOcc<VT>::blocks) void k_apply_brick(
 // Threads per workgroup of the octree operator pass.  The LDS of a chunk
 // allows two workgroups per CU; with 512 threads that is four waves per SIMD
 // (twice the latency hiding of 256, and half the per-thread staging, element
-// and store work), which needs at most 128 VGPRs: the FP64 and BF16
-// coarse-space variants need more and keep 256.
-constexpr int chunk_threads(int prec, int coarse) { return (coarse && prec != P_F32) ? 256 : 512; }
+// and store work), which needs at most 128 VGPRs: the BF16 coarse-space
+// variants need more and keep 256.
+constexpr int chunk_threads(int prec, int coarse) { return (coarse && prec == P_BF16) ? 256 : 512; }
 
 template <typename VT, int PREC, bool FUSED, int COARSE = 0>
 __global__ __launch_bounds__(chunk_threads(PREC, COARSE)) void k_apply_chunks(UArgs a, ChunkArgs ca, BrickK<VT> kc, CgArgs cg) {
@@ -675,7 +675,10 @@ __global__ __launch_bounds__(chunk_threads(PREC, COARSE)) void k_apply_chunks(UA
   __shared__ uint32_t gmask_s[NT / 64];
   uint32_t mall = 0;
   int g0 = -1, g1 = -1;
-  double e0[COARSE ? 24 : 1];
+  // E^-1 columns prefetched: two regions' (FP32, BF16), one region's in FP64
+  // (their 24 registers keep the FP64 pass within 128 VGPRs at 512 threads)
+  constexpr int EPF = sizeof(VT) == 8 ? 12 : 24;
+  double e0[COARSE ? EPF : 1];
   if (COARSE && a.zq_part) {
     uint32_t m = 0;
 #pragma unroll
@@ -693,7 +696,7 @@ __global__ __launch_bounds__(chunk_threads(PREC, COARSE)) void k_apply_chunks(UA
     g1 = m1 ? __ffs((int)m1) - 1 : -1;
     const int R = a.coarse_R, kk = 12 * R;
 #pragma unroll
-    for (int u = 0; u < 24; ++u) {
+    for (int u = 0; u < EPF; ++u) {
       const int g = u < 12 ? g0 : g1, v = u % 12;
       e0[u] = (g >= 0 && tid < kk) ? a.einv[(long)(((v / 3) * R + g) * 3 + v % 3) * kk + tid] : 0.0;
     }
@@ -898,18 +901,18 @@ __global__ __launch_bounds__(chunk_threads(PREC, COARSE)) void k_apply_chunks(UA
     }
     __syncthreads();
     // E^-1 Z^T q over the nonzero columns (twelve per region present; E^-1
-    // symmetric, so column i serves as row i): those of the first two regions
-    // are in e0 (for j = tid), the others are loaded two regions at a time
+    // symmetric, so column i serves as row i): those of the first one or two
+    // regions are in e0 (for j = tid), the others are loaded two at a time
     for (int j = tid; j < kk; j += NT) {
       double wj = 0.0;
       uint32_t rest = mall;
       if (j == tid) {
 #pragma unroll
-        for (int u = 0; u < 24; ++u) {
+        for (int u = 0; u < EPF; ++u) {
           const int g = u < 12 ? g0 : g1, v = u % 12;
           if (g >= 0) wj += e0[u] * czs[((v / 3) * R + g) * 3 + v % 3];
         }
-        rest &= ~((g0 >= 0 ? 1u << g0 : 0u) | (g1 >= 0 ? 1u << g1 : 0u));
+        rest &= ~((g0 >= 0 ? 1u << g0 : 0u) | (EPF > 12 && g1 >= 0 ? 1u << g1 : 0u));
       }
       while (rest) {
         const int ga = __ffs((int)rest) - 1;
