@@ -398,9 +398,9 @@ def c4_simp(torch, binding, synth, regions=(2, 2, 2)):
 
 
 def cpu_baseline(synth, case, tree, mesh, rho_h, gpu_iters):
-    """The oracle's Jacobi-PCG on the same C2 system, single thread: time a
-    bounded number of iterations and scale to the iteration count a full
-    1e-8 solve needs (taken from the FP64 GPU solve of the same system)."""
+    """The oracle's Jacobi-PCG on the same C2 system, single thread: one full
+    solve to a relative residual of 1e-8 (about 10 s of CPU work), timed as
+    it stands; the assembly before it is reported, not counted."""
     from threadpoolctl import threadpool_limits
 
     from oracle import mesh as om, system as osys
@@ -415,15 +415,14 @@ def cpu_baseline(synth, case, tree, mesh, rho_h, gpu_iters):
         rho_o[eperm] = rho_h
         s = osys.build_system(m, osys.elem_coeff(m, rho_o), om.fixed_dofs(m, case.fixed), om.load_vector(m, case.load))
         setup = time.perf_counter() - t0
-        n_it = 150
-        r = osys.pcg_jacobi(s.A, s.b, rtol=1e-30, max_it=n_it)
+        r = osys.pcg_jacobi(s.A, s.b, rtol=1e-8, max_it=20000)
         per_it = r.seconds / max(1, r.iters)
-    iters = gpu_iters or r.iters
-    log(f"[bench] CPU oracle: setup {setup:.1f}s, {per_it * 1e3:.2f} ms/iteration x {iters} iterations")
-    return dict(value=round(per_it * iters * 1e3, 1), unit="ms", cores=1, kind="oracle",
-                sample=f"oracle Jacobi-PCG on the same assembled system: {n_it} iterations timed "
-                       f"({r.seconds:.1f}s), scaled to the {iters} iterations of a full 1e-8 solve; "
-                       f"assembly/setup {setup:.1f}s not included; host {platform.processor() or platform.machine()}")
+    log(f"[bench] CPU oracle: setup {setup:.1f}s, full solve {r.seconds:.1f}s: {r.iters} iterations "
+        f"({per_it * 1e3:.2f} ms each; the FP64 GPU solve took {gpu_iters}), true rel. residual {r.rel_res:.2e}")
+    return dict(value=round(r.seconds * 1e3, 1), unit="ms", cores=1, kind="oracle",
+                sample=f"oracle Jacobi-PCG on the same assembled system, one full solve to 1e-8: {r.iters} "
+                       f"iterations in {r.seconds:.1f}s; assembly/setup {setup:.1f}s not included; "
+                       f"host {platform.processor() or platform.machine()}")
 
 
 if __name__ == "__main__":
