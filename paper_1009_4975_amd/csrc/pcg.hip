@@ -469,19 +469,25 @@ __global__ __launch_bounds__(256) void k_cg_update_rec(VT* __restrict__ x, VT* _
   const bool col = blockIdx.x >= RED_BLOCKS;
   const int j = (int)blockIdx.x - RED_BLOCKS;
   const long i0 = blockIdx.x * (long)blockDim.x + threadIdx.x, stride = (long)RED_BLOCKS * blockDim.x;
-  // first node of this thread, and the column sums, requested before the
-  // p.q partials are reduced
-  VT xv[3], pv[3], rv[3], qv[3], mv[MW];
-  const bool in0 = !col && i0 < nn;
+  // the first UPT nodes of this thread (meshes larger than the grid give a
+  // thread more than one), and the column sums, requested before the p.q
+  // partials are reduced
+  constexpr int UPT = 2;
+  VT xv[UPT][3], pv[UPT][3], rv[UPT][3], qv[UPT][3], mv[UPT][MW];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    xv[c] = in0 ? x[3 * i0 + c] : (VT)0;
-    pv[c] = in0 ? p[3 * i0 + c] : (VT)0;
-    rv[c] = in0 ? r[3 * i0 + c] : (VT)0;
-    qv[c] = in0 ? q[3 * i0 + c] : (VT)0;
+  for (int u = 0; u < UPT; ++u) {
+    const long i = i0 + u * stride;
+    const bool in = !col && i < nn;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      xv[u][c] = in ? x[3 * i + c] : (VT)0;
+      pv[u][c] = in ? p[3 * i + c] : (VT)0;
+      rv[u][c] = in ? r[3 * i + c] : (VT)0;
+      qv[u][c] = in ? q[3 * i + c] : (VT)0;
+    }
+#pragma unroll
+    for (int c = 0; c < MW; ++c) mv[u][c] = in ? minv[MW * i + c] : (VT)0;
   }
-#pragma unroll
-  for (int c = 0; c < MW; ++c) mv[c] = in0 ? minv[MW * i0 + c] : (VT)0;
   double s1 = 0.0, s2 = 0.0;
   if (col)
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
@@ -505,35 +511,42 @@ __global__ __launch_bounds__(256) void k_cg_update_rec(VT* __restrict__ x, VT* _
     return;
   }
   double srz = 0.0, srr = 0.0;
-  for (long i = i0; i < nn; i += stride) {
-    if (i != i0) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        xv[c] = x[3 * i + c];
-        pv[c] = p[3 * i + c];
-        rv[c] = r[3 * i + c];
-        qv[c] = q[3 * i + c];
-      }
-#pragma unroll
-      for (int c = 0; c < MW; ++c) mv[c] = minv[MW * i + c];
-    }
+  auto node = [&](long i, const VT* xl, const VT* pl, const VT* rl, const VT* ql, const VT* ml) {
     VT rn[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      x[3 * i + c] = xv[c] + alpha * pv[c];
-      rn[c] = rv[c] - alpha * qv[c];
+      x[3 * i + c] = xl[c] + alpha * pl[c];
+      rn[c] = rl[c] - alpha * ql[c];
       r[3 * i + c] = rn[c];
       srr += (double)rn[c] * (double)rn[c];
     }
     if (B3) {
       VT zn[3];
-      block_apply<VT>(mv, rn, zn);
+      block_apply<VT>(ml, rn, zn);
 #pragma unroll
       for (int c = 0; c < 3; ++c) srz += (double)rn[c] * (double)zn[c];
     } else {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) srz += (double)rn[c] * (double)mv[c] * (double)rn[c];
+      for (int c = 0; c < 3; ++c) srz += (double)rn[c] * (double)ml[c] * (double)rn[c];
     }
+  };
+#pragma unroll
+  for (int u = 0; u < UPT; ++u) {
+    const long i = i0 + u * stride;
+    if (i < nn) node(i, xv[u], pv[u], rv[u], qv[u], mv[u]);
+  }
+  for (long i = i0 + UPT * stride; i < nn; i += stride) {
+    VT xl[3], pl[3], rl[3], ql[3], ml[MW];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      xl[c] = x[3 * i + c];
+      pl[c] = p[3 * i + c];
+      rl[c] = r[3 * i + c];
+      ql[c] = q[3 * i + c];
+    }
+#pragma unroll
+    for (int c = 0; c < MW; ++c) ml[c] = minv[MW * i + c];
+    node(i, xl, pl, rl, ql, ml);
   }
   block_sum2(srz, srr, sh);
   if (threadIdx.x == 0) {

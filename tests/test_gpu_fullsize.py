@@ -106,6 +106,44 @@ def test_c2_solve_judged_by_oracle_operator(c2, prec):
     assert np.allclose(got, dc_want[picks], rtol=1e-10, atol=1e-12 * np.abs(dc_want).max())
 
 
+def test_recurrence_update_with_several_nodes_per_thread():
+    """An octree with more nodes (148,083) than the update pass has threads
+    (512 x 256): each thread updates two or more nodes, the first two loaded
+    before the p.q partials are reduced.  The mixed coarse-space solve (the
+    recurrence form of the timed solver) reaches 1e-8 on the library's FP64
+    true residual, and its compliance matches the plain FP64 solve's."""
+    from paper_1009_4975_amd import binding
+    pair = cases.octree_pair((32, 16, 16), 2)
+    assert pair.orc.n_nodes > 512 * 256
+    rho_o = cases.centre_density(pair, pair.case["field"])
+    ctx = binding.Context(0)
+    ctx.upload_mesh(pair.lib_mesh)
+    ctx.set_density(dev(pair.to_lib_elems(rho_o)))
+    f = dev(pair.lib_mesh.f_load)
+    b = torch.empty_like(f)
+    ctx.project_rhs(f, b)
+    comp = {}
+    for kind in ("fp64", "fp32+coarse+block3"):
+        u = torch.zeros_like(f)
+        if kind == "fp64":
+            st = ctx.pcg(b, u, rtol=1e-8, max_it=50000)
+        else:
+            ctx.coarse_setup([], 3, 2, 2, affine=True)
+            st = ctx.pcg(b, u, rtol=1e-8, inner_prec=binding.FP32, inner_rtol=0.1, max_it=50000,
+                         precond=binding.BLOCK3)
+            ctx.coarse_clear()
+        assert st["status"] == "OK" and st["rel_res"] <= 1e-8, (kind, st)
+        # the returned u carries the hanging values; the constrained system's
+        # residual takes them (and the supported entries) as zero
+        ut = u.clone()
+        ctx.mask(ut)
+        y = torch.empty_like(f)
+        ctx.apply(ut, y, binding.FP64)
+        assert float(torch.linalg.norm(b - y)) <= 1.05e-8 * float(torch.linalg.norm(b)), kind
+        comp[kind] = ctx.compliance(u, f)
+    assert comp["fp32+coarse+block3"] == pytest.approx(comp["fp64"], rel=1e-6), comp
+
+
 # ---------------------------------------------------------------------- C3
 @pytest.fixture(scope="module")
 def c3():
