@@ -208,3 +208,26 @@ def test_rebuild_tree_from_leaf_set(seed):
         rebuild_tree(base, L, lv[1:], an[1:])
     with pytest.raises(ValueError):
         rebuild_tree((4, 2, 1), L, lv, an)
+
+
+def test_sweep2_case_matches_oracle():
+    """The hand-built sweep-2 tree (a complete void family whose derefinement
+    would put an edge-4 leaf next to edge-1 leaves): the library's adaptation
+    drops it exactly as the oracle's does and leaves the tree unchanged."""
+    from test_oracle_amr import sweep2_tree
+    level, anchor, L = sweep2_tree()
+    t = binding.Octree((2, 1, 1), L)
+    want = leafset(level, anchor)
+    for _ in range(L):
+        tl, ta = t.leaves()
+        # split every library leaf that is an ancestor of (strictly contains) a target leaf
+        s = 1 << (L - tl)
+        marks = [any(lv > l and (a >= an).all() and (a < an + sz).all() for lv, a in zip(level, anchor))
+                 for l, an, sz in zip(tl, ta, s)]
+        t.refine(np.array(marks, np.uint8))
+    tl, ta = t.leaves()
+    assert leafset(tl, ta) == want
+    rho = np.where(tl == 3, 1.0, 0.1)
+    t.adapt(rho, 0.5, 1.5)
+    nl, na = t.leaves()
+    assert leafset(nl, na) == want
