@@ -148,11 +148,25 @@ def _ptr(t) -> Optional[int]:
 
 def _dev(t, dtype=None):
     import torch
-    assert isinstance(t, torch.Tensor) and t.is_cuda, "expected a device tensor"
-    if dtype is not None:
-        assert t.dtype == dtype, f"expected {dtype}, got {t.dtype}"
-    assert t.is_contiguous()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise AmrtoError(-1, "expected a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise AmrtoError(-1, f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise AmrtoError(-1, "device buffers must be contiguous")
     return t.data_ptr()
+
+
+def _need(n, **bufs):
+    """Raise EINVAL unless every given buffer (None skipped) holds exactly n
+    values: the C ABI takes bare pointers, so a short or stale buffer would be
+    read or written out of bounds on the device."""
+    for name, t in bufs.items():
+        if t is None:
+            continue
+        have = t.numel() if hasattr(t, "numel") else int(np.size(t))
+        if have != n:
+            raise AmrtoError(-1, f"{name} has {have} values, {n} expected")
 
 
 # ---------------------------------------------------------------------- mesh
@@ -339,9 +353,28 @@ class Context:
 
     def upload_mesh(self, mesh: MeshArrays):
         s, keep = mesh.struct()
+        self.mesh = None
         self._chk(self.lib.amrto_upload_mesh(self.h, C.byref(s)))
         del keep
         self.mesh = mesh
+
+    @property
+    def _n3(self):
+        """DOF-vector length of the uploaded mesh (None before an upload: the
+        library then answers ESTATE itself)."""
+        return None if self.mesh is None else 3 * self.mesh.n_nodes
+
+    @property
+    def _ne(self):
+        return None if self.mesh is None else self.mesh.n_elems
+
+    def _dofs(self, **bufs):
+        if self.mesh is not None:
+            _need(self._n3, **bufs)
+
+    def _elems(self, **bufs):
+        if self.mesh is not None:
+            _need(self._ne, **bufs)
 
     def info(self):
         a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
@@ -349,28 +382,36 @@ class Context:
         return dict(n_nodes=a.value, n_elems=b.value, n_chunks=c.value)
 
     def set_density(self, rho):
+        self._elems(rho=rho)
         self._chk(self.lib.amrto_set_density(self.h, _dev(rho, self.torch.float64)))
 
     def apply(self, x, y, prec=FP64):
         dt = self.torch.float64 if prec == FP64 else self.torch.float32
+        self._dofs(x=x, y=y)
         self._chk(self.lib.amrto_apply(self.h, _dev(x, dt), _dev(y, dt), int(prec)))
 
     def project_rhs(self, f, b):
+        self._dofs(f=f, b=b)
         self._chk(self.lib.amrto_project_rhs(self.h, _dev(f, self.torch.float64), _dev(b, self.torch.float64)))
 
     def recover(self, ut, u):
+        self._dofs(ut=ut, u=u)
         self._chk(self.lib.amrto_recover(self.h, _dev(ut, self.torch.float64), _dev(u, self.torch.float64)))
 
     def diag(self, out):
+        self._dofs(out=out)
         self._chk(self.lib.amrto_get_diag(self.h, _dev(out, self.torch.float64)))
 
     def block_diag(self, out):
         """3x3 node blocks of A~ into out (9 n_nodes float64, row-major per node)."""
+        if self.mesh is not None:
+            _need(9 * self.mesh.n_nodes, out=out)
         self._chk(self.lib.amrto_get_block_diag(self.h, _dev(out, self.torch.float64)))
 
     def pcg(self, b, u, rtol=1e-8, max_it=20000, inner_prec=FP64, inner_rtol=0.1, check_every=16,
             use_coarse=True, fallback_fp64=True, single_reduction=False, precond=JACOBI,
             allow_not_converged=False):
+        self._dofs(b=b, u=u)
         o = SolveOpts()
         self.lib.amrto_solve_opts_default(C.byref(o))
         o.rtol, o.max_it, o.inner_prec, o.inner_rtol = rtol, max_it, inner_prec, inner_rtol
@@ -386,6 +427,8 @@ class Context:
                     fell_back=bool(st.fell_back))
 
     def compliance(self, u, f, rho=None, dc=None):
+        self._dofs(u=u, f=f)
+        self._elems(rho=rho, dc=dc)
         c = C.c_double()
         self._chk(self.lib.amrto_compliance(self.h, _dev(u, self.torch.float64), _dev(f, self.torch.float64),
                                             None if rho is None else _dev(rho, self.torch.float64),
@@ -393,15 +436,19 @@ class Context:
         return c.value
 
     def sensitivity(self, u, rho, dc):
+        self._dofs(u=u)
+        self._elems(rho=rho, dc=dc)
         self._chk(self.lib.amrto_compliance(self.h, _dev(u, self.torch.float64), None,
                                             _dev(rho, self.torch.float64), None, _dev(dc, self.torch.float64)))
 
     def filter(self, mode, rmin, inp, out, rho=None):
+        self._elems(inp=inp, out=out, rho=rho)
         self._chk(self.lib.amrto_filter(self.h, int(mode), float(rmin), _dev(inp, self.torch.float64),
                                         None if rho is None else _dev(rho, self.torch.float64),
                                         _dev(out, self.torch.float64)))
 
     def oc_update(self, rho, dc, rho_new, volfrac, move=0.2, eta=0.5, rho_min=1e-3):
+        self._elems(rho=rho, dc=dc, rho_new=rho_new)
         ch, lam = C.c_double(), C.c_double()
         self._chk(self.lib.amrto_oc_update(self.h, _dev(rho, self.torch.float64), _dev(dc, self.torch.float64),
                                            volfrac, move, eta, rho_min, _dev(rho_new, self.torch.float64),
@@ -409,11 +456,13 @@ class Context:
         return ch.value, lam.value
 
     def mask(self, x):
+        self._dofs(x=x)
         self._chk(self.lib.amrto_mask(self.h, _dev(x, self.torch.float64)))
 
     def coarse_setup(self, fields, rx, ry, rz, affine=False):
         """fields: sequence of float64 device vectors (3n); returns the rank kept."""
         n = len(fields)
+        self._dofs(**{f"fields[{i}]": f for i, f in enumerate(fields)})
         arr = (_p * max(n, 1))(*[_dev(f, self.torch.float64) for f in fields])
         kept = C.c_int32()
         self._chk(self.lib.amrto_coarse_setup(self.h, int(bool(affine)), arr, n, int(rx), int(ry), int(rz),
@@ -433,6 +482,7 @@ class Context:
 
     def energy_combine(self, b, vecs, x0, base=None):
         n = len(vecs)
+        self._dofs(b=b, x0=x0, base=base, **{f"vecs[{i}]": v for i, v in enumerate(vecs)})
         f64 = self.torch.float64
         arr = (_p * n)(*[_dev(v, f64) for v in vecs])
         coef = (C.c_double * n)()
@@ -440,14 +490,33 @@ class Context:
                                                 arr, n, _dev(x0, f64), coef))
         return list(coef)
 
+    def _grid_nodes(self, cell):
+        """Node count of the regular grid with nodes every `cell` lattice units
+        (None when there is no mesh or the cell does not divide the extents:
+        the library rejects those itself)."""
+        if self.mesh is None or cell <= 0 or any(int(d) % int(cell) for d in self.mesh.dims):
+            return None
+        gx, gy, gz = (int(d) // int(cell) for d in self.mesh.dims)
+        return (gx + 1) * (gy + 1) * (gz + 1)
+
     def grid_from_mesh(self, cell, rho=None, u=None, rho_grid=None, u_grid=None, u_scale=1.0, u_ref=None):
         f64, f32 = self.torch.float64, self.torch.float32
+        self._dofs(u=u, u_ref=u_ref)
+        self._elems(rho=rho)
+        g = self._grid_nodes(cell)
+        if g is not None:
+            _need(g, rho_grid=rho_grid)
+            _need(3 * g, u_grid=u_grid)
         self._chk(self.lib.amrto_grid_from_mesh(
             self.h, int(cell), None if rho is None else _dev(rho, f64), None if u is None else _dev(u, f64),
             None if u_ref is None else _dev(u_ref, f64), float(u_scale),
             None if rho_grid is None else _dev(rho_grid, f32), None if u_grid is None else _dev(u_grid, f32)))
 
     def grid_to_mesh(self, cell, u_grid, u, scale=1.0):
+        self._dofs(u=u)
+        g = self._grid_nodes(cell)
+        if g is not None:
+            _need(3 * g, u_grid=u_grid)
         self._chk(self.lib.amrto_grid_to_mesh(self.h, int(cell), _dev(u_grid, self.torch.float32), float(scale),
                                               _dev(u, self.torch.float64)))
 
@@ -515,15 +584,28 @@ class Net:
         assert m.size == v.size == self.n_params()
         self._chk(self.lib.amrto_net_set_adam(self.h, m.ctypes.data, v.ctypes.data))
 
+    def _act(self, batch, ch):
+        gx, gy, gz = self.grid
+        return batch * ch * gx * gy * gz
+
     def forward(self, x, out):
+        batch = int(x.shape[0]) if x.dim() > 0 else 0
+        _need(self._act(batch, self.channels[0]), x=x)
+        _need(self._act(batch, self.channels[-1]), out=out)
+        self._batch = batch
         self._chk(self.lib.amrto_net_forward(self.h, _dev(x, self.torch.float32), int(x.shape[0]),
                                              _dev(out, self.torch.float32)))
 
     def backward(self, dout, din=None):
+        batch = getattr(self, "_batch", None)
+        if batch is not None:
+            _need(self._act(batch, self.channels[-1]), dout=dout)
+            _need(self._act(batch, self.channels[0]), din=din)
         self._chk(self.lib.amrto_net_backward(self.h, _dev(dout, self.torch.float32),
                                               None if din is None else _dev(din, self.torch.float32)))
 
     def mse(self, pred, target, dpred, mask=None):
+        _need(pred.numel(), target=target, dpred=dpred, mask=mask)
         loss = C.c_double()
         self._chk(self.lib.amrto_net_mse(self.h, _dev(pred, self.torch.float32), _dev(target, self.torch.float32),
                                          None if mask is None else _dev(mask, self.torch.uint8), int(pred.numel()),
