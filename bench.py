@@ -421,8 +421,27 @@ def cpu_baseline(synth, case, tree, mesh, rho_h, gpu_iters):
         f"({per_it * 1e3:.2f} ms each; the FP64 GPU solve took {gpu_iters}), true rel. residual {r.rel_res:.2e}")
     return dict(value=round(r.seconds * 1e3, 1), unit="ms", cores=1, kind="oracle",
                 sample=f"oracle Jacobi-PCG on the same assembled system, one full solve to 1e-8: {r.iters} "
-                       f"iterations in {r.seconds:.1f}s; assembly/setup {setup:.1f}s not included; "
-                       f"host {platform.processor() or platform.machine()}")
+                       f"iterations in {r.seconds:.1f}s; assembly/setup {setup:.1f}s not included",
+                host=host_info(), threads="1 (threadpoolctl limit on BLAS/OpenMP; SciPy CSR matvec is serial)")
+
+
+def host_info():
+    """CPU model, logical CPUs and thread settings of the host the oracle runs on."""
+    model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
+    return dict(cpu_model=model, os_cpu_count=os.cpu_count(), affinity_cpus=affinity,
+                OMP_NUM_THREADS=os.environ.get("OMP_NUM_THREADS"))
 
 
 if __name__ == "__main__":

@@ -161,8 +161,10 @@ def c3():
     return ctx, x, y
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 5e-6), ("bf16", 1e-2)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 5e-6), ("bf16", 1e-4)])
 def test_c3_apply_fullsize(c3, prec, tol):
+    """BF16: the hi + lo split bound of 1e-4 of max |y| (derived in
+    tests/test_bf16_split.py, which also shows a hi-only contraction failing it)."""
     from paper_1009_4975_amd import binding
     ctx, x, y = c3
     p = {"fp64": binding.FP64, "fp32": binding.FP32, "bf16": binding.BF16}[prec]
@@ -270,7 +272,12 @@ def test_c5_fp32_recurrence_floor_is_caught(c5):
     """inner_rtol 1e-3 asks the FP32 recurrence for more than its attainable
     accuracy on this contrast-1e6 system: it levels off, a reliable update is
     forced after 2048 iterations without progress, the stalled mixed solve
-    ends and plain FP64 PCG finishes to the requested residual."""
+    ends and plain FP64 PCG finishes to the requested residual.  The result is
+    judged against the 1e-11 reference u at 1e-6 relative error.  The error of
+    an iterate is bounded by cond(A~) times its relative residual, and this
+    system's condition number (contrast 1e6 at 1.6M DOFs) is far above 100,
+    so a 1e-8 residual does not imply a 1e-6 error: the solve is run to 1e-10,
+    where it does."""
     from paper_1009_4975_amd import binding
     case, mesh, o, prob, c, g, u = c5
     ctx = binding.Context(0)
@@ -280,6 +287,9 @@ def test_c5_fp32_recurrence_floor_is_caught(c5):
     b = torch.empty_like(f)
     ctx.project_rhs(f, b)
     x = torch.zeros_like(f)
-    st = ctx.pcg(b, x, rtol=1e-8, max_it=100000, inner_prec=binding.FP32, inner_rtol=1e-3)
-    assert st["status"] == "OK" and st["rel_res"] <= 1e-8 and st["fell_back"], st
+    st = ctx.pcg(b, x, rtol=1e-10, max_it=100000, inner_prec=binding.FP32, inner_rtol=1e-3)
+    assert st["status"] == "OK" and st["rel_res"] <= 1e-10 and st["fell_back"], st
+    err = np.linalg.norm(host(x) - u) / np.linalg.norm(u)
+    print(f"C5 stalled mixed solve finished by FP64 to 1e-10: relative error {err:.2e}")
+    assert err <= 1e-6, err
 

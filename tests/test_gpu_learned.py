@@ -221,36 +221,80 @@ def test_coarse_setup_drops_dependent_columns(c1_small):
 
 
 # ---------------------------------------------------------------------- learned gain
-def test_learned_warm_start_and_coarse_space_gain():
-    """Small adaptive bridge run: train on iterations 1-10, then compare the
-    solves of iterations 11-15 with the plain warm start (previous solution).
-    The network must fit its training pairs better than the no-change
-    prediction; the learned start with the affine coarse space must reach the
-    same designs in fewer iterations."""
+def energy(sim, x):
+    """J(x) = x^T A~ x / 2 - b^T x on the simulation's current system (FP64),
+    over the unconstrained DOFs (supported and hanging entries, which the solve
+    ignores, zeroed on a copy first)."""
+    from paper_1009_4975_amd import binding
+    x = x.clone()
+    sim.ctx.mask(x)
+    y = torch.empty_like(x)
+    sim.ctx.apply(x, y, binding.FP64)
+    return 0.5 * float(x @ y) - float(sim.b @ x)
+
+
+def test_learned_gain_over_the_same_method_without_the_network():
+    """Small adaptive bridge run: a network trained on iterations 1-10 is used
+    on iterations 11-15 and compared with the same solver without it:
+    (a) learned start + affine coarse space against the affine coarse space
+    alone (both from u_prev), (b) learned start alone against u_prev alone.
+    What the network gains is measured two ways and printed: the fraction of
+    the initial energy error J(u_prev) - J(u*) its start removes, and the PCG
+    iterations.  Asserted: the network fits its training pairs better than the
+    no-change prediction; its start is never worse than u_prev in energy (the
+    combination is an energy line search); every solve reaches 1e-8 on the same
+    designs.  The affine coarse space's own gain is asserted separately."""
     from paper_1009_4975_amd.learned import LearnedWarmStart
     from paper_1009_4975_amd.simp import AdaptiveSIMP
     base, L = (8, 4, 4), 2
     dims = tuple(x << L for x in base)
     fixed, load = synth.bridge_bc(*dims)
-    plain = AdaptiveSIMP(base, L, fixed, load, rtol=1e-8)
-    lrn = AdaptiveSIMP(base, L, fixed, load, rtol=1e-8)
+    sims = {k: AdaptiveSIMP(base, L, fixed, load, rtol=1e-8) for k in ("plain", "affine", "net+affine", "net")}
     ws = LearnedWarmStart(dims, cell=2, hidden=8, layers=3, epochs=150, regions=(2, 2, 2), coarse="affine")
     for _ in range(10):
-        rp = plain.step()
-        rl = lrn.step(warm_start=ws.collect_before, after_solve=ws.collect_after)
-        # same solves (LDS accumulation order may move the count by one or two)
-        assert abs(rl["iters"] - rp["iters"]) <= max(2, rp["iters"] // 20)
+        recs = {k: (s.step(warm_start=ws.collect_before, after_solve=ws.collect_after) if k == "net+affine"
+                    else s.step()) for k, s in sims.items()}
+        it0 = recs["plain"]["iters"]
+        for r in recs.values():  # same solves (LDS accumulation order may move the count by one or two)
+            assert abs(r["iters"] - it0) <= max(2, it0 // 20)
     assert ws.n_pairs == 9
     base_loss = ws.baseline_loss()
     final = ws.train()
     assert final < 0.5 * base_loss
-    it_plain = it_lrn = 0
+    hooks = {"plain": None,
+             "affine": lambda s: ws.warm_start(s, use_net=False, coarse="affine"),
+             "net+affine": lambda s: ws.warm_start(s, use_net=True, coarse="affine"),
+             "net": lambda s: ws.warm_start(s, use_net=True, coarse=False)}
+    iters = {k: 0 for k in sims}
+    gain = {"net+affine": [], "net": []}
     for _ in range(5):
-        rp = plain.step()
-        rl = lrn.step(warm_start=ws.warm_start)
-        assert ws.last["kept"] > 0
-        assert rl["rel_res"] <= 1e-8 and rp["rel_res"] <= 1e-8
-        assert rl["compliance"] == pytest.approx(rp["compliance"], rel=1e-5)
-        it_plain += rp["iters"]
-        it_lrn += rl["iters"]
-    assert it_lrn < 0.85 * it_plain
+        comp = {}
+        for k, s in sims.items():
+            starts = {}
+
+            def hook(sim, k=k):
+                if hooks[k] is None:
+                    return
+                starts["prev"] = energy(sim, sim.u)
+                hooks[k](sim)
+                starts["x0"] = energy(sim, sim.u)
+
+            r = s.step(warm_start=hook)
+            assert r["rel_res"] <= 1e-8
+            iters[k] += r["iters"]
+            comp[k] = r["compliance"]
+            if k in gain:
+                j_star = energy(s, s.u)
+                # the line search never raises the energy
+                assert starts["x0"] <= starts["prev"] + 1e-12 * abs(starts["prev"])
+                gain[k].append((starts["prev"] - starts["x0"]) / (starts["prev"] - j_star))
+            s.ctx.coarse_clear()
+        for k in sims:
+            assert comp[k] == pytest.approx(comp["plain"], rel=1e-5)
+    print(f"learned gain, iterations 11-15: PCG iterations plain {iters['plain']}, net {iters['net']} "
+          f"({iters['net'] / iters['plain']:.3f}x), affine {iters['affine']}, net+affine {iters['net+affine']} "
+          f"({iters['net+affine'] / iters['affine']:.3f}x); share of the start's energy error removed by the "
+          f"network: alone {np.round(gain['net'], 4).tolist()}, with the coarse space "
+          f"{np.round(gain['net+affine'], 4).tolist()}")
+    assert min(gain["net"]) >= 0.0 and min(gain["net+affine"]) >= 0.0
+    assert iters["affine"] < 0.85 * iters["plain"]
