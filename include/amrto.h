@@ -116,7 +116,9 @@ typedef struct {
  * hanging-node tables and the solver workspace.  Replaces any earlier mesh
  * (densities must be set again).  Errors: EINVAL (inconsistent sizes, node
  * indices out of range, a hanging master that is hanging, a chunk whose node
- * table cannot fit, 3 n_nodes or 8 n_elems not below 2^31), ENOMEM, EHIP. */
+ * table cannot fit, 3 n_nodes or 8 n_elems not below 2^31, an octree whose
+ * finest lattice has more than 2^30 cells: the filter's cell map holds one
+ * int32 per cell), ENOMEM, EHIP. */
 int amrto_upload_mesh(amrto_ctx* ctx, const amrto_mesh* mesh);
 
 /* Sizes of the uploaded mesh. */
@@ -182,6 +184,12 @@ typedef struct {
                          arithmetic); 0 (default): two passes, which measured
                          faster on the octree cantilever (the one pass carries
                          the update's gathers and is as long as both) */
+  int32_t record;     /* 1: keep the first m preconditioned residuals and the
+                         CG coefficients of this solve for
+                         amrto_recycle_harvest (needs amrto_recycle_setup; FP64
+                         solves, Jacobi with or without a coarse space, or
+                         block-Jacobi without one; only the first CG run of a
+                         solve is recorded).  0 (default): nothing recorded */
 } amrto_solve_opts;
 
 typedef struct {
@@ -212,6 +220,58 @@ void amrto_solve_opts_default(amrto_solve_opts* opts);
 int amrto_pcg(amrto_ctx* ctx, const double* b_dev, double* u_dev,
               const amrto_solve_opts* opts, amrto_solve_stats* stats);
 
+/* Measurement of the solver's two passes per iteration: the variant named by
+ * opts (precision, preconditioner, coarse space in use) is started from
+ * u_dev as amrto_pcg starts it, run for two iterations, then its operator
+ * pass (stiffness apply fused with the preconditioner and the search
+ * direction update) is launched reps times back to back, then its update
+ * side (vector updates, preconditioner, reductions, coarse-space recurrences)
+ * reps times; *op_us and *update_us receive the mean device time of one
+ * launch of each from HIP events on the context stream.  u_dev is left
+ * masked and otherwise unchanged (FP64 variants use it as the iterate and
+ * leave it overwritten); nothing else computed is a result, and the next
+ * amrto_pcg starts afresh.  Synchronises.  Errors as amrto_pcg; EINVAL for
+ * reps outside [1, 100000]. */
+int amrto_pcg_pass_times(amrto_ctx* ctx, const double* b_dev, double* u_dev, const amrto_solve_opts* opts,
+                         int32_t reps, double* op_us, double* update_us);
+
+/* ------------------------------------------------------------------ recycling
+ * Krylov subspace recycling across the systems of a design sequence (Sec. 5:
+ * an approximate invariant subspace for the smallest eigenvalues, taken from
+ * one solve's Krylov space, is carried to the next system).  A recorded FP64
+ * solve keeps its first m preconditioned residuals z_j with r_j^T z_j and
+ * p_j^T A~ p_j; their Lanczos matrix T (T[j][j] = 1/alpha_j +
+ * beta_{j-1}/alpha_{j-1}, T[j][j+1] = sqrt(beta_j)/alpha_j, Lanczos vectors
+ * (-1)^j z_j / sqrt(r_j^T z_j)) gives Ritz pairs of the solve's preconditioned
+ * operator.  Rayleigh-Ritz for the pencil (A~, D), D = diag(A~), picks the
+ * best k directions of a set of vectors for the current system; the caller
+ * passes them to amrto_coarse_setup as fields. */
+
+/* Allocate the recording store (m x 3 n_nodes doubles plus Rayleigh-Ritz
+ * workspace of 16 x 3 n_nodes) for the uploaded mesh; 2 <= m <= 256.  A new
+ * mesh drops it.  Errors: EINVAL, ESTATE (no mesh), ENOMEM, EHIP. */
+int amrto_recycle_setup(amrto_ctx* ctx, int32_t m);
+/* From the last recorded solve: the k (1..16) smallest Ritz values
+ * (theta_host, may be NULL), their Lanczos residual norms
+ * |T[m-1][m] y_{m-1}| = ||A~ u - theta M u||_{M^-1} (resid_host, may be NULL),
+ * the Ritz vectors u_i = V y_i into the k device vectors u_host[i] (3 n FP64,
+ * M-normalised, zero on supported and hanging DOFs) and the number of Lanczos
+ * steps used (*m_used, may be NULL; the solve's iterations + 1 or m, minus
+ * one).  Synchronises.  Errors: ESTATE (nothing recorded, or fewer than k + 1
+ * steps), EINVAL, EBREAKDOWN (a non-positive recorded coefficient). */
+int amrto_recycle_harvest(amrto_ctx* ctx, int32_t k, double* const* u_host, double* theta_host,
+                          double* resid_host, int32_t* m_used);
+/* Rayleigh-Ritz: the k smallest pairs of S^T A~ S y = theta S^T D S y over
+ * the span of the n (1..16) device vectors s_host[i] (3 n FP64, masked),
+ * D = diag(A~) of the current density; w_host[i] (k outputs, distinct from
+ * the inputs) receive W = S Y with W^T D W = I, theta_host (may be NULL) the
+ * values, *rank (may be NULL) the number of independent input directions
+ * kept (eigenvalues of S^T D S above 1e-12 of the largest).  Synchronises.
+ * Errors: ESTATE (no density or no amrto_recycle_setup), EINVAL (sizes,
+ * aliasing, inputs spanning fewer than k directions). */
+int amrto_rayleigh_ritz(amrto_ctx* ctx, const double* const* s_host, int32_t n, int32_t k,
+                        double* const* w_host, double* theta_host, int32_t* rank);
+
 /* ------------------------------------------------------------------ design */
 
 /* Compliance c = f^T u (Eq. (1)) into *c_host (may be NULL) and, if dc_dev is
@@ -224,7 +284,11 @@ int amrto_compliance(amrto_ctx* ctx, const double* u_dev, const double* f_dev,
  * centres (Eq. (4)) and volume weights (Eq. (5)):
  *  SENSITIVITY: out_e = sum_d rho_d H V_d in_d / (max(rho_e, 1e-3) sum_d H V_d)
  *  DENSITY:     out_e = sum_d H V_d in_d / sum_d H V_d
- * rho_dev is ignored in DENSITY mode.  in/out must not alias. */
+ * rho_dev is ignored in DENSITY mode.  in/out must not alias.  Any rmin in
+ * (0, 16] (finest-lattice units) works on the same mesh: neighbours are found
+ * on the device from the lattice cell map built by amrto_upload_mesh, so the
+ * call builds, copies and allocates nothing.  Errors: EINVAL (mode, rmin,
+ * NULL or aliased buffers), ESTATE (no mesh). */
 int amrto_filter(amrto_ctx* ctx, int mode, double rmin, const double* in_dev,
                  const double* rho_dev, double* out_dev);
 
@@ -236,6 +300,18 @@ int amrto_filter(amrto_ctx* ctx, int mode, double rmin, const double* in_dev,
 int amrto_oc_update(amrto_ctx* ctx, const double* rho_dev, const double* dc_dev,
                     double volfrac, double move, double eta, double rho_min,
                     double* rho_new_dev, double* change_host, double* lam_host);
+
+/* Relative difference of two designs (Sec. 7, Eq. (10)):
+ *   D = int |rho_a - rho_b| dOmega / int rho_a dOmega,
+ * evaluated on the finest lattice after carrying both designs to the finest
+ * level everywhere (each cell takes its covering leaf's density; a uniform
+ * brick's elements are the cells).  rho_a_dev / rho_b_dev: per-element
+ * densities of the meshes uploaded to contexts a and b, which must be on one
+ * device and cover the same lattice box.  The work runs on a's stream; b's
+ * densities must be ready.  Synchronises a's stream.  Errors: EINVAL
+ * (different boxes or devices, NULL), ESTATE (no mesh). */
+int amrto_design_difference(amrto_ctx* a, const double* rho_a_dev, const amrto_ctx* b,
+                            const double* rho_b_dev, double* D_host);
 
 /* Zero the supported and hanging entries of a DOF vector x_dev[3n] in place
  * (the entries whose rows of A~ are the identity with zero right-hand side). */

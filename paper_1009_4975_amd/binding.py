@@ -46,7 +46,8 @@ class Region(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_it", C.c_int32), ("precond", C.c_int32),
                 ("inner_prec", C.c_int32), ("inner_rtol", C.c_double), ("check_every", C.c_int32),
-                ("use_coarse", C.c_int32), ("fallback_fp64", C.c_int32), ("single_reduction", C.c_int32)]
+                ("use_coarse", C.c_int32), ("fallback_fp64", C.c_int32), ("single_reduction", C.c_int32),
+                ("record", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -70,10 +71,18 @@ _SIGS = {
     "amrto_get_block_diag": (C.c_int, [_p, _p]),
     "amrto_solve_opts_default": (None, [C.POINTER(SolveOpts)]),
     "amrto_pcg": (C.c_int, [_p, _p, _p, C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
+    "amrto_pcg_pass_times": (C.c_int, [_p, _p, _p, C.POINTER(SolveOpts), C.c_int32, C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double)]),
+    "amrto_recycle_setup": (C.c_int, [_p, C.c_int32]),
+    "amrto_recycle_harvest": (C.c_int, [_p, C.c_int32, C.POINTER(_p), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double), _i32p]),
+    "amrto_rayleigh_ritz": (C.c_int, [_p, C.POINTER(_p), C.c_int32, C.c_int32, C.POINTER(_p),
+                                      C.POINTER(C.c_double), _i32p]),
     "amrto_compliance": (C.c_int, [_p, _p, _p, _p, C.POINTER(C.c_double), _p]),
     "amrto_filter": (C.c_int, [_p, C.c_int, C.c_double, _p, _p, _p]),
     "amrto_oc_update": (C.c_int, [_p, _p, _p, C.c_double, C.c_double, C.c_double, C.c_double, _p,
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "amrto_design_difference": (C.c_int, [_p, _p, _p, _p, C.POINTER(C.c_double)]),
     "amrto_mask": (C.c_int, [_p, _p]),
     "amrto_coarse_setup": (C.c_int, [_p, C.c_int32, C.POINTER(_p), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                      _i32p]),
@@ -410,7 +419,7 @@ class Context:
 
     def pcg(self, b, u, rtol=1e-8, max_it=20000, inner_prec=FP64, inner_rtol=0.1, check_every=16,
             use_coarse=True, fallback_fp64=True, single_reduction=False, precond=JACOBI,
-            allow_not_converged=False):
+            allow_not_converged=False, record=False):
         self._dofs(b=b, u=u)
         o = SolveOpts()
         self.lib.amrto_solve_opts_default(C.byref(o))
@@ -419,12 +428,49 @@ class Context:
         o.check_every, o.use_coarse = check_every, int(bool(use_coarse))
         o.fallback_fp64 = int(bool(fallback_fp64))
         o.single_reduction = int(bool(single_reduction))
+        o.record = int(bool(record))
         st = SolveStats()
         rc = self.lib.amrto_pcg(self.h, _dev(b, self.torch.float64), _dev(u, self.torch.float64), C.byref(o),
                                 C.byref(st))
         self._chk(rc, allow_not_converged=allow_not_converged)
         return dict(iters=st.iters, outer=st.outer, rel_res=st.rel_res, ms=st.ms, status=STATUS[rc],
                     fell_back=bool(st.fell_back))
+
+    def recycle_setup(self, m):
+        self._chk(self.lib.amrto_recycle_setup(self.h, int(m)))
+
+    def recycle_harvest(self, outs):
+        """Ritz vectors of the last recorded solve into the FP64 DOF vectors
+        `outs`; returns (theta, residual norms, Lanczos steps used)."""
+        k = len(outs)
+        self._dofs(**{f"outs[{i}]": o for i, o in enumerate(outs)})
+        arr = (_p * k)(*[_dev(o, self.torch.float64) for o in outs])
+        th, rs, m = (C.c_double * k)(), (C.c_double * k)(), C.c_int32()
+        self._chk(self.lib.amrto_recycle_harvest(self.h, k, arr, th, rs, C.byref(m)))
+        return list(th), list(rs), m.value
+
+    def rayleigh_ritz(self, vecs, outs):
+        """The len(outs) smallest Rayleigh-Ritz pairs of (A~, diag A~) on
+        span(vecs); returns (theta, rank kept)."""
+        n, k = len(vecs), len(outs)
+        self._dofs(**{f"vecs[{i}]": v for i, v in enumerate(vecs)}, **{f"outs[{i}]": o for i, o in enumerate(outs)})
+        sa = (_p * n)(*[_dev(v, self.torch.float64) for v in vecs])
+        wa = (_p * k)(*[_dev(o, self.torch.float64) for o in outs])
+        th, rank = (C.c_double * k)(), C.c_int32()
+        self._chk(self.lib.amrto_rayleigh_ritz(self.h, sa, n, k, wa, th, C.byref(rank)))
+        return list(th), rank.value
+
+    def pcg_pass_times(self, b, u, reps=200, inner_prec=FP64, precond=JACOBI, use_coarse=True):
+        """Mean device time (us) of one launch of the solver variant's operator
+        pass and of its update side (amrto_pcg_pass_times)."""
+        self._dofs(b=b, u=u)
+        o = SolveOpts()
+        self.lib.amrto_solve_opts_default(C.byref(o))
+        o.inner_prec, o.precond, o.use_coarse = inner_prec, int(precond), int(bool(use_coarse))
+        op, up = C.c_double(), C.c_double()
+        self._chk(self.lib.amrto_pcg_pass_times(self.h, _dev(b, self.torch.float64), _dev(u, self.torch.float64),
+                                                C.byref(o), int(reps), C.byref(op), C.byref(up)))
+        return op.value, up.value
 
     def compliance(self, u, f, rho=None, dc=None):
         self._dofs(u=u, f=f)
@@ -454,6 +500,15 @@ class Context:
                                            volfrac, move, eta, rho_min, _dev(rho_new, self.torch.float64),
                                            C.byref(ch), C.byref(lam)))
         return ch.value, lam.value
+
+    def design_difference(self, rho, other, rho_other):
+        """Eq. (10) between this context's design rho and other's rho_other."""
+        self._elems(rho=rho)
+        other._elems(rho_other=rho_other)
+        d = C.c_double()
+        self._chk(self.lib.amrto_design_difference(self.h, _dev(rho, self.torch.float64), other.h,
+                                                   _dev(rho_other, self.torch.float64), C.byref(d)))
+        return d.value
 
     def mask(self, x):
         self._dofs(x=x)

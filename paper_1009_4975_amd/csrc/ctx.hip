@@ -85,7 +85,10 @@ static void free_mesh(amrto_ctx* c) {
   dfree(c->d_hang_node); dfree(c->d_hang_ptr); dfree(c->d_hang_master); dfree(c->d_hang_w);
   dfree(c->d_mt_node); dfree(c->d_mt_ptr); dfree(c->d_mt_h); dfree(c->d_mt_w);
   c->n_mt = 0;
-  dfree(c->d_nb_ptr); dfree(c->d_nb_idx); dfree(c->d_nb_w);
+  dfree(c->d_edesc); dfree(c->d_cmap);
+  dfree(c->d_rec_store); dfree(c->d_rec_coef); dfree(c->d_rec_C); dfree(c->d_rr_aw); dfree(c->d_rr_part);
+  c->rec_m = 0;
+  c->rec_active = false;
   dfree(c->d_coef); dfree(c->d_coef_f); dfree(c->d_dinv); dfree(c->d_dinv_f); dfree(c->d_vol);
   dfree(c->d_r); dfree(c->d_z); dfree(c->d_p); dfree(c->d_q); dfree(c->d_p2); dfree(c->f_p2);
   dfree(c->d_partpq);
@@ -103,7 +106,6 @@ static void free_mesh(amrto_ctx* c) {
   c->coarse_k = 0;
   c->coarse_cap = 0;
   c->grid_cell = 0;
-  c->filt_rmin = -1.0;
   c->has_mesh = false;
   c->has_density = false;
 }
@@ -285,6 +287,8 @@ int amrto_upload_mesh(amrto_ctx* ctx, const amrto_mesh* m) {
     AMRTO_HIP(dalloc(ctx->d_elem_nodes, 8L * m->n_elems));
     AMRTO_HIP(hipMemcpy(ctx->d_elem_nodes, m->elem_nodes, 8L * m->n_elems * sizeof(int32_t), hipMemcpyHostToDevice));
     int rc = build_chunks(ctx, m);
+    if (rc != AMRTO_OK) return rc;
+    rc = build_cell_map(ctx);
     if (rc != AMRTO_OK) return rc;
   } else {
     ctx->h_node_xyz.clear();

@@ -142,12 +142,11 @@ struct amrto_ctx {
   int32_t* d_mt_ptr = nullptr;       // [n_mt + 1]
   int32_t* d_mt_h = nullptr;         // hanging node per entry
   double* d_mt_w = nullptr;          // weight per entry
-  // filter neighbour lists (octree), rebuilt when rmin changes
-  double filt_rmin = -1.0;
-  int n_sten = 0;
-  int32_t* d_nb_ptr = nullptr;
-  int32_t* d_nb_idx = nullptr;
-  double* d_nb_w = nullptr;
+  // octree filter (built at upload): element descriptors (anchor, edge) and
+  // the finest-lattice cell map (leaf per cell, bit 31 on its anchor cell)
+  int filt_hmax = 1;
+  int32_t* d_edesc = nullptr;   // [4 n_elems]
+  int32_t* d_cmap = nullptr;    // [nx ny nz]
 
   // device: density dependent
   double* d_coef = nullptr;   // c_e
@@ -199,6 +198,17 @@ struct amrto_ctx {
   size_t gram_cap = 0;
   int coarse_exact_it = 0;      // iteration at which ct, cz were last formed from r
   bool coarse_fresh = false;    // ct, cz were just formed from r (coarse_init)
+  // Krylov recycling (recycle.hip): recorded preconditioned residuals of one
+  // FP64 solve (rec_m x 3n), their coefficients (r.z at 2j, p.q at 2j + 1,
+  // the count of stored vectors at 2 REC_MMAX + 1), combination coefficients,
+  // and the Rayleigh-Ritz workspace (A~ s_j for up to 16 vectors, partials)
+  int rec_m = 0;
+  bool rec_active = false;      // the running FP64 solve records
+  double* d_rec_store = nullptr;
+  double* d_rec_coef = nullptr;
+  double* d_rec_C = nullptr;
+  double* d_rr_aw = nullptr;
+  double* d_rr_part = nullptr;
   // mesh <-> grid transfers (net.hip)
   int grid_cell = 0;
   int32_t* d_node_xyz = nullptr;
@@ -220,6 +230,11 @@ namespace amrto {
 int launch_apply(amrto_ctx* ctx, const void* x, void* y, int prec);
 int launch_diag(amrto_ctx* ctx);
 int build_chunks(amrto_ctx* ctx, const amrto_mesh* m);
+// recycle.hip
+int recycle_begin(amrto_ctx* ctx);
+int recycle_store(amrto_ctx* ctx, const double* z, int j);
+// topopt.hip
+int build_cell_map(amrto_ctx* ctx);
 // vec.hip
 int launch_set_density(amrto_ctx* ctx, const double* rho);
 int launch_project_rhs(amrto_ctx* ctx, const double* f, double* b);

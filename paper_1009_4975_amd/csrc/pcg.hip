@@ -703,7 +703,8 @@ static int cz_threads(const amrto_ctx* ctx) {
 // node blocks; r.z = r^T M1 r + ct^T cz), in the recurrence form of
 // k_cg_update_rec unless built with AMRTO_COARSE_REC=0.
 static bool coarse_fused(const amrto_ctx* ctx) {
-  return ctx->coarse_k > 0 && !ctx->uniform && ctx->coarse_affine_only;
+  // a recorded solve keeps z = M^-1 r in memory: the direct form
+  return ctx->coarse_k > 0 && !ctx->uniform && ctx->coarse_affine_only && !ctx->rec_active;
 }
 
 // with a coarse space: cz = E^-1 Z^T r for the initial residual and either
@@ -768,11 +769,81 @@ static int read_scalars(amrto_ctx* ctx) {
   return AMRTO_OK;
 }
 
+// The two halves of CG iteration `it`: the fused operator pass (p = z + beta
+// p_old, q = A~ p, p.q partials; with the fused coarse space z = M1 r + Z cz
+// and, in the recurrence form, the Z^T q and E^-1 Z^T q partials) ...
+template <typename VT>
+static int enqueue_op_pass(amrto_ctx* ctx, const Vecs<VT>& v, int prec, double tol2, int it, bool block3) {
+  const bool fused = coarse_fused(ctx);
+  const bool rec = fused && AMRTO_COARSE_REC && ctx->d_cqpart;
+  VT* pnew = (it & 1) ? v.p1 : v.p0;
+  VT* pold = (it & 1) ? v.p0 : v.p1;
+  CgArgs cg{ctx->d_scal, ctx->d_part, ctx->d_partpq, 0, it, tol2, (fused && !rec) ? 1 : 0};
+  const VT* binv = nullptr;
+  if (block3) {
+    if constexpr (std::is_same<VT, double>::value) binv = ctx->d_binv;
+    else binv = ctx->d_binv_f;
+  }
+  return fused ? apply_fused_coarse(ctx, v.r, block3 ? (const void*)binv : (const void*)v.dinv, pold, pnew, v.q, prec,
+                                    cg, block3, rec ? ctx->d_cqpart : nullptr)
+               : apply_fused(ctx, v.z, pold, pnew, v.q, prec, cg);
+}
+
+// ... and the update side (alpha, x, r, z = M^-1 r, the r.z and r.r partials,
+// and the coarse-space launches that follow it).
+template <typename VT>
+static int enqueue_update(amrto_ctx* ctx, const Vecs<VT>& v, VT* x, int it, bool block3) {
+  const long n3 = 3L * ctx->n_nodes;
+  const bool fused = coarse_fused(ctx);
+  const bool rec = fused && AMRTO_COARSE_REC && ctx->d_cqpart;
+  VT* pnew = (it & 1) ? v.p1 : v.p0;
+  const VT* binv = nullptr;
+  if (block3) {
+    if constexpr (std::is_same<VT, double>::value) binv = ctx->d_binv;
+    else binv = ctx->d_binv_f;
+  }
+  if (rec) {
+    const int nb = apply_blocks(ctx);
+    if (block3)
+      hipLaunchKernelGGL((k_cg_update_rec<VT, true>), dim3(RED_BLOCKS + ctx->coarse_k), dim3(256), 0, ctx->stream,
+                         x, v.r, pnew, v.q, binv, (long)ctx->n_nodes, ctx->d_partpq, ctx->n_partpq, ctx->d_scal,
+                         it, (const double*)ctx->d_cqpart, nb, ctx->coarse_k, ctx->d_ct, ctx->d_cz,
+                         ctx->d_part);
+    else
+      hipLaunchKernelGGL((k_cg_update_rec<VT, false>), dim3(RED_BLOCKS + ctx->coarse_k), dim3(256), 0,
+                         ctx->stream, x, v.r, pnew, v.q, (const VT*)v.dinv, (long)ctx->n_nodes, ctx->d_partpq,
+                         ctx->n_partpq, ctx->d_scal, it, (const double*)ctx->d_cqpart, nb, ctx->coarse_k,
+                         ctx->d_ct, ctx->d_cz, ctx->d_part);
+  } else if (ctx->coarse_k > 0) {
+    if (block3)  // coarse_fused holds (checked in amrto_pcg)
+      hipLaunchKernelGGL(k_cg_update_coarse_b3<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew,
+                         v.q, binv, (long)ctx->n_nodes, ctx->d_partpq, ctx->n_partpq, ctx->d_scal, it,
+                         coarse_args(ctx), ctx->d_cpart, ctx->d_part);
+    else
+      hipLaunchKernelGGL(k_cg_update_coarse<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew, v.q,
+                         v.dinv, n3, ctx->d_partpq, ctx->n_partpq, ctx->d_scal, it, coarse_args(ctx),
+                         ctx->d_cpart, ctx->d_part);
+    hipLaunchKernelGGL(k_coarse_sum, dim3(ctx->coarse_k), dim3(256), 0, ctx->stream, ctx->d_cpart,
+                       ctx->coarse_k, RED_BLOCKS, ctx->d_ct, ctx->d_scal + S_DONE);
+    hipLaunchKernelGGL(k_coarse_cz, dim3(1), dim3(cz_threads(ctx)), 0, ctx->stream, (const double*)ctx->d_ct, ctx->coarse_k,
+                       (const double*)ctx->d_cinv, ctx->d_cz, ctx->d_scal + S_CTZ, ctx->d_scal + S_DONE);
+    if (!fused)
+      hipLaunchKernelGGL(k_coarse_z<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, v.r, v.z, v.dinv, n3,
+                         ctx->d_cz, coarse_args(ctx), ctx->d_part, ctx->d_scal + S_DONE);
+  } else if (block3) {
+    const int rc = block3_update<VT>(ctx, x, v.r, pnew, v.q, v.z, it);
+    if (rc) return rc;
+  } else {
+    hipLaunchKernelGGL(k_cg_update<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew, v.q, v.dinv,
+                       v.z, n3, ctx->d_partpq, ctx->n_partpq, ctx->d_scal, it, ctx->d_part);
+  }
+  return AMRTO_OK;
+}
+
 // enqueue CG iterations [it0, it0 + count) on the current r, z (and p from it0 - 1)
 template <typename VT>
 static int enqueue_iters(amrto_ctx* ctx, const Vecs<VT>& v, VT* x, int prec, double tol2, int it0, int count,
                          bool block3 = false) {
-  const long n3 = 3L * ctx->n_nodes;
   const bool fused = coarse_fused(ctx);
   const bool rec = fused && AMRTO_COARSE_REC && ctx->d_cqpart;
   if (rec) {
@@ -787,54 +858,91 @@ static int enqueue_iters(amrto_ctx* ctx, const Vecs<VT>& v, VT* x, int prec, dou
     }
   }
   for (int it = it0; it < it0 + count; ++it) {
-    VT* pnew = (it & 1) ? v.p1 : v.p0;
-    VT* pold = (it & 1) ? v.p0 : v.p1;
-    CgArgs cg{ctx->d_scal, ctx->d_part, ctx->d_partpq, 0, it, tol2, (fused && !rec) ? 1 : 0};
-    const VT* binv = nullptr;
-    if (block3) {
-      if constexpr (std::is_same<VT, double>::value) binv = ctx->d_binv;
-      else binv = ctx->d_binv_f;
+    int rc = enqueue_op_pass<VT>(ctx, v, prec, tol2, it, block3);
+    if (!rc) rc = enqueue_update<VT>(ctx, v, x, it, block3);
+    if constexpr (std::is_same<VT, double>::value) {
+      if (!rc && ctx->rec_active) rc = recycle_store(ctx, v.z, it + 1);
     }
-    int rc = fused ? apply_fused_coarse(ctx, v.r, block3 ? (const void*)binv : (const void*)v.dinv, pold, pnew, v.q,
-                                        prec, cg, block3, rec ? ctx->d_cqpart : nullptr)
-                   : apply_fused(ctx, v.z, pold, pnew, v.q, prec, cg);
     if (rc) return rc;
-    if (rec) {
-      const int nb = apply_blocks(ctx);
-      if (block3)
-        hipLaunchKernelGGL((k_cg_update_rec<VT, true>), dim3(RED_BLOCKS + ctx->coarse_k), dim3(256), 0, ctx->stream,
-                           x, v.r, pnew, v.q, binv, (long)ctx->n_nodes, ctx->d_partpq, ctx->n_partpq, ctx->d_scal,
-                           it, (const double*)ctx->d_cqpart, nb, ctx->coarse_k, ctx->d_ct, ctx->d_cz,
-                           ctx->d_part);
-      else
-        hipLaunchKernelGGL((k_cg_update_rec<VT, false>), dim3(RED_BLOCKS + ctx->coarse_k), dim3(256), 0,
-                           ctx->stream, x, v.r, pnew, v.q, (const VT*)v.dinv, (long)ctx->n_nodes, ctx->d_partpq,
-                           ctx->n_partpq, ctx->d_scal, it, (const double*)ctx->d_cqpart, nb, ctx->coarse_k,
-                           ctx->d_ct, ctx->d_cz, ctx->d_part);
-    } else if (ctx->coarse_k > 0) {
-      if (block3)  // coarse_fused holds (checked in amrto_pcg)
-        hipLaunchKernelGGL(k_cg_update_coarse_b3<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew,
-                           v.q, binv, (long)ctx->n_nodes, ctx->d_partpq, ctx->n_partpq, ctx->d_scal, it,
-                           coarse_args(ctx), ctx->d_cpart, ctx->d_part);
-      else
-        hipLaunchKernelGGL(k_cg_update_coarse<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew, v.q,
-                           v.dinv, n3, ctx->d_partpq, ctx->n_partpq, ctx->d_scal, it, coarse_args(ctx),
-                           ctx->d_cpart, ctx->d_part);
-      hipLaunchKernelGGL(k_coarse_sum, dim3(ctx->coarse_k), dim3(256), 0, ctx->stream, ctx->d_cpart,
-                         ctx->coarse_k, RED_BLOCKS, ctx->d_ct, ctx->d_scal + S_DONE);
-      hipLaunchKernelGGL(k_coarse_cz, dim3(1), dim3(cz_threads(ctx)), 0, ctx->stream, (const double*)ctx->d_ct, ctx->coarse_k,
-                         (const double*)ctx->d_cinv, ctx->d_cz, ctx->d_scal + S_CTZ, ctx->d_scal + S_DONE);
-      if (!fused)
-        hipLaunchKernelGGL(k_coarse_z<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, v.r, v.z, v.dinv, n3,
-                           ctx->d_cz, coarse_args(ctx), ctx->d_part, ctx->d_scal + S_DONE);
-    } else if (block3) {
-      rc = block3_update<VT>(ctx, x, v.r, pnew, v.q, v.z, it);
+  }
+  AMRTO_HIP(hipGetLastError());
+  return AMRTO_OK;
+}
+
+static int true_residual(amrto_ctx* ctx, const double* b, const double* x, double* rr, double* bb);
+
+// Time the two halves of one CG iteration of a solver variant: the solve is
+// started as amrto_pcg starts it (from x, with a stopping target of zero so
+// the recurrence cannot stop) and run for two iterations; then the operator
+// pass of iteration 2 is launched `reps` times back to back (it reads the
+// same inputs each time and rewrites the same outputs), then its update side
+// `reps` times, each group between two events on the context stream.
+template <typename VT>
+static int pass_times(amrto_ctx* ctx, const double* b, double* x, int prec, bool block3, int reps, float* op_ms,
+                      float* up_ms) {
+  const long n3 = 3L * ctx->n_nodes;
+  const int g1 = (int)((n3 + 255) / 256);
+  Vecs<VT> v{};
+  VT* xi = nullptr;
+  hipLaunchKernelGGL(k_mask<double>, dim3(g1), dim3(256), 0, ctx->stream, x, ctx->d_fix, n3);
+  if (ctx->n_hang)
+    hipLaunchKernelGGL(k_mask_hanging<double>, dim3((3L * ctx->n_hang + 255) / 256), dim3(256), 0, ctx->stream, x,
+                       ctx->d_hang_node, ctx->n_hang);
+  if (block3) {
+    const int rc = block3_setup(ctx);
+    if (rc) return rc;
+  }
+  if constexpr (std::is_same<VT, double>::value) {
+    v = vecs64(ctx);
+    xi = x;
+    int rc = apply_stop(ctx, x, v.q, AMRTO_FP64, nullptr);
+    if (rc) return rc;
+    if (block3) {
+      rc = block3_init<double, double>(ctx, b, v.q, v.r, v.z);
       if (rc) return rc;
     } else {
-      hipLaunchKernelGGL(k_cg_update<VT>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, x, v.r, pnew, v.q, v.dinv,
-                         v.z, n3, ctx->d_partpq, ctx->n_partpq, ctx->d_scal, it, ctx->d_part);
+      hipLaunchKernelGGL((k_init<double, double>), dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, b, v.q, v.r, v.z,
+                         v.dinv, n3, ctx->d_part);
+    }
+  } else {
+    v = vecs32(ctx);
+    xi = ctx->f_x;
+    hipLaunchKernelGGL(k_fill<float>, dim3(g1), dim3(256), 0, ctx->stream, ctx->f_x, n3);
+    double rr, bb;
+    int rc = true_residual(ctx, b, x, &rr, &bb);
+    if (rc) return rc;
+    if (block3) {
+      rc = block3_init<float, double>(ctx, ctx->d_r, (const double*)nullptr, v.r, v.z);
+      if (rc) return rc;
+    } else {
+      hipLaunchKernelGGL((k_init<float, double>), dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, ctx->d_r,
+                         (const double*)nullptr, v.r, v.z, v.dinv, n3, ctx->d_part);
     }
   }
+  coarse_init<VT>(ctx, v);
+  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(256), 0, ctx->stream, ctx->d_part, ctx->d_scal, 0.0, 0,
+                     coarse_fused(ctx) ? 1 : 0);
+  int rc = enqueue_iters<VT>(ctx, v, xi, prec, 0.0, 0, 2, block3);
+  if (rc) return rc;
+  hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+  for (auto& ev : e) AMRTO_HIP(hipEventCreate(&ev));
+  struct Ev {
+    hipEvent_t* e;
+    ~Ev() { for (int i = 0; i < 3; ++i) if (e[i]) (void)hipEventDestroy(e[i]); }
+  } guard{e};
+  AMRTO_HIP(hipEventRecord(e[0], ctx->stream));
+  for (int i = 0; i < reps && !rc; ++i) rc = enqueue_op_pass<VT>(ctx, v, prec, 0.0, 2, block3);
+  AMRTO_HIP(hipEventRecord(e[1], ctx->stream));
+  for (int i = 0; i < reps && !rc; ++i) rc = enqueue_update<VT>(ctx, v, xi, 2, block3);
+  AMRTO_HIP(hipEventRecord(e[2], ctx->stream));
+  if (rc) return rc;
+  AMRTO_HIP(hipGetLastError());
+  AMRTO_HIP(hipEventSynchronize(e[2]));
+  AMRTO_HIP(hipEventElapsedTime(op_ms, e[0], e[1]));
+  AMRTO_HIP(hipEventElapsedTime(up_ms, e[1], e[2]));
+  // nothing of this run is a result: the finished flag stops any later
+  // kernel of this state, and the next solve starts afresh
+  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, ctx->stream, ctx->d_scal, (int)S_DONE, 2.0);
   AMRTO_HIP(hipGetLastError());
   return AMRTO_OK;
 }
@@ -883,9 +991,14 @@ static int cg_fp64_run(amrto_ctx* ctx, const double* b, double* x, double rtol, 
   hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(256), 0, ctx->stream, ctx->d_part, ctx->d_scal, tol2, 0,
                      coarse_fused(ctx) ? 1 : 0);
   AMRTO_HIP(hipGetLastError());
+  if (ctx->rec_active) {
+    rc = recycle_begin(ctx);
+    if (!rc) rc = recycle_store(ctx, v.z, 0);
+    if (rc) return rc;
+  }
   // one reduction per iteration where the recurrences allow it (octree mesh,
   // Jacobi preconditioner)
-  const bool one = one_reduction && !block3 && ctx->coarse_k <= 0 && cg1_available(ctx);
+  const bool one = one_reduction && !block3 && ctx->coarse_k <= 0 && !ctx->rec_active && cg1_available(ctx);
   if (one) {
     rc = cg1_init(ctx);
     if (rc) return rc;
@@ -944,6 +1057,7 @@ static int cg_fp64(amrto_ctx* ctx, const double* b, double* x, double rtol, int 
   while (true) {
     int it = 0;
     status = cg_fp64_run(ctx, b, x, rtol, max_it - total, check_every, one_reduction, block3, &it);
+    ctx->rec_active = false;  // a restart starts another Krylov space: only the first run is recorded
     total += it;
     if (status < 0 && status != AMRTO_EBREAKDOWN) return status;
     double rr, bb;
@@ -1100,6 +1214,7 @@ void amrto_solve_opts_default(amrto_solve_opts* o) {
   o->use_coarse = 1;
   o->fallback_fp64 = 1;
   o->single_reduction = 0;
+  o->record = 0;
 }
 
 int amrto_pcg(amrto_ctx* ctx, const double* b, double* u, const amrto_solve_opts* opts_in,
@@ -1121,7 +1236,18 @@ int amrto_pcg(amrto_ctx* ctx, const double* b, double* u, const amrto_solve_opts
   if (block3 && o.use_coarse && ctx->coarse_k > 0 && !coarse_fused(ctx))
     return ctx->fail(AMRTO_EINVAL,
                      "amrto_pcg: block-Jacobi with a coarse space needs an octree mesh and the affine space");
+  if (o.record) {
+    if (ctx->rec_m <= 0) return ctx->fail(AMRTO_ESTATE, "amrto_pcg: record needs amrto_recycle_setup");
+    if (o.inner_prec != AMRTO_FP64) return ctx->fail(AMRTO_EINVAL, "amrto_pcg: record needs an FP64 solve");
+    if (block3 && o.use_coarse && ctx->coarse_k > 0)
+      return ctx->fail(AMRTO_EINVAL, "amrto_pcg: record with block-Jacobi needs no coarse space");
+  }
   AMRTO_HIP(hipSetDevice(ctx->device));
+  struct RecOff {
+    amrto_ctx* c;
+    ~RecOff() { c->rec_active = false; }
+  } rec_guard{ctx};
+  ctx->rec_active = o.record != 0;
   // the solve loops read the coarse space from the context
   struct CoarseOff {
     amrto_ctx* c; int k;
@@ -1178,6 +1304,37 @@ int amrto_pcg(amrto_ctx* ctx, const double* b, double* u, const amrto_solve_opts
     ctx->err = msg;
   }
   return status;
+}
+
+int amrto_pcg_pass_times(amrto_ctx* ctx, const double* b, double* u, const amrto_solve_opts* opts_in, int32_t reps,
+                         double* op_us, double* update_us) {
+  if (!ctx) return AMRTO_EINVAL;
+  if (!ctx->has_density) return ctx->fail(AMRTO_ESTATE, "amrto_pcg_pass_times: density not set");
+  if (!b || !u || b == u || !op_us || !update_us || reps < 1 || reps > 100000)
+    return ctx->fail(AMRTO_EINVAL, "amrto_pcg_pass_times: bad arguments");
+  amrto_solve_opts o;
+  amrto_solve_opts_default(&o);
+  if (opts_in) o = *opts_in;
+  if (o.inner_prec != AMRTO_FP64 && o.inner_prec != AMRTO_FP32 && o.inner_prec != AMRTO_BF16)
+    return ctx->fail(AMRTO_EINVAL, "amrto_pcg_pass_times: unknown inner precision");
+  if (o.precond != AMRTO_PRECOND_JACOBI && o.precond != AMRTO_PRECOND_BLOCK3)
+    return ctx->fail(AMRTO_EINVAL, "amrto_pcg_pass_times: unknown preconditioner");
+  const bool block3 = o.precond == AMRTO_PRECOND_BLOCK3;
+  if (block3 && o.use_coarse && ctx->coarse_k > 0 && !coarse_fused(ctx))
+    return ctx->fail(AMRTO_EINVAL, "amrto_pcg_pass_times: block-Jacobi with this coarse space is not a solver variant");
+  AMRTO_HIP(hipSetDevice(ctx->device));
+  struct CoarseOff {
+    amrto_ctx* c; int k;
+    ~CoarseOff() { c->coarse_k = k; }
+  } coarse_guard{ctx, ctx->coarse_k};
+  if (!o.use_coarse) ctx->coarse_k = 0;
+  float op = 0.f, up = 0.f;
+  const int rc = o.inner_prec == AMRTO_FP64 ? pass_times<double>(ctx, b, u, AMRTO_FP64, block3, reps, &op, &up)
+                                            : pass_times<float>(ctx, b, u, o.inner_prec, block3, reps, &op, &up);
+  if (rc) return rc;
+  *op_us = 1e3 * (double)op / reps;
+  *update_us = 1e3 * (double)up / reps;
+  return AMRTO_OK;
 }
 
 }  // extern "C"

@@ -6,7 +6,6 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
-#include <unordered_map>
 
 #include "internal.h"
 
@@ -100,39 +99,103 @@ __global__ __launch_bounds__(256) void k_sensitivity(
 }
 
 // ------------------------------------------------------------------ filters
-// weights W_ed = H_de V_d; SENSITIVITY: sum W rho_d in_d / (max(rho_e, 1e-3) sum W)
-//                          DENSITY:     sum W in_d / sum W
+// weights W_ed = H_de V_d with H_de = max(rmin - |x_d - x_e|, 0) (Eq. (4));
+//   SENSITIVITY: sum W rho_d in_d / (max(rho_e, 1e-3) sum W)   (Eq. (5))
+//   DENSITY:     sum W in_d / sum W
+// Neither kernel reads a neighbour table: the uniform one walks the box of
+// offsets |d_a| <= R with H from a per-block table indexed by |d|^2, the
+// octree one walks the finest-lattice cells around the element and takes each
+// leaf at its anchor cell.  Nothing is built or allocated per call, and the
+// summation order is fixed (z, y, x of the offsets or anchors).
+constexpr int FILT_RMAX = 16;                       // largest rmin accepted
+constexpr int FILT_D2MAX = 3 * FILT_RMAX * FILT_RMAX;  // largest |d|^2 in the box
+
 __global__ __launch_bounds__(256) void k_filter_uniform(
-    const double* __restrict__ in, const double* __restrict__ rho, double* __restrict__ out,
-    const int4* __restrict__ sten, const double* __restrict__ sw, int n_sten, int nx, int ny, int nz, int mode) {
+    const double* __restrict__ in, const double* __restrict__ rho, double* __restrict__ out, int nx, int ny, int nz,
+    double rmin, int R, int mode) {
+  __shared__ double s_h[FILT_D2MAX + 1];
+  const int d2max = 3 * R * R;
+  for (int s = threadIdx.x; s <= d2max; s += blockDim.x) s_h[s] = fmax(rmin - sqrt((double)s), 0.0);
+  __syncthreads();
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (e >= (long)nx * ny * nz) return;
   const int ex = e % nx, ey = (e / nx) % ny, ez = e / ((long)nx * ny);
   double num = 0.0, den = 0.0;
-  for (int s = 0; s < n_sten; ++s) {
-    const int4 st = sten[s];
-    const int dx = ex + st.x, dy = ey + st.y, dz = ez + st.z;
-    if (dx < 0 || dx >= nx || dy < 0 || dy >= ny || dz < 0 || dz >= nz) continue;
-    const long d = dx + (long)nx * (dy + (long)ny * dz);
-    const double w = sw[s];
-    num += w * (mode == AMRTO_FILTER_SENSITIVITY ? rho[d] * in[d] : in[d]);
-    den += w;
+  for (int dz = -R; dz <= R; ++dz) {
+    const int z = ez + dz;
+    if (z < 0 || z >= nz) continue;
+    for (int dy = -R; dy <= R; ++dy) {
+      const int y = ey + dy;
+      if (y < 0 || y >= ny) continue;
+      for (int dx = -R; dx <= R; ++dx) {
+        const int x = ex + dx;
+        if (x < 0 || x >= nx) continue;
+        const double w = s_h[dx * dx + dy * dy + dz * dz];
+        if (w <= 0.0) continue;
+        const long d = x + (long)nx * (y + (long)ny * z);
+        num += w * (mode == AMRTO_FILTER_SENSITIVITY ? rho[d] * in[d] : in[d]);
+        den += w;
+      }
+    }
   }
   out[e] = mode == AMRTO_FILTER_SENSITIVITY ? num / (fmax(rho[e], 1e-3) * den) : num / den;
 }
 
-__global__ __launch_bounds__(256) void k_filter_csr(
+// Octree: desc[e] = (anchor x, y, z, edge h) on the finest lattice; cmap[c] =
+// the leaf covering lattice cell c, with bit 31 set on the leaf's anchor
+// (lowest) cell.  A neighbour d satisfies |2 a_d + h_d - (2 a_e + h_e)| <
+// 2 rmin per axis with 1 <= h_d <= hmax, which bounds its anchor; every leaf
+// in that box is counted once, at its anchor cell.
+__global__ __launch_bounds__(256) void k_filter_octree(
     const double* __restrict__ in, const double* __restrict__ rho, double* __restrict__ out,
-    const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx, const double* __restrict__ w, int n, int mode) {
+    const int4* __restrict__ desc, const int32_t* __restrict__ cmap, int n, int nx, int ny, int nz, int hmax,
+    double rmin, int mode) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
+  const int4 de = desc[e];
+  const int cx = 2 * de.x + de.w, cy = 2 * de.y + de.w, cz = 2 * de.z + de.w;  // doubled centre
+  const double r2 = 2.0 * rmin;
+  auto lo = [&](int c) { return max(0, (int)floor(0.5 * ((double)c - r2 - (double)hmax))); };
+  auto hi = [&](int c, int nmax) { return min(nmax - 1, (int)ceil(0.5 * ((double)c + r2))); };
+  const int x0 = lo(cx), x1 = hi(cx, nx), y0 = lo(cy), y1 = hi(cy, ny), z0 = lo(cz), z1 = hi(cz, nz);
+  const double lim2 = r2 * r2;
   double num = 0.0, den = 0.0;
-  for (int k = ptr[e]; k < ptr[e + 1]; ++k) {
-    const int d = idx[k];
-    num += w[k] * (mode == AMRTO_FILTER_SENSITIVITY ? rho[d] * in[d] : in[d]);
-    den += w[k];
-  }
+  for (int z = z0; z <= z1; ++z)
+    for (int y = y0; y <= y1; ++y) {
+      const long row = (long)nx * (y + (long)ny * z);
+      for (int x = x0; x <= x1; ++x) {
+        const int v = cmap[row + x];
+        if (v >= 0) continue;  // not an anchor cell
+        const int d = v & 0x7fffffff;
+        const int4 dd = desc[d];
+        const double ddx = (double)(2 * dd.x + dd.w - cx), ddy = (double)(2 * dd.y + dd.w - cy),
+                     ddz = (double)(2 * dd.z + dd.w - cz);
+        const double D2 = ddx * ddx + ddy * ddy + ddz * ddz;  // (2 |x_d - x_e|)^2
+        if (D2 >= lim2) continue;
+        const double H = rmin - 0.5 * sqrt(D2);
+        if (H <= 0.0) continue;
+        const double w = H * (double)dd.w * dd.w * dd.w;
+        num += w * (mode == AMRTO_FILTER_SENSITIVITY ? rho[d] * in[d] : in[d]);
+        den += w;
+      }
+    }
   out[e] = mode == AMRTO_FILTER_SENSITIVITY ? num / (fmax(rho[e], 1e-3) * den) : num / den;
+}
+
+// cmap from the element descriptors: leaf e writes e into its h^3 cells and
+// e | 2^31 into its anchor cell (leaves tile the box, so every cell is
+// written exactly once).
+__global__ __launch_bounds__(256) void k_cell_map(const int4* __restrict__ desc, int n, int nx, int ny,
+                                                 int32_t* __restrict__ cmap) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    const int4 d = desc[e];
+    for (int k = 0; k < d.w; ++k)
+      for (int j = 0; j < d.w; ++j)
+        for (int i = 0; i < d.w; ++i) {
+          const long c = (d.x + i) + (long)nx * ((d.y + j) + (long)ny * (d.z + k));
+          cmap[c] = (i | j | k) ? e : (int32_t)((uint32_t)e | 0x80000000u);
+        }
+  }
 }
 
 // ------------------------------------------------------------------ OC
@@ -244,66 +307,119 @@ __global__ void k_init_bracket(double* ws, double llo, double lhi) {
   ws[1] = lhi;
 }
 
+// ------------------------------------------------------------------ design difference
+// Eq. (10) on the finest lattice: each cell takes the density of the leaf
+// covering it (uniform brick: the element of the same index); per block the
+// sums of |rho_a - rho_b| and rho_a over a fixed cell range, then one block
+// adds the partials in order.
+__global__ __launch_bounds__(256) void k_design_diff(const double* __restrict__ ra, const int32_t* __restrict__ cmap_a,
+                                                     const double* __restrict__ rb, const int32_t* __restrict__ cmap_b,
+                                                     long cells, double* __restrict__ part) {
+  __shared__ double sh[16];
+  double num = 0.0, den = 0.0;
+  for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < cells; c += (long)gridDim.x * blockDim.x) {
+    const long ea = cmap_a ? (long)(cmap_a[c] & 0x7fffffff) : c;
+    const long eb = cmap_b ? (long)(cmap_b[c] & 0x7fffffff) : c;
+    const double a = ra[ea];
+    num += fabs(a - rb[eb]);
+    den += a;
+  }
+  num = block_sum_t(num, sh);
+  den = block_sum_t(den, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = num;
+    part[gridDim.x + blockIdx.x] = den;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_design_diff_sum(const double* __restrict__ part, int nb,
+                                                         double* __restrict__ out) {
+  __shared__ double sh[16];
+  double num = 0.0, den = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    num += part[i];
+    den += part[nb + i];
+  }
+  num = block_sum_t(num, sh);
+  den = block_sum_t(den, sh);
+  if (threadIdx.x == 0) {
+    out[0] = num;
+    out[1] = den;
+  }
+}
+
 // ------------------------------------------------------------------ host
-// Neighbour lists for an octree mesh: all element pairs with centre distance
-// below rmin (a hash grid of cell size ceil(rmin) over element centres; a
-// coarse element is inserted once at its centre, and the search radius is
-// widened by half the largest element edge in each direction).
-static int build_neighbours(amrto_ctx* ctx, double rmin) {
+// Element descriptors and the lattice cell map of an octree mesh, built at
+// mesh upload (the filter reads them; no per-call host work).
+int build_cell_map(amrto_ctx* ctx) {
   const int ne = ctx->n_elems;
-  std::vector<double> cx(ne), cy(ne), cz(ne), vol(ne);
+  const long cells = (long)ctx->nx * ctx->ny * ctx->nz;
+  if (cells > (1L << 30))
+    return ctx->fail(AMRTO_EINVAL, "amrto_upload_mesh: finest lattice above 2^30 cells (filter cell map)");
+  std::vector<int32_t> desc(4L * ne);
+  int hmax = 1;
   for (int e = 0; e < ne; ++e) {
     const int n0 = ctx->h_elem_nodes[8L * e];
     const int h = 1 << (ctx->max_level - ctx->h_level[e]);
-    cx[e] = ctx->h_node_xyz[3L * n0] + 0.5 * h;
-    cy[e] = ctx->h_node_xyz[3L * n0 + 1] + 0.5 * h;
-    cz[e] = ctx->h_node_xyz[3L * n0 + 2] + 0.5 * h;
-    vol[e] = (double)h * h * h;
+    for (int a = 0; a < 3; ++a) desc[4L * e + a] = ctx->h_node_xyz[3L * n0 + a];
+    desc[4L * e + 3] = h;
+    hmax = std::max(hmax, h);
   }
-  const double cell = std::max(1.0, std::ceil(rmin));
-  auto key = [](long a, long b, long c) { return (a * 73856093L) ^ (b * 19349663L) ^ (c * 83492791L); };
-  std::unordered_multimap<long, int> grid;
-  grid.reserve(ne * 2);
-  for (int e = 0; e < ne; ++e)
-    grid.emplace(key((long)std::floor(cx[e] / cell), (long)std::floor(cy[e] / cell), (long)std::floor(cz[e] / cell)), e);
-  std::vector<int> ptr(ne + 1, 0), idx;
-  std::vector<double> w;
-  const int reach = (int)std::ceil(rmin / cell);
+  ctx->filt_hmax = hmax;
+  AMRTO_HIP(hipMalloc((void**)&ctx->d_edesc, std::max<size_t>(1, desc.size()) * sizeof(int32_t)));
+  AMRTO_HIP(hipMalloc((void**)&ctx->d_cmap, std::max<long>(1, cells) * sizeof(int32_t)));
+  AMRTO_HIP(hipMemcpyAsync(ctx->d_edesc, desc.data(), desc.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           ctx->stream));
+  hipLaunchKernelGGL(k_cell_map, dim3(grid_for(ne, 256, 4096)), dim3(256), 0, ctx->stream, (const int4*)ctx->d_edesc,
+                     ne, ctx->nx, ctx->ny, ctx->d_cmap);
+  AMRTO_HIP(hipGetLastError());
+  AMRTO_HIP(hipStreamSynchronize(ctx->stream));  // desc is a host temporary
+  return AMRTO_OK;
+}
+
+// The OC step on workspace ws (OC_WS doubles on the device); host results
+// come back through hbuf (4 doubles).
+static int oc_update_ws(amrto_ctx* ctx, double* ws, double* hbuf, const char* name, const double* rho,
+                        const double* dc, double volfrac, double move, double eta, double rho_min, double* rho_new,
+                        double* change_host, double* lam_host) {
+  if (!ctx->has_mesh) return ctx->fail(AMRTO_ESTATE, std::string(name) + ": no mesh");
+  if (!rho || !dc || !rho_new || rho_new == rho) return ctx->fail(AMRTO_EINVAL, std::string(name) + ": bad buffers");
+  if (!(volfrac > 0.0 && volfrac <= 1.0) || !(move > 0.0) || !(eta > 0.0) || !(rho_min >= 0.0 && rho_min < 1.0))
+    return ctx->fail(AMRTO_EINVAL, std::string(name) + ": bad parameters");
+  AMRTO_HIP(hipSetDevice(ctx->device));
+  const int ne = ctx->n_elems;
+  double vtot = 0.0;
   for (int e = 0; e < ne; ++e) {
-    const long gx = (long)std::floor(cx[e] / cell), gy = (long)std::floor(cy[e] / cell), gz = (long)std::floor(cz[e] / cell);
-    std::vector<std::pair<int, double>> nb;
-    for (long dz = -reach; dz <= reach; ++dz)
-      for (long dy = -reach; dy <= reach; ++dy)
-        for (long dx = -reach; dx <= reach; ++dx) {
-          auto range = grid.equal_range(key(gx + dx, gy + dy, gz + dz));
-          for (auto it = range.first; it != range.second; ++it) {
-            const int d = it->second;
-            const double ddx = cx[d] - cx[e], ddy = cy[d] - cy[e], ddz = cz[d] - cz[e];
-            if (std::fabs(ddx) > rmin || std::fabs(ddy) > rmin || std::fabs(ddz) > rmin) continue;
-            const double H = rmin - std::sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
-            if (H > 0.0) nb.emplace_back(d, H * vol[d]);
-          }
-        }
-    std::sort(nb.begin(), nb.end());
-    nb.erase(std::unique(nb.begin(), nb.end(), [](const std::pair<int, double>& a, const std::pair<int, double>& b) {
-               return a.first == b.first;
-             }), nb.end());
-    for (auto& pr : nb) { idx.push_back(pr.first); w.push_back(pr.second); }
-    ptr[e + 1] = (int)idx.size();
+    const double h = (double)(1 << (ctx->max_level - ctx->h_level[e]));
+    vtot += h * h * h;
   }
-  auto up = [&](auto*& dst, const auto& v) -> hipError_t {
-    using T = typename std::remove_reference<decltype(v)>::type::value_type;
-    if (dst) (void)hipFree(dst);
-    dst = nullptr;
-    hipError_t er = hipMalloc((void**)&dst, std::max<size_t>(1, v.size()) * sizeof(T));
-    if (er != hipSuccess) return er;
-    if (!v.empty()) er = hipMemcpy(dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
-    return er;
-  };
-  AMRTO_HIP(up(ctx->d_nb_ptr, ptr));
-  AMRTO_HIP(up(ctx->d_nb_idx, idx));
-  AMRTO_HIP(up(ctx->d_nb_w, w));
-  ctx->filt_rmin = rmin;
+  const double v0 = volfrac * vtot;
+  const int nblk = std::min(OC_BLOCKS, (ne + OC_TILE - 1) / OC_TILE);
+  const int g = std::min(256, (ne + 255) / 256);
+  // workspace layout: bracket [0, 2), partial volumes [2, 2 + OC_K nblk),
+  // candidate volumes [OC_VOL, OC_VOL + OC_K), per-block changes [2, 2 + g)
+  if (OC_VOL + OC_K > OC_WS || 2 + (long)OC_K * nblk > OC_VOL || 2 + g > OC_VOL)
+    return ctx->fail(AMRTO_EINVAL, std::string(name) + ": workspace layout exceeds its size");
+  // log(lam) in [log 1e-300, log 1e300]; each pass narrows it 255-fold
+  hipLaunchKernelGGL(k_init_bracket, dim3(1), dim3(1), 0, ctx->stream, ws, std::log(1e-300), std::log(1e300));
+  double width = std::log(1e300) - std::log(1e-300);
+  while (width > 1e-14) {
+    hipLaunchKernelGGL(k_oc_volumes, dim3(nblk), dim3(OC_K), 0, ctx->stream, rho, dc, ctx->d_vol, ne, eta, move,
+                       rho_min, ws);
+    hipLaunchKernelGGL(k_oc_candsum, dim3(OC_K), dim3(256), 0, ctx->stream, ws, nblk);
+    hipLaunchKernelGGL(k_oc_bracket, dim3(1), dim3(OC_K), 0, ctx->stream, ws, v0);
+    width /= (OC_K - 1);
+  }
+  hipLaunchKernelGGL(k_oc_apply, dim3(g), dim3(256), 0, ctx->stream, rho, dc, ctx->d_vol, ne, eta, move, rho_min,
+                     rho_new, ws);
+  hipLaunchKernelGGL(k_oc_finish, dim3(1), dim3(256), 0, ctx->stream, ws, g);
+  AMRTO_HIP(hipGetLastError());
+  if (change_host || lam_host) {
+    AMRTO_HIP(hipMemcpyAsync(hbuf, ws, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    AMRTO_HIP(hipStreamSynchronize(ctx->stream));
+    if (change_host) *change_host = hbuf[2];
+    if (lam_host) *lam_host = hbuf[3];
+  }
   return AMRTO_OK;
 }
 
@@ -343,46 +459,19 @@ int amrto_filter(amrto_ctx* ctx, int mode, double rmin, const double* in, const 
   if (!ctx->has_mesh) return ctx->fail(AMRTO_ESTATE, "amrto_filter: no mesh");
   if (mode != AMRTO_FILTER_SENSITIVITY && mode != AMRTO_FILTER_DENSITY)
     return ctx->fail(AMRTO_EINVAL, "amrto_filter: unknown mode");
-  if (!(rmin > 0.0) || rmin > 16.0) return ctx->fail(AMRTO_EINVAL, "amrto_filter: rmin must be in (0, 16]");
+  if (!(rmin > 0.0) || rmin > (double)FILT_RMAX) return ctx->fail(AMRTO_EINVAL, "amrto_filter: rmin must be in (0, 16]");
   if (!in || !out || in == out || (mode == AMRTO_FILTER_SENSITIVITY && !rho))
     return ctx->fail(AMRTO_EINVAL, "amrto_filter: bad buffers");
   AMRTO_HIP(hipSetDevice(ctx->device));
   const int ne = ctx->n_elems;
   if (ctx->uniform) {
-    if (ctx->filt_rmin != rmin) {
-      // stencil of offsets with H = rmin - |d| > 0 (Eq. (4)); V_d = 1
-      std::vector<int32_t> st;
-      std::vector<double> wd;
-      const int R = (int)std::ceil(rmin);
-      for (int dz = -R; dz <= R; ++dz)
-        for (int dy = -R; dy <= R; ++dy)
-          for (int dx = -R; dx <= R; ++dx) {
-            const double H = rmin - std::sqrt((double)(dx * dx + dy * dy + dz * dz));
-            if (H > 0.0) {
-              st.insert(st.end(), {dx, dy, dz, 0});
-              wd.push_back(H);
-            }
-          }
-      if (ctx->d_nb_idx) (void)hipFree(ctx->d_nb_idx);
-      if (ctx->d_nb_w) (void)hipFree(ctx->d_nb_w);
-      ctx->d_nb_idx = nullptr;
-      ctx->d_nb_w = nullptr;
-      AMRTO_HIP(hipMalloc((void**)&ctx->d_nb_idx, st.size() * sizeof(int32_t)));
-      AMRTO_HIP(hipMalloc((void**)&ctx->d_nb_w, wd.size() * sizeof(double)));
-      AMRTO_HIP(hipMemcpy(ctx->d_nb_idx, st.data(), st.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-      AMRTO_HIP(hipMemcpy(ctx->d_nb_w, wd.data(), wd.size() * sizeof(double), hipMemcpyHostToDevice));
-      ctx->n_sten = (int)wd.size();
-      ctx->filt_rmin = rmin;
-    }
-    hipLaunchKernelGGL(k_filter_uniform, dim3((ne + 255) / 256), dim3(256), 0, ctx->stream, in, rho, out,
-                       (const int4*)ctx->d_nb_idx, ctx->d_nb_w, ctx->n_sten, ctx->nx, ctx->ny, ctx->nz, mode);
+    const int R = std::min(FILT_RMAX, (int)std::ceil(rmin));
+    hipLaunchKernelGGL(k_filter_uniform, dim3((ne + 255) / 256), dim3(256), 0, ctx->stream, in, rho, out, ctx->nx,
+                       ctx->ny, ctx->nz, rmin, R, mode);
   } else {
-    if (ctx->filt_rmin != rmin) {
-      int rc = build_neighbours(ctx, rmin);
-      if (rc) return rc;
-    }
-    hipLaunchKernelGGL(k_filter_csr, dim3((ne + 255) / 256), dim3(256), 0, ctx->stream, in, rho, out, ctx->d_nb_ptr,
-                       ctx->d_nb_idx, ctx->d_nb_w, ne, mode);
+    hipLaunchKernelGGL(k_filter_octree, dim3((ne + 255) / 256), dim3(256), 0, ctx->stream, in, rho, out,
+                       (const int4*)ctx->d_edesc, ctx->d_cmap, ne, ctx->nx, ctx->ny, ctx->nz, ctx->filt_hmax, rmin,
+                       mode);
   }
   AMRTO_HIP(hipGetLastError());
   return AMRTO_OK;
@@ -391,42 +480,32 @@ int amrto_filter(amrto_ctx* ctx, int mode, double rmin, const double* in, const 
 int amrto_oc_update(amrto_ctx* ctx, const double* rho, const double* dc, double volfrac, double move, double eta,
                     double rho_min, double* rho_new, double* change_host, double* lam_host) {
   if (!ctx) return AMRTO_EINVAL;
-  if (!ctx->has_mesh) return ctx->fail(AMRTO_ESTATE, "amrto_oc_update: no mesh");
-  if (!rho || !dc || !rho_new || rho_new == rho) return ctx->fail(AMRTO_EINVAL, "amrto_oc_update: bad buffers");
-  if (!(volfrac > 0.0 && volfrac <= 1.0) || !(move > 0.0) || !(eta > 0.0) || !(rho_min >= 0.0 && rho_min < 1.0))
-    return ctx->fail(AMRTO_EINVAL, "amrto_oc_update: bad parameters");
+  double h[4];
+  return oc_update_ws(ctx, ctx->d_oc, h, "amrto_oc_update", rho, dc, volfrac, move, eta, rho_min, rho_new,
+                      change_host, lam_host);
+}
+
+int amrto_design_difference(amrto_ctx* a, const double* rho_a, const amrto_ctx* b, const double* rho_b,
+                            double* D_host) {
+  if (!a || !b) return AMRTO_EINVAL;
+  amrto_ctx* ctx = a;
+  if (!a->has_mesh || !b->has_mesh) return ctx->fail(AMRTO_ESTATE, "amrto_design_difference: no mesh");
+  if (!rho_a || !rho_b || !D_host) return ctx->fail(AMRTO_EINVAL, "amrto_design_difference: NULL argument");
+  if (a->device != b->device) return ctx->fail(AMRTO_EINVAL, "amrto_design_difference: contexts on different devices");
+  if (a->nx != b->nx || a->ny != b->ny || a->nz != b->nz)
+    return ctx->fail(AMRTO_EINVAL, "amrto_design_difference: meshes cover different lattice boxes");
   AMRTO_HIP(hipSetDevice(ctx->device));
-  const int ne = ctx->n_elems;
-  double vtot = 0.0;
-  for (int e = 0; e < ne; ++e) {
-    const double h = (double)(1 << (ctx->max_level - ctx->h_level[e]));
-    vtot += h * h * h;
-  }
-  const double v0 = volfrac * vtot;
-  const int nblk = std::min(OC_BLOCKS, (ne + OC_TILE - 1) / OC_TILE);
-  double* ws = ctx->d_oc;
-  // log(lam) in [log 1e-300, log 1e300]; each pass narrows it 255-fold
-  hipLaunchKernelGGL(k_init_bracket, dim3(1), dim3(1), 0, ctx->stream, ws, std::log(1e-300), std::log(1e300));
-  double width = std::log(1e300) - std::log(1e-300);
-  while (width > 1e-14) {
-    hipLaunchKernelGGL(k_oc_volumes, dim3(nblk), dim3(OC_K), 0, ctx->stream, rho, dc, ctx->d_vol, ne, eta, move,
-                       rho_min, ws);
-    hipLaunchKernelGGL(k_oc_candsum, dim3(OC_K), dim3(256), 0, ctx->stream, ws, nblk);
-    hipLaunchKernelGGL(k_oc_bracket, dim3(1), dim3(OC_K), 0, ctx->stream, ws, v0);
-    width /= (OC_K - 1);
-  }
-  const int g = std::min(256, (ne + 255) / 256);
-  hipLaunchKernelGGL(k_oc_apply, dim3(g), dim3(256), 0, ctx->stream, rho, dc, ctx->d_vol, ne, eta, move, rho_min,
-                     rho_new, ws);
-  hipLaunchKernelGGL(k_oc_finish, dim3(1), dim3(256), 0, ctx->stream, ws, g);
+  const long cells = (long)a->nx * a->ny * a->nz;
+  const int nb = grid_for(cells, 256, RED_BLOCKS);
+  // b's mesh and densities are read on a's stream: b's earlier work must be
+  // complete (its calls that return host values synchronise)
+  hipLaunchKernelGGL(k_design_diff, dim3(nb), dim3(256), 0, ctx->stream, rho_a, a->uniform ? nullptr : a->d_cmap,
+                     rho_b, b->uniform ? nullptr : b->d_cmap, cells, ctx->d_part);
+  hipLaunchKernelGGL(k_design_diff_sum, dim3(1), dim3(256), 0, ctx->stream, ctx->d_part, nb, ctx->d_scal + 6);
   AMRTO_HIP(hipGetLastError());
-  if (change_host || lam_host) {
-    double h[4];
-    AMRTO_HIP(hipMemcpyAsync(h, ws, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    AMRTO_HIP(hipStreamSynchronize(ctx->stream));
-    if (change_host) *change_host = h[2];
-    if (lam_host) *lam_host = h[3];
-  }
+  AMRTO_HIP(hipMemcpyAsync(ctx->h_scal, ctx->d_scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  AMRTO_HIP(hipStreamSynchronize(ctx->stream));
+  *D_host = ctx->h_scal[6] / ctx->h_scal[7];
   return AMRTO_OK;
 }
 

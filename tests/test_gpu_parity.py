@@ -354,7 +354,7 @@ def test_compliance_and_sensitivity(pair_rho):
 
 
 @pytest.mark.parametrize("mode", [0, 1])
-@pytest.mark.parametrize("rmin", [1.5, 2.6])
+@pytest.mark.parametrize("rmin", [1.5, 2.6, 4.3])
 def test_filters(pair_rho, mode, rmin):
     p, rho = pair_rho
     ctx = make_ctx(p, rho)
