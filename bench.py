@@ -41,29 +41,36 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6  # FP64 vector: 256 CUs x 2.4 GHz x 128 flop/clk
 APPLY_SOURCES = ("paper_1009_4975_amd/csrc/apply.hip", "paper_1009_4975_amd/csrc/kernels.h",
                  "paper_1009_4975_amd/csrc/internal.h")
+PASS_SOURCES = APPLY_SOURCES + ("paper_1009_4975_amd/csrc/pcg.hip", "paper_1009_4975_amd/csrc/block3.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_octree_c2_traffic.txt")
+PASS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "op_pass_octree_c2_fp32_coarse_block3_traffic.txt")
 
 
-def apply_source_hash():
+def source_hash(sources=APPLY_SOURCES):
     h = hashlib.sha1()
-    for rel in APPLY_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the octree FP64 apply from the committed counter
-    summary, or None when the kernel sources changed since it was taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def apply_source_hash():
+    return source_hash(APPLY_SOURCES)
+
+
+def measured_traffic(path=TRAFFIC_FILE, sources=APPLY_SOURCES):
+    """HBM bytes per launch of a kernel from its committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the kernel's
+    sources changed since the counters were taken."""
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("source_hash") != apply_source_hash():
+    if kv.get("source_hash") != source_hash(sources):
         return None
     try:
         return float(kv["bytes_per_launch"])
@@ -127,6 +134,9 @@ def main():
     ap.add_argument("--profile-only", action="store_true", help="only the timed steps (for profilers)")
     ap.add_argument("--c3-only", action="store_true", help="only the uniform 192x96x96 apply measurement")
     ap.add_argument("--no-c4", action="store_true", help="skip the 50-iteration adaptive SIMP run")
+    ap.add_argument("--no-c15", action="store_true", help="skip the C1 and C5 solve lines")
+    ap.add_argument("--no-amr-vs-uniform", action="store_true", help="skip the AMR against uniform comparison")
+    ap.add_argument("--amr-vs-uniform-only", action="store_true", help="only the AMR against uniform comparison")
     ap.add_argument("--c4-only", action="store_true", help="only the 50-iteration adaptive SIMP run")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the C2 apply loop and a copy kernel of known size (for counter runs)")
@@ -145,6 +155,9 @@ def main():
     dev = lambda a, dt=torch.float64: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
     if args.c3_only:
         print(json.dumps(apply_uniform_bandwidth(torch, binding, synth, dev)), flush=True)
+        return
+    if args.amr_vs_uniform_only:
+        print(json.dumps(amr_vs_uniform(torch, binding, synth)), flush=True)
         return
     if args.c4_only:
         print(json.dumps(c4_simp(torch, binding, synth, tuple(int(r) for r in args.c4_regions.split(",")))),
@@ -174,6 +187,10 @@ def main():
         y = torch.empty_like(f)
         ms = event_time(torch, lambda: ctx.apply(x, y, binding.FP64), 50)
         log(f"[bench] C2 FP64 apply: {ms * 1e3:.2f} us/launch")
+        name = args.solver if args.solver != "best" else "fp32+coarse+block3"
+        op_us, up_us = pass_times(ctx, binding, b, u, name, tuple(int(r) for r in args.regions.split(",")), 50)
+        log(f"[bench] C2 {name} operator pass {op_us:.2f} us, update {up_us:.2f} us per launch")
+        log(f"[bench] pass source hash {source_hash(PASS_SOURCES)}")
         # calibration: a plain device copy of 256 MiB (reads and writes 268,435,456 bytes each)
         a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
         c = torch.empty_like(a)
@@ -249,20 +266,40 @@ def main():
     if args.profile_only:
         return
 
-    # --- dominant kernel: the FP64 stiffness apply on this mesh (chunk + shared-node pass)
+    # --- dominant kernel of the timed step: the solver variant's fused operator
+    # pass (stiffness apply + preconditioner + search direction), timed live
+    ne, nn = mesh.n_elems, mesh.n_nodes
+    op_us, up_us = pass_times(ctx, binding, b, u, solver, regions, 200)
+    pb = pass_bytes(solver, nn, ne)
+    gbs = pb / (op_us * 1e-6) / 1e9
+    log(f"[bench] C2 {solver} operator pass: {op_us:.2f} us/launch, {gbs:.0f} GB/s algorithmic; "
+        f"update side {up_us:.2f} us")
+    roofline = dict(bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(gbs / HBM_PEAK_GBS, 5),
+                    traffic=(measured_traffic(PASS_TRAFFIC_FILE, PASS_SOURCES)
+                             if solver == "fp32+coarse+block3" else None),
+                    kernel=f"fused CG operator pass of the {solver} solve (k_apply_chunks: stiffness apply, "
+                           "preconditioner, search direction, coarse-space partials)",
+                    per_launch_us=round(op_us, 3), alg_bytes_per_launch=int(pb),
+                    bytes_rule=PASS_BYTES_RULE, update_side_us=round(up_us, 3),
+                    traffic_unit="bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)")
+    # second entry: the plain FP64 stiffness apply on the same mesh
     x = torch.randn_like(f)
     y = torch.empty_like(f)
-    reps = 200
-    apply_ms = event_time(torch, lambda: ctx.apply(x, y, binding.FP64), reps)
-    ne, nn = mesh.n_elems, mesh.n_nodes
-    flops = 1152.0 * ne
-    log(f"[bench] C2 FP64 apply: {apply_ms * 1e3:.2f} us/launch ({flops / apply_ms / 1e9:.2f} TFLOP/s)")
-    traffic = measured_traffic()
-    roofline = dict(bound="alu", achieved=round(flops / (apply_ms * 1e-3) / 1e12, 4), peak=FP64_PEAK_TFLOPS,
-                    unit="TFLOP/s", frac=round(flops / (apply_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 5),
-                    traffic=traffic, kernel="octree FP64 stiffness apply (k_apply_chunks, FP64)",
-                    per_launch_us=round(apply_ms * 1e3, 3), flop_per_element=1152, elements=ne,
-                    traffic_unit="bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)")
+    apply_ms = event_time(torch, lambda: ctx.apply(x, y, binding.FP64), 200)
+    ab = 48.0 * nn + 8.0 * ne
+    log(f"[bench] C2 FP64 apply: {apply_ms * 1e3:.2f} us/launch ({ab / apply_ms / 1e6:.0f} GB/s algorithmic)")
+    roofline_apply = dict(bound="hbm", achieved=round(ab / (apply_ms * 1e-3) / 1e9, 2), peak=HBM_PEAK_GBS,
+                          unit="GB/s", frac=round(ab / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                          traffic=measured_traffic(), kernel="octree FP64 stiffness apply (k_apply_chunks, FP64)",
+                          per_launch_us=round(apply_ms * 1e3, 3), alg_bytes_per_launch=int(ab),
+                          bytes_rule="x read 24 B/node + y write 24 B/node + c_e 8 B/element",
+                          traffic_unit="bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)")
+
+    # --- C1 (one SIMP iteration on the uniform 24x12x12 cantilever) and C5
+    # (1.6 M DOF bridge: solves and the adjoint sensitivities)
+    c1 = None if args.no_c15 else solve_c1(torch, binding, synth, dev)
+    c5 = None if args.no_c15 else solve_c5(torch, binding, synth, dev)
 
     # --- uniform 192x96x96 apply bandwidth
     c3 = None
@@ -273,6 +310,9 @@ def main():
     c4 = None
     if not args.no_c4:
         c4 = c4_simp(torch, binding, synth, c4_regions)
+
+    # --- AMR against the uniform fine mesh (paper's trigger, design difference)
+    avu = None if args.no_amr_vs_uniform else amr_vs_uniform(torch, binding, synth)
 
     # --- CPU oracle on a bounded sample
     cpu = None
@@ -289,10 +329,172 @@ def main():
                    "hanging_nodes": int(len(mesh.hang_node)), "chunks": info["n_chunks"], "solver": solver,
                    "coarse_regions": list(regions) if "+coarse" in solver else None, "rtol": 1e-8, "E0": 1.0, "Emin": 1e-9, "nu": 0.3, "p": 3.0},
         "solve_iters": int(np.median(iters)), "solve_rel_res": float(max(rel)),
-        "solve_variants": variants, "roofline": roofline, "apply_uniform_192x96x96": c3, "simp_adaptive_bridge": c4,
+        "solve_variants": variants, "roofline": roofline, "roofline_apply_fp64": roofline_apply,
+        "c1_simp_iteration_24x12x12": c1, "c5_bridge_128x64x64": c5,
+        "apply_uniform_192x96x96": c3, "simp_adaptive_bridge": c4, "amr_vs_uniform_cantilever": avu,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+PASS_BYTES_RULE = ("vectors the fused operator pass must move, per node: r read, preconditioner read (Jacobi "
+                   "3 or node blocks 6 values), previous direction read, new direction and q written (3 values "
+                   "each); plain passes read z instead of r and the preconditioner; plus c_e per element; "
+                   "values of the inner precision (FP64 8 B, FP32 4 B)")
+
+
+def pass_bytes(name, nn, ne):
+    """Algorithmic bytes of one fused operator pass of solver variant `name`."""
+    vb = 8 if name.startswith("fp64") else 4
+    if "+coarse" in name:
+        per_node = 3 + (6 if "+block3" in name else 3) + 3 + 3 + 3
+    else:
+        per_node = 3 + 3 + 3 + 3
+    return per_node * vb * nn + vb * ne
+
+
+def pass_times(ctx, binding, b, u, name, regions, reps):
+    """Mean device time (us) of one operator pass and one update side of the
+    solver variant `name` (amrto_pcg_pass_times, HIP events on the context
+    stream); the coarse space is set up first for "+coarse" variants."""
+    precs = {"fp64": binding.FP64, "fp32": binding.FP32, "bf16": binding.BF16}
+    coarse = "+coarse" in name
+    if coarse:
+        ctx.coarse_setup([], *regions, affine=True)
+    w = u.clone().zero_()
+    op, up = ctx.pcg_pass_times(b, w, reps=reps, inner_prec=precs[name.split("+")[0]],
+                                precond=binding.BLOCK3 if "+block3" in name else binding.JACOBI)
+    if coarse:
+        ctx.coarse_clear()
+    return op, up
+
+
+def best_ms(fn, n=3):
+    out = [fn() for _ in range(n)]
+    return min(out, key=lambda r: r["ms"]), out
+
+
+def solve_c1(torch, binding, synth, dev):
+    """One SIMP iteration on the uniform 24x12x12 cantilever (3,456 elements,
+    12,675 DOFs): the seeded densities smoothed once by the r = 1.5 cone
+    filter, then Jacobi-PCG (FP64) from zero to 1e-8, compliance and
+    sensitivities, the Eq. (5) filter and the OC step; best of three."""
+    case = synth.c1()
+    mesh = binding.uniform_mesh(case.dims, case.fixed, case.load)
+    ctx = binding.Context(0)
+    ctx.upload_mesh(mesh)
+    rho0 = dev(case.rho)
+    rho = torch.empty_like(rho0)
+    ctx.filter(binding.FILTER_DENSITY, case.smooth_radius, rho0, rho)
+    f = dev(mesh.f_load)
+    b = torch.empty_like(f)
+    u = torch.zeros_like(f)
+    dc, dcf, rho_new = (torch.empty_like(rho) for _ in range(3))
+
+    def it():
+        t0 = time.perf_counter()
+        ctx.set_density(rho)
+        ctx.project_rhs(f, b)
+        u.zero_()
+        st = ctx.pcg(b, u, rtol=1e-8)
+        t1 = time.perf_counter()
+        c = ctx.compliance(u, f, rho, dc)
+        ctx.filter(binding.FILTER_SENSITIVITY, case.filter_radius, dc, dcf, rho=rho)
+        ch, _ = ctx.oc_update(rho, dcf, rho_new, 0.3)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return dict(ms=(t2 - t0) * 1e3, solve_ms=st["ms"], design_ms=(t2 - t1) * 1e3, iters=st["iters"],
+                    rel_res=st["rel_res"], compliance=c)
+
+    it()
+    r, _ = best_ms(it)
+    log(f"[bench] C1 SIMP iteration: {r['ms']:.2f} ms (solve {r['solve_ms']:.2f} ms, {r['iters']} iterations, "
+        f"rel_res {r['rel_res']:.2e}; compliance, sensitivities, filter, OC {r['design_ms']:.2f} ms)")
+    return dict(iteration_ms=round(r["ms"], 3), solve_ms=round(r["solve_ms"], 3), design_ms=round(r["design_ms"], 3),
+                iters=r["iters"], rel_res=r["rel_res"], compliance=r["compliance"], dofs=3 * mesh.n_nodes,
+                solver="fp64 Jacobi-PCG from zero", rtol=1e-8)
+
+
+def solve_c5(torch, binding, synth, dev):
+    """The 128x64x64 bridge (524,288 elements, 1,635,075 DOFs), rho ~ U[0.01, 1]:
+    solves from zero to 1e-8 in FP64 and with FP32 inner solves (Jacobi and
+    block-Jacobi), then compliance + adjoint sensitivities of the FP64
+    solution; best of two per variant."""
+    case = synth.c5()
+    mesh = binding.uniform_mesh(case.dims, case.fixed, case.load)
+    ctx = binding.Context(0)
+    ctx.upload_mesh(mesh)
+    rho = dev(case.rho)
+    ctx.set_density(rho)
+    f = dev(mesh.f_load)
+    b = torch.empty_like(f)
+    ctx.project_rhs(f, b)
+    u = torch.zeros_like(f)
+    dc = torch.empty_like(rho)
+    out = {}
+    for name, prec, pc in (("fp64", binding.FP64, binding.JACOBI), ("fp32", binding.FP32, binding.JACOBI),
+                           ("fp64+block3", binding.FP64, binding.BLOCK3),
+                           ("fp32+block3", binding.FP32, binding.BLOCK3)):
+        def run():
+            u.zero_()
+            return ctx.pcg(b, u, rtol=1e-8, inner_prec=prec, inner_rtol=0.1, max_it=50000, precond=pc)
+        r, _ = best_ms(run, 2)
+        out[name] = dict(ms=round(r["ms"], 2), iters=r["iters"], outer=r["outer"], rel_res=r["rel_res"])
+        log(f"[bench] C5 solve {name}: {r['ms']:.1f} ms, {r['iters']} iterations, rel_res {r['rel_res']:.2e}")
+    u.zero_()
+    ctx.pcg(b, u, rtol=1e-8)
+    ctx.compliance(u, f, rho, dc)
+    sens_ms = event_time(torch, lambda: ctx.sensitivity(u, rho, dc), 20)
+    out["adjoint_sensitivity_us"] = round(sens_ms * 1e3, 2)
+    out["dofs"] = 3 * mesh.n_nodes
+    log(f"[bench] C5 adjoint sensitivities: {sens_ms * 1e3:.1f} us per launch")
+    return out
+
+
+def amr_vs_uniform(torch, binding, synth):
+    """The paper's AMR-against-uniform comparison on a synthetic cantilever:
+    the same SIMP loop (plain FP64 Jacobi-PCG to 1e-8 from the previous
+    displacement, Eq. (5) filter, OC) on the fixed uniform 128x32x32 mesh and
+    on an adaptive mesh started at 64x16x16 (one refinement level) adapted by
+    the paper's trigger (CASE (i): largest design change < 0.01 after >= 5
+    steps; CASE (ii): 10 steps), for the same number of design steps.  Both
+    run the octree operator kernels.  Reports sizes, iterations, solve time
+    and the design difference D of Eq. (10) between the final designs."""
+    from paper_1009_4975_amd.simp import AdaptiveSIMP
+    case = synth.amr_vs_uniform()
+    ex = case.extra
+    runs = {}
+    for name, base, L, rule in (("uniform", case.dims, 0, "never"), ("amr", case.base, case.max_level, "paper")):
+        t0 = time.perf_counter()
+        sim = AdaptiveSIMP(base, L, case.fixed, case.load, volfrac=ex["volfrac"], rho_init=ex["rho_init"],
+                           rmin=ex["rmin"], rho_solid=ex["rho_solid"], r_amr=ex["r_amr"], adapt_rule=rule,
+                           min_steps=ex["min_steps"], max_steps=ex["max_steps"], change_tol=ex["change_tol"],
+                           rtol=1e-8, p_continuation=ex.get("p_continuation"))
+        recs = [sim.step() for _ in range(ex["steps"])]
+        torch.cuda.synchronize()
+        runs[name] = dict(sim=sim, recs=recs, wall_s=time.perf_counter() - t0)
+    out = {}
+    for name, r in runs.items():
+        recs = r["recs"]
+        out[name] = dict(steps=len(recs), solve_ms=round(sum(x["solve_ms"] for x in recs), 1),
+                         pcg_iters=int(sum(x["iters"] for x in recs)),
+                         dofs_mean=int(np.mean([x["dofs"] for x in recs])), dofs_final=recs[-1]["dofs"],
+                         elements_final=recs[-1]["n_elems"], adaptations=int(sum(x["adapted"] for x in recs)),
+                         final_compliance=recs[-1]["compliance"], final_change=recs[-1]["change"],
+                         max_rel_res=max(x["rel_res"] for x in recs), wall_s=round(r["wall_s"], 2))
+    su, sa = runs["uniform"]["sim"], runs["amr"]["sim"]
+    D = su.ctx.design_difference(su.rho, sa.ctx, sa.rho)
+    out["design_difference_D"] = D
+    out["solve_time_ratio_uniform_over_amr"] = round(out["uniform"]["solve_ms"] / out["amr"]["solve_ms"], 3)
+    out["dofs_ratio_amr_over_uniform"] = round(out["amr"]["dofs_mean"] / out["uniform"]["dofs_mean"], 3)
+    out["config"] = dict(uniform=list(case.dims), amr_initial=list(case.base), levels=case.max_level,
+                         volfrac=ex["volfrac"], rmin=ex["rmin"], steps=ex["steps"], solver="fp64 Jacobi-PCG, 1e-8",
+                         p_continuation=ex.get("p_continuation"))
+    log(f"[bench] AMR vs uniform ({ex['steps']} steps): uniform {out['uniform']['solve_ms']} ms solve, "
+        f"{out['uniform']['pcg_iters']} its, {out['uniform']['dofs_mean']} DOFs mean; AMR {out['amr']['solve_ms']} ms, "
+        f"{out['amr']['pcg_iters']} its, {out['amr']['dofs_mean']} DOFs mean, {out['amr']['adaptations']} adapts; "
+        f"D = {100 * D:.3f} %, time ratio {out['solve_time_ratio_uniform_over_amr']}")
+    return out
 
 
 def apply_uniform_bandwidth(torch, binding, synth, dev):
@@ -353,18 +555,29 @@ def c4_simp(torch, binding, synth, regions=(2, 2, 2)):
                              ("coarse_block3_fp64", binding.FP64, "coarse+block3"),
                              ("coarse_block3_fp32", binding.FP32, "coarse+block3"),
                              ("learned_coarse_fp64", binding.FP64, "learned"),
-                             ("learned_coarse_fp32", binding.FP32, "learned")):
+                             ("learned_coarse_fp32", binding.FP32, "learned"),
+                             ("recycle_coarse_fp64", binding.FP64, "recycle")):
         t0 = time.perf_counter()
         sim = AdaptiveSIMP(case.base, case.max_level, case.fixed, case.load, volfrac=ex["volfrac"],
                            rho_init=ex["rho_init"], rmin=ex["rmin"], rho_solid=ex["rho_solid"], r_amr=ex["r_amr"],
                            adapt_every=ex["adapt_every"], rtol=1e-8, inner_prec=prec, inner_rtol=0.1,
                            precond=binding.BLOCK3 if (mode or "").endswith("block3") else binding.JACOBI)
+        if mode == "recycle":
+            # from iteration 11 on: recorded solves, Ritz vectors carried to
+            # the next system and added to the affine coarse space
+            mode = None
+            rec_from = n_train
+        else:
+            rec_from = None
         # the node-block preconditioner changes nothing else in a run
         mode = {"block3": None, "coarse+block3": "coarse"}.get(mode, mode)
         ws = LearnedWarmStart(case.dims, cell=2, hidden=8, layers=3, epochs=100, seed=ex["net_seed"],
                               regions=tuple(regions)) if mode else None
         recs, train_ms = [], 0.0
         for k in range(ex["iters"]):
+            if rec_from is not None and k == rec_from:
+                sim.recycle = dict(m=64, k=4, keep=4, regions=tuple(regions), affine=True)
+                sim.ctx.recycle_setup(64)
             if mode == "learned" and k < n_train:
                 r = sim.step(warm_start=ws.collect_before, after_solve=ws.collect_after)
             elif mode and k >= n_train:

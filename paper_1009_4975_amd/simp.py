@@ -2,9 +2,15 @@
 
 Each iteration solves K(rho) u = f on the current mesh (Eq. (1), (7)-(9)),
 forms the compliance sensitivities (Sec. 3), filters them (Eq. (5)) and takes
-an optimality-criteria step; every ``adapt_every`` iterations the mesh is
-adapted to the current design (Sec. 4) and rho and u are carried over.  The
-previous displacement is the initial guess of the next solve (Sec. 5).
+an optimality-criteria step.  The mesh is adapted to the current design
+(Sec. 4) and rho and u are carried over either every ``adapt_every``
+iterations (``adapt_rule="every"``) or by the paper's rule (``"paper"``):
+CASE (i) the largest design change of the last step is below ``change_tol``
+(0.01) after at least ``min_steps`` (5) steps on the mesh, CASE (ii) after
+``max_steps`` (10) steps without CASE (i).  The previous displacement is the
+initial guess of the next solve (Sec. 5).  ``p_continuation`` (Sec. 3) starts
+the penalty at p0 and raises it by dp whenever the design has settled (change
+below tol) or max_steps steps were taken at the current p, up to p_max.
 
 All arithmetic runs in ``libamrto.so``; this module only sequences the calls
 and moves the per-leaf arrays between the host octree and the device when the
@@ -25,7 +31,9 @@ from .binding import FILTER_SENSITIVITY, FP64
 class AdaptiveSIMP:
     def __init__(self, base, max_level, fixed, load, volfrac=0.25, rho_init=0.25, rmin=1.5, move=0.2, eta=0.5,
                  rho_min=1e-3, rho_solid=0.5, r_amr=1.5, adapt_every=5, rtol=1e-8, inner_prec=FP64,
-                 inner_rtol=0.1, max_it=100000, device=0, metrics_path=None, precond=binding.JACOBI):
+                 inner_rtol=0.1, max_it=100000, device=0, metrics_path=None, precond=binding.JACOBI,
+                 adapt_rule="every", min_steps=5, max_steps=10, change_tol=0.01, p_continuation=None,
+                 p=3.0, recycle=None):
         self.base, self.max_level = tuple(int(b) for b in base), int(max_level)
         self.tree = binding.Octree(base, max_level)
         self.ctx = binding.Context(device)
@@ -35,10 +43,25 @@ class AdaptiveSIMP:
         self.rho_solid, self.r_amr, self.adapt_every = rho_solid, r_amr, adapt_every
         self.rtol, self.inner_prec, self.inner_rtol, self.max_it = rtol, inner_prec, inner_rtol, max_it
         self.precond = precond
+        if adapt_rule not in ("every", "paper", "never"):
+            raise ValueError("adapt_rule must be 'every', 'paper' or 'never'")
+        self.adapt_rule, self.min_steps, self.max_steps, self.change_tol = adapt_rule, min_steps, max_steps, change_tol
+        self.steps_on_mesh = 0
+        self.last_change = float("inf")
+        # p-continuation: dict(p0=1, dp=0.5, p_max=3, tol=0.01, max_steps=20) or None (fixed p)
+        self.p_cont = None if p_continuation is None else dict(dict(p0=1.0, dp=0.5, p_max=3.0, tol=0.01,
+                                                                    max_steps=20), **p_continuation)
+        self.p = float(self.p_cont["p0"] if self.p_cont else p)
+        self.steps_at_p = 0
+        # Krylov recycling: dict(m=64, k=4, keep=4, regions=(3, 2, 2), affine=True) or None
+        self.recycle = None if recycle is None else dict(dict(m=64, k=4, keep=4, regions=(3, 2, 2), affine=True),
+                                                         **recycle)
+        self.rec_vecs = []  # carried vectors (kept Rayleigh-Ritz vectors, then the last harvest)
         self.it = 0
         self.compliance = None
         self.mesh_version = 0
         self.metrics_path = metrics_path
+        self.ctx.set_material(p=self.p)
         n = self.tree.lib.amrto_octree_n_leaves(self.tree.h)
         self._set_mesh(np.full(n, rho_init), None)
 
@@ -58,6 +81,8 @@ class AdaptiveSIMP:
         self.u = (torch.zeros_like(self.f) if u_host is None
                   else torch.tensor(u_host, dtype=torch.float64, device=d))
         self.mesh_version += 1
+        if self.recycle is not None:
+            self.ctx.recycle_setup(self.recycle["m"])
         # per-mesh counts for the metrics log
         lv = mesh.elem_level.astype(np.int64)
         self.elem_volume = np.ldexp(1.0, 3 * (self.max_level - lv))  # leaf edge 2^(L - level) lattice units
@@ -75,7 +100,22 @@ class AdaptiveSIMP:
         rho_new = self.tree.adapt(rho_h, self.rho_solid, self.r_amr)
         mesh = self.tree.build_mesh(self.fixed, self.load)
         u_new = self.tree.transfer_nodal(u_h, mesh.n_nodes)
+        # recycled vectors follow the mesh as the displacement does
+        rec = [self.tree.transfer_nodal(v.cpu().numpy(), mesh.n_nodes) for v in self.rec_vecs]
         self._set_mesh(rho_new, u_new)
+        self.rec_vecs = [torch.tensor(v, dtype=torch.float64, device=self.dev) for v in rec]
+        for v in self.rec_vecs:
+            self.ctx.mask(v)
+        self.steps_on_mesh = 0
+
+    def adapt_due(self):
+        """Whether this iteration starts with an adaptation (Sec. 4)."""
+        if self.it == 0 or self.adapt_rule == "never":
+            return False
+        if self.adapt_rule == "every":
+            return self.adapt_every > 0 and self.it % self.adapt_every == 0
+        settled = self.last_change < self.change_tol and self.steps_on_mesh >= self.min_steps
+        return settled or self.steps_on_mesh >= self.max_steps
 
     # ------------------------------------------------------------------ step
     def step(self, warm_start=None, after_solve=None):
@@ -84,17 +124,24 @@ class AdaptiveSIMP:
         ``after_solve(sim)`` sees the new displacement before the design update."""
         rec = {"it": self.it, "adapted": False}
         t0 = time.perf_counter()
-        if self.it > 0 and self.adapt_every > 0 and self.it % self.adapt_every == 0:
+        if self.adapt_due():
             self.adapt()
             rec["adapted"] = True
         t1 = time.perf_counter()
         self.ctx.set_density(self.rho)
         if warm_start is not None:
             warm_start(self)
+        if self.recycle is not None:
+            self._recycle_coarse()
         torch.cuda.synchronize(self.dev)
         t2 = time.perf_counter()
         st = self.ctx.pcg(self.b, self.u, rtol=self.rtol, max_it=self.max_it, inner_prec=self.inner_prec,
-                          inner_rtol=self.inner_rtol, precond=self.precond)
+                          inner_rtol=self.inner_rtol, precond=self.precond, record=self.recycle is not None)
+        harvest_s = 0.0
+        if self.recycle is not None:
+            th = time.perf_counter()
+            self._recycle_harvest()
+            harvest_s = time.perf_counter() - th
         if after_solve is not None:
             after_solve(self)
         t3 = time.perf_counter()
@@ -105,16 +152,52 @@ class AdaptiveSIMP:
         self.rho, self.rho_new = self.rho_new, self.rho
         self.compliance = c
         self.it += 1
+        self.steps_on_mesh += 1
+        self.last_change = change
+        rec["p"] = self.p
+        self.steps_at_p += 1
+        pc = self.p_cont
+        if pc is not None and self.p < pc["p_max"] and (change < pc["tol"] or self.steps_at_p >= pc["max_steps"]):
+            self.p = min(pc["p_max"], self.p + pc["dp"])
+            self.steps_at_p = 0
+            self.ctx.set_material(p=self.p)
         t4 = time.perf_counter()
         info = self.ctx.info()
         rec.update(n_elems=info["n_elems"], n_nodes=info["n_nodes"], dofs=3 * info["n_nodes"],
                    iters=st["iters"], outer=st["outer"], rel_res=st["rel_res"], solve_ms=st["ms"],
                    fell_back=st["fell_back"],
-                   warm_ms=1e3 * (t2 - t1), adapt_ms=1e3 * (t1 - t0), design_ms=1e3 * (t4 - t3),
+                   warm_ms=1e3 * (t2 - t1 + harvest_s), adapt_ms=1e3 * (t1 - t0), design_ms=1e3 * (t4 - t3),
                    step_ms=1e3 * (t4 - t0), compliance=c, change=change, lam=lam)
         if self.metrics_path is not None:
             self.log_metrics(rec)
         return rec
+
+    def _recycle_coarse(self):
+        """Coarse space of this solve: the affine fields (optional) and the
+        best `keep` directions, by Rayleigh-Ritz for the current system, of
+        the carried vectors."""
+        rc = self.recycle
+        W = []
+        if self.rec_vecs:
+            keep = min(rc["keep"], len(self.rec_vecs))
+            W = [torch.empty_like(self.u) for _ in range(keep)]
+            try:
+                self.ctx.rayleigh_ritz(self.rec_vecs, W)
+            except binding.AmrtoError:
+                W = []  # the carried vectors lost their independent directions
+        if W or rc["affine"]:
+            self.ctx.coarse_setup(W, *rc["regions"], affine=rc["affine"])
+        self.rec_vecs = W
+
+    def _recycle_harvest(self):
+        """Ritz vectors of the recorded solve join the kept vectors."""
+        U = [torch.empty_like(self.u) for _ in range(self.recycle["k"])]
+        try:
+            self.ctx.recycle_harvest(U)
+        except binding.AmrtoError:
+            U = []  # the solve was too short to harvest k vectors
+        self.rec_vecs = self.rec_vecs + U
+        self.ctx.coarse_clear()
 
     def log_metrics(self, rec):
         """Append one JSON line: the step record, the volume fraction of the
@@ -128,12 +211,15 @@ class AdaptiveSIMP:
     def state_dict(self):
         """Host arrays that restart the run at the next iteration: the leaf set
         (levels and anchors in Morton order), rho per leaf, u on the mesh nodes,
-        the iteration counter and the last compliance."""
+        the iteration counter, the last compliance, and the state of the
+        adaptation trigger and of the p-continuation."""
         levels, anchors = self.tree.leaves()
         return {"base": np.array(self.base, np.int32), "max_level": np.int32(self.max_level),
                 "leaf_level": levels, "leaf_anchor": anchors, "rho": self.rho.cpu().numpy(),
                 "u": self.u.cpu().numpy(), "it": np.int64(self.it),
-                "compliance": np.float64(np.nan if self.compliance is None else self.compliance)}
+                "compliance": np.float64(np.nan if self.compliance is None else self.compliance),
+                "p": np.float64(self.p), "steps_on_mesh": np.int64(self.steps_on_mesh),
+                "last_change": np.float64(self.last_change), "steps_at_p": np.int64(self.steps_at_p)}
 
     def load_state_dict(self, st):
         """Rebuild the tree from the saved leaf set (refining every leaf that
@@ -154,6 +240,12 @@ class AdaptiveSIMP:
         self.it = int(st["it"])
         c = float(st["compliance"])
         self.compliance = None if np.isnan(c) else c
+        if "p" in st:
+            self.p = float(st["p"])
+            self.steps_on_mesh = int(st["steps_on_mesh"])
+            self.last_change = float(st["last_change"])
+            self.steps_at_p = int(st["steps_at_p"])
+            self.ctx.set_material(p=self.p)
 
 
 def rebuild_tree(base, max_level, levels, anchors):
