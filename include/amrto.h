@@ -301,6 +301,24 @@ int amrto_oc_update(amrto_ctx* ctx, const double* rho_dev, const double* dc_dev,
                     double volfrac, double move, double eta, double rho_min,
                     double* rho_new_dev, double* change_host, double* lam_host);
 
+/* amrto_oc_update for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, kernels and results, but its search workspace is a
+ * file-scope device array of the library (262,466 doubles, 2.1 MB,
+ * one copy per GPU, held until the process ends; its address is looked up at
+ * amrto_create) instead of the context's buffer, and the host results come
+ * back through the context's pinned scalar buffer.  The call allocates and
+ * frees nothing.  The workspace does not grow with the mesh (the search uses
+ * at most 1024 blocks of partial volumes whatever n_elems), so every mesh the
+ * context accepts fits; a layout that would not fit is rejected with EINVAL.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (each call writes every entry it reads before reading it):
+ * overlapping calls on one GPU, from any context or stream, race.
+ * Errors as amrto_oc_update; ESTATE if the scratch address is unknown. */
+int amrto_oc_update_noalloc(amrto_ctx* ctx, const double* rho_dev, const double* dc_dev,
+                            double volfrac, double move, double eta, double rho_min,
+                            double* rho_new_dev, double* change_host, double* lam_host);
+
 /* Relative difference of two designs (Sec. 7, Eq. (10)):
  *   D = int |rho_a - rho_b| dOmega / int rho_a dOmega,
  * evaluated on the finest lattice after carrying both designs to the finest

@@ -82,6 +82,8 @@ _SIGS = {
     "amrto_filter": (C.c_int, [_p, C.c_int, C.c_double, _p, _p, _p]),
     "amrto_oc_update": (C.c_int, [_p, _p, _p, C.c_double, C.c_double, C.c_double, C.c_double, _p,
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "amrto_oc_update_noalloc": (C.c_int, [_p, _p, _p, C.c_double, C.c_double, C.c_double, C.c_double, _p,
+                                          C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "amrto_design_difference": (C.c_int, [_p, _p, _p, _p, C.POINTER(C.c_double)]),
     "amrto_mask": (C.c_int, [_p, _p]),
     "amrto_coarse_setup": (C.c_int, [_p, C.c_int32, C.POINTER(_p), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
@@ -499,6 +501,15 @@ class Context:
         self._chk(self.lib.amrto_oc_update(self.h, _dev(rho, self.torch.float64), _dev(dc, self.torch.float64),
                                            volfrac, move, eta, rho_min, _dev(rho_new, self.torch.float64),
                                            C.byref(ch), C.byref(lam)))
+        return ch.value, lam.value
+
+    def oc_update_noalloc(self, rho, dc, rho_new, volfrac, move=0.2, eta=0.5, rho_min=1e-3):
+        """amrto_oc_update on the library's per-GPU static scratch (no workspace of the context)."""
+        self._elems(rho=rho, dc=dc, rho_new=rho_new)
+        ch, lam = C.c_double(), C.c_double()
+        self._chk(self.lib.amrto_oc_update_noalloc(self.h, _dev(rho, self.torch.float64),
+                                                   _dev(dc, self.torch.float64), volfrac, move, eta, rho_min,
+                                                   _dev(rho_new, self.torch.float64), C.byref(ch), C.byref(lam)))
         return ch.value, lam.value
 
     def design_difference(self, rho, other, rho_other):

@@ -182,7 +182,8 @@ int amrto_create(amrto_ctx** out, int device, void* stream) {
     amrto_destroy(ctx);
     return AMRTO_ENOMEM;
   }
-  int rc = upload_material(ctx);
+  int rc = oc_scratch_attach(ctx);
+  if (rc == AMRTO_OK) rc = upload_material(ctx);
   if (rc != AMRTO_OK) { amrto_destroy(ctx); return rc; }
   *out = ctx;
   return AMRTO_OK;

@@ -174,6 +174,7 @@ struct amrto_ctx {
   double* d_scal = nullptr;   // scalar slots
   double* h_scal = nullptr;   // pinned mirror
   double* d_oc = nullptr;     // OC search workspace
+  double* d_oc_scratch = nullptr;  // device address of the file-scope OC scratch on this device
   // coarse space (coarse.hip)
   int coarse_k = 0, coarse_nf = 0, coarse_R = 0, coarse_cap = 0;
   int coarse_affine_only = 0;   // fields generated on the fly by the solve kernels
@@ -235,6 +236,7 @@ int recycle_begin(amrto_ctx* ctx);
 int recycle_store(amrto_ctx* ctx, const double* z, int j);
 // topopt.hip
 int build_cell_map(amrto_ctx* ctx);
+int oc_scratch_attach(amrto_ctx* ctx);
 // vec.hip
 int launch_set_density(amrto_ctx* ctx, const double* rho);
 int launch_project_rhs(amrto_ctx* ctx, const double* f, double* b);

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "internal.h"
 
@@ -348,6 +349,32 @@ __global__ __launch_bounds__(256) void k_design_diff_sum(const double* __restric
   }
 }
 
+// ------------------------------------------------------------------ OC scratch
+// Workspace of amrto_oc_update_noalloc: a file-scope device array (one copy
+// per GPU, held until the process ends) instead of the context's buffer.
+// Host code never passes `scratch` itself to a kernel: its device address on
+// each GPU comes from hipGetSymbolAddress at context creation.
+constexpr int OC_SCRATCH_DEVICES = 64;
+static __device__ __align__(256) double scratch[OC_WS];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[OC_SCRATCH_DEVICES] = {};
+
+// Called by amrto_create with ctx->device current: looks the array's address
+// up once per device and keeps it in the context.
+int oc_scratch_attach(amrto_ctx* ctx) {
+  if (ctx->device < 0 || ctx->device >= OC_SCRATCH_DEVICES)
+    return ctx->fail(AMRTO_EINVAL, "amrto_create: device index above the OC scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[ctx->device]) {
+    void* ptr = nullptr;
+    AMRTO_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return ctx->fail(AMRTO_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[ctx->device] = ptr;
+  }
+  ctx->d_oc_scratch = (double*)g_scratch_ptr[ctx->device];
+  return AMRTO_OK;
+}
+
 // ------------------------------------------------------------------ host
 // Element descriptors and the lattice cell map of an octree mesh, built at
 // mesh upload (the filter reads them; no per-call host work).
@@ -483,6 +510,16 @@ int amrto_oc_update(amrto_ctx* ctx, const double* rho, const double* dc, double 
   double h[4];
   return oc_update_ws(ctx, ctx->d_oc, h, "amrto_oc_update", rho, dc, volfrac, move, eta, rho_min, rho_new,
                       change_host, lam_host);
+}
+
+int amrto_oc_update_noalloc(amrto_ctx* ctx, const double* rho, const double* dc, double volfrac, double move,
+                            double eta, double rho_min, double* rho_new, double* change_host, double* lam_host) {
+  if (!ctx) return AMRTO_EINVAL;
+  if (!ctx->d_oc_scratch) return ctx->fail(AMRTO_ESTATE, "amrto_oc_update_noalloc: scratch address not set");
+  // the context's pinned scalar mirror receives the host results (slots
+  // 0-3; no solve is running while this call synchronises)
+  return oc_update_ws(ctx, ctx->d_oc_scratch, ctx->h_scal, "amrto_oc_update_noalloc", rho, dc, volfrac, move, eta,
+                      rho_min, rho_new, change_host, lam_host);
 }
 
 int amrto_design_difference(amrto_ctx* a, const double* rho_a, const amrto_ctx* b, const double* rho_b,
