@@ -556,19 +556,22 @@ def c4_simp(torch, binding, synth, regions=(2, 2, 2)):
                              ("coarse_block3_fp32", binding.FP32, "coarse+block3"),
                              ("learned_coarse_fp64", binding.FP64, "learned"),
                              ("learned_coarse_fp32", binding.FP32, "learned"),
-                             ("recycle_coarse_fp64", binding.FP64, "recycle")):
+                             ("recycle_init_coarse_block3_fp64", binding.FP64, "recycle_init+coarse+block3"),
+                             ("recycle_init_coarse_block3_fp32", binding.FP32, "recycle_init+coarse+block3"),
+                             ("recycle_in_coarse_space_fp64", binding.FP64, "recycle_coarse")):
         t0 = time.perf_counter()
         sim = AdaptiveSIMP(case.base, case.max_level, case.fixed, case.load, volfrac=ex["volfrac"],
                            rho_init=ex["rho_init"], rmin=ex["rmin"], rho_solid=ex["rho_solid"], r_amr=ex["r_amr"],
                            adapt_every=ex["adapt_every"], rtol=1e-8, inner_prec=prec, inner_rtol=0.1,
                            precond=binding.BLOCK3 if (mode or "").endswith("block3") else binding.JACOBI)
-        if mode == "recycle":
-            # from iteration 11 on: recorded solves, Ritz vectors carried to
-            # the next system and added to the affine coarse space
-            mode = None
+        rec_from, rec_mode = None, None
+        if (mode or "").startswith("recycle"):
+            # from iteration 11 on: recorded solves whose Ritz vectors start
+            # the next solve ("init", with the solver of the coarse+block3
+            # variant) or join the affine coarse space ("coarse")
+            rec_mode = "init" if mode.startswith("recycle_init") else "coarse"
+            mode = "coarse" if rec_mode == "init" else None
             rec_from = n_train
-        else:
-            rec_from = None
         # the node-block preconditioner changes nothing else in a run
         mode = {"block3": None, "coarse+block3": "coarse"}.get(mode, mode)
         ws = LearnedWarmStart(case.dims, cell=2, hidden=8, layers=3, epochs=100, seed=ex["net_seed"],
@@ -576,7 +579,7 @@ def c4_simp(torch, binding, synth, regions=(2, 2, 2)):
         recs, train_ms = [], 0.0
         for k in range(ex["iters"]):
             if rec_from is not None and k == rec_from:
-                sim.recycle = dict(m=64, k=4, keep=4, regions=tuple(regions), affine=True)
+                sim.recycle = dict(mode=rec_mode, m=64, k=4, keep=4, regions=tuple(regions), affine=True)
                 sim.ctx.recycle_setup(64)
             if mode == "learned" and k < n_train:
                 r = sim.step(warm_start=ws.collect_before, after_solve=ws.collect_after)

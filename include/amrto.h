@@ -184,12 +184,12 @@ typedef struct {
                          arithmetic); 0 (default): two passes, which measured
                          faster on the octree cantilever (the one pass carries
                          the update's gathers and is as long as both) */
-  int32_t record;     /* 1: keep the first m preconditioned residuals and the
-                         CG coefficients of this solve for
-                         amrto_recycle_harvest (needs amrto_recycle_setup; FP64
-                         solves, Jacobi with or without a coarse space, or
-                         block-Jacobi without one; only the first CG run of a
-                         solve is recorded).  0 (default): nothing recorded */
+  int32_t record;     /* 1: keep the first m residuals and the CG
+                         coefficients of this solve for amrto_recycle_harvest
+                         (needs amrto_recycle_setup; any precision and
+                         preconditioner of the two-pass form; only the first
+                         CG run of a solve, or the first cycle of a mixed
+                         solve, is recorded).  0 (default): nothing recorded */
 } amrto_solve_opts;
 
 typedef struct {
@@ -238,27 +238,30 @@ int amrto_pcg_pass_times(amrto_ctx* ctx, const double* b_dev, double* u_dev, con
 /* ------------------------------------------------------------------ recycling
  * Krylov subspace recycling across the systems of a design sequence (Sec. 5:
  * an approximate invariant subspace for the smallest eigenvalues, taken from
- * one solve's Krylov space, is carried to the next system).  A recorded FP64
- * solve keeps its first m preconditioned residuals z_j with r_j^T z_j and
- * p_j^T A~ p_j; their Lanczos matrix T (T[j][j] = 1/alpha_j +
+ * one solve's Krylov space, is carried to the next system).  A recorded solve
+ * keeps its first m residuals r_j with r_j^T z_j and p_j^T A~ p_j (z_j =
+ * M^-1 r_j); their Lanczos matrix T (T[j][j] = 1/alpha_j +
  * beta_{j-1}/alpha_{j-1}, T[j][j+1] = sqrt(beta_j)/alpha_j, Lanczos vectors
  * (-1)^j z_j / sqrt(r_j^T z_j)) gives Ritz pairs of the solve's preconditioned
- * operator.  Rayleigh-Ritz for the pencil (A~, D), D = diag(A~), picks the
- * best k directions of a set of vectors for the current system; the caller
- * passes them to amrto_coarse_setup as fields. */
+ * operator.  The caller starts the next solve from the Galerkin projection of
+ * its initial error onto them (amrto_energy_combine), or passes them to
+ * amrto_coarse_setup as fields after Rayleigh-Ritz for the pencil (A~, D),
+ * D = diag(A~), has picked the best k directions for the current system. */
 
 /* Allocate the recording store (m x 3 n_nodes doubles plus Rayleigh-Ritz
  * workspace of 16 x 3 n_nodes) for the uploaded mesh; 2 <= m <= 256.  A new
  * mesh drops it.  Errors: EINVAL, ESTATE (no mesh), ENOMEM, EHIP. */
 int amrto_recycle_setup(amrto_ctx* ctx, int32_t m);
-/* From the last recorded solve: the k (1..16) smallest Ritz values
+/* From the last recorded solve, with the coarse space (if it used one) and
+ * density it ran with still set: the k (1..16) smallest Ritz values
  * (theta_host, may be NULL), their Lanczos residual norms
  * |T[m-1][m] y_{m-1}| = ||A~ u - theta M u||_{M^-1} (resid_host, may be NULL),
  * the Ritz vectors u_i = V y_i into the k device vectors u_host[i] (3 n FP64,
- * M-normalised, zero on supported and hanging DOFs) and the number of Lanczos
- * steps used (*m_used, may be NULL; the solve's iterations + 1 or m, minus
- * one).  Synchronises.  Errors: ESTATE (nothing recorded, or fewer than k + 1
- * steps), EINVAL, EBREAKDOWN (a non-positive recorded coefficient). */
+ * M-normalised, zero on supported and hanging DOFs; the solve's FP64
+ * preconditioner is applied once per vector) and the number of Lanczos steps
+ * used (*m_used, may be NULL: the recorded steps minus one).  Synchronises.
+ * Errors: ESTATE (nothing recorded, or fewer than k + 1 steps), EINVAL,
+ * EBREAKDOWN (a non-positive recorded coefficient). */
 int amrto_recycle_harvest(amrto_ctx* ctx, int32_t k, double* const* u_host, double* theta_host,
                           double* resid_host, int32_t* m_used);
 /* Rayleigh-Ritz: the k smallest pairs of S^T A~ S y = theta S^T D S y over

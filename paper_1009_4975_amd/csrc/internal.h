@@ -199,12 +199,14 @@ struct amrto_ctx {
   size_t gram_cap = 0;
   int coarse_exact_it = 0;      // iteration at which ct, cz were last formed from r
   bool coarse_fresh = false;    // ct, cz were just formed from r (coarse_init)
-  // Krylov recycling (recycle.hip): recorded preconditioned residuals of one
-  // FP64 solve (rec_m x 3n), their coefficients (r.z at 2j, p.q at 2j + 1,
-  // the count of stored vectors at 2 REC_MMAX + 1), combination coefficients,
-  // and the Rayleigh-Ritz workspace (A~ s_j for up to 16 vectors, partials)
+  // Krylov recycling (recycle.hip): recorded residuals of one solve
+  // (rec_m x 3n, FP64), their coefficients (r.z at 2j, p.q at 2j + 1, the
+  // counts of stored vectors and coefficient pairs at 2 REC_MMAX and
+  // 2 REC_MMAX + 1), combination coefficients, and the Rayleigh-Ritz
+  // workspace (A~ s_j for up to 16 vectors, partials)
   int rec_m = 0;
-  bool rec_active = false;      // the running FP64 solve records
+  bool rec_active = false;      // the running solve records
+  bool rec_block3 = false, rec_coarse = false;  // its preconditioner
   double* d_rec_store = nullptr;
   double* d_rec_coef = nullptr;
   double* d_rec_C = nullptr;
@@ -232,8 +234,11 @@ int launch_apply(amrto_ctx* ctx, const void* x, void* y, int prec);
 int launch_diag(amrto_ctx* ctx);
 int build_chunks(amrto_ctx* ctx, const amrto_mesh* m);
 // recycle.hip
-int recycle_begin(amrto_ctx* ctx);
-int recycle_store(amrto_ctx* ctx, const double* z, int j);
+int recycle_begin(amrto_ctx* ctx, bool block3);
+template <typename VT>
+int recycle_store(amrto_ctx* ctx, const VT* r, int it);
+// pcg.hip
+int apply_precond(amrto_ctx* ctx, const double* s, double* u, bool block3, bool coarse);
 // topopt.hip
 int build_cell_map(amrto_ctx* ctx);
 int oc_scratch_attach(amrto_ctx* ctx);

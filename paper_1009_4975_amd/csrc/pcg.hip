@@ -703,8 +703,7 @@ static int cz_threads(const amrto_ctx* ctx) {
 // node blocks; r.z = r^T M1 r + ct^T cz), in the recurrence form of
 // k_cg_update_rec unless built with AMRTO_COARSE_REC=0.
 static bool coarse_fused(const amrto_ctx* ctx) {
-  // a recorded solve keeps z = M^-1 r in memory: the direct form
-  return ctx->coarse_k > 0 && !ctx->uniform && ctx->coarse_affine_only && !ctx->rec_active;
+  return ctx->coarse_k > 0 && !ctx->uniform && ctx->coarse_affine_only;
 }
 
 // with a coarse space: cz = E^-1 Z^T r for the initial residual and either
@@ -860,9 +859,7 @@ static int enqueue_iters(amrto_ctx* ctx, const Vecs<VT>& v, VT* x, int prec, dou
   for (int it = it0; it < it0 + count; ++it) {
     int rc = enqueue_op_pass<VT>(ctx, v, prec, tol2, it, block3);
     if (!rc) rc = enqueue_update<VT>(ctx, v, x, it, block3);
-    if constexpr (std::is_same<VT, double>::value) {
-      if (!rc && ctx->rec_active) rc = recycle_store(ctx, v.z, it + 1);
-    }
+    if (!rc && ctx->rec_active) rc = recycle_store<VT>(ctx, v.r, it);
     if (rc) return rc;
   }
   AMRTO_HIP(hipGetLastError());
@@ -947,6 +944,63 @@ static int pass_times(amrto_ctx* ctx, const double* b, double* x, int prec, bool
   return AMRTO_OK;
 }
 
+// u = M^-1 s with the preconditioner of a solve: M1 = D^-1 (or the inverse
+// node blocks) plus, with a coarse space, Z E^-1 Z^T s (FP64 copies).
+__global__ __launch_bounds__(256) void k_apply_m1(const double* __restrict__ s, double* __restrict__ u,
+                                                  const double* __restrict__ dinv, const double* __restrict__ binv,
+                                                  long n_nodes) {
+  for (long v = blockIdx.x * (long)blockDim.x + threadIdx.x; v < n_nodes; v += (long)gridDim.x * blockDim.x) {
+    const double r0 = s[3 * v], r1 = s[3 * v + 1], r2 = s[3 * v + 2];
+    if (binv) {
+      const double* b = binv + 6 * v;  // (B00, B11, B22, B01, B02, B12)
+      u[3 * v] = b[0] * r0 + b[3] * r1 + b[4] * r2;
+      u[3 * v + 1] = b[3] * r0 + b[1] * r1 + b[5] * r2;
+      u[3 * v + 2] = b[4] * r0 + b[5] * r1 + b[2] * r2;
+    } else {
+      u[3 * v] = dinv[3 * v] * r0;
+      u[3 * v + 1] = dinv[3 * v + 1] * r1;
+      u[3 * v + 2] = dinv[3 * v + 2] * r2;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_add_zcz(double* __restrict__ u, long n, const double* __restrict__ cz_g,
+                                                 CoarseArgs ca) {
+  __shared__ double cz[COARSE_KMAX];
+  const int nf = ca.nf, R = ca.R, k = 3 * nf * R;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) cz[j] = cz_g[j];
+  __syncthreads();
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double fv[COARSE_NFMAX];
+    const int g = coarse_fields(ca, i, n, fv);
+    const int c = (int)(i % 3);
+    double add = 0.0;
+#pragma unroll
+    for (int f = 0; f < COARSE_NFMAX; ++f)
+      if (f < nf) add += fv[f] * cz[(f * R + g) * 3 + c];
+    u[i] += add;
+  }
+}
+
+int apply_precond(amrto_ctx* ctx, const double* s, double* u, bool block3, bool coarse) {
+  const long n3 = 3L * ctx->n_nodes;
+  hipLaunchKernelGGL(k_apply_m1, dim3(grid_for(ctx->n_nodes, 256, 2048)), dim3(256), 0, ctx->stream, s, u,
+                     (const double*)ctx->d_dinv, block3 ? (const double*)ctx->d_binv : nullptr, (long)ctx->n_nodes);
+  if (coarse && ctx->coarse_k > 0) {
+    hipLaunchKernelGGL(k_zt_part<double>, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, coarse_args(ctx), s, n3,
+                       ctx->d_cpart);
+    hipLaunchKernelGGL(k_coarse_sum, dim3(ctx->coarse_k), dim3(256), 0, ctx->stream, ctx->d_cpart, ctx->coarse_k,
+                       RED_BLOCKS, ctx->d_ct, (const double*)nullptr);
+    hipLaunchKernelGGL(k_coarse_cz, dim3(1), dim3(cz_threads(ctx)), 0, ctx->stream, (const double*)ctx->d_ct,
+                       ctx->coarse_k, (const double*)ctx->d_cinv, ctx->d_cz, ctx->d_scal + S_CTZ,
+                       (const double*)nullptr);
+    hipLaunchKernelGGL(k_add_zcz, dim3(grid_for(n3, 256, 2048)), dim3(256), 0, ctx->stream, u, n3,
+                       (const double*)ctx->d_cz, coarse_args(ctx));
+  }
+  AMRTO_HIP(hipGetLastError());
+  return AMRTO_OK;
+}
+
 // Iterations to enqueue before the next host check.  Every check drains the
 // stream (the device idles until the next batch is queued), and every
 // iteration queued past convergence is a pair of launches that return at
@@ -992,8 +1046,8 @@ static int cg_fp64_run(amrto_ctx* ctx, const double* b, double* x, double rtol, 
                      coarse_fused(ctx) ? 1 : 0);
   AMRTO_HIP(hipGetLastError());
   if (ctx->rec_active) {
-    rc = recycle_begin(ctx);
-    if (!rc) rc = recycle_store(ctx, v.z, 0);
+    rc = recycle_begin(ctx, block3);
+    if (!rc) rc = recycle_store<double>(ctx, v.r, -1);
     if (rc) return rc;
   }
   // one reduction per iteration where the recurrences allow it (octree mesh,
@@ -1128,6 +1182,12 @@ static int cg_mixed(amrto_ctx* ctx, const double* b, double* x, int prec, double
                            (const double*)nullptr, v.r, v.z, v.dinv, n3, ctx->d_part);
       }
       coarse_init<float>(ctx, v);
+      if (ctx->rec_active && *updates == 0) {
+        // the first cycle (up to the first reliable update) is one Krylov space
+        rc = recycle_begin(ctx, block3);
+        if (!rc) rc = recycle_store<float>(ctx, v.r, -1);
+        if (rc) return rc;
+      }
       // the recurrence measures its residual against b.b
       hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, ctx->stream, ctx->d_scal, (int)S_BB, bb);
       if (*updates == 0) {
@@ -1169,6 +1229,7 @@ static int cg_mixed(amrto_ctx* ctx, const double* b, double* x, int prec, double
       }
     }
     if (done == 1.0 || it >= max_it || stagnant) {
+      ctx->rec_active = false;  // a reliable update ends the recorded cycle
       rr_rec_best = 1e300;
       since_gain = 0;
       // reliable update: x64 += d, true residual in FP64
@@ -1236,18 +1297,15 @@ int amrto_pcg(amrto_ctx* ctx, const double* b, double* u, const amrto_solve_opts
   if (block3 && o.use_coarse && ctx->coarse_k > 0 && !coarse_fused(ctx))
     return ctx->fail(AMRTO_EINVAL,
                      "amrto_pcg: block-Jacobi with a coarse space needs an octree mesh and the affine space");
-  if (o.record) {
-    if (ctx->rec_m <= 0) return ctx->fail(AMRTO_ESTATE, "amrto_pcg: record needs amrto_recycle_setup");
-    if (o.inner_prec != AMRTO_FP64) return ctx->fail(AMRTO_EINVAL, "amrto_pcg: record needs an FP64 solve");
-    if (block3 && o.use_coarse && ctx->coarse_k > 0)
-      return ctx->fail(AMRTO_EINVAL, "amrto_pcg: record with block-Jacobi needs no coarse space");
-  }
+  if (o.record && ctx->rec_m <= 0) return ctx->fail(AMRTO_ESTATE, "amrto_pcg: record needs amrto_recycle_setup");
+  if (o.record && o.single_reduction) return ctx->fail(AMRTO_EINVAL, "amrto_pcg: record needs the two-pass form");
   AMRTO_HIP(hipSetDevice(ctx->device));
   struct RecOff {
     amrto_ctx* c;
     ~RecOff() { c->rec_active = false; }
   } rec_guard{ctx};
   ctx->rec_active = o.record != 0;
+  if (o.record) ctx->rec_coarse = o.use_coarse && ctx->coarse_k > 0;
   // the solve loops read the coarse space from the context
   struct CoarseOff {
     amrto_ctx* c; int k;

@@ -2,14 +2,17 @@
 // Sec. 5: an approximate invariant subspace for the smallest eigenvalues is
 // taken from one solve's Krylov space and carried to the next system).
 //
-// A recorded FP64 PCG solve keeps its first m preconditioned residuals z_j
-// and the products r_j^T z_j, p_j^T A~ p_j.  Those coefficients give the
+// A recorded PCG solve keeps its first m residuals r_j and the products
+// r_j^T z_j, p_j^T A~ p_j (z_j = M^-1 r_j); it runs its usual kernels, the
+// recording adds one copy per iteration.  Those coefficients give the
 // Lanczos matrix T of the preconditioned operator (the CG/Lanczos
 // correspondence; Lanczos vectors v_j = (-1)^j z_j / sqrt(r_j^T z_j)), whose
-// smallest eigenpairs give Ritz vectors u = V y.  Before the next solve the
-// carried vectors and the new Ritz vectors are combined by Rayleigh-Ritz for
-// the pencil (A~, D) of the new system (D = diag A~), and the k best enter
-// the coarse space of the two-level preconditioner.
+// smallest eigenpairs give Ritz vectors u = V y = M^-1 (sum_j c_j r_j): one
+// preconditioner application per Ritz vector.  Before the next solve the
+// Ritz vectors start it (the initial error's Galerkin projection onto them,
+// amrto_energy_combine) or, combined with carried vectors by Rayleigh-Ritz
+// for the pencil (A~, D) of the new system (D = diag A~), enter the coarse
+// space of the two-level preconditioner.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -37,26 +40,31 @@ __device__ __forceinline__ const double* vs_get(const VecSet& s, int j) {
   return s.base ? s.base + (long)j * s.stride : s.p[j];
 }
 
-// Record z_j into slot j, with rz_j from the r.z partials of the pass that
-// formed z_j and (j > 0) pq_{j-1} from the p.q partials of iteration j - 1.
+// After the update pass of CG iteration it (it = -1: after the start),
+// store r_{it+1} into slot it + 1 and, for it >= 0, the pair (r_it^T z_it,
+// p_it^T A~ p_it): r.z from the scalar slot the operator pass of iteration
+// it wrote (its coarse part included), p.q from that pass's partials.
 // Nothing is stored once the solve has stopped (its flag raised).
-__global__ __launch_bounds__(256) void k_rec_store(const double* __restrict__ z, double* __restrict__ slot, long n3,
-                                                   const double* __restrict__ part_rz,
+template <typename VT>
+__global__ __launch_bounds__(256) void k_rec_store(const VT* __restrict__ r, double* __restrict__ slot, long n3,
                                                    const double* __restrict__ part_pq, int n_pq,
                                                    const double* __restrict__ scal, double* __restrict__ coef,
-                                                   int j) {
+                                                   int it) {
   if (scal[S_DONE] != 0.0) return;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n3; i += (long)gridDim.x * blockDim.x)
-    slot[i] = z[i];
+  if (slot)
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n3; i += (long)gridDim.x * blockDim.x)
+      slot[i] = (double)r[i];
   if (blockIdx.x == 0) {
     __shared__ double sh[8];
-    const double rz = sum_partials(part_rz, RED_BLOCKS, sh);
     double pq = 0.0;
-    if (j > 0) pq = sum_partials(part_pq, n_pq, sh);
+    if (it >= 0) pq = sum_partials(part_pq, n_pq, sh);
     if (threadIdx.x == 0) {
-      coef[2 * j] = rz;
-      if (j > 0) coef[2 * j - 1] = pq;
-      coef[2 * REC_MMAX + 1] = (double)(j + 1);  // vectors stored
+      if (it >= 0) {
+        coef[2 * it] = scal[S_RZ0 + (it & 1)];
+        coef[2 * it + 1] = pq;
+        coef[2 * REC_MMAX + 1] = (double)(it + 1);  // coefficient pairs
+      }
+      if (slot) coef[2 * REC_MMAX] = (double)(it + 2);  // stored vectors
     }
   }
 }
@@ -226,22 +234,27 @@ static void jacobi_eig(int n, std::vector<double>& A, std::vector<double>& w, st
 }
 
 // ------------------------------------------------------------------ recording (called by the solve)
-int recycle_store(amrto_ctx* ctx, const double* z, int j) {
-  if (!ctx->rec_active || j >= ctx->rec_m) return AMRTO_OK;
+template <typename VT>
+int recycle_store(amrto_ctx* ctx, const VT* r, int it) {
+  if (!ctx->rec_active || it >= ctx->rec_m) return AMRTO_OK;
   const long n3 = 3L * ctx->n_nodes;
-  hipLaunchKernelGGL(k_rec_store, dim3(grid_for(n3, 256, 1024)), dim3(256), 0, ctx->stream, z,
-                     ctx->d_rec_store + (long)j * n3, n3, (const double*)ctx->d_part, (const double*)ctx->d_partpq,
-                     ctx->n_partpq, (const double*)ctx->d_scal, ctx->d_rec_coef, j);
+  double* slot = it + 1 < ctx->rec_m ? ctx->d_rec_store + (long)(it + 1) * n3 : nullptr;
+  hipLaunchKernelGGL(k_rec_store<VT>, dim3(slot ? grid_for(n3, 256, 1024) : 1), dim3(256), 0, ctx->stream, r, slot,
+                     n3, (const double*)ctx->d_partpq, ctx->n_partpq, (const double*)ctx->d_scal, ctx->d_rec_coef,
+                     it);
   AMRTO_HIP(hipGetLastError());
   return AMRTO_OK;
 }
+template int recycle_store<double>(amrto_ctx*, const double*, int);
+template int recycle_store<float>(amrto_ctx*, const float*, int);
 
 __global__ void k_zero(double* __restrict__ x, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = 0.0;
 }
 
-int recycle_begin(amrto_ctx* ctx) {
+int recycle_begin(amrto_ctx* ctx, bool block3) {
   if (!ctx->rec_active) return AMRTO_OK;
+  ctx->rec_block3 = block3;
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, ctx->stream, ctx->d_rec_coef, 2 * REC_MMAX + 2);
   AMRTO_HIP(hipGetLastError());
   return AMRTO_OK;
@@ -302,8 +315,8 @@ int amrto_recycle_harvest(amrto_ctx* ctx, int32_t k, double* const* u_host, doub
   AMRTO_HIP(hipMemcpyAsync(coef.data(), ctx->d_rec_coef, coef.size() * sizeof(double), hipMemcpyDeviceToHost,
                            ctx->stream));
   AMRTO_HIP(hipStreamSynchronize(ctx->stream));
-  const int stored = (int)coef[2 * REC_MMAX + 1];
-  const int m = stored - 1;  // Lanczos steps with known alpha
+  const int nvec = (int)coef[2 * REC_MMAX], npair = (int)coef[2 * REC_MMAX + 1];
+  const int m = std::min(npair - 1, nvec);  // Lanczos steps with known alpha, beta and the next r.z
   if (m < k) return ctx->fail(AMRTO_ESTATE, "amrto_recycle_harvest: the recorded solve is shorter than k + 1 steps");
   std::vector<double> rz(m + 1), pq(m);
   for (int j = 0; j <= m; ++j) rz[j] = coef[2 * j];
@@ -334,7 +347,13 @@ int amrto_recycle_harvest(amrto_ctx* ctx, int32_t k, double* const* u_host, doub
   src.base = ctx->d_rec_store;
   src.stride = 3L * ctx->n_nodes;
   if ((long)m * k > COMB_MAX) return ctx->fail(AMRTO_EINVAL, "amrto_recycle_harvest: m k above 4096");
-  int rc = combine(ctx, src, m, C, k, u_host);
+  // u_i = M^-1 (sum_j c_ij r_j): the stored residuals are combined first, the
+  // recorded solve's preconditioner is applied once per Ritz vector
+  const long n3 = 3L * ctx->n_nodes;
+  double* tmp[RR_NMAX];
+  for (int i = 0; i < k; ++i) tmp[i] = ctx->d_rr_aw + i * n3;
+  int rc = combine(ctx, src, m, C, k, tmp);
+  for (int i = 0; i < k && !rc; ++i) rc = apply_precond(ctx, tmp[i], u_host[i], ctx->rec_block3, ctx->rec_coarse);
   if (rc) return rc;
   AMRTO_HIP(hipStreamSynchronize(ctx->stream));
   return AMRTO_OK;

@@ -53,9 +53,14 @@ class AdaptiveSIMP:
                                                                     max_steps=20), **p_continuation)
         self.p = float(self.p_cont["p0"] if self.p_cont else p)
         self.steps_at_p = 0
-        # Krylov recycling: dict(m=64, k=4, keep=4, regions=(3, 2, 2), affine=True) or None
-        self.recycle = None if recycle is None else dict(dict(m=64, k=4, keep=4, regions=(3, 2, 2), affine=True),
-                                                         **recycle)
+        # Krylov recycling, or None.  mode "init": each solve starts from the
+        # Galerkin projection of its initial error onto the Ritz vectors of
+        # the previous solve (k of them, from its first m residuals); mode
+        # "coarse": Rayleigh-Ritz keeps the best `keep` of the carried and new
+        # Ritz vectors, which join the affine fields (optional) of the coarse
+        # space on `regions`
+        self.recycle = None if recycle is None else dict(dict(mode="init", m=64, k=4, keep=4, regions=(3, 2, 2),
+                                                              affine=True), **recycle)
         self.rec_vecs = []  # carried vectors (kept Rayleigh-Ritz vectors, then the last harvest)
         self.it = 0
         self.compliance = None
@@ -172,11 +177,27 @@ class AdaptiveSIMP:
             self.log_metrics(rec)
         return rec
 
+    def _recycle_start(self):
+        """Mode "init": u = the warm start plus the combination of the carried
+        Ritz vectors minimising the energy (the initial error's Galerkin
+        projection onto their span)."""
+        if not self.rec_vecs:
+            return
+        x0 = torch.empty_like(self.u)
+        try:
+            self.ctx.energy_combine(self.b, self.rec_vecs, x0, base=self.u)
+        except binding.AmrtoError:
+            return  # a carried vector is not finite: start from the warm start alone
+        self.u.copy_(x0)
+
     def _recycle_coarse(self):
         """Coarse space of this solve: the affine fields (optional) and the
         best `keep` directions, by Rayleigh-Ritz for the current system, of
         the carried vectors."""
         rc = self.recycle
+        if rc["mode"] == "init":
+            self._recycle_start()
+            return
         W = []
         if self.rec_vecs:
             keep = min(rc["keep"], len(self.rec_vecs))
@@ -190,14 +211,18 @@ class AdaptiveSIMP:
         self.rec_vecs = W
 
     def _recycle_harvest(self):
-        """Ritz vectors of the recorded solve join the kept vectors."""
+        """Ritz vectors of the recorded solve: the next start's vectors (mode
+        "init") or joined to the kept vectors (mode "coarse")."""
         U = [torch.empty_like(self.u) for _ in range(self.recycle["k"])]
         try:
             self.ctx.recycle_harvest(U)
         except binding.AmrtoError:
             U = []  # the solve was too short to harvest k vectors
-        self.rec_vecs = self.rec_vecs + U
-        self.ctx.coarse_clear()
+        if self.recycle["mode"] == "init":
+            self.rec_vecs = U
+        else:
+            self.rec_vecs = self.rec_vecs + U
+            self.ctx.coarse_clear()
 
     def log_metrics(self, rec):
         """Append one JSON line: the step record, the volume fraction of the
