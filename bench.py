@@ -78,6 +78,15 @@ def measured_traffic(path=TRAFFIC_FILE, sources=APPLY_SOURCES):
         return None
 
 
+def copy_calibration(torch):
+    """A plain device copy of 256 MiB (reads and writes 268,435,456 bytes
+    each): the known traffic that scales FETCH_SIZE and WRITE_SIZE."""
+    a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+    ms_c = event_time(torch, lambda: c.copy_(a), 10)
+    log(f"[bench] copy 256 MiB: {ms_c * 1e3:.1f} us ({2 * a.numel() * 8 / ms_c / 1e6:.0f} GB/s)")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -155,6 +164,7 @@ def main():
     dev = lambda a, dt=torch.float64: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
     if args.c3_only:
         print(json.dumps(apply_uniform_bandwidth(torch, binding, synth, dev)), flush=True)
+        copy_calibration(torch)
         return
     if args.amr_vs_uniform_only:
         print(json.dumps(amr_vs_uniform(torch, binding, synth)), flush=True)
@@ -191,11 +201,7 @@ def main():
         op_us, up_us = pass_times(ctx, binding, b, u, name, tuple(int(r) for r in args.regions.split(",")), 50)
         log(f"[bench] C2 {name} operator pass {op_us:.2f} us, update {up_us:.2f} us per launch")
         log(f"[bench] pass source hash {source_hash(PASS_SOURCES)}")
-        # calibration: a plain device copy of 256 MiB (reads and writes 268,435,456 bytes each)
-        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
-        c = torch.empty_like(a)
-        ms_c = event_time(torch, lambda: c.copy_(a), 10)
-        log(f"[bench] copy 256 MiB: {ms_c * 1e3:.1f} us ({2 * a.numel() * 8 / ms_c / 1e6:.0f} GB/s)")
+        copy_calibration(torch)
         log(f"[bench] apply source hash {apply_source_hash()}")
         return
 

@@ -9,8 +9,9 @@
 //  * uniform brick: implicit connectivity, workgroups march upwards through
 //    a range of node layers of a block of node columns.  FP64 and FP32: one
 //    thread per node column, output rows summed in registers (z), across
-//    lanes (x) and through LDS (y), no atomics (k_apply_brick).  BF16: one
-//    16-element MFMA tile per wave row, rows accumulated in LDS
+//    lanes (x) and through LDS (y), no atomics (k_apply_brick).  BF16: rows
+//    of 16 elements per MFMA tile, element outputs through LDS to the thread
+//    owning each node column, summed in fixed order, no atomics
 //    (k_apply_uniform_bf16).
 //  * octree: node-owner chunks (chunks.hip).  A chunk stages its node table
 //    (vertices plus masters of hanging vertices) in LDS, interpolates hanging
@@ -31,7 +32,6 @@
 namespace amrto {
 
 constexpr int P_F64 = 0, P_F32 = 1, P_BF16 = 2;
-constexpr int NBUF = 4;                            // LDS node-layer buffers (uniform path)
 constexpr int LSLOTS = (UN * UN * 3 + 255) / 256;  // load slots per thread
 
 struct UArgs {
@@ -61,16 +61,25 @@ struct UArgs {
 };
 
 // ------------------------------------------------------------------ uniform brick, BF16 on the matrix cores
-// One 16-element MFMA tile per wave row; a workgroup covers UE x UE element
-// columns around UT x UT owned node columns and marches upwards.  Node layers
-// rotate through four LDS buffers and are fetched three layers ahead; output
-// rows accumulate in FP64 LDS (ds_add_f64 runs at full rate on gfx950, FP32
-// LDS atomics were measured to stall the waves on LDS issue).
+// Node-owner form, no atomics.  A workgroup covers UE x UE element columns
+// around UT x UT owned node columns and marches upwards through a range of
+// node layers.  Per element layer each wave contracts four rows of 16
+// elements, one v_mfma_f32_16x16x32_bf16 tile per row (lane n + 16 q holds
+// DOFs 8q..8q+7 of element n; the element mean per component, summed across
+// the four lanes of an element, is removed before the hi + lo split), and
+// writes the element outputs scaled by c_e to LDS.  After a barrier the thread
+// owning a node column adds, in fixed order, the bottom-face rows of the four
+// elements of this layer around its node and the top-face rows of the layer
+// below (carried in registers).  Node layers rotate through three LDS
+// buffers and are fetched two layers ahead.
 template <bool FUSED>
-__global__ __launch_bounds__(256, 4) void k_apply_uniform_bf16(UArgs a, CgArgs cg) {
+__global__ __launch_bounds__(256, FUSED ? 3 : 4) void k_apply_uniform_bf16(UArgs a, CgArgs cg) {
   using VT = float;
-  __shared__ VT xs[NBUF][UN * UN * 3];
-  __shared__ double ys[3][UT * UT * 3];
+  constexpr int NL = UN * UN * 3;  // values of one staged node layer
+  constexpr int YS = 25;           // LDS stride of one element's 24 outputs (padded)
+  __shared__ VT xs[3][NL];
+  __shared__ VT cs[3][UE * UE];  // element coefficients of the staged layers
+  __shared__ VT yel[UE * UE * YS + 256 * 4];  // + a slot per thread for the padding rows 24..31
   __shared__ double sh[16];
   double beta = 0.0;
   if (FUSED) {
@@ -99,142 +108,244 @@ __global__ __launch_bounds__(256, 4) void k_apply_uniform_bf16(UArgs a, CgArgs c
   const int z0 = tz * a.zchunk;
   const int z1 = min(z0 + a.zchunk, nz + 1);
   const int sx = nx + 1;
-  const long sxy3 = 3L * (nx + 1) * (ny + 1);
+  const long sxy = (long)(nx + 1) * (ny + 1);
   const VT vbeta = (VT)beta;
   const bool first = FUSED && cg.it == 0;
 
-  // load slot s of this thread: LDS index tid + 256 s of a (UN x UN x 3) layer
-  int gxy[LSLOTS], own[LSLOTS];
+  // load slot s of this thread: value tid + 256 s of a staged (UN x UN x 3)
+  // layer; addresses of slots outside the mesh are clamped to 0 and their
+  // values dropped when staged
+  int gnode[LSLOTS];
   uint32_t inside = 0;
 #pragma unroll
   for (int s = 0; s < LSLOTS; ++s) {
     const int idx = tid + 256 * s;
-    const int c = idx % 3, nd = idx / 3;
+    const int nd = idx / 3;
     const int li = nd % UN, lj = nd / UN;
     const int gx = ox - 1 + li, gy = oy - 1 + lj;
-    const bool in = idx < UN * UN * 3 && gx >= 0 && gx <= nx && gy >= 0 && gy <= ny;
+    const bool in = idx < NL && gx >= 0 && gx <= nx && gy >= 0 && gy <= ny;
     inside |= (uint32_t)in << s;
-    gxy[s] = 3 * (gx + sx * gy) + c;
-    own[s] = (in && li >= 1 && li <= UT && lj >= 1 && lj <= UT) ? ((lj - 1) * UT + li - 1) * 3 + c : -1;
+    gnode[s] = in ? gx + sx * gy : 0;
   }
-  // support bits of the last four staged layers, 4 bits per layer (one per
-  // slot), so the store phase needs no dependent global read
-  uint32_t fring = 0;
-  // a layer in flight, masked (and beta-updated) at load time
+  // the node column this thread owns (threads 0 .. UT^2 - 1)
+  const int oli = 1 + tid % UT, olj = 1 + tid / UT;
+  const int ogx = ox - 1 + oli, ogy = oy - 1 + olj;
+  const bool own = tid < UT * UT && ogx <= nx && ogy <= ny;
+  const int onode = own ? ogx + sx * ogy : 0;
+  // this lane's element in tile r: local (n, 4 wave + r); its DOF group q
+  const int lane = tid & 63, wave = tid >> 6;
+  const int n = lane & 15, q = lane >> 4;
+
+  // this thread's element column for the coefficient loads: local (tid % UE, tid / UE)
+  const int cex = ox - 1 + (tid % UE), cey = oy - 1 + tid / UE;
+  const bool cev = cex >= 0 && cex < nx && cey >= 0 && cey < ny;
+  const int cid = cev ? cex + nx * cey : 0;
+  const long nxy = (long)nx * ny;
+
   struct Slot {
     VT x[LSLOTS];
-    uint32_t fb;
+    VT po[FUSED ? LSLOTS : 1];
+    uint8_t f[LSLOTS];
+    uint8_t fo;  // support bits of the owned node
+    VT ce;       // coefficient of this thread's element column
   };
+  // per-lane offsets within a layer are 32-bit (3 n_nodes < 2^31 is checked
+  // at upload), per-layer offsets uniform
+  int xoff[LSLOTS];
+#pragma unroll
+  for (int s = 0; s < LSLOTS; ++s) xoff[s] = 3 * gnode[s] + (tid + 256 * s) % 3;
   auto load = [&](Slot& R, int k) {
-    R.fb = 0;
+    const long kk = min(k, nz);
+    const VT* __restrict__ Xl = X + 3 * sxy * kk;
+    const VT* __restrict__ Pl = PO + 3 * sxy * kk;
+    const uint8_t* __restrict__ Fl = fix + sxy * kk;
 #pragma unroll
     for (int s = 0; s < LSLOTS; ++s) {
-      R.x[s] = 0;
-      if ((inside >> s) & 1) {
-        const long g = gxy[s] + sxy3 * k;
-        const uint8_t f = fix[g / 3];
-        VT xv = X[g];
-        if (FUSED && !first) xv += vbeta * PO[g];
-        const bool fx = (f >> ((tid + 256 * s) % 3)) & 1;
-        R.fb |= (uint32_t)fx << s;
-        R.x[s] = fx ? (VT)0 : xv;
-      }
+      R.f[s] = Fl[gnode[s]];
+      R.x[s] = Xl[xoff[s]];
+      if (FUSED) R.po[s] = Pl[xoff[s]];
     }
+    R.fo = Fl[onode];
+    R.ce = (coef + nxy * min(k, nz - 1))[cid];
   };
+  // stage layer k into ring slot k % 3: masked values (fused: p = z + beta
+  // p_old, masked), the owned node's support bits and the coefficients of
+  // element layer k (zero outside the mesh)
+  uint32_t fring = 0;  // owned node support bits, 3 per ring slot
   auto stage = [&](const Slot& R, int k) {
+    const bool lay = k <= nz;
 #pragma unroll
     for (int s = 0; s < LSLOTS; ++s) {
       const int idx = tid + 256 * s;
-      if (idx < UN * UN * 3) xs[k % NBUF][idx] = R.x[s];
-    }
-    const int sh4 = 4 * (k % NBUF);
-    fring = (fring & ~(0xfu << sh4)) | (R.fb << sh4);
-  };
-  double dot = 0.0;
-  auto store = [&](int k) {
-#pragma unroll
-    for (int s = 0; s < LSLOTS; ++s) {
-      if (own[s] < 0) continue;
-      const long g = gxy[s] + sxy3 * k;
-      const VT acc = (VT)ys[k % 3][own[s]];
-      ys[k % 3][own[s]] = 0.0;
-      const bool fixed = (fring >> (4 * (k % NBUF) + s)) & 1;
-      if (FUSED) {
-        const VT pn = xs[k % NBUF][tid + 256 * s];
-        const VT q = fixed ? (VT)0 : acc;
-        PN[g] = pn;
-        Y[g] = q;
-        dot += (double)pn * (double)q;
-      } else {
-        Y[g] = fixed ? X[g] : acc;
+      if (idx < NL) {
+        const bool in = ((inside >> s) & 1) && lay;
+        VT v = in ? R.x[s] : (VT)0;
+        if (FUSED && !first) v += vbeta * (in ? R.po[s] : (VT)0);
+        const bool fx = in && ((R.f[s] >> (idx % 3)) & 1);
+        xs[k % 3][idx] = fx ? (VT)0 : v;
       }
     }
+    const uint32_t ff = (own && lay) ? (uint32_t)(R.fo & 7) : 0u;
+    fring = (fring & ~(7u << (3 * (k % 3)))) | (ff << (3 * (k % 3)));
+    cs[k % 3][tid] = (cev && k < nz) ? R.ce : (VT)0;
   };
 
-  for (int idx = tid; idx < UT * UT * 3; idx += 256) { ys[0][idx] = 0; ys[1][idx] = 0; ys[2][idx] = 0; }
   const int kbeg = max(z0 - 1, 0);
   const int kend = min(z1 - 1, nz - 1);
-  Slot Ra, Rb;
-  load(Ra, kbeg);
-  stage(Ra, kbeg);
-  load(Ra, kbeg + 1);
-  stage(Ra, kbeg + 1);
-  if (kbeg + 2 <= nz) load(Ra, kbeg + 2);
-
-  const int lane = tid & 63, wave = tid >> 6;
-  const int n16 = lane & 15, q4 = lane >> 4;
   bf16x8 ka[2][2];
   load_k0_bf16((const uint16_t*)a.kb, ka);
+  Slot S0, S1;
+  load(S0, kbeg);
+  stage(S0, kbeg);
+  load(S0, kbeg + 1);
+  stage(S0, kbeg + 1);
+  load(S0, kbeg + 2);
   __syncthreads();
 
-  // one layer: request layer k + 3 into Rfly, contract elements of layer k,
-  // stage layer k + 2 from Rnext, barrier, write the finished node layer k
-  auto layer_step = [&](int k, Slot& Rnext, Slot& Rfly) {
-    if (k + 3 <= nz) load(Rfly, k + 3);
-    const VT* bot = xs[k % NBUF];
-    const VT* top = xs[(k + 1) % NBUF];
-#pragma unroll 1
-    for (int row = 0; row < 4; ++row) {
-      const int jj = 4 * wave + row, ii = n16;
-      const int ex = ox - 1 + ii, ey = oy - 1 + jj;
-      const bool ev = ex >= 0 && ex < nx && ey >= 0 && ey < ny;
-      const float ce = ev ? (float)coef[ex + (long)nx * (ey + (long)ny * k)] : 0.f;
-      float u[24];
+  VT carry[3] = {0, 0, 0};
+  double dot = 0.0;
+  // the DOFs this lane's group holds: d = 8 q + i (q = 3: padding, zeros);
+  // DOF d is component (c0 + i) mod 3 with c0 = 2q mod 3, so the lane keeps
+  // its per-component sums rotated by c0 (compile-time register indices)
+  const int c0 = (2 * q) % 3;
+  const float qv = q < 3 ? 1.f : 0.f;
+  int loff[8];     // LDS offset of DOF i within a staged layer pair (element at the tile origin)
+  bool ltop[8];    // DOF i lies on the element's top face
 #pragma unroll
-      for (int aa = 0; aa < 8; ++aa) {
-        const VT* src = (aa >> 2) ? top : bot;
-        const int l = ((jj + ((aa >> 1) & 1)) * UN + ii + (aa & 1)) * 3;
-        u[3 * aa + 0] = src[l + 0];
-        u[3 * aa + 1] = src[l + 1];
-        u[3 * aa + 2] = src[l + 2];
+  for (int i = 0; i < 8; ++i) {
+    // padding lanes (q = 3) read the addresses of q = 2 (an LDS broadcast,
+    // no extra bank cycles) and scale the values by zero
+    const int d = 8 * min(q, 2) + i;
+    const int aa = d / 3, c = d % 3;
+    ltop[i] = (aa >> 2) != 0;
+    loff[i] = (((aa >> 1) & 1) * UN + n + (aa & 1)) * 3 + c;
+  }
+  // element layer k: contract, finish node layer k, stage layer k + 2
+  auto step = [&](int k, Slot& Rst, Slot& Rld) {
+    if (k + 3 <= nz) load(Rld, k + 3);
+    const VT* bot = xs[k % 3];
+    const VT* top = xs[(k + 1) % 3];
+#pragma unroll 2
+    for (int r = 0; r < 4; ++r) {
+      const int jj = 4 * wave + r;
+      float u[8];
+      float t3[3] = {0.f, 0.f, 0.f};  // t3[j]: component (c0 + j) mod 3
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const float v = (ltop[i] ? top : bot)[jj * UN * 3 + loff[i]] * qv;
+        u[i] = v;
+        t3[i % 3] += v;
       }
-      f32x4 d0, d1;
-      mfma_tile_bf16(ka, u, q4, d0, d1);
-      if (ev) {
+      // back to component order (the lane groups rotate differently), then
+      // summed over the element's four lanes
+      float s3[3];
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
+      for (int c = 0; c < 3; ++c) {
+        const int j = (c - c0 + 3) % 3;
+        s3[c] = j == 0 ? t3[0] : (j == 1 ? t3[1] : t3[2]);
+      }
+      float m3[3];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int R = 16 * t + 4 * q4 + r;
-            if (R < 24) {
-              const int aa = R / 3, c = R % 3;
-              const int li = ii + (aa & 1) - 1, lj = jj + ((aa >> 1) & 1) - 1;
-              const int layer = k + (aa >> 2);
-              if (li >= 0 && li < UT && lj >= 0 && lj < UT && layer >= z0 && layer < z1)
-                atomicAdd(&ys[layer % 3][(lj * UT + li) * 3 + c], (double)(ce * (t ? d1[r] : d0[r])));
-            }
-          }
+      for (int c = 0; c < 3; ++c) {
+        float t = s3[c] + __shfl_xor(s3[c], 16, 64);
+        t += __shfl_xor(t, 32, 64);
+        m3[c] = 0.125f * t;
+      }
+      float mr[3];  // mr[j] = mean of component (c0 + j) mod 3
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int c = (c0 + j) % 3;
+        mr[j] = c == 0 ? m3[0] : (c == 1 ? m3[1] : m3[2]);
+      }
+      bf16x8 bh, bl;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const float v = (u[i] - mr[i % 3]) * qv;
+        const __bf16 h = (__bf16)v;
+        bh[i] = h;
+        bl[i] = (__bf16)(v - (float)h);
+      }
+      // the two row tiles' accumulation chains interleaved
+      const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+      f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[0][0], bh, z, 0, 0, 0);
+      f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[1][0], bh, z, 0, 0, 0);
+      d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[0][1], bh, d0, 0, 0, 0);
+      d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[1][1], bh, d1, 0, 0, 0);
+      d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[0][0], bl, d0, 0, 0, 0);
+      d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[1][0], bl, d1, 0, 0, 0);
+      const float ce = cs[k % 3][jj * UE + n];
+      VT* ye = yel + (jj * UE + n) * YS;
+      VT* ye1 = q < 2 ? ye + 16 + 4 * q : yel + UE * UE * YS + 4 * tid;  // rows 24..31: the thread's spare slot
+#pragma unroll
+      for (int r4 = 0; r4 < 4; ++r4) {
+        ye[4 * q + r4] = ce * d0[r4];
+        ye1[r4] = ce * d1[r4];
       }
     }
-    if (k + 2 <= nz) stage(Rnext, k + 2);
     __syncthreads();
-    if (k >= z0) store(k);
+    // node layer k: carried top rows of element layer k - 1 plus the bottom
+    // rows of element layer k, four elements in fixed order
+    if (own) {
+      VT yb[3] = {0, 0, 0}, yt[3] = {0, 0, 0};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int ii = oli - 1 + (e & 1), jj = olj - 1 + (e >> 1);
+        const int av = (oli - ii) + 2 * (olj - jj);
+        const VT* ye = yel + (jj * UE + ii) * YS;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          yb[c] += ye[3 * av + c];
+          yt[c] += ye[3 * (av + 4) + c];
+        }
+      }
+      if (k >= z0) {
+        const long g = 3 * (sxy * k + onode);
+        const uint32_t fx = (fring >> (3 * (k % 3))) & 7u;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const VT acc = carry[c] + yb[c];
+          const bool fc = (fx >> c) & 1;
+          if (FUSED) {
+            const VT pn = xs[k % 3][(olj * UN + oli) * 3 + c];
+            const VT qv = fc ? (VT)0 : acc;
+            PN[g + c] = pn;
+            Y[g + c] = qv;
+            dot += (double)pn * (double)qv;
+          } else {
+            Y[g + c] = fc ? X[g + c] : acc;
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) carry[c] = yt[c];
+    }
+    if (k + 2 <= nz) stage(Rst, k + 2);
+    __syncthreads();
   };
-  for (int k = kbeg; k <= kend; ++k) {
-    layer_step(k, Ra, Rb);
-    Ra = Rb;
+  // S0 holds layer kbeg + 2 (staged at step kbeg); steps alternate the two slots
+  for (int k = kbeg; k <= kend; k += 2) {
+    step(k, S0, S1);
+    if (k + 1 <= kend) step(k + 1, S1, S0);
   }
-  if (kend + 1 < z1 && kend + 1 >= z0) store(kend + 1);
+  // the top node layer of the mesh: only the elements below contribute
+  if (own && kend + 1 < z1) {
+    const int k = kend + 1;
+    const long g = 3 * (sxy * k + onode);
+    const uint32_t fx = (fring >> (3 * (k % 3))) & 7u;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const bool fc = (fx >> c) & 1;
+      if (FUSED) {
+        const VT pn = xs[k % 3][(olj * UN + oli) * 3 + c];
+        const VT qv = fc ? (VT)0 : carry[c];
+        PN[g + c] = pn;
+        Y[g + c] = qv;
+        dot += (double)pn * (double)qv;
+      } else {
+        Y[g + c] = fc ? X[g + c] : carry[c];
+      }
+    }
+  }
   if (FUSED) {
     dot = block_sum(dot, sh);
     if (tid == 0) cg.part_out[cg.part_base + blockIdx.x] = dot;
@@ -498,7 +609,7 @@ constexpr int chunk_threads(int prec, int coarse) { return (coarse && prec == P_
 template <typename VT, int PREC, bool FUSED, int COARSE = 0>
 __global__ __launch_bounds__(chunk_threads(PREC, COARSE)) void k_apply_chunks(UArgs a, ChunkArgs ca, BrickK<VT> kc, CgArgs cg) {
   __shared__ VT xs[TAB_MAX * 3];
-  __shared__ double ys[TAB_MAX * 3];  // FP64 LDS accumulators (see k_apply_uniform_bf16)
+  __shared__ double ys[TAB_MAX * 3];  // FP64 LDS accumulators (ds_add_f64 runs at full rate on gfx950)
   __shared__ uint16_t lsm[PREC == P_BF16 ? ENT_MAX * 8 : 1];
   __shared__ double sh[16];
   __shared__ uint32_t trip_hm_s[TRIP_MAX];
