@@ -105,8 +105,8 @@ __global__ __launch_bounds__(256) void k_sensitivity(
 //   DENSITY:     sum W in_d / sum W
 // Neither kernel reads a neighbour table: the uniform one walks the box of
 // offsets |d_a| <= R with H from a per-block table indexed by |d|^2, the
-// octree one walks the finest-lattice cells around the element and takes each
-// leaf at its anchor cell.  Nothing is built or allocated per call, and the
+// octree one probes, per leaf size, the aligned anchors a neighbour of that
+// size can have and takes each leaf at its anchor cell.  Nothing is built or allocated per call, and the
 // summation order is fixed (z, y, x of the offsets or anchors).
 constexpr int FILT_RMAX = 16;                       // largest rmin accepted
 constexpr int FILT_D2MAX = 3 * FILT_RMAX * FILT_RMAX;  // largest |d|^2 in the box
@@ -144,9 +144,10 @@ __global__ __launch_bounds__(256) void k_filter_uniform(
 
 // Octree: desc[e] = (anchor x, y, z, edge h) on the finest lattice; cmap[c] =
 // the leaf covering lattice cell c, with bit 31 set on the leaf's anchor
-// (lowest) cell.  A neighbour d satisfies |2 a_d + h_d - (2 a_e + h_e)| <
-// 2 rmin per axis with 1 <= h_d <= hmax, which bounds its anchor; every leaf
-// in that box is counted once, at its anchor cell.
+// (lowest) cell.  A neighbour d of edge h_d satisfies |2 a_d + h_d - (2 a_e +
+// h_e)| < 2 rmin per axis, and its anchor a_d is a multiple of h_d: per edge
+// size, the few aligned candidate anchors are probed, and a cell counts only
+// if it is the anchor of a leaf of that size (every leaf once).
 __global__ __launch_bounds__(256) void k_filter_octree(
     const double* __restrict__ in, const double* __restrict__ rho, double* __restrict__ out,
     const int4* __restrict__ desc, const int32_t* __restrict__ cmap, int n, int nx, int ny, int nz, int hmax,
@@ -156,30 +157,34 @@ __global__ __launch_bounds__(256) void k_filter_octree(
   const int4 de = desc[e];
   const int cx = 2 * de.x + de.w, cy = 2 * de.y + de.w, cz = 2 * de.z + de.w;  // doubled centre
   const double r2 = 2.0 * rmin;
-  auto lo = [&](int c) { return max(0, (int)floor(0.5 * ((double)c - r2 - (double)hmax))); };
-  auto hi = [&](int c, int nmax) { return min(nmax - 1, (int)ceil(0.5 * ((double)c + r2))); };
-  const int x0 = lo(cx), x1 = hi(cx, nx), y0 = lo(cy), y1 = hi(cy, ny), z0 = lo(cz), z1 = hi(cz, nz);
   const double lim2 = r2 * r2;
   double num = 0.0, den = 0.0;
-  for (int z = z0; z <= z1; ++z)
-    for (int y = y0; y <= y1; ++y) {
-      const long row = (long)nx * (y + (long)ny * z);
-      for (int x = x0; x <= x1; ++x) {
-        const int v = cmap[row + x];
-        if (v >= 0) continue;  // not an anchor cell
-        const int d = v & 0x7fffffff;
-        const int4 dd = desc[d];
-        const double ddx = (double)(2 * dd.x + dd.w - cx), ddy = (double)(2 * dd.y + dd.w - cy),
-                     ddz = (double)(2 * dd.z + dd.w - cz);
-        const double D2 = ddx * ddx + ddy * ddy + ddz * ddz;  // (2 |x_d - x_e|)^2
-        if (D2 >= lim2) continue;
-        const double H = rmin - 0.5 * sqrt(D2);
-        if (H <= 0.0) continue;
-        const double w = H * (double)dd.w * dd.w * dd.w;
-        num += w * (mode == AMRTO_FILTER_SENSITIVITY ? rho[d] * in[d] : in[d]);
-        den += w;
+  for (int h = 1; h <= hmax; h <<= 1) {
+    // aligned anchors a (multiples of h) with |2 a + h - c| < 2 rmin
+    auto lo = [&](int c) { return max(0, (int)ceil(0.5 * ((double)(c - h) - r2) / h) * h); };
+    auto hi = [&](int c, int nmax) { return min(nmax - h, (int)floor(0.5 * ((double)(c - h) + r2) / h) * h); };
+    const int x0 = lo(cx), x1 = hi(cx, nx), y0 = lo(cy), y1 = hi(cy, ny), z0 = lo(cz), z1 = hi(cz, nz);
+    for (int z = z0; z <= z1; z += h)
+      for (int y = y0; y <= y1; y += h) {
+        const long row = (long)nx * (y + (long)ny * z);
+        for (int x = x0; x <= x1; x += h) {
+          const int v = cmap[row + x];
+          if (v >= 0) continue;  // not an anchor cell
+          const int d = v & 0x7fffffff;
+          const int4 dd = desc[d];
+          if (dd.w != h) continue;  // the anchor of a leaf of another size
+          const double ddx = (double)(2 * dd.x + h - cx), ddy = (double)(2 * dd.y + h - cy),
+                       ddz = (double)(2 * dd.z + h - cz);
+          const double D2 = ddx * ddx + ddy * ddy + ddz * ddz;  // (2 |x_d - x_e|)^2
+          if (D2 >= lim2) continue;
+          const double H = rmin - 0.5 * sqrt(D2);
+          if (H <= 0.0) continue;
+          const double w = H * (double)h * h * h;
+          num += w * (mode == AMRTO_FILTER_SENSITIVITY ? rho[d] * in[d] : in[d]);
+          den += w;
+        }
       }
-    }
+  }
   out[e] = mode == AMRTO_FILTER_SENSITIVITY ? num / (fmax(rho[e], 1e-3) * den) : num / den;
 }
 
