@@ -484,6 +484,118 @@ int amrto_octree_mesh_export(const amrto_octree* t, int32_t* node_xyz, int32_t* 
  * of the current mesh: u_new = trilinear interpolation on the old leaves. */
 int amrto_octree_transfer_nodal(const amrto_octree* t, const double* u_old, double* u_new);
 
+/* ------------------------------------------------------------------ 2-D variant (Sec. 6-7, Test 1) */
+/* Q4 plane-stress elements (unit thickness) on a quadtree mesh with hanging
+ * nodes, FP64 throughout.  K0 is the unit square's matrix (the stiffness of
+ * a square does not depend on its size in 2-D), K_e = (Emin + rho^p (E0 -
+ * Emin)) K0; local node a = i + 2 j at (i, j), local DOF 2 a + c.  The
+ * constrained operator is A~ = F T^T K T F + (I - F) (Eq. (7)-(8)) with
+ * hanging nodes interpolated from their masters (Eq. (6)) and supported DOFs
+ * as identity rows.  Vectors hold 2 doubles per node (x, y); element arrays
+ * hold one double per element.  All device pointers are on the context's
+ * device and stream; calls are asynchronous unless they return a host value.
+ * Errors: AMRTO_EINVAL for bad arguments, AMRTO_ESTATE when a required step
+ * (mesh, density) is missing, AMRTO_EHIP for runtime failures;
+ * amrto_plane_last_error() describes the last one. */
+typedef struct amrto_plane amrto_plane;
+
+typedef struct {
+  int32_t n_nodes, n_elems;
+  int32_t dims[2];            /* finest-lattice box (cells per axis) */
+  int32_t max_level;          /* a level-l element has edge 2^(max_level - l) */
+  const int32_t* node_xy;     /* [2 n_nodes] lattice coordinates */
+  const int32_t* elem_nodes;  /* [4 n_elems], local a = i + 2 j; node 0 is the anchor */
+  const int8_t* elem_level;   /* [n_elems], NULL = all at max_level */
+  int32_t n_hang;             /* hanging nodes and their master lists (CSR) */
+  const int32_t* hang_node;   /* [n_hang] */
+  const int32_t* hang_ptr;    /* [n_hang + 1] */
+  const int32_t* hang_master; /* [hang_ptr[n_hang]], never hanging themselves */
+  const double* hang_w;       /* [hang_ptr[n_hang]] */
+  const uint8_t* dof_fixed;   /* [2 n_nodes] supported DOFs */
+} amrto_mesh2d;
+
+int amrto_plane_create(amrto_plane** pl, int device, void* stream);
+int amrto_plane_destroy(amrto_plane* pl);
+const char* amrto_plane_last_error(const amrto_plane* pl);
+/* E0 > Emin >= 0, -1 < nu < 0.5, p >= 1 (defaults 1, 1e-9, 0.3, 3). */
+int amrto_plane_set_material(amrto_plane* pl, double E0, double Emin, double nu, double p);
+/* Copies the (host) mesh; builds the per-node incidence lists (element
+ * vertex, weight) through which the operator sums element outputs in a
+ * fixed order, and the lattice cell map of the filter. */
+int amrto_plane_upload_mesh(amrto_plane* pl, const amrto_mesh2d* mesh);
+/* Element Young's moduli and the exact diagonal of A~ from rho (device). */
+int amrto_plane_set_density(amrto_plane* pl, const double* rho);
+/* y = A~ x (device, distinct). */
+int amrto_plane_apply(amrto_plane* pl, const double* x, double* y);
+/* b = F T^T f (device, distinct): hanging loads moved onto their masters,
+ * supported and hanging rows zero. */
+int amrto_plane_project_rhs(amrto_plane* pl, const double* f, double* b);
+/* Jacobi-preconditioned CG on A~ u = b in FP64 from the initial guess in u
+ * (its supported and hanging entries are ignored), to ||r|| <= rtol ||b||
+ * over the unconstrained rows; the host reads the convergence flag every
+ * check_every iterations.  On exit the hanging entries of u hold their
+ * interpolated values (Eq. (9)).  A pass whose recurrence converges is checked
+ * against the true residual and restarted from the current iterate when it
+ * is above rtol (at most 8 restarts, counted in stats->outer).  Returns
+ * AMRTO_OK, AMRTO_NOT_CONVERGED or
+ * AMRTO_EBREAKDOWN; stats may be NULL. */
+int amrto_plane_pcg(amrto_plane* pl, const double* b, double* u, double rtol, int32_t max_it,
+                    int32_t check_every, amrto_solve_stats* stats);
+/* Compliance c = f . u to *c_host (when c_host != NULL) and the Eq. (4)
+ * sensitivities dc_e = -p rho^(p-1) (E0 - Emin) u_e^T K0 u_e into dc (device,
+ * when dc != NULL; needs rho). */
+int amrto_plane_compliance(amrto_plane* pl, const double* u, const double* f, const double* rho,
+                           double* c_host, double* dc);
+/* The Eq. (5) filter with area weights H_ed = max(0, rmin - |x_e - x_d|)
+ * h_d^2 over element centres (lattice units, 0 < rmin <= 16):
+ * sensitivity mode out_e = sum H rho_d in_d / (max(rho_e, 1e-3) sum H),
+ * density mode out_e = sum H in_d / sum H.  Allocates nothing. */
+int amrto_plane_filter(amrto_plane* pl, int32_t mode, double rmin, const double* in, const double* rho,
+                       double* out);
+/* OC step: rho_new = clamp(rho (max(-dc, 0) / (lam h_e^2))^eta, max(rho_min,
+ * rho - move), min(1, rho + move)) with lam such that sum rho_new h_e^2 =
+ * volfrac sum h_e^2 (log-spaced candidate multipliers narrowed to a relative
+ * width below 1e-14).  change_host = max |rho_new - rho|, lam_host = lam;
+ * either may be NULL. */
+int amrto_plane_oc_update(amrto_plane* pl, const double* rho, const double* dc, double volfrac, double move,
+                          double eta, double rho_min, double* rho_new, double* change_host, double* lam_host);
+
+/* ------------------------------------------------------------------ quadtree (host) */
+/* The 2-D tree of base[0] x base[1] level-0 leaves with max_level levels;
+ * leaves are kept in Morton order.  Regions use has[0..1] / at[0..1]. */
+typedef struct amrto_quadtree amrto_quadtree;
+
+int amrto_quadtree_create(amrto_quadtree** t, const int32_t base[2], int32_t max_level);
+int amrto_quadtree_destroy(amrto_quadtree* t);
+int32_t amrto_quadtree_n_leaves(const amrto_quadtree* t);
+int amrto_quadtree_leaves(const amrto_quadtree* t, int8_t* level, int32_t* anchor /*[2n]*/);
+/* Split every leaf with marks[i] != 0 (below max_level) into 4 children. */
+int amrto_quadtree_refine(amrto_quadtree* t, const uint8_t* marks);
+/* Refine until leaves sharing an edge segment differ by at most one level. */
+int amrto_quadtree_balance(amrto_quadtree* t);
+/* Sec. 4 adaptation in 2-D: mark (refine solid leaves and leaves whose
+ * centre lies within r_amr of a solid centre, derefine the rest), keep only
+ * complete families of four, refine with closure, drop families whose
+ * parent would break the edge rule, derefine.  Densities: children inherit,
+ * parents average (amrto_quadtree_adapt_result). */
+int amrto_quadtree_adapt(amrto_quadtree* t, const double* rho, double rho_s, double r_amr, int32_t* n_new);
+int amrto_quadtree_adapt_result(const amrto_quadtree* t, double* rho_new);
+/* The Q4 mesh of the current leaves: nodes numbered with x fastest, element
+ * connectivity (a = i + 2 j), hanging edge midpoints on their edge ends
+ * (1/2, 1/2) with chains resolved, both DOFs supported at nodes matching a
+ * fixed region, and a point load of load_total on component load_comp at the
+ * node (load_x, load_y), which must exist and not hang. */
+int amrto_quadtree_build_mesh(amrto_quadtree* t, int32_t n_fixed, const amrto_region* fixed, int32_t load_x,
+                              int32_t load_y, int32_t load_comp, double load_total);
+int amrto_quadtree_mesh_sizes(const amrto_quadtree* t, int32_t* n_nodes, int32_t* n_elems, int32_t* n_hang,
+                              int32_t* n_hang_entries);
+int amrto_quadtree_mesh_export(const amrto_quadtree* t, int32_t* node_xy, int32_t* elem_nodes, int8_t* elem_level,
+                               int32_t* hang_node, int32_t* hang_ptr, int32_t* hang_master, double* hang_w,
+                               uint8_t* dof_fixed, double* f_load);
+/* Bilinear interpolation of a nodal field of the mesh before the last adapt
+ * at the nodes of the current mesh. */
+int amrto_quadtree_transfer_nodal(const amrto_quadtree* t, const double* u_old, double* u_new);
+
 #ifdef __cplusplus
 }
 #endif

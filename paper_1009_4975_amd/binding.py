@@ -39,6 +39,13 @@ class MeshStruct(C.Structure):
                 ("hang_w", _p), ("dof_fixed", _p)]
 
 
+class Mesh2DStruct(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_elems", C.c_int32), ("dims", C.c_int32 * 2),
+                ("max_level", C.c_int32), ("node_xy", _p), ("elem_nodes", _p), ("elem_level", _p),
+                ("n_hang", C.c_int32), ("hang_node", _p), ("hang_ptr", _p), ("hang_master", _p),
+                ("hang_w", _p), ("dof_fixed", _p)]
+
+
 class Region(C.Structure):
     _fields_ = [("has", C.c_int32 * 3), ("at", C.c_int32 * 3)]
 
@@ -120,6 +127,32 @@ _SIGS = {
     "amrto_octree_mesh_sizes": (C.c_int, [_p, _i32p, _i32p, _i32p, _i32p]),
     "amrto_octree_mesh_export": (C.c_int, [_p] + [_p] * 9),
     "amrto_octree_transfer_nodal": (C.c_int, [_p, _p, _p]),
+    "amrto_plane_create": (C.c_int, [C.POINTER(_p), C.c_int, _p]),
+    "amrto_plane_destroy": (C.c_int, [_p]),
+    "amrto_plane_last_error": (C.c_char_p, [_p]),
+    "amrto_plane_set_material": (C.c_int, [_p, C.c_double, C.c_double, C.c_double, C.c_double]),
+    "amrto_plane_upload_mesh": (C.c_int, [_p, C.POINTER(Mesh2DStruct)]),
+    "amrto_plane_set_density": (C.c_int, [_p, _p]),
+    "amrto_plane_apply": (C.c_int, [_p, _p, _p]),
+    "amrto_plane_project_rhs": (C.c_int, [_p, _p, _p]),
+    "amrto_plane_pcg": (C.c_int, [_p, _p, _p, C.c_double, C.c_int32, C.c_int32, C.POINTER(SolveStats)]),
+    "amrto_plane_compliance": (C.c_int, [_p, _p, _p, _p, C.POINTER(C.c_double), _p]),
+    "amrto_plane_filter": (C.c_int, [_p, C.c_int32, C.c_double, _p, _p, _p]),
+    "amrto_plane_oc_update": (C.c_int, [_p, _p, _p, C.c_double, C.c_double, C.c_double, C.c_double, _p,
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "amrto_quadtree_create": (C.c_int, [C.POINTER(_p), C.POINTER(C.c_int32), C.c_int32]),
+    "amrto_quadtree_destroy": (C.c_int, [_p]),
+    "amrto_quadtree_n_leaves": (C.c_int32, [_p]),
+    "amrto_quadtree_leaves": (C.c_int, [_p, _p, _p]),
+    "amrto_quadtree_refine": (C.c_int, [_p, _p]),
+    "amrto_quadtree_balance": (C.c_int, [_p]),
+    "amrto_quadtree_adapt": (C.c_int, [_p, _p, C.c_double, C.c_double, _i32p]),
+    "amrto_quadtree_adapt_result": (C.c_int, [_p, _p]),
+    "amrto_quadtree_build_mesh": (C.c_int, [_p, C.c_int32, C.POINTER(Region), C.c_int32, C.c_int32, C.c_int32,
+                                            C.c_double]),
+    "amrto_quadtree_mesh_sizes": (C.c_int, [_p, _i32p, _i32p, _i32p, _i32p]),
+    "amrto_quadtree_mesh_export": (C.c_int, [_p] + [_p] * 9),
+    "amrto_quadtree_transfer_nodal": (C.c_int, [_p, _p, _p]),
 }
 
 _LIB = None
@@ -680,3 +713,230 @@ class Net:
 
     def adam(self, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):
         self._chk(self.lib.amrto_net_adam(self.h, lr, beta1, beta2, eps, int(t)))
+
+
+# ---------------------------------------------------------------------- 2-D variant
+@dataclass
+class Mesh2DArrays:
+    """Host arrays of a quadtree mesh (``Quadtree.build_mesh``)."""
+    dims: tuple
+    max_level: int
+    node_xy: np.ndarray           # (nn, 2) int32, x fastest
+    elem_nodes: np.ndarray        # (ne, 4) int32, local a = i + 2 j
+    elem_level: np.ndarray        # (ne,) int8
+    hang_node: np.ndarray
+    hang_ptr: np.ndarray
+    hang_master: np.ndarray
+    hang_w: np.ndarray
+    dof_fixed: np.ndarray         # (2 nn,) uint8
+    f_load: np.ndarray            # (2 nn,) float64
+
+    @property
+    def n_nodes(self):
+        return len(self.node_xy)
+
+    @property
+    def n_elems(self):
+        return len(self.elem_level)
+
+    def struct(self):
+        keep = []
+
+        def arr(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            keep.append(a)
+            return a.ctypes.data
+
+        m = Mesh2DStruct()
+        m.n_nodes, m.n_elems = self.n_nodes, self.n_elems
+        m.dims[:] = list(self.dims)
+        m.max_level = self.max_level
+        m.node_xy = arr(self.node_xy, np.int32)
+        m.elem_nodes = arr(self.elem_nodes, np.int32)
+        m.elem_level = arr(self.elem_level, np.int8)
+        m.n_hang = len(self.hang_node)
+        m.hang_node = arr(self.hang_node, np.int32)
+        m.hang_ptr = arr(self.hang_ptr, np.int32)
+        m.hang_master = arr(self.hang_master, np.int32)
+        m.hang_w = arr(self.hang_w, np.float64)
+        m.dof_fixed = arr(self.dof_fixed, np.uint8)
+        return m, keep
+
+
+class Quadtree:
+    """Host quadtree of the 2-D variant (refine, closure, adapt, mesh build)."""
+
+    def __init__(self, base, max_level):
+        self.lib = load()
+        self.h = _p()
+        b = (C.c_int32 * 2)(*base)
+        self._chk(self.lib.amrto_quadtree_create(C.byref(self.h), b, int(max_level)))
+        self.base = tuple(base)
+        self.max_level = int(max_level)
+        self.dims = tuple(int(x) << self.max_level for x in base)
+
+    def _chk(self, rc):
+        if rc < 0:
+            raise AmrtoError(rc, "quadtree call failed")
+        return rc
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) and self.h.value:
+                self.lib.amrto_quadtree_destroy(self.h)
+                self.h = _p()
+        except Exception:  # interpreter shutdown: ctypes may already be gone
+            pass
+
+    @property
+    def n_leaves(self):
+        return self.lib.amrto_quadtree_n_leaves(self.h)
+
+    def leaves(self):
+        n = self.n_leaves
+        lv = np.zeros(n, np.int8)
+        an = np.zeros((n, 2), np.int32)
+        self._chk(self.lib.amrto_quadtree_leaves(self.h, lv.ctypes.data, an.ctypes.data))
+        return lv.astype(np.int64), an.astype(np.int64)
+
+    def refine(self, marks):
+        m = np.ascontiguousarray(marks, dtype=np.uint8)
+        if len(m) != self.n_leaves:
+            raise AmrtoError(-1, f"marks has {len(m)} values, {self.n_leaves} expected")
+        self._chk(self.lib.amrto_quadtree_refine(self.h, m.ctypes.data))
+
+    def balance(self):
+        self._chk(self.lib.amrto_quadtree_balance(self.h))
+
+    def adapt(self, rho, rho_s=0.5, r_amr=1.5):
+        r = np.ascontiguousarray(rho, dtype=np.float64)
+        if len(r) != self.n_leaves:
+            raise AmrtoError(-1, f"rho has {len(r)} values, {self.n_leaves} expected")
+        n = C.c_int32()
+        self._chk(self.lib.amrto_quadtree_adapt(self.h, r.ctypes.data, rho_s, r_amr, C.byref(n)))
+        out = np.zeros(n.value)
+        self._chk(self.lib.amrto_quadtree_adapt_result(self.h, out.ctypes.data))
+        return out
+
+    def build_mesh(self, fixed, load) -> Mesh2DArrays:
+        """fixed: list of {"x": v} / {"y": v} / {"x": v, "y": w}; load:
+        {"at": (x, y), "comp": c, "total": F}."""
+        regs = (Region * max(1, len(fixed)))(*[_region(w) for w in fixed])
+        x, y = load["at"]
+        self._chk(self.lib.amrto_quadtree_build_mesh(self.h, len(fixed), regs, int(x), int(y), int(load["comp"]),
+                                                     float(load["total"])))
+        nn, ne, nh, nhe = (C.c_int32() for _ in range(4))
+        self._chk(self.lib.amrto_quadtree_mesh_sizes(self.h, C.byref(nn), C.byref(ne), C.byref(nh), C.byref(nhe)))
+        nn, ne, nh, nhe = nn.value, ne.value, nh.value, nhe.value
+        xy = np.zeros((nn, 2), np.int32)
+        en = np.zeros((ne, 4), np.int32)
+        lv = np.zeros(ne, np.int8)
+        hn = np.zeros(nh, np.int32)
+        hp = np.zeros(nh + 1, np.int32)
+        hm = np.zeros(nhe, np.int32)
+        hw = np.zeros(nhe, np.float64)
+        fx = np.zeros(2 * nn, np.uint8)
+        fl = np.zeros(2 * nn, np.float64)
+        self._chk(self.lib.amrto_quadtree_mesh_export(self.h, *[a.ctypes.data for a in (xy, en, lv, hn, hp, hm, hw,
+                                                                                            fx, fl)]))
+        return Mesh2DArrays(self.dims, self.max_level, xy, en, lv, hn, hp, hm, hw, fx, fl)
+
+    def transfer_nodal(self, u_old: np.ndarray, n_new_nodes: int) -> np.ndarray:
+        u_old = np.ascontiguousarray(u_old, dtype=np.float64)
+        out = np.zeros(2 * n_new_nodes)
+        self._chk(self.lib.amrto_quadtree_transfer_nodal(self.h, u_old.ctypes.data, out.ctypes.data))
+        return out
+
+
+class PlaneContext:
+    """Device context of the 2-D variant (amrto_plane_*)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.lib = load()
+        self.torch = torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        self.h = _p()
+        rc = self.lib.amrto_plane_create(C.byref(self.h), int(device), _p(stream.cuda_stream))
+        if rc != 0:
+            raise AmrtoError(rc, "amrto_plane_create failed")
+        self.mesh: Optional[Mesh2DArrays] = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) and self.h.value:
+                self.lib.amrto_plane_destroy(self.h)
+                self.h = _p()
+        except Exception:  # interpreter shutdown: ctypes may already be gone
+            pass
+
+    def _chk(self, rc, allow_not_converged=False):
+        if rc < 0 or (rc > 0 and not allow_not_converged):
+            raise AmrtoError(rc, self.lib.amrto_plane_last_error(self.h).decode())
+        return rc
+
+    def _dofs(self, **bufs):
+        if self.mesh is not None:
+            _need(2 * self.mesh.n_nodes, **bufs)
+
+    def _elems(self, **bufs):
+        if self.mesh is not None:
+            _need(self.mesh.n_elems, **bufs)
+
+    def set_material(self, E0=1.0, Emin=1e-9, nu=0.3, p=3.0):
+        self._chk(self.lib.amrto_plane_set_material(self.h, E0, Emin, nu, p))
+
+    def upload_mesh(self, mesh: Mesh2DArrays):
+        s, keep = mesh.struct()
+        self.mesh = None
+        self._chk(self.lib.amrto_plane_upload_mesh(self.h, C.byref(s)))
+        del keep
+        self.mesh = mesh
+
+    def set_density(self, rho):
+        self._elems(rho=rho)
+        self._chk(self.lib.amrto_plane_set_density(self.h, _dev(rho, self.torch.float64)))
+
+    def apply(self, x, y):
+        self._dofs(x=x, y=y)
+        self._chk(self.lib.amrto_plane_apply(self.h, _dev(x, self.torch.float64), _dev(y, self.torch.float64)))
+
+    def project_rhs(self, f, b):
+        self._dofs(f=f, b=b)
+        self._chk(self.lib.amrto_plane_project_rhs(self.h, _dev(f, self.torch.float64),
+                                                   _dev(b, self.torch.float64)))
+
+    def pcg(self, b, u, rtol=1e-8, max_it=20000, check_every=16):
+        self._dofs(b=b, u=u)
+        st = SolveStats()
+        rc = self.lib.amrto_plane_pcg(self.h, _dev(b, self.torch.float64), _dev(u, self.torch.float64),
+                                      float(rtol), int(max_it), int(check_every), C.byref(st))
+        self._chk(rc, allow_not_converged=True)
+        return dict(status=STATUS.get(rc, rc), iters=st.iters, outer=st.outer, rel_res=st.rel_res, ms=st.ms)
+
+    def compliance(self, u, f=None, rho=None, dc=None):
+        self._dofs(u=u, f=f)
+        self._elems(rho=rho, dc=dc)
+        c = C.c_double()
+        f64 = self.torch.float64
+        self._chk(self.lib.amrto_plane_compliance(
+            self.h, _dev(u, f64), None if f is None else _dev(f, f64), None if rho is None else _dev(rho, f64),
+            C.byref(c) if f is not None else None, None if dc is None else _dev(dc, f64)))
+        return c.value if f is not None else None
+
+    def filter(self, mode, rmin, x, out, rho=None):
+        self._elems(x=x, out=out, rho=rho)
+        f64 = self.torch.float64
+        self._chk(self.lib.amrto_plane_filter(self.h, int(mode), float(rmin), _dev(x, f64),
+                                              None if rho is None else _dev(rho, f64), _dev(out, f64)))
+
+    def oc_update(self, rho, dc, rho_new, volfrac, move=0.2, eta=0.5, rho_min=1e-3):
+        self._elems(rho=rho, dc=dc, rho_new=rho_new)
+        ch, lam = C.c_double(), C.c_double()
+        f64 = self.torch.float64
+        self._chk(self.lib.amrto_plane_oc_update(self.h, _dev(rho, f64), _dev(dc, f64), float(volfrac),
+                                                 float(move), float(eta), float(rho_min), _dev(rho_new, f64),
+                                                 C.byref(ch), C.byref(lam)))
+        return ch.value, lam.value
