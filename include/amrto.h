@@ -484,6 +484,57 @@ int amrto_octree_mesh_export(const amrto_octree* t, int32_t* node_xyz, int32_t* 
  * of the current mesh: u_new = trilinear interpolation on the old leaves. */
 int amrto_octree_transfer_nodal(const amrto_octree* t, const double* u_old, double* u_new);
 
+/* ------------------------------------------------------------------ multigrid preconditioner */
+/* A geometric multigrid V-cycle on the octree hierarchy as the preconditioner
+ * of FP64 CG: a stronger preconditioner than Jacobi for the p = 3 contrast
+ * (the paper's own choice, Sec. 5, is IC(0) on the rescaled system).
+ * Level 0 is the uploaded mesh; level k <= L merges every leaf finer than
+ * level L - k into its ancestor; levels k > L coarsen the uniform base grid
+ * by two per axis; levels are added until a uniform level has at most
+ * coarse_dofs DOFs (it must have at most 1024).  Coarse operators are exactly
+ * Galerkin (P^T A P, element by element), the prolongation evaluates the
+ * continuous coarse field at the fine nodes, smoothing is Chebyshev on
+ * D^-1 A over [hi / ratio, hi] with hi = hi_factor * lambda_max estimated by
+ * power_its power iterations, and the coarsest level is solved with its
+ * dense inverse.  Vectors are in the constrained form (zero at hanging and
+ * supported DOFs). */
+typedef struct {
+  int32_t degree;       /* Chebyshev degree per smoothing (default 2) */
+  double ratio;         /* smoothing interval [hi / ratio, hi] (default 10) */
+  int32_t power_its;    /* power iterations for lambda_max (default 20) */
+  double hi_factor;     /* hi = hi_factor * estimate (default 1.1) */
+  int32_t coarse_dofs;  /* target size of the coarsest level (default 200) */
+} amrto_mg_opts;
+
+/* Build the hierarchy of the uploaded mesh from the host tree it was built
+ * from (its last amrto_octree_build_mesh; uniform meshes: the one-level tree
+ * with lexicographic numbering).  Per mesh; allocates the level data.
+ * opts may be NULL.  AMRTO_EINVAL when the tree's mesh is not the uploaded
+ * one or no small uniform coarsest level exists. */
+int amrto_mg_setup(amrto_ctx* ctx, const amrto_octree* tree, const amrto_mg_opts* opts);
+/* Level count, DOFs per level and dense (merged) elements per level (host
+ * arrays of at least 16 entries, either may be NULL). */
+int amrto_mg_info(amrto_ctx* ctx, int32_t* n_levels, int32_t* dofs, int32_t* dense);
+/* Replace the power-iteration estimates of lambda_max(D^-1 A) by the given
+ * values (one per smoothed level, host), or restore them (lam == NULL). */
+int amrto_mg_set_bounds(amrto_ctx* ctx, const double* lam);
+/* The lambda_max in use per smoothed level (host output). */
+int amrto_mg_get_bounds(amrto_ctx* ctx, double* lam);
+/* z = one V-cycle applied to r (device, 3 n_nodes each, distinct). */
+int amrto_mg_vcycle(amrto_ctx* ctx, const double* r, double* z);
+/* y = A_k x on level k >= 1 (identity rows for constrained DOFs), the
+ * diagonal inverse of A_k, x_f = P_k x_c and r_c = P_k^T r_f (device). */
+int amrto_mg_level_apply(amrto_ctx* ctx, int32_t k, const double* x, double* y);
+int amrto_mg_level_diag(amrto_ctx* ctx, int32_t k, double* dinv);
+int amrto_mg_prolong(amrto_ctx* ctx, int32_t k, const double* xc, double* xf);
+int amrto_mg_restrict(amrto_ctx* ctx, int32_t k, const double* rf, double* rc);
+/* CG in FP64 on A~ u = b preconditioned by one V-cycle per iteration, from
+ * the initial guess in u (constrained entries ignored), to ||r|| <= rtol
+ * ||b||; the numeric set-up runs first after a density change.  Returns
+ * AMRTO_OK, AMRTO_NOT_CONVERGED or AMRTO_EBREAKDOWN. */
+int amrto_mg_pcg(amrto_ctx* ctx, const double* b, double* u, double rtol, int32_t max_it,
+                 int32_t check_every, amrto_solve_stats* stats);
+
 /* ------------------------------------------------------------------ 2-D variant (Sec. 6-7, Test 1) */
 /* Q4 plane-stress elements (unit thickness) on a quadtree mesh with hanging
  * nodes, FP64 throughout.  K0 is the unit square's matrix (the stiffness of

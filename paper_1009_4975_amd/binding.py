@@ -57,6 +57,11 @@ class SolveOpts(C.Structure):
                 ("record", C.c_int32)]
 
 
+class MgOpts(C.Structure):
+    _fields_ = [("degree", C.c_int32), ("ratio", C.c_double), ("power_its", C.c_int32), ("hi_factor", C.c_double),
+                ("coarse_dofs", C.c_int32)]
+
+
 class SolveStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("outer", C.c_int32), ("rel_res", C.c_double), ("ms", C.c_double),
                 ("fell_back", C.c_int32)]
@@ -127,6 +132,16 @@ _SIGS = {
     "amrto_octree_mesh_sizes": (C.c_int, [_p, _i32p, _i32p, _i32p, _i32p]),
     "amrto_octree_mesh_export": (C.c_int, [_p] + [_p] * 9),
     "amrto_octree_transfer_nodal": (C.c_int, [_p, _p, _p]),
+    "amrto_mg_setup": (C.c_int, [_p, _p, C.POINTER(MgOpts)]),
+    "amrto_mg_info": (C.c_int, [_p, _i32p, _p, _p]),
+    "amrto_mg_set_bounds": (C.c_int, [_p, _p]),
+    "amrto_mg_get_bounds": (C.c_int, [_p, _p]),
+    "amrto_mg_vcycle": (C.c_int, [_p, _p, _p]),
+    "amrto_mg_level_apply": (C.c_int, [_p, C.c_int32, _p, _p]),
+    "amrto_mg_level_diag": (C.c_int, [_p, C.c_int32, _p]),
+    "amrto_mg_prolong": (C.c_int, [_p, C.c_int32, _p, _p]),
+    "amrto_mg_restrict": (C.c_int, [_p, C.c_int32, _p, _p]),
+    "amrto_mg_pcg": (C.c_int, [_p, _p, _p, C.c_double, C.c_int32, C.c_int32, C.POINTER(SolveStats)]),
     "amrto_plane_create": (C.c_int, [C.POINTER(_p), C.c_int, _p]),
     "amrto_plane_destroy": (C.c_int, [_p]),
     "amrto_plane_last_error": (C.c_char_p, [_p]),
@@ -352,10 +367,11 @@ class Octree:
         return out
 
 
-def uniform_mesh(dims, fixed, load) -> MeshArrays:
+def uniform_mesh(dims, fixed, load, tree=None) -> MeshArrays:
     """A uniform brick (implicit connectivity on the device): the octree with
-    one level and lexicographic node numbering supplies supports and loads."""
-    t = Octree(dims, 0)
+    one level and lexicographic node numbering supplies supports and loads
+    (pass ``tree = Octree(dims, 0)`` to keep it, e.g. for the multigrid)."""
+    t = Octree(dims, 0) if tree is None else tree
     m = t.build_mesh(fixed, load, lexicographic=True)
     m.uniform = True
     return m
@@ -506,6 +522,83 @@ class Context:
         self._chk(self.lib.amrto_pcg_pass_times(self.h, _dev(b, self.torch.float64), _dev(u, self.torch.float64),
                                                 C.byref(o), int(reps), C.byref(op), C.byref(up)))
         return op.value, up.value
+
+    # ------------------------------------------------------------ multigrid
+    def mg_setup(self, tree, degree=2, ratio=10.0, power_its=20, hi_factor=1.1, coarse_dofs=200):
+        """Multigrid hierarchy of the uploaded mesh from the host tree it was built from."""
+        o = MgOpts(int(degree), float(ratio), int(power_its), float(hi_factor), int(coarse_dofs))
+        self._mg_dofs = None
+        self._chk(self.lib.amrto_mg_setup(self.h, tree.h, C.byref(o)))
+        self._mg_dofs = self.mg_info()["dofs"]
+
+    def mg_info(self):
+        n = C.c_int32()
+        dofs = np.zeros(16, np.int32)
+        dense = np.zeros(16, np.int32)
+        self._chk(self.lib.amrto_mg_info(self.h, C.byref(n), dofs.ctypes.data, dense.ctypes.data))
+        return dict(levels=n.value, dofs=dofs[:n.value].tolist(), dense=dense[:n.value].tolist())
+
+    def _mg_level(self, k):
+        dofs = getattr(self, "_mg_dofs", None)
+        if dofs is None:
+            raise AmrtoError(-5, "no multigrid hierarchy (mg_setup)")
+        if not 1 <= k < len(dofs):
+            raise AmrtoError(-1, f"level {k} out of range 1..{len(dofs) - 1}")
+        return dofs
+
+    def mg_set_bounds(self, lam=None):
+        if lam is None:
+            self._chk(self.lib.amrto_mg_set_bounds(self.h, None))
+            return
+        dofs = getattr(self, "_mg_dofs", None) or []
+        a = np.ascontiguousarray(lam, dtype=np.float64)
+        if len(a) != max(0, len(dofs) - 1):
+            raise AmrtoError(-1, f"{len(a)} bounds given, {max(0, len(dofs) - 1)} smoothed levels")
+        self._chk(self.lib.amrto_mg_set_bounds(self.h, a.ctypes.data))
+
+    def mg_get_bounds(self):
+        dofs = getattr(self, "_mg_dofs", None) or []
+        out = np.zeros(max(1, len(dofs) - 1))
+        self._chk(self.lib.amrto_mg_get_bounds(self.h, out.ctypes.data))
+        return out[:max(0, len(dofs) - 1)]
+
+    def mg_vcycle(self, r, z):
+        self._dofs(r=r, z=z)
+        self._chk(self.lib.amrto_mg_vcycle(self.h, _dev(r, self.torch.float64), _dev(z, self.torch.float64)))
+
+    def mg_level_apply(self, k, x, y):
+        dofs = self._mg_level(k)
+        _need(dofs[k], x=x, y=y)
+        self._chk(self.lib.amrto_mg_level_apply(self.h, int(k), _dev(x, self.torch.float64),
+                                                _dev(y, self.torch.float64)))
+
+    def mg_level_diag(self, k, out):
+        dofs = self._mg_level(k)
+        _need(dofs[k], out=out)
+        self._chk(self.lib.amrto_mg_level_diag(self.h, int(k), _dev(out, self.torch.float64)))
+
+    def mg_prolong(self, k, xc, xf):
+        dofs = self._mg_level(k)
+        _need(dofs[k], xc=xc)
+        _need(dofs[k - 1], xf=xf)
+        self._chk(self.lib.amrto_mg_prolong(self.h, int(k), _dev(xc, self.torch.float64),
+                                            _dev(xf, self.torch.float64)))
+
+    def mg_restrict(self, k, rf, rc):
+        dofs = self._mg_level(k)
+        _need(dofs[k - 1], rf=rf)
+        _need(dofs[k], rc=rc)
+        self._chk(self.lib.amrto_mg_restrict(self.h, int(k), _dev(rf, self.torch.float64),
+                                             _dev(rc, self.torch.float64)))
+
+    def mg_pcg(self, b, u, rtol=1e-8, max_it=5000, check_every=2):
+        self._dofs(b=b, u=u)
+        st = SolveStats()
+        rc = self.lib.amrto_mg_pcg(self.h, _dev(b, self.torch.float64), _dev(u, self.torch.float64), float(rtol),
+                                   int(max_it), int(check_every), C.byref(st))
+        self._chk(rc, allow_not_converged=True)
+        return dict(status=STATUS.get(rc, rc), iters=st.iters, outer=st.outer, rel_res=st.rel_res, ms=st.ms,
+                    fell_back=0)
 
     def compliance(self, u, f, rho=None, dc=None):
         self._dofs(u=u, f=f)

@@ -79,6 +79,7 @@ static hipError_t dalloc(T*& p, size_t n) {
 }
 
 static void free_mesh(amrto_ctx* c) {
+  mg_free(c);
   dfree(c->d_fix); dfree(c->d_level); dfree(c->d_elem_nodes);
   dfree(c->d_chunk_cnt); dfree(c->d_ent_elem); dfree(c->d_ent_loc);
   dfree(c->d_tab_node); dfree(c->d_trip_hm); dfree(c->d_trip_w); dfree(c->d_tab_hbeg);
@@ -219,6 +220,7 @@ int amrto_set_material(amrto_ctx* ctx, double E0, double Emin, double nu, double
   AMRTO_HIP(hipSetDevice(ctx->device));
   ctx->E0 = E0; ctx->Emin = Emin; ctx->nu = nu; ctx->p = p;
   ctx->has_density = false;
+  ctx->mg_valid = false;
   return upload_material(ctx);
 }
 
@@ -334,6 +336,7 @@ int amrto_set_density(amrto_ctx* ctx, const double* rho) {
   if (!rho) return ctx->fail(AMRTO_EINVAL, "amrto_set_density: rho is NULL");
   AMRTO_HIP(hipSetDevice(ctx->device));
   ctx->coarse_k = 0;  // Z^T A~ Z depends on the density
+  ctx->mg_valid = false;
   int rc = launch_set_density(ctx, rho);
   if (rc) return rc;
   rc = launch_diag(ctx);

@@ -9,6 +9,10 @@
 
 #include "amrto.h"
 
+namespace amrto {
+struct MgData;
+}
+
 #define AMRTO_HIP(call)                                                          \
   do {                                                                           \
     hipError_t e_ = (call);                                                      \
@@ -221,6 +225,12 @@ struct amrto_ctx {
   int32_t* d_gn_node = nullptr;    // [8 grid nodes] mesh nodes interpolated at each grid node
   float* d_gn_w = nullptr;         // [8 grid nodes] their trilinear weights
 
+  // geometric multigrid (mg.hip): hierarchy of the uploaded mesh; its
+  // numeric part (Galerkin matrices, smoothing intervals, coarsest inverse)
+  // is rebuilt on first use after a density or material change
+  amrto::MgData* mg = nullptr;
+  bool mg_valid = false;
+
   int fail(int code, const std::string& msg) {
     err = msg;
     return code;
@@ -239,6 +249,8 @@ template <typename VT>
 int recycle_store(amrto_ctx* ctx, const VT* r, int it);
 // pcg.hip
 int apply_precond(amrto_ctx* ctx, const double* s, double* u, bool block3, bool coarse);
+// mg.hip
+void mg_free(amrto_ctx* ctx);
 // topopt.hip
 int build_cell_map(amrto_ctx* ctx);
 int oc_scratch_attach(amrto_ctx* ctx);

@@ -1,0 +1,1355 @@
+// Geometric multigrid on the octree hierarchy as the preconditioner of CG.
+//
+// The paper (Sec. 5) needs a strong preconditioner at the p = 3 stiffness
+// contrast and uses IC(0) on the rescaled system; its triangular solves are
+// sequential, so this library uses a V-cycle built from the mesh hierarchy
+// the octree already has:
+//
+// * level 0 is the analysis mesh; level k <= L merges every leaf finer than
+//   level L - k into its ancestor, levels k > L coarsen the uniform base grid
+//   by two per axis (levels.h); levels are added until one has at most
+//   coarse_dofs DOFs and is a uniform grid (no hanging nodes);
+// * the prolongation evaluates the continuous level-k field (hanging values
+//   from their masters) at the level k - 1 nodes, P = F_{k-1} I T_k F_k, and
+//   the restriction is its transpose;
+// * coarse operators are exactly Galerkin, A_k = P^T A_{k-1} P + (I - F_k),
+//   assembled element by element: a level-k element that is a single level-0
+//   leaf keeps c_e K0, every merged element stores the dense 24 x 24 sum
+//   of its children's matrices mapped through the trilinear interpolation
+//   from its corners to theirs;
+// * smoothing is the Chebyshev iteration for D^-1 A on [hi / ratio, hi], hi
+//   from power iteration, fused into the per-node pass that sums element
+//   outputs (no atomics, fixed order); the coarsest level is solved with its
+//   dense inverse (Gauss-Jordan, one workgroup).
+//
+// Vectors of every level are in the constrained form (zero at hanging and
+// supported DOFs), 3 doubles per node.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+#include <vector>
+
+#include "kernels.h"
+#include "levels.h"
+
+namespace amrto {
+
+constexpr int MG_LMAX = 16;
+constexpr int MG_COARSE_MAX = 1024;
+constexpr int MG_RED = 256;  // partial sums of the multigrid kernels
+enum { MS_LAM = 0, MS_THETA = 1, MS_DELTA = 2, MS_SIGMA = 3, MS_COUNT = 4 };
+// PCG scalars
+enum { MC_RZ = 0, MC_BB = 1, MC_DONE = 2, MC_ITERS = 3, MC_RR = 4, MC_RES = 5, MC_COUNT = 8 };
+enum MgMode { MG_APPLY = 0, MG_CHEB = 1, MG_CHEB_LAST = 2, MG_CORR = 3, MG_POWER = 4, MG_RAYLEIGH = 5 };
+
+struct MgLevel {
+  int nn = 0, ne = 0, nd = 0, nh = 0;  // nodes, elements, dense elements (first nd), hanging nodes
+  int32_t* elem = nullptr;       // [8 ne]
+  int32_t* pure_src = nullptr;   // [ne - nd] index into the context's c_e
+  double* Kd = nullptr;          // [576 nd] entry-major: Kd[i * nd + e]
+  uint8_t* flag = nullptr;       // per node: bits 0-2 supported components, bit 3 hanging
+  int32_t* hang_of = nullptr;    // per node: row of the hanging table, or -1
+  int32_t* hptr = nullptr; int32_t* hm = nullptr; double* hw = nullptr;
+  int32_t* iptr = nullptr; int32_t* islot = nullptr; double* iw = nullptr;  // incidences (slot 8 e + a)
+  double* dinv = nullptr;        // owned except on level 0
+  double* E = nullptr;           // [24 ne] element outputs
+  double *x = nullptr, *r = nullptr, *d = nullptr, *q = nullptr, *b = nullptr;
+  double* scal = nullptr;        // MS_COUNT
+  // coarse side of the transfer to the next finer level (this level k >= 1):
+  int32_t* pptr = nullptr; int32_t* pcol = nullptr; double* pw = nullptr;  // rows: level k-1 nodes
+  int32_t* rptr = nullptr; int32_t* rcol = nullptr; double* rw = nullptr;  // rows: level k nodes
+  int32_t* cptr = nullptr; int32_t* celem = nullptr; int8_t* coct = nullptr;  // children of dense elements
+  double* Ainv = nullptr;        // coarsest level: dense inverse of A~ (3 nn x 3 nn)
+  std::vector<void*> owned;
+};
+
+struct MgData {
+  int nlev = 0;
+  MgLevel lv[MG_LMAX];
+  int degree = 2, power_its = 20;
+  double ratio = 10.0, hi_factor = 1.1;
+  bool user_bounds = false;
+  double lam_user[MG_LMAX] = {};
+  double* part = nullptr;   // 4 x MG_RED
+  double* cg = nullptr;     // MC_COUNT
+  double* h_cg = nullptr;   // pinned
+  double *z = nullptr, *p = nullptr, *qv = nullptr;  // PCG vectors
+  std::vector<void*> owned;
+};
+
+void mg_free(amrto_ctx* ctx);
+
+}  // namespace amrto
+
+using namespace amrto;
+
+namespace {
+
+template <typename T>
+hipError_t mg_alloc(std::vector<void*>& own, T*& p, size_t n) {
+  p = nullptr;
+  hipError_t e = hipMalloc((void**)&p, std::max<size_t>(n, 1) * sizeof(T));
+  if (e == hipSuccess) own.push_back(p);
+  return e;
+}
+template <typename T>
+hipError_t mg_upload(std::vector<void*>& own, T*& p, const std::vector<T>& v) {
+  hipError_t e = mg_alloc(own, p, v.size());
+  if (e == hipSuccess && !v.empty()) e = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+__device__ __forceinline__ bool mg_cons(uint8_t f, int c) { return ((f >> 3) & 1) || ((f >> c) & 1); }
+
+// value of DOF c of the continuous field at node v (hanging values from masters)
+__device__ __forceinline__ double mg_val(const double* __restrict__ x, const uint8_t* __restrict__ flag,
+                                         const int32_t* __restrict__ hang_of, const int32_t* __restrict__ hptr,
+                                         const int32_t* __restrict__ hm, const double* __restrict__ hw, int v,
+                                         int c) {
+  const int h = hang_of[v];
+  if (h < 0) return ((flag[v] >> c) & 1) ? 0.0 : x[3L * v + c];
+  double s = 0.0;
+  for (int k = hptr[h]; k < hptr[h + 1]; ++k) {
+    const int m = hm[k];
+    if (!((flag[m] >> c) & 1)) s += hw[k] * x[3L * m + c];
+  }
+  return s;
+}
+
+// element outputs E[24 e + 3 a + c] = (K_e u_e) for the continuous field of x
+__global__ __launch_bounds__(256) void k_mg_elem(const double* __restrict__ x, const int32_t* __restrict__ elem,
+                                                 const uint8_t* __restrict__ flag,
+                                                 const int32_t* __restrict__ hang_of, const int32_t* __restrict__ hptr,
+                                                 const int32_t* __restrict__ hm, const double* __restrict__ hw,
+                                                 const double* __restrict__ Kd, int nd,
+                                                 const int32_t* __restrict__ pure_src,
+                                                 const double* __restrict__ coef, const double* __restrict__ K0g,
+                                                 double* __restrict__ E, int ne) {
+  __shared__ double K0[576];
+  for (int i = threadIdx.x; i < 576; i += blockDim.x) K0[i] = K0g[i];
+  __syncthreads();
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  double u[24];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int v = elem[8L * e + a];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[3 * a + c] = mg_val(x, flag, hang_of, hptr, hm, hw, v, c);
+  }
+  if (e < nd) {
+    for (int i = 0; i < 24; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < 24; ++j) s = fma(Kd[(long)(i * 24 + j) * nd + e], u[j], s);
+      E[24L * e + i] = s;
+    }
+  } else {
+    const double ce = coef[pure_src[e - nd]];
+    for (int i = 0; i < 24; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < 24; ++j) s = fma(K0[i * 24 + j], u[j], s);
+      E[24L * e + i] = ce * s;
+    }
+  }
+}
+
+struct MgUpd {
+  int mode;
+  int step;                 // Chebyshev step (MG_CHEB)
+  const double* scal;       // MS_* of the level
+  const double* dinv;
+  double *x, *r, *d;
+  const double* xin;        // MG_APPLY: identity rows; MG_POWER / MG_RAYLEIGH: iterate
+  double* y;                // MG_APPLY / MG_POWER output
+};
+
+// per-DOF update after q = (A d)_i; returns the two Rayleigh terms in MG_RAYLEIGH
+__device__ __forceinline__ void mg_update(const MgUpd& u, long i, bool cons, double q, double& t1, double& t2) {
+  switch (u.mode) {
+    case MG_APPLY:
+      u.y[i] = cons ? u.xin[i] : q;
+      break;
+    case MG_CHEB: {
+      const double sigma = u.scal[MS_SIGMA], delta = u.scal[MS_DELTA];
+      double rho = 1.0 / sigma;
+      for (int s = 0; s < u.step; ++s) rho = 1.0 / (2.0 * sigma - rho);
+      const double rho1 = 1.0 / (2.0 * sigma - rho);
+      if (cons) {
+        u.x[i] = 0.0; u.r[i] = 0.0; u.d[i] = 0.0;
+      } else {
+        const double dd = u.d[i];
+        u.x[i] += dd;
+        const double rr = u.r[i] - q;
+        u.r[i] = rr;
+        u.d[i] = rho1 * rho * dd + (2.0 * rho1 / delta) * u.dinv[i] * rr;
+      }
+      break;
+    }
+    case MG_CHEB_LAST:
+      if (cons) {
+        u.x[i] = 0.0; u.r[i] = 0.0;
+      } else {
+        u.x[i] += u.d[i];
+        u.r[i] -= q;
+      }
+      break;
+    case MG_CORR: {
+      const double rr = cons ? 0.0 : u.r[i] - q;
+      u.r[i] = rr;
+      u.d[i] = u.dinv[i] * rr / u.scal[MS_THETA];
+      break;
+    }
+    case MG_POWER:
+      u.y[i] = cons ? 0.0 : u.dinv[i] * q;
+      break;
+    case MG_RAYLEIGH:
+      if (!cons) {
+        const double xi = u.xin[i];
+        t1 += xi * q;
+        t2 += xi * xi / u.dinv[i];
+      }
+      break;
+  }
+}
+
+// per node: q = F T^T (sum of element outputs) and the update of mode u.mode
+__global__ __launch_bounds__(256) void k_mg_gather(const double* __restrict__ E, const int32_t* __restrict__ iptr,
+                                                   const int32_t* __restrict__ islot, const double* __restrict__ iw,
+                                                   const uint8_t* __restrict__ flag, int nn, MgUpd u,
+                                                   double* __restrict__ part) {
+  __shared__ double sh[16];
+  double t1 = 0.0, t2 = 0.0;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nn; v += gridDim.x * blockDim.x) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int k = iptr[v]; k < iptr[v + 1]; ++k) {
+      const long sl = islot[k];
+      const double w = iw[k];
+      s0 = fma(w, E[3 * sl], s0);
+      s1 = fma(w, E[3 * sl + 1], s1);
+      s2 = fma(w, E[3 * sl + 2], s2);
+    }
+    const uint8_t f = flag[v];
+    const double s[3] = {s0, s1, s2};
+    for (int c = 0; c < 3; ++c) {
+      const bool cs = mg_cons(f, c);
+      mg_update(u, 3L * v + c, cs, cs ? 0.0 : s[c], t1, t2);
+    }
+  }
+  if (u.mode == MG_RAYLEIGH) {
+    block_sum2(t1, t2, sh);
+    if (threadIdx.x == 0) {
+      part[blockIdx.x] = t1;
+      part[MG_RED + blockIdx.x] = t2;
+    }
+  }
+}
+
+// level 0: the same updates with q from the context's operator
+__global__ __launch_bounds__(256) void k_mg_vec0(const double* __restrict__ q, const uint8_t* __restrict__ flag,
+                                                 int nn, MgUpd u, double* __restrict__ part) {
+  __shared__ double sh[16];
+  double t1 = 0.0, t2 = 0.0;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nn; v += gridDim.x * blockDim.x) {
+    const uint8_t f = flag[v];
+    for (int c = 0; c < 3; ++c) {
+      const bool cs = mg_cons(f, c);
+      mg_update(u, 3L * v + c, cs, cs ? 0.0 : q[3L * v + c], t1, t2);
+    }
+  }
+  if (u.mode == MG_RAYLEIGH) {
+    block_sum2(t1, t2, sh);
+    if (threadIdx.x == 0) {
+      part[blockIdx.x] = t1;
+      part[MG_RED + blockIdx.x] = t2;
+    }
+  }
+}
+
+// b_c = R r_f on the coarse level; with init, the smoother starts there:
+// x = 0, r = b, d = D^-1 b / theta
+__global__ __launch_bounds__(256) void k_mg_restrict(const double* __restrict__ rf, const int32_t* __restrict__ rptr,
+                                                     const int32_t* __restrict__ rcol, const double* __restrict__ rw,
+                                                     const uint8_t* __restrict__ flag, int nn, double* __restrict__ b,
+                                                     int init, double* __restrict__ x, double* __restrict__ r,
+                                                     double* __restrict__ d, const double* __restrict__ dinv,
+                                                     const double* __restrict__ scal) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nn) return;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int k = rptr[v]; k < rptr[v + 1]; ++k) {
+    const long m = rcol[k];
+    const double w = rw[k];
+    s0 = fma(w, rf[3 * m], s0);
+    s1 = fma(w, rf[3 * m + 1], s1);
+    s2 = fma(w, rf[3 * m + 2], s2);
+  }
+  const uint8_t f = flag[v];
+  const double s[3] = {s0, s1, s2};
+  for (int c = 0; c < 3; ++c) {
+    const long i = 3L * v + c;
+    const double bi = mg_cons(f, c) ? 0.0 : s[c];
+    b[i] = bi;
+    if (init) {
+      x[i] = 0.0;
+      r[i] = bi;
+      d[i] = dinv[i] * bi / scal[MS_THETA];
+    }
+  }
+}
+
+// t = P (xc + dc) at the fine nodes; df = t, xf += t
+__global__ __launch_bounds__(256) void k_mg_prolong(const double* __restrict__ xc, const double* __restrict__ dc,
+                                                    const int32_t* __restrict__ pptr, const int32_t* __restrict__ pcol,
+                                                    const double* __restrict__ pw, const uint8_t* __restrict__ flag,
+                                                    int nn, double* __restrict__ xf, double* __restrict__ df) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nn) return;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int k = pptr[v]; k < pptr[v + 1]; ++k) {
+    const long m = pcol[k];
+    const double w = pw[k];
+    s0 = fma(w, xc[3 * m] + (dc ? dc[3 * m] : 0.0), s0);
+    s1 = fma(w, xc[3 * m + 1] + (dc ? dc[3 * m + 1] : 0.0), s1);
+    s2 = fma(w, xc[3 * m + 2] + (dc ? dc[3 * m + 2] : 0.0), s2);
+  }
+  const uint8_t f = flag[v];
+  const double s[3] = {s0, s1, s2};
+  for (int c = 0; c < 3; ++c) {
+    const long i = 3L * v + c;
+    const double t = mg_cons(f, c) ? 0.0 : s[c];
+    df[i] = t;
+    xf[i] += t;
+  }
+}
+
+// plain prolongation (tests): xf = P xc
+__global__ __launch_bounds__(256) void k_mg_prolong_plain(const double* __restrict__ xc,
+                                                          const int32_t* __restrict__ pptr,
+                                                          const int32_t* __restrict__ pcol,
+                                                          const double* __restrict__ pw,
+                                                          const uint8_t* __restrict__ flag, int nn,
+                                                          double* __restrict__ xf) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nn) return;
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int k = pptr[v]; k < pptr[v + 1]; ++k)
+    for (int c = 0; c < 3; ++c) s[c] = fma(pw[k], xc[3L * pcol[k] + c], s[c]);
+  for (int c = 0; c < 3; ++c) xf[3L * v + c] = mg_cons(flag[v], c) ? 0.0 : s[c];
+}
+
+// coarsest level: x = A~^-1 b
+__global__ __launch_bounds__(256) void k_mg_coarse_solve(const double* __restrict__ Ainv,
+                                                         const double* __restrict__ b, double* __restrict__ x, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int j = 0; j < n; ++j) s = fma(Ainv[(long)i * n + j], b[j], s);
+  x[i] = s;
+}
+
+// ---------------------------------------------------------------- set-up kernels
+// weight of parent corner a at corner a2 of the child in octant o (trilinear)
+__device__ __forceinline__ double mg_pw(int o, int a2, int a) {
+  double w = 1.0;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    const double t = 0.5 * (double)(((o >> ax) & 1) + ((a2 >> ax) & 1));  // child corner in parent coordinates
+    w *= ((a >> ax) & 1) ? t : 1.0 - t;
+  }
+  return w;
+}
+
+// dense Galerkin matrix of each merged element: sum over children j of
+// (P_j (x) I3)^T K_j (P_j (x) I3); K_j dense (previous level) or c K0
+__global__ __launch_bounds__(256) void k_mg_galerkin(const int32_t* __restrict__ cptr,
+                                                     const int32_t* __restrict__ celem,
+                                                     const int8_t* __restrict__ coct, int nd,
+                                                     const double* __restrict__ Kd_f, int nd_f,
+                                                     const int32_t* __restrict__ pure_f,
+                                                     const double* __restrict__ coef, const double* __restrict__ K0,
+                                                     double* __restrict__ Kd) {
+  __shared__ double Kc[576], T1[576];
+  const int e = blockIdx.x;
+  if (e >= nd) return;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int k = cptr[e]; k < cptr[e + 1]; ++k) {
+    const int ch = celem[k], o = coct[k];
+    __syncthreads();
+    if (ch < nd_f) {
+      for (int i = threadIdx.x; i < 576; i += blockDim.x) Kc[i] = Kd_f[(long)i * nd_f + ch];
+    } else {
+      const double c = coef[pure_f[ch - nd_f]];
+      for (int i = threadIdx.x; i < 576; i += blockDim.x) Kc[i] = c * K0[i];
+    }
+    __syncthreads();
+    if (o == 8) {
+      for (int i = threadIdx.x, t = 0; i < 576; i += blockDim.x, ++t) acc[t] += Kc[i];
+      continue;
+    }
+    // T1[(a2,c),(b,d)] = sum_b2 Kc[(a2,c),(b2,d)] P[b2][b]
+    for (int i = threadIdx.x; i < 576; i += blockDim.x) {
+      const int row = i / 24, col = i % 24, b = col / 3, dd = col % 3;
+      double s = 0.0;
+      for (int b2 = 0; b2 < 8; ++b2) s = fma(Kc[row * 24 + 3 * b2 + dd], mg_pw(o, b2, b), s);
+      T1[i] = s;
+    }
+    __syncthreads();
+    // acc[(a,c),(b,d)] += sum_a2 P[a2][a] T1[(a2,c),(b,d)]
+    for (int i = threadIdx.x, t = 0; i < 576; i += blockDim.x, ++t) {
+      const int row = i / 24, col = i % 24, a = row / 3, c = row % 3;
+      double s = 0.0;
+      for (int a2 = 0; a2 < 8; ++a2) s = fma(mg_pw(o, a2, a), T1[(3 * a2 + c) * 24 + col], s);
+      acc[t] += s;
+    }
+  }
+  for (int i = threadIdx.x, t = 0; i < 576; i += blockDim.x, ++t) Kd[(long)i * nd + e] = acc[t];
+}
+
+// exact diagonal of A~ on a level: per node and component, over the node's
+// incidences grouped by element, sum t_a t_b K_e[(a,c),(b,c)]
+__global__ __launch_bounds__(256) void k_mg_diag(const int32_t* __restrict__ iptr, const int32_t* __restrict__ islot,
+                                                 const double* __restrict__ iw, const uint8_t* __restrict__ flag,
+                                                 const double* __restrict__ Kd, int nd,
+                                                 const int32_t* __restrict__ pure_src,
+                                                 const double* __restrict__ coef, const double* __restrict__ K0g,
+                                                 double* __restrict__ dinv, int nn) {
+  __shared__ double K0[576];
+  for (int i = threadIdx.x; i < 576; i += blockDim.x) K0[i] = K0g[i];
+  __syncthreads();
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nn) return;
+  double dg[3] = {0.0, 0.0, 0.0};
+  const int k1 = iptr[v + 1];
+  for (int k = iptr[v]; k < k1;) {
+    const int e = islot[k] >> 3;
+    double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int kk = k;
+    while (kk < k1 && (islot[kk] >> 3) == e) {
+      t[islot[kk] & 7] += iw[kk];
+      ++kk;
+    }
+    for (int c = 0; c < 3; ++c) {
+      double s = 0.0;
+      for (int a = 0; a < 8; ++a) {
+        if (t[a] == 0.0) continue;
+        for (int b = 0; b < 8; ++b) {
+          if (t[b] == 0.0) continue;
+          const int i = (3 * a + c) * 24 + 3 * b + c;
+          s += t[a] * t[b] * (e < nd ? Kd[(long)i * nd + e] : K0[i]);
+        }
+      }
+      dg[c] += e < nd ? s : coef[pure_src[e - nd]] * s;
+    }
+    k = kk;
+  }
+  const uint8_t f = flag[v];
+  for (int c = 0; c < 3; ++c) dinv[3L * v + c] = mg_cons(f, c) ? 1.0 : 1.0 / dg[c];
+}
+
+// power-iteration start: +-1 from a counter hash (SplitMix64 finaliser), zero at constrained DOFs
+__global__ __launch_bounds__(256) void k_mg_power_init(double* __restrict__ x, const uint8_t* __restrict__ flag,
+                                                       int nn) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= 3L * nn) return;
+  uint64_t z = (uint64_t)i + 0x9e3779b97f4a7c15ULL;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  z ^= z >> 31;
+  x[i] = mg_cons(flag[i / 3], (int)(i % 3)) ? 0.0 : ((z >> 63) ? 1.0 : -1.0);
+}
+
+// lambda = (x.Ax)/(x.Dx) from the partials, or the caller's value; smoothing interval
+__global__ void k_mg_lambda(const double* __restrict__ part, double* __restrict__ scal, double user, double hi_factor,
+                            double ratio) {
+  __shared__ double sh[16];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < MG_RED; i += blockDim.x) {
+    a += part[i];
+    b += part[MG_RED + i];
+  }
+  block_sum2(a, b, sh);
+  if (threadIdx.x == 0) {
+    const double lam = user > 0.0 ? user : (b > 0.0 ? a / b : 1.0);
+    const double hi = hi_factor * lam, lo = hi / ratio;
+    scal[MS_LAM] = lam;
+    scal[MS_THETA] = 0.5 * (hi + lo);
+    scal[MS_DELTA] = 0.5 * (hi - lo);
+    scal[MS_SIGMA] = (hi + lo) / (hi - lo);
+  }
+}
+
+// coarsest level (no hanging nodes): dense A~ from its element matrices,
+// identity rows and columns for supported DOFs; one workgroup, elements in order
+__global__ __launch_bounds__(1024) void k_mg_coarse_assemble(const int32_t* __restrict__ elem, int ne,
+                                                             const double* __restrict__ Kd, int nd,
+                                                             const int32_t* __restrict__ pure_src,
+                                                             const double* __restrict__ coef,
+                                                             const double* __restrict__ K0,
+                                                             const uint8_t* __restrict__ flag, int n,
+                                                             double* __restrict__ A) {
+  for (long i = threadIdx.x; i < (long)n * n; i += blockDim.x) A[i] = 0.0;
+  __syncthreads();
+  for (int e = 0; e < ne; ++e) {
+    for (int i = threadIdx.x; i < 576; i += blockDim.x) {
+      const int row = i / 24, col = i % 24;
+      const int I = 3 * elem[8L * e + row / 3] + row % 3, J = 3 * elem[8L * e + col / 3] + col % 3;
+      const double k = e < nd ? Kd[(long)i * nd + e] : coef[pure_src[e - nd]] * K0[i];
+      A[(long)I * n + J] += k;
+    }
+    __syncthreads();
+  }
+  for (long i = threadIdx.x; i < (long)n * n; i += blockDim.x) {
+    const int I = (int)(i / n), J = (int)(i % n);
+    const bool ci = mg_cons(flag[I / 3], I % 3), cj = mg_cons(flag[J / 3], J % 3);
+    if (ci || cj) A[i] = (I == J) ? 1.0 : 0.0;
+  }
+}
+
+// in-place Gauss-Jordan inverse of an SPD matrix (no pivoting); one workgroup
+__global__ __launch_bounds__(1024) void k_mg_invert(double* __restrict__ A, int n) {
+  __shared__ double col[MG_COARSE_MAX], row[MG_COARSE_MAX];
+  for (int k = 0; k < n; ++k) {
+    const double piv = 1.0 / A[(long)k * n + k];
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      col[j] = A[(long)j * n + k];
+      row[j] = (j == k ? 1.0 : A[(long)k * n + j]) * piv;
+    }
+    __syncthreads();
+    for (long i = threadIdx.x; i < (long)n * n; i += blockDim.x) {
+      const int I = (int)(i / n), J = (int)(i % n);
+      if (I == k) {
+        A[i] = row[J];
+      } else {
+        const double a = (J == k) ? 0.0 : A[i];
+        A[i] = a - col[I] * row[J];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- PCG kernels
+__global__ __launch_bounds__(256) void k_mgcg_init(const double* __restrict__ b, const double* __restrict__ q,
+                                                   const uint8_t* __restrict__ flag, double* __restrict__ r, long n,
+                                                   double* __restrict__ part) {
+  __shared__ double sh[16];
+  double rr = 0.0, bb = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const bool cs = mg_cons(flag[i / 3], (int)(i % 3));
+    const double bi = cs ? 0.0 : b[i];
+    const double ri = cs ? 0.0 : bi - q[i];
+    r[i] = ri;
+    rr += ri * ri;
+    bb += bi * bi;
+  }
+  block_sum2(rr, bb, sh);
+  if (threadIdx.x == 0) {
+    part[2 * MG_RED + blockIdx.x] = rr;
+    part[3 * MG_RED + blockIdx.x] = bb;
+  }
+}
+
+__global__ void k_mgcg_init_scal(const double* __restrict__ part, double* __restrict__ cg, double tol2) {
+  __shared__ double sh[16];
+  double rr = 0.0, bb = 0.0;
+  for (int i = threadIdx.x; i < MG_RED; i += blockDim.x) {
+    rr += part[2 * MG_RED + i];
+    bb += part[3 * MG_RED + i];
+  }
+  block_sum2(rr, bb, sh);
+  if (threadIdx.x == 0) {
+    cg[MC_BB] = bb;
+    cg[MC_RR] = rr;
+    cg[MC_ITERS] = 0.0;
+    cg[MC_RZ] = 0.0;
+    cg[MC_DONE] = (rr <= tol2 * bb) ? 1.0 : ((rr == rr && rr < 1e300) ? 0.0 : 2.0);
+  }
+}
+
+// z = x0 + d0 (the V-cycle's last correction folded in); partials of r.z
+__global__ __launch_bounds__(256) void k_mgcg_rz(const double* __restrict__ x0, const double* __restrict__ d0,
+                                                 const double* __restrict__ r, double* __restrict__ z, long n,
+                                                 double* __restrict__ part, const double* __restrict__ cg) {
+  __shared__ double sh[16];
+  if (cg && cg[MC_DONE] != 0.0) return;
+  double s = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double zi = x0[i] + d0[i];
+    z[i] = zi;
+    s += r[i] * zi;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// p = z + beta p with beta = r.z / (r.z)_old (beta = 0 on the first iteration)
+__global__ __launch_bounds__(256) void k_mgcg_dir(const double* __restrict__ z, double* __restrict__ p, long n,
+                                                  const double* __restrict__ part, double* __restrict__ cg,
+                                                  int first) {
+  __shared__ double sh[16];
+  const double rz = sum_partials(part, MG_RED, sh);
+  if (cg[MC_DONE] != 0.0) return;
+  const double beta = first ? 0.0 : rz / cg[MC_RZ];
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+  // every block has read the old r.z before any block can run the next kernel
+  if (blockIdx.x == 0 && threadIdx.x == 0) cg[MC_RZ + 6] = rz;
+}
+
+__global__ __launch_bounds__(256) void k_mgcg_pq(const double* __restrict__ p, const double* __restrict__ q, long n,
+                                                 double* __restrict__ part, double* __restrict__ cg) {
+  __shared__ double sh[16];
+  if (cg[MC_DONE] != 0.0) return;
+  double s = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    s += p[i] * q[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[MG_RED + blockIdx.x] = s;
+  if (blockIdx.x == 0 && threadIdx.x == 0) cg[MC_RZ] = cg[MC_RZ + 6];
+}
+
+__global__ __launch_bounds__(256) void k_mgcg_update(double* __restrict__ x, double* __restrict__ r,
+                                                     const double* __restrict__ p, const double* __restrict__ q,
+                                                     long n, double* __restrict__ part, double* __restrict__ cg) {
+  __shared__ double sh[16];
+  const double pq = sum_partials(part + MG_RED, MG_RED, sh);
+  if (cg[MC_DONE] != 0.0) return;
+  if (!(pq > 0.0) || !(pq < 1e300)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) cg[MC_DONE] = 2.0;
+    return;
+  }
+  const double alpha = cg[MC_RZ] / pq;
+  double rr = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    rr += ri * ri;
+  }
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) part[2 * MG_RED + blockIdx.x] = rr;
+}
+
+__global__ void k_mgcg_check(const double* __restrict__ part, double* __restrict__ cg, int it, double tol2) {
+  __shared__ double sh[16];
+  const double rr = sum_partials(part + 2 * MG_RED, MG_RED, sh);
+  if (threadIdx.x != 0 || cg[MC_DONE] != 0.0) return;
+  cg[MC_RR] = rr;
+  cg[MC_ITERS] = it + 1;
+  if (!(rr == rr) || rr > 1e300) cg[MC_DONE] = 2.0;
+  else if (rr <= tol2 * cg[MC_BB]) cg[MC_DONE] = 1.0;
+}
+
+__global__ __launch_bounds__(256) void k_mgcg_resid(const double* __restrict__ b, const double* __restrict__ q,
+                                                    const uint8_t* __restrict__ flag, long n,
+                                                    double* __restrict__ part) {
+  __shared__ double sh[16];
+  double rr = 0.0, bb = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    if (mg_cons(flag[i / 3], (int)(i % 3))) continue;
+    const double ri = b[i] - q[i];
+    rr += ri * ri;
+    bb += b[i] * b[i];
+  }
+  block_sum2(rr, bb, sh);
+  if (threadIdx.x == 0) {
+    part[2 * MG_RED + blockIdx.x] = rr;
+    part[3 * MG_RED + blockIdx.x] = bb;
+  }
+}
+
+__global__ void k_mgcg_resid_scal(const double* __restrict__ part, double* __restrict__ cg) {
+  __shared__ double sh[16];
+  double rr = 0.0, bb = 0.0;
+  for (int i = threadIdx.x; i < MG_RED; i += blockDim.x) {
+    rr += part[2 * MG_RED + i];
+    bb += part[3 * MG_RED + i];
+  }
+  block_sum2(rr, bb, sh);
+  if (threadIdx.x == 0) cg[MC_RES] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_mg_mask_copy(const double* __restrict__ src, double* __restrict__ dst,
+                                                      const uint8_t* __restrict__ flag, long n) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = mg_cons(flag[i / 3], (int)(i % 3)) ? 0.0 : src[i];
+}
+
+// ---------------------------------------------------------------- host side
+int blocks_for(long n) { return (int)std::max<long>(1, std::min<long>((n + 255) / 256, 1L << 20)); }
+
+// q = A_k d on level k >= 1 (element pass), then the gather pass with update u
+int level_pass(amrto_ctx* ctx, MgLevel& L, const double* in, const MgUpd& u, double* part) {
+  hipLaunchKernelGGL(k_mg_elem, dim3(blocks_for(L.ne)), dim3(256), 0, ctx->stream, in, L.elem, L.flag, L.hang_of,
+                     L.hptr, L.hm, L.hw, L.Kd, L.nd, L.pure_src, ctx->d_coef, ctx->d_K0, L.E, L.ne);
+  // the Rayleigh partials fill exactly MG_RED slots
+  const int grid = u.mode == MG_RAYLEIGH ? MG_RED : blocks_for(L.nn);
+  hipLaunchKernelGGL(k_mg_gather, dim3(grid), dim3(256), 0, ctx->stream, L.E, L.iptr,
+                     L.islot, L.iw, L.flag, L.nn, u, part);
+  return hipGetLastError() == hipSuccess ? AMRTO_OK : ctx->fail(AMRTO_EHIP, "multigrid level pass");
+}
+
+// level 0: q = A~ d through the context's operator, then the vector update
+int level0_pass(amrto_ctx* ctx, MgLevel& L, const double* in, const MgUpd& u, double* part) {
+  int rc = launch_apply(ctx, in, L.q, AMRTO_FP64);
+  if (rc) return rc;
+  const int grid = u.mode == MG_RAYLEIGH ? MG_RED : blocks_for(L.nn);
+  hipLaunchKernelGGL(k_mg_vec0, dim3(grid), dim3(256), 0, ctx->stream, L.q, L.flag,
+                     L.nn, u, part);
+  return hipGetLastError() == hipSuccess ? AMRTO_OK : ctx->fail(AMRTO_EHIP, "multigrid level-0 pass");
+}
+
+int pass(amrto_ctx* ctx, int k, const double* in, const MgUpd& u) {
+  MgData* g = ctx->mg;
+  return k == 0 ? level0_pass(ctx, g->lv[0], in, u, g->part) : level_pass(ctx, g->lv[k], in, u, g->part);
+}
+
+MgUpd upd(MgLevel& L, int mode, int step = 0) {
+  MgUpd u{};
+  u.mode = mode;
+  u.step = step;
+  u.scal = L.scal;
+  u.dinv = L.dinv;
+  u.x = L.x;
+  u.r = L.r;
+  u.d = L.d;
+  return u;
+}
+
+// one V-cycle below level k; level k's b holds the right-hand side and, for
+// k < coarsest, its smoother state was initialised by the restriction
+int vcycle_from(amrto_ctx* ctx, int k) {
+  MgData* g = ctx->mg;
+  MgLevel& L = g->lv[k];
+  int rc;
+  if (k == g->nlev - 1) {
+    const int n = 3 * L.nn;
+    hipLaunchKernelGGL(k_mg_coarse_solve, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, L.Ainv, L.b, L.x, n);
+    return hipGetLastError() == hipSuccess ? AMRTO_OK : ctx->fail(AMRTO_EHIP, "multigrid coarse solve");
+  }
+  const int m = g->degree;
+  for (int s = 0; s < m; ++s)
+    if ((rc = pass(ctx, k, L.d, upd(L, s == m - 1 ? MG_CHEB_LAST : MG_CHEB, s)))) return rc;
+  MgLevel& C = g->lv[k + 1];
+  const bool coarsest = k + 1 == g->nlev - 1;
+  hipLaunchKernelGGL(k_mg_restrict, dim3(blocks_for(C.nn)), dim3(256), 0, ctx->stream, L.r, C.rptr, C.rcol, C.rw,
+                     C.flag, C.nn, C.b, coarsest ? 0 : 1, C.x, C.r, C.d, C.dinv, C.scal);
+  if ((rc = vcycle_from(ctx, k + 1))) return rc;
+  // x += P x_c (the coarse level's last correction d folded in), d = that correction
+  hipLaunchKernelGGL(k_mg_prolong, dim3(blocks_for(L.nn)), dim3(256), 0, ctx->stream, C.x,
+                     coarsest ? (const double*)nullptr : C.d, C.pptr, C.pcol, C.pw, L.flag, L.nn, L.x, L.d);
+  if ((rc = pass(ctx, k, L.d, upd(L, MG_CORR)))) return rc;
+  // post-smoothing: m - 1 passes; the last correction stays in d (added by the consumer)
+  for (int s = 0; s < m - 1; ++s)
+    if ((rc = pass(ctx, k, L.d, upd(L, MG_CHEB, s)))) return rc;
+  return hipGetLastError() == hipSuccess ? AMRTO_OK : ctx->fail(AMRTO_EHIP, "multigrid V-cycle");
+}
+
+// level-0 smoother start from the right-hand side b (device): x = 0, r = b, d = D^-1 b / theta
+__global__ __launch_bounds__(256) void k_mg_start0(const double* __restrict__ b, const uint8_t* __restrict__ flag,
+                                                   const double* __restrict__ dinv, const double* __restrict__ scal,
+                                                   double* __restrict__ x, double* __restrict__ r,
+                                                   double* __restrict__ d, long n) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double bi = mg_cons(flag[i / 3], (int)(i % 3)) ? 0.0 : b[i];
+  x[i] = 0.0;
+  r[i] = bi;
+  d[i] = dinv[i] * bi / scal[MS_THETA];
+}
+
+int vcycle(amrto_ctx* ctx, const double* b) {
+  MgData* g = ctx->mg;
+  MgLevel& L = g->lv[0];
+  const long n = 3L * L.nn;
+  hipLaunchKernelGGL(k_mg_start0, dim3(blocks_for(n)), dim3(256), 0, ctx->stream, b, L.flag, L.dinv, L.scal, L.x,
+                     L.r, L.d, n);
+  return vcycle_from(ctx, 0);
+}
+
+// numeric set-up after a density change: Galerkin matrices, diagonals,
+// smoothing intervals, coarsest inverse
+int mg_numeric(amrto_ctx* ctx) {
+  MgData* g = ctx->mg;
+  g->lv[0].dinv = ctx->d_dinv;
+  for (int k = 1; k < g->nlev; ++k) {
+    MgLevel& L = g->lv[k];
+    MgLevel& F = g->lv[k - 1];
+    if (L.nd > 0)
+      hipLaunchKernelGGL(k_mg_galerkin, dim3(L.nd), dim3(256), 0, ctx->stream, L.cptr, L.celem, L.coct, L.nd, F.Kd,
+                         F.nd, F.pure_src, ctx->d_coef, ctx->d_K0, L.Kd);
+    hipLaunchKernelGGL(k_mg_diag, dim3(blocks_for(L.nn)), dim3(256), 0, ctx->stream, L.iptr, L.islot, L.iw, L.flag,
+                       L.Kd, L.nd, L.pure_src, ctx->d_coef, ctx->d_K0, L.dinv, L.nn);
+  }
+  if (hipGetLastError() != hipSuccess) return ctx->fail(AMRTO_EHIP, "multigrid Galerkin set-up");
+  // lambda_max of D^-1 A on every smoothed level by power iteration
+  for (int k = 0; k < g->nlev - 1; ++k) {
+    MgLevel& L = g->lv[k];
+    const long n = 3L * L.nn;
+    int rc;
+    if (!g->user_bounds) {
+      hipLaunchKernelGGL(k_mg_power_init, dim3(blocks_for(n)), dim3(256), 0, ctx->stream, L.x, L.flag, L.nn);
+      for (int it = 0; it < g->power_its; ++it) {
+        MgUpd u = upd(L, MG_POWER);
+        u.y = (it & 1) ? L.x : L.r;
+        if ((rc = pass(ctx, k, (it & 1) ? L.r : L.x, u))) return rc;
+      }
+      const double* xl = (g->power_its & 1) ? L.r : L.x;
+      MgUpd u = upd(L, MG_RAYLEIGH);
+      u.xin = xl;
+      if ((rc = pass(ctx, k, xl, u))) return rc;
+    }
+    hipLaunchKernelGGL(k_mg_lambda, dim3(1), dim3(256), 0, ctx->stream, g->part, L.scal,
+                       g->user_bounds ? g->lam_user[k] : 0.0, g->hi_factor, g->ratio);
+  }
+  MgLevel& C = g->lv[g->nlev - 1];
+  const int n = 3 * C.nn;
+  hipLaunchKernelGGL(k_mg_coarse_assemble, dim3(1), dim3(1024), 0, ctx->stream, C.elem, C.ne, C.Kd, C.nd,
+                     C.pure_src, ctx->d_coef, ctx->d_K0, C.flag, n, C.Ainv);
+  hipLaunchKernelGGL(k_mg_invert, dim3(1), dim3(1024), 0, ctx->stream, C.Ainv, n);
+  if (hipGetLastError() != hipSuccess) return ctx->fail(AMRTO_EHIP, "multigrid coarse set-up");
+  ctx->mg_valid = true;
+  return AMRTO_OK;
+}
+
+}  // namespace
+
+namespace amrto {
+
+void mg_free(amrto_ctx* ctx) {
+  if (!ctx->mg) return;
+  MgData* g = ctx->mg;
+  for (int k = 0; k < g->nlev; ++k)
+    for (void* p : g->lv[k].owned) (void)hipFree(p);
+  for (void* p : g->owned) (void)hipFree(p);
+  if (g->h_cg) (void)hipHostFree(g->h_cg);
+  delete g;
+  ctx->mg = nullptr;
+  ctx->mg_valid = false;
+}
+
+}  // namespace amrto
+
+// ---------------------------------------------------------------- hierarchy (host)
+namespace {
+
+struct HostLevel {
+  LevelMesh m;
+  std::vector<int32_t> perm;      // original element -> device order
+  std::vector<int32_t> parent;    // original element -> parent on the next level (original order there)
+  std::vector<int8_t> oct;        // octant within the parent, 8 = the same box
+  std::vector<uint8_t> pure;      // per original element
+  std::vector<int32_t> src;       // per original element: coefficient index when pure
+  int nd = 0;
+};
+
+// lattice coordinates stay below 2^20 (octree limits); a point is the anchor
+// of at most one leaf of a level
+inline uint64_t anchor_key(int64_t x, int64_t y, int64_t z) {
+  return ((uint64_t)z << 40) | ((uint64_t)y << 20) | (uint64_t)x;
+}
+
+int build_hierarchy(amrto_ctx* ctx, const amrto_octree* tree, int coarse_dofs, std::vector<HostLevel>& H) {
+  H.clear();
+  H.emplace_back();
+  if (!octree_level_mesh(tree, 0, &H[0].m)) return ctx->fail(AMRTO_ESTATE, "amrto_mg_setup: the tree has no mesh");
+  if (H[0].m.n_nodes != ctx->n_nodes || H[0].m.n_elems != ctx->n_elems)
+    return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: the tree's mesh is not the uploaded mesh");
+  const int L = H[0].m.L;
+  for (int k = 1;; ++k) {
+    const LevelMesh& prev = H.back().m;
+    const bool uniform_prev = k - 1 >= L;  // levels >= L are uniform grids
+    if (uniform_prev && 3 * prev.n_nodes <= coarse_dofs) break;
+    if (k >= MG_LMAX) break;
+    LevelMesh lm;
+    if (!octree_level_mesh(tree, k, &lm)) break;
+    H.emplace_back();
+    H.back().m = std::move(lm);
+  }
+  const HostLevel& C = H.back();
+  if (!C.m.hang_node.empty() || 3 * C.m.n_nodes > MG_COARSE_MAX || H.size() < 2)
+    return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: no coarsest uniform level with at most 1024 DOFs "
+                                   "(base extents must allow coarsening)");
+  // level 0: every element is its own coefficient
+  HostLevel& F0 = H[0];
+  const int ne0 = F0.m.n_elems;
+  F0.pure.assign(ne0, 1);
+  F0.src.resize(ne0);
+  for (int e = 0; e < ne0; ++e) {
+    if (ctx->uniform) {
+      const int32_t* a = &F0.m.anchor[3L * e];
+      F0.src[e] = a[0] + ctx->nx * (a[1] + ctx->ny * a[2]);
+    } else {
+      F0.src[e] = e;
+    }
+  }
+  F0.nd = 0;
+  F0.perm.resize(ne0);
+  for (int e = 0; e < ne0; ++e) F0.perm[e] = e;
+  // parents, purity and device element order level by level
+  for (size_t k = 1; k < H.size(); ++k) {
+    HostLevel& F = H[k - 1];
+    HostLevel& Cl = H[k];
+    const int ne = Cl.m.n_elems;
+    std::unordered_map<uint64_t, int> box;
+    box.reserve(2L * ne);
+    for (int e = 0; e < ne; ++e)
+      box.emplace(anchor_key(Cl.m.anchor[3L * e], Cl.m.anchor[3L * e + 1], Cl.m.anchor[3L * e + 2]), e);
+    std::vector<int> nchild(ne, 0), only(ne, -1);
+    F.parent.resize(F.m.n_elems);
+    F.oct.resize(F.m.n_elems);
+    for (int e = 0; e < F.m.n_elems; ++e) {
+      const int64_t s = 1L << (F.m.L - F.m.level[e]);
+      const int32_t* a = &F.m.anchor[3L * e];
+      int found = -1, o = 8;
+      for (int64_t S : {s, 2 * s}) {
+        auto it = box.find(anchor_key(a[0] / S * S, a[1] / S * S, a[2] / S * S));
+        if (it != box.end() && (1L << (Cl.m.L - Cl.m.level[it->second])) == S) {
+          found = it->second;
+          if (S != s) o = (int)(((a[0] / s) & 1) | (((a[1] / s) & 1) << 1) | (((a[2] / s) & 1) << 2));
+          break;
+        }
+      }
+      if (found < 0) return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: a leaf has no parent on the next level");
+      F.parent[e] = found;
+      F.oct[e] = (int8_t)o;
+      nchild[found]++;
+      only[found] = e;
+    }
+    Cl.pure.assign(ne, 0);
+    Cl.src.assign(ne, -1);
+    for (int e = 0; e < ne; ++e)
+      if (nchild[e] == 1 && F.oct[only[e]] == 8 && F.pure[only[e]]) {
+        Cl.pure[e] = 1;
+        Cl.src[e] = F.src[only[e]];
+      }
+    Cl.perm.assign(ne, -1);
+    int nd = 0;
+    for (int e = 0; e < ne; ++e)
+      if (!Cl.pure[e]) Cl.perm[e] = nd++;
+    int np = nd;
+    for (int e = 0; e < ne; ++e)
+      if (Cl.pure[e]) Cl.perm[e] = np++;
+    Cl.nd = nd;
+  }
+  return AMRTO_OK;
+}
+
+int upload_level(amrto_ctx* ctx, MgData* g, std::vector<HostLevel>& H, int k) {
+  MgLevel& L = g->lv[k];
+  HostLevel& h = H[k];
+  const LevelMesh& m = h.m;
+  auto& own = L.owned;
+  L.nn = m.n_nodes;
+  L.ne = m.n_elems;
+  L.nd = h.nd;
+  L.nh = (int)m.hang_node.size();
+  const int nn = m.n_nodes, ne = m.n_elems;
+  std::vector<int32_t> hang_of(nn, -1);
+  for (int i = 0; i < L.nh; ++i) hang_of[m.hang_node[i]] = i;
+  std::vector<uint8_t> flag(nn, 0);
+  for (int v = 0; v < nn; ++v) {
+    for (int c = 0; c < 3; ++c)
+      if (m.fixed[3L * v + c]) flag[v] |= (uint8_t)(1 << c);
+    if (hang_of[v] >= 0) flag[v] |= 8;
+  }
+  AMRTO_HIP(mg_upload(own, L.flag, flag));
+  const long n3 = 3L * nn;
+  AMRTO_HIP(mg_alloc(own, L.x, n3));
+  AMRTO_HIP(mg_alloc(own, L.r, n3));
+  AMRTO_HIP(mg_alloc(own, L.d, n3));
+  AMRTO_HIP(mg_alloc(own, L.q, n3));
+  AMRTO_HIP(mg_alloc(own, L.b, n3));
+  AMRTO_HIP(mg_alloc(own, L.scal, MS_COUNT));
+  if (k == 0) {
+    // every level-0 element is a leaf with its own coefficient (read by the
+    // level-1 Galerkin pass)
+    for (int32_t i : h.src)
+      if (i < 0 || i >= ctx->n_elems) return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: bad level-0 element");
+    AMRTO_HIP(mg_upload(own, L.pure_src, h.src));
+    return AMRTO_OK;
+  }
+  AMRTO_HIP(mg_alloc(own, L.dinv, n3));
+  // elements in device order
+  std::vector<int32_t> elem(8L * ne), psrc(ne - h.nd);
+  for (int e = 0; e < ne; ++e) {
+    const int de = h.perm[e];
+    for (int a = 0; a < 8; ++a) elem[8L * de + a] = m.elem_nodes[8L * e + a];
+    if (h.pure[e]) psrc[de - h.nd] = h.src[e];
+  }
+  AMRTO_HIP(mg_upload(own, L.elem, elem));
+  AMRTO_HIP(mg_upload(own, L.pure_src, psrc));
+  AMRTO_HIP(mg_alloc(own, L.Kd, 576L * h.nd));
+  AMRTO_HIP(mg_alloc(own, L.E, 24L * ne));
+  // hanging table
+  std::vector<int32_t> hptr(m.hang_ptr.begin(), m.hang_ptr.end());
+  if (hptr.empty()) hptr.push_back(0);
+  AMRTO_HIP(mg_upload(own, L.hang_of, hang_of));
+  AMRTO_HIP(mg_upload(own, L.hptr, hptr));
+  AMRTO_HIP(mg_upload(own, L.hm, m.hang_master));
+  AMRTO_HIP(mg_upload(own, L.hw, m.hang_w));
+  // incidences per node (slot 8 e + a in device order), sorted by slot
+  std::vector<std::vector<std::pair<int32_t, double>>> inc(nn);
+  for (int e = 0; e < ne; ++e)
+    for (int a = 0; a < 8; ++a) {
+      const int v = m.elem_nodes[8L * e + a];
+      const int32_t slot = 8 * h.perm[e] + a;
+      if (hang_of[v] < 0) {
+        inc[v].push_back({slot, 1.0});
+      } else {
+        const int hh = hang_of[v];
+        for (int j = m.hang_ptr[hh]; j < m.hang_ptr[hh + 1]; ++j) inc[m.hang_master[j]].push_back({slot, m.hang_w[j]});
+      }
+    }
+  std::vector<int32_t> iptr(nn + 1, 0), islot;
+  std::vector<double> iw;
+  for (int v = 0; v < nn; ++v) {
+    std::sort(inc[v].begin(), inc[v].end());
+    for (auto& sw : inc[v]) {
+      islot.push_back(sw.first);
+      iw.push_back(sw.second);
+    }
+    iptr[v + 1] = (int32_t)islot.size();
+  }
+  AMRTO_HIP(mg_upload(own, L.iptr, iptr));
+  AMRTO_HIP(mg_upload(own, L.islot, islot));
+  AMRTO_HIP(mg_upload(own, L.iw, iw));
+  // children of the dense elements (previous level, its device order)
+  HostLevel& F = H[k - 1];
+  std::vector<std::vector<std::pair<int32_t, int8_t>>> ch(h.nd);
+  for (int e = 0; e < F.m.n_elems; ++e) {
+    const int de = h.perm[F.parent[e]];
+    if (de < h.nd) ch[de].push_back({F.perm[e], F.oct[e]});
+  }
+  std::vector<int32_t> cptr(h.nd + 1, 0), celem;
+  std::vector<int8_t> coct;
+  for (int e = 0; e < h.nd; ++e) {
+    std::sort(ch[e].begin(), ch[e].end());
+    for (auto& c : ch[e]) {
+      celem.push_back(c.first);
+      coct.push_back(c.second);
+    }
+    cptr[e + 1] = (int32_t)celem.size();
+  }
+  AMRTO_HIP(mg_upload(own, L.cptr, cptr));
+  AMRTO_HIP(mg_upload(own, L.celem, celem));
+  AMRTO_HIP(mg_upload(own, L.coct, coct));
+  // prolongation rows (previous level's nodes) from this level's masters
+  const LevelMesh& fm = F.m;
+  std::vector<std::vector<std::pair<int32_t, double>>> prow(fm.n_nodes);
+  std::vector<uint8_t> done(fm.n_nodes, 0);
+  std::vector<int32_t> fh(fm.n_nodes, -1);
+  for (size_t i = 0; i < fm.hang_node.size(); ++i) fh[fm.hang_node[i]] = (int32_t)i;
+  for (int e = 0; e < fm.n_elems; ++e) {
+    const int C = F.parent[e];
+    const double S = (double)(1L << (m.L - m.level[C]));
+    const int32_t* ca = &m.anchor[3L * C];
+    for (int a = 0; a < 8; ++a) {
+      const int v = fm.elem_nodes[8L * e + a];
+      if (done[v] || fh[v] >= 0) continue;
+      done[v] = 1;
+      double xi[3];
+      for (int ax = 0; ax < 3; ++ax) xi[ax] = (fm.xyz[3L * v + ax] - ca[ax]) / S;
+      std::unordered_map<int32_t, double> acc;
+      for (int b = 0; b < 8; ++b) {
+        double w = 1.0;
+        for (int ax = 0; ax < 3; ++ax) w *= ((b >> ax) & 1) ? xi[ax] : 1.0 - xi[ax];
+        if (w == 0.0) continue;
+        const int cn = m.elem_nodes[8L * C + b];
+        if (hang_of[cn] < 0) {
+          acc[cn] += w;
+        } else {
+          const int hh = hang_of[cn];
+          for (int j = m.hang_ptr[hh]; j < m.hang_ptr[hh + 1]; ++j) acc[m.hang_master[j]] += w * m.hang_w[j];
+        }
+      }
+      for (auto& kv : acc) prow[v].push_back(kv);
+      std::sort(prow[v].begin(), prow[v].end());
+    }
+  }
+  std::vector<int32_t> pptr(fm.n_nodes + 1, 0), pcol;
+  std::vector<double> pw;
+  std::vector<std::vector<std::pair<int32_t, double>>> rrow(nn);
+  for (int v = 0; v < fm.n_nodes; ++v) {
+    for (auto& cw : prow[v]) {
+      pcol.push_back(cw.first);
+      pw.push_back(cw.second);
+      rrow[cw.first].push_back({v, cw.second});
+    }
+    pptr[v + 1] = (int32_t)pcol.size();
+  }
+  std::vector<int32_t> rptr(nn + 1, 0), rcol;
+  std::vector<double> rw;
+  for (int v = 0; v < nn; ++v) {
+    for (auto& fw : rrow[v]) {  // already in fine-node order
+      rcol.push_back(fw.first);
+      rw.push_back(fw.second);
+    }
+    rptr[v + 1] = (int32_t)rcol.size();
+  }
+  // every index a kernel follows must stay inside its target array
+  auto in_range = [](const std::vector<int32_t>& v, long lim) {
+    for (int32_t i : v)
+      if (i < 0 || i >= lim) return false;
+    return true;
+  };
+  if (!in_range(elem, nn) || !in_range(psrc, ctx->n_elems) || !in_range(m.hang_master, nn) ||
+      !in_range(islot, 8L * ne) || !in_range(celem, F.m.n_elems) || !in_range(pcol, nn) ||
+      !in_range(rcol, fm.n_nodes) || (long)iptr.back() != (long)islot.size() ||
+      (long)pptr.back() != (long)pcol.size() || (long)rptr.back() != (long)rcol.size() ||
+      (long)cptr.back() != (long)celem.size() || (!hptr.empty() && (long)hptr.back() != (long)m.hang_master.size()))
+    return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: inconsistent level tables");
+  for (size_t i = 0; i < celem.size(); ++i)
+    if (coct[i] < 0 || coct[i] > 8) return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: bad child octant");
+  AMRTO_HIP(mg_upload(own, L.pptr, pptr));
+  AMRTO_HIP(mg_upload(own, L.pcol, pcol));
+  AMRTO_HIP(mg_upload(own, L.pw, pw));
+  AMRTO_HIP(mg_upload(own, L.rptr, rptr));
+  AMRTO_HIP(mg_upload(own, L.rcol, rcol));
+  AMRTO_HIP(mg_upload(own, L.rw, rw));
+  if (k == g->nlev - 1) AMRTO_HIP(mg_alloc(own, L.Ainv, (size_t)n3 * n3));
+  return AMRTO_OK;
+}
+
+int check_mg(amrto_ctx* ctx, const char* name) {
+  if (!ctx) return AMRTO_EINVAL;
+  if (!ctx->mg) return ctx->fail(AMRTO_ESTATE, std::string(name) + ": no multigrid hierarchy (amrto_mg_setup)");
+  if (!ctx->has_density) return ctx->fail(AMRTO_ESTATE, std::string(name) + ": density not set");
+  return AMRTO_OK;
+}
+
+int ensure_numeric(amrto_ctx* ctx) { return ctx->mg_valid ? AMRTO_OK : mg_numeric(ctx); }
+
+}  // namespace
+
+extern "C" {
+
+int amrto_mg_setup(amrto_ctx* ctx, const amrto_octree* tree, const amrto_mg_opts* opts) {
+  if (!ctx) return AMRTO_EINVAL;
+  if (!ctx->has_mesh) return ctx->fail(AMRTO_ESTATE, "amrto_mg_setup: no mesh uploaded");
+  if (!tree) return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: NULL tree");
+  amrto_mg_opts o{2, 10.0, 20, 1.1, 200};
+  if (opts) o = *opts;
+  if (o.degree < 1 || o.degree > 8 || !(o.ratio > 1.0) || o.power_its < 1 || o.power_its > 200 ||
+      !(o.hi_factor >= 1.0) || o.coarse_dofs < 3)
+    return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: bad options");
+  AMRTO_HIP(hipSetDevice(ctx->device));
+  AMRTO_HIP(hipStreamSynchronize(ctx->stream));
+  mg_free(ctx);
+  std::vector<HostLevel> H;
+  int rc = build_hierarchy(ctx, tree, o.coarse_dofs, H);
+  if (rc) return rc;
+  MgData* g = new (std::nothrow) MgData();
+  if (!g) return ctx->fail(AMRTO_ENOMEM, "amrto_mg_setup: out of host memory");
+  ctx->mg = g;
+  g->nlev = (int)H.size();
+  g->degree = o.degree;
+  g->ratio = o.ratio;
+  g->power_its = o.power_its;
+  g->hi_factor = o.hi_factor;
+  for (int k = 0; k < g->nlev; ++k)
+    if ((rc = upload_level(ctx, g, H, k))) {
+      mg_free(ctx);
+      return rc;
+    }
+  const long n0 = 3L * ctx->n_nodes;
+  if (mg_alloc(g->owned, g->part, 4 * MG_RED) != hipSuccess || mg_alloc(g->owned, g->cg, MC_COUNT) != hipSuccess ||
+      mg_alloc(g->owned, g->z, n0) != hipSuccess || mg_alloc(g->owned, g->p, n0) != hipSuccess ||
+      mg_alloc(g->owned, g->qv, n0) != hipSuccess ||
+      hipHostMalloc((void**)&g->h_cg, MC_COUNT * sizeof(double)) != hipSuccess) {
+    mg_free(ctx);
+    return ctx->fail(AMRTO_ENOMEM, "amrto_mg_setup: out of device memory");
+  }
+  ctx->mg_valid = false;
+  return AMRTO_OK;
+}
+
+int amrto_mg_info(amrto_ctx* ctx, int32_t* n_levels, int32_t* dofs, int32_t* dense) {
+  if (!ctx) return AMRTO_EINVAL;
+  if (!ctx->mg) return ctx->fail(AMRTO_ESTATE, "amrto_mg_info: no multigrid hierarchy");
+  MgData* g = ctx->mg;
+  if (n_levels) *n_levels = g->nlev;
+  for (int k = 0; k < g->nlev; ++k) {
+    if (dofs) dofs[k] = 3 * g->lv[k].nn;
+    if (dense) dense[k] = g->lv[k].nd;
+  }
+  return AMRTO_OK;
+}
+
+int amrto_mg_set_bounds(amrto_ctx* ctx, const double* lam) {
+  if (!ctx) return AMRTO_EINVAL;
+  if (!ctx->mg) return ctx->fail(AMRTO_ESTATE, "amrto_mg_set_bounds: no multigrid hierarchy");
+  MgData* g = ctx->mg;
+  if (lam) {
+    for (int k = 0; k < g->nlev - 1; ++k)
+      if (!(lam[k] > 0.0)) return ctx->fail(AMRTO_EINVAL, "amrto_mg_set_bounds: lambda must be positive");
+    for (int k = 0; k < g->nlev - 1; ++k) g->lam_user[k] = lam[k];
+  }
+  g->user_bounds = lam != nullptr;
+  ctx->mg_valid = false;
+  return AMRTO_OK;
+}
+
+int amrto_mg_get_bounds(amrto_ctx* ctx, double* lam) {
+  int rc = check_mg(ctx, "amrto_mg_get_bounds");
+  if (rc) return rc;
+  if (!lam) return ctx->fail(AMRTO_EINVAL, "amrto_mg_get_bounds: NULL output");
+  AMRTO_HIP(hipSetDevice(ctx->device));
+  if ((rc = ensure_numeric(ctx))) return rc;
+  MgData* g = ctx->mg;
+  for (int k = 0; k < g->nlev - 1; ++k)
+    AMRTO_HIP(hipMemcpyAsync(&lam[k], g->lv[k].scal + MS_LAM, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  AMRTO_HIP(hipStreamSynchronize(ctx->stream));
+  return AMRTO_OK;
+}
+
+int amrto_mg_vcycle(amrto_ctx* ctx, const double* r, double* z) {
+  int rc = check_mg(ctx, "amrto_mg_vcycle");
+  if (rc) return rc;
+  if (!r || !z || r == z) return ctx->fail(AMRTO_EINVAL, "amrto_mg_vcycle: r and z must be distinct device buffers");
+  AMRTO_HIP(hipSetDevice(ctx->device));
+  if ((rc = ensure_numeric(ctx))) return rc;
+  if ((rc = vcycle(ctx, r))) return rc;
+  MgLevel& L = ctx->mg->lv[0];
+  const long n = 3L * L.nn;
+  // z = x0 + d0 (the level-0 smoother's last correction); the r.z partials are unused here
+  hipLaunchKernelGGL(k_mgcg_rz, dim3(MG_RED), dim3(256), 0, ctx->stream, L.x, L.d, r, z, n, ctx->mg->part,
+                     (const double*)nullptr);
+  AMRTO_HIP(hipGetLastError());
+  return AMRTO_OK;
+}
+
+int amrto_mg_level_apply(amrto_ctx* ctx, int32_t k, const double* x, double* y) {
+  int rc = check_mg(ctx, "amrto_mg_level_apply");
+  if (rc) return rc;
+  MgData* g = ctx->mg;
+  if (k < 1 || k >= g->nlev || !x || !y || x == y)
+    return ctx->fail(AMRTO_EINVAL, "amrto_mg_level_apply: level out of range or bad buffers");
+  AMRTO_HIP(hipSetDevice(ctx->device));
+  if ((rc = ensure_numeric(ctx))) return rc;
+  MgUpd u = upd(g->lv[k], MG_APPLY);
+  u.xin = x;
+  u.y = y;
+  return level_pass(ctx, g->lv[k], x, u, g->part);
+}
+
+int amrto_mg_level_diag(amrto_ctx* ctx, int32_t k, double* dinv) {
+  int rc = check_mg(ctx, "amrto_mg_level_diag");
+  if (rc) return rc;
+  MgData* g = ctx->mg;
+  if (k < 1 || k >= g->nlev || !dinv) return ctx->fail(AMRTO_EINVAL, "amrto_mg_level_diag: bad arguments");
+  AMRTO_HIP(hipSetDevice(ctx->device));
+  if ((rc = ensure_numeric(ctx))) return rc;
+  AMRTO_HIP(hipMemcpyAsync(dinv, g->lv[k].dinv, 3L * g->lv[k].nn * sizeof(double), hipMemcpyDeviceToDevice,
+                           ctx->stream));
+  return AMRTO_OK;
+}
+
+int amrto_mg_prolong(amrto_ctx* ctx, int32_t k, const double* xc, double* xf) {
+  if (!ctx) return AMRTO_EINVAL;
+  if (!ctx->mg) return ctx->fail(AMRTO_ESTATE, "amrto_mg_prolong: no multigrid hierarchy");
+  MgData* g = ctx->mg;
+  if (k < 1 || k >= g->nlev || !xc || !xf || xc == xf)
+    return ctx->fail(AMRTO_EINVAL, "amrto_mg_prolong: level out of range or bad buffers");
+  AMRTO_HIP(hipSetDevice(ctx->device));
+  MgLevel& C = g->lv[k];
+  MgLevel& F = g->lv[k - 1];
+  hipLaunchKernelGGL(k_mg_prolong_plain, dim3(blocks_for(F.nn)), dim3(256), 0, ctx->stream, xc, C.pptr, C.pcol, C.pw,
+                     F.flag, F.nn, xf);
+  AMRTO_HIP(hipGetLastError());
+  return AMRTO_OK;
+}
+
+int amrto_mg_restrict(amrto_ctx* ctx, int32_t k, const double* rf, double* rc_out) {
+  if (!ctx) return AMRTO_EINVAL;
+  if (!ctx->mg) return ctx->fail(AMRTO_ESTATE, "amrto_mg_restrict: no multigrid hierarchy");
+  MgData* g = ctx->mg;
+  if (k < 1 || k >= g->nlev || !rf || !rc_out || rf == rc_out)
+    return ctx->fail(AMRTO_EINVAL, "amrto_mg_restrict: level out of range or bad buffers");
+  AMRTO_HIP(hipSetDevice(ctx->device));
+  MgLevel& C = g->lv[k];
+  hipLaunchKernelGGL(k_mg_restrict, dim3(blocks_for(C.nn)), dim3(256), 0, ctx->stream, rf, C.rptr, C.rcol, C.rw,
+                     C.flag, C.nn, rc_out, 0, (double*)nullptr, (double*)nullptr, (double*)nullptr,
+                     (const double*)nullptr, (const double*)nullptr);
+  AMRTO_HIP(hipGetLastError());
+  return AMRTO_OK;
+}
+
+int amrto_mg_pcg(amrto_ctx* ctx, const double* b, double* u, double rtol, int32_t max_it, int32_t check_every,
+                 amrto_solve_stats* stats) {
+  int rc = check_mg(ctx, "amrto_mg_pcg");
+  if (rc) return rc;
+  if (!b || !u || b == u || !(rtol > 0.0) || max_it < 0 || check_every < 1)
+    return ctx->fail(AMRTO_EINVAL, "amrto_mg_pcg: bad arguments");
+  AMRTO_HIP(hipSetDevice(ctx->device));
+  const auto t0 = std::chrono::steady_clock::now();
+  if ((rc = ensure_numeric(ctx))) return rc;
+  MgData* g = ctx->mg;
+  MgLevel& L0 = g->lv[0];
+  const long n = 3L * ctx->n_nodes;
+  const double tol2 = rtol * rtol;
+  double* r = g->lv[0].b;  // the level-0 right-hand side buffer holds the CG residual
+  // x = u masked; r = b - A~ x
+  hipLaunchKernelGGL(k_mg_mask_copy, dim3(blocks_for(n)), dim3(256), 0, ctx->stream, u, g->qv, L0.flag, n);
+  AMRTO_HIP(hipMemcpyAsync(u, g->qv, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  if ((rc = launch_apply(ctx, u, g->qv, AMRTO_FP64))) return rc;
+  hipLaunchKernelGGL(k_mgcg_init, dim3(MG_RED), dim3(256), 0, ctx->stream, b, g->qv, L0.flag, r, n, g->part);
+  hipLaunchKernelGGL(k_mgcg_init_scal, dim3(1), dim3(256), 0, ctx->stream, g->part, g->cg, tol2);
+  AMRTO_HIP(hipGetLastError());
+  int it = 0, status = AMRTO_NOT_CONVERGED;
+  while (true) {
+    AMRTO_HIP(hipMemcpyAsync(g->h_cg, g->cg, MC_COUNT * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    AMRTO_HIP(hipStreamSynchronize(ctx->stream));
+    const double done = g->h_cg[MC_DONE];
+    if (done == 1.0) {
+      status = AMRTO_OK;
+      it = (int)g->h_cg[MC_ITERS];
+      break;
+    }
+    if (done == 2.0) {
+      status = AMRTO_EBREAKDOWN;
+      it = (int)g->h_cg[MC_ITERS];
+      break;
+    }
+    if (it >= max_it) break;
+    const int batch = std::min(check_every, max_it - it);
+    for (int k = it; k < it + batch; ++k) {
+      if ((rc = vcycle(ctx, r))) return rc;
+      hipLaunchKernelGGL(k_mgcg_rz, dim3(MG_RED), dim3(256), 0, ctx->stream, L0.x, L0.d, r, g->z, n, g->part, g->cg);
+      hipLaunchKernelGGL(k_mgcg_dir, dim3(MG_RED), dim3(256), 0, ctx->stream, g->z, g->p, n, g->part, g->cg,
+                         k == 0 ? 1 : 0);
+      if ((rc = launch_apply(ctx, g->p, g->qv, AMRTO_FP64))) return rc;
+      hipLaunchKernelGGL(k_mgcg_pq, dim3(MG_RED), dim3(256), 0, ctx->stream, g->p, g->qv, n, g->part, g->cg);
+      hipLaunchKernelGGL(k_mgcg_update, dim3(MG_RED), dim3(256), 0, ctx->stream, u, r, g->p, g->qv, n, g->part,
+                         g->cg);
+      hipLaunchKernelGGL(k_mgcg_check, dim3(1), dim3(256), 0, ctx->stream, g->part, g->cg, k, tol2);
+    }
+    AMRTO_HIP(hipGetLastError());
+    it += batch;
+  }
+  // true residual
+  if ((rc = launch_apply(ctx, u, g->qv, AMRTO_FP64))) return rc;
+  hipLaunchKernelGGL(k_mgcg_resid, dim3(MG_RED), dim3(256), 0, ctx->stream, b, g->qv, L0.flag, n, g->part);
+  hipLaunchKernelGGL(k_mgcg_resid_scal, dim3(1), dim3(256), 0, ctx->stream, g->part, g->cg);
+  AMRTO_HIP(hipGetLastError());
+  AMRTO_HIP(hipMemcpyAsync(g->h_cg, g->cg, MC_COUNT * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  AMRTO_HIP(hipStreamSynchronize(ctx->stream));
+  const double rel = g->h_cg[MC_RES];
+  if (status == AMRTO_OK && rel > rtol) status = AMRTO_NOT_CONVERGED;
+  if (stats) {
+    stats->iters = it;
+    stats->outer = 0;
+    stats->rel_res = rel;
+    stats->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    stats->fell_back = 0;
+  }
+  if (status == AMRTO_EBREAKDOWN) return ctx->fail(AMRTO_EBREAKDOWN, "amrto_mg_pcg: breakdown");
+  if (status == AMRTO_NOT_CONVERGED) ctx->err = "amrto_mg_pcg: not converged";
+  return status;
+}
+
+}  // extern "C"

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "amrto.h"
+#include "levels.h"
 
 namespace {
 
@@ -71,6 +72,7 @@ struct amrto_octree {
   MeshData mesh;                // mesh of the current leaves (after build_mesh)
   MeshData old_mesh;            // mesh before the last adapt (for transfers)
   bool has_old = false;
+  std::vector<amrto_region> fixed_regions;  // supports of the last build_mesh
   std::string err;
 
   int32_t size_of(int level) const { return 1 << (L - level); }
@@ -581,6 +583,7 @@ int amrto_octree_build_mesh(amrto_octree* t, int32_t n_fixed, const amrto_region
       for (auto& v : md.load) v *= load_total / total;
   }
   t->mesh = std::move(md);
+  t->fixed_regions.assign(fixed, fixed + n_fixed);
   return AMRTO_OK;
 }
 
@@ -656,3 +659,60 @@ int amrto_octree_transfer_nodal(const amrto_octree* t, const double* u_old, doub
 }
 
 }  // extern "C"
+
+namespace amrto {
+
+static void to_level_mesh(const MeshData& md, int L, LevelMesh* out) {
+  out->n_nodes = md.n_nodes;
+  out->n_elems = (int)md.level.size();
+  out->L = L;
+  out->xyz = md.xyz;
+  out->elem_nodes = md.elem_nodes;
+  out->level = md.level;
+  out->anchor = md.anchor;
+  out->hang_node = md.hang_node;
+  out->hang_ptr = md.hang_ptr;
+  out->hang_master = md.hang_master;
+  out->hang_w = md.hang_w;
+  out->fixed = md.fixed;
+}
+
+bool octree_level_mesh(const amrto_octree* t, int k, LevelMesh* out) {
+  if (!t || !out || k < 0 || t->mesh.elem_nodes.empty()) return false;
+  if (k == 0) {
+    to_level_mesh(t->mesh, t->L, out);
+    return true;
+  }
+  amrto_octree c;
+  int32_t lmax;
+  if (k <= t->L) {
+    lmax = t->L;
+    for (int a = 0; a < 3; ++a) c.base[a] = t->base[a];
+  } else {
+    const int j = k - t->L;
+    if (j > 20) return false;
+    for (int a = 0; a < 3; ++a) {
+      if (t->base[a] % (1 << j)) return false;
+      c.base[a] = t->base[a] >> j;
+    }
+    lmax = k;
+  }
+  c.L = lmax;
+  for (int a = 0; a < 3; ++a) c.dims[a] = t->dims[a];
+  const int top = k <= t->L ? t->L - k : 0;
+  std::unordered_map<uint64_t, int> seen;
+  for (const Leaf& f : t->leaves) {
+    const int8_t lv = (int8_t)std::min<int>(f.level, top);
+    const int32_t s = 1 << (lmax - lv);
+    const Leaf g{lv, f.x / s * s, f.y / s * s, f.z / s * s};
+    if (seen.emplace(leaf_key(g.level, g.x, g.y, g.z), 1).second) c.leaves.push_back(g);
+  }
+  c.sort_leaves();
+  const int rc = amrto_octree_build_mesh(&c, (int32_t)t->fixed_regions.size(), t->fixed_regions.data(), nullptr, 0, 0,
+                                         0.0, 1);
+  if (rc != AMRTO_OK) return false;
+  to_level_mesh(c.mesh, lmax, out);
+  return true;
+}
+
+}  // namespace amrto

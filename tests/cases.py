@@ -37,11 +37,12 @@ class Pair:
 def uniform_pair(dims, bc="cantilever"):
     from paper_1009_4975_amd import binding
     fixed, load = (synth.cantilever_bc if bc == "cantilever" else synth.bridge_bc)(*dims)
-    lm = binding.uniform_mesh(dims, fixed, load)
+    t = binding.Octree(dims, 0)
+    lm = binding.uniform_mesh(dims, fixed, load, tree=t)
     o = om.uniform_mesh(dims)
     n = o.n_nodes
     return Pair(lm, o, np.arange(n), np.arange(o.n_elems), om.fixed_dofs(o, fixed), om.load_vector(o, load),
-                dict(fixed=fixed, load=load, dims=dims))
+                dict(fixed=fixed, load=load, dims=dims, tree=t))
 
 
 def octree_pair(base, L, width=synth.C2_WIDTH, bc="cantilever"):

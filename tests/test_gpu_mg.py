@@ -1,0 +1,163 @@
+"""The multigrid preconditioner on the GPU (amrto_mg_*) against the multigrid
+oracle (oracle/mg.py) on the same meshes: level sizes, prolongation and
+restriction, the Galerkin operators and their diagonals, one V-cycle with
+the oracle's exact smoothing intervals, the power-iteration estimate of
+lambda_max, and multigrid-preconditioned CG against the direct solve, on an
+octree with hanging nodes and on a uniform brick.  Level-0 vectors are
+matched by node coordinates; coarse levels number their nodes with x fastest
+on both sides."""
+import numpy as np
+import pytest
+import torch
+
+from cases import centre_density, octree_pair, oracle_system, uniform_pair
+from oracle import mg
+from oracle import system as osys
+from paper_1009_4975_amd import binding
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+COARSE = 200
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+class MgCase:
+    def __init__(self, kind):
+        if kind == "octree":
+            self.pair = octree_pair((8, 4, 4), 2)
+            self.base = (8, 4, 4)
+            rho = np.clip(centre_density(self.pair, self.pair.case["field"]), 0.05, 1.0)
+        else:
+            self.pair = uniform_pair((24, 12, 12))
+            self.base = (24, 12, 12)
+            rho = np.random.default_rng(11).uniform(0.05, 1.0, self.pair.orc.n_elems)
+        p = self.pair
+        self.rho = rho
+        self.ctx = binding.Context(0)
+        self.ctx.upload_mesh(p.lib_mesh)
+        self.ctx.set_density(_t(p.to_lib_elems(rho)))
+        self.ctx.mg_setup(p.case["tree"], coarse_dofs=COARSE)
+        self.sys = oracle_system(p, rho)
+        self.levels = mg.hierarchy(p.orc, self.base, p.case["fixed"], coarse_dofs=COARSE)
+        self.M = mg.setup(self.levels, self.sys.A)
+        self.dp = p.dof_perm  # library level-0 DOF -> oracle DOF
+
+    def to_lib(self, k, v):
+        return _t(np.asarray(v)[self.dp]) if k == 0 else _t(v)
+
+    def to_orc(self, k, t):
+        v = t.cpu().numpy()
+        if k != 0:
+            return v
+        out = np.zeros_like(v)
+        out[self.dp] = v
+        return out
+
+
+@pytest.fixture(scope="module", params=["octree", "uniform"])
+def case(request):
+    return MgCase(request.param)
+
+
+def test_hierarchy_matches_oracle(case):
+    info = case.ctx.mg_info()
+    assert info["dofs"] == [3 * lv.mesh.n_nodes for lv in case.levels]
+    assert info["levels"] >= 3
+    if case.levels[1].mesh.hanging.any():
+        assert info["dense"][1] > 0
+
+
+def test_prolong_and_restrict_match_oracle(case):
+    rng = np.random.default_rng(1)
+    for k in range(1, len(case.levels)):
+        f, c = case.levels[k - 1], case.levels[k]
+        P = c.P
+        xc = rng.standard_normal(3 * c.mesh.n_nodes) * c.free
+        xf = torch.empty(3 * f.mesh.n_nodes, dtype=torch.float64, device=DEV)
+        case.ctx.mg_prolong(k, _t(xc), xf)
+        want = P @ xc
+        assert np.abs(case.to_orc(k - 1, xf) - want).max() <= 1e-14 * np.abs(want).max()
+        rf = rng.standard_normal(3 * f.mesh.n_nodes) * f.free
+        rc = torch.empty(3 * c.mesh.n_nodes, dtype=torch.float64, device=DEV)
+        case.ctx.mg_restrict(k, case.to_lib(k - 1, rf), rc)
+        want = P.T @ rf
+        assert np.abs(rc.cpu().numpy() - want).max() <= 1e-13 * np.abs(want).max()
+
+
+def test_level_operators_and_diagonals_match_galerkin(case):
+    rng = np.random.default_rng(2)
+    for k in range(1, len(case.levels)):
+        lv = case.levels[k]
+        x = rng.standard_normal(3 * lv.mesh.n_nodes)
+        y = torch.empty_like(_t(x))
+        case.ctx.mg_level_apply(k, _t(x), y)
+        want = lv.A @ x
+        assert np.abs(y.cpu().numpy() - want).max() <= 1e-12 * np.abs(want).max(), k
+        d = torch.empty_like(y)
+        case.ctx.mg_level_diag(k, d)
+        assert np.allclose(d.cpu().numpy(), lv.dinv, rtol=1e-12, atol=0), k
+
+
+def test_vcycle_matches_oracle_with_the_same_intervals(case):
+    lam = [lv.hi / 1.1 for lv in case.levels[:-1]]
+    case.ctx.mg_set_bounds(lam)
+    try:
+        rng = np.random.default_rng(3)
+        r = rng.standard_normal(3 * case.pair.orc.n_nodes) * case.levels[0].free
+        z = torch.empty_like(_t(r))
+        case.ctx.mg_vcycle(case.to_lib(0, r), z)
+        want = case.M.vcycle(r)
+        got = case.to_orc(0, z)
+        assert np.abs(got - want).max() <= 1e-9 * np.abs(want).max()
+        assert np.allclose(case.ctx.mg_get_bounds(), lam, rtol=1e-15)
+    finally:
+        case.ctx.mg_set_bounds(None)
+
+
+def test_power_estimate_of_lambda_max(case):
+    exact = np.array([lv.hi / 1.1 for lv in case.levels[:-1]])
+    est = case.ctx.mg_get_bounds()
+    assert (est <= exact * (1 + 1e-9)).all() and (est >= 0.9 * exact).all(), (est, exact)
+
+
+def test_mg_pcg_matches_direct_solve(case):
+    u_ref = osys.solve_direct(case.sys)
+    f = _t(case.pair.to_lib_nodes(case.pair.f))
+    b = torch.empty_like(f)
+    case.ctx.project_rhs(f, b)
+    u = torch.zeros_like(f)
+    st = case.ctx.mg_pcg(b, u, rtol=1e-10, max_it=500, check_every=1)
+    assert st["status"] == "OK" and st["rel_res"] <= 1e-10, st
+    ut = torch.empty_like(u)
+    case.ctx.recover(u, ut)
+    got = case.to_orc(0, ut)
+    want = osys.recover(case.sys, u_ref)
+    assert np.abs(got - want).max() <= 1e-8 * np.abs(want).max()
+    jac = osys.pcg_jacobi(case.sys.A, case.sys.b, rtol=1e-10)
+    assert st["iters"] * 5 < jac.iters, (st["iters"], jac.iters)
+    # warm start from the solution's neighbourhood takes fewer iterations
+    u2 = (u * (1.0 + 1e-4 * torch.randn_like(u))).contiguous()
+    st2 = case.ctx.mg_pcg(b, u2, rtol=1e-10, max_it=500, check_every=1)
+    assert st2["status"] == "OK" and st2["iters"] < st["iters"]
+
+
+def test_mg_errors():
+    p = uniform_pair((8, 4, 4))
+    ctx = binding.Context(0)
+    ctx.upload_mesh(p.lib_mesh)
+    ctx.set_density(_t(np.full(p.orc.n_elems, 0.5)))
+    b = torch.zeros(3 * p.orc.n_nodes, dtype=torch.float64, device=DEV)
+    with pytest.raises(binding.AmrtoError) as e:
+        ctx.mg_pcg(b, b.clone())
+    assert e.value.code == -5
+    other = binding.Octree((4, 4, 4), 0)
+    other.build_mesh(p.case["fixed"], p.case["load"], lexicographic=True)
+    with pytest.raises(binding.AmrtoError) as e:
+        ctx.mg_setup(other)
+    assert e.value.code == -1
+    ctx.mg_setup(p.case["tree"], coarse_dofs=COARSE)
+    with pytest.raises(binding.AmrtoError):
+        ctx.mg_level_apply(0, b, b.clone())
