@@ -124,7 +124,7 @@ def event_time(torch, fn, reps):
 # solve variants: inner precision, then "+coarse" (affine coarse space) and/or
 # "+block3" (3x3 node-block Jacobi in place of the scalar diagonal)
 SOLVERS = ("fp64", "fp32", "bf16", "fp64+coarse", "fp32+coarse", "fp64+block3", "fp32+block3",
-           "fp64+coarse+block3", "fp32+coarse+block3")
+           "fp64+coarse+block3", "fp32+coarse+block3", "fp64+mg")
 
 
 def main():
@@ -147,6 +147,8 @@ def main():
     ap.add_argument("--no-amr-vs-uniform", action="store_true", help="skip the AMR against uniform comparison")
     ap.add_argument("--amr-vs-uniform-only", action="store_true", help="only the AMR against uniform comparison")
     ap.add_argument("--c4-only", action="store_true", help="only the 50-iteration adaptive SIMP run")
+    ap.add_argument("--no-2d", action="store_true", help="skip the 2-D cantilever (Q4 quadtree) lines")
+    ap.add_argument("--2d-only", dest="only_2d", action="store_true", help="only the 2-D cantilever lines")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the C2 apply loop and a copy kernel of known size (for counter runs)")
     args = ap.parse_args()
@@ -172,6 +174,9 @@ def main():
     if args.c4_only:
         print(json.dumps(c4_simp(torch, binding, synth, tuple(int(r) for r in args.c4_regions.split(",")))),
               flush=True)
+        return
+    if args.only_2d:
+        print(json.dumps(plane_2d(torch, binding)), flush=True)
         return
 
     t0 = time.time()
@@ -208,12 +213,26 @@ def main():
     c4_regions = tuple(int(r) for r in args.c4_regions.split(","))
     regions = tuple(int(r) for r in args.regions.split(","))
 
+    mg_ready = [False]
+
     def solve(name):
         """One solve from zero; with "+coarse" the affine coarse space (--regions,
         12 columns per region) is built first and its set-up counts in ms; with
         "+block3" the 3x3 node-block Jacobi preconditioner (its inverse blocks
-        are formed on the first solve after a density change, inside ms)."""
+        are formed on the first solve after a density change, inside ms); with
+        "+mg" multigrid-preconditioned CG (the hierarchy is built once per mesh,
+        like the operator's chunk tables; its numeric set-up after the density
+        change runs inside ms)."""
         u.zero_()
+        if "+mg" in name:
+            if not mg_ready[0]:
+                ctx.mg_setup(tree)
+                mg_ready[0] = True
+            ctx.set_density(rho)  # a fresh density: the solve rebuilds the coarse operators
+            torch.cuda.synchronize()
+            st = ctx.mg_pcg(b, u, rtol=1e-8, max_it=2000, check_every=2)
+            st["setup_ms"] = 0.0
+            return st
         prec = precs[name.split("+")[0]]
         t0 = time.perf_counter()
         coarse = "+coarse" in name
@@ -320,6 +339,9 @@ def main():
     # --- AMR against the uniform fine mesh (paper's trigger, design difference)
     avu = None if args.no_amr_vs_uniform else amr_vs_uniform(torch, binding, synth)
 
+    # --- the 2-D variant: 256 x 128 Q4 cantilever, uniform and adaptive
+    p2d = None if args.no_2d else plane_2d(torch, binding)
+
     # --- CPU oracle on a bounded sample
     cpu = None
     if not args.no_cpu:
@@ -338,7 +360,7 @@ def main():
         "solve_variants": variants, "roofline": roofline, "roofline_apply_fp64": roofline_apply,
         "c1_simp_iteration_24x12x12": c1, "c5_bridge_128x64x64": c5,
         "apply_uniform_192x96x96": c3, "simp_adaptive_bridge": c4, "amr_vs_uniform_cantilever": avu,
-        "cpu_baseline": cpu,
+        "plane_2d_cantilever_256x128": p2d, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
@@ -616,6 +638,59 @@ def c4_simp(torch, binding, synth, regions=(2, 2, 2)):
     for k, v in out.items():
         v["time_vs_plain_fp64"] = round((v["solve_ms_11_50"] + v["warm_and_coarse_setup_ms_11_50"] + v["train_ms"]) /
                                         (base["solve_ms_11_50"] + base["warm_and_coarse_setup_ms_11_50"]), 4)
+    return out
+
+
+PLANE_BYTES_RULE = ("per CG iteration, per node: z and the previous direction read, the new direction written; "
+                    "the direction read and q written by the operator; x, r, the direction, q and the inverse "
+                    "diagonal read and x, r, z written by the update (2 FP64 values each, 208 B); plus the "
+                    "element modulus (8 B per element)")
+
+
+def plane_2d(torch, binding):
+    """The 2-D variant on the 256 x 128 cantilever (left edge clamped, unit
+    point load at the middle of the right edge, volume fraction 0.5, rmin 1.5):
+    one design iteration on the uniform grid (solve from zero to 1e-8 on a
+    seeded smooth density), and 40 adaptive iterations from 32 x 16 base
+    leaves with 3 levels (adapt every 10) against the same 40 on the uniform
+    grid."""
+    from paper_1009_4975_amd.plane_simp import PlaneSIMP
+    out = {}
+    sim = PlaneSIMP((32, 16), 3, uniform=True, volfrac=0.5, rmin=1.5, adapt_every=0, check_every=64)
+    lv, an = sim.leaves()
+    cen = an + 0.5 * (1 << (3 - lv))[:, None]
+    rng = np.random.default_rng(2024)
+    rho_h = np.clip(0.5 + 0.35 * np.sin(cen[:, 0] / 17.0 + rng.uniform(0, 6.28)) *
+                    np.cos(cen[:, 1] / 11.0 + rng.uniform(0, 6.28)), 0.05, 1.0)
+    rho = torch.tensor(rho_h, dtype=torch.float64, device="cuda")
+    sim.ctx.set_density(rho)
+    u = torch.zeros_like(sim.f)
+    runs = []
+    for _ in range(3):
+        u.zero_()
+        torch.cuda.synchronize()
+        runs.append(sim.ctx.pcg(sim.b, u, rtol=1e-8, max_it=100000, check_every=64))
+    best = min(runs, key=lambda r: r["ms"])
+    nn, ne = sim.mesh.n_nodes, sim.mesh.n_elems
+    us_it = best["ms"] * 1e3 / max(1, best["iters"])
+    alg = 208.0 * nn + 8.0 * ne
+    out["uniform_solve"] = dict(elements=ne, dofs=2 * nn, solve_ms=round(best["ms"], 3), iters=best["iters"],
+                                outer=best["outer"], rel_res=best["rel_res"], us_per_iter=round(us_it, 3),
+                                alg_bytes_per_iter=int(alg), gbs=round(alg / (us_it * 1e-6) / 1e9, 2),
+                                bytes_rule=PLANE_BYTES_RULE)
+    log(f"[bench] 2-D uniform 256x128 solve: {best['ms']:.2f} ms, {best['iters']} iters, {us_it:.2f} us/iter")
+    for name, kw in (("uniform", dict(uniform=True, adapt_every=0)), ("amr", dict(uniform=False, adapt_every=10))):
+        s = PlaneSIMP((32, 16), 3, volfrac=0.5, rmin=1.5, check_every=64, **kw)
+        recs = [s.step() for _ in range(40)]
+        out[name + "_40_iterations"] = dict(
+            solve_ms_total=round(sum(r["solve_ms"] for r in recs), 2),
+            step_ms_total=round(sum(r["step_ms"] for r in recs), 2),
+            iters_total=int(sum(r["iters"] for r in recs)), dofs_mean=round(float(np.mean([r["dofs"] for r in recs])), 1),
+            dofs_last=recs[-1]["dofs"], compliance_last=recs[-1]["compliance"], adapts=sum(r["adapted"] for r in recs))
+        log(f"[bench] 2-D {name} 40 iterations: solve {out[name + '_40_iterations']['solve_ms_total']:.1f} ms, "
+            f"compliance {recs[-1]['compliance']:.4f}, dofs {recs[-1]['dofs']}")
+    out["config"] = dict(lattice=[256, 128], base=[32, 16], levels=3, load="unit point load at (256, 64), -y",
+                         support="x = 0", volfrac=0.5, rmin=1.5, rtol=1e-8, p=3.0)
     return out
 
 

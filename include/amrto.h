@@ -488,10 +488,11 @@ int amrto_octree_transfer_nodal(const amrto_octree* t, const double* u_old, doub
 /* A geometric multigrid V-cycle on the octree hierarchy as the preconditioner
  * of FP64 CG: a stronger preconditioner than Jacobi for the p = 3 contrast
  * (the paper's own choice, Sec. 5, is IC(0) on the rescaled system).
- * Level 0 is the uploaded mesh; level k <= L merges every leaf finer than
- * level L - k into its ancestor; levels k > L coarsen the uniform base grid
- * by two per axis; levels are added until a uniform level has at most
- * coarse_dofs DOFs (it must have at most 1024).  Coarse operators are exactly
+ * Level 0 is the uploaded mesh; a level of depth k <= L merges every leaf
+ * finer than level L - k into its ancestor; depths k > L coarsen the uniform
+ * base grid by two per axis; the coarse levels have depths first, first + 1,
+ * ... and are added until a uniform level has at most coarse_dofs DOFs (it
+ * must have at most 1024).  Coarse operators are exactly
  * Galerkin (P^T A P, element by element), the prolongation evaluates the
  * continuous coarse field at the fine nodes, smoothing is Chebyshev on
  * D^-1 A over [hi / ratio, hi] with hi = hi_factor * lambda_max estimated by
@@ -504,6 +505,7 @@ typedef struct {
   int32_t power_its;    /* power iterations for lambda_max (default 20) */
   double hi_factor;     /* hi = hi_factor * estimate (default 1.1) */
   int32_t coarse_dofs;  /* target size of the coarsest level (default 200) */
+  int32_t first;        /* octree levels merged by the first coarsening, 1 or 2 (default 1) */
 } amrto_mg_opts;
 
 /* Build the hierarchy of the uploaded mesh from the host tree it was built

@@ -12,9 +12,11 @@ is a stronger, parallel alternative built from textbook definitions:
   at that level (all siblings of a finest leaf are leaves, so merging keeps the
   one-level rule between neighbours).  For k > L the uniform base grid is
   coarsened by two per axis, k - L times, as long as every base extent stays
-  divisible.  Levels are added until one is a uniform grid (k >= L, no
-  hanging nodes) with at most ``coarse_dofs`` DOFs, or no further level can
-  be built.  Supports are the same lattice planes or lines on every level.
+  divisible.  The first coarse level may take ``first`` > 1 such steps at
+  once (level depths first, first + 1, ...).  Levels are added until one is
+  a uniform grid (depth >= L, no hanging nodes) with at most ``coarse_dofs``
+  DOFs, or no further level can be built.  Supports are the same lattice
+  planes or lines on every level.
 * Prolongation P_k from level k to level k - 1 (vectors in the constrained
   form: zero at hanging and supported DOFs): the level-k field T_k F_k x is
   continuous and trilinear on each level-k leaf; its values at the level
@@ -81,19 +83,19 @@ class Level:
     hi: float = 0.0
 
 
-def hierarchy(mesh0: Mesh, base, fixed_spec, coarse_dofs=1000):
-    """Level meshes 0, 1, ... (level 0 is mesh0)."""
+def hierarchy(mesh0: Mesh, base, fixed_spec, coarse_dofs=1000, first=1):
+    """Level meshes of depths 0, first, first + 1, ... (depth 0 is mesh0)."""
     levels = [Level(mesh0, fixed_dofs(mesh0, fixed_spec), None)]
     levels[0].free = free_mask(mesh0, levels[0].fixed)
-    k = 1
-    while k - 1 < mesh0.max_level or 3 * levels[-1].mesh.n_nodes > coarse_dofs:
+    k, prev = first, 0
+    while prev < mesh0.max_level or 3 * levels[-1].mesh.n_nodes > coarse_dofs:
         c = coarsen_leaves(mesh0.level, mesh0.anchor, mesh0.max_level, base, k)
         if c is None:
             break
         m = build_mesh(c[0], c[1], c[2], mesh0.dims)
         fx = fixed_dofs(m, fixed_spec)
         levels.append(Level(m, fx, free_mask(m, fx)))
-        k += 1
+        prev, k = k, k + 1
     return levels
 
 

@@ -47,11 +47,12 @@ enum MgMode { MG_APPLY = 0, MG_CHEB = 1, MG_CHEB_LAST = 2, MG_CORR = 3, MG_POWER
 struct MgLevel {
   int nn = 0, ne = 0, nd = 0, nh = 0;  // nodes, elements, dense elements (first nd), hanging nodes
   int32_t* elem = nullptr;       // [8 ne]
+  int32_t* ev = nullptr;         // [8 ne] vertex node, or -(row + 1) of the hanging table
   int32_t* pure_src = nullptr;   // [ne - nd] index into the context's c_e
-  double* Kd = nullptr;          // [576 nd] entry-major: Kd[i * nd + e]
+  double* Kd = nullptr;          // [576 nd] per element, column-major: entry (i, j) at 576 e + 24 j + i
   uint8_t* flag = nullptr;       // per node: bits 0-2 supported components, bit 3 hanging
-  int32_t* hang_of = nullptr;    // per node: row of the hanging table, or -1
-  int32_t* hptr = nullptr; int32_t* hm = nullptr; double* hw = nullptr;
+  int32_t* hm4 = nullptr; double* hw4 = nullptr;  // hanging masters, four per hanging node (unused weight 0)
+  int lanes = 4;                 // lanes per node in the gather pass
   int32_t* iptr = nullptr; int32_t* islot = nullptr; double* iw = nullptr;  // incidences (slot 8 e + a)
   double* dinv = nullptr;        // owned except on level 0
   double* E = nullptr;           // [24 ne] element outputs
@@ -60,7 +61,7 @@ struct MgLevel {
   // coarse side of the transfer to the next finer level (this level k >= 1):
   int32_t* pptr = nullptr; int32_t* pcol = nullptr; double* pw = nullptr;  // rows: level k-1 nodes
   int32_t* rptr = nullptr; int32_t* rcol = nullptr; double* rw = nullptr;  // rows: level k nodes
-  int32_t* cptr = nullptr; int32_t* celem = nullptr; int8_t* coct = nullptr;  // children of dense elements
+  int32_t* cptr = nullptr; int32_t* celem = nullptr; uint8_t* coct = nullptr;  // children of dense elements
   double* Ainv = nullptr;        // coarsest level: dense inverse of A~ (3 nn x 3 nn)
   std::vector<void*> owned;
 };
@@ -74,8 +75,10 @@ struct MgData {
   double lam_user[MG_LMAX] = {};
   double* part = nullptr;   // 4 x MG_RED
   double* cg = nullptr;     // MC_COUNT
-  double* h_cg = nullptr;   // pinned
-  double *z = nullptr, *p = nullptr, *qv = nullptr;  // PCG vectors
+  double* h_cg = nullptr;   // pinned, S_COUNT >= MC_COUNT
+  double *z = nullptr, *p = nullptr, *z2 = nullptr, *qv = nullptr;  // PCG vectors (p and z2: direction pair)
+  double* cpart = nullptr;  // 2 x RED_BLOCKS partials of the fused CG
+  double* cs = nullptr;     // S_COUNT scalars of the fused CG
   std::vector<void*> owned;
 };
 
@@ -103,58 +106,134 @@ hipError_t mg_upload(std::vector<void*>& own, T*& p, const std::vector<T>& v) {
 
 __device__ __forceinline__ bool mg_cons(uint8_t f, int c) { return ((f >> 3) & 1) || ((f >> c) & 1); }
 
-// value of DOF c of the continuous field at node v (hanging values from masters)
-__device__ __forceinline__ double mg_val(const double* __restrict__ x, const uint8_t* __restrict__ flag,
-                                         const int32_t* __restrict__ hang_of, const int32_t* __restrict__ hptr,
-                                         const int32_t* __restrict__ hm, const double* __restrict__ hw, int v,
-                                         int c) {
-  const int h = hang_of[v];
-  if (h < 0) return ((flag[v] >> c) & 1) ? 0.0 : x[3L * v + c];
-  double s = 0.0;
-  for (int k = hptr[h]; k < hptr[h + 1]; ++k) {
-    const int m = hm[k];
-    if (!((flag[m] >> c) & 1)) s += hw[k] * x[3L * m + c];
+// s[c] = sum over k in [k0, k1) of w[k] src[3 col[k] + c], in order, four
+// entries' loads issued together
+__device__ __forceinline__ void csr_gather3(const double* __restrict__ src, int k0, int k1,
+                                            const int32_t* __restrict__ col, const double* __restrict__ w,
+                                            double* s) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  int k = k0;
+  for (; k + 4 <= k1; k += 4) {
+    long c[4];
+    double ww[4], v[12];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      c[j] = col[k + j];
+      ww[j] = w[k + j];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) v[3 * j + q] = src[3 * c[j] + q];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      s0 = fma(ww[j], v[3 * j], s0);
+      s1 = fma(ww[j], v[3 * j + 1], s1);
+      s2 = fma(ww[j], v[3 * j + 2], s2);
+    }
   }
-  return s;
+  for (; k < k1; ++k) {
+    const long c = col[k];
+    const double ww = w[k];
+    s0 = fma(ww, src[3 * c], s0);
+    s1 = fma(ww, src[3 * c + 1], s1);
+    s2 = fma(ww, src[3 * c + 2], s2);
+  }
+  s[0] = s0;
+  s[1] = s1;
+  s[2] = s2;
 }
 
-// element outputs E[24 e + 3 a + c] = (K_e u_e) for the continuous field of x
-__global__ __launch_bounds__(256) void k_mg_elem(const double* __restrict__ x, const int32_t* __restrict__ elem,
-                                                 const uint8_t* __restrict__ flag,
-                                                 const int32_t* __restrict__ hang_of, const int32_t* __restrict__ hptr,
-                                                 const int32_t* __restrict__ hm, const double* __restrict__ hw,
+// LANES lanes per row: lane q sums entries k0 + q, k0 + q + LANES, ... in
+// order; the lane sums are combined with xor shuffles in a fixed tree, so
+// every lane of the row gets the same deterministic value
+template <int LANES>
+__device__ __forceinline__ void row_gather(const double* __restrict__ src, int k0, int k1,
+                                           const int32_t* __restrict__ col, const double* __restrict__ w, int q,
+                                           double& a0, double& a1, double& a2) {
+  a0 = a1 = a2 = 0.0;
+  for (int k = k0 + q; k < k1; k += LANES) {
+    const long c = col[k];
+    const double ww = w[k];
+    a0 = fma(ww, src[3 * c], a0);
+    a1 = fma(ww, src[3 * c + 1], a1);
+    a2 = fma(ww, src[3 * c + 2], a2);
+  }
+#pragma unroll
+  for (int o = 1; o < LANES; o <<= 1) {
+    a0 += __shfl_xor(a0, o, 64);
+    a1 += __shfl_xor(a1, o, 64);
+    a2 += __shfl_xor(a2, o, 64);
+  }
+}
+
+__device__ __forceinline__ void row_gather4(const double* __restrict__ src, int k0, int k1,
+                                            const int32_t* __restrict__ col, const double* __restrict__ w, int q,
+                                            double& a0, double& a1, double& a2) {
+  row_gather<4>(src, k0, k1, col, w, q, a0, a1, a2);
+}
+
+__device__ __forceinline__ double pick3(int c, double a0, double a1, double a2) {
+  return c == 0 ? a0 : (c == 1 ? a1 : a2);
+}
+
+// element outputs E[24 e + 3 a + c] = (K_e u_e) for the continuous field of x;
+// one thread per (element, row): the element's 24 values are gathered once
+// into LDS, then each thread streams its row of the element matrix
+constexpr int ME = 10;  // elements per workgroup (240 threads)
+__global__ __launch_bounds__(240) void k_mg_elem(const double* __restrict__ x, const int32_t* __restrict__ ev,
+                                                 const uint8_t* __restrict__ flag, const int32_t* __restrict__ hm4,
+                                                 const double* __restrict__ hw4,
                                                  const double* __restrict__ Kd, int nd,
                                                  const int32_t* __restrict__ pure_src,
                                                  const double* __restrict__ coef, const double* __restrict__ K0g,
                                                  double* __restrict__ E, int ne) {
-  __shared__ double K0[576];
-  for (int i = threadIdx.x; i < 576; i += blockDim.x) K0[i] = K0g[i];
+  __shared__ double K0[576];  // column-major: entry (i, j) at 24 j + i
+  __shared__ double su[ME][24];
+  for (int t = threadIdx.x; t < 576; t += blockDim.x) K0[t] = K0g[(t % 24) * 24 + t / 24];
+  const int le = threadIdx.x / 24, i = threadIdx.x % 24;
+  const int e = blockIdx.x * ME + le;
+  if (e < ne) {
+    const int v = ev[8L * e + i / 3], c = i % 3;
+    double val = 0.0;
+    if (v >= 0) {
+      const double xv = x[3L * v + c];
+      val = ((flag[v] >> c) & 1) ? 0.0 : xv;
+    } else {
+      // hanging vertex: at most four masters at a fixed stride (unused weights 0)
+      const long h = -(long)v - 1;
+      int m[4];
+      double w[4], xm[4];
+      uint8_t fm[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        m[k] = hm4[4 * h + k];
+        w[k] = hw4[4 * h + k];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        xm[k] = x[3L * m[k] + c];
+        fm[k] = flag[m[k]];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (!((fm[k] >> c) & 1)) val += w[k] * xm[k];
+    }
+    su[le][i] = val;
+  }
   __syncthreads();
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne) return;
-  double u[24];
-#pragma unroll
-  for (int a = 0; a < 8; ++a) {
-    const int v = elem[8L * e + a];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) u[3 * a + c] = mg_val(x, flag, hang_of, hptr, hm, hw, v, c);
-  }
+  double s = 0.0;
   if (e < nd) {
-    for (int i = 0; i < 24; ++i) {
-      double s = 0.0;
+    const double* Kc = Kd + 576L * e + i;
 #pragma unroll
-      for (int j = 0; j < 24; ++j) s = fma(Kd[(long)(i * 24 + j) * nd + e], u[j], s);
-      E[24L * e + i] = s;
-    }
+    for (int j = 0; j < 24; ++j) s = fma(Kc[24 * j], su[le][j], s);
   } else {
-    const double ce = coef[pure_src[e - nd]];
-    for (int i = 0; i < 24; ++i) {
-      double s = 0.0;
 #pragma unroll
-      for (int j = 0; j < 24; ++j) s = fma(K0[i * 24 + j], u[j], s);
-      E[24L * e + i] = ce * s;
-    }
+    for (int j = 0; j < 24; ++j) s = fma(K0[24 * j + i], su[le][j], s);
+    s *= coef[pure_src[e - nd]];
   }
+  E[24L * e + i] = s;
 }
 
 struct MgUpd {
@@ -216,27 +295,24 @@ __device__ __forceinline__ void mg_update(const MgUpd& u, long i, bool cons, dou
   }
 }
 
-// per node: q = F T^T (sum of element outputs) and the update of mode u.mode
+// per node: q = F T^T (sum of element outputs) and the update of mode u.mode;
+// four lanes per node (lane c < 3 updates component c)
+template <int LANES>
 __global__ __launch_bounds__(256) void k_mg_gather(const double* __restrict__ E, const int32_t* __restrict__ iptr,
                                                    const int32_t* __restrict__ islot, const double* __restrict__ iw,
                                                    const uint8_t* __restrict__ flag, int nn, MgUpd u,
                                                    double* __restrict__ part) {
   __shared__ double sh[16];
   double t1 = 0.0, t2 = 0.0;
-  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nn; v += gridDim.x * blockDim.x) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int k = iptr[v]; k < iptr[v + 1]; ++k) {
-      const long sl = islot[k];
-      const double w = iw[k];
-      s0 = fma(w, E[3 * sl], s0);
-      s1 = fma(w, E[3 * sl + 1], s1);
-      s2 = fma(w, E[3 * sl + 2], s2);
-    }
-    const uint8_t f = flag[v];
-    const double s[3] = {s0, s1, s2};
-    for (int c = 0; c < 3; ++c) {
-      const bool cs = mg_cons(f, c);
-      mg_update(u, 3L * v + c, cs, cs ? 0.0 : s[c], t1, t2);
+  const int q = threadIdx.x & (LANES - 1);
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)LANES * nn;
+       t += (long)gridDim.x * blockDim.x) {
+    const int v = (int)(t / LANES);
+    double a0, a1, a2;
+    row_gather<LANES>(E, iptr[v], iptr[v + 1], islot, iw, q, a0, a1, a2);
+    if (q < 3) {
+      const bool cs = mg_cons(flag[v], q);
+      mg_update(u, 3L * v + q, cs, cs ? 0.0 : pick3(q, a0, a1, a2), t1, t2);
     }
   }
   if (u.mode == MG_RAYLEIGH) {
@@ -270,60 +346,46 @@ __global__ __launch_bounds__(256) void k_mg_vec0(const double* __restrict__ q, c
 }
 
 // b_c = R r_f on the coarse level; with init, the smoother starts there:
-// x = 0, r = b, d = D^-1 b / theta
+// x = 0, r = b, d = D^-1 b / theta.  Four lanes per coarse node.
 __global__ __launch_bounds__(256) void k_mg_restrict(const double* __restrict__ rf, const int32_t* __restrict__ rptr,
                                                      const int32_t* __restrict__ rcol, const double* __restrict__ rw,
                                                      const uint8_t* __restrict__ flag, int nn, double* __restrict__ b,
                                                      int init, double* __restrict__ x, double* __restrict__ r,
                                                      double* __restrict__ d, const double* __restrict__ dinv,
                                                      const double* __restrict__ scal) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nn) return;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (int k = rptr[v]; k < rptr[v + 1]; ++k) {
-    const long m = rcol[k];
-    const double w = rw[k];
-    s0 = fma(w, rf[3 * m], s0);
-    s1 = fma(w, rf[3 * m + 1], s1);
-    s2 = fma(w, rf[3 * m + 2], s2);
-  }
-  const uint8_t f = flag[v];
-  const double s[3] = {s0, s1, s2};
-  for (int c = 0; c < 3; ++c) {
-    const long i = 3L * v + c;
-    const double bi = mg_cons(f, c) ? 0.0 : s[c];
-    b[i] = bi;
-    if (init) {
-      x[i] = 0.0;
-      r[i] = bi;
-      d[i] = dinv[i] * bi / scal[MS_THETA];
-    }
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const int v = (int)(t >> 2), q = threadIdx.x & 3;
+  if (v >= nn) return;  // the four lanes of a node leave together
+  double a0, a1, a2;
+  row_gather4(rf, rptr[v], rptr[v + 1], rcol, rw, q, a0, a1, a2);
+  if (q == 3) return;
+  const long i = 3L * v + q;
+  const double bi = mg_cons(flag[v], q) ? 0.0 : pick3(q, a0, a1, a2);
+  b[i] = bi;
+  if (init) {
+    x[i] = 0.0;
+    r[i] = bi;
+    d[i] = dinv[i] * bi / scal[MS_THETA];
   }
 }
 
-// t = P (xc + dc) at the fine nodes; df = t, xf += t
+// t = P (xc + dc) at the fine nodes; df = t, xf += t.  Four lanes per node;
+// dc (the coarse level's last smoothing correction) may be null.
 __global__ __launch_bounds__(256) void k_mg_prolong(const double* __restrict__ xc, const double* __restrict__ dc,
                                                     const int32_t* __restrict__ pptr, const int32_t* __restrict__ pcol,
                                                     const double* __restrict__ pw, const uint8_t* __restrict__ flag,
                                                     int nn, double* __restrict__ xf, double* __restrict__ df) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const int v = (int)(t >> 2), q = threadIdx.x & 3;
   if (v >= nn) return;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (int k = pptr[v]; k < pptr[v + 1]; ++k) {
-    const long m = pcol[k];
-    const double w = pw[k];
-    s0 = fma(w, xc[3 * m] + (dc ? dc[3 * m] : 0.0), s0);
-    s1 = fma(w, xc[3 * m + 1] + (dc ? dc[3 * m + 1] : 0.0), s1);
-    s2 = fma(w, xc[3 * m + 2] + (dc ? dc[3 * m + 2] : 0.0), s2);
-  }
-  const uint8_t f = flag[v];
-  const double s[3] = {s0, s1, s2};
-  for (int c = 0; c < 3; ++c) {
-    const long i = 3L * v + c;
-    const double t = mg_cons(f, c) ? 0.0 : s[c];
-    df[i] = t;
-    xf[i] += t;
-  }
+  double a0, a1, a2, e0 = 0.0, e1 = 0.0, e2 = 0.0;
+  row_gather4(xc, pptr[v], pptr[v + 1], pcol, pw, q, a0, a1, a2);
+  if (dc) row_gather4(dc, pptr[v], pptr[v + 1], pcol, pw, q, e0, e1, e2);
+  if (q == 3) return;
+  const long i = 3L * v + q;
+  const double tv = mg_cons(flag[v], q) ? 0.0 : pick3(q, a0, a1, a2) + pick3(q, e0, e1, e2);
+  df[i] = tv;
+  xf[i] += tv;
 }
 
 // plain prolongation (tests): xf = P xc
@@ -344,20 +406,24 @@ __global__ __launch_bounds__(256) void k_mg_prolong_plain(const double* __restri
 // coarsest level: x = A~^-1 b
 __global__ __launch_bounds__(256) void k_mg_coarse_solve(const double* __restrict__ Ainv,
                                                          const double* __restrict__ b, double* __restrict__ x, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= n) return;  // whole waves leave together
   double s = 0.0;
-  for (int j = 0; j < n; ++j) s = fma(Ainv[(long)i * n + j], b[j], s);
-  x[i] = s;
+  for (int j = lane; j < n; j += 64) s = fma(Ainv[(long)i * n + j], b[j], s);
+  s = wave_sum(s);
+  if (lane == 0) x[i] = s;
 }
 
 // ---------------------------------------------------------------- set-up kernels
-// weight of parent corner a at corner a2 of the child in octant o (trilinear)
-__device__ __forceinline__ double mg_pw(int o, int a2, int a) {
+// placement of a child in its parent: bits 0-1 log2 of the size ratio r
+// (1, 2 or 4), bits 2 + 2 ax the child's offset along axis ax in child edges
+// (0 .. r - 1).  Weight of parent corner a at child corner a2 (trilinear).
+__device__ __forceinline__ double mg_pw(int code, int a2, int a) {
+  const double inv_r = 1.0 / (double)(1 << (code & 3));
   double w = 1.0;
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax) {
-    const double t = 0.5 * (double)(((o >> ax) & 1) + ((a2 >> ax) & 1));  // child corner in parent coordinates
+    const double t = (double)(((code >> (2 + 2 * ax)) & 3) + ((a2 >> ax) & 1)) * inv_r;
     w *= ((a >> ax) & 1) ? t : 1.0 - t;
   }
   return w;
@@ -367,7 +433,7 @@ __device__ __forceinline__ double mg_pw(int o, int a2, int a) {
 // (P_j (x) I3)^T K_j (P_j (x) I3); K_j dense (previous level) or c K0
 __global__ __launch_bounds__(256) void k_mg_galerkin(const int32_t* __restrict__ cptr,
                                                      const int32_t* __restrict__ celem,
-                                                     const int8_t* __restrict__ coct, int nd,
+                                                     const uint8_t* __restrict__ coct, int nd,
                                                      const double* __restrict__ Kd_f, int nd_f,
                                                      const int32_t* __restrict__ pure_f,
                                                      const double* __restrict__ coef, const double* __restrict__ K0,
@@ -380,13 +446,13 @@ __global__ __launch_bounds__(256) void k_mg_galerkin(const int32_t* __restrict__
     const int ch = celem[k], o = coct[k];
     __syncthreads();
     if (ch < nd_f) {
-      for (int i = threadIdx.x; i < 576; i += blockDim.x) Kc[i] = Kd_f[(long)i * nd_f + ch];
+      for (int i = threadIdx.x; i < 576; i += blockDim.x) Kc[i] = Kd_f[576L * ch + (i % 24) * 24 + i / 24];
     } else {
       const double c = coef[pure_f[ch - nd_f]];
       for (int i = threadIdx.x; i < 576; i += blockDim.x) Kc[i] = c * K0[i];
     }
     __syncthreads();
-    if (o == 8) {
+    if (o == 0) {  // the same box
       for (int i = threadIdx.x, t = 0; i < 576; i += blockDim.x, ++t) acc[t] += Kc[i];
       continue;
     }
@@ -406,7 +472,7 @@ __global__ __launch_bounds__(256) void k_mg_galerkin(const int32_t* __restrict__
       acc[t] += s;
     }
   }
-  for (int i = threadIdx.x, t = 0; i < 576; i += blockDim.x, ++t) Kd[(long)i * nd + e] = acc[t];
+  for (int i = threadIdx.x, t = 0; i < 576; i += blockDim.x, ++t) Kd[576L * e + (i % 24) * 24 + i / 24] = acc[t];
 }
 
 // exact diagonal of A~ on a level: per node and component, over the node's
@@ -438,8 +504,9 @@ __global__ __launch_bounds__(256) void k_mg_diag(const int32_t* __restrict__ ipt
         if (t[a] == 0.0) continue;
         for (int b = 0; b < 8; ++b) {
           if (t[b] == 0.0) continue;
-          const int i = (3 * a + c) * 24 + 3 * b + c;
-          s += t[a] * t[b] * (e < nd ? Kd[(long)i * nd + e] : K0[i]);
+          const int i = (3 * a + c) * 24 + 3 * b + c;   // row-major in K0
+          const int ic = (3 * b + c) * 24 + 3 * a + c;  // column-major in Kd
+          s += t[a] * t[b] * (e < nd ? Kd[576L * e + ic] : K0[i]);
         }
       }
       dg[c] += e < nd ? s : coef[pure_src[e - nd]] * s;
@@ -497,7 +564,7 @@ __global__ __launch_bounds__(1024) void k_mg_coarse_assemble(const int32_t* __re
     for (int i = threadIdx.x; i < 576; i += blockDim.x) {
       const int row = i / 24, col = i % 24;
       const int I = 3 * elem[8L * e + row / 3] + row % 3, J = 3 * elem[8L * e + col / 3] + col % 3;
-      const double k = e < nd ? Kd[(long)i * nd + e] : coef[pure_src[e - nd]] * K0[i];
+      const double k = e < nd ? Kd[576L * e + col * 24 + row] : coef[pure_src[e - nd]] * K0[i];
       A[(long)I * n + J] += k;
     }
     __syncthreads();
@@ -533,42 +600,7 @@ __global__ __launch_bounds__(1024) void k_mg_invert(double* __restrict__ A, int 
 }
 
 // ---------------------------------------------------------------- PCG kernels
-__global__ __launch_bounds__(256) void k_mgcg_init(const double* __restrict__ b, const double* __restrict__ q,
-                                                   const uint8_t* __restrict__ flag, double* __restrict__ r, long n,
-                                                   double* __restrict__ part) {
-  __shared__ double sh[16];
-  double rr = 0.0, bb = 0.0;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const bool cs = mg_cons(flag[i / 3], (int)(i % 3));
-    const double bi = cs ? 0.0 : b[i];
-    const double ri = cs ? 0.0 : bi - q[i];
-    r[i] = ri;
-    rr += ri * ri;
-    bb += bi * bi;
-  }
-  block_sum2(rr, bb, sh);
-  if (threadIdx.x == 0) {
-    part[2 * MG_RED + blockIdx.x] = rr;
-    part[3 * MG_RED + blockIdx.x] = bb;
-  }
-}
 
-__global__ void k_mgcg_init_scal(const double* __restrict__ part, double* __restrict__ cg, double tol2) {
-  __shared__ double sh[16];
-  double rr = 0.0, bb = 0.0;
-  for (int i = threadIdx.x; i < MG_RED; i += blockDim.x) {
-    rr += part[2 * MG_RED + i];
-    bb += part[3 * MG_RED + i];
-  }
-  block_sum2(rr, bb, sh);
-  if (threadIdx.x == 0) {
-    cg[MC_BB] = bb;
-    cg[MC_RR] = rr;
-    cg[MC_ITERS] = 0.0;
-    cg[MC_RZ] = 0.0;
-    cg[MC_DONE] = (rr <= tol2 * bb) ? 1.0 : ((rr == rr && rr < 1e300) ? 0.0 : 2.0);
-  }
-}
 
 // z = x0 + d0 (the V-cycle's last correction folded in); partials of r.z
 __global__ __launch_bounds__(256) void k_mgcg_rz(const double* __restrict__ x0, const double* __restrict__ d0,
@@ -587,62 +619,9 @@ __global__ __launch_bounds__(256) void k_mgcg_rz(const double* __restrict__ x0, 
 }
 
 // p = z + beta p with beta = r.z / (r.z)_old (beta = 0 on the first iteration)
-__global__ __launch_bounds__(256) void k_mgcg_dir(const double* __restrict__ z, double* __restrict__ p, long n,
-                                                  const double* __restrict__ part, double* __restrict__ cg,
-                                                  int first) {
-  __shared__ double sh[16];
-  const double rz = sum_partials(part, MG_RED, sh);
-  if (cg[MC_DONE] != 0.0) return;
-  const double beta = first ? 0.0 : rz / cg[MC_RZ];
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-    p[i] = z[i] + beta * p[i];
-  // every block has read the old r.z before any block can run the next kernel
-  if (blockIdx.x == 0 && threadIdx.x == 0) cg[MC_RZ + 6] = rz;
-}
 
-__global__ __launch_bounds__(256) void k_mgcg_pq(const double* __restrict__ p, const double* __restrict__ q, long n,
-                                                 double* __restrict__ part, double* __restrict__ cg) {
-  __shared__ double sh[16];
-  if (cg[MC_DONE] != 0.0) return;
-  double s = 0.0;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-    s += p[i] * q[i];
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) part[MG_RED + blockIdx.x] = s;
-  if (blockIdx.x == 0 && threadIdx.x == 0) cg[MC_RZ] = cg[MC_RZ + 6];
-}
 
-__global__ __launch_bounds__(256) void k_mgcg_update(double* __restrict__ x, double* __restrict__ r,
-                                                     const double* __restrict__ p, const double* __restrict__ q,
-                                                     long n, double* __restrict__ part, double* __restrict__ cg) {
-  __shared__ double sh[16];
-  const double pq = sum_partials(part + MG_RED, MG_RED, sh);
-  if (cg[MC_DONE] != 0.0) return;
-  if (!(pq > 0.0) || !(pq < 1e300)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) cg[MC_DONE] = 2.0;
-    return;
-  }
-  const double alpha = cg[MC_RZ] / pq;
-  double rr = 0.0;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * q[i];
-    r[i] = ri;
-    rr += ri * ri;
-  }
-  rr = block_sum(rr, sh);
-  if (threadIdx.x == 0) part[2 * MG_RED + blockIdx.x] = rr;
-}
 
-__global__ void k_mgcg_check(const double* __restrict__ part, double* __restrict__ cg, int it, double tol2) {
-  __shared__ double sh[16];
-  const double rr = sum_partials(part + 2 * MG_RED, MG_RED, sh);
-  if (threadIdx.x != 0 || cg[MC_DONE] != 0.0) return;
-  cg[MC_RR] = rr;
-  cg[MC_ITERS] = it + 1;
-  if (!(rr == rr) || rr > 1e300) cg[MC_DONE] = 2.0;
-  else if (rr <= tol2 * cg[MC_BB]) cg[MC_DONE] = 1.0;
-}
 
 __global__ __launch_bounds__(256) void k_mgcg_resid(const double* __restrict__ b, const double* __restrict__ q,
                                                     const uint8_t* __restrict__ flag, long n,
@@ -679,17 +658,123 @@ __global__ __launch_bounds__(256) void k_mg_mask_copy(const double* __restrict__
   if (i < n) dst[i] = mg_cons(flag[i / 3], (int)(i % 3)) ? 0.0 : src[i];
 }
 
+// CG on the fused operator pass (S_* scalar slots, RED_BLOCKS partials):
+// r = b - q masked, the level-0 smoother started from r, partials r.r and b.b
+__global__ __launch_bounds__(256) void k_mgcg_start(const double* __restrict__ b, const double* __restrict__ q,
+                                                    const uint8_t* __restrict__ flag, double* __restrict__ r,
+                                                    long n, const double* __restrict__ dinv,
+                                                    const double* __restrict__ s0, double* __restrict__ x0,
+                                                    double* __restrict__ r0, double* __restrict__ d0,
+                                                    double* __restrict__ part) {
+  __shared__ double sh[16];
+  double rr = 0.0, bb = 0.0;
+  const double th = s0[MS_THETA];
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const bool cs = mg_cons(flag[i / 3], (int)(i % 3));
+    const double bi = cs ? 0.0 : b[i];
+    const double ri = cs ? 0.0 : bi - q[i];
+    r[i] = ri;
+    x0[i] = 0.0;
+    r0[i] = ri;
+    d0[i] = dinv[i] * ri / th;
+    rr += ri * ri;
+    bb += bi * bi;
+  }
+  block_sum2(rr, bb, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = rr;
+    part[RED_BLOCKS + blockIdx.x] = bb;
+  }
+}
+
+__global__ void k_mgcg_start_scal(const double* __restrict__ part, double* __restrict__ scal, double tol2) {
+  __shared__ double sh[16];
+  double rr = 0.0, bb = 0.0;
+  for (int i = threadIdx.x; i < RED_BLOCKS; i += blockDim.x) {
+    rr += part[i];
+    bb += part[RED_BLOCKS + i];
+  }
+  block_sum2(rr, bb, sh);
+  if (threadIdx.x == 0) {
+    scal[S_BB] = bb;
+    scal[S_RR] = rr;
+    scal[S_ITERS] = 0.0;
+    scal[S_RZ0] = scal[S_RZ1] = 0.0;
+    scal[S_DONE] = (rr <= tol2 * bb) ? 1.0 : ((rr == rr && rr < 1e300) ? 0.0 : 2.0);
+  }
+}
+
+// z = x0 + d0 (the V-cycle's output with its last correction); partials r.z, r.r
+__global__ __launch_bounds__(256) void k_mgcg_z(const double* __restrict__ x0, const double* __restrict__ d0,
+                                                const double* __restrict__ r, double* __restrict__ z, long n,
+                                                double* __restrict__ part, const double* __restrict__ scal) {
+  __shared__ double sh[16];
+  if (scal[S_DONE] != 0.0) return;
+  double rz = 0.0, rr = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double zi = x0[i] + d0[i], ri = r[i];
+    z[i] = zi;
+    rz += ri * zi;
+    rr += ri * ri;
+  }
+  block_sum2(rz, rr, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = rz;
+    part[RED_BLOCKS + blockIdx.x] = rr;
+  }
+}
+
+// alpha = r.z / p.q; x += alpha p; r -= alpha q; the level-0 smoother starts from r
+__global__ __launch_bounds__(256) void k_mgcg_step(double* __restrict__ x, double* __restrict__ r,
+                                                   const double* __restrict__ p, const double* __restrict__ q,
+                                                   long n, const double* __restrict__ part_pq, int n_pq,
+                                                   double* __restrict__ scal, int it,
+                                                   const double* __restrict__ dinv, const double* __restrict__ s0,
+                                                   double* __restrict__ x0, double* __restrict__ r0,
+                                                   double* __restrict__ d0) {
+  __shared__ double sh[16];
+  const double done = scal[S_DONE];
+  const double pq = sum_partials(part_pq, n_pq, sh);
+  if (done != 0.0) return;
+  const double rz = scal[S_RZ0 + (it & 1)];
+  if (!(pq > 0.0) || !(pq < 1e300) || !(rz == rz)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_DONE] = 2.0;
+    return;
+  }
+  const double alpha = rz / pq, th = s0[MS_THETA];
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    x0[i] = 0.0;
+    r0[i] = ri;
+    d0[i] = dinv[i] * ri / th;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mg_zero(double* __restrict__ a, double* __restrict__ b, long n) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < n) {
+    a[i] = 0.0;
+    b[i] = 0.0;
+  }
+}
+
 // ---------------------------------------------------------------- host side
 int blocks_for(long n) { return (int)std::max<long>(1, std::min<long>((n + 255) / 256, 1L << 20)); }
 
 // q = A_k d on level k >= 1 (element pass), then the gather pass with update u
 int level_pass(amrto_ctx* ctx, MgLevel& L, const double* in, const MgUpd& u, double* part) {
-  hipLaunchKernelGGL(k_mg_elem, dim3(blocks_for(L.ne)), dim3(256), 0, ctx->stream, in, L.elem, L.flag, L.hang_of,
-                     L.hptr, L.hm, L.hw, L.Kd, L.nd, L.pure_src, ctx->d_coef, ctx->d_K0, L.E, L.ne);
+  hipLaunchKernelGGL(k_mg_elem, dim3((L.ne + ME - 1) / ME), dim3(24 * ME), 0, ctx->stream, in, L.ev, L.flag, L.hm4,
+                     L.hw4, L.Kd, L.nd, L.pure_src, ctx->d_coef, ctx->d_K0, L.E, L.ne);
   // the Rayleigh partials fill exactly MG_RED slots
-  const int grid = u.mode == MG_RAYLEIGH ? MG_RED : blocks_for(L.nn);
-  hipLaunchKernelGGL(k_mg_gather, dim3(grid), dim3(256), 0, ctx->stream, L.E, L.iptr,
-                     L.islot, L.iw, L.flag, L.nn, u, part);
+  const int grid = u.mode == MG_RAYLEIGH ? MG_RED : blocks_for((long)L.lanes * L.nn);
+  if (L.lanes == 8)
+    hipLaunchKernelGGL(k_mg_gather<8>, dim3(grid), dim3(256), 0, ctx->stream, L.E, L.iptr, L.islot, L.iw, L.flag, L.nn,
+                       u, part);
+  else
+    hipLaunchKernelGGL(k_mg_gather<4>, dim3(grid), dim3(256), 0, ctx->stream, L.E, L.iptr, L.islot, L.iw, L.flag, L.nn,
+                       u, part);
   return hipGetLastError() == hipSuccess ? AMRTO_OK : ctx->fail(AMRTO_EHIP, "multigrid level pass");
 }
 
@@ -728,7 +813,7 @@ int vcycle_from(amrto_ctx* ctx, int k) {
   int rc;
   if (k == g->nlev - 1) {
     const int n = 3 * L.nn;
-    hipLaunchKernelGGL(k_mg_coarse_solve, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, L.Ainv, L.b, L.x, n);
+    hipLaunchKernelGGL(k_mg_coarse_solve, dim3((n + 3) / 4), dim3(256), 0, ctx->stream, L.Ainv, L.b, L.x, n);
     return hipGetLastError() == hipSuccess ? AMRTO_OK : ctx->fail(AMRTO_EHIP, "multigrid coarse solve");
   }
   const int m = g->degree;
@@ -736,11 +821,11 @@ int vcycle_from(amrto_ctx* ctx, int k) {
     if ((rc = pass(ctx, k, L.d, upd(L, s == m - 1 ? MG_CHEB_LAST : MG_CHEB, s)))) return rc;
   MgLevel& C = g->lv[k + 1];
   const bool coarsest = k + 1 == g->nlev - 1;
-  hipLaunchKernelGGL(k_mg_restrict, dim3(blocks_for(C.nn)), dim3(256), 0, ctx->stream, L.r, C.rptr, C.rcol, C.rw,
+  hipLaunchKernelGGL(k_mg_restrict, dim3(blocks_for(4L * C.nn)), dim3(256), 0, ctx->stream, L.r, C.rptr, C.rcol, C.rw,
                      C.flag, C.nn, C.b, coarsest ? 0 : 1, C.x, C.r, C.d, C.dinv, C.scal);
   if ((rc = vcycle_from(ctx, k + 1))) return rc;
   // x += P x_c (the coarse level's last correction d folded in), d = that correction
-  hipLaunchKernelGGL(k_mg_prolong, dim3(blocks_for(L.nn)), dim3(256), 0, ctx->stream, C.x,
+  hipLaunchKernelGGL(k_mg_prolong, dim3(blocks_for(4L * L.nn)), dim3(256), 0, ctx->stream, C.x,
                      coarsest ? (const double*)nullptr : C.d, C.pptr, C.pcol, C.pw, L.flag, L.nn, L.x, L.d);
   if ((rc = pass(ctx, k, L.d, upd(L, MG_CORR)))) return rc;
   // post-smoothing: m - 1 passes; the last correction stays in d (added by the consumer)
@@ -841,7 +926,7 @@ struct HostLevel {
   LevelMesh m;
   std::vector<int32_t> perm;      // original element -> device order
   std::vector<int32_t> parent;    // original element -> parent on the next level (original order there)
-  std::vector<int8_t> oct;        // octant within the parent, 8 = the same box
+  std::vector<uint8_t> oct;       // placement within the parent (see mg_pw), 0 = the same box
   std::vector<uint8_t> pure;      // per original element
   std::vector<int32_t> src;       // per original element: coefficient index when pure
   int nd = 0;
@@ -853,18 +938,17 @@ inline uint64_t anchor_key(int64_t x, int64_t y, int64_t z) {
   return ((uint64_t)z << 40) | ((uint64_t)y << 20) | (uint64_t)x;
 }
 
-int build_hierarchy(amrto_ctx* ctx, const amrto_octree* tree, int coarse_dofs, std::vector<HostLevel>& H) {
+int build_hierarchy(amrto_ctx* ctx, const amrto_octree* tree, int coarse_dofs, int first, std::vector<HostLevel>& H) {
   H.clear();
   H.emplace_back();
   if (!octree_level_mesh(tree, 0, &H[0].m)) return ctx->fail(AMRTO_ESTATE, "amrto_mg_setup: the tree has no mesh");
   if (H[0].m.n_nodes != ctx->n_nodes || H[0].m.n_elems != ctx->n_elems)
     return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: the tree's mesh is not the uploaded mesh");
   const int L = H[0].m.L;
-  for (int k = 1;; ++k) {
-    const LevelMesh& prev = H.back().m;
-    const bool uniform_prev = k - 1 >= L;  // levels >= L are uniform grids
-    if (uniform_prev && 3 * prev.n_nodes <= coarse_dofs) break;
-    if (k >= MG_LMAX) break;
+  // depths 0, first, first + 1, ...; depths >= L are uniform grids
+  for (int k = first, prev = 0;; prev = k, ++k) {
+    if (prev >= L && 3 * H.back().m.n_nodes <= coarse_dofs) break;
+    if ((int)H.size() >= MG_LMAX) break;
     LevelMesh lm;
     if (!octree_level_mesh(tree, k, &lm)) break;
     H.emplace_back();
@@ -905,25 +989,26 @@ int build_hierarchy(amrto_ctx* ctx, const amrto_octree* tree, int coarse_dofs, s
     for (int e = 0; e < F.m.n_elems; ++e) {
       const int64_t s = 1L << (F.m.L - F.m.level[e]);
       const int32_t* a = &F.m.anchor[3L * e];
-      int found = -1, o = 8;
-      for (int64_t S : {s, 2 * s}) {
+      int found = -1, o = 0;
+      for (int lr = 0; lr <= 2 && found < 0; ++lr) {
+        const int64_t S = s << lr;
         auto it = box.find(anchor_key(a[0] / S * S, a[1] / S * S, a[2] / S * S));
         if (it != box.end() && (1L << (Cl.m.L - Cl.m.level[it->second])) == S) {
           found = it->second;
-          if (S != s) o = (int)(((a[0] / s) & 1) | (((a[1] / s) & 1) << 1) | (((a[2] / s) & 1) << 2));
-          break;
+          o = lr;
+          for (int ax = 0; ax < 3; ++ax) o |= (int)(((a[ax] % S) / s) << (2 + 2 * ax));
         }
       }
       if (found < 0) return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: a leaf has no parent on the next level");
       F.parent[e] = found;
-      F.oct[e] = (int8_t)o;
+      F.oct[e] = (uint8_t)o;
       nchild[found]++;
       only[found] = e;
     }
     Cl.pure.assign(ne, 0);
     Cl.src.assign(ne, -1);
     for (int e = 0; e < ne; ++e)
-      if (nchild[e] == 1 && F.oct[only[e]] == 8 && F.pure[only[e]]) {
+      if (nchild[e] == 1 && F.oct[only[e]] == 0 && F.pure[only[e]]) {
         Cl.pure[e] = 1;
         Cl.src[e] = F.src[only[e]];
       }
@@ -981,17 +1066,28 @@ int upload_level(amrto_ctx* ctx, MgData* g, std::vector<HostLevel>& H, int k) {
     for (int a = 0; a < 8; ++a) elem[8L * de + a] = m.elem_nodes[8L * e + a];
     if (h.pure[e]) psrc[de - h.nd] = h.src[e];
   }
+  std::vector<int32_t> evv(elem.size());
+  for (size_t i = 0; i < elem.size(); ++i) evv[i] = hang_of[elem[i]] < 0 ? elem[i] : -(hang_of[elem[i]] + 1);
   AMRTO_HIP(mg_upload(own, L.elem, elem));
+  AMRTO_HIP(mg_upload(own, L.ev, evv));
   AMRTO_HIP(mg_upload(own, L.pure_src, psrc));
   AMRTO_HIP(mg_alloc(own, L.Kd, 576L * h.nd));
   AMRTO_HIP(mg_alloc(own, L.E, 24L * ne));
-  // hanging table
+  // hanging table at a fixed stride of four masters
   std::vector<int32_t> hptr(m.hang_ptr.begin(), m.hang_ptr.end());
   if (hptr.empty()) hptr.push_back(0);
-  AMRTO_HIP(mg_upload(own, L.hang_of, hang_of));
-  AMRTO_HIP(mg_upload(own, L.hptr, hptr));
-  AMRTO_HIP(mg_upload(own, L.hm, m.hang_master));
-  AMRTO_HIP(mg_upload(own, L.hw, m.hang_w));
+  std::vector<int32_t> hm4(4L * L.nh);
+  std::vector<double> hw4(4L * L.nh, 0.0);
+  for (int h = 0; h < L.nh; ++h) {
+    const int k0 = m.hang_ptr[h], cnt = m.hang_ptr[h + 1] - k0;
+    if (cnt < 1 || cnt > 4) return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: a hanging node with more than four masters");
+    for (int k = 0; k < 4; ++k) {
+      hm4[4L * h + k] = m.hang_master[k0 + std::min(k, cnt - 1)];
+      hw4[4L * h + k] = k < cnt ? m.hang_w[k0 + k] : 0.0;
+    }
+  }
+  AMRTO_HIP(mg_upload(own, L.hm4, hm4));
+  AMRTO_HIP(mg_upload(own, L.hw4, hw4));
   // incidences per node (slot 8 e + a in device order), sorted by slot
   std::vector<std::vector<std::pair<int32_t, double>>> inc(nn);
   for (int e = 0; e < ne; ++e)
@@ -1018,15 +1114,16 @@ int upload_level(amrto_ctx* ctx, MgData* g, std::vector<HostLevel>& H, int k) {
   AMRTO_HIP(mg_upload(own, L.iptr, iptr));
   AMRTO_HIP(mg_upload(own, L.islot, islot));
   AMRTO_HIP(mg_upload(own, L.iw, iw));
+  L.lanes = islot.size() > 12L * nn ? 8 : 4;  // long incidence lists: more lanes per node
   // children of the dense elements (previous level, its device order)
   HostLevel& F = H[k - 1];
-  std::vector<std::vector<std::pair<int32_t, int8_t>>> ch(h.nd);
+  std::vector<std::vector<std::pair<int32_t, uint8_t>>> ch(h.nd);
   for (int e = 0; e < F.m.n_elems; ++e) {
     const int de = h.perm[F.parent[e]];
     if (de < h.nd) ch[de].push_back({F.perm[e], F.oct[e]});
   }
   std::vector<int32_t> cptr(h.nd + 1, 0), celem;
-  std::vector<int8_t> coct;
+  std::vector<uint8_t> coct;
   for (int e = 0; e < h.nd; ++e) {
     std::sort(ch[e].begin(), ch[e].end());
     for (auto& c : ch[e]) {
@@ -1097,14 +1194,18 @@ int upload_level(amrto_ctx* ctx, MgData* g, std::vector<HostLevel>& H, int k) {
       if (i < 0 || i >= lim) return false;
     return true;
   };
-  if (!in_range(elem, nn) || !in_range(psrc, ctx->n_elems) || !in_range(m.hang_master, nn) ||
+  if (!in_range(elem, nn) || !in_range(psrc, ctx->n_elems) || !in_range(hm4, nn) ||
       !in_range(islot, 8L * ne) || !in_range(celem, F.m.n_elems) || !in_range(pcol, nn) ||
       !in_range(rcol, fm.n_nodes) || (long)iptr.back() != (long)islot.size() ||
       (long)pptr.back() != (long)pcol.size() || (long)rptr.back() != (long)rcol.size() ||
       (long)cptr.back() != (long)celem.size() || (!hptr.empty() && (long)hptr.back() != (long)m.hang_master.size()))
     return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: inconsistent level tables");
-  for (size_t i = 0; i < celem.size(); ++i)
-    if (coct[i] < 0 || coct[i] > 8) return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: bad child octant");
+  for (size_t i = 0; i < celem.size(); ++i) {
+    const int lr = coct[i] & 3;
+    for (int ax = 0; ax < 3; ++ax)
+      if (lr > 2 || ((coct[i] >> (2 + 2 * ax)) & 3) >= (1 << lr))
+        return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: bad child placement");
+  }
   AMRTO_HIP(mg_upload(own, L.pptr, pptr));
   AMRTO_HIP(mg_upload(own, L.pcol, pcol));
   AMRTO_HIP(mg_upload(own, L.pw, pw));
@@ -1132,16 +1233,16 @@ int amrto_mg_setup(amrto_ctx* ctx, const amrto_octree* tree, const amrto_mg_opts
   if (!ctx) return AMRTO_EINVAL;
   if (!ctx->has_mesh) return ctx->fail(AMRTO_ESTATE, "amrto_mg_setup: no mesh uploaded");
   if (!tree) return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: NULL tree");
-  amrto_mg_opts o{2, 10.0, 20, 1.1, 200};
+  amrto_mg_opts o{2, 10.0, 20, 1.1, 200, 1};
   if (opts) o = *opts;
   if (o.degree < 1 || o.degree > 8 || !(o.ratio > 1.0) || o.power_its < 1 || o.power_its > 200 ||
-      !(o.hi_factor >= 1.0) || o.coarse_dofs < 3)
+      !(o.hi_factor >= 1.0) || o.coarse_dofs < 3 || o.first < 1 || o.first > 2)
     return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: bad options");
   AMRTO_HIP(hipSetDevice(ctx->device));
   AMRTO_HIP(hipStreamSynchronize(ctx->stream));
   mg_free(ctx);
   std::vector<HostLevel> H;
-  int rc = build_hierarchy(ctx, tree, o.coarse_dofs, H);
+  int rc = build_hierarchy(ctx, tree, o.coarse_dofs, o.first, H);
   if (rc) return rc;
   MgData* g = new (std::nothrow) MgData();
   if (!g) return ctx->fail(AMRTO_ENOMEM, "amrto_mg_setup: out of host memory");
@@ -1159,8 +1260,9 @@ int amrto_mg_setup(amrto_ctx* ctx, const amrto_octree* tree, const amrto_mg_opts
   const long n0 = 3L * ctx->n_nodes;
   if (mg_alloc(g->owned, g->part, 4 * MG_RED) != hipSuccess || mg_alloc(g->owned, g->cg, MC_COUNT) != hipSuccess ||
       mg_alloc(g->owned, g->z, n0) != hipSuccess || mg_alloc(g->owned, g->p, n0) != hipSuccess ||
-      mg_alloc(g->owned, g->qv, n0) != hipSuccess ||
-      hipHostMalloc((void**)&g->h_cg, MC_COUNT * sizeof(double)) != hipSuccess) {
+      mg_alloc(g->owned, g->qv, n0) != hipSuccess || mg_alloc(g->owned, g->z2, n0) != hipSuccess ||
+      mg_alloc(g->owned, g->cpart, 2 * RED_BLOCKS) != hipSuccess || mg_alloc(g->owned, g->cs, S_COUNT) != hipSuccess ||
+      hipHostMalloc((void**)&g->h_cg, std::max<int>(MC_COUNT, S_COUNT) * sizeof(double)) != hipSuccess) {
     mg_free(ctx);
     return ctx->fail(AMRTO_ENOMEM, "amrto_mg_setup: out of device memory");
   }
@@ -1272,7 +1374,7 @@ int amrto_mg_restrict(amrto_ctx* ctx, int32_t k, const double* rf, double* rc_ou
     return ctx->fail(AMRTO_EINVAL, "amrto_mg_restrict: level out of range or bad buffers");
   AMRTO_HIP(hipSetDevice(ctx->device));
   MgLevel& C = g->lv[k];
-  hipLaunchKernelGGL(k_mg_restrict, dim3(blocks_for(C.nn)), dim3(256), 0, ctx->stream, rf, C.rptr, C.rcol, C.rw,
+  hipLaunchKernelGGL(k_mg_restrict, dim3(blocks_for(4L * C.nn)), dim3(256), 0, ctx->stream, rf, C.rptr, C.rcol, C.rw,
                      C.flag, C.nn, rc_out, 0, (double*)nullptr, (double*)nullptr, (double*)nullptr,
                      (const double*)nullptr, (const double*)nullptr);
   AMRTO_HIP(hipGetLastError());
@@ -1292,41 +1394,46 @@ int amrto_mg_pcg(amrto_ctx* ctx, const double* b, double* u, double rtol, int32_
   MgLevel& L0 = g->lv[0];
   const long n = 3L * ctx->n_nodes;
   const double tol2 = rtol * rtol;
-  double* r = g->lv[0].b;  // the level-0 right-hand side buffer holds the CG residual
-  // x = u masked; r = b - A~ x
+  double* r = L0.b;  // the CG residual (the level-0 smoother keeps its own in L0.r)
+  double* p0 = g->p;
+  double* p1 = g->z2;
+  // x = u masked; r = b - A~ x; the level-0 smoother starts from r
   hipLaunchKernelGGL(k_mg_mask_copy, dim3(blocks_for(n)), dim3(256), 0, ctx->stream, u, g->qv, L0.flag, n);
   AMRTO_HIP(hipMemcpyAsync(u, g->qv, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  hipLaunchKernelGGL(k_mg_zero, dim3(blocks_for(n)), dim3(256), 0, ctx->stream, p0, p1, n);
   if ((rc = launch_apply(ctx, u, g->qv, AMRTO_FP64))) return rc;
-  hipLaunchKernelGGL(k_mgcg_init, dim3(MG_RED), dim3(256), 0, ctx->stream, b, g->qv, L0.flag, r, n, g->part);
-  hipLaunchKernelGGL(k_mgcg_init_scal, dim3(1), dim3(256), 0, ctx->stream, g->part, g->cg, tol2);
+  hipLaunchKernelGGL(k_mgcg_start, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, b, g->qv, L0.flag, r, n, L0.dinv,
+                     L0.scal, L0.x, L0.r, L0.d, g->cpart);
+  hipLaunchKernelGGL(k_mgcg_start_scal, dim3(1), dim3(256), 0, ctx->stream, g->cpart, g->cs, tol2);
   AMRTO_HIP(hipGetLastError());
   int it = 0, status = AMRTO_NOT_CONVERGED;
   while (true) {
-    AMRTO_HIP(hipMemcpyAsync(g->h_cg, g->cg, MC_COUNT * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    AMRTO_HIP(hipMemcpyAsync(g->h_cg, g->cs, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     AMRTO_HIP(hipStreamSynchronize(ctx->stream));
-    const double done = g->h_cg[MC_DONE];
+    const double done = g->h_cg[S_DONE];
     if (done == 1.0) {
       status = AMRTO_OK;
-      it = (int)g->h_cg[MC_ITERS];
+      it = (int)g->h_cg[S_ITERS];
       break;
     }
     if (done == 2.0) {
       status = AMRTO_EBREAKDOWN;
-      it = (int)g->h_cg[MC_ITERS];
+      it = (int)g->h_cg[S_ITERS];
       break;
     }
     if (it >= max_it) break;
     const int batch = std::min(check_every, max_it - it);
     for (int k = it; k < it + batch; ++k) {
-      if ((rc = vcycle(ctx, r))) return rc;
-      hipLaunchKernelGGL(k_mgcg_rz, dim3(MG_RED), dim3(256), 0, ctx->stream, L0.x, L0.d, r, g->z, n, g->part, g->cg);
-      hipLaunchKernelGGL(k_mgcg_dir, dim3(MG_RED), dim3(256), 0, ctx->stream, g->z, g->p, n, g->part, g->cg,
-                         k == 0 ? 1 : 0);
-      if ((rc = launch_apply(ctx, g->p, g->qv, AMRTO_FP64))) return rc;
-      hipLaunchKernelGGL(k_mgcg_pq, dim3(MG_RED), dim3(256), 0, ctx->stream, g->p, g->qv, n, g->part, g->cg);
-      hipLaunchKernelGGL(k_mgcg_update, dim3(MG_RED), dim3(256), 0, ctx->stream, u, r, g->p, g->qv, n, g->part,
-                         g->cg);
-      hipLaunchKernelGGL(k_mgcg_check, dim3(1), dim3(256), 0, ctx->stream, g->part, g->cg, k, tol2);
+      // z = V-cycle(r); p = z + beta p_old, q = A~ p and p.q in one fused pass; update
+      if ((rc = vcycle_from(ctx, 0))) return rc;
+      hipLaunchKernelGGL(k_mgcg_z, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, L0.x, L0.d, r, g->z, n, g->cpart,
+                         g->cs);
+      double* pnew = (k & 1) ? p1 : p0;
+      double* pold = (k & 1) ? p0 : p1;
+      CgArgs cg{g->cs, g->cpart, ctx->d_partpq, 0, k, tol2, 0};
+      if ((rc = apply_fused(ctx, g->z, pold, pnew, g->qv, AMRTO_FP64, cg))) return rc;
+      hipLaunchKernelGGL(k_mgcg_step, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, u, r, pnew, g->qv, n,
+                         ctx->d_partpq, ctx->n_partpq, g->cs, k, L0.dinv, L0.scal, L0.x, L0.r, L0.d);
     }
     AMRTO_HIP(hipGetLastError());
     it += batch;

@@ -25,7 +25,7 @@ def _t(a):
 
 
 class MgCase:
-    def __init__(self, kind):
+    def __init__(self, kind, first):
         if kind == "octree":
             self.pair = octree_pair((8, 4, 4), 2)
             self.base = (8, 4, 4)
@@ -39,9 +39,9 @@ class MgCase:
         self.ctx = binding.Context(0)
         self.ctx.upload_mesh(p.lib_mesh)
         self.ctx.set_density(_t(p.to_lib_elems(rho)))
-        self.ctx.mg_setup(p.case["tree"], coarse_dofs=COARSE)
+        self.ctx.mg_setup(p.case["tree"], coarse_dofs=COARSE, first=first)
         self.sys = oracle_system(p, rho)
-        self.levels = mg.hierarchy(p.orc, self.base, p.case["fixed"], coarse_dofs=COARSE)
+        self.levels = mg.hierarchy(p.orc, self.base, p.case["fixed"], coarse_dofs=COARSE, first=first)
         self.M = mg.setup(self.levels, self.sys.A)
         self.dp = p.dof_perm  # library level-0 DOF -> oracle DOF
 
@@ -57,15 +57,16 @@ class MgCase:
         return out
 
 
-@pytest.fixture(scope="module", params=["octree", "uniform"])
+@pytest.fixture(scope="module", params=[("octree", 1), ("octree", 2), ("uniform", 1), ("uniform", 2)],
+                ids=lambda p: f"{p[0]}-first{p[1]}")
 def case(request):
-    return MgCase(request.param)
+    return MgCase(*request.param)
 
 
 def test_hierarchy_matches_oracle(case):
     info = case.ctx.mg_info()
     assert info["dofs"] == [3 * lv.mesh.n_nodes for lv in case.levels]
-    assert info["levels"] >= 3
+    assert info["levels"] >= 2
     if case.levels[1].mesh.hanging.any():
         assert info["dense"][1] > 0
 

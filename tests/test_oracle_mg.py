@@ -63,9 +63,10 @@ def test_hierarchy_stops_at_a_small_uniform_level(small):
     assert all(3 * a.mesh.n_nodes > 3 * b.mesh.n_nodes for a, b in zip(levels, levels[1:]))
 
 
-def test_prolongation_reproduces_linear_fields(small):
+@pytest.mark.parametrize("first", [1, 2])
+def test_prolongation_reproduces_linear_fields(small, first):
     case, m0 = small
-    levels = mg.hierarchy(m0, case.base, [], coarse_dofs=100)   # no supports: every field is admissible
+    levels = mg.hierarchy(m0, case.base, [], coarse_dofs=100, first=first)   # no supports: any field
     rng = np.random.default_rng(3)
     G = rng.standard_normal((3, 3))
     c0 = rng.standard_normal(3)
@@ -76,9 +77,10 @@ def test_prolongation_reproduces_linear_fields(small):
         assert np.abs(P @ uc - uf).max() <= 1e-12 * np.abs(uf).max()
 
 
-def test_galerkin_equals_coarse_stiffness_for_coarse_constant_density(small):
+@pytest.mark.parametrize("first", [1, 2])
+def test_galerkin_equals_coarse_stiffness_for_coarse_constant_density(small, first):
     case, m0 = small
-    levels = mg.hierarchy(m0, case.base, case.fixed, coarse_dofs=100)
+    levels = mg.hierarchy(m0, case.base, case.fixed, coarse_dofs=100, first=first)
     f, c = levels[0], levels[1]
     rng = np.random.default_rng(4)
     rho_c = rng.uniform(0.1, 1.0, c.mesh.n_elems)
