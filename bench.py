@@ -226,7 +226,7 @@ def main():
         u.zero_()
         if "+mg" in name:
             if not mg_ready[0]:
-                ctx.mg_setup(tree)
+                ctx.mg_setup(tree, first=2)
                 mg_ready[0] = True
             ctx.set_density(rho)  # a fresh density: the solve rebuilds the coarse operators
             torch.cuda.synchronize()

@@ -500,12 +500,13 @@ int amrto_octree_transfer_nodal(const amrto_octree* t, const double* u_old, doub
  * dense inverse.  Vectors are in the constrained form (zero at hanging and
  * supported DOFs). */
 typedef struct {
-  int32_t degree;       /* Chebyshev degree per smoothing (default 2) */
+  int32_t degree;       /* Chebyshev degree per smoothing on level 0 (default 2) */
   double ratio;         /* smoothing interval [hi / ratio, hi] (default 10) */
   int32_t power_its;    /* power iterations for lambda_max (default 20) */
   double hi_factor;     /* hi = hi_factor * estimate (default 1.1) */
   int32_t coarse_dofs;  /* target size of the coarsest level (default 200) */
   int32_t first;        /* octree levels merged by the first coarsening, 1 or 2 (default 1) */
+  int32_t coarse_degree; /* Chebyshev degree on the coarse levels (0: the same as degree) */
 } amrto_mg_opts;
 
 /* Build the hierarchy of the uploaded mesh from the host tree it was built

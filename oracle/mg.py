@@ -25,7 +25,8 @@ is a stronger, parallel alternative built from textbook definitions:
 * Galerkin operators A_k = P_k^T A_{k-1} P_k + (I - F_k) (identity rows for
   the constrained DOFs, as A~ has on level 0).
 * Smoother: the Chebyshev iteration for D^-1 A (D = diag A) on the interval
-  [hi / ratio, hi], hi = 1.1 lambda_max(D^-1 A), degree m (Golub and Varga's
+  [hi / ratio, hi], hi = 1.1 lambda_max(D^-1 A), degree m on level 0 and
+  optionally another degree on the coarse levels (Golub and Varga's
   three-term recurrence as in Saad, Iterative Methods for Sparse Linear
   Systems, Alg. 12.1).  The same polynomial smooths before and after the
   coarse correction, so one V-cycle is a symmetric operator.
@@ -174,20 +175,22 @@ class MG:
     degree: int = 2
     ratio: float = 10.0
     coarse_inv: np.ndarray = field(default=None)
+    coarse_degree: int = 0      # degree on levels k >= 1 (0: the same as degree)
 
     def vcycle(self, b, k=0):
         lv = self.levels[k]
         if k == len(self.levels) - 1:
             return self.coarse_inv @ b
-        x, r = chebyshev(lv.A, lv.dinv, b, np.zeros_like(b), lv.lo, lv.hi, self.degree)
+        m = self.degree if k == 0 or self.coarse_degree <= 0 else self.coarse_degree
+        x, r = chebyshev(lv.A, lv.dinv, b, np.zeros_like(b), lv.lo, lv.hi, m)
         P = self.levels[k + 1].P
         x = x + P @ self.vcycle(P.T @ r, k + 1)
         r = b - lv.A @ x
-        e, _ = chebyshev(lv.A, lv.dinv, r, np.zeros_like(b), lv.lo, lv.hi, self.degree, need_residual=False)
+        e, _ = chebyshev(lv.A, lv.dinv, r, np.zeros_like(b), lv.lo, lv.hi, m, need_residual=False)
         return x + e
 
 
-def setup(levels, A0, degree=2, ratio=10.0, bounds=None) -> MG:
+def setup(levels, A0, degree=2, ratio=10.0, bounds=None, coarse_degree=0) -> MG:
     """Galerkin operators, diagonals, smoothing intervals (``bounds``: optional
     list of lambda_max per smoothed level) and the coarsest inverse."""
     levels[0].A = A0.tocsr()
@@ -202,7 +205,7 @@ def setup(levels, A0, degree=2, ratio=10.0, bounds=None) -> MG:
             lv.lo = lv.hi / ratio
     Ac = levels[-1].A.toarray()
     inv = sla.cho_solve(sla.cho_factor(Ac), np.identity(len(Ac)))
-    return MG(levels, degree, ratio, 0.5 * (inv + inv.T))
+    return MG(levels, degree, ratio, 0.5 * (inv + inv.T), coarse_degree)
 
 
 def mg_pcg(A: sp.csr_matrix, b, mg: MG, x0=None, rtol=1e-8, max_it=10_000) -> PCGResult:

@@ -58,6 +58,16 @@ struct UArgs {
   double* zq_part = nullptr;
   const double* einv = nullptr;
   const double* ct = nullptr;
+  // multigrid smoothing epilogue (octree, FP64, plain pass): with q = A~ d at
+  // the owned nodes (x holds d), mode 1 updates x += d, r -= q and writes the
+  // next Chebyshev direction to y; mode 2 updates x and r only; mode 3 sets
+  // r -= q and y = D^-1 r / theta.  cheb_scal holds the level's interval
+  // (MS_* slots); dinv the diagonal inverse
+  int cheb_mode = 0;
+  int cheb_step = 0;
+  const double* cheb_scal = nullptr;
+  double* cheb_x = nullptr;
+  double* cheb_r = nullptr;
 };
 
 // ------------------------------------------------------------------ uniform brick, BF16 on the matrix cores
@@ -887,6 +897,17 @@ __global__ __launch_bounds__(chunk_threads(PREC, COARSE)) void k_apply_chunks(UA
   __syncthreads();
   double dot = 0.0;
   VT qk[COARSE ? NPT : 1][3];  // q of the owned regular nodes (coarse recurrence)
+  // Chebyshev coefficients of this step: rho_s from rho_0 = 1 / sigma
+  double ch_a = 0.0, ch_c = 0.0, ch_t = 1.0;
+  if (!FUSED && a.cheb_mode) {
+    const double sigma = a.cheb_scal[MS_SIGMA], delta = a.cheb_scal[MS_DELTA];
+    double rho = 1.0 / sigma;
+    for (int s = 0; s < a.cheb_step; ++s) rho = 1.0 / (2.0 * sigma - rho);
+    const double rho1 = 1.0 / (2.0 * sigma - rho);
+    ch_a = rho1 * rho;
+    ch_c = 2.0 * rho1 / delta;
+    ch_t = a.cheb_scal[MS_THETA];
+  }
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
     const int t = tid + NT * r;
@@ -901,6 +922,8 @@ __global__ __launch_bounds__(chunk_threads(PREC, COARSE)) void k_apply_chunks(UA
         if (FUSED) {
           PN[g + comp] = 0;
           Y[g + comp] = 0;
+        } else if (a.cheb_mode) {
+          if (a.cheb_mode != 2) Y[g + comp] = 0;
         } else {
           Y[g + comp] = X[g + comp];
         }
@@ -917,6 +940,20 @@ __global__ __launch_bounds__(chunk_threads(PREC, COARSE)) void k_apply_chunks(UA
         Y[g + comp] = q;
         dot += (double)pn * (double)q;
         if (COARSE) qk[r][comp] = q;
+      } else if (a.cheb_mode) {
+        // constrained-form vectors are zero at supported DOFs: q = 0 there
+        const double q = fixed ? 0.0 : (double)acc, dv = (double)xs[t * 3 + comp];
+        const double* __restrict__ dinv = (const double*)a.dinv;
+        if (a.cheb_mode == 3) {
+          const double rv = a.cheb_r[g + comp] - q;
+          a.cheb_r[g + comp] = rv;
+          Y[g + comp] = (VT)(dinv[g + comp] * rv / ch_t);
+        } else {
+          a.cheb_x[g + comp] += dv;
+          const double rv = a.cheb_r[g + comp] - q;
+          a.cheb_r[g + comp] = rv;
+          if (a.cheb_mode == 1) Y[g + comp] = (VT)(ch_a * dv + ch_c * dinv[g + comp] * rv);
+        }
       } else {
         Y[g + comp] = fixed ? X[g + comp] : acc;
       }
@@ -1243,6 +1280,26 @@ int apply_stop(amrto_ctx* ctx, const void* x, void* y, int prec, const double* s
 }
 
 int launch_apply(amrto_ctx* ctx, const void* x, void* y, int prec) { return apply_stop(ctx, x, y, prec, nullptr); }
+
+// the octree FP64 operator pass with the multigrid smoothing epilogue (see UArgs)
+int apply_cheb(amrto_ctx* ctx, const double* d, double* dnew, int mode, int step, const double* scal,
+               const double* dinv, double* x, double* r) {
+  if (ctx->uniform) return ctx->fail(AMRTO_ESTATE, "apply_cheb: octree meshes only");
+  if (mode < 1 || mode > 3 || !scal || !dinv || !x || !r || (mode != 2 && (!dnew || dnew == d)))
+    return ctx->fail(AMRTO_EINVAL, "apply_cheb: bad arguments");
+  UArgs a = base_args(ctx, AMRTO_FP64);
+  a.x = d;
+  a.y = dnew;
+  a.dinv = dinv;
+  a.cheb_mode = mode;
+  a.cheb_step = step;
+  a.cheb_scal = scal;
+  a.cheb_x = x;
+  a.cheb_r = r;
+  CgArgs cg;
+  std::memset(&cg, 0, sizeof cg);
+  return launch_t<double, P_F64, false>(ctx, a, cg);
+}
 
 // one fused CG step: p = z + beta p_old, q = A~ p, partial p.q
 int apply_fused(amrto_ctx* ctx, const void* z, const void* pold, void* pnew, void* q, int prec, const CgArgs& cg) {

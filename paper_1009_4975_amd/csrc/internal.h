@@ -67,6 +67,10 @@ struct DevArray {
   size_t n = 0;
 };
 
+// Smoothing interval of a multigrid level (device resident): lambda_max
+// estimate, theta, delta and sigma = theta / delta of the Chebyshev iteration.
+enum { MS_LAM = 0, MS_THETA = 1, MS_DELTA = 2, MS_SIGMA = 3, MS_COUNT = 4 };
+
 // Scalars of a running Krylov solve (device resident).
 enum ScalarSlot {
   S_RZ0 = 0,   // r.z, double buffered on iteration parity
@@ -263,6 +267,8 @@ int mask_vector(amrto_ctx* ctx, double* x);
 int mask_vector_n(amrto_ctx* ctx, double* x, int count);
 int launch_zt(amrto_ctx* ctx, const double* v);
 int apply_stop(amrto_ctx* ctx, const void* x, void* y, int prec, const double* stop);
+int apply_cheb(amrto_ctx* ctx, const double* d, double* dnew, int mode, int step, const double* scal,
+               const double* dinv, double* x, double* r);
 int apply_fused(amrto_ctx* ctx, const void* z, const void* pold, void* pnew, void* q, int prec, const CgArgs& cg);
 int block3_setup(amrto_ctx* ctx);
 template <typename VT, typename BT>

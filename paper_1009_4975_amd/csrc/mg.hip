@@ -39,23 +39,23 @@ namespace amrto {
 constexpr int MG_LMAX = 16;
 constexpr int MG_COARSE_MAX = 1024;
 constexpr int MG_RED = 256;  // partial sums of the multigrid kernels
-enum { MS_LAM = 0, MS_THETA = 1, MS_DELTA = 2, MS_SIGMA = 3, MS_COUNT = 4 };
 // PCG scalars
 enum { MC_RZ = 0, MC_BB = 1, MC_DONE = 2, MC_ITERS = 3, MC_RR = 4, MC_RES = 5, MC_COUNT = 8 };
 enum MgMode { MG_APPLY = 0, MG_CHEB = 1, MG_CHEB_LAST = 2, MG_CORR = 3, MG_POWER = 4, MG_RAYLEIGH = 5 };
 
 struct MgLevel {
   int nn = 0, ne = 0, nd = 0, nh = 0;  // nodes, elements, dense elements (first nd), hanging nodes
-  int32_t* elem = nullptr;       // [8 ne]
-  int32_t* ev = nullptr;         // [8 ne] vertex node, or -(row + 1) of the hanging table
   int32_t* pure_src = nullptr;   // [ne - nd] index into the context's c_e
   double* Kd = nullptr;          // [576 nd] per element, column-major: entry (i, j) at 576 e + 24 j + i
   uint8_t* flag = nullptr;       // per node: bits 0-2 supported components, bit 3 hanging
-  int32_t* hm4 = nullptr; double* hw4 = nullptr;  // hanging masters, four per hanging node (unused weight 0)
-  int lanes = 4;                 // lanes per node in the gather pass
-  int32_t* iptr = nullptr; int32_t* islot = nullptr; double* iw = nullptr;  // incidences (slot 8 e + a)
+  // assembled Galerkin operator: 3 x 3 block rows (supported columns zeroed;
+  // hanging rows empty), rebuilt per density from contribution lists
+  int nnzb = 0;
+  int32_t* bptr = nullptr; int32_t* bcol = nullptr; int32_t* bdiag = nullptr; double* bval = nullptr;
+  int32_t* kptr = nullptr; int32_t* ke = nullptr; uint8_t* kab = nullptr; double* kw = nullptr;
+  int lanes = 4;                 // lanes per node in the block-row pass
+  int rlanes = 4;                // lanes per node in the restriction to this level
   double* dinv = nullptr;        // owned except on level 0
-  double* E = nullptr;           // [24 ne] element outputs
   double *x = nullptr, *r = nullptr, *d = nullptr, *q = nullptr, *b = nullptr;
   double* scal = nullptr;        // MS_COUNT
   // coarse side of the transfer to the next finer level (this level k >= 1):
@@ -69,7 +69,7 @@ struct MgLevel {
 struct MgData {
   int nlev = 0;
   MgLevel lv[MG_LMAX];
-  int degree = 2, power_its = 20;
+  int degree = 2, coarse_degree = 2, power_its = 20;
   double ratio = 10.0, hi_factor = 1.1;
   bool user_bounds = false;
   double lam_user[MG_LMAX] = {};
@@ -177,71 +177,14 @@ __device__ __forceinline__ double pick3(int c, double a0, double a1, double a2) 
   return c == 0 ? a0 : (c == 1 ? a1 : a2);
 }
 
-// element outputs E[24 e + 3 a + c] = (K_e u_e) for the continuous field of x;
-// one thread per (element, row): the element's 24 values are gathered once
-// into LDS, then each thread streams its row of the element matrix
-constexpr int ME = 10;  // elements per workgroup (240 threads)
-__global__ __launch_bounds__(240) void k_mg_elem(const double* __restrict__ x, const int32_t* __restrict__ ev,
-                                                 const uint8_t* __restrict__ flag, const int32_t* __restrict__ hm4,
-                                                 const double* __restrict__ hw4,
-                                                 const double* __restrict__ Kd, int nd,
-                                                 const int32_t* __restrict__ pure_src,
-                                                 const double* __restrict__ coef, const double* __restrict__ K0g,
-                                                 double* __restrict__ E, int ne) {
-  __shared__ double K0[576];  // column-major: entry (i, j) at 24 j + i
-  __shared__ double su[ME][24];
-  for (int t = threadIdx.x; t < 576; t += blockDim.x) K0[t] = K0g[(t % 24) * 24 + t / 24];
-  const int le = threadIdx.x / 24, i = threadIdx.x % 24;
-  const int e = blockIdx.x * ME + le;
-  if (e < ne) {
-    const int v = ev[8L * e + i / 3], c = i % 3;
-    double val = 0.0;
-    if (v >= 0) {
-      const double xv = x[3L * v + c];
-      val = ((flag[v] >> c) & 1) ? 0.0 : xv;
-    } else {
-      // hanging vertex: at most four masters at a fixed stride (unused weights 0)
-      const long h = -(long)v - 1;
-      int m[4];
-      double w[4], xm[4];
-      uint8_t fm[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        m[k] = hm4[4 * h + k];
-        w[k] = hw4[4 * h + k];
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        xm[k] = x[3L * m[k] + c];
-        fm[k] = flag[m[k]];
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (!((fm[k] >> c) & 1)) val += w[k] * xm[k];
-    }
-    su[le][i] = val;
-  }
-  __syncthreads();
-  if (e >= ne) return;
-  double s = 0.0;
-  if (e < nd) {
-    const double* Kc = Kd + 576L * e + i;
-#pragma unroll
-    for (int j = 0; j < 24; ++j) s = fma(Kc[24 * j], su[le][j], s);
-  } else {
-#pragma unroll
-    for (int j = 0; j < 24; ++j) s = fma(K0[24 * j + i], su[le][j], s);
-    s *= coef[pure_src[e - nd]];
-  }
-  E[24L * e + i] = s;
-}
-
 struct MgUpd {
   int mode;
   int step;                 // Chebyshev step (MG_CHEB)
   const double* scal;       // MS_* of the level
   const double* dinv;
   double *x, *r, *d;
+  double* dn;               // where the next direction goes (MG_CHEB, MG_CORR): d itself only
+                            // when no thread of the pass reads other nodes' d
   const double* xin;        // MG_APPLY: identity rows; MG_POWER / MG_RAYLEIGH: iterate
   double* y;                // MG_APPLY / MG_POWER output
 };
@@ -258,13 +201,13 @@ __device__ __forceinline__ void mg_update(const MgUpd& u, long i, bool cons, dou
       for (int s = 0; s < u.step; ++s) rho = 1.0 / (2.0 * sigma - rho);
       const double rho1 = 1.0 / (2.0 * sigma - rho);
       if (cons) {
-        u.x[i] = 0.0; u.r[i] = 0.0; u.d[i] = 0.0;
+        u.x[i] = 0.0; u.r[i] = 0.0; u.dn[i] = 0.0;
       } else {
         const double dd = u.d[i];
         u.x[i] += dd;
         const double rr = u.r[i] - q;
         u.r[i] = rr;
-        u.d[i] = rho1 * rho * dd + (2.0 * rho1 / delta) * u.dinv[i] * rr;
+        u.dn[i] = rho1 * rho * dd + (2.0 * rho1 / delta) * u.dinv[i] * rr;
       }
       break;
     }
@@ -279,7 +222,7 @@ __device__ __forceinline__ void mg_update(const MgUpd& u, long i, bool cons, dou
     case MG_CORR: {
       const double rr = cons ? 0.0 : u.r[i] - q;
       u.r[i] = rr;
-      u.d[i] = u.dinv[i] * rr / u.scal[MS_THETA];
+      u.dn[i] = u.dinv[i] * rr / u.scal[MS_THETA];
       break;
     }
     case MG_POWER:
@@ -295,21 +238,35 @@ __device__ __forceinline__ void mg_update(const MgUpd& u, long i, bool cons, dou
   }
 }
 
-// per node: q = F T^T (sum of element outputs) and the update of mode u.mode;
-// four lanes per node (lane c < 3 updates component c)
+// per node: q = (A_k in)_v from the level's block rows (3 x 3 blocks of the
+// assembled Galerkin operator, supported columns zeroed), then the update of
+// mode u.mode; LANES lanes per node (lane c < 3 updates component c)
 template <int LANES>
-__global__ __launch_bounds__(256) void k_mg_gather(const double* __restrict__ E, const int32_t* __restrict__ iptr,
-                                                   const int32_t* __restrict__ islot, const double* __restrict__ iw,
-                                                   const uint8_t* __restrict__ flag, int nn, MgUpd u,
-                                                   double* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_mg_spmv(const double* __restrict__ in, const int32_t* __restrict__ bptr,
+                                                 const int32_t* __restrict__ bcol, const double* __restrict__ bval,
+                                                 const uint8_t* __restrict__ flag, int nn, MgUpd u,
+                                                 double* __restrict__ part) {
   __shared__ double sh[16];
   double t1 = 0.0, t2 = 0.0;
   const int q = threadIdx.x & (LANES - 1);
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)LANES * nn;
        t += (long)gridDim.x * blockDim.x) {
     const int v = (int)(t / LANES);
-    double a0, a1, a2;
-    row_gather<LANES>(E, iptr[v], iptr[v + 1], islot, iw, q, a0, a1, a2);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int k = bptr[v] + q; k < bptr[v + 1]; k += LANES) {
+      const long c = bcol[k];
+      const double x0 = in[3 * c], x1 = in[3 * c + 1], x2 = in[3 * c + 2];
+      const double* __restrict__ B = bval + 9L * k;
+      a0 = fma(B[0], x0, fma(B[1], x1, fma(B[2], x2, a0)));
+      a1 = fma(B[3], x0, fma(B[4], x1, fma(B[5], x2, a1)));
+      a2 = fma(B[6], x0, fma(B[7], x1, fma(B[8], x2, a2)));
+    }
+#pragma unroll
+    for (int o = 1; o < LANES; o <<= 1) {
+      a0 += __shfl_xor(a0, o, 64);
+      a1 += __shfl_xor(a1, o, 64);
+      a2 += __shfl_xor(a2, o, 64);
+    }
     if (q < 3) {
       const bool cs = mg_cons(flag[v], q);
       mg_update(u, 3L * v + q, cs, cs ? 0.0 : pick3(q, a0, a1, a2), t1, t2);
@@ -346,7 +303,10 @@ __global__ __launch_bounds__(256) void k_mg_vec0(const double* __restrict__ q, c
 }
 
 // b_c = R r_f on the coarse level; with init, the smoother starts there:
-// x = 0, r = b, d = D^-1 b / theta.  Four lanes per coarse node.
+// x = 0, r = b, d = D^-1 b / theta.  LANES lanes per coarse node (rows of R
+// grow with the coarsening ratio: 27 fine nodes per coarse node at ratio 2,
+// up to 343 at ratio 4).
+template <int LANES>
 __global__ __launch_bounds__(256) void k_mg_restrict(const double* __restrict__ rf, const int32_t* __restrict__ rptr,
                                                      const int32_t* __restrict__ rcol, const double* __restrict__ rw,
                                                      const uint8_t* __restrict__ flag, int nn, double* __restrict__ b,
@@ -354,11 +314,11 @@ __global__ __launch_bounds__(256) void k_mg_restrict(const double* __restrict__ 
                                                      double* __restrict__ d, const double* __restrict__ dinv,
                                                      const double* __restrict__ scal) {
   const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const int v = (int)(t >> 2), q = threadIdx.x & 3;
-  if (v >= nn) return;  // the four lanes of a node leave together
+  const int v = (int)(t / LANES), q = threadIdx.x & (LANES - 1);
+  if (v >= nn) return;  // the lanes of a node leave together
   double a0, a1, a2;
-  row_gather4(rf, rptr[v], rptr[v + 1], rcol, rw, q, a0, a1, a2);
-  if (q == 3) return;
+  row_gather<LANES>(rf, rptr[v], rptr[v + 1], rcol, rw, q, a0, a1, a2);
+  if (q >= 3) return;
   const long i = 3L * v + q;
   const double bi = mg_cons(flag[v], q) ? 0.0 : pick3(q, a0, a1, a2);
   b[i] = bi;
@@ -475,46 +435,58 @@ __global__ __launch_bounds__(256) void k_mg_galerkin(const int32_t* __restrict__
   for (int i = threadIdx.x, t = 0; i < 576; i += blockDim.x, ++t) Kd[576L * e + (i % 24) * 24 + i / 24] = acc[t];
 }
 
-// exact diagonal of A~ on a level: per node and component, over the node's
-// incidences grouped by element, sum t_a t_b K_e[(a,c),(b,c)]
-__global__ __launch_bounds__(256) void k_mg_diag(const int32_t* __restrict__ iptr, const int32_t* __restrict__ islot,
-                                                 const double* __restrict__ iw, const uint8_t* __restrict__ flag,
-                                                 const double* __restrict__ Kd, int nd,
-                                                 const int32_t* __restrict__ pure_src,
-                                                 const double* __restrict__ coef, const double* __restrict__ K0g,
-                                                 double* __restrict__ dinv, int nn) {
-  __shared__ double K0[576];
-  for (int i = threadIdx.x; i < 576; i += blockDim.x) K0[i] = K0g[i];
-  __syncthreads();
+// block rows of A_k after a density change: each block sums its
+// contributions w K_e[(a, .), (b, .)] (w the product of the two vertices'
+// interpolation weights) in the stored order, then zeroes the columns of
+// supported DOFs
+__global__ __launch_bounds__(256) void k_mg_bsr_values(const int32_t* __restrict__ kptr,
+                                                       const int32_t* __restrict__ ke,
+                                                       const uint8_t* __restrict__ kab,
+                                                       const double* __restrict__ kw,
+                                                       const int32_t* __restrict__ bcol,
+                                                       const uint8_t* __restrict__ flag,
+                                                       const double* __restrict__ Kd, int nd,
+                                                       const int32_t* __restrict__ pure_src,
+                                                       const double* __restrict__ coef,
+                                                       const double* __restrict__ K0, double* __restrict__ bval,
+                                                       int nnzb) {
+  const int blk = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blk >= nnzb) return;
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int k = kptr[blk]; k < kptr[blk + 1]; ++k) {
+    const int e = ke[k], a = kab[k] >> 3, b = kab[k] & 7;
+    const double w = kw[k];
+    if (e < nd) {
+      const double* __restrict__ Ke = Kd + 576L * e;  // column-major
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc[3 * i + j] = fma(w, Ke[(3 * b + j) * 24 + 3 * a + i], acc[3 * i + j]);
+    } else {
+      const double wc = w * coef[pure_src[e - nd]];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc[3 * i + j] = fma(wc, K0[(3 * a + i) * 24 + 3 * b + j], acc[3 * i + j]);
+    }
+  }
+  const uint8_t fc = flag[bcol[blk]];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) bval[9L * blk + 3 * i + j] = ((fc >> j) & 1) ? 0.0 : acc[3 * i + j];
+}
+
+// diagonal inverse of A~ on a level from its diagonal blocks
+__global__ __launch_bounds__(256) void k_mg_bsr_diag(const int32_t* __restrict__ bdiag,
+                                                     const double* __restrict__ bval,
+                                                     const uint8_t* __restrict__ flag, double* __restrict__ dinv,
+                                                     int nn) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nn) return;
-  double dg[3] = {0.0, 0.0, 0.0};
-  const int k1 = iptr[v + 1];
-  for (int k = iptr[v]; k < k1;) {
-    const int e = islot[k] >> 3;
-    double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int kk = k;
-    while (kk < k1 && (islot[kk] >> 3) == e) {
-      t[islot[kk] & 7] += iw[kk];
-      ++kk;
-    }
-    for (int c = 0; c < 3; ++c) {
-      double s = 0.0;
-      for (int a = 0; a < 8; ++a) {
-        if (t[a] == 0.0) continue;
-        for (int b = 0; b < 8; ++b) {
-          if (t[b] == 0.0) continue;
-          const int i = (3 * a + c) * 24 + 3 * b + c;   // row-major in K0
-          const int ic = (3 * b + c) * 24 + 3 * a + c;  // column-major in Kd
-          s += t[a] * t[b] * (e < nd ? Kd[576L * e + ic] : K0[i]);
-        }
-      }
-      dg[c] += e < nd ? s : coef[pure_src[e - nd]] * s;
-    }
-    k = kk;
-  }
-  const uint8_t f = flag[v];
-  for (int c = 0; c < 3; ++c) dinv[3L * v + c] = mg_cons(f, c) ? 1.0 : 1.0 / dg[c];
+  const int blk = bdiag[v];
+  for (int c = 0; c < 3; ++c)
+    dinv[3L * v + c] = (mg_cons(flag[v], c) || blk < 0) ? 1.0 : 1.0 / bval[9L * blk + 4 * c];
 }
 
 // power-iteration start: +-1 from a counter hash (SplitMix64 finaliser), zero at constrained DOFs
@@ -549,26 +521,21 @@ __global__ void k_mg_lambda(const double* __restrict__ part, double* __restrict_
   }
 }
 
-// coarsest level (no hanging nodes): dense A~ from its element matrices,
-// identity rows and columns for supported DOFs; one workgroup, elements in order
-__global__ __launch_bounds__(1024) void k_mg_coarse_assemble(const int32_t* __restrict__ elem, int ne,
-                                                             const double* __restrict__ Kd, int nd,
-                                                             const int32_t* __restrict__ pure_src,
-                                                             const double* __restrict__ coef,
-                                                             const double* __restrict__ K0,
-                                                             const uint8_t* __restrict__ flag, int n,
+// coarsest level: dense A~ from its block rows, identity rows and columns
+// for constrained DOFs; one workgroup
+__global__ __launch_bounds__(1024) void k_mg_coarse_assemble(const int32_t* __restrict__ bptr,
+                                                             const int32_t* __restrict__ bcol,
+                                                             const double* __restrict__ bval,
+                                                             const uint8_t* __restrict__ flag, int nn,
                                                              double* __restrict__ A) {
+  const int n = 3 * nn;
   for (long i = threadIdx.x; i < (long)n * n; i += blockDim.x) A[i] = 0.0;
   __syncthreads();
-  for (int e = 0; e < ne; ++e) {
-    for (int i = threadIdx.x; i < 576; i += blockDim.x) {
-      const int row = i / 24, col = i % 24;
-      const int I = 3 * elem[8L * e + row / 3] + row % 3, J = 3 * elem[8L * e + col / 3] + col % 3;
-      const double k = e < nd ? Kd[576L * e + col * 24 + row] : coef[pure_src[e - nd]] * K0[i];
-      A[(long)I * n + J] += k;
-    }
-    __syncthreads();
-  }
+  for (int v = threadIdx.x; v < nn; v += blockDim.x)
+    for (int k = bptr[v]; k < bptr[v + 1]; ++k)
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) A[(long)(3 * v + i) * n + 3 * bcol[k] + j] = bval[9L * k + 3 * i + j];
+  __syncthreads();
   for (long i = threadIdx.x; i < (long)n * n; i += blockDim.x) {
     const int I = (int)(i / n), J = (int)(i % n);
     const bool ci = mg_cons(flag[I / 3], I % 3), cj = mg_cons(flag[J / 3], J % 3);
@@ -596,6 +563,50 @@ __global__ __launch_bounds__(1024) void k_mg_invert(double* __restrict__ A, int 
       }
     }
     __syncthreads();
+  }
+}
+
+// the same inverse with the matrix in registers (n <= MG_REG_N): thread t
+// holds entries t, t + 1024, ... with their row and column; per pivot the
+// pivot row and column go through LDS, so each step costs two barriers and
+// no memory round trip
+constexpr int MG_REG_N = 144;
+constexpr int MG_REG_M = (MG_REG_N * MG_REG_N + 1023) / 1024;
+__global__ __launch_bounds__(1024) void k_mg_invert_reg(double* __restrict__ A, int n) {
+  __shared__ double col[MG_REG_N], row[MG_REG_N];
+  const int t = threadIdx.x;
+  const int nn = n * n;
+  double a[MG_REG_M];
+  int rc[MG_REG_M];  // row << 16 | column, -1: no entry
+#pragma unroll
+  for (int m = 0; m < MG_REG_M; ++m) {
+    const int e = t + 1024 * m;
+    a[m] = e < nn ? A[e] : 0.0;
+    rc[m] = e < nn ? ((e / n) << 16) | (e - (e / n) * n) : -1;
+  }
+  for (int k = 0; k < n; ++k) {
+#pragma unroll
+    for (int m = 0; m < MG_REG_M; ++m) {
+      if (rc[m] < 0) continue;
+      const int I = rc[m] >> 16, J = rc[m] & 0xffff;
+      if (I == k) row[J] = a[m];
+      if (J == k) col[I] = a[m];
+    }
+    __syncthreads();
+    const double piv = 1.0 / row[k];
+#pragma unroll
+    for (int m = 0; m < MG_REG_M; ++m) {
+      if (rc[m] < 0) continue;
+      const int I = rc[m] >> 16, J = rc[m] & 0xffff;
+      const double rj = (J == k ? 1.0 : row[J]) * piv;
+      a[m] = (I == k) ? rj : ((J == k) ? 0.0 : a[m]) - col[I] * rj;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int m = 0; m < MG_REG_M; ++m) {
+    const int e = t + 1024 * m;
+    if (e < nn) A[e] = a[m];
   }
 }
 
@@ -763,17 +774,38 @@ __global__ __launch_bounds__(256) void k_mg_zero(double* __restrict__ a, double*
 // ---------------------------------------------------------------- host side
 int blocks_for(long n) { return (int)std::max<long>(1, std::min<long>((n + 255) / 256, 1L << 20)); }
 
-// q = A_k d on level k >= 1 (element pass), then the gather pass with update u
+// b_c = R r_f (with the coarse smoother's start when init), lanes by row length
+void launch_restrict(hipStream_t st, MgLevel& C, const double* rf, double* b, int init) {
+  const double *dinv = init ? C.dinv : nullptr, *scal = init ? C.scal : nullptr;
+  double *x = init ? C.x : nullptr, *r = init ? C.r : nullptr, *d = init ? C.d : nullptr;
+  switch (C.rlanes) {
+    case 32:
+      hipLaunchKernelGGL(k_mg_restrict<32>, dim3(blocks_for(32L * C.nn)), dim3(256), 0, st, rf, C.rptr, C.rcol, C.rw,
+                         C.flag, C.nn, b, init, x, r, d, dinv, scal);
+      break;
+    case 16:
+      hipLaunchKernelGGL(k_mg_restrict<16>, dim3(blocks_for(16L * C.nn)), dim3(256), 0, st, rf, C.rptr, C.rcol, C.rw,
+                         C.flag, C.nn, b, init, x, r, d, dinv, scal);
+      break;
+    case 8:
+      hipLaunchKernelGGL(k_mg_restrict<8>, dim3(blocks_for(8L * C.nn)), dim3(256), 0, st, rf, C.rptr, C.rcol, C.rw,
+                         C.flag, C.nn, b, init, x, r, d, dinv, scal);
+      break;
+    default:
+      hipLaunchKernelGGL(k_mg_restrict<4>, dim3(blocks_for(4L * C.nn)), dim3(256), 0, st, rf, C.rptr, C.rcol, C.rw,
+                         C.flag, C.nn, b, init, x, r, d, dinv, scal);
+  }
+}
+
+// q = A_k in on level k >= 1 from its block rows, fused with the update u
 int level_pass(amrto_ctx* ctx, MgLevel& L, const double* in, const MgUpd& u, double* part) {
-  hipLaunchKernelGGL(k_mg_elem, dim3((L.ne + ME - 1) / ME), dim3(24 * ME), 0, ctx->stream, in, L.ev, L.flag, L.hm4,
-                     L.hw4, L.Kd, L.nd, L.pure_src, ctx->d_coef, ctx->d_K0, L.E, L.ne);
   // the Rayleigh partials fill exactly MG_RED slots
   const int grid = u.mode == MG_RAYLEIGH ? MG_RED : blocks_for((long)L.lanes * L.nn);
   if (L.lanes == 8)
-    hipLaunchKernelGGL(k_mg_gather<8>, dim3(grid), dim3(256), 0, ctx->stream, L.E, L.iptr, L.islot, L.iw, L.flag, L.nn,
+    hipLaunchKernelGGL(k_mg_spmv<8>, dim3(grid), dim3(256), 0, ctx->stream, in, L.bptr, L.bcol, L.bval, L.flag, L.nn,
                        u, part);
   else
-    hipLaunchKernelGGL(k_mg_gather<4>, dim3(grid), dim3(256), 0, ctx->stream, L.E, L.iptr, L.islot, L.iw, L.flag, L.nn,
+    hipLaunchKernelGGL(k_mg_spmv<4>, dim3(grid), dim3(256), 0, ctx->stream, in, L.bptr, L.bcol, L.bval, L.flag, L.nn,
                        u, part);
   return hipGetLastError() == hipSuccess ? AMRTO_OK : ctx->fail(AMRTO_EHIP, "multigrid level pass");
 }
@@ -790,7 +822,26 @@ int level0_pass(amrto_ctx* ctx, MgLevel& L, const double* in, const MgUpd& u, do
 
 int pass(amrto_ctx* ctx, int k, const double* in, const MgUpd& u) {
   MgData* g = ctx->mg;
-  return k == 0 ? level0_pass(ctx, g->lv[0], in, u, g->part) : level_pass(ctx, g->lv[k], in, u, g->part);
+  MgLevel& L = g->lv[k];
+  if (k == 0 && !ctx->uniform && in == L.d &&
+      (u.mode == MG_CHEB || u.mode == MG_CHEB_LAST || u.mode == MG_CORR)) {
+    // octree level 0: the smoothing update runs in the operator pass itself;
+    // the next direction goes to the other buffer of the pair (d, q)
+    const int mode = u.mode == MG_CHEB ? 1 : (u.mode == MG_CHEB_LAST ? 2 : 3);
+    const int rc = apply_cheb(ctx, L.d, L.q, mode, u.step, L.scal, L.dinv, L.x, L.r);
+    if (rc) return rc;
+    if (mode != 2) std::swap(L.d, L.q);
+    return AMRTO_OK;
+  }
+  if (k == 0) return level0_pass(ctx, L, in, u, g->part);  // pointwise update: d in place
+  // the block-row pass reads neighbours' d: the next direction goes to the
+  // other buffer of the pair (d, q)
+  const bool newdir = u.mode == MG_CHEB || u.mode == MG_CORR;
+  MgUpd v = u;
+  if (newdir) v.dn = L.q;
+  const int rc = level_pass(ctx, L, in, v, g->part);
+  if (rc == AMRTO_OK && newdir) std::swap(L.d, L.q);
+  return rc;
 }
 
 MgUpd upd(MgLevel& L, int mode, int step = 0) {
@@ -802,6 +853,7 @@ MgUpd upd(MgLevel& L, int mode, int step = 0) {
   u.x = L.x;
   u.r = L.r;
   u.d = L.d;
+  u.dn = L.d;
   return u;
 }
 
@@ -816,13 +868,12 @@ int vcycle_from(amrto_ctx* ctx, int k) {
     hipLaunchKernelGGL(k_mg_coarse_solve, dim3((n + 3) / 4), dim3(256), 0, ctx->stream, L.Ainv, L.b, L.x, n);
     return hipGetLastError() == hipSuccess ? AMRTO_OK : ctx->fail(AMRTO_EHIP, "multigrid coarse solve");
   }
-  const int m = g->degree;
+  const int m = k == 0 ? g->degree : g->coarse_degree;
   for (int s = 0; s < m; ++s)
     if ((rc = pass(ctx, k, L.d, upd(L, s == m - 1 ? MG_CHEB_LAST : MG_CHEB, s)))) return rc;
   MgLevel& C = g->lv[k + 1];
   const bool coarsest = k + 1 == g->nlev - 1;
-  hipLaunchKernelGGL(k_mg_restrict, dim3(blocks_for(4L * C.nn)), dim3(256), 0, ctx->stream, L.r, C.rptr, C.rcol, C.rw,
-                     C.flag, C.nn, C.b, coarsest ? 0 : 1, C.x, C.r, C.d, C.dinv, C.scal);
+  launch_restrict(ctx->stream, C, L.r, C.b, coarsest ? 0 : 1);
   if ((rc = vcycle_from(ctx, k + 1))) return rc;
   // x += P x_c (the coarse level's last correction d folded in), d = that correction
   hipLaunchKernelGGL(k_mg_prolong, dim3(blocks_for(4L * L.nn)), dim3(256), 0, ctx->stream, C.x,
@@ -867,8 +918,10 @@ int mg_numeric(amrto_ctx* ctx) {
     if (L.nd > 0)
       hipLaunchKernelGGL(k_mg_galerkin, dim3(L.nd), dim3(256), 0, ctx->stream, L.cptr, L.celem, L.coct, L.nd, F.Kd,
                          F.nd, F.pure_src, ctx->d_coef, ctx->d_K0, L.Kd);
-    hipLaunchKernelGGL(k_mg_diag, dim3(blocks_for(L.nn)), dim3(256), 0, ctx->stream, L.iptr, L.islot, L.iw, L.flag,
-                       L.Kd, L.nd, L.pure_src, ctx->d_coef, ctx->d_K0, L.dinv, L.nn);
+    hipLaunchKernelGGL(k_mg_bsr_values, dim3(blocks_for(L.nnzb)), dim3(256), 0, ctx->stream, L.kptr, L.ke, L.kab,
+                       L.kw, L.bcol, L.flag, L.Kd, L.nd, L.pure_src, ctx->d_coef, ctx->d_K0, L.bval, L.nnzb);
+    hipLaunchKernelGGL(k_mg_bsr_diag, dim3(blocks_for(L.nn)), dim3(256), 0, ctx->stream, L.bdiag, L.bval, L.flag,
+                       L.dinv, L.nn);
   }
   if (hipGetLastError() != hipSuccess) return ctx->fail(AMRTO_EHIP, "multigrid Galerkin set-up");
   // lambda_max of D^-1 A on every smoothed level by power iteration
@@ -893,9 +946,12 @@ int mg_numeric(amrto_ctx* ctx) {
   }
   MgLevel& C = g->lv[g->nlev - 1];
   const int n = 3 * C.nn;
-  hipLaunchKernelGGL(k_mg_coarse_assemble, dim3(1), dim3(1024), 0, ctx->stream, C.elem, C.ne, C.Kd, C.nd,
-                     C.pure_src, ctx->d_coef, ctx->d_K0, C.flag, n, C.Ainv);
-  hipLaunchKernelGGL(k_mg_invert, dim3(1), dim3(1024), 0, ctx->stream, C.Ainv, n);
+  hipLaunchKernelGGL(k_mg_coarse_assemble, dim3(1), dim3(1024), 0, ctx->stream, C.bptr, C.bcol, C.bval, C.flag,
+                     C.nn, C.Ainv);
+  if (n <= MG_REG_N)
+    hipLaunchKernelGGL(k_mg_invert_reg, dim3(1), dim3(1024), 0, ctx->stream, C.Ainv, n);
+  else
+    hipLaunchKernelGGL(k_mg_invert, dim3(1), dim3(1024), 0, ctx->stream, C.Ainv, n);
   if (hipGetLastError() != hipSuccess) return ctx->fail(AMRTO_EHIP, "multigrid coarse set-up");
   ctx->mg_valid = true;
   return AMRTO_OK;
@@ -1059,62 +1115,87 @@ int upload_level(amrto_ctx* ctx, MgData* g, std::vector<HostLevel>& H, int k) {
     return AMRTO_OK;
   }
   AMRTO_HIP(mg_alloc(own, L.dinv, n3));
-  // elements in device order
-  std::vector<int32_t> elem(8L * ne), psrc(ne - h.nd);
-  for (int e = 0; e < ne; ++e) {
-    const int de = h.perm[e];
-    for (int a = 0; a < 8; ++a) elem[8L * de + a] = m.elem_nodes[8L * e + a];
-    if (h.pure[e]) psrc[de - h.nd] = h.src[e];
-  }
-  std::vector<int32_t> evv(elem.size());
-  for (size_t i = 0; i < elem.size(); ++i) evv[i] = hang_of[elem[i]] < 0 ? elem[i] : -(hang_of[elem[i]] + 1);
-  AMRTO_HIP(mg_upload(own, L.elem, elem));
-  AMRTO_HIP(mg_upload(own, L.ev, evv));
+  // coefficient index of the single-leaf elements (device order)
+  std::vector<int32_t> psrc(ne - h.nd);
+  for (int e = 0; e < ne; ++e)
+    if (h.pure[e]) psrc[h.perm[e] - h.nd] = h.src[e];
   AMRTO_HIP(mg_upload(own, L.pure_src, psrc));
   AMRTO_HIP(mg_alloc(own, L.Kd, 576L * h.nd));
-  AMRTO_HIP(mg_alloc(own, L.E, 24L * ne));
-  // hanging table at a fixed stride of four masters
-  std::vector<int32_t> hptr(m.hang_ptr.begin(), m.hang_ptr.end());
-  if (hptr.empty()) hptr.push_back(0);
-  std::vector<int32_t> hm4(4L * L.nh);
-  std::vector<double> hw4(4L * L.nh, 0.0);
-  for (int h = 0; h < L.nh; ++h) {
-    const int k0 = m.hang_ptr[h], cnt = m.hang_ptr[h + 1] - k0;
-    if (cnt < 1 || cnt > 4) return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: a hanging node with more than four masters");
-    for (int k = 0; k < 4; ++k) {
-      hm4[4L * h + k] = m.hang_master[k0 + std::min(k, cnt - 1)];
-      hw4[4L * h + k] = k < cnt ? m.hang_w[k0 + k] : 0.0;
+  // assembled operator: every element vertex pair (a, b) contributes
+  // w_a w_b K_e[(a, .), (b, .)] to the block (m_a, m_b) for each master m_a
+  // of a (a itself when it does not hang) and m_b of b; contributions are
+  // kept per block in (element, a, b, master) order
+  struct Contrib {
+    int32_t col, e;
+    uint8_t ab;
+    double w;
+  };
+  std::vector<std::vector<Contrib>> rows(nn);
+  auto expand = [&](int v, int32_t* mm, double* ww) -> int {
+    if (hang_of[v] < 0) {
+      mm[0] = v;
+      ww[0] = 1.0;
+      return 1;
     }
-  }
-  AMRTO_HIP(mg_upload(own, L.hm4, hm4));
-  AMRTO_HIP(mg_upload(own, L.hw4, hw4));
-  // incidences per node (slot 8 e + a in device order), sorted by slot
-  std::vector<std::vector<std::pair<int32_t, double>>> inc(nn);
-  for (int e = 0; e < ne; ++e)
+    const int hh = hang_of[v], k0 = m.hang_ptr[hh], cnt = m.hang_ptr[hh + 1] - k0;
+    for (int j = 0; j < cnt && j < 8; ++j) {
+      mm[j] = m.hang_master[k0 + j];
+      ww[j] = m.hang_w[k0 + j];
+    }
+    return std::min(cnt, 8);
+  };
+  for (int e = 0; e < ne; ++e) {
+    const int32_t de = h.perm[e];
+    int32_t mm[8][8];
+    double ww[8][8];
+    int cnt[8];
     for (int a = 0; a < 8; ++a) {
       const int v = m.elem_nodes[8L * e + a];
-      const int32_t slot = 8 * h.perm[e] + a;
-      if (hang_of[v] < 0) {
-        inc[v].push_back({slot, 1.0});
-      } else {
-        const int hh = hang_of[v];
-        for (int j = m.hang_ptr[hh]; j < m.hang_ptr[hh + 1]; ++j) inc[m.hang_master[j]].push_back({slot, m.hang_w[j]});
-      }
+      if (hang_of[v] >= 0 && m.hang_ptr[hang_of[v] + 1] - m.hang_ptr[hang_of[v]] > 8)
+        return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: a hanging node with more than eight masters");
+      cnt[a] = expand(v, mm[a], ww[a]);
     }
-  std::vector<int32_t> iptr(nn + 1, 0), islot;
-  std::vector<double> iw;
-  for (int v = 0; v < nn; ++v) {
-    std::sort(inc[v].begin(), inc[v].end());
-    for (auto& sw : inc[v]) {
-      islot.push_back(sw.first);
-      iw.push_back(sw.second);
-    }
-    iptr[v + 1] = (int32_t)islot.size();
+    for (int a = 0; a < 8; ++a)
+      for (int b = 0; b < 8; ++b)
+        for (int i = 0; i < cnt[a]; ++i)
+          for (int j = 0; j < cnt[b]; ++j)
+            rows[mm[a][i]].push_back({mm[b][j], de, (uint8_t)(8 * a + b), ww[a][i] * ww[b][j]});
   }
-  AMRTO_HIP(mg_upload(own, L.iptr, iptr));
-  AMRTO_HIP(mg_upload(own, L.islot, islot));
-  AMRTO_HIP(mg_upload(own, L.iw, iw));
-  L.lanes = islot.size() > 12L * nn ? 8 : 4;  // long incidence lists: more lanes per node
+  std::vector<int32_t> bptr(nn + 1, 0), bcol, bdiag(nn, -1), kptr(1, 0), ke;
+  std::vector<uint8_t> kab;
+  std::vector<double> kw;
+  for (int v = 0; v < nn; ++v) {
+    auto& R = rows[v];
+    std::stable_sort(R.begin(), R.end(), [](const Contrib& x, const Contrib& y) {
+      if (x.col != y.col) return x.col < y.col;
+      if (x.e != y.e) return x.e < y.e;
+      return x.ab < y.ab;
+    });
+    for (size_t i = 0; i < R.size(); ++i) {
+      if (i == 0 || R[i].col != R[i - 1].col) {
+        if (R[i].col == v) bdiag[v] = (int32_t)bcol.size();
+        bcol.push_back(R[i].col);
+        if (bcol.size() > 1) kptr.push_back((int32_t)ke.size());
+      }
+      ke.push_back(R[i].e);
+      kab.push_back(R[i].ab);
+      kw.push_back(R[i].w);
+    }
+    bptr[v + 1] = (int32_t)bcol.size();
+    std::vector<Contrib>().swap(R);
+  }
+  kptr.push_back((int32_t)ke.size());
+  if (bcol.empty()) kptr.assign(1, 0);
+  L.nnzb = (int)bcol.size();
+  AMRTO_HIP(mg_upload(own, L.bptr, bptr));
+  AMRTO_HIP(mg_upload(own, L.bcol, bcol));
+  AMRTO_HIP(mg_upload(own, L.bdiag, bdiag));
+  AMRTO_HIP(mg_upload(own, L.kptr, kptr));
+  AMRTO_HIP(mg_upload(own, L.ke, ke));
+  AMRTO_HIP(mg_upload(own, L.kab, kab));
+  AMRTO_HIP(mg_upload(own, L.kw, kw));
+  AMRTO_HIP(mg_alloc(own, L.bval, 9L * std::max(1, L.nnzb)));
+  L.lanes = (long)bcol.size() > 12L * nn ? 8 : 4;  // long block rows: more lanes per node
   // children of the dense elements (previous level, its device order)
   HostLevel& F = H[k - 1];
   std::vector<std::vector<std::pair<int32_t, uint8_t>>> ch(h.nd);
@@ -1194,11 +1275,11 @@ int upload_level(amrto_ctx* ctx, MgData* g, std::vector<HostLevel>& H, int k) {
       if (i < 0 || i >= lim) return false;
     return true;
   };
-  if (!in_range(elem, nn) || !in_range(psrc, ctx->n_elems) || !in_range(hm4, nn) ||
-      !in_range(islot, 8L * ne) || !in_range(celem, F.m.n_elems) || !in_range(pcol, nn) ||
-      !in_range(rcol, fm.n_nodes) || (long)iptr.back() != (long)islot.size() ||
+  if (!in_range(psrc, ctx->n_elems) || !in_range(bcol, nn) || !in_range(ke, ne) || !in_range(celem, F.m.n_elems) ||
+      !in_range(pcol, nn) || !in_range(rcol, fm.n_nodes) || (long)bptr.back() != (long)bcol.size() ||
+      (long)kptr.size() != (long)bcol.size() + 1 || (long)kptr.back() != (long)ke.size() ||
       (long)pptr.back() != (long)pcol.size() || (long)rptr.back() != (long)rcol.size() ||
-      (long)cptr.back() != (long)celem.size() || (!hptr.empty() && (long)hptr.back() != (long)m.hang_master.size()))
+      (long)cptr.back() != (long)celem.size())
     return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: inconsistent level tables");
   for (size_t i = 0; i < celem.size(); ++i) {
     const int lr = coct[i] & 3;
@@ -1209,6 +1290,9 @@ int upload_level(amrto_ctx* ctx, MgData* g, std::vector<HostLevel>& H, int k) {
   AMRTO_HIP(mg_upload(own, L.pptr, pptr));
   AMRTO_HIP(mg_upload(own, L.pcol, pcol));
   AMRTO_HIP(mg_upload(own, L.pw, pw));
+  long rmax = 0;
+  for (int v = 0; v < nn; ++v) rmax = std::max<long>(rmax, rptr[v + 1] - rptr[v]);
+  L.rlanes = rmax > 128 ? 32 : (rmax > 48 ? 16 : (rmax > 16 ? 8 : 4));  // the longest rows set the pace
   AMRTO_HIP(mg_upload(own, L.rptr, rptr));
   AMRTO_HIP(mg_upload(own, L.rcol, rcol));
   AMRTO_HIP(mg_upload(own, L.rw, rw));
@@ -1233,10 +1317,11 @@ int amrto_mg_setup(amrto_ctx* ctx, const amrto_octree* tree, const amrto_mg_opts
   if (!ctx) return AMRTO_EINVAL;
   if (!ctx->has_mesh) return ctx->fail(AMRTO_ESTATE, "amrto_mg_setup: no mesh uploaded");
   if (!tree) return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: NULL tree");
-  amrto_mg_opts o{2, 10.0, 20, 1.1, 200, 1};
+  amrto_mg_opts o{2, 10.0, 20, 1.1, 200, 1, 0};
   if (opts) o = *opts;
-  if (o.degree < 1 || o.degree > 8 || !(o.ratio > 1.0) || o.power_its < 1 || o.power_its > 200 ||
-      !(o.hi_factor >= 1.0) || o.coarse_dofs < 3 || o.first < 1 || o.first > 2)
+  if (o.degree < 1 || o.degree > 8 || o.coarse_degree < 0 || o.coarse_degree > 8 || !(o.ratio > 1.0) ||
+      o.power_its < 1 || o.power_its > 200 || !(o.hi_factor >= 1.0) || o.coarse_dofs < 3 || o.first < 1 ||
+      o.first > 2)
     return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: bad options");
   AMRTO_HIP(hipSetDevice(ctx->device));
   AMRTO_HIP(hipStreamSynchronize(ctx->stream));
@@ -1249,6 +1334,7 @@ int amrto_mg_setup(amrto_ctx* ctx, const amrto_octree* tree, const amrto_mg_opts
   ctx->mg = g;
   g->nlev = (int)H.size();
   g->degree = o.degree;
+  g->coarse_degree = o.coarse_degree > 0 ? o.coarse_degree : o.degree;
   g->ratio = o.ratio;
   g->power_its = o.power_its;
   g->hi_factor = o.hi_factor;
@@ -1374,9 +1460,7 @@ int amrto_mg_restrict(amrto_ctx* ctx, int32_t k, const double* rf, double* rc_ou
     return ctx->fail(AMRTO_EINVAL, "amrto_mg_restrict: level out of range or bad buffers");
   AMRTO_HIP(hipSetDevice(ctx->device));
   MgLevel& C = g->lv[k];
-  hipLaunchKernelGGL(k_mg_restrict, dim3(blocks_for(4L * C.nn)), dim3(256), 0, ctx->stream, rf, C.rptr, C.rcol, C.rw,
-                     C.flag, C.nn, rc_out, 0, (double*)nullptr, (double*)nullptr, (double*)nullptr,
-                     (const double*)nullptr, (const double*)nullptr);
+  launch_restrict(ctx->stream, C, rf, rc_out, 0);
   AMRTO_HIP(hipGetLastError());
   return AMRTO_OK;
 }

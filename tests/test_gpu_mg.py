@@ -39,6 +39,7 @@ class MgCase:
         self.ctx = binding.Context(0)
         self.ctx.upload_mesh(p.lib_mesh)
         self.ctx.set_density(_t(p.to_lib_elems(rho)))
+        self.first = first
         self.ctx.mg_setup(p.case["tree"], coarse_dofs=COARSE, first=first)
         self.sys = oracle_system(p, rho)
         self.levels = mg.hierarchy(p.orc, self.base, p.case["fixed"], coarse_dofs=COARSE, first=first)
@@ -118,6 +119,23 @@ def test_vcycle_matches_oracle_with_the_same_intervals(case):
         case.ctx.mg_set_bounds(None)
 
 
+def test_vcycle_with_another_coarse_degree(case):
+    """Degree 3 on level 0 and 1 on the coarse levels, against the oracle."""
+    tree = case.pair.case["tree"]
+    case.ctx.mg_setup(tree, coarse_dofs=COARSE, first=case.first, degree=3, coarse_degree=1)
+    try:
+        M = mg.setup(case.levels, case.sys.A, degree=3, coarse_degree=1)
+        case.ctx.mg_set_bounds([lv.hi / 1.1 for lv in M.levels[:-1]])
+        r = np.random.default_rng(4).standard_normal(3 * case.pair.orc.n_nodes) * case.levels[0].free
+        z = torch.empty_like(_t(r))
+        case.ctx.mg_vcycle(case.to_lib(0, r), z)
+        want = M.vcycle(r)
+        assert np.abs(case.to_orc(0, z) - want).max() <= 1e-9 * np.abs(want).max()
+    finally:
+        case.ctx.mg_setup(tree, coarse_dofs=COARSE, first=case.first)
+        case.M = mg.setup(case.levels, case.sys.A)
+
+
 def test_power_estimate_of_lambda_max(case):
     exact = np.array([lv.hi / 1.1 for lv in case.levels[:-1]])
     est = case.ctx.mg_get_bounds()
@@ -162,3 +180,58 @@ def test_mg_errors():
     ctx.mg_setup(p.case["tree"], coarse_dofs=COARSE)
     with pytest.raises(binding.AmrtoError):
         ctx.mg_level_apply(0, b, b.clone())
+
+
+def _c2_library_only():
+    """The full-size octree cantilever (16 x 8 x 8 base, 3 levels, band refined),
+    built by the library's own octree; densities from the seeded field."""
+    import synth
+    case = synth.c2()
+    fld = case.extra["field"]
+    L = case.max_level
+    t = binding.Octree(case.base, L)
+    for _ in range(L):
+        lv, an = t.leaves()
+        t.refine(synth.band_marks(fld, lv, an, L))
+    t.balance()
+    mesh = t.build_mesh(case.fixed, case.load)
+    lv, an = t.leaves()
+    rho = fld((an + 0.5 * (1 << (L - lv))[:, None]).astype(np.float64))
+    return t, mesh, rho
+
+
+@pytest.mark.parametrize("first", [1, 2])
+def test_vcycle_deterministic_symmetric_at_full_size(first):
+    """At the full octree size (255,636 DOFs, many concurrent workgroups per
+    level): the same residual gives the same z to rounding (the level-0
+    octree pass sums element contributions with LDS atomics, so only the last
+    bits may differ; a pass reading values another thread of it rewrites
+    would differ far more), r1 . V r2 equals r2 . V r1 to rounding, V is
+    positive, and the solve converges within the iteration count the oracle
+    multigrid takes on this mesh (79 with two levels merged first) plus a
+    margin."""
+    t, mesh, rho = _c2_library_only()
+    ctx = binding.Context(0)
+    ctx.upload_mesh(mesh)
+    ctx.set_density(_t(rho))
+    ctx.mg_setup(t, first=first)
+    f = _t(mesh.f_load)
+    b = torch.empty_like(f)
+    ctx.project_rhs(f, b)
+    g = torch.Generator(device=DEV).manual_seed(7)
+    r1 = torch.randn(b.numel(), dtype=torch.float64, device=DEV, generator=g)
+    r2 = torch.randn(b.numel(), dtype=torch.float64, device=DEV, generator=g)
+    # constrained form (zero at hanging and supported DOFs): project through A~'s mask
+    ctx.project_rhs(r1.clone(), r1)
+    ctx.project_rhs(r2.clone(), r2)
+    z1, z1b, z2 = (torch.empty_like(b) for _ in range(3))
+    ctx.mg_vcycle(r1, z1)
+    ctx.mg_vcycle(r1, z1b)
+    ctx.mg_vcycle(r2, z2)
+    assert float((z1 - z1b).abs().max()) <= 1e-12 * float(z1.abs().max())
+    s12, s21 = float((r2 * z1).sum()), float((r1 * z2).sum())
+    assert abs(s12 - s21) <= 1e-10 * abs(s12)
+    assert float((r1 * z1).sum()) > 0 and float((r2 * z2).sum()) > 0
+    u = torch.zeros_like(b)
+    st = ctx.mg_pcg(b, u, rtol=1e-8, max_it=400, check_every=4)
+    assert st["status"] == "OK" and st["iters"] <= 110, st
