@@ -44,6 +44,12 @@ APPLY_SOURCES = ("paper_1009_4975_amd/csrc/apply.hip", "paper_1009_4975_amd/csrc
 PASS_SOURCES = APPLY_SOURCES + ("paper_1009_4975_amd/csrc/pcg.hip", "paper_1009_4975_amd/csrc/block3.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_octree_c2_traffic.txt")
 PASS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "op_pass_octree_c2_fp32_coarse_block3_traffic.txt")
+MG_SOURCES = APPLY_SOURCES + ("paper_1009_4975_amd/csrc/mg.hip",)
+MG_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mg_level0_pass_octree_c2_traffic.txt")
+MG_PASS_BYTES_RULE = ("the level-0 smoothing pass must move, per node that does not hang (hanging nodes carry no "
+                      "values in the constrained form): the direction d read, the iterate x and the residual r "
+                      "read and written, the diagonal inverse read, the next direction written (3 FP64 values "
+                      "each, 168 B); plus c_e per element (8 B)")
 
 
 def source_hash(sources=APPLY_SOURCES):
@@ -123,6 +129,11 @@ def event_time(torch, fn, reps):
 
 # solve variants: inner precision, then "+coarse" (affine coarse space) and/or
 # "+block3" (3x3 node-block Jacobi in place of the scalar diagonal)
+# multigrid options of the octree solves: two octree levels merged by the first
+# coarsening, Chebyshev degree 1 on the analysis mesh and 2 on the coarse
+# levels over [lambda_max / 50, 1.1 lambda_max]
+MG_OPTS = dict(first=2, ratio=50.0, degree=1, coarse_degree=2)
+
 SOLVERS = ("fp64", "fp32", "bf16", "fp64+coarse", "fp32+coarse", "fp64+block3", "fp32+block3",
            "fp64+coarse+block3", "fp32+coarse+block3", "fp64+mg")
 
@@ -149,6 +160,8 @@ def main():
     ap.add_argument("--c4-only", action="store_true", help="only the 50-iteration adaptive SIMP run")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2-D cantilever (Q4 quadtree) lines")
     ap.add_argument("--2d-only", dest="only_2d", action="store_true", help="only the 2-D cantilever lines")
+    ap.add_argument("--mg-roofline-only", action="store_true",
+                    help="only the multigrid level passes on C2 and a copy kernel of known size (for counter runs)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the C2 apply loop and a copy kernel of known size (for counter runs)")
     args = ap.parse_args()
@@ -197,6 +210,13 @@ def main():
     ctx.project_rhs(f, b)
 
     precs = {"fp64": binding.FP64, "fp32": binding.FP32, "bf16": binding.BF16}
+    if args.mg_roofline_only:
+        ctx.mg_setup(tree, **MG_OPTS)
+        lv_us = ctx.mg_pass_times(50)  # the last 50 level-0 operator dispatches are these passes
+        log(f"[bench] C2 multigrid level passes (us): {', '.join(f'{t:.2f}' for t in lv_us)}")
+        log(f"[bench] multigrid source hash {source_hash(MG_SOURCES)}")
+        copy_calibration(torch)
+        return
     if args.roofline_only:
         x = torch.randn_like(f)
         y = torch.empty_like(f)
@@ -206,6 +226,9 @@ def main():
         op_us, up_us = pass_times(ctx, binding, b, u, name, tuple(int(r) for r in args.regions.split(",")), 50)
         log(f"[bench] C2 {name} operator pass {op_us:.2f} us, update {up_us:.2f} us per launch")
         log(f"[bench] pass source hash {source_hash(PASS_SOURCES)}")
+        ctx.mg_setup(tree, **MG_OPTS)
+        log(f"[bench] C2 multigrid level passes (us): {ctx.mg_pass_times(50)}")
+        log(f"[bench] multigrid source hash {source_hash(MG_SOURCES)}")
         copy_calibration(torch)
         log(f"[bench] apply source hash {apply_source_hash()}")
         return
@@ -226,7 +249,7 @@ def main():
         u.zero_()
         if "+mg" in name:
             if not mg_ready[0]:
-                ctx.mg_setup(tree, first=2)
+                ctx.mg_setup(tree, **MG_OPTS)
                 mg_ready[0] = True
             ctx.set_density(rho)  # a fresh density: the solve rebuilds the coarse operators
             torch.cuda.synchronize()
@@ -291,23 +314,39 @@ def main():
     if args.profile_only:
         return
 
-    # --- dominant kernel of the timed step: the solver variant's fused operator
-    # pass (stiffness apply + preconditioner + search direction), timed live
+    # --- dominant kernel of the timed step, timed live: for the multigrid
+    # solve the level-0 smoothing pass (octree operator with the Chebyshev
+    # update), otherwise the solver variant's fused CG operator pass
     ne, nn = mesh.n_elems, mesh.n_nodes
-    op_us, up_us = pass_times(ctx, binding, b, u, solver, regions, 200)
-    pb = pass_bytes(solver, nn, ne)
-    gbs = pb / (op_us * 1e-6) / 1e9
-    log(f"[bench] C2 {solver} operator pass: {op_us:.2f} us/launch, {gbs:.0f} GB/s algorithmic; "
-        f"update side {up_us:.2f} us")
-    roofline = dict(bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(gbs / HBM_PEAK_GBS, 5),
-                    traffic=(measured_traffic(PASS_TRAFFIC_FILE, PASS_SOURCES)
-                             if solver == "fp32+coarse+block3" else None),
-                    kernel=f"fused CG operator pass of the {solver} solve (k_apply_chunks: stiffness apply, "
-                           "preconditioner, search direction, coarse-space partials)",
-                    per_launch_us=round(op_us, 3), alg_bytes_per_launch=int(pb),
-                    bytes_rule=PASS_BYTES_RULE, update_side_us=round(up_us, 3),
-                    traffic_unit="bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)")
+    if "+mg" in solver:
+        lv_us = ctx.mg_pass_times(200)
+        op_us = lv_us[0]
+        pb = 168.0 * (nn - len(mesh.hang_node)) + 8.0 * ne
+        gbs = pb / (op_us * 1e-6) / 1e9
+        log(f"[bench] C2 multigrid level passes (us): {', '.join(f'{t:.2f}' for t in lv_us)}; level 0 "
+            f"{gbs:.0f} GB/s algorithmic")
+        roofline = dict(bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(gbs / HBM_PEAK_GBS, 5), traffic=measured_traffic(MG_TRAFFIC_FILE, MG_SOURCES),
+                        kernel="level-0 smoothing pass of the multigrid V-cycle (k_apply_chunks FP64: stiffness "
+                               "apply with the Chebyshev update of x, r and the next direction)",
+                        per_launch_us=round(op_us, 3), alg_bytes_per_launch=int(pb), bytes_rule=MG_PASS_BYTES_RULE,
+                        coarse_level_pass_us=[round(t, 3) for t in lv_us[1:]],
+                        traffic_unit="bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)")
+    else:
+        op_us, up_us = pass_times(ctx, binding, b, u, solver, regions, 200)
+        pb = pass_bytes(solver, nn, ne)
+        gbs = pb / (op_us * 1e-6) / 1e9
+        log(f"[bench] C2 {solver} operator pass: {op_us:.2f} us/launch, {gbs:.0f} GB/s algorithmic; "
+            f"update side {up_us:.2f} us")
+        roofline = dict(bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(gbs / HBM_PEAK_GBS, 5),
+                        traffic=(measured_traffic(PASS_TRAFFIC_FILE, PASS_SOURCES)
+                                 if solver == "fp32+coarse+block3" else None),
+                        kernel=f"fused CG operator pass of the {solver} solve (k_apply_chunks: stiffness apply, "
+                               "preconditioner, search direction, coarse-space partials)",
+                        per_launch_us=round(op_us, 3), alg_bytes_per_launch=int(pb),
+                        bytes_rule=PASS_BYTES_RULE, update_side_us=round(up_us, 3),
+                        traffic_unit="bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)")
     # second entry: the plain FP64 stiffness apply on the same mesh
     x = torch.randn_like(f)
     y = torch.empty_like(f)
@@ -355,7 +394,9 @@ def main():
         "config": {"workload": "octree cantilever 16x8x8 base leaves, 3 refinement levels, band-refined and "
                                "2:1 balanced", "elements": ne, "nodes": nn, "dofs": 3 * nn,
                    "hanging_nodes": int(len(mesh.hang_node)), "chunks": info["n_chunks"], "solver": solver,
-                   "coarse_regions": list(regions) if "+coarse" in solver else None, "rtol": 1e-8, "E0": 1.0, "Emin": 1e-9, "nu": 0.3, "p": 3.0},
+                   "coarse_regions": list(regions) if "+coarse" in solver else None,
+                   "multigrid": dict(MG_OPTS) if "+mg" in solver else None,
+                   "rtol": 1e-8, "E0": 1.0, "Emin": 1e-9, "nu": 0.3, "p": 3.0},
         "solve_iters": int(np.median(iters)), "solve_rel_res": float(max(rel)),
         "solve_variants": variants, "roofline": roofline, "roofline_apply_fp64": roofline_apply,
         "c1_simp_iteration_24x12x12": c1, "c5_bridge_128x64x64": c5,
@@ -570,7 +611,8 @@ def c4_simp(torch, binding, synth, regions=(2, 2, 2)):
     solve: plain (previous solution as the start, Jacobi-PCG), plain with the
     3x3 node-block Jacobi preconditioner, the affine coarse space, and the
     learned start (network trained on iterations 1-10) with the coarse space;
-    each in FP64 and with FP32 inner solves."""
+    each in FP64 and with FP32 inner solves; recycled Krylov vectors; and
+    multigrid-preconditioned CG (its hierarchy rebuilt at every adaptation)."""
     from paper_1009_4975_amd.learned import LearnedWarmStart
     from paper_1009_4975_amd.simp import AdaptiveSIMP
     case = synth.c4()
@@ -586,12 +628,16 @@ def c4_simp(torch, binding, synth, regions=(2, 2, 2)):
                              ("learned_coarse_fp32", binding.FP32, "learned"),
                              ("recycle_init_coarse_block3_fp64", binding.FP64, "recycle_init+coarse+block3"),
                              ("recycle_init_coarse_block3_fp32", binding.FP32, "recycle_init+coarse+block3"),
-                             ("recycle_in_coarse_space_fp64", binding.FP64, "recycle_coarse")):
+                             ("recycle_in_coarse_space_fp64", binding.FP64, "recycle_coarse"),
+                             ("mg_fp64", binding.FP64, "mg")):
         t0 = time.perf_counter()
         sim = AdaptiveSIMP(case.base, case.max_level, case.fixed, case.load, volfrac=ex["volfrac"],
                            rho_init=ex["rho_init"], rmin=ex["rmin"], rho_solid=ex["rho_solid"], r_amr=ex["r_amr"],
                            adapt_every=ex["adapt_every"], rtol=1e-8, inner_prec=prec, inner_rtol=0.1,
-                           precond=binding.BLOCK3 if (mode or "").endswith("block3") else binding.JACOBI)
+                           precond=binding.BLOCK3 if (mode or "").endswith("block3") else binding.JACOBI,
+                           mg=MG_OPTS if mode == "mg" else None)
+        if mode == "mg":
+            mode = None  # every solve (iterations 1-50) is multigrid-preconditioned
         rec_from, rec_mode = None, None
         if (mode or "").startswith("recycle"):
             # from iteration 11 on: recorded solves whose Ritz vectors start

@@ -531,10 +531,16 @@ int amrto_mg_level_apply(amrto_ctx* ctx, int32_t k, const double* x, double* y);
 int amrto_mg_level_diag(amrto_ctx* ctx, int32_t k, double* dinv);
 int amrto_mg_prolong(amrto_ctx* ctx, int32_t k, const double* xc, double* xf);
 int amrto_mg_restrict(amrto_ctx* ctx, int32_t k, const double* rf, double* rc);
-/* CG in FP64 on A~ u = b preconditioned by one V-cycle per iteration, from
+/* Mean device time (microseconds, HIP events on the context stream) of one
+ * smoothing pass per smoothed level, over reps passes on zeroed vectors:
+ * us[0] the level-0 operator pass with its Chebyshev update, us[k] level k's
+ * block-row pass (host array of n_levels - 1 entries). */
+int amrto_mg_pass_times(amrto_ctx* ctx, int32_t reps, double* us);
+/* CG in FP64 on A~ u~ = b preconditioned by one V-cycle per iteration, from
  * the initial guess in u (constrained entries ignored), to ||r|| <= rtol
- * ||b||; the numeric set-up runs first after a density change.  Returns
- * AMRTO_OK, AMRTO_NOT_CONVERGED or AMRTO_EBREAKDOWN. */
+ * ||b||; the numeric set-up runs first after a density change.  On exit
+ * u = T u~ with hanging DOFs recovered (Eq. (9)), as from amrto_pcg.
+ * Returns AMRTO_OK, AMRTO_NOT_CONVERGED or AMRTO_EBREAKDOWN. */
 int amrto_mg_pcg(amrto_ctx* ctx, const double* b, double* u, double rtol, int32_t max_it,
                  int32_t check_every, amrto_solve_stats* stats);
 

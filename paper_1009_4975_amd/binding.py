@@ -142,6 +142,7 @@ _SIGS = {
     "amrto_mg_prolong": (C.c_int, [_p, C.c_int32, _p, _p]),
     "amrto_mg_restrict": (C.c_int, [_p, C.c_int32, _p, _p]),
     "amrto_mg_pcg": (C.c_int, [_p, _p, _p, C.c_double, C.c_int32, C.c_int32, C.POINTER(SolveStats)]),
+    "amrto_mg_pass_times": (C.c_int, [_p, C.c_int32, _p]),
     "amrto_plane_create": (C.c_int, [C.POINTER(_p), C.c_int, _p]),
     "amrto_plane_destroy": (C.c_int, [_p]),
     "amrto_plane_last_error": (C.c_char_p, [_p]),
@@ -592,6 +593,13 @@ class Context:
         _need(dofs[k], rc=rc)
         self._chk(self.lib.amrto_mg_restrict(self.h, int(k), _dev(rf, self.torch.float64),
                                              _dev(rc, self.torch.float64)))
+
+    def mg_pass_times(self, reps=100):
+        """Mean us of one smoothing pass per smoothed level (level 0 first)."""
+        dofs = getattr(self, "_mg_dofs", None) or []
+        out = np.zeros(max(1, len(dofs) - 1))
+        self._chk(self.lib.amrto_mg_pass_times(self.h, int(reps), out.ctypes.data))
+        return out[:max(0, len(dofs) - 1)].tolist()
 
     def mg_pcg(self, b, u, rtol=1e-8, max_it=5000, check_every=2):
         self._dofs(b=b, u=u)

@@ -1465,6 +1465,39 @@ int amrto_mg_restrict(amrto_ctx* ctx, int32_t k, const double* rf, double* rc_ou
   return AMRTO_OK;
 }
 
+int amrto_mg_pass_times(amrto_ctx* ctx, int32_t reps, double* us) {
+  int rc = check_mg(ctx, "amrto_mg_pass_times");
+  if (rc) return rc;
+  if (reps < 1 || !us) return ctx->fail(AMRTO_EINVAL, "amrto_mg_pass_times: bad arguments");
+  AMRTO_HIP(hipSetDevice(ctx->device));
+  if ((rc = ensure_numeric(ctx))) return rc;
+  MgData* g = ctx->mg;
+  hipEvent_t e0, e1;
+  AMRTO_HIP(hipEventCreate(&e0));
+  AMRTO_HIP(hipEventCreate(&e1));
+  for (int k = 0; k < g->nlev - 1 && rc == AMRTO_OK; ++k) {
+    MgLevel& L = g->lv[k];
+    const long n = 3L * L.nn;
+    // zero vectors: every pass keeps them zero, so repetitions stay finite
+    hipLaunchKernelGGL(k_mg_zero, dim3(blocks_for(n)), dim3(256), 0, ctx->stream, L.x, L.r, n);
+    hipLaunchKernelGGL(k_mg_zero, dim3(blocks_for(n)), dim3(256), 0, ctx->stream, L.d, L.q, n);
+    if ((rc = pass(ctx, k, L.d, upd(L, MG_CHEB, 0)))) break;  // warm-up
+    if (hipEventRecord(e0, ctx->stream) != hipSuccess) { rc = ctx->fail(AMRTO_EHIP, "event"); break; }
+    for (int i = 0; i < reps && rc == AMRTO_OK; ++i) rc = pass(ctx, k, L.d, upd(L, MG_CHEB, 0));
+    if (rc) break;
+    if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      rc = ctx->fail(AMRTO_EHIP, "event");
+      break;
+    }
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    us[k] = 1e3 * (double)ms / reps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
 int amrto_mg_pcg(amrto_ctx* ctx, const double* b, double* u, double rtol, int32_t max_it, int32_t check_every,
                  amrto_solve_stats* stats) {
   int rc = check_mg(ctx, "amrto_mg_pcg");
@@ -1522,11 +1555,12 @@ int amrto_mg_pcg(amrto_ctx* ctx, const double* b, double* u, double rtol, int32_
     AMRTO_HIP(hipGetLastError());
     it += batch;
   }
-  // true residual
+  // true residual, then u = T u~ (hanging values from their masters, Eq. (9))
   if ((rc = launch_apply(ctx, u, g->qv, AMRTO_FP64))) return rc;
   hipLaunchKernelGGL(k_mgcg_resid, dim3(MG_RED), dim3(256), 0, ctx->stream, b, g->qv, L0.flag, n, g->part);
   hipLaunchKernelGGL(k_mgcg_resid_scal, dim3(1), dim3(256), 0, ctx->stream, g->part, g->cg);
   AMRTO_HIP(hipGetLastError());
+  if ((rc = launch_recover(ctx, u, u))) return rc;
   AMRTO_HIP(hipMemcpyAsync(g->h_cg, g->cg, MC_COUNT * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   AMRTO_HIP(hipStreamSynchronize(ctx->stream));
   const double rel = g->h_cg[MC_RES];

@@ -33,7 +33,7 @@ class AdaptiveSIMP:
                  rho_min=1e-3, rho_solid=0.5, r_amr=1.5, adapt_every=5, rtol=1e-8, inner_prec=FP64,
                  inner_rtol=0.1, max_it=100000, device=0, metrics_path=None, precond=binding.JACOBI,
                  adapt_rule="every", min_steps=5, max_steps=10, change_tol=0.01, p_continuation=None,
-                 p=3.0, recycle=None):
+                 p=3.0, recycle=None, mg=None):
         self.base, self.max_level = tuple(int(b) for b in base), int(max_level)
         self.tree = binding.Octree(base, max_level)
         self.ctx = binding.Context(device)
@@ -62,6 +62,10 @@ class AdaptiveSIMP:
         self.recycle = None if recycle is None else dict(dict(mode="init", m=64, k=4, keep=4, regions=(3, 2, 2),
                                                               affine=True), **recycle)
         self.rec_vecs = []  # carried vectors (kept Rayleigh-Ritz vectors, then the last harvest)
+        # multigrid-preconditioned CG (options of Context.mg_setup, e.g.
+        # dict(first=2, degree=1, coarse_degree=2, ratio=50)), or None; the
+        # hierarchy is rebuilt with every mesh
+        self.mg = None if mg is None else dict(mg)
         self.it = 0
         self.compliance = None
         self.mesh_version = 0
@@ -75,6 +79,8 @@ class AdaptiveSIMP:
         mesh = self.tree.build_mesh(self.fixed, self.load)
         self.ctx.upload_mesh(mesh)
         self.mesh = mesh
+        if self.mg is not None:
+            self.ctx.mg_setup(self.tree, **self.mg)
         d = self.dev
         self.f = torch.tensor(mesh.f_load, dtype=torch.float64, device=d)
         self.b = torch.empty_like(self.f)
@@ -140,8 +146,11 @@ class AdaptiveSIMP:
             self._recycle_coarse()
         torch.cuda.synchronize(self.dev)
         t2 = time.perf_counter()
-        st = self.ctx.pcg(self.b, self.u, rtol=self.rtol, max_it=self.max_it, inner_prec=self.inner_prec,
-                          inner_rtol=self.inner_rtol, precond=self.precond, record=self.recycle is not None)
+        if self.mg is not None:
+            st = self.ctx.mg_pcg(self.b, self.u, rtol=self.rtol, max_it=min(self.max_it, 5000), check_every=2)
+        else:
+            st = self.ctx.pcg(self.b, self.u, rtol=self.rtol, max_it=self.max_it, inner_prec=self.inner_prec,
+                              inner_rtol=self.inner_rtol, precond=self.precond, record=self.recycle is not None)
         harvest_s = 0.0
         if self.recycle is not None:
             th = time.perf_counter()

@@ -150,9 +150,8 @@ def test_mg_pcg_matches_direct_solve(case):
     u = torch.zeros_like(f)
     st = case.ctx.mg_pcg(b, u, rtol=1e-10, max_it=500, check_every=1)
     assert st["status"] == "OK" and st["rel_res"] <= 1e-10, st
-    ut = torch.empty_like(u)
-    case.ctx.recover(u, ut)
-    got = case.to_orc(0, ut)
+    # u comes back as T u~: hanging DOFs interpolated from their masters
+    got = case.to_orc(0, u)
     want = osys.recover(case.sys, u_ref)
     assert np.abs(got - want).max() <= 1e-8 * np.abs(want).max()
     jac = osys.pcg_jacobi(case.sys.A, case.sys.b, rtol=1e-10)
