@@ -133,6 +133,8 @@ def event_time(torch, fn, reps):
 # coarsening, Chebyshev degree 1 on the analysis mesh and 2 on the coarse
 # levels over [lambda_max / 50, 1.1 lambda_max]
 MG_OPTS = dict(first=2, ratio=50.0, degree=1, coarse_degree=2)
+# uniform bricks (C1, C5): degree 2 on every level over [lambda_max / 30, 1.1 lambda_max]
+MG_OPTS_UNIFORM = dict(first=2, ratio=30.0, degree=2, coarse_degree=2)
 
 SOLVERS = ("fp64", "fp32", "bf16", "fp64+coarse", "fp32+coarse", "fp64+block3", "fp32+block3",
            "fp64+coarse+block3", "fp32+coarse+block3", "fp64+mg")
@@ -449,7 +451,8 @@ def solve_c1(torch, binding, synth, dev):
     filter, then Jacobi-PCG (FP64) from zero to 1e-8, compliance and
     sensitivities, the Eq. (5) filter and the OC step; best of three."""
     case = synth.c1()
-    mesh = binding.uniform_mesh(case.dims, case.fixed, case.load)
+    tree = binding.Octree(case.dims, 0)
+    mesh = binding.uniform_mesh(case.dims, case.fixed, case.load, tree=tree)
     ctx = binding.Context(0)
     ctx.upload_mesh(mesh)
     rho0 = dev(case.rho)
@@ -460,12 +463,12 @@ def solve_c1(torch, binding, synth, dev):
     u = torch.zeros_like(f)
     dc, dcf, rho_new = (torch.empty_like(rho) for _ in range(3))
 
-    def it():
+    def it(mg=False):
         t0 = time.perf_counter()
         ctx.set_density(rho)
         ctx.project_rhs(f, b)
         u.zero_()
-        st = ctx.pcg(b, u, rtol=1e-8)
+        st = ctx.mg_pcg(b, u, rtol=1e-8, max_it=2000) if mg else ctx.pcg(b, u, rtol=1e-8)
         t1 = time.perf_counter()
         c = ctx.compliance(u, f, rho, dc)
         ctx.filter(binding.FILTER_SENSITIVITY, case.filter_radius, dc, dcf, rho=rho)
@@ -479,9 +482,16 @@ def solve_c1(torch, binding, synth, dev):
     r, _ = best_ms(it)
     log(f"[bench] C1 SIMP iteration: {r['ms']:.2f} ms (solve {r['solve_ms']:.2f} ms, {r['iters']} iterations, "
         f"rel_res {r['rel_res']:.2e}; compliance, sensitivities, filter, OC {r['design_ms']:.2f} ms)")
+    ctx.mg_setup(tree, **MG_OPTS_UNIFORM)
+    it(True)
+    m, _ = best_ms(lambda: it(True))
+    log(f"[bench] C1 SIMP iteration, multigrid: {m['ms']:.2f} ms (solve {m['solve_ms']:.2f} ms, {m['iters']} iterations, "
+        f"rel_res {m['rel_res']:.2e})")
     return dict(iteration_ms=round(r["ms"], 3), solve_ms=round(r["solve_ms"], 3), design_ms=round(r["design_ms"], 3),
                 iters=r["iters"], rel_res=r["rel_res"], compliance=r["compliance"], dofs=3 * mesh.n_nodes,
-                solver="fp64 Jacobi-PCG from zero", rtol=1e-8)
+                solver="fp64 Jacobi-PCG from zero", rtol=1e-8,
+                multigrid=dict(iteration_ms=round(m["ms"], 3), solve_ms=round(m["solve_ms"], 3), iters=m["iters"],
+                               rel_res=m["rel_res"], compliance=m["compliance"], options=dict(MG_OPTS_UNIFORM)))
 
 
 def solve_c5(torch, binding, synth, dev):
@@ -490,7 +500,8 @@ def solve_c5(torch, binding, synth, dev):
     block-Jacobi), then compliance + adjoint sensitivities of the FP64
     solution; best of two per variant."""
     case = synth.c5()
-    mesh = binding.uniform_mesh(case.dims, case.fixed, case.load)
+    tree = binding.Octree(case.dims, 0)
+    mesh = binding.uniform_mesh(case.dims, case.fixed, case.load, tree=tree)
     ctx = binding.Context(0)
     ctx.upload_mesh(mesh)
     rho = dev(case.rho)
@@ -510,6 +521,16 @@ def solve_c5(torch, binding, synth, dev):
         r, _ = best_ms(run, 2)
         out[name] = dict(ms=round(r["ms"], 2), iters=r["iters"], outer=r["outer"], rel_res=r["rel_res"])
         log(f"[bench] C5 solve {name}: {r['ms']:.1f} ms, {r['iters']} iterations, rel_res {r['rel_res']:.2e}")
+    ctx.mg_setup(tree, **MG_OPTS_UNIFORM)
+
+    def run_mg():
+        u.zero_()
+        ctx.set_density(rho)  # the solve rebuilds the coarse operators
+        torch.cuda.synchronize()
+        return ctx.mg_pcg(b, u, rtol=1e-8, max_it=2000)
+    r, _ = best_ms(run_mg, 2)
+    out["fp64+mg"] = dict(ms=round(r["ms"], 2), iters=r["iters"], rel_res=r["rel_res"], options=dict(MG_OPTS_UNIFORM))
+    log(f"[bench] C5 solve fp64+mg: {r['ms']:.1f} ms, {r['iters']} iterations, rel_res {r['rel_res']:.2e}")
     u.zero_()
     ctx.pcg(b, u, rtol=1e-8)
     ctx.compliance(u, f, rho, dc)
