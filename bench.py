@@ -543,46 +543,62 @@ def solve_c5(torch, binding, synth, dev):
 
 def amr_vs_uniform(torch, binding, synth):
     """The paper's AMR-against-uniform comparison on a synthetic cantilever:
-    the same SIMP loop (plain FP64 Jacobi-PCG to 1e-8 from the previous
+    the same SIMP loop (multigrid-preconditioned CG to 1e-8 from the previous
     displacement, Eq. (5) filter, OC) on the fixed uniform 128x32x32 mesh and
     on an adaptive mesh started at 64x16x16 (one refinement level) adapted by
     the paper's trigger (CASE (i): largest design change < 0.01 after >= 5
     steps; CASE (ii): 10 steps), for the same number of design steps.  Both
-    run the octree operator kernels.  Reports sizes, iterations, solve time
-    and the design difference D of Eq. (10) between the final designs."""
+    run the octree operator kernels and the same multigrid options.  Reports
+    sizes, iterations, solve time, the first step whose design change fell
+    below 0.01, the final compliances and the design difference D of
+    Eq. (10) between the final designs (also every 50 steps)."""
     from paper_1009_4975_amd.simp import AdaptiveSIMP
     case = synth.amr_vs_uniform()
     ex = case.extra
-    runs = {}
+    sims, recs = {}, {"uniform": [], "amr": []}
     for name, base, L, rule in (("uniform", case.dims, 0, "never"), ("amr", case.base, case.max_level, "paper")):
-        t0 = time.perf_counter()
-        sim = AdaptiveSIMP(base, L, case.fixed, case.load, volfrac=ex["volfrac"], rho_init=ex["rho_init"],
-                           rmin=ex["rmin"], rho_solid=ex["rho_solid"], r_amr=ex["r_amr"], adapt_rule=rule,
-                           min_steps=ex["min_steps"], max_steps=ex["max_steps"], change_tol=ex["change_tol"],
-                           rtol=1e-8, p_continuation=ex.get("p_continuation"))
-        recs = [sim.step() for _ in range(ex["steps"])]
-        torch.cuda.synchronize()
-        runs[name] = dict(sim=sim, recs=recs, wall_s=time.perf_counter() - t0)
+        sims[name] = AdaptiveSIMP(base, L, case.fixed, case.load, volfrac=ex["volfrac"], rho_init=ex["rho_init"],
+                                  rmin=ex["rmin"], rho_solid=ex["rho_solid"], r_amr=ex["r_amr"], adapt_rule=rule,
+                                  min_steps=ex["min_steps"], max_steps=ex["max_steps"],
+                                  change_tol=ex["change_tol"], rtol=1e-8, mg=MG_OPTS,
+                                  p_continuation=ex.get("p_continuation"))
+    trail = []
+    t0 = time.perf_counter()
+    for s in range(ex["steps"]):
+        for name, sim in sims.items():
+            recs[name].append(sim.step())
+        if (s + 1) % 50 == 0:
+            trail.append([s + 1, round(sims["uniform"].ctx.design_difference(
+                sims["uniform"].rho, sims["amr"].ctx, sims["amr"].rho), 5)])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
     out = {}
-    for name, r in runs.items():
-        recs = r["recs"]
-        out[name] = dict(steps=len(recs), solve_ms=round(sum(x["solve_ms"] for x in recs), 1),
-                         pcg_iters=int(sum(x["iters"] for x in recs)),
-                         dofs_mean=int(np.mean([x["dofs"] for x in recs])), dofs_final=recs[-1]["dofs"],
-                         elements_final=recs[-1]["n_elems"], adaptations=int(sum(x["adapted"] for x in recs)),
-                         final_compliance=recs[-1]["compliance"], final_change=recs[-1]["change"],
-                         max_rel_res=max(x["rel_res"] for x in recs), wall_s=round(r["wall_s"], 2))
-    su, sa = runs["uniform"]["sim"], runs["amr"]["sim"]
+    for name, rs in recs.items():
+        conv = [i + 1 for i, x in enumerate(rs) if x["change"] < ex["change_tol"]]
+        out[name] = dict(steps=len(rs), solve_ms=round(sum(x["solve_ms"] for x in rs), 1),
+                         pcg_iters=int(sum(x["iters"] for x in rs)),
+                         dofs_mean=int(np.mean([x["dofs"] for x in rs])), dofs_final=rs[-1]["dofs"],
+                         elements_final=rs[-1]["n_elems"], adaptations=int(sum(x["adapted"] for x in rs)),
+                         final_compliance=rs[-1]["compliance"], final_change=rs[-1]["change"],
+                         first_step_change_below_tol=conv[0] if conv else None,
+                         max_rel_res=max(x["rel_res"] for x in rs))
+    su, sa = sims["uniform"], sims["amr"]
     D = su.ctx.design_difference(su.rho, sa.ctx, sa.rho)
     out["design_difference_D"] = D
+    out["design_difference_every_50_steps"] = trail
+    out["compliance_rel_diff_amr_vs_uniform"] = round(
+        out["amr"]["final_compliance"] / out["uniform"]["final_compliance"] - 1.0, 5)
     out["solve_time_ratio_uniform_over_amr"] = round(out["uniform"]["solve_ms"] / out["amr"]["solve_ms"], 3)
     out["dofs_ratio_amr_over_uniform"] = round(out["amr"]["dofs_mean"] / out["uniform"]["dofs_mean"], 3)
+    out["wall_s_both"] = round(wall, 2)
     out["config"] = dict(uniform=list(case.dims), amr_initial=list(case.base), levels=case.max_level,
-                         volfrac=ex["volfrac"], rmin=ex["rmin"], steps=ex["steps"], solver="fp64 Jacobi-PCG, 1e-8",
+                         volfrac=ex["volfrac"], rmin=ex["rmin"], r_amr=ex["r_amr"], steps=ex["steps"],
+                         solver="fp64 multigrid-PCG, 1e-8", multigrid=dict(MG_OPTS),
                          p_continuation=ex.get("p_continuation"))
     log(f"[bench] AMR vs uniform ({ex['steps']} steps): uniform {out['uniform']['solve_ms']} ms solve, "
-        f"{out['uniform']['pcg_iters']} its, {out['uniform']['dofs_mean']} DOFs mean; AMR {out['amr']['solve_ms']} ms, "
-        f"{out['amr']['pcg_iters']} its, {out['amr']['dofs_mean']} DOFs mean, {out['amr']['adaptations']} adapts; "
+        f"{out['uniform']['pcg_iters']} its, {out['uniform']['dofs_mean']} DOFs mean, c {out['uniform']['final_compliance']:.4f}; "
+        f"AMR {out['amr']['solve_ms']} ms, {out['amr']['pcg_iters']} its, {out['amr']['dofs_mean']} DOFs mean, "
+        f"{out['amr']['adaptations']} adapts, c {out['amr']['final_compliance']:.4f}; "
         f"D = {100 * D:.3f} %, time ratio {out['solve_time_ratio_uniform_over_amr']}")
     return out
 

@@ -76,6 +76,21 @@ int amrto_destroy(amrto_ctx* ctx);
 const char* amrto_last_error(const amrto_ctx* ctx);
 /* Replace the stream used by later calls. */
 int amrto_set_stream(amrto_ctx* ctx, void* hip_stream);
+/* Deterministic mode (on != 0).  The octree passes sum element contributions
+ * in workgroup-local FP64 accumulators; by default the waves of a workgroup
+ * add to them in the order they happen to run, so the last bits of y = A~ x,
+ * of the diagonal and of the coarse-space sums, and with them iteration
+ * counts, can vary from run to run.  In deterministic mode the waves take
+ * turns in a fixed order and hanging-node condensation runs in one wave, so
+ * every result depends only on the inputs (same device, same build).  It
+ * covers the operator passes of every precision and solver form, the Jacobi
+ * diagonal and node blocks, the coarse-space passes and the multigrid; the
+ * uniform-brick passes are deterministic in both modes.  Costs time on the
+ * octree passes.  Switching recomputes the diagonal now and the node-block
+ * inverses and multigrid operators when next used; a coarse space formed
+ * before the switch keeps its Gram matrix until amrto_coarse_setup runs
+ * again.  Default off.  Errors: none beyond a HIP failure of the diagonal. */
+int amrto_set_deterministic(amrto_ctx* ctx, int32_t on);
 
 /* SIMP material law E(rho) = Emin + rho^p (E0 - Emin) (Sec. 3, Eq. (2);
  * Emin plays the role of the density floor rho_o^p) and Poisson ratio nu,

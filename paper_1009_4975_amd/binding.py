@@ -72,6 +72,7 @@ _SIGS = {
     "amrto_destroy": (C.c_int, [_p]),
     "amrto_last_error": (C.c_char_p, [_p]),
     "amrto_set_stream": (C.c_int, [_p, _p]),
+    "amrto_set_deterministic": (C.c_int, [_p, C.c_int32]),
     "amrto_set_material": (C.c_int, [_p, C.c_double, C.c_double, C.c_double, C.c_double]),
     "amrto_upload_mesh": (C.c_int, [_p, C.POINTER(MeshStruct)]),
     "amrto_mesh_info": (C.c_int, [_p, _i32p, _i32p, _i32p]),
@@ -411,6 +412,9 @@ class Context:
 
     def set_material(self, E0=1.0, Emin=1e-9, nu=0.3, p=3.0):
         self._chk(self.lib.amrto_set_material(self.h, E0, Emin, nu, p))
+
+    def set_deterministic(self, on=True):
+        self._chk(self.lib.amrto_set_deterministic(self.h, 1 if on else 0))
 
     def upload_mesh(self, mesh: MeshArrays):
         s, keep = mesh.struct()

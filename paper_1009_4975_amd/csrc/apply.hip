@@ -616,7 +616,9 @@ __global__ __launch_bounds__(BTHREADS, BrickOcc<VT>::blocks) void k_apply_brick(
 // variants need more and keep 256.
 constexpr int chunk_threads(int prec, int coarse) { return (coarse && prec == P_BF16) ? 256 : 512; }
 
-template <typename VT, int PREC, bool FUSED, int COARSE = 0>
+// DET: deterministic mode (a template parameter, so that the default kernels
+// keep their register budget); see wave_turns
+template <typename VT, int PREC, bool FUSED, int COARSE = 0, bool DET = false>
 __global__ __launch_bounds__(chunk_threads(PREC, COARSE)) void k_apply_chunks(UArgs a, ChunkArgs ca, BrickK<VT> kc, CgArgs cg) {
   __shared__ VT xs[TAB_MAX * 3];
   __shared__ double ys[TAB_MAX * 3];  // FP64 LDS accumulators (ds_add_f64 runs at full rate on gfx950)
@@ -831,65 +833,86 @@ __global__ __launch_bounds__(chunk_threads(PREC, COARSE)) void k_apply_chunks(UA
   }
   __syncthreads();
   if (PREC != P_BF16) {
+    // deterministic mode: the waves take turns over whole elements (the
+    // contraction stays next to its adds, so the mode costs no registers)
 #pragma unroll
     for (int r = 0; r < EPT; ++r) {
       const int en = tid + NT * r;
-      if (en >= nent) break;
-      int loc[8];
-      const uint4 lv = lvp[r];
-      loc[0] = lv.x & 0xffff; loc[1] = lv.x >> 16; loc[2] = lv.y & 0xffff; loc[3] = lv.y >> 16;
-      loc[4] = lv.z & 0xffff; loc[5] = lv.z >> 16; loc[6] = lv.w & 0xffff; loc[7] = lv.w >> 16;
-      const VT ce = cep[r];
-      VT u[24], out[24];
+      const bool ev = en < nent;
+      if (!ev && !DET) break;
+      auto elem = [&]() {
+        if (!ev) return;
+        int loc[8];
+        const uint4 lv = lvp[r];
+        loc[0] = lv.x & 0xffff; loc[1] = lv.x >> 16; loc[2] = lv.y & 0xffff; loc[3] = lv.y >> 16;
+        loc[4] = lv.z & 0xffff; loc[5] = lv.z >> 16; loc[6] = lv.w & 0xffff; loc[7] = lv.w >> 16;
+        const VT ce = cep[r];
+        VT u[24], out[24];
 #pragma unroll
-      for (int aa = 0; aa < 8; ++aa) {
-        u[3 * aa + 0] = xs[loc[aa] * 3 + 0];
-        u[3 * aa + 1] = xs[loc[aa] * 3 + 1];
-        u[3 * aa + 2] = xs[loc[aa] * 3 + 2];
-      }
-      VT ks[8];
+        for (int aa = 0; aa < 8; ++aa) {
+          u[3 * aa + 0] = xs[loc[aa] * 3 + 0];
+          u[3 * aa + 1] = xs[loc[aa] * 3 + 1];
+          u[3 * aa + 2] = xs[loc[aa] * 3 + 2];
+        }
+        VT ks[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) ks[q] = ce * kc.c[q];
-      contract_brick<VT>(ks, u, out);
+        for (int q = 0; q < 8; ++q) ks[q] = ce * kc.c[q];
+        contract_brick<VT>(ks, u, out);
 #pragma unroll
-      for (int aa = 0; aa < 8; ++aa) {
-        atomicAdd(&ys[loc[aa] * 3 + 0], (double)out[3 * aa + 0]);
-        atomicAdd(&ys[loc[aa] * 3 + 1], (double)out[3 * aa + 1]);
-        atomicAdd(&ys[loc[aa] * 3 + 2], (double)out[3 * aa + 2]);
-      }
+        for (int aa = 0; aa < 8; ++aa) {
+          atomicAdd(&ys[loc[aa] * 3 + 0], (double)out[3 * aa + 0]);
+          atomicAdd(&ys[loc[aa] * 3 + 1], (double)out[3 * aa + 1]);
+          atomicAdd(&ys[loc[aa] * 3 + 2], (double)out[3 * aa + 2]);
+        }
+      };
+      if (DET) wave_turns(elem);
+      else elem();
     }
   } else {
     bf16x8 ka[2][2];
     load_k0_bf16((const uint16_t*)a.kb, ka);
     const int lane = tid & 63, wave = tid >> 6;
     const int n16 = lane & 15, q4 = lane >> 4;
-    for (int tb = 16 * wave; tb < nent; tb += 16 * (NT / 64)) {
-      const int en = tb + n16;
-      const bool ev = en < nent;
-      float u[24];
+    // deterministic mode: every wave takes the same number of tile steps and
+    // the waves take turns over them; one quarter of the lanes adds at a
+    // time, so the lanes of an add instruction hold distinct elements at the
+    // same vertex slot
+    const int tb_end = DET ? nent + 16 * wave : nent;
+    for (int tb = 16 * wave; tb < tb_end; tb += 16 * (NT / 64)) {
+      auto tile = [&](bool quarters) {
+        const int en = tb + n16;
+        const bool ev = en < nent;
+        float u[24];
 #pragma unroll
-      for (int aa = 0; aa < 8; ++aa) {
-        const int l = ev ? lsm[en * 8 + aa] * 3 : 0;
-        u[3 * aa + 0] = ev ? (float)xs[l + 0] : 0.f;
-        u[3 * aa + 1] = ev ? (float)xs[l + 1] : 0.f;
-        u[3 * aa + 2] = ev ? (float)xs[l + 2] : 0.f;
-      }
-      f32x4 d0, d1;
-      mfma_tile_bf16(ka, u, q4, d0, d1);
-      if (ev) {
+        for (int aa = 0; aa < 8; ++aa) {
+          const int l = ev ? lsm[en * 8 + aa] * 3 : 0;
+          u[3 * aa + 0] = ev ? (float)xs[l + 0] : 0.f;
+          u[3 * aa + 1] = ev ? (float)xs[l + 1] : 0.f;
+          u[3 * aa + 2] = ev ? (float)xs[l + 2] : 0.f;
+        }
+        f32x4 d0, d1;
+        mfma_tile_bf16(ka, u, q4, d0, d1);
+        if (!ev) return;
         const float ce = (float)coef[ca.ent_elem[n0 + en]];
+        for (int qs = 0; qs < (quarters ? 4 : 1); ++qs) {
+          if (quarters && q4 != qs) continue;
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
+          for (int t = 0; t < 2; ++t)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int R = 16 * t + 4 * q4 + r;
-            if (R < 24) atomicAdd(&ys[lsm[en * 8 + R / 3] * 3 + R % 3], (double)(ce * (t ? d1[r] : d0[r])));
-          }
-      }
+            for (int r = 0; r < 4; ++r) {
+              const int R = 16 * t + 4 * q4 + r;
+              if (R < 24) atomicAdd(&ys[lsm[en * 8 + R / 3] * 3 + R % 3], (double)(ce * (t ? d1[r] : d0[r])));
+            }
+        }
+      };
+      if (DET) wave_turns([&]() { tile(true); });
+      else tile(false);
     }
   }
   __syncthreads();
-  for (int i = tid; i < nh * 3; i += NT) {  // y_m += w_hm y_h  (P^T of Eq. (7))
+  // y_m += w_hm y_h  (P^T of Eq. (7)); deterministic mode: wave 0 alone, in
+  // triple order
+  for (int i = DET ? (tid < 64 ? tid : nh * 3) : tid; i < nh * 3; i += DET ? 64 : NT) {
     const int k = i / 3, comp = i % 3;
     const uint32_t hm = trip_hm_s[k];
     atomicAdd(&ys[(hm & 0xffff) * 3 + comp], trip_w_s[k] * ys[(hm >> 16) * 3 + comp]);
@@ -1016,22 +1039,26 @@ __global__ __launch_bounds__(chunk_threads(PREC, COARSE)) void k_apply_chunks(UA
         for (int c3 = 0; c3 < 3; ++c3) ys[(f * 3 + c3) * 256 + tid] = s[f][c3];
     __syncthreads();  // also orders the zeroing of czs before the atomics below
     if (mall & (mall - 1)) {
+      auto add = [&]() {
 #pragma unroll
-      for (int r = 0; r < NPT; ++r) {
-        const int w = __float_as_int(gv[r].w), g = w & 0xff;
-        if (tid + NT * r < nown && g != g0) {
-          const double d[3] = {(double)gv[r].x, (double)gv[r].y, (double)gv[r].z};
+        for (int r = 0; r < NPT; ++r) {
+          const int w = __float_as_int(gv[r].w), g = w & 0xff;
+          if (tid + NT * r < nown && g != g0) {
+            const double d[3] = {(double)gv[r].x, (double)gv[r].y, (double)gv[r].z};
 #pragma unroll
-          for (int c3 = 0; c3 < 3; ++c3) {
-            const double qc = ((w >> (8 + c3)) & 1) ? 0.0 : (double)qk[r][c3];
-            if (qc == 0.0) continue;
-            atomicAdd(&czs[g * 3 + c3], qc);
-            atomicAdd(&czs[(R + g) * 3 + c3], qc * d[c3]);
-            atomicAdd(&czs[(2 * R + g) * 3 + c3], qc * d[c3 == 2 ? 0 : c3 + 1]);
-            atomicAdd(&czs[(3 * R + g) * 3 + c3], qc * d[c3 == 0 ? 2 : c3 - 1]);
+            for (int c3 = 0; c3 < 3; ++c3) {
+              const double qc = ((w >> (8 + c3)) & 1) ? 0.0 : (double)qk[r][c3];
+              if (qc == 0.0) continue;
+              atomicAdd(&czs[g * 3 + c3], qc);
+              atomicAdd(&czs[(R + g) * 3 + c3], qc * d[c3]);
+              atomicAdd(&czs[(2 * R + g) * 3 + c3], qc * d[c3 == 2 ? 0 : c3 + 1]);
+              atomicAdd(&czs[(3 * R + g) * 3 + c3], qc * d[c3 == 0 ? 2 : c3 - 1]);
+            }
           }
         }
-      }
+      };
+      if (DET) wave_turns(add);
+      else add();
     }
     if (tid < 192) {
       const int u = tid >> 4, sub = tid & 15;
@@ -1150,7 +1177,11 @@ __global__ __launch_bounds__(512) void k_diag_chunks(double* __restrict__ dinv, 
   };
   // one work item per (entry, vertex): the few entries that touch hanging
   // nodes carry most of the work, so it is spread over the threads by vertex
-  for (int it = tid; it < nent * 8; it += DT) {
+  // (deterministic mode: the waves take turns, see wave_turns)
+  for (int base = 0; base < nent * 8; base += DT) {
+    const int it = base + tid;
+    auto item = [&]() {
+    if (it >= nent * 8) return;
     const int en = it >> 3, aa = it & 7;
     int loc[8];
     const uint4 lv = *reinterpret_cast<const uint4*>(ca.ent_loc + 8L * (n0 + en));
@@ -1178,6 +1209,9 @@ __global__ __launch_bounds__(512) void k_diag_chunks(double* __restrict__ dinv, 
         for (int cc = 0; cc < 3; ++cc) atomicAdd(&ds[ma * 3 + cc], ce * acc[cc]);
       }
     }
+    };
+    if (ca.det) wave_turns(item);
+    else item();
   }
   __syncthreads();
   for (int i = tid; i < (nown + nhown) * 3; i += DT) {
@@ -1232,6 +1266,16 @@ int apply_blocks(const amrto_ctx* ctx) {
   return ((ctx->n_chunks + 7) / 8) * 8;
 }
 
+template <typename VT, int PREC, bool FUSED, int COARSE = 0>
+static void launch_chunks(amrto_ctx* ctx, dim3 grid, const UArgs& a, const ChunkArgs& ch, const CgArgs& cg) {
+  if (ch.det)
+    hipLaunchKernelGGL((k_apply_chunks<VT, PREC, FUSED, COARSE, true>), grid, dim3(chunk_threads(PREC, COARSE)), 0,
+                       ctx->stream, a, ch, brick_k<VT>(ctx), cg);
+  else
+    hipLaunchKernelGGL((k_apply_chunks<VT, PREC, FUSED, COARSE, false>), grid, dim3(chunk_threads(PREC, COARSE)), 0,
+                       ctx->stream, a, ch, brick_k<VT>(ctx), cg);
+}
+
 template <typename VT, int PREC, bool FUSED>
 static int launch_t(amrto_ctx* ctx, const UArgs& ua, const CgArgs& cg) {
   if (ctx->uniform) {
@@ -1251,8 +1295,7 @@ static int launch_t(amrto_ctx* ctx, const UArgs& ua, const CgArgs& cg) {
                          cg);
     }
   } else {
-    hipLaunchKernelGGL((k_apply_chunks<VT, PREC, FUSED>), dim3(apply_blocks(ctx)), dim3(chunk_threads(PREC, 0)), 0, ctx->stream, ua,
-                       chunk_args(ctx), brick_k<VT>(ctx), cg);
+    launch_chunks<VT, PREC, FUSED>(ctx, dim3(apply_blocks(ctx)), ua, chunk_args(ctx), cg);
   }
   AMRTO_HIP(hipGetLastError());
   return AMRTO_OK;
@@ -1337,25 +1380,19 @@ int apply_fused_coarse(amrto_ctx* ctx, const void* r, const void* minv, const vo
   const ChunkArgs ch = chunk_args(ctx);
   if (prec == AMRTO_FP64) {
     if (block3)
-      hipLaunchKernelGGL((k_apply_chunks<double, P_F64, true, 2>), grid, dim3(chunk_threads(P_F64, 2)), 0, ctx->stream, a, ch,
-                         brick_k<double>(ctx), cg);
+      launch_chunks<double, P_F64, true, 2>(ctx, grid, a, ch, cg);
     else
-      hipLaunchKernelGGL((k_apply_chunks<double, P_F64, true, 1>), grid, dim3(chunk_threads(P_F64, 1)), 0, ctx->stream, a, ch,
-                         brick_k<double>(ctx), cg);
+      launch_chunks<double, P_F64, true, 1>(ctx, grid, a, ch, cg);
   } else if (prec == AMRTO_FP32) {
     if (block3)
-      hipLaunchKernelGGL((k_apply_chunks<float, P_F32, true, 2>), grid, dim3(chunk_threads(P_F32, 2)), 0, ctx->stream, a, ch,
-                         brick_k<float>(ctx), cg);
+      launch_chunks<float, P_F32, true, 2>(ctx, grid, a, ch, cg);
     else
-      hipLaunchKernelGGL((k_apply_chunks<float, P_F32, true, 1>), grid, dim3(chunk_threads(P_F32, 1)), 0, ctx->stream, a, ch,
-                         brick_k<float>(ctx), cg);
+      launch_chunks<float, P_F32, true, 1>(ctx, grid, a, ch, cg);
   } else {
     if (block3)
-      hipLaunchKernelGGL((k_apply_chunks<float, P_BF16, true, 2>), grid, dim3(chunk_threads(P_BF16, 2)), 0, ctx->stream, a, ch,
-                         brick_k<float>(ctx), cg);
+      launch_chunks<float, P_BF16, true, 2>(ctx, grid, a, ch, cg);
     else
-      hipLaunchKernelGGL((k_apply_chunks<float, P_BF16, true, 1>), grid, dim3(chunk_threads(P_BF16, 1)), 0, ctx->stream, a, ch,
-                         brick_k<float>(ctx), cg);
+      launch_chunks<float, P_BF16, true, 1>(ctx, grid, a, ch, cg);
   }
   AMRTO_HIP(hipGetLastError());
   return AMRTO_OK;

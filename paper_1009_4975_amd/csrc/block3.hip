@@ -121,7 +121,11 @@ __global__ __launch_bounds__(512) void k_block_chunks(const double* __restrict__
   };
   // one work item per (entry, vertex): the few entries that touch hanging
   // nodes carry most of the work, so it is spread over the threads by vertex
-  for (int it = tid; it < nent * 8; it += DT) {
+  // (deterministic mode: the waves take turns, see wave_turns)
+  for (int base = 0; base < nent * 8; base += DT) {
+    const int it = base + tid;
+    auto item = [&]() {
+    if (it >= nent * 8) return;
     const int en = it >> 3, aa = it & 7;
     int loc[8];
     const uint4 lv = *reinterpret_cast<const uint4*>(ca.ent_loc + 8L * (n0 + en));
@@ -155,6 +159,9 @@ __global__ __launch_bounds__(512) void k_block_chunks(const double* __restrict__
         for (int q = 0; q < 6; ++q) atomicAdd(&ds[ma * 6 + q], ce * acc[q]);
       }
     }
+    };
+    if (ca.det) wave_turns(item);
+    else item();
   }
   __syncthreads();
   for (int t = tid; t < nown + nhown; t += DT) {

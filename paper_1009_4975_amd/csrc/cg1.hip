@@ -236,31 +236,38 @@ __global__ __launch_bounds__(256) void k_cg1_chunks(Cg1Vecs<VT> v, ChunkArgs ca,
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
     const int en = tid + 256 * q;
-    if (en >= nent) break;
-    int loc[8];
-    const uint4 lv = lvp[q];
-    loc[0] = lv.x & 0xffff; loc[1] = lv.x >> 16; loc[2] = lv.y & 0xffff; loc[3] = lv.y >> 16;
-    loc[4] = lv.z & 0xffff; loc[5] = lv.z >> 16; loc[6] = lv.w & 0xffff; loc[7] = lv.w >> 16;
-    VT u[24], out[24];
+    const bool ev = en < nent;
+    if (!ev && !ca.det) break;  // deterministic mode: the waves take turns over whole elements
+    auto elem = [&]() {
+      if (!ev) return;
+      int loc[8];
+      const uint4 lv = lvp[q];
+      loc[0] = lv.x & 0xffff; loc[1] = lv.x >> 16; loc[2] = lv.y & 0xffff; loc[3] = lv.y >> 16;
+      loc[4] = lv.z & 0xffff; loc[5] = lv.z >> 16; loc[6] = lv.w & 0xffff; loc[7] = lv.w >> 16;
+      VT u[24], out[24];
 #pragma unroll
-    for (int aa = 0; aa < 8; ++aa) {
-      u[3 * aa + 0] = xs[loc[aa] * 3 + 0];
-      u[3 * aa + 1] = xs[loc[aa] * 3 + 1];
-      u[3 * aa + 2] = xs[loc[aa] * 3 + 2];
-    }
-    VT ks[8];
+      for (int aa = 0; aa < 8; ++aa) {
+        u[3 * aa + 0] = xs[loc[aa] * 3 + 0];
+        u[3 * aa + 1] = xs[loc[aa] * 3 + 1];
+        u[3 * aa + 2] = xs[loc[aa] * 3 + 2];
+      }
+      VT ks[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) ks[k] = cep[q] * kc.c[k];
-    contract_brick<VT>(ks, u, out);
+      for (int k = 0; k < 8; ++k) ks[k] = cep[q] * kc.c[k];
+      contract_brick<VT>(ks, u, out);
 #pragma unroll
-    for (int aa = 0; aa < 8; ++aa) {
-      atomicAdd(&ys[loc[aa] * 3 + 0], (double)out[3 * aa + 0]);
-      atomicAdd(&ys[loc[aa] * 3 + 1], (double)out[3 * aa + 1]);
-      atomicAdd(&ys[loc[aa] * 3 + 2], (double)out[3 * aa + 2]);
-    }
+      for (int aa = 0; aa < 8; ++aa) {
+        atomicAdd(&ys[loc[aa] * 3 + 0], (double)out[3 * aa + 0]);
+        atomicAdd(&ys[loc[aa] * 3 + 1], (double)out[3 * aa + 1]);
+        atomicAdd(&ys[loc[aa] * 3 + 2], (double)out[3 * aa + 2]);
+      }
+    };
+    if (ca.det) wave_turns(elem);
+    else elem();
   }
   __syncthreads();
-  for (int i = tid; i < nh * 3; i += 256) {  // y_m += w_hm y_h  (P^T of Eq. (7))
+  // y_m += w_hm y_h  (P^T of Eq. (7)); deterministic mode: wave 0 alone
+  for (int i = ca.det ? (tid < 64 ? tid : nh * 3) : tid; i < nh * 3; i += ca.det ? 64 : 256) {
     const int k = i / 3, comp = i % 3;
     const uint32_t hm = trip_hm_s[k];
     atomicAdd(&ys[(hm & 0xffff) * 3 + comp], trip_w_s[k] * ys[(hm >> 16) * 3 + comp]);

@@ -231,30 +231,37 @@ __global__ __launch_bounds__(256) void k_gram_chunks(ChunkArgs ca, BrickK<double
 #pragma unroll
       for (int r = 0; r < EPT; ++r) {
         const int en = tid + 256 * r;
-        if (en >= nent) break;
-        int loc[8];
-        const uint4 lv = lvp[r];
-        loc[0] = lv.x & 0xffff; loc[1] = lv.x >> 16; loc[2] = lv.y & 0xffff; loc[3] = lv.y >> 16;
-        loc[4] = lv.z & 0xffff; loc[5] = lv.z >> 16; loc[6] = lv.w & 0xffff; loc[7] = lv.w >> 16;
-        double u[24], out[24], ks[8];
+        const bool ev = en < nent;
+        if (!ev && !ca.det) break;  // deterministic mode: the waves take turns over whole elements
+        auto elem = [&]() {
+          if (!ev) return;
+          int loc[8];
+          const uint4 lv = lvp[r];
+          loc[0] = lv.x & 0xffff; loc[1] = lv.x >> 16; loc[2] = lv.y & 0xffff; loc[3] = lv.y >> 16;
+          loc[4] = lv.z & 0xffff; loc[5] = lv.z >> 16; loc[6] = lv.w & 0xffff; loc[7] = lv.w >> 16;
+          double u[24], out[24], ks[8];
 #pragma unroll
-        for (int aa = 0; aa < 8; ++aa) {
-          u[3 * aa + 0] = xs[loc[aa] * 3 + 0];
-          u[3 * aa + 1] = xs[loc[aa] * 3 + 1];
-          u[3 * aa + 2] = xs[loc[aa] * 3 + 2];
-        }
+          for (int aa = 0; aa < 8; ++aa) {
+            u[3 * aa + 0] = xs[loc[aa] * 3 + 0];
+            u[3 * aa + 1] = xs[loc[aa] * 3 + 1];
+            u[3 * aa + 2] = xs[loc[aa] * 3 + 2];
+          }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) ks[q] = cep[r] * kc.c[q];
-        contract_brick<double>(ks, u, out);
+          for (int q = 0; q < 8; ++q) ks[q] = cep[r] * kc.c[q];
+          contract_brick<double>(ks, u, out);
 #pragma unroll
-        for (int aa = 0; aa < 8; ++aa) {
-          atomicAdd(&ys[loc[aa] * 3 + 0], out[3 * aa + 0]);
-          atomicAdd(&ys[loc[aa] * 3 + 1], out[3 * aa + 1]);
-          atomicAdd(&ys[loc[aa] * 3 + 2], out[3 * aa + 2]);
-        }
+          for (int aa = 0; aa < 8; ++aa) {
+            atomicAdd(&ys[loc[aa] * 3 + 0], out[3 * aa + 0]);
+            atomicAdd(&ys[loc[aa] * 3 + 1], out[3 * aa + 1]);
+            atomicAdd(&ys[loc[aa] * 3 + 2], out[3 * aa + 2]);
+          }
+        };
+        if (ca.det) wave_turns(elem);
+        else elem();
       }
       __syncthreads();
-      for (int i = tid; i < nh * 3; i += 256) {  // y_m += w_hm y_h
+      // y_m += w_hm y_h; deterministic mode: wave 0 alone
+      for (int i = ca.det ? (tid < 64 ? tid : nh * 3) : tid; i < nh * 3; i += ca.det ? 64 : 256) {
         const int k = i / 3, comp = i % 3;
         const uint32_t hm = trip_hm_s[k];
         atomicAdd(&ys[(hm & 0xffff) * 3 + comp], trip_w_s[k] * ys[(hm >> 16) * 3 + comp]);

@@ -224,6 +224,20 @@ int amrto_set_material(amrto_ctx* ctx, double E0, double Emin, double nu, double
   return upload_material(ctx);
 }
 
+int amrto_set_deterministic(amrto_ctx* ctx, int32_t on) {
+  if (!ctx) return AMRTO_EINVAL;
+  const bool det = on != 0;
+  if (det == ctx->deterministic) return AMRTO_OK;
+  AMRTO_HIP(hipSetDevice(ctx->device));
+  ctx->deterministic = det;
+  // what the density determines is formed again in the new mode: the
+  // diagonal now, the node-block inverses and multigrid operators when next
+  // used (a coarse space keeps its Gram matrix until it is set up again)
+  ctx->binv_valid = false;
+  ctx->mg_valid = false;
+  return ctx->has_density ? launch_diag(ctx) : AMRTO_OK;
+}
+
 int amrto_upload_mesh(amrto_ctx* ctx, const amrto_mesh* m) {
   if (!ctx) return AMRTO_EINVAL;
   if (!m || m->n_nodes <= 0 || m->n_elems <= 0 || !m->dof_fixed)

@@ -113,6 +113,8 @@ struct amrto_ctx {
   // a - b, b, d, e, f, g, h - i, i (see k_apply_brick)
   double bk[8];
   std::string err;
+  // deterministic mode: LDS accumulations of the octree passes in a fixed order
+  bool deterministic = false;
 
   // mesh
   bool has_mesh = false, uniform = false, has_density = false;

@@ -258,7 +258,27 @@ struct ChunkArgs {
   const double* trip_w;
   const int32_t* tab_hbeg;    // hanging entries: first triple (chunk-relative)
   int n_chunks;
+  int det;                    // deterministic mode: LDS accumulation in a fixed order
 };
+
+// Deterministic mode for LDS accumulation.  FP64 adds into one LDS slot from
+// different waves land in the order the waves happen to run, so the last bits
+// of the sums vary from run to run.  wave_turns(f) runs f in each wave of the
+// block in turn, wave 0 first, with a barrier after every turn: the adds then
+// follow (wave, program order, lane), a fixed order, when no two lanes of one
+// add instruction name the same slot (the element loops: per vertex slot and
+// component, distinct elements have distinct nodes, since two boxes with the
+// same corner in the same octant would overlap), and otherwise the order in
+// which the LDS unit applies one instruction's conflicting lanes, which does
+// not depend on timing.  Every thread of the block must call it.
+template <typename F>
+__device__ __forceinline__ void wave_turns(F&& f) {
+  const int nw = (int)(blockDim.x >> 6), w = (int)(threadIdx.x >> 6);
+  for (int t = 0; t < nw; ++t) {
+    if (w == t) f();
+    __syncthreads();
+  }
+}
 
 struct ChunkDims {
   int n0, nent, t0, nt, h0, nh, nown, nreg, nhown;
@@ -293,6 +313,7 @@ inline ChunkArgs chunk_args(amrto_ctx* ctx) {
   a.ent_elem = ctx->d_ent_elem; a.ent_loc = ctx->d_ent_loc; a.tab_node = ctx->d_tab_node;
   a.trip_hm = ctx->d_trip_hm; a.trip_w = ctx->d_trip_w; a.tab_hbeg = ctx->d_tab_hbeg;
   a.n_chunks = ctx->n_chunks;
+  a.det = ctx->deterministic ? 1 : 0;
   return a;
 }
 

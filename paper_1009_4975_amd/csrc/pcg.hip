@@ -162,6 +162,7 @@ struct CoarseArgs {
   int nf, R;
   const uint8_t* region;
   const float4* geo;      // affine space: per node (dx, dy, dz, region | mask << 8); NULL: stored fields
+  int det;                // deterministic mode (see zt_loop_acc)
 };
 
 // field values of DOF i into fv; returns the DOF's region
@@ -237,8 +238,36 @@ __device__ __forceinline__ void zt_add(ZtAcc& a, double* acc, const double (&fv)
 // the block's first DOF (the usual case), they are transposed through LDS and
 // each of the 3 nf columns is summed by one thread in thread order (no atomics,
 // deterministic); otherwise each thread adds its own sums atomically.
+// Deterministic mode: the lane flushes go to one accumulator per wave (in
+// red, which is unused until the end of the block's range), and the end of
+// the range adds the waves' accumulators in wave order.  Within a wave the
+// flushes follow program order, and one instruction's lanes that name the
+// same slot are applied by the LDS unit in an order that does not depend on
+// timing, so the sums do not vary from run to run.
+__device__ __forceinline__ double* zt_loop_acc(int det, double* acc, double (*red)[256]) {
+  return det ? &red[0][0] + (threadIdx.x >> 6) * COARSE_KMAX : acc;
+}
+
+__device__ __forceinline__ void zt_loop_clear(int det, double (*red)[256]) {
+  static_assert(COARSE_NFMAX * 3 * 256 >= 4 * COARSE_KMAX, "one accumulator per wave of 256 threads fits in red");
+  if (det)
+    for (int j = threadIdx.x; j < (int)(blockDim.x >> 6) * COARSE_KMAX; j += blockDim.x) (&red[0][0])[j] = 0.0;
+}
+
 __device__ __forceinline__ void zt_flush(ZtAcc& a, double* acc, int nf, int R, int g_first,
-                                         double (*red)[256]) {
+                                         double (*red)[256], int det) {
+  if (det) {
+    double* accw = &red[0][0];
+    zt_flush_lane(a, accw + (threadIdx.x >> 6) * COARSE_KMAX, nf, R);
+    __syncthreads();
+    const int k = 3 * nf * R, nw = (int)(blockDim.x >> 6);
+    for (int j = threadIdx.x; j < k; j += blockDim.x) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += accw[w * COARSE_KMAX + j];
+      acc[j] += s;
+    }
+    return;
+  }
   const bool uniform = __syncthreads_and(a.g == g_first || a.g < 0);
   if (!uniform) {
     zt_flush_lane(a, acc, nf, R);
@@ -279,7 +308,9 @@ __global__ __launch_bounds__(256) void k_zt_part(CoarseArgs ca, const VT* __rest
   __shared__ double red[COARSE_NFMAX * 3][256];
   const int nf = ca.nf, R = ca.R, k = 3 * nf * R;
   for (int j = threadIdx.x; j < k; j += blockDim.x) acc[j] = 0.0;
+  zt_loop_clear(ca.det, red);
   __syncthreads();
+  double* const acc_l = zt_loop_acc(ca.det, acc, red);
   long lo, hi;
   block_range(n3, lo, hi);
   ZtAcc a;
@@ -288,9 +319,9 @@ __global__ __launch_bounds__(256) void k_zt_part(CoarseArgs ca, const VT* __rest
   for (long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     double fv[COARSE_NFMAX];
     const int g = coarse_fields(ca, i, n3, fv);
-    zt_add(a, acc, fv, nf, R, g, (int)(i % 3), (double)v[i]);
+    zt_add(a, acc_l, fv, nf, R, g, (int)(i % 3), (double)v[i]);
   }
-  zt_flush(a, acc, nf, R, lo < hi ? coarse_region(ca, (int)(lo / 3)) : 0, red);
+  zt_flush(a, acc, nf, R, lo < hi ? coarse_region(ca, (int)(lo / 3)) : 0, red, ca.det);
   __syncthreads();
   zt_store(acc, k, part);
 }
@@ -337,7 +368,9 @@ __global__ __launch_bounds__(256) void k_cg_update_coarse(VT* __restrict__ x, VT
     return;
   }
   for (int j = threadIdx.x; j < k; j += blockDim.x) acc[j] = 0.0;
+  zt_loop_clear(ca.det, red);
   __syncthreads();
+  double* const acc_l = zt_loop_acc(ca.det, acc, red);
   const VT alpha = (VT)(rz / pq);
   ZtAcc a;
   zt_clear(a, -1);
@@ -353,7 +386,7 @@ __global__ __launch_bounds__(256) void k_cg_update_coarse(VT* __restrict__ x, VT
       r[i] = rv;
       srz += (double)rv * (double)dv0[u] * (double)rv;
       srr += (double)rv * (double)rv;
-      zt_add(a, acc, fv, nf, R, g, (int)(i % 3), (double)rv);
+      zt_add(a, acc_l, fv, nf, R, g, (int)(i % 3), (double)rv);
     }
   }
 #pragma unroll 2
@@ -366,9 +399,9 @@ __global__ __launch_bounds__(256) void k_cg_update_coarse(VT* __restrict__ x, VT
     r[i] = rv;
     srz += (double)rv * (double)di * (double)rv;
     srr += (double)rv * (double)rv;
-    zt_add(a, acc, fv, nf, R, g, (int)(i % 3), (double)rv);
+    zt_add(a, acc_l, fv, nf, R, g, (int)(i % 3), (double)rv);
   }
-  zt_flush(a, acc, nf, R, lo < hi ? coarse_region(ca, (int)(lo / 3)) : 0, red);
+  zt_flush(a, acc, nf, R, lo < hi ? coarse_region(ca, (int)(lo / 3)) : 0, red, ca.det);
   __syncthreads();
   zt_store(acc, k, part_z);
   block_sum2(srz, srr, sh);
@@ -406,7 +439,9 @@ __global__ __launch_bounds__(256) void k_cg_update_coarse_b3(VT* __restrict__ x,
     return;
   }
   for (int j = threadIdx.x; j < k; j += blockDim.x) acc[j] = 0.0;
+  zt_loop_clear(ca.det, red);
   __syncthreads();
+  double* const acc_l = zt_loop_acc(ca.det, acc, red);
   const VT alpha = (VT)(rz / pq);
   ZtAcc a;
   zt_clear(a, -1);
@@ -426,10 +461,10 @@ __global__ __launch_bounds__(256) void k_cg_update_coarse_b3(VT* __restrict__ x,
       srr += (double)rv[c] * (double)rv[c];
       double fv[COARSE_NFMAX];
       const int g = coarse_fields(ca, 3 * i + c, n3, fv);
-      zt_add(a, acc, fv, nf, R, g, c, (double)rv[c]);
+      zt_add(a, acc_l, fv, nf, R, g, c, (double)rv[c]);
     }
   }
-  zt_flush(a, acc, nf, R, lo < hi ? coarse_region(ca, (int)lo) : 0, red);
+  zt_flush(a, acc, nf, R, lo < hi ? coarse_region(ca, (int)lo) : 0, red, ca.det);
   __syncthreads();
   zt_store(acc, k, part_z);
   block_sum2(srz, srr, sh);
@@ -688,6 +723,7 @@ static CoarseArgs coarse_args(const amrto_ctx* ctx) {
   CoarseArgs a;
   a.F = ctx->d_cf; a.nf = ctx->coarse_nf; a.R = ctx->coarse_R; a.region = ctx->d_region;
   a.geo = ctx->coarse_affine_only ? ctx->d_cgeo : nullptr;
+  a.det = ctx->deterministic ? 1 : 0;
   return a;
 }
 
