@@ -184,7 +184,7 @@ def main():
         copy_calibration(torch)
         return
     if args.amr_vs_uniform_only:
-        print(json.dumps(amr_vs_uniform(torch, binding, synth)), flush=True)
+        print(json.dumps({f"r{r}": amr_vs_uniform(torch, binding, synth, r) for r in (1.5, 3.0)}), flush=True)
         return
     if args.c4_only:
         print(json.dumps(c4_simp(torch, binding, synth, tuple(int(r) for r in args.c4_regions.split(",")))),
@@ -378,7 +378,7 @@ def main():
         c4 = c4_simp(torch, binding, synth, c4_regions)
 
     # --- AMR against the uniform fine mesh (paper's trigger, design difference)
-    avu = None if args.no_amr_vs_uniform else amr_vs_uniform(torch, binding, synth)
+    avu = None if args.no_amr_vs_uniform else {f"r{r}": amr_vs_uniform(torch, binding, synth, r) for r in (1.5, 3.0)}
 
     # --- the 2-D variant: 256 x 128 Q4 cantilever, uniform and adaptive
     p2d = None if args.no_2d else plane_2d(torch, binding)
@@ -541,7 +541,7 @@ def solve_c5(torch, binding, synth, dev):
     return out
 
 
-def amr_vs_uniform(torch, binding, synth):
+def amr_vs_uniform(torch, binding, synth, r=1.5):
     """The paper's AMR-against-uniform comparison on a synthetic cantilever:
     the same SIMP loop (multigrid-preconditioned CG to 1e-8 from the previous
     displacement, Eq. (5) filter, OC) on the fixed uniform 128x32x32 mesh and
@@ -551,9 +551,10 @@ def amr_vs_uniform(torch, binding, synth):
     run the octree operator kernels and the same multigrid options.  Reports
     sizes, iterations, solve time, the first step whose design change fell
     below 0.01, the final compliances and the design difference D of
-    Eq. (10) between the final designs (also every 50 steps)."""
+    Eq. (10) between the final designs (also every 50 steps).  r is the
+    filter and refinement radius in finest cells."""
     from paper_1009_4975_amd.simp import AdaptiveSIMP
-    case = synth.amr_vs_uniform()
+    case = synth.amr_vs_uniform(r=r)
     ex = case.extra
     sims, recs = {}, {"uniform": [], "amr": []}
     for name, base, L, rule in (("uniform", case.dims, 0, "never"), ("amr", case.base, case.max_level, "paper")):
@@ -595,7 +596,7 @@ def amr_vs_uniform(torch, binding, synth):
                          volfrac=ex["volfrac"], rmin=ex["rmin"], r_amr=ex["r_amr"], steps=ex["steps"],
                          solver="fp64 multigrid-PCG, 1e-8", multigrid=dict(MG_OPTS),
                          p_continuation=ex.get("p_continuation"))
-    log(f"[bench] AMR vs uniform ({ex['steps']} steps): uniform {out['uniform']['solve_ms']} ms solve, "
+    log(f"[bench] AMR vs uniform (r = {r}, {ex['steps']} steps): uniform {out['uniform']['solve_ms']} ms solve, "
         f"{out['uniform']['pcg_iters']} its, {out['uniform']['dofs_mean']} DOFs mean, c {out['uniform']['final_compliance']:.4f}; "
         f"AMR {out['amr']['solve_ms']} ms, {out['amr']['pcg_iters']} its, {out['amr']['dofs_mean']} DOFs mean, "
         f"{out['amr']['adaptations']} adapts, c {out['amr']['final_compliance']:.4f}; "

@@ -729,6 +729,31 @@ __global__ __launch_bounds__(chunk_threads(PREC, COARSE)) void k_apply_chunks(UA
       if (COARSE) gv[r] = a.geo[gn[r]];
     }
   }
+  // Chebyshev smoothing step (plain FP64 pass): the owned rows' r, D^-1 and
+  // x, and the step's interval, are requested with the staged vector, so the
+  // store phase does not wait on them (each owned row is read and written by
+  // its own thread only)
+  constexpr bool CHEB = !FUSED && PREC == P_F64;
+  double cr[CHEB ? NPT : 1][3], cdi[CHEB ? NPT : 1][3], cxo[CHEB ? NPT : 1][3];
+  double c_sigma = 1.0, c_delta = 1.0, c_theta = 1.0;
+  if (CHEB && a.cheb_mode) {
+    c_sigma = a.cheb_scal[MS_SIGMA];
+    c_delta = a.cheb_scal[MS_DELTA];
+    c_theta = a.cheb_scal[MS_THETA];
+    const double* __restrict__ dinv = (const double*)a.dinv;
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+      const int t = tid + NT * r;
+      const long g = 3L * (t < nown ? gn[r] : 0);
+#pragma unroll
+      for (int c3 = 0; c3 < 3; ++c3) {
+        const bool own = t < nown;
+        cr[r][c3] = own ? a.cheb_r[g + c3] : 0.0;
+        cdi[r][c3] = own && a.cheb_mode != 2 ? dinv[g + c3] : 0.0;
+        cxo[r][c3] = own && a.cheb_mode != 3 ? a.cheb_x[g + c3] : 0.0;
+      }
+    }
+  }
   VT cep[EPT];
 #pragma unroll
   for (int r = 0; r < EPT; ++r) cep[r] = coef[eel[r]];
@@ -922,14 +947,13 @@ __global__ __launch_bounds__(chunk_threads(PREC, COARSE)) void k_apply_chunks(UA
   VT qk[COARSE ? NPT : 1][3];  // q of the owned regular nodes (coarse recurrence)
   // Chebyshev coefficients of this step: rho_s from rho_0 = 1 / sigma
   double ch_a = 0.0, ch_c = 0.0, ch_t = 1.0;
-  if (!FUSED && a.cheb_mode) {
-    const double sigma = a.cheb_scal[MS_SIGMA], delta = a.cheb_scal[MS_DELTA];
-    double rho = 1.0 / sigma;
-    for (int s = 0; s < a.cheb_step; ++s) rho = 1.0 / (2.0 * sigma - rho);
-    const double rho1 = 1.0 / (2.0 * sigma - rho);
+  if (CHEB && a.cheb_mode) {
+    double rho = 1.0 / c_sigma;
+    for (int s = 0; s < a.cheb_step; ++s) rho = 1.0 / (2.0 * c_sigma - rho);
+    const double rho1 = 1.0 / (2.0 * c_sigma - rho);
     ch_a = rho1 * rho;
-    ch_c = 2.0 * rho1 / delta;
-    ch_t = a.cheb_scal[MS_THETA];
+    ch_c = 2.0 * rho1 / c_delta;
+    ch_t = c_theta;
   }
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
@@ -945,7 +969,7 @@ __global__ __launch_bounds__(chunk_threads(PREC, COARSE)) void k_apply_chunks(UA
         if (FUSED) {
           PN[g + comp] = 0;
           Y[g + comp] = 0;
-        } else if (a.cheb_mode) {
+        } else if (CHEB && a.cheb_mode) {
           if (a.cheb_mode != 2) Y[g + comp] = 0;
         } else {
           Y[g + comp] = X[g + comp];
@@ -963,19 +987,16 @@ __global__ __launch_bounds__(chunk_threads(PREC, COARSE)) void k_apply_chunks(UA
         Y[g + comp] = q;
         dot += (double)pn * (double)q;
         if (COARSE) qk[r][comp] = q;
-      } else if (a.cheb_mode) {
+      } else if (CHEB && a.cheb_mode) {
         // constrained-form vectors are zero at supported DOFs: q = 0 there
         const double q = fixed ? 0.0 : (double)acc, dv = (double)xs[t * 3 + comp];
-        const double* __restrict__ dinv = (const double*)a.dinv;
+        const double rv = cr[r][comp] - q;
+        a.cheb_r[g + comp] = rv;
         if (a.cheb_mode == 3) {
-          const double rv = a.cheb_r[g + comp] - q;
-          a.cheb_r[g + comp] = rv;
-          Y[g + comp] = (VT)(dinv[g + comp] * rv / ch_t);
+          Y[g + comp] = (VT)(cdi[r][comp] * rv / ch_t);
         } else {
-          a.cheb_x[g + comp] += dv;
-          const double rv = a.cheb_r[g + comp] - q;
-          a.cheb_r[g + comp] = rv;
-          if (a.cheb_mode == 1) Y[g + comp] = (VT)(ch_a * dv + ch_c * dinv[g + comp] * rv);
+          a.cheb_x[g + comp] = cxo[r][comp] + dv;
+          if (a.cheb_mode == 1) Y[g + comp] = (VT)(ch_a * dv + ch_c * cdi[r][comp] * rv);
         }
       } else {
         Y[g + comp] = fixed ? X[g + comp] : acc;

@@ -4,10 +4,11 @@
 //
 // Network: n_layers 3x3x3 convolutions (stride 1, zero padding 1) with ReLU
 // between layers and none after the last.  Activations (B, C, Z, Y, X),
-// weights (Cout, Cin, 3, 3, 3).  The grids are small (tens of thousands of
-// cells), so the convolutions are direct: one thread per output value for the
-// forward and data-gradient passes, one workgroup per weight for the
-// weight-gradient reduction (deterministic tree sums).
+// weights (Cout, Cin, 3, 3, 3).  The convolutions are direct and tiled: a
+// workgroup stages a halo tile of its sample in LDS and every thread keeps
+// several output channels in registers (forward and data gradient); the weight
+// gradient sums per workgroup in registers and then over workgroups in a fixed
+// order (deterministic).
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -31,6 +32,9 @@ struct amrto_net {
   float* d_tmp0 = nullptr;   // gradient buffers (max activation size)
   float* d_tmp1 = nullptr;
   double* d_red = nullptr;
+  float* d_wpart = nullptr;  // weight-gradient partial rows (wrows x the largest layer's parameter count)
+  int wrows = 0;
+  float* d_wt = nullptr;     // one layer's weights arranged for the tiled convolution
   std::string err;
   int fail(int code, const std::string& m) {
     err = m;
@@ -44,86 +48,228 @@ __device__ __forceinline__ bool in_grid(int z, int y, int x, int Z, int Y, int X
   return z >= 0 && z < Z && y >= 0 && y < Y && x >= 0 && x < X;
 }
 
-// out[n, o, p] = b[o] + sum_{i, d} w[o, i, d] in[n, i, p + d - 1]; optional ReLU
-__global__ __launch_bounds__(256) void k_conv_fwd(const float* __restrict__ in, const float* __restrict__ w,
-                                                  const float* __restrict__ b, float* __restrict__ out, int B,
-                                                  int Ci, int Co, int Z, int Y, int X, int relu) {
-  const long V = (long)Z * Y * X;
-  const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (idx >= (long)B * Co * V) return;
-  const long p = idx % V;
-  const int o = (int)((idx / V) % Co), n = (int)(idx / (V * Co));
-  const int x = p % X, y = (p / X) % Y, z = (int)(p / ((long)X * Y));
-  float acc = b[o];
-  for (int i = 0; i < Ci; ++i) {
-    const float* src = in + ((long)n * Ci + i) * V;
-    const float* wk = w + ((long)o * Ci + i) * 27;
-#pragma unroll
-    for (int d = 0; d < 27; ++d) {
-      const int zz = z + d / 9 - 1, yy = y + (d / 3) % 3 - 1, xx = x + d % 3 - 1;
-      if (in_grid(zz, yy, xx, Z, Y, X)) acc = fmaf(wk[d], src[((long)zz * Y + yy) * X + xx], acc);
+// ---------------------------------------------------------------- convolutions
+// Tiled direct convolutions.  A workgroup of 256 threads owns an 8x8x4 tile
+// of output positions (one per thread) of one sample and stages the input
+// channels over the tile plus its one-cell halo in LDS, CG channels at a time
+// (zero outside the grid: the zero padding).  The weights are the same for
+// every thread of the workgroup and are read as uniform values; each thread
+// keeps CG output channels in registers, so every staged value feeds CG
+// multiply-adds.  Offsets d = (dz, dy, dx) + 1 in 0..2 run as d = 9 dz + 3 dy +
+// dx, and off(d) = (dz - 1, dy - 1, dx - 1).
+constexpr int CT_X = 8, CT_Y = 8, CT_Z = 4, CT_N = CT_X * CT_Y * CT_Z;  // output tile
+constexpr int CH_X = CT_X + 2, CH_Y = CT_Y + 2, CH_Z = CT_Z + 2;
+constexpr int CH_N = CH_X * CH_Y * CH_Z;  // staged tile with halo (600)
+constexpr int CH_S = CH_N + 1;            // channel stride in LDS (odd: channels fall in different banks)
+constexpr int CG = 16;                    // channels staged / outputs per thread at a time
+constexpr int CGS = CT_N + 1;             // gradient-tile channel stride in LDS
+static_assert(CT_N == 256, "one output position per thread");
+
+struct ConvGrid {
+  int Z, Y, X, tx, ty, tz;  // grid and tiles per axis
+};
+
+__device__ __forceinline__ int halo_off(int d) { return ((d / 9) * CH_Y + (d / 3) % 3) * CH_X + d % 3; }
+
+// channels [c0, c0 + CG) of src (sample n, C channels) over the halo tile whose
+// first cell is (x0 - 1, y0 - 1, z0 - 1) into s; zero outside the grid and for
+// c >= C; with mask (same shape as src) values whose mask is not > 0 are zero
+// (the ReLU derivative)
+__device__ __forceinline__ void stage_halo(const float* __restrict__ src, const float* __restrict__ mask, int n,
+                                           int C, int c0, const ConvGrid& G, int z0, int y0, int x0, float* s) {
+  const long V = (long)G.Z * G.Y * G.X;
+  for (int k = threadIdx.x; k < CG * CH_N; k += blockDim.x) {
+    const int c = k / CH_N, h = k - c * CH_N;
+    const int hx = h % CH_X, hy = (h / CH_X) % CH_Y, hz = h / (CH_X * CH_Y);
+    const int x = x0 - 1 + hx, y = y0 - 1 + hy, z = z0 - 1 + hz;
+    float v = 0.f;
+    if (c0 + c < C && in_grid(z, y, x, G.Z, G.Y, G.X)) {
+      const long q = ((long)n * C + c0 + c) * V + ((long)z * G.Y + y) * G.X + x;
+      v = src[q];
+      if (mask && !(mask[q] > 0.f)) v = 0.f;
     }
+    s[c * CH_S + h] = v;
   }
-  out[idx] = relu ? fmaxf(acc, 0.f) : acc;
 }
 
-// din[n, i, p] = sum_{o, d} w[o, i, d] g[n, o, p - d + 1], g masked by ReLU of `post` (if given)
-__global__ __launch_bounds__(256) void k_conv_bwd_data(const float* __restrict__ g, const float* __restrict__ post,
-                                                       const float* __restrict__ w, float* __restrict__ din, int B,
-                                                       int Ci, int Co, int Z, int Y, int X) {
-  const long V = (long)Z * Y * X;
-  const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (idx >= (long)B * Ci * V) return;
-  const long p = idx % V;
-  const int i = (int)((idx / V) % Ci), n = (int)(idx / (V * Ci));
-  const int x = p % X, y = (p / X) % Y, z = (int)(p / ((long)X * Y));
-  float acc = 0.f;
-  for (int o = 0; o < Co; ++o) {
-    const float* go = g + ((long)n * Co + o) * V;
-    const float* po = post ? post + ((long)n * Co + o) * V : nullptr;
-    const float* wk = w + ((long)o * Ci + i) * 27;
+// Weights of one layer rearranged for k_conv_tiled: wt[og][c][d][16] holds, for
+// output group og (16 outputs, zero beyond Cd) and staged channel c < Cs,
+//   FWD: w[o, c, d]       (o = 16 og + k, Cs = Cin, Cd = Cout)
+//   BWD: w[c, i, 26 - d]  (i = 16 og + k, Cs = Cout, Cd = Cin),
+// so the 16 weights of a tap are contiguous and every thread of a workgroup
+// reads the same ones (uniform loads into scalar registers).
+template <bool BWD>
+__global__ __launch_bounds__(256) void k_conv_wt(const float* __restrict__ w, float* __restrict__ wt, int Cs, int Cd) {
+  const int n_og = (Cd + CG - 1) / CG;
+  const long n = (long)n_og * Cs * 27 * CG;
+  const long j = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int k = (int)(j % CG), d = (int)((j / CG) % 27), c = (int)((j / (CG * 27)) % Cs), og = (int)(j / ((long)CG * 27 * Cs));
+  const int o = og * CG + k;
+  float v = 0.f;
+  if (o < Cd) v = BWD ? w[((long)c * Cd + o) * 27 + 26 - d] : w[((long)o * Cs + c) * 27 + d];
+  wt[j] = v;
+}
+
+// FWD (BWD = false): dst[n, o, p] = bias[o] + sum_{i < Cs, d} w[o, i, d] src[n, i, p + off(d)],
+//   then ReLU if relu (Cs = Cin, Cd = Cout).
+// BWD: dst[n, i, p] = sum_{o < Cs, d} w[o, i, d] srcm[n, o, p - off(d)]
+//   = sum_{o, d} w[o, i, 26 - d] srcm[n, o, p + off(d)], srcm = src masked by mask
+//   (Cs = Cout, Cd = Cin): the data gradient through the ReLU of the layer's output.
+// wt: the weights as k_conv_tiled<BWD> arranges them.  Grid: (tiles, ceil(Cd / CG), batch).
+template <bool BWD>
+__global__ __launch_bounds__(256) void k_conv_tiled(const float* __restrict__ src, const float* __restrict__ mask,
+                                                    const float* __restrict__ wt, const float* __restrict__ bias,
+                                                    float* __restrict__ dst, int Cs, int Cd, ConvGrid G, int relu) {
+  __shared__ float s[CG * CH_S];
+  const int tile = blockIdx.x, o0 = blockIdx.y * CG, n = blockIdx.z;
+  const int x0 = (tile % G.tx) * CT_X, y0 = ((tile / G.tx) % G.ty) * CT_Y, z0 = (tile / (G.tx * G.ty)) * CT_Z;
+  const int lx = threadIdx.x % CT_X, ly = (threadIdx.x / CT_X) % CT_Y, lz = threadIdx.x / (CT_X * CT_Y);
+  const int hb = (lz * CH_Y + ly) * CH_X + lx;
+  const float* __restrict__ wg = wt + (long)blockIdx.y * Cs * 27 * CG;
+  float acc[CG];
 #pragma unroll
-    for (int d = 0; d < 27; ++d) {
-      const int zz = z - (d / 9 - 1), yy = y - ((d / 3) % 3 - 1), xx = x - (d % 3 - 1);
-      if (in_grid(zz, yy, xx, Z, Y, X)) {
-        const long q = ((long)zz * Y + yy) * X + xx;
-        if (!po || po[q] > 0.f) acc = fmaf(wk[d], go[q], acc);
+  for (int oo = 0; oo < CG; ++oo) acc[oo] = 0.f;
+  for (int c0 = 0; c0 < Cs; c0 += CG) {
+    __syncthreads();  // the previous group has been read
+    stage_halo(src, BWD ? mask : nullptr, n, Cs, c0, G, z0, y0, x0, s);
+    __syncthreads();
+    const int cn = min(CG, Cs - c0);
+    for (int c = 0; c < cn; ++c) {
+      // one z plane of taps (9) per step
+#pragma unroll 1
+      for (int dz = 0; dz < 3; ++dz) {
+        const float* sc = s + c * CH_S + hb + dz * CH_X * CH_Y;
+        const float* wc = wg + ((long)(c0 + c) * 27 + dz * 9) * CG;
+#pragma unroll
+        for (int d = 0; d < 9; ++d) {
+          const float v = sc[(d / 3) * CH_X + d % 3];
+#pragma unroll
+          for (int oo = 0; oo < CG; ++oo) acc[oo] = fmaf(wc[d * CG + oo], v, acc[oo]);
+        }
       }
     }
   }
-  din[idx] = acc;
+  const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+  if (!in_grid(z, y, x, G.Z, G.Y, G.X)) return;
+  const long V = (long)G.Z * G.Y * G.X, p = ((long)z * G.Y + y) * G.X + x;
+#pragma unroll
+  for (int oo = 0; oo < CG; ++oo)
+    if (o0 + oo < Cd) {
+      float v = acc[oo] + (BWD ? 0.f : bias[o0 + oo]);
+      if (relu) v = fmaxf(v, 0.f);
+      dst[((long)n * Cd + o0 + oo) * V + p] = v;
+    }
 }
 
-// dw[o, i, d] = sum_{n, p} g[n, o, p] in[n, i, p + d - 1]; db[o] = sum g (one block per weight)
-__global__ __launch_bounds__(256) void k_conv_bwd_weight(const float* __restrict__ g, const float* __restrict__ post,
-                                                         const float* __restrict__ in, float* __restrict__ dw,
-                                                         float* __restrict__ db, int B, int Ci, int Co, int Z,
-                                                         int Y, int X) {
-  __shared__ double sh[8];
-  const int wid = blockIdx.x;  // o * (Ci * 27 + 1) + (i * 27 + d) or the bias slot
-  const int per = Ci * 27 + 1;
-  const int o = wid / per, r = wid % per;
-  const bool bias = r == Ci * 27;
-  const int i = bias ? 0 : r / 27, d = bias ? 0 : r % 27;
-  const int oz = d / 9 - 1, oy = (d / 3) % 3 - 1, ox = d % 3 - 1;
-  const long V = (long)Z * Y * X;
-  double acc = 0.0;
-  for (long t = threadIdx.x; t < (long)B * V; t += blockDim.x) {
-    const int n = (int)(t / V);
-    const long p = t % V;
-    const long gi = ((long)n * Co + o) * V + p;
-    float gv = g[gi];
-    if (post && !(post[gi] > 0.f)) gv = 0.f;
-    if (bias) { acc += gv; continue; }
-    const int x = p % X, y = (p / X) % Y, z = (int)(p / ((long)X * Y));
-    const int zz = z + oz, yy = y + oy, xx = x + ox;
-    if (in_grid(zz, yy, xx, Z, Y, X)) acc += (double)gv * in[((long)n * Ci + i) * V + ((long)zz * Y + yy) * X + xx];
+// Weight gradient, partial sums per workgroup:
+//   dw[o, i, d] = sum_{n, p} gm[n, o, p] in[n, i, p + off(d)],  db[o] = sum gm[n, o, p],
+// gm = g masked by the ReLU of the layer's output.  Workgroup (b, combo) walks
+// the (sample, tile) pairs b, b + gridDim.x, ... for the channel groups of its
+// combo (input group ig, output group og); thread (i, oq, pg) = tid (16, 4, 4)
+// keeps 4 outputs x 27 offsets of input channel i over the 64 positions of
+// group pg.  The four position groups (one per wave) are folded in wave order
+// through LDS, and row b of part receives this workgroup's share of the layer's
+// P = Co Ci 27 + Co gradient entries (k_wgrad_reduce sums the rows in order).
+__global__ __launch_bounds__(256) void k_conv_wgrad(const float* __restrict__ g, const float* __restrict__ post,
+                                                    const float* __restrict__ in, float* __restrict__ part, int B,
+                                                    int Ci, int Co, ConvGrid G, long P) {
+  __shared__ float s_in[CG * CH_S];
+  __shared__ float s_g[CG * CGS];
+  static_assert(CG * CH_S >= 64 * 4 * 27 + 64 * 4, "the fold buffer fits in s_in");
+  const int n_ig = (Ci + CG - 1) / CG;
+  const int ig = blockIdx.y % n_ig, og = blockIdx.y / n_ig;
+  const int i0 = ig * CG, o0 = og * CG;
+  const int tid = threadIdx.x, i = tid & 15, oq = (tid >> 4) & 3, pg = tid >> 6;
+  const int n_tiles = G.tx * G.ty * G.tz;
+  const long V = (long)G.Z * G.Y * G.X;
+  float acc[4][27], accb[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    accb[k] = 0.f;
+#pragma unroll
+    for (int d = 0; d < 27; ++d) acc[k][d] = 0.f;
   }
-  acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) {
-    if (bias) db[o] = (float)acc;
-    else dw[((long)o * Ci + i) * 27 + d] = (float)acc;
+  for (int t = blockIdx.x; t < n_tiles * B; t += gridDim.x) {
+    const int n = t / n_tiles, tile = t - n * n_tiles;
+    const int x0 = (tile % G.tx) * CT_X, y0 = ((tile / G.tx) % G.ty) * CT_Y, z0 = (tile / (G.tx * G.ty)) * CT_Z;
+    __syncthreads();
+    stage_halo(in, nullptr, n, Ci, i0, G, z0, y0, x0, s_in);
+    for (int k = tid; k < CG * CT_N; k += blockDim.x) {
+      const int c = k / CT_N, q = k - c * CT_N;
+      const int x = x0 + q % CT_X, y = y0 + (q / CT_X) % CT_Y, z = z0 + q / (CT_X * CT_Y);
+      float v = 0.f;
+      if (o0 + c < Co && in_grid(z, y, x, G.Z, G.Y, G.X)) {
+        const long gi = ((long)n * Co + o0 + c) * V + ((long)z * G.Y + y) * G.X + x;
+        v = g[gi];
+        if (post && !(post[gi] > 0.f)) v = 0.f;
+      }
+      s_g[c * CGS + q] = v;
+    }
+    __syncthreads();
+    for (int q = pg * 64; q < pg * 64 + 64; ++q) {
+      const int hb = ((q / (CT_X * CT_Y)) * CH_Y + (q / CT_X) % CT_Y) * CH_X + q % CT_X;
+      float gv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        gv[k] = s_g[(oq * 4 + k) * CGS + q];
+        accb[k] += gv[k];
+      }
+      const float* sc = s_in + i * CH_S + hb;
+#pragma unroll
+      for (int d = 0; d < 27; ++d) {
+        const float v = sc[halo_off(d)];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k][d] = fmaf(gv[k], v, acc[k][d]);
+      }
+    }
   }
+  // fold the four position groups in wave order: slot (i, oq) holds 4 x 27
+  // weight sums, then 4 bias sums
+  float* red = s_in;
+  const int slot = i * 4 + oq;
+  for (int wv = 0; wv < 4; ++wv) {
+    __syncthreads();
+    if (pg == wv) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int d = 0; d < 27; ++d) {
+          float* r = red + slot * 108 + k * 27 + d;
+          *r = (wv ? *r : 0.f) + acc[k][d];
+        }
+        float* rb = red + 64 * 108 + slot * 4 + k;
+        *rb = (wv ? *rb : 0.f) + accb[k];
+      }
+    }
+  }
+  __syncthreads();
+  float* row = part + (long)blockIdx.x * P;
+  for (int e = tid; e < 64 * 108; e += blockDim.x) {
+    const int sl = e / 108, r = e - sl * 108, k = r / 27, d = r - k * 27;
+    const int ii = i0 + sl / 4, o = o0 + (sl % 4) * 4 + k;
+    if (ii < Ci && o < Co) row[((long)o * Ci + ii) * 27 + d] = red[e];
+  }
+  if (ig == 0 && tid < 16) {  // bias: the slots of input channel 0 carry the sums of g
+    const int o = o0 + tid;
+    if (o < Co) row[(long)Co * Ci * 27 + o] = red[64 * 108 + (tid / 4) * 4 + tid % 4];
+  }
+}
+
+// out[j] = sum over rows b < nrows of part[b P + j], in a fixed order: a
+// workgroup takes 64 entries; its four waves sum the rows b = w, w + 4, ...
+// (FP64) and the four sums are added in wave order.
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int nrows, long P,
+                                                      float* __restrict__ out) {
+  __shared__ double sh[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const long j = blockIdx.x * 64L + lane;
+  double s = 0.0;
+  if (j < P)
+    for (int b = wv; b < nrows; b += 4) s += (double)part[(long)b * P + j];
+  sh[wv][lane] = s;
+  __syncthreads();
+  if (wv == 0 && j < P) out[j] = (float)(((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane]);
 }
 
 // masked MSE: partial sums of mask (p - t)^2 and of mask; dpred = 2 mask (p - t) / sum(mask)
@@ -257,6 +403,15 @@ using namespace amrto;
     if (e_ != hipSuccess) return net->fail(AMRTO_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+static ConvGrid conv_grid(const amrto_net* net) {
+  ConvGrid G;
+  G.Z = net->gz; G.Y = net->gy; G.X = net->gx;
+  G.tx = (net->gx + CT_X - 1) / CT_X;
+  G.ty = (net->gy + CT_Y - 1) / CT_Y;
+  G.tz = (net->gz + CT_Z - 1) / CT_Z;
+  return G;
+}
+
 extern "C" {
 
 int amrto_net_create(amrto_net** out, int device, void* stream, int32_t n_layers, const int32_t* channels,
@@ -291,6 +446,17 @@ int amrto_net_create(amrto_net** out, int device, void* stream, int32_t n_layers
             hipMalloc((void**)&net->d_tmp0, (long)max_batch * cmax * V * 4) == hipSuccess &&
             hipMalloc((void**)&net->d_tmp1, (long)max_batch * cmax * V * 4) == hipSuccess &&
             hipMalloc((void**)&net->d_red, 4 * RED_BLOCKS * sizeof(double)) == hipSuccess;
+  // weight-gradient partials: up to 512 rows, at most 16 M floats in all
+  long pmax = 1;
+  for (int l = 0; l < n_layers; ++l) pmax = std::max(pmax, (long)channels[l + 1] * channels[l] * 27 + channels[l + 1]);
+  net->wrows = (int)std::max(1L, std::min(512L, (16L << 20) / pmax));
+  ok = ok && hipMalloc((void**)&net->d_wpart, (long)net->wrows * pmax * 4) == hipSuccess;
+  long wtmax = 1;
+  for (int l = 0; l < n_layers; ++l) {
+    const long a = channels[l], b = channels[l + 1];
+    wtmax = std::max(wtmax, std::max((b + 15) / 16 * 16 * a * 27, (a + 15) / 16 * 16 * b * 27));
+  }
+  ok = ok && hipMalloc((void**)&net->d_wt, wtmax * 4) == hipSuccess;
   for (int l = 0; l <= n_layers && ok; ++l) {
     float* p = nullptr;
     ok = hipMalloc((void**)&p, (long)max_batch * channels[l] * V * 4) == hipSuccess;
@@ -327,6 +493,8 @@ int amrto_net_destroy(amrto_net* net) {
   for (float* p : net->acts)
     if (p) (void)hipFree(p);
   if (net->d_red) (void)hipFree(net->d_red);
+  if (net->d_wpart) (void)hipFree(net->d_wpart);
+  if (net->d_wt) (void)hipFree(net->d_wt);
   delete net;
   return AMRTO_OK;
 }
@@ -382,12 +550,15 @@ int amrto_net_forward(amrto_net* net, const float* in, int32_t batch, float* out
   net->batch = batch;
   NET_HIP(hipMemcpyAsync(net->acts[0], in, (long)batch * net->ch[0] * V * 4, hipMemcpyDeviceToDevice, net->stream));
   for (int l = 0; l < net->L; ++l) {
-    const long n = (long)batch * net->ch[l + 1] * V;
     const float* w = net->d_params + net->woff[l];
     const float* b = w + (long)net->ch[l + 1] * net->ch[l] * 27;
-    hipLaunchKernelGGL(k_conv_fwd, dim3((n + 255) / 256), dim3(256), 0, net->stream, net->acts[l], w, b,
-                       net->acts[l + 1], batch, net->ch[l], net->ch[l + 1], net->gz, net->gy, net->gx,
-                       l + 1 < net->L ? 1 : 0);
+    const ConvGrid G = conv_grid(net);
+    const int Ci = net->ch[l], Co = net->ch[l + 1], n_og = (Co + CG - 1) / CG;
+    const long nwt = (long)n_og * CG * Ci * 27;
+    hipLaunchKernelGGL(k_conv_wt<false>, dim3((unsigned)((nwt + 255) / 256)), dim3(256), 0, net->stream, w, net->d_wt,
+                       Ci, Co);
+    hipLaunchKernelGGL(k_conv_tiled<false>, dim3(G.tx * G.ty * G.tz, n_og, batch), dim3(256), 0, net->stream,
+                       net->acts[l], nullptr, net->d_wt, b, net->acts[l + 1], Ci, Co, G, l + 1 < net->L ? 1 : 0);
   }
   if (net->skip >= 0) {
     const long n = (long)batch * net->ch[net->L] * V;
@@ -413,13 +584,22 @@ int amrto_net_backward(amrto_net* net, const float* dout, float* din) {
     const float* post = l + 1 < net->L ? net->acts[l + 1] : nullptr;  // ReLU mask of this layer's output
     float* w = net->d_params + net->woff[l];
     float* dw = net->d_grads + net->woff[l];
-    hipLaunchKernelGGL(k_conv_bwd_weight, dim3(Co * (Ci * 27 + 1)), dim3(256), 0, net->stream, g, post,
-                       net->acts[l], dw, dw + (long)Co * Ci * 27, B, Ci, Co, net->gz, net->gy, net->gx);
+    const ConvGrid G = conv_grid(net);
+    const long P = (long)Co * Ci * 27 + Co;
+    const int rows = (int)std::min<long>(net->wrows, (long)G.tx * G.ty * G.tz * B);
+    const int combos = ((Ci + CG - 1) / CG) * ((Co + CG - 1) / CG);
+    hipLaunchKernelGGL(k_conv_wgrad, dim3(rows, combos), dim3(256), 0, net->stream, g, post, net->acts[l],
+                       net->d_wpart, B, Ci, Co, G, P);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((P + 63) / 64)), dim3(256), 0, net->stream, net->d_wpart,
+                       rows, P, dw);
     if (l > 0 || din) {
       float* dst = l > 0 ? bufs[l & 1] : din;
-      const long n = (long)B * Ci * V;
-      hipLaunchKernelGGL(k_conv_bwd_data, dim3((n + 255) / 256), dim3(256), 0, net->stream, g, post, w, dst, B, Ci,
-                         Co, net->gz, net->gy, net->gx);
+      const int n_ig = (Ci + CG - 1) / CG;
+      const long nwt = (long)n_ig * CG * Co * 27;
+      hipLaunchKernelGGL(k_conv_wt<true>, dim3((unsigned)((nwt + 255) / 256)), dim3(256), 0, net->stream, w,
+                         net->d_wt, Co, Ci);
+      hipLaunchKernelGGL(k_conv_tiled<true>, dim3(G.tx * G.ty * G.tz, n_ig, B), dim3(256), 0, net->stream, g, post,
+                         net->d_wt, nullptr, dst, Co, Ci, G, 0);
       g = dst;
     }
   }

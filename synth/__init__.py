@@ -238,16 +238,16 @@ def c4(base=(32, 16, 16), max_level: int = 2, volfrac: float = 0.25, iters: int 
 # test: uniform 128x32x32 against an adaptive run whose initial mesh is
 # 64x16x16, one refinement level, volume fraction 0.25).  The test's loads and
 # supports exist only in a figure: the synthetic cantilever BCs stand in.  The
-# filter radius equals the refinement radius (Sec. 6) and is 3 finest cells, so
-# that the filter acts on the initial mesh too (its elements are 2 cells wide;
-# a radius at or below that gives every neighbour weight zero).
+# filter radius equals the refinement radius r (Sec. 6), in finest cells: 1.5,
+# or 3, with which the filter acts on the initial mesh too (its elements are 2
+# cells wide; a radius at or below that gives every neighbour weight zero).
 # --------------------------------------------------------------------------
-def amr_vs_uniform(base=(64, 16, 16), max_level: int = 1, steps: int = 300) -> OctreeCase:
+def amr_vs_uniform(base=(64, 16, 16), max_level: int = 1, steps: int = 300, r: float = 1.5) -> OctreeCase:
     s = 1 << max_level
     dims = tuple(b * s for b in base)
     fixed, load = cantilever_bc(*dims)
     return OctreeCase("cantilever_amr_vs_uniform", tuple(base), max_level, fixed, load,
-                      extra=dict(rho_init=0.25, volfrac=0.25, rmin=3.0, r_amr=3.0, rho_solid=0.5, steps=steps,
+                      extra=dict(rho_init=0.25, volfrac=0.25, rmin=r, r_amr=r, rho_solid=0.5, steps=steps,
                                  min_steps=5, max_steps=10, change_tol=0.01))
 
 
