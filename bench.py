@@ -160,6 +160,8 @@ def main():
     ap.add_argument("--no-amr-vs-uniform", action="store_true", help="skip the AMR against uniform comparison")
     ap.add_argument("--amr-vs-uniform-only", action="store_true", help="only the AMR against uniform comparison")
     ap.add_argument("--c4-only", action="store_true", help="only the 50-iteration adaptive SIMP run")
+    ap.add_argument("--net-only", action="store_true",
+                    help="only the network training rate at C4's sizes (9 pairs, 65x33x33, channels 4-16-16-16-3)")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2-D cantilever (Q4 quadtree) lines")
     ap.add_argument("--2d-only", dest="only_2d", action="store_true", help="only the 2-D cantilever lines")
     ap.add_argument("--mg-roofline-only", action="store_true",
@@ -182,6 +184,9 @@ def main():
     if args.c3_only:
         print(json.dumps(apply_uniform_bandwidth(torch, binding, synth, dev)), flush=True)
         copy_calibration(torch)
+        return
+    if args.net_only:
+        print(json.dumps(net_training_rate(torch, binding)), flush=True)
         return
     if args.amr_vs_uniform_only:
         print(json.dumps({f"r{r}": amr_vs_uniform(torch, binding, synth, r) for r in (1.5, 3.0)}), flush=True)
@@ -379,6 +384,7 @@ def main():
 
     # --- AMR against the uniform fine mesh (paper's trigger, design difference)
     avu = None if args.no_amr_vs_uniform else {f"r{r}": amr_vs_uniform(torch, binding, synth, r) for r in (1.5, 3.0)}
+    net_rate = None if args.no_c4 else net_training_rate(torch, binding)
 
     # --- the 2-D variant: 256 x 128 Q4 cantilever, uniform and adaptive
     p2d = None if args.no_2d else plane_2d(torch, binding)
@@ -402,7 +408,7 @@ def main():
         "solve_iters": int(np.median(iters)), "solve_rel_res": float(max(rel)),
         "solve_variants": variants, "roofline": roofline, "roofline_apply_fp64": roofline_apply,
         "c1_simp_iteration_24x12x12": c1, "c5_bridge_128x64x64": c5,
-        "apply_uniform_192x96x96": c3, "simp_adaptive_bridge": c4, "amr_vs_uniform_cantilever": avu,
+        "apply_uniform_192x96x96": c3, "simp_adaptive_bridge": c4, "network_training": net_rate, "amr_vs_uniform_cantilever": avu,
         "plane_2d_cantilever_256x128": p2d, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -602,6 +608,40 @@ def amr_vs_uniform(torch, binding, synth, r=1.5):
         f"{out['amr']['adaptations']} adapts, c {out['amr']['final_compliance']:.4f}; "
         f"D = {100 * D:.3f} %, time ratio {out['solve_time_ratio_uniform_over_amr']}")
     return out
+
+
+def net_training_rate(torch, binding, epochs=100):
+    """Training epochs (forward, masked MSE, backward, Adam) of the warm-start
+    network at the sizes C4 trains it on: 9 (density, displacement) pairs on
+    the 65x33x33 grid of the 128x64x64 lattice (every second node), channels
+    4-16-16-16-3, synthetic inputs (seed 0).  FLOPs count the convolutions'
+    multiply-adds, forward once and backward twice."""
+    ch, grid, B = [4, 16, 16, 16, 3], (65, 33, 33), 9
+    net = binding.Net(ch, grid, max_batch=16, seed=0)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    shape = (B, 4, grid[2], grid[1], grid[0])
+    X = torch.randn(shape, device="cuda", generator=g)
+    Y = torch.randn((B, 3) + shape[2:], device="cuda", generator=g)
+    out, dout = torch.empty_like(Y), torch.empty_like(Y)
+
+    def epoch(t):
+        net.forward(X, out)
+        net.mse(out, Y, dout)
+        net.backward(dout)
+        net.adam(1e-3, t)
+
+    for t in range(1, 4):
+        epoch(t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(4, 4 + epochs):
+        epoch(t)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / epochs
+    V = grid[0] * grid[1] * grid[2]
+    flop = 3 * sum(2 * B * V * a * c * 27 for a, c in zip(ch[:-1], ch[1:]))
+    log(f"[bench] network training: {ms:.3f} ms per epoch ({flop / ms / 1e9:.1f} TFLOP/s of convolution work)")
+    return dict(ms_per_epoch=round(ms, 4), tflops=round(flop / ms / 1e9, 2), pairs=B, grid=list(grid), channels=ch)
 
 
 def apply_uniform_bandwidth(torch, binding, synth, dev):
