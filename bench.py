@@ -132,7 +132,7 @@ def event_time(torch, fn, reps):
 # multigrid options of the octree solves: two octree levels merged by the first
 # coarsening, Chebyshev degree 1 on the analysis mesh and 2 on the coarse
 # levels over [lambda_max / 50, 1.1 lambda_max]
-MG_OPTS = dict(first=2, ratio=50.0, degree=1, coarse_degree=2)
+MG_OPTS = dict(first=2, ratio=50.0, degree=1, coarse_degree=2, coarse_dofs=700)
 # uniform bricks (C1, C5): degree 2 on every level over [lambda_max / 30, 1.1 lambda_max]
 MG_OPTS_UNIFORM = dict(first=2, ratio=30.0, degree=2, coarse_degree=2)
 

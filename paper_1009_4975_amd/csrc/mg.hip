@@ -522,91 +522,179 @@ __global__ void k_mg_lambda(const double* __restrict__ part, double* __restrict_
 }
 
 // coarsest level: dense A~ from its block rows, identity rows and columns
-// for constrained DOFs; one workgroup
-__global__ __launch_bounds__(1024) void k_mg_coarse_assemble(const int32_t* __restrict__ bptr,
-                                                             const int32_t* __restrict__ bcol,
-                                                             const double* __restrict__ bval,
-                                                             const uint8_t* __restrict__ flag, int nn,
-                                                             double* __restrict__ A) {
-  const int n = 3 * nn;
-  for (long i = threadIdx.x; i < (long)n * n; i += blockDim.x) A[i] = 0.0;
+// for constrained DOFs; one workgroup per node row (its three DOF rows)
+__global__ __launch_bounds__(256) void k_mg_coarse_assemble(const int32_t* __restrict__ bptr,
+                                                            const int32_t* __restrict__ bcol,
+                                                            const double* __restrict__ bval,
+                                                            const uint8_t* __restrict__ flag, int nn,
+                                                            double* __restrict__ A) {
+  const int n = 3 * nn, v = blockIdx.x;
+  for (int e = threadIdx.x; e < 3 * n; e += blockDim.x) {
+    const int I = 3 * v + e / n, J = e % n;
+    A[(long)I * n + J] = (I == J && mg_cons(flag[v], I - 3 * v)) ? 1.0 : 0.0;
+  }
   __syncthreads();
-  for (int v = threadIdx.x; v < nn; v += blockDim.x)
-    for (int k = bptr[v]; k < bptr[v + 1]; ++k)
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) A[(long)(3 * v + i) * n + 3 * bcol[k] + j] = bval[9L * k + 3 * i + j];
-  __syncthreads();
-  for (long i = threadIdx.x; i < (long)n * n; i += blockDim.x) {
-    const int I = (int)(i / n), J = (int)(i % n);
-    const bool ci = mg_cons(flag[I / 3], I % 3), cj = mg_cons(flag[J / 3], J % 3);
-    if (ci || cj) A[i] = (I == J) ? 1.0 : 0.0;
+  const int k0 = bptr[v], nk = bptr[v + 1] - k0;
+  for (int e = threadIdx.x; e < 9 * nk; e += blockDim.x) {
+    const int k = k0 + e / 9, i = (e % 9) / 3, j = e % 3, w = bcol[k];
+    if (!mg_cons(flag[v], i) && !mg_cons(flag[w], j)) A[(long)(3 * v + i) * n + 3 * w + j] = bval[9L * k + 3 * i + j];
   }
 }
 
-// in-place Gauss-Jordan inverse of an SPD matrix (no pivoting); one workgroup
-__global__ __launch_bounds__(1024) void k_mg_invert(double* __restrict__ A, int n) {
-  __shared__ double col[MG_COARSE_MAX], row[MG_COARSE_MAX];
-  for (int k = 0; k < n; ++k) {
-    const double piv = 1.0 / A[(long)k * n + k];
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-      col[j] = A[(long)j * n + k];
-      row[j] = (j == k ? 1.0 : A[(long)k * n + j]) * piv;
-    }
+// In-place inverse of the SPD coarsest matrix (row-major, n x n) by blocked
+// Gauss-Jordan elimination without pivoting (the pivot blocks of an SPD
+// matrix are SPD Schur complements).  For each block k of BGJ rows (the last
+// one may be shorter), with P the inverse of the pivot block A_kk:
+//   A_kk = P;  A_kj = P A_kj (j != k);  A_ij -= A_ik A_kj (i, j != k);
+//   A_ik = -A_ik P (i != k),
+// the block form of the scalar steps a_kk = 1 / a_kk, a_kj /= a_kk,
+// a_ij -= a_ik a_kj, a_ik = -a_ik / a_kk.  One step is four launches (pivot
+// block, row panel, trailing update, column panel), the last three over
+// 64-wide tiles in parallel workgroups.
+constexpr int BGJ = 64;
+constexpr int BGJ_S = BGJ + 1;  // LDS row stride
+
+// pivot block k0: scalar Gauss-Jordan in registers, one workgroup of 256
+// threads; thread (rg, J) = (t / 64, t % 64) holds column J, rows rg + 4 m
+// (m < 16).  Per step s the pivot row and column go through LDS (two buffers
+// alternating by step, so one barrier per step suffices).
+__global__ __launch_bounds__(256) void k_bgj_pivot(double* __restrict__ A, int n, int k0) {
+  __shared__ double rowv[2][BGJ], colv[2][BGJ];
+  const int bs = min(BGJ, n - k0), t = threadIdx.x, J = t & 63, rg = t >> 6;
+  double p[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int I = rg + 4 * m;
+    p[m] = (I < bs && J < bs) ? A[(long)(k0 + I) * n + k0 + J] : 0.0;
+  }
+  // selects rather than branches: every thread runs the same straight code
+  for (int s = 0; s < bs; ++s) {
+    const int b = s & 1, ms = s >> 2;
+    double ps = 0.0;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) ps = (m == ms) ? p[m] : ps;
+    if (rg == (s & 3)) rowv[b][J] = ps;
+    if (J == s)
+#pragma unroll
+      for (int m = 0; m < 16; ++m) colv[b][rg + 4 * m] = p[m];
     __syncthreads();
-    for (long i = threadIdx.x; i < (long)n * n; i += blockDim.x) {
-      const int I = (int)(i / n), J = (int)(i % n);
-      if (I == k) {
-        A[i] = row[J];
-      } else {
-        const double a = (J == k) ? 0.0 : A[i];
-        A[i] = a - col[I] * row[J];
+    const double piv = 1.0 / rowv[b][s];
+    const double rj = (J == s ? 1.0 : rowv[b][J]) * piv;
+    const bool js = J == s;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const double c = colv[b][rg + 4 * m];
+      const double u = fma(-c, rj, js ? 0.0 : p[m]);
+      p[m] = (rg + 4 * m == s) ? rj : u;
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int I = rg + 4 * m;
+    if (I < bs && J < bs) A[(long)(k0 + I) * n + k0 + J] = p[m];
+  }
+}
+
+// C (rows x cols, at most 64 x 64) = X (rows x m) Y (m x cols) from LDS
+// (strides BGJ_S); each of the 256 threads owns a 4 x 4 patch
+__device__ __forceinline__ void bgj_patch(const double* X, const double* Y, int m, double (&c)[4][4]) {
+  const int r0 = (threadIdx.x >> 4) * 4, c0 = (threadIdx.x & 15) * 4;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) c[a][b] = 0.0;
+  for (int q = 0; q < m; ++q) {
+    double x[4], y[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) x[a] = X[(r0 + a) * BGJ_S + q];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) y[b] = Y[q * BGJ_S + c0 + b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) c[a][b] = fma(x[a], y[b], c[a][b]);
+  }
+}
+
+// load the tile of A at (r0, c0) with rows x cols (zero outside) into S
+__device__ __forceinline__ void bgj_load(const double* __restrict__ A, int n, int r0, int c0, int rows, int cols,
+                                         double* S) {
+  for (int e = threadIdx.x; e < BGJ * BGJ; e += blockDim.x) {
+    const int I = e / BGJ, J = e - I * BGJ;
+    S[I * BGJ_S + J] = (I < rows && J < cols) ? A[(long)(r0 + I) * n + c0 + J] : 0.0;
+  }
+}
+
+// row panel: A_kj = P A_kj for the column tiles j != k (grid: one tile each)
+__global__ __launch_bounds__(256) void k_bgj_row(double* __restrict__ A, int n, int k0) {
+  __shared__ double Ps[BGJ * BGJ_S], T[BGJ * BGJ_S];
+  const int j0 = blockIdx.x * BGJ;
+  if (j0 == k0) return;
+  const int bs = min(BGJ, n - k0), w = min(BGJ, n - j0);
+  bgj_load(A, n, k0, k0, bs, bs, Ps);
+  bgj_load(A, n, k0, j0, bs, w, T);
+  __syncthreads();
+  double c[4][4];
+  bgj_patch(Ps, T, bs, c);
+  const int r0 = (threadIdx.x >> 4) * 4, cc0 = (threadIdx.x & 15) * 4;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (r0 + a < bs && cc0 + b < w) A[(long)(k0 + r0 + a) * n + j0 + cc0 + b] = c[a][b];
+}
+
+// trailing update: A_ij -= A_ik A_kj for the tiles i, j != k (grid: nb x nb)
+__global__ __launch_bounds__(256) void k_bgj_trail(double* __restrict__ A, int n, int k0) {
+  __shared__ double X[BGJ * BGJ_S], Y[BGJ * BGJ_S];
+  const int i0 = blockIdx.y * BGJ, j0 = blockIdx.x * BGJ;
+  if (i0 == k0 || j0 == k0) return;
+  const int bs = min(BGJ, n - k0), h = min(BGJ, n - i0), w = min(BGJ, n - j0);
+  bgj_load(A, n, i0, k0, h, bs, X);
+  bgj_load(A, n, k0, j0, bs, w, Y);
+  __syncthreads();
+  double c[4][4];
+  bgj_patch(X, Y, bs, c);
+  const int r0 = (threadIdx.x >> 4) * 4, cc0 = (threadIdx.x & 15) * 4;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (r0 + a < h && cc0 + b < w) {
+        double* e = A + (long)(i0 + r0 + a) * n + j0 + cc0 + b;
+        *e -= c[a][b];
       }
-    }
-    __syncthreads();
-  }
 }
 
-// the same inverse with the matrix in registers (n <= MG_REG_N): thread t
-// holds entries t, t + 1024, ... with their row and column; per pivot the
-// pivot row and column go through LDS, so each step costs two barriers and
-// no memory round trip
-constexpr int MG_REG_N = 144;
-constexpr int MG_REG_M = (MG_REG_N * MG_REG_N + 1023) / 1024;
-__global__ __launch_bounds__(1024) void k_mg_invert_reg(double* __restrict__ A, int n) {
-  __shared__ double col[MG_REG_N], row[MG_REG_N];
-  const int t = threadIdx.x;
-  const int nn = n * n;
-  double a[MG_REG_M];
-  int rc[MG_REG_M];  // row << 16 | column, -1: no entry
+// column panel: A_ik = -A_ik P for the row tiles i != k (after the trailing
+// update, which read the old A_ik)
+__global__ __launch_bounds__(256) void k_bgj_col(double* __restrict__ A, int n, int k0) {
+  __shared__ double X[BGJ * BGJ_S], Ps[BGJ * BGJ_S];
+  const int i0 = blockIdx.x * BGJ;
+  if (i0 == k0) return;
+  const int bs = min(BGJ, n - k0), h = min(BGJ, n - i0);
+  bgj_load(A, n, i0, k0, h, bs, X);
+  bgj_load(A, n, k0, k0, bs, bs, Ps);
+  __syncthreads();
+  double c[4][4];
+  bgj_patch(X, Ps, bs, c);
+  const int r0 = (threadIdx.x >> 4) * 4, cc0 = (threadIdx.x & 15) * 4;
 #pragma unroll
-  for (int m = 0; m < MG_REG_M; ++m) {
-    const int e = t + 1024 * m;
-    a[m] = e < nn ? A[e] : 0.0;
-    rc[m] = e < nn ? ((e / n) << 16) | (e - (e / n) * n) : -1;
-  }
-  for (int k = 0; k < n; ++k) {
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int m = 0; m < MG_REG_M; ++m) {
-      if (rc[m] < 0) continue;
-      const int I = rc[m] >> 16, J = rc[m] & 0xffff;
-      if (I == k) row[J] = a[m];
-      if (J == k) col[I] = a[m];
-    }
-    __syncthreads();
-    const double piv = 1.0 / row[k];
-#pragma unroll
-    for (int m = 0; m < MG_REG_M; ++m) {
-      if (rc[m] < 0) continue;
-      const int I = rc[m] >> 16, J = rc[m] & 0xffff;
-      const double rj = (J == k ? 1.0 : row[J]) * piv;
-      a[m] = (I == k) ? rj : ((J == k) ? 0.0 : a[m]) - col[I] * rj;
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int m = 0; m < MG_REG_M; ++m) {
-    const int e = t + 1024 * m;
-    if (e < nn) A[e] = a[m];
+    for (int b = 0; b < 4; ++b)
+      if (r0 + a < h && cc0 + b < bs) A[(long)(i0 + r0 + a) * n + k0 + cc0 + b] = -c[a][b];
+}
+
+static void bgj_invert(hipStream_t st, double* A, int n) {
+  const int nb = (n + BGJ - 1) / BGJ;
+  for (int k = 0; k < nb; ++k) {
+    const int k0 = k * BGJ;
+    hipLaunchKernelGGL(k_bgj_pivot, dim3(1), dim3(256), 0, st, A, n, k0);
+    if (nb == 1) break;
+    hipLaunchKernelGGL(k_bgj_row, dim3(nb), dim3(256), 0, st, A, n, k0);
+    hipLaunchKernelGGL(k_bgj_trail, dim3(nb, nb), dim3(256), 0, st, A, n, k0);
+    hipLaunchKernelGGL(k_bgj_col, dim3(nb), dim3(256), 0, st, A, n, k0);
   }
 }
 
@@ -946,12 +1034,9 @@ int mg_numeric(amrto_ctx* ctx) {
   }
   MgLevel& C = g->lv[g->nlev - 1];
   const int n = 3 * C.nn;
-  hipLaunchKernelGGL(k_mg_coarse_assemble, dim3(1), dim3(1024), 0, ctx->stream, C.bptr, C.bcol, C.bval, C.flag,
+  hipLaunchKernelGGL(k_mg_coarse_assemble, dim3(C.nn), dim3(256), 0, ctx->stream, C.bptr, C.bcol, C.bval, C.flag,
                      C.nn, C.Ainv);
-  if (n <= MG_REG_N)
-    hipLaunchKernelGGL(k_mg_invert_reg, dim3(1), dim3(1024), 0, ctx->stream, C.Ainv, n);
-  else
-    hipLaunchKernelGGL(k_mg_invert, dim3(1), dim3(1024), 0, ctx->stream, C.Ainv, n);
+  bgj_invert(ctx->stream, C.Ainv, n);
   if (hipGetLastError() != hipSuccess) return ctx->fail(AMRTO_EHIP, "multigrid coarse set-up");
   ctx->mg_valid = true;
   return AMRTO_OK;
