@@ -46,6 +46,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_octree_c2_traffic.txt")
 PASS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "op_pass_octree_c2_fp32_coarse_block3_traffic.txt")
 MG_SOURCES = APPLY_SOURCES + ("paper_1009_4975_amd/csrc/mg.hip",)
 MG_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mg_level0_pass_octree_c2_traffic.txt")
+MG_COARSE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mg_coarse_pass_octree_c2_traffic.txt")
+MG_COARSE_BYTES_RULE = ("a coarse-level smoothing pass must move, per 3x3 block of the level's assembled operator, "
+                        "its 9 FP64 values and its column index (76 B), and per node the row pointer (4 B), the "
+                        "support flags (1 B), the direction d read, the iterate x and the residual r read and "
+                        "written, the diagonal inverse read and the next direction written (168 B)")
 MG_PASS_BYTES_RULE = ("the level-0 smoothing pass must move, per node that does not hang (hanging nodes carry no "
                       "values in the constrained form): the direction d read, the iterate x and the residual r "
                       "read and written, the diagonal inverse read, the next direction written (3 FP64 values "
@@ -219,8 +224,12 @@ def main():
     precs = {"fp64": binding.FP64, "fp32": binding.FP32, "bf16": binding.BF16}
     if args.mg_roofline_only:
         ctx.mg_setup(tree, **MG_OPTS)
-        lv_us = ctx.mg_pass_times(50)  # the last 50 level-0 operator dispatches are these passes
-        log(f"[bench] C2 multigrid level passes (us): {', '.join(f'{t:.2f}' for t in lv_us)}")
+        # the last dispatches of the level-0 operator and of the coarse-level
+        # pass are these passes: 50 on level 0, then 50 on each smoothed coarse level
+        lv_us = ctx.mg_pass_times(50)
+        info = ctx.mg_info()
+        log(f"[bench] C2 multigrid level passes (us): {', '.join(f'{t:.2f}' for t in lv_us)}; "
+            f"DOFs {info['dofs']}, blocks {info['blocks']}")
         log(f"[bench] multigrid source hash {source_hash(MG_SOURCES)}")
         copy_calibration(torch)
         return
@@ -322,23 +331,46 @@ def main():
         return
 
     # --- dominant kernel of the timed step, timed live: for the multigrid
-    # solve the level-0 smoothing pass (octree operator with the Chebyshev
-    # update), otherwise the solver variant's fused CG operator pass
+    # solve the coarse-level smoothing pass (block rows with the Chebyshev
+    # update; the level-0 pass is a second entry), otherwise the solver
+    # variant's fused CG operator pass
     ne, nn = mesh.n_elems, mesh.n_nodes
+    roofline_level0 = None
     if "+mg" in solver:
         lv_us = ctx.mg_pass_times(200)
+        info = ctx.mg_info()
         op_us = lv_us[0]
         pb = 168.0 * (nn - len(mesh.hang_node)) + 8.0 * ne
         gbs = pb / (op_us * 1e-6) / 1e9
+        # smoothed coarse levels (the last level is solved by its inverse); each
+        # runs the same number of passes per V-cycle, so the launch-weighted
+        # rate is total bytes over total time of one pass on each
+        coarse = list(range(1, info["levels"] - 1))
+        cb = [76.0 * info["blocks"][k] + 173.0 * (info["dofs"][k] // 3) + 4.0 for k in coarse]
+        ct = [lv_us[k] for k in coarse]
+        cgbs = sum(cb) / (sum(ct) * 1e-6) / 1e9
         log(f"[bench] C2 multigrid level passes (us): {', '.join(f'{t:.2f}' for t in lv_us)}; level 0 "
-            f"{gbs:.0f} GB/s algorithmic")
-        roofline = dict(bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(gbs / HBM_PEAK_GBS, 5), traffic=measured_traffic(MG_TRAFFIC_FILE, MG_SOURCES),
-                        kernel="level-0 smoothing pass of the multigrid V-cycle (k_apply_chunks FP64: stiffness "
-                               "apply with the Chebyshev update of x, r and the next direction)",
-                        per_launch_us=round(op_us, 3), alg_bytes_per_launch=int(pb), bytes_rule=MG_PASS_BYTES_RULE,
-                        coarse_level_pass_us=[round(t, 3) for t in lv_us[1:]],
+            f"{gbs:.0f} GB/s, coarse levels {cgbs:.0f} GB/s algorithmic")
+        roofline = dict(bound="hbm", achieved=round(cgbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(cgbs / HBM_PEAK_GBS, 5),
+                        traffic=measured_traffic(MG_COARSE_TRAFFIC_FILE, MG_SOURCES),
+                        kernel="coarse-level smoothing pass of the multigrid V-cycle (k_mg_spmv<8>: product with "
+                               "the level's 3x3 block rows and the Chebyshev update), one pass on each smoothed "
+                               "coarse level (they run equally often)",
+                        per_launch_us=round(sum(ct) / len(ct), 3), alg_bytes_per_launch=int(sum(cb) / len(cb)),
+                        bytes_rule=MG_COARSE_BYTES_RULE,
+                        levels=[dict(level=k, dofs=info["dofs"][k], blocks=info["blocks"][k], us=round(t, 3),
+                                     alg_bytes=int(x), gbs=round(x / (t * 1e-6) / 1e9, 1))
+                                for k, t, x in zip(coarse, ct, cb)],
                         traffic_unit="bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)")
+        roofline_level0 = dict(bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                               frac=round(gbs / HBM_PEAK_GBS, 5),
+                               traffic=measured_traffic(MG_TRAFFIC_FILE, MG_SOURCES),
+                               kernel="level-0 smoothing pass of the multigrid V-cycle (k_apply_chunks FP64: "
+                                      "stiffness apply with the Chebyshev update of x, r and the next direction)",
+                               per_launch_us=round(op_us, 3), alg_bytes_per_launch=int(pb),
+                               bytes_rule=MG_PASS_BYTES_RULE,
+                               traffic_unit="bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)")
     else:
         op_us, up_us = pass_times(ctx, binding, b, u, solver, regions, 200)
         pb = pass_bytes(solver, nn, ne)
@@ -406,7 +438,8 @@ def main():
                    "multigrid": dict(MG_OPTS) if "+mg" in solver else None,
                    "rtol": 1e-8, "E0": 1.0, "Emin": 1e-9, "nu": 0.3, "p": 3.0},
         "solve_iters": int(np.median(iters)), "solve_rel_res": float(max(rel)),
-        "solve_variants": variants, "roofline": roofline, "roofline_apply_fp64": roofline_apply,
+        "solve_variants": variants, "roofline": roofline, "roofline_level0_pass": roofline_level0,
+        "roofline_apply_fp64": roofline_apply,
         "c1_simp_iteration_24x12x12": c1, "c5_bridge_128x64x64": c5,
         "apply_uniform_192x96x96": c3, "simp_adaptive_bridge": c4, "network_training": net_rate, "amr_vs_uniform_cantilever": avu,
         "plane_2d_cantilever_256x128": p2d, "cpu_baseline": cpu,

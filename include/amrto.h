@@ -530,9 +530,11 @@ typedef struct {
  * opts may be NULL.  AMRTO_EINVAL when the tree's mesh is not the uploaded
  * one or no small uniform coarsest level exists. */
 int amrto_mg_setup(amrto_ctx* ctx, const amrto_octree* tree, const amrto_mg_opts* opts);
-/* Level count, DOFs per level and dense (merged) elements per level (host
- * arrays of at least 16 entries, either may be NULL). */
-int amrto_mg_info(amrto_ctx* ctx, int32_t* n_levels, int32_t* dofs, int32_t* dense);
+/* Level count, DOFs per level, dense (merged) elements per level and 3x3
+ * blocks of each coarse level's assembled operator (0 on level 0, which runs
+ * the octree operator pass) (host arrays of at least 16 entries, any may be
+ * NULL). */
+int amrto_mg_info(amrto_ctx* ctx, int32_t* n_levels, int32_t* dofs, int32_t* dense, int64_t* blocks);
 /* Replace the power-iteration estimates of lambda_max(D^-1 A) by the given
  * values (one per smoothed level, host), or restore them (lam == NULL). */
 int amrto_mg_set_bounds(amrto_ctx* ctx, const double* lam);

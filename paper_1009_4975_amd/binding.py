@@ -134,7 +134,7 @@ _SIGS = {
     "amrto_octree_mesh_export": (C.c_int, [_p] + [_p] * 9),
     "amrto_octree_transfer_nodal": (C.c_int, [_p, _p, _p]),
     "amrto_mg_setup": (C.c_int, [_p, _p, C.POINTER(MgOpts)]),
-    "amrto_mg_info": (C.c_int, [_p, _i32p, _p, _p]),
+    "amrto_mg_info": (C.c_int, [_p, _i32p, _p, _p, _p]),
     "amrto_mg_set_bounds": (C.c_int, [_p, _p]),
     "amrto_mg_get_bounds": (C.c_int, [_p, _p]),
     "amrto_mg_vcycle": (C.c_int, [_p, _p, _p]),
@@ -542,8 +542,11 @@ class Context:
         n = C.c_int32()
         dofs = np.zeros(16, np.int32)
         dense = np.zeros(16, np.int32)
-        self._chk(self.lib.amrto_mg_info(self.h, C.byref(n), dofs.ctypes.data, dense.ctypes.data))
-        return dict(levels=n.value, dofs=dofs[:n.value].tolist(), dense=dense[:n.value].tolist())
+        blocks = np.zeros(16, np.int64)
+        self._chk(self.lib.amrto_mg_info(self.h, C.byref(n), dofs.ctypes.data, dense.ctypes.data,
+                                         blocks.ctypes.data))
+        return dict(levels=n.value, dofs=dofs[:n.value].tolist(), dense=dense[:n.value].tolist(),
+                    blocks=blocks[:n.value].tolist())
 
     def _mg_level(self, k):
         dofs = getattr(self, "_mg_dofs", None)

@@ -1441,7 +1441,7 @@ int amrto_mg_setup(amrto_ctx* ctx, const amrto_octree* tree, const amrto_mg_opts
   return AMRTO_OK;
 }
 
-int amrto_mg_info(amrto_ctx* ctx, int32_t* n_levels, int32_t* dofs, int32_t* dense) {
+int amrto_mg_info(amrto_ctx* ctx, int32_t* n_levels, int32_t* dofs, int32_t* dense, int64_t* blocks) {
   if (!ctx) return AMRTO_EINVAL;
   if (!ctx->mg) return ctx->fail(AMRTO_ESTATE, "amrto_mg_info: no multigrid hierarchy");
   MgData* g = ctx->mg;
@@ -1449,6 +1449,7 @@ int amrto_mg_info(amrto_ctx* ctx, int32_t* n_levels, int32_t* dofs, int32_t* den
   for (int k = 0; k < g->nlev; ++k) {
     if (dofs) dofs[k] = 3 * g->lv[k].nn;
     if (dense) dense[k] = g->lv[k].nd;
+    if (blocks) blocks[k] = k == 0 ? 0 : g->lv[k].nnzb;
   }
   return AMRTO_OK;
 }
