@@ -338,15 +338,15 @@ def main():
     roofline_level0 = None
     if "+mg" in solver:
         lv_us = ctx.mg_pass_times(200)
-        info = ctx.mg_info()
+        mgi = ctx.mg_info()
         op_us = lv_us[0]
         pb = 168.0 * (nn - len(mesh.hang_node)) + 8.0 * ne
         gbs = pb / (op_us * 1e-6) / 1e9
         # smoothed coarse levels (the last level is solved by its inverse); each
         # runs the same number of passes per V-cycle, so the launch-weighted
         # rate is total bytes over total time of one pass on each
-        coarse = list(range(1, info["levels"] - 1))
-        cb = [76.0 * info["blocks"][k] + 173.0 * (info["dofs"][k] // 3) + 4.0 for k in coarse]
+        coarse = list(range(1, mgi["levels"] - 1))
+        cb = [76.0 * mgi["blocks"][k] + 173.0 * (mgi["dofs"][k] // 3) + 4.0 for k in coarse]
         ct = [lv_us[k] for k in coarse]
         cgbs = sum(cb) / (sum(ct) * 1e-6) / 1e9
         log(f"[bench] C2 multigrid level passes (us): {', '.join(f'{t:.2f}' for t in lv_us)}; level 0 "
@@ -354,12 +354,12 @@ def main():
         roofline = dict(bound="hbm", achieved=round(cgbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=round(cgbs / HBM_PEAK_GBS, 5),
                         traffic=measured_traffic(MG_COARSE_TRAFFIC_FILE, MG_SOURCES),
-                        kernel="coarse-level smoothing pass of the multigrid V-cycle (k_mg_spmv<8>: product with "
+                        kernel="coarse-level smoothing pass of the multigrid V-cycle (k_mg_spmv<16>: product with "
                                "the level's 3x3 block rows and the Chebyshev update), one pass on each smoothed "
                                "coarse level (they run equally often)",
                         per_launch_us=round(sum(ct) / len(ct), 3), alg_bytes_per_launch=int(sum(cb) / len(cb)),
                         bytes_rule=MG_COARSE_BYTES_RULE,
-                        levels=[dict(level=k, dofs=info["dofs"][k], blocks=info["blocks"][k], us=round(t, 3),
+                        levels=[dict(level=k, dofs=mgi["dofs"][k], blocks=mgi["blocks"][k], us=round(t, 3),
                                      alg_bytes=int(x), gbs=round(x / (t * 1e-6) / 1e9, 1))
                                 for k, t, x in zip(coarse, ct, cb)],
                         traffic_unit="bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)")

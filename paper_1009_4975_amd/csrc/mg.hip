@@ -889,12 +889,23 @@ void launch_restrict(hipStream_t st, MgLevel& C, const double* rf, double* b, in
 int level_pass(amrto_ctx* ctx, MgLevel& L, const double* in, const MgUpd& u, double* part) {
   // the Rayleigh partials fill exactly MG_RED slots
   const int grid = u.mode == MG_RAYLEIGH ? MG_RED : blocks_for((long)L.lanes * L.nn);
-  if (L.lanes == 8)
-    hipLaunchKernelGGL(k_mg_spmv<8>, dim3(grid), dim3(256), 0, ctx->stream, in, L.bptr, L.bcol, L.bval, L.flag, L.nn,
-                       u, part);
-  else
-    hipLaunchKernelGGL(k_mg_spmv<4>, dim3(grid), dim3(256), 0, ctx->stream, in, L.bptr, L.bcol, L.bval, L.flag, L.nn,
-                       u, part);
+  switch (L.lanes) {
+    case 32:
+      hipLaunchKernelGGL(k_mg_spmv<32>, dim3(grid), dim3(256), 0, ctx->stream, in, L.bptr, L.bcol, L.bval, L.flag,
+                         L.nn, u, part);
+      break;
+    case 16:
+      hipLaunchKernelGGL(k_mg_spmv<16>, dim3(grid), dim3(256), 0, ctx->stream, in, L.bptr, L.bcol, L.bval, L.flag,
+                         L.nn, u, part);
+      break;
+    case 8:
+      hipLaunchKernelGGL(k_mg_spmv<8>, dim3(grid), dim3(256), 0, ctx->stream, in, L.bptr, L.bcol, L.bval, L.flag,
+                         L.nn, u, part);
+      break;
+    default:
+      hipLaunchKernelGGL(k_mg_spmv<4>, dim3(grid), dim3(256), 0, ctx->stream, in, L.bptr, L.bcol, L.bval, L.flag,
+                         L.nn, u, part);
+  }
   return hipGetLastError() == hipSuccess ? AMRTO_OK : ctx->fail(AMRTO_EHIP, "multigrid level pass");
 }
 
@@ -1280,7 +1291,10 @@ int upload_level(amrto_ctx* ctx, MgData* g, std::vector<HostLevel>& H, int k) {
   AMRTO_HIP(mg_upload(own, L.kab, kab));
   AMRTO_HIP(mg_upload(own, L.kw, kw));
   AMRTO_HIP(mg_alloc(own, L.bval, 9L * std::max(1, L.nnzb)));
-  L.lanes = (long)bcol.size() > 12L * nn ? 8 : 4;  // long block rows: more lanes per node
+  // long block rows: more lanes per node, so a row's blocks are requested at
+  // once (C2's coarse levels, ~22 blocks per row: 8 lanes 5.6 / 4.7 us per
+  // pass, 16 lanes 5.3 / 3.8, 32 lanes 6.0 / 3.7)
+  L.lanes = (long)bcol.size() > 12L * nn ? 16 : 4;
   // children of the dense elements (previous level, its device order)
   HostLevel& F = H[k - 1];
   std::vector<std::vector<std::pair<int32_t, uint8_t>>> ch(h.nd);
