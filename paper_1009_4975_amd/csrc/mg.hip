@@ -363,15 +363,16 @@ __global__ __launch_bounds__(256) void k_mg_prolong_plain(const double* __restri
   for (int c = 0; c < 3; ++c) xf[3L * v + c] = mg_cons(flag[v], c) ? 0.0 : s[c];
 }
 
-// coarsest level: x = A~^-1 b
+// coarsest level: x = A~^-1 b, one workgroup per row (every thread requests
+// its few entries at once; fixed-order block sum)
 __global__ __launch_bounds__(256) void k_mg_coarse_solve(const double* __restrict__ Ainv,
                                                          const double* __restrict__ b, double* __restrict__ x, int n) {
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (i >= n) return;  // whole waves leave together
+  __shared__ double sh[4];
+  const int i = blockIdx.x;
   double s = 0.0;
-  for (int j = lane; j < n; j += 64) s = fma(Ainv[(long)i * n + j], b[j], s);
-  s = wave_sum(s);
-  if (lane == 0) x[i] = s;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) s = fma(Ainv[(long)i * n + j], b[j], s);
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) x[i] = s;
 }
 
 // ---------------------------------------------------------------- set-up kernels
@@ -964,7 +965,7 @@ int vcycle_from(amrto_ctx* ctx, int k) {
   int rc;
   if (k == g->nlev - 1) {
     const int n = 3 * L.nn;
-    hipLaunchKernelGGL(k_mg_coarse_solve, dim3((n + 3) / 4), dim3(256), 0, ctx->stream, L.Ainv, L.b, L.x, n);
+    hipLaunchKernelGGL(k_mg_coarse_solve, dim3(n), dim3(256), 0, ctx->stream, L.Ainv, L.b, L.x, n);
     return hipGetLastError() == hipSuccess ? AMRTO_OK : ctx->fail(AMRTO_EHIP, "multigrid coarse solve");
   }
   const int m = k == 0 ? g->degree : g->coarse_degree;

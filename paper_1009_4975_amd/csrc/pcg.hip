@@ -881,18 +881,17 @@ static int enqueue_iters(amrto_ctx* ctx, const Vecs<VT>& v, VT* x, int prec, dou
                          bool block3 = false) {
   const bool fused = coarse_fused(ctx);
   const bool rec = fused && AMRTO_COARSE_REC && ctx->d_cqpart;
-  if (rec) {
-    // ct and cz follow r by recurrences; every CT_REFRESH iterations they are
-    // formed from r again, so rounding cannot accumulate without bound
-    if (ctx->coarse_fresh) {
-      ctx->coarse_fresh = false;
-      ctx->coarse_exact_it = it0;
-    } else if (it0 - ctx->coarse_exact_it >= CT_REFRESH) {
-      coarse_exact(ctx, v.r, ctx->d_scal + S_DONE);
-      ctx->coarse_exact_it = it0;
-    }
+  if (rec && ctx->coarse_fresh) {
+    ctx->coarse_fresh = false;
+    ctx->coarse_exact_it = it0;
   }
   for (int it = it0; it < it0 + count; ++it) {
+    // ct and cz follow r by recurrences; every CT_REFRESH iterations they are
+    // formed from r again, so rounding cannot accumulate without bound
+    if (rec && it - ctx->coarse_exact_it >= CT_REFRESH) {
+      coarse_exact(ctx, v.r, ctx->d_scal + S_DONE);
+      ctx->coarse_exact_it = it;
+    }
     int rc = enqueue_op_pass<VT>(ctx, v, prec, tol2, it, block3);
     if (!rc) rc = enqueue_update<VT>(ctx, v, x, it, block3);
     if (!rc && ctx->rec_active) rc = recycle_store<VT>(ctx, v.r, it);

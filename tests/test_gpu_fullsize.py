@@ -108,8 +108,9 @@ def test_c2_solve_judged_by_oracle_operator(c2, prec):
 
 def test_recurrence_update_with_several_nodes_per_thread():
     """An octree with more nodes (148,083) than the update pass has threads
-    (512 x 256): each thread updates two or more nodes, the first two loaded
-    before the p.q partials are reduced.  The mixed coarse-space solve (the
+    (512 x 256): about one thread in eight updates a second node (both loaded
+    before the p.q partials are reduced; no thread reaches the loop for a
+    third node at this size).  The mixed coarse-space solve (the
     recurrence form of the timed solver) reaches 1e-8 on the library's FP64
     true residual, and its compliance matches the plain FP64 solve's."""
     from paper_1009_4975_amd import binding
