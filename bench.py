@@ -722,8 +722,10 @@ def c4_simp(torch, binding, synth, regions=(2, 2, 2)):
     solve: plain (previous solution as the start, Jacobi-PCG), plain with the
     3x3 node-block Jacobi preconditioner, the affine coarse space, and the
     learned start (network trained on iterations 1-10) with the coarse space;
-    each in FP64 and with FP32 inner solves; recycled Krylov vectors; and
-    multigrid-preconditioned CG (its hierarchy rebuilt at every adaptation)."""
+    each in FP64 and with FP32 inner solves; recycled Krylov vectors;
+    multigrid-preconditioned CG (its hierarchy rebuilt at every adaptation);
+    and multigrid started from the network's prediction (the energy line
+    search from u_prev along it), which isolates what the network gains."""
     from paper_1009_4975_amd.learned import LearnedWarmStart
     from paper_1009_4975_amd.simp import AdaptiveSIMP
     case = synth.c4()
@@ -740,15 +742,16 @@ def c4_simp(torch, binding, synth, regions=(2, 2, 2)):
                              ("recycle_init_coarse_block3_fp64", binding.FP64, "recycle_init+coarse+block3"),
                              ("recycle_init_coarse_block3_fp32", binding.FP32, "recycle_init+coarse+block3"),
                              ("recycle_in_coarse_space_fp64", binding.FP64, "recycle_coarse"),
-                             ("mg_fp64", binding.FP64, "mg")):
+                             ("mg_fp64", binding.FP64, "mg"), ("learned_mg_fp64", binding.FP64, "learned_mg")):
         t0 = time.perf_counter()
         sim = AdaptiveSIMP(case.base, case.max_level, case.fixed, case.load, volfrac=ex["volfrac"],
                            rho_init=ex["rho_init"], rmin=ex["rmin"], rho_solid=ex["rho_solid"], r_amr=ex["r_amr"],
                            adapt_every=ex["adapt_every"], rtol=1e-8, inner_prec=prec, inner_rtol=0.1,
                            precond=binding.BLOCK3 if (mode or "").endswith("block3") else binding.JACOBI,
-                           mg=MG_OPTS if mode == "mg" else None)
+                           mg=MG_OPTS if mode in ("mg", "learned_mg") else None)
         if mode == "mg":
             mode = None  # every solve (iterations 1-50) is multigrid-preconditioned
+        learned = mode in ("learned", "learned_mg")
         rec_from, rec_mode = None, None
         if (mode or "").startswith("recycle"):
             # from iteration 11 on: recorded solves whose Ritz vectors start
@@ -766,13 +769,15 @@ def c4_simp(torch, binding, synth, regions=(2, 2, 2)):
             if rec_from is not None and k == rec_from:
                 sim.recycle = dict(mode=rec_mode, m=64, k=4, keep=4, regions=tuple(regions), affine=True)
                 sim.ctx.recycle_setup(64)
-            if mode == "learned" and k < n_train:
+            if learned and k < n_train:
                 r = sim.step(warm_start=ws.collect_before, after_solve=ws.collect_after)
             elif mode and k >= n_train:
-                if mode == "learned" and not ws.trained:
+                if learned and not ws.trained:
                     ws.train()
                     train_ms = ws.train_ms
-                r = sim.step(warm_start=(lambda s: ws.warm_start(s, use_net=(mode == "learned"))))
+                # with multigrid the network's start is the only change (no coarse space)
+                r = sim.step(warm_start=(lambda s: ws.warm_start(s, use_net=learned,
+                                                                 coarse=False if mode == "learned_mg" else None)))
             else:
                 r = sim.step()
             recs.append(r)
