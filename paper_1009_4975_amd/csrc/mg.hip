@@ -617,12 +617,21 @@ __device__ __forceinline__ void bgj_patch(const double* X, const double* Y, int 
   }
 }
 
-// load the tile of A at (r0, c0) with rows x cols (zero outside) into S
+// load the tile of A at (r0, c0) with rows x cols (zero outside) into S; a
+// thread's 16 loads are all requested before the first is stored (256 threads)
+constexpr int BGJ_PER = BGJ * BGJ / 256;
 __device__ __forceinline__ void bgj_load(const double* __restrict__ A, int n, int r0, int c0, int rows, int cols,
                                          double* S) {
-  for (int e = threadIdx.x; e < BGJ * BGJ; e += blockDim.x) {
-    const int I = e / BGJ, J = e - I * BGJ;
-    S[I * BGJ_S + J] = (I < rows && J < cols) ? A[(long)(r0 + I) * n + c0 + J] : 0.0;
+  double v[BGJ_PER];
+#pragma unroll
+  for (int m = 0; m < BGJ_PER; ++m) {
+    const int e = threadIdx.x + 256 * m, I = e / BGJ, J = e % BGJ;
+    v[m] = (I < rows && J < cols) ? A[(long)(r0 + I) * n + c0 + J] : 0.0;
+  }
+#pragma unroll
+  for (int m = 0; m < BGJ_PER; ++m) {
+    const int e = threadIdx.x + 256 * m, I = e / BGJ, J = e % BGJ;
+    S[I * BGJ_S + J] = v[m];
   }
 }
 
@@ -651,20 +660,24 @@ __global__ __launch_bounds__(256) void k_bgj_trail(double* __restrict__ A, int n
   const int i0 = blockIdx.y * BGJ, j0 = blockIdx.x * BGJ;
   if (i0 == k0 || j0 == k0) return;
   const int bs = min(BGJ, n - k0), h = min(BGJ, n - i0), w = min(BGJ, n - j0);
+  // the patch of A_ij this thread updates is requested with the tiles
+  const int r0 = (threadIdx.x >> 4) * 4, cc0 = (threadIdx.x & 15) * 4;
+  double old[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      old[a][b] = (r0 + a < h && cc0 + b < w) ? A[(long)(i0 + r0 + a) * n + j0 + cc0 + b] : 0.0;
   bgj_load(A, n, i0, k0, h, bs, X);
   bgj_load(A, n, k0, j0, bs, w, Y);
   __syncthreads();
   double c[4][4];
   bgj_patch(X, Y, bs, c);
-  const int r0 = (threadIdx.x >> 4) * 4, cc0 = (threadIdx.x & 15) * 4;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b)
-      if (r0 + a < h && cc0 + b < w) {
-        double* e = A + (long)(i0 + r0 + a) * n + j0 + cc0 + b;
-        *e -= c[a][b];
-      }
+      if (r0 + a < h && cc0 + b < w) A[(long)(i0 + r0 + a) * n + j0 + cc0 + b] = old[a][b] - c[a][b];
 }
 
 // column panel: A_ik = -A_ik P for the row tiles i != k (after the trailing

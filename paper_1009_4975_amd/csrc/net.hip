@@ -75,20 +75,34 @@ __device__ __forceinline__ int halo_off(int d) { return ((d / 9) * CH_Y + (d / 3
 // first cell is (x0 - 1, y0 - 1, z0 - 1) into s; zero outside the grid and for
 // c >= C; with mask (same shape as src) values whose mask is not > 0 are zero
 // (the ReLU derivative)
+// (256 threads: a thread's loads go out in batches of 8 before they are
+// stored, so at most 8 wait at once and the registers stay few)
+constexpr int STAGE_PER = (CG * CH_N + 255) / 256;
+constexpr int STAGE_B = 8;
 __device__ __forceinline__ void stage_halo(const float* __restrict__ src, const float* __restrict__ mask, int n,
                                            int C, int c0, const ConvGrid& G, int z0, int y0, int x0, float* s) {
   const long V = (long)G.Z * G.Y * G.X;
-  for (int k = threadIdx.x; k < CG * CH_N; k += blockDim.x) {
-    const int c = k / CH_N, h = k - c * CH_N;
-    const int hx = h % CH_X, hy = (h / CH_X) % CH_Y, hz = h / (CH_X * CH_Y);
-    const int x = x0 - 1 + hx, y = y0 - 1 + hy, z = z0 - 1 + hz;
-    float v = 0.f;
-    if (c0 + c < C && in_grid(z, y, x, G.Z, G.Y, G.X)) {
-      const long q = ((long)n * C + c0 + c) * V + ((long)z * G.Y + y) * G.X + x;
-      v = src[q];
-      if (mask && !(mask[q] > 0.f)) v = 0.f;
+#pragma unroll 1
+  for (int m0 = 0; m0 < STAGE_PER; m0 += STAGE_B) {
+    float v[STAGE_B];
+#pragma unroll
+    for (int m = 0; m < STAGE_B; ++m) {
+      const int k = threadIdx.x + 256 * (m0 + m);
+      const int c = k / CH_N, h = k - c * CH_N;
+      const int hx = h % CH_X, hy = (h / CH_X) % CH_Y, hz = h / (CH_X * CH_Y);
+      const int x = x0 - 1 + hx, y = y0 - 1 + hy, z = z0 - 1 + hz;
+      v[m] = 0.f;
+      if (k < CG * CH_N && c0 + c < C && in_grid(z, y, x, G.Z, G.Y, G.X)) {
+        const long q = ((long)n * C + c0 + c) * V + ((long)z * G.Y + y) * G.X + x;
+        v[m] = src[q];
+        if (mask && !(mask[q] > 0.f)) v[m] = 0.f;
+      }
     }
-    s[c * CH_S + h] = v;
+#pragma unroll
+    for (int m = 0; m < STAGE_B; ++m) {
+      const int k = threadIdx.x + 256 * (m0 + m);
+      if (k < CG * CH_N) s[(k / CH_N) * CH_S + k % CH_N] = v[m];
+    }
   }
 }
 
@@ -195,16 +209,24 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const float* __restrict__ g,
     const int x0 = (tile % G.tx) * CT_X, y0 = ((tile / G.tx) % G.ty) * CT_Y, z0 = (tile / (G.tx * G.ty)) * CT_Z;
     __syncthreads();
     stage_halo(in, nullptr, n, Ci, i0, G, z0, y0, x0, s_in);
-    for (int k = tid; k < CG * CT_N; k += blockDim.x) {
-      const int c = k / CT_N, q = k - c * CT_N;
-      const int x = x0 + q % CT_X, y = y0 + (q / CT_X) % CT_Y, z = z0 + q / (CT_X * CT_Y);
-      float v = 0.f;
-      if (o0 + c < Co && in_grid(z, y, x, G.Z, G.Y, G.X)) {
-        const long gi = ((long)n * Co + o0 + c) * V + ((long)z * G.Y + y) * G.X + x;
-        v = g[gi];
-        if (post && !(post[gi] > 0.f)) v = 0.f;
+    // the gradient tile: thread tid holds position tid of every channel, so
+    // one position's index work serves its CG loads (all requested at once)
+    {
+      const int x = x0 + tid % CT_X, y = y0 + (tid / CT_X) % CT_Y, z = z0 + tid / (CT_X * CT_Y);
+      const bool in = in_grid(z, y, x, G.Z, G.Y, G.X);
+      const long p = ((long)z * G.Y + y) * G.X + x;
+      float gv_in[CG];
+#pragma unroll
+      for (int c = 0; c < CG; ++c) {
+        gv_in[c] = 0.f;
+        if (in && o0 + c < Co) {
+          const long gi = ((long)n * Co + o0 + c) * V + p;
+          gv_in[c] = g[gi];
+          if (post && !(post[gi] > 0.f)) gv_in[c] = 0.f;
+        }
       }
-      s_g[c * CGS + q] = v;
+#pragma unroll
+      for (int c = 0; c < CG; ++c) s_g[c * CGS + tid] = gv_in[c];
     }
     __syncthreads();
     for (int q = pg * 64; q < pg * 64 + 64; ++q) {
