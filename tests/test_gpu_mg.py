@@ -199,8 +199,8 @@ def _c2_library_only():
     return t, mesh, rho
 
 
-@pytest.mark.parametrize("first", [1, 2])
-def test_vcycle_deterministic_symmetric_at_full_size(first):
+@pytest.mark.parametrize("first,coarse", [(1, 200), (2, 200), (2, 700)])
+def test_vcycle_deterministic_symmetric_at_full_size(first, coarse):
     """At the full octree size (255,636 DOFs, many concurrent workgroups per
     level): the same residual gives the same z to rounding (the level-0
     octree pass sums element contributions with LDS atomics, so only the last
@@ -208,12 +208,16 @@ def test_vcycle_deterministic_symmetric_at_full_size(first):
     would differ far more), r1 . V r2 equals r2 . V r1 to rounding, V is
     positive, and the solve converges within the iteration count the oracle
     multigrid takes on this mesh (79 with two levels merged first) plus a
-    margin."""
+    margin.  With coarse = 700 the coarsest level has 675 DOFs, so its inverse
+    takes eleven blocked Gauss-Jordan steps (the last block 35 rows): an
+    inexact or unsymmetric inverse would break the symmetry check."""
     t, mesh, rho = _c2_library_only()
     ctx = binding.Context(0)
     ctx.upload_mesh(mesh)
     ctx.set_density(_t(rho))
-    ctx.mg_setup(t, first=first)
+    ctx.mg_setup(t, first=first, coarse_dofs=coarse)
+    if coarse == 700:
+        assert ctx.mg_info()["dofs"][-1] == 675
     f = _t(mesh.f_load)
     b = torch.empty_like(f)
     ctx.project_rhs(f, b)
