@@ -24,12 +24,15 @@ is a stronger, parallel alternative built from textbook definitions:
   one level-k leaf, so the coarse space is contained in the fine one.
 * Galerkin operators A_k = P_k^T A_{k-1} P_k + (I - F_k) (identity rows for
   the constrained DOFs, as A~ has on level 0).
-* Smoother: the Chebyshev iteration for D^-1 A (D = diag A) on the interval
-  [hi / ratio, hi], hi = 1.1 lambda_max(D^-1 A), degree m on level 0 and
+* Smoother: the Chebyshev iteration for M^-1 A on the interval
+  [hi / ratio, hi], hi = 1.1 lambda_max(M^-1 A), degree m on level 0 and
   optionally another degree on the coarse levels (Golub and Varga's
   three-term recurrence as in Saad, Iterative Methods for Sparse Linear
-  Systems, Alg. 12.1).  The same polynomial smooths before and after the
-  coarse correction, so one V-cycle is a symmetric operator.
+  Systems, Alg. 12.1).  M is D = diag A, or on level 0 optionally the block
+  diagonal of A's 3 x 3 node blocks (point-block Jacobi: the three
+  displacement components of a node are coupled in A).  The same polynomial
+  smooths before and after the coarse correction, so one V-cycle is a
+  symmetric operator.
 * V-cycle: pre-smooth from zero, restrict the residual with P^T, recurse,
   prolong and add the coarse correction, recompute the residual, post-smooth;
   the coarsest level is solved exactly.
@@ -79,6 +82,7 @@ class Level:
     free: np.ndarray           # (3 nn,) neither hanging nor supported
     A: sp.csr_matrix = None
     dinv: np.ndarray = None
+    minv: object = None        # smoother's M^-1: dinv, or the sparse node-block inverse
     P: sp.csr_matrix = None    # from the next coarser level to this one
     lo: float = 0.0
     hi: float = 0.0
@@ -139,32 +143,56 @@ def galerkin(A_f: sp.csr_matrix, P: sp.csr_matrix, free_c) -> sp.csr_matrix:
     return Ac
 
 
-def lambda_max(A: sp.csr_matrix, dinv) -> float:
-    """Largest eigenvalue of D^-1 A (through the symmetric D^-1/2 A D^-1/2)."""
-    s = sp.diags(np.sqrt(dinv))
-    S = (s @ A @ s).tocsr()
+def node_blocks(A: sp.csr_matrix) -> np.ndarray:
+    """The 3 x 3 diagonal blocks of A, one per node (n, 3, 3)."""
+    n = A.shape[0] // 3
+    A = A.tocsr()
+    return np.stack([A[3 * v:3 * v + 3, 3 * v:3 * v + 3].toarray() for v in range(n)])
+
+
+def block_diag_matrix(blocks) -> sp.csr_matrix:
+    """Sparse block-diagonal matrix from (n, 3, 3) blocks."""
+    n = len(blocks)
+    rows = np.repeat(np.arange(3 * n).reshape(n, 3), 3, axis=1).ravel()
+    cols = np.tile(np.arange(3 * n).reshape(n, 3), (1, 3)).ravel()
+    return sp.csr_matrix((np.asarray(blocks).ravel(), (rows, cols)), shape=(3 * n, 3 * n))
+
+
+def lambda_max(A: sp.csr_matrix, minv) -> float:
+    """Largest eigenvalue of M^-1 A, through the symmetric form L^T A L with
+    M^-1 = L L^T: L = diag(sqrt(dinv)) for a diagonal M (minv the vector of
+    1 / D), else the node-block Cholesky factors of M^-1 (minv sparse)."""
+    if sp.issparse(minv):
+        n = minv.shape[0] // 3
+        b = np.stack([minv[3 * v:3 * v + 3, 3 * v:3 * v + 3].toarray() for v in range(n)])
+        s = block_diag_matrix(np.linalg.cholesky(b))
+    else:
+        s = sp.diags(np.sqrt(minv))
+    S = (s.T @ A @ s).tocsr()
     if S.shape[0] <= 400:
         return float(np.linalg.eigvalsh(S.toarray())[-1])
     return float(spla.eigsh(S, k=1, which="LA", tol=1e-10, return_eigenvectors=False)[0])
 
 
 # ---------------------------------------------------------------- smoothing and cycles
-def chebyshev(A, dinv, b, x, lo, hi, m, need_residual=True):
-    """m steps of the Chebyshev iteration for D^-1 A on [lo, hi] from x;
-    returns (x, r) with r = b - A x (None when not needed after the last step)."""
+def chebyshev(A, minv, b, x, lo, hi, m, need_residual=True):
+    """m steps of the Chebyshev iteration for M^-1 A on [lo, hi] from x
+    (minv: the vector 1 / diag A, or the sparse matrix M^-1); returns (x, r)
+    with r = b - A x (None when not needed after the last step)."""
+    apply_m = (lambda v: minv @ v) if sp.issparse(minv) else (lambda v: minv * v)
     theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
     sigma = theta / delta
     x = np.array(x, dtype=np.float64)
     r = b - A @ x if np.any(x) else np.array(b, dtype=np.float64)
     rho = 1.0 / sigma
-    d = (dinv * r) / theta
+    d = apply_m(r) / theta
     for k in range(m):
         x = x + d
         if k == m - 1 and not need_residual:
             return x, None
         r = r - A @ d
         rho_new = 1.0 / (2.0 * sigma - rho)
-        d = rho_new * rho * d + (2.0 * rho_new / delta) * (dinv * r)
+        d = rho_new * rho * d + (2.0 * rho_new / delta) * apply_m(r)
         rho = rho_new
     return x, r
 
@@ -182,25 +210,29 @@ class MG:
         if k == len(self.levels) - 1:
             return self.coarse_inv @ b
         m = self.degree if k == 0 or self.coarse_degree <= 0 else self.coarse_degree
-        x, r = chebyshev(lv.A, lv.dinv, b, np.zeros_like(b), lv.lo, lv.hi, m)
+        x, r = chebyshev(lv.A, lv.minv, b, np.zeros_like(b), lv.lo, lv.hi, m)
         P = self.levels[k + 1].P
         x = x + P @ self.vcycle(P.T @ r, k + 1)
         r = b - lv.A @ x
-        e, _ = chebyshev(lv.A, lv.dinv, r, np.zeros_like(b), lv.lo, lv.hi, m, need_residual=False)
+        e, _ = chebyshev(lv.A, lv.minv, r, np.zeros_like(b), lv.lo, lv.hi, m, need_residual=False)
         return x + e
 
 
-def setup(levels, A0, degree=2, ratio=10.0, bounds=None, coarse_degree=0) -> MG:
+def setup(levels, A0, degree=2, ratio=10.0, bounds=None, coarse_degree=0, blocks0=False) -> MG:
     """Galerkin operators, diagonals, smoothing intervals (``bounds``: optional
-    list of lambda_max per smoothed level) and the coarsest inverse."""
+    list of lambda_max per smoothed level) and the coarsest inverse; with
+    ``blocks0`` level 0 smooths with its inverse 3 x 3 node blocks."""
     levels[0].A = A0.tocsr()
     for k in range(1, len(levels)):
         levels[k].P = prolongation(levels[k - 1], levels[k])
         levels[k].A = galerkin(levels[k - 1].A, levels[k].P, levels[k].free)
     for k, lv in enumerate(levels):
         lv.dinv = 1.0 / lv.A.diagonal()
+        lv.minv = lv.dinv
+        if k == 0 and blocks0:
+            lv.minv = block_diag_matrix(np.linalg.inv(node_blocks(lv.A)))
         if k < len(levels) - 1:
-            lam = lambda_max(lv.A, lv.dinv) if bounds is None else bounds[k]
+            lam = lambda_max(lv.A, lv.minv) if bounds is None else bounds[k]
             lv.hi = 1.1 * lam
             lv.lo = lv.hi / ratio
     Ac = levels[-1].A.toarray()
