@@ -139,7 +139,7 @@ def event_time(torch, fn, reps):
 # levels over [lambda_max / 50, 1.1 lambda_max]
 MG_OPTS = dict(first=2, ratio=50.0, degree=1, coarse_degree=2, coarse_dofs=700, power_its=8, hi_factor=1.3)
 # uniform bricks (C1, C5): degree 2 on every level over [lambda_max / 30, 1.1 lambda_max]
-MG_OPTS_UNIFORM = dict(first=2, ratio=30.0, degree=2, coarse_degree=2, power_its=8, hi_factor=1.3)
+MG_OPTS_UNIFORM = dict(first=2, ratio=30.0, degree=2, coarse_degree=2, power_its=8, hi_factor=1.3, blocks0=True)
 
 SOLVERS = ("fp64", "fp32", "bf16", "fp64+coarse", "fp32+coarse", "fp64+block3", "fp32+block3",
            "fp64+coarse+block3", "fp32+coarse+block3", "fp64+mg")

@@ -522,6 +522,8 @@ typedef struct {
   int32_t coarse_dofs;  /* target size of the coarsest level (default 200) */
   int32_t first;        /* octree levels merged by the first coarsening, 1 or 2 (default 1) */
   int32_t coarse_degree; /* Chebyshev degree on the coarse levels (0: the same as degree) */
+  int32_t blocks0;      /* level 0 smooths with the inverse 3x3 node blocks of A~ (point-block
+                           Jacobi inside the Chebyshev iteration) instead of D^-1 (default 0) */
 } amrto_mg_opts;
 
 /* Build the hierarchy of the uploaded mesh from the host tree it was built

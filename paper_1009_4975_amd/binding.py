@@ -59,7 +59,8 @@ class SolveOpts(C.Structure):
 
 class MgOpts(C.Structure):
     _fields_ = [("degree", C.c_int32), ("ratio", C.c_double), ("power_its", C.c_int32), ("hi_factor", C.c_double),
-                ("coarse_dofs", C.c_int32), ("first", C.c_int32), ("coarse_degree", C.c_int32)]
+                ("coarse_dofs", C.c_int32), ("first", C.c_int32), ("coarse_degree", C.c_int32),
+                ("blocks0", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -530,10 +531,10 @@ class Context:
 
     # ------------------------------------------------------------ multigrid
     def mg_setup(self, tree, degree=2, ratio=10.0, power_its=20, hi_factor=1.1, coarse_dofs=200, first=1,
-                 coarse_degree=0):
+                 coarse_degree=0, blocks0=False):
         """Multigrid hierarchy of the uploaded mesh from the host tree it was built from."""
         o = MgOpts(int(degree), float(ratio), int(power_its), float(hi_factor), int(coarse_dofs), int(first),
-                   int(coarse_degree))
+                   int(coarse_degree), int(bool(blocks0)))
         self._mg_dofs = None
         self._chk(self.lib.amrto_mg_setup(self.h, tree.h, C.byref(o)))
         self._mg_dofs = self.mg_info()["dofs"]

@@ -68,6 +68,9 @@ struct UArgs {
   const double* cheb_scal = nullptr;
   double* cheb_x = nullptr;
   double* cheb_r = nullptr;
+  // with node blocks: the inverse 3 x 3 node blocks (six entries per node)
+  // take the place of D^-1 in the smoothing update
+  const double* cheb_binv = nullptr;
 };
 
 // ------------------------------------------------------------------ uniform brick, BF16 on the matrix cores
@@ -734,24 +737,28 @@ __global__ __launch_bounds__(chunk_threads(PREC, COARSE)) void k_apply_chunks(UA
   // store phase does not wait on them (each owned row is read and written by
   // its own thread only)
   constexpr bool CHEB = !FUSED && PREC == P_F64;
-  double cr[CHEB ? NPT : 1][3], cdi[CHEB ? NPT : 1][3], cxo[CHEB ? NPT : 1][3];
+  double cr[CHEB ? NPT : 1][3], cdi[CHEB ? NPT : 1][6], cxo[CHEB ? NPT : 1][3];
   double c_sigma = 1.0, c_delta = 1.0, c_theta = 1.0;
   if (CHEB && a.cheb_mode) {
     c_sigma = a.cheb_scal[MS_SIGMA];
     c_delta = a.cheb_scal[MS_DELTA];
     c_theta = a.cheb_scal[MS_THETA];
     const double* __restrict__ dinv = (const double*)a.dinv;
+    const double* __restrict__ binv = a.cheb_binv;
 #pragma unroll
     for (int r = 0; r < NPT; ++r) {
       const int t = tid + NT * r;
-      const long g = 3L * (t < nown ? gn[r] : 0);
+      const bool own = t < nown;
+      const long v = own ? gn[r] : 0, g = 3L * v;
 #pragma unroll
       for (int c3 = 0; c3 < 3; ++c3) {
-        const bool own = t < nown;
         cr[r][c3] = own ? a.cheb_r[g + c3] : 0.0;
-        cdi[r][c3] = own && a.cheb_mode != 2 ? dinv[g + c3] : 0.0;
         cxo[r][c3] = own && a.cheb_mode != 3 ? a.cheb_x[g + c3] : 0.0;
       }
+      const bool need = own && a.cheb_mode != 2;
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        cdi[r][k] = !need ? 0.0 : (binv ? binv[6 * v + k] : (k < 3 ? dinv[g + k] : 0.0));
     }
   }
   VT cep[EPT];
@@ -973,6 +980,35 @@ __global__ __launch_bounds__(chunk_threads(PREC, COARSE)) void k_apply_chunks(UA
           if (a.cheb_mode != 2) Y[g + comp] = 0;
         } else {
           Y[g + comp] = X[g + comp];
+        }
+      }
+      continue;
+    }
+    if (CHEB && a.cheb_mode && a.cheb_binv) {
+      // node-block smoothing: the node's three residual components first,
+      // then the inverse node block (constrained components have identity
+      // rows in it and a zero residual, so they stay zero)
+      double q3[3], rv[3], zb[3];
+#pragma unroll
+      for (int comp = 0; comp < 3; ++comp) {
+        q3[comp] = ((fb[r] >> comp) & 1) ? 0.0 : ys[t * 3 + comp];
+        rv[comp] = cr[r][comp] - q3[comp];
+        a.cheb_r[g + comp] = rv[comp];
+      }
+      if (a.cheb_mode != 2) {
+        double b6[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) b6[k] = cdi[r][k];
+        block_apply<double>(b6, rv, zb);
+      }
+#pragma unroll
+      for (int comp = 0; comp < 3; ++comp) {
+        const double dv = (double)xs[t * 3 + comp];
+        if (a.cheb_mode == 3) {
+          Y[g + comp] = (VT)(zb[comp] / ch_t);
+        } else {
+          a.cheb_x[g + comp] = cxo[r][comp] + dv;
+          if (a.cheb_mode == 1) Y[g + comp] = (VT)(ch_a * dv + ch_c * zb[comp]);
         }
       }
       continue;
@@ -1347,7 +1383,7 @@ int launch_apply(amrto_ctx* ctx, const void* x, void* y, int prec) { return appl
 
 // the octree FP64 operator pass with the multigrid smoothing epilogue (see UArgs)
 int apply_cheb(amrto_ctx* ctx, const double* d, double* dnew, int mode, int step, const double* scal,
-               const double* dinv, double* x, double* r) {
+               const double* dinv, double* x, double* r, const double* binv) {
   if (ctx->uniform) return ctx->fail(AMRTO_ESTATE, "apply_cheb: octree meshes only");
   if (mode < 1 || mode > 3 || !scal || !dinv || !x || !r || (mode != 2 && (!dnew || dnew == d)))
     return ctx->fail(AMRTO_EINVAL, "apply_cheb: bad arguments");
@@ -1360,6 +1396,7 @@ int apply_cheb(amrto_ctx* ctx, const double* d, double* dnew, int mode, int step
   a.cheb_scal = scal;
   a.cheb_x = x;
   a.cheb_r = r;
+  a.cheb_binv = binv;
   CgArgs cg;
   std::memset(&cg, 0, sizeof cg);
   return launch_t<double, P_F64, false>(ctx, a, cg);

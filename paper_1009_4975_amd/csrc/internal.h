@@ -270,7 +270,7 @@ int mask_vector_n(amrto_ctx* ctx, double* x, int count);
 int launch_zt(amrto_ctx* ctx, const double* v);
 int apply_stop(amrto_ctx* ctx, const void* x, void* y, int prec, const double* stop);
 int apply_cheb(amrto_ctx* ctx, const double* d, double* dnew, int mode, int step, const double* scal,
-               const double* dinv, double* x, double* r);
+               const double* dinv, double* x, double* r, const double* binv = nullptr);
 int apply_fused(amrto_ctx* ctx, const void* z, const void* pold, void* pnew, void* q, int prec, const CgArgs& cg);
 int block3_setup(amrto_ctx* ctx);
 template <typename VT, typename BT>

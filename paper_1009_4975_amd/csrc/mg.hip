@@ -56,6 +56,7 @@ struct MgLevel {
   int lanes = 4;                 // lanes per node in the block-row pass
   int rlanes = 4;                // lanes per node in the restriction to this level
   double* dinv = nullptr;        // owned except on level 0
+  const double* binv = nullptr;  // level 0 with node-block smoothing: the inverse node blocks (6 per node)
   double *x = nullptr, *r = nullptr, *d = nullptr, *q = nullptr, *b = nullptr;
   double* scal = nullptr;        // MS_COUNT
   // coarse side of the transfer to the next finer level (this level k >= 1):
@@ -71,6 +72,7 @@ struct MgData {
   MgLevel lv[MG_LMAX];
   int degree = 2, coarse_degree = 2, power_its = 20;
   double ratio = 10.0, hi_factor = 1.1;
+  bool blocks0 = false;          // level 0 smooths with the inverse node blocks
   bool user_bounds = false;
   double lam_user[MG_LMAX] = {};
   double* part = nullptr;   // 4 x MG_RED
@@ -182,6 +184,7 @@ struct MgUpd {
   int step;                 // Chebyshev step (MG_CHEB)
   const double* scal;       // MS_* of the level
   const double* dinv;
+  const double* binv;       // set: node-block smoothing (level 0)
   double *x, *r, *d;
   double* dn;               // where the next direction goes (MG_CHEB, MG_CORR): d itself only
                             // when no thread of the pass reads other nodes' d
@@ -238,6 +241,99 @@ __device__ __forceinline__ void mg_update(const MgUpd& u, long i, bool cons, dou
   }
 }
 
+// z = M^-1 r at node v: the diagonal inverse, or with binv the inverse node
+// block (six entries xx, yy, zz, xy, xz, yz)
+__device__ __forceinline__ void mg_minv(const double* __restrict__ dinv, const double* __restrict__ binv, long v,
+                                        const double (&r)[3], double (&z)[3]) {
+  if (binv) {
+    block_apply<double>(binv + 6 * v, r, z);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) z[c] = dinv[3 * v + c] * r[c];
+  }
+}
+
+// y = B x at node v, B the node block itself (the inverse of the stored
+// inverse, symmetric: cofactors over the determinant)
+__device__ __forceinline__ void mg_bnode(const double* __restrict__ binv, long v, const double (&x)[3],
+                                         double (&y)[3]) {
+  const double* b = binv + 6 * v;
+  const double a0 = b[0], a1 = b[1], a2 = b[2], a3 = b[3], a4 = b[4], a5 = b[5];
+  const double c00 = a1 * a2 - a5 * a5, c01 = a4 * a5 - a3 * a2, c02 = a3 * a5 - a1 * a4;
+  const double c11 = a0 * a2 - a4 * a4, c12 = a3 * a4 - a0 * a5, c22 = a0 * a1 - a3 * a3;
+  const double inv_det = 1.0 / (a0 * c00 + a3 * c01 + a4 * c02);
+  y[0] = (c00 * x[0] + c01 * x[1] + c02 * x[2]) * inv_det;
+  y[1] = (c01 * x[0] + c11 * x[1] + c12 * x[2]) * inv_det;
+  y[2] = (c02 * x[0] + c12 * x[1] + c22 * x[2]) * inv_det;
+}
+
+// the update of mode u.mode for the three components of node v after q = (A d)_v;
+// with node blocks (u.binv) the modes that apply M^-1 work on the node at once
+__device__ __forceinline__ void mg_update_node(const MgUpd& u, long v, uint8_t f, const double (&q)[3], double& t1,
+                                               double& t2) {
+  const bool blk = u.binv != nullptr &&
+                   (u.mode == MG_CHEB || u.mode == MG_CORR || u.mode == MG_POWER || u.mode == MG_RAYLEIGH);
+  if (!blk) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const bool cs = mg_cons(f, c);
+      mg_update(u, 3 * v + c, cs, cs ? 0.0 : q[c], t1, t2);
+    }
+    return;
+  }
+  bool cs[3];
+  double w[3], z[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) cs[c] = mg_cons(f, c);
+  switch (u.mode) {
+    case MG_CHEB: {
+      const double sigma = u.scal[MS_SIGMA], delta = u.scal[MS_DELTA];
+      double rho = 1.0 / sigma;
+      for (int s = 0; s < u.step; ++s) rho = 1.0 / (2.0 * sigma - rho);
+      const double rho1 = 1.0 / (2.0 * sigma - rho);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) w[c] = cs[c] ? 0.0 : u.r[3 * v + c] - q[c];
+      mg_minv(u.dinv, u.binv, v, w, z);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const long i = 3 * v + c;
+        const double dd = cs[c] ? 0.0 : u.d[i];
+        u.x[i] = cs[c] ? 0.0 : u.x[i] + dd;
+        u.r[i] = w[c];
+        u.dn[i] = cs[c] ? 0.0 : rho1 * rho * dd + (2.0 * rho1 / delta) * z[c];
+      }
+      break;
+    }
+    case MG_CORR:
+#pragma unroll
+      for (int c = 0; c < 3; ++c) w[c] = cs[c] ? 0.0 : u.r[3 * v + c] - q[c];
+      mg_minv(u.dinv, u.binv, v, w, z);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        u.r[3 * v + c] = w[c];
+        u.dn[3 * v + c] = cs[c] ? 0.0 : z[c] / u.scal[MS_THETA];
+      }
+      break;
+    case MG_POWER:
+#pragma unroll
+      for (int c = 0; c < 3; ++c) w[c] = cs[c] ? 0.0 : q[c];
+      mg_minv(u.dinv, u.binv, v, w, z);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) u.y[3 * v + c] = cs[c] ? 0.0 : z[c];
+      break;
+    default: {  // MG_RAYLEIGH: x.q and x.(B x) over the free components
+#pragma unroll
+      for (int c = 0; c < 3; ++c) w[c] = cs[c] ? 0.0 : u.xin[3 * v + c];
+      mg_bnode(u.binv, v, w, z);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        t1 += w[c] * (cs[c] ? 0.0 : q[c]);
+        t2 += w[c] * z[c];
+      }
+    }
+  }
+}
+
 // per node: q = (A_k in)_v from the level's block rows (3 x 3 blocks of the
 // assembled Galerkin operator, supported columns zeroed), then the update of
 // mode u.mode; LANES lanes per node (lane c < 3 updates component c)
@@ -287,11 +383,8 @@ __global__ __launch_bounds__(256) void k_mg_vec0(const double* __restrict__ q, c
   __shared__ double sh[16];
   double t1 = 0.0, t2 = 0.0;
   for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nn; v += gridDim.x * blockDim.x) {
-    const uint8_t f = flag[v];
-    for (int c = 0; c < 3; ++c) {
-      const bool cs = mg_cons(f, c);
-      mg_update(u, 3L * v + c, cs, cs ? 0.0 : q[3L * v + c], t1, t2);
-    }
+    const double qv[3] = {q[3L * v], q[3L * v + 1], q[3L * v + 2]};
+    mg_update_node(u, v, flag[v], qv, t1, t2);
   }
   if (u.mode == MG_RAYLEIGH) {
     block_sum2(t1, t2, sh);
@@ -775,23 +868,31 @@ __global__ __launch_bounds__(256) void k_mg_mask_copy(const double* __restrict__
 // r = b - q masked, the level-0 smoother started from r, partials r.r and b.b
 __global__ __launch_bounds__(256) void k_mgcg_start(const double* __restrict__ b, const double* __restrict__ q,
                                                     const uint8_t* __restrict__ flag, double* __restrict__ r,
-                                                    long n, const double* __restrict__ dinv,
+                                                    long nn, const double* __restrict__ dinv,
+                                                    const double* __restrict__ binv,
                                                     const double* __restrict__ s0, double* __restrict__ x0,
                                                     double* __restrict__ r0, double* __restrict__ d0,
                                                     double* __restrict__ part) {
   __shared__ double sh[16];
   double rr = 0.0, bb = 0.0;
   const double th = s0[MS_THETA];
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const bool cs = mg_cons(flag[i / 3], (int)(i % 3));
-    const double bi = cs ? 0.0 : b[i];
-    const double ri = cs ? 0.0 : bi - q[i];
-    r[i] = ri;
-    x0[i] = 0.0;
-    r0[i] = ri;
-    d0[i] = dinv[i] * ri / th;
-    rr += ri * ri;
-    bb += bi * bi;
+  for (long v = blockIdx.x * (long)blockDim.x + threadIdx.x; v < nn; v += (long)gridDim.x * blockDim.x) {
+    double rv[3], z[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const long i = 3 * v + c;
+      const bool cs = mg_cons(flag[v], c);
+      const double bi = cs ? 0.0 : b[i];
+      rv[c] = cs ? 0.0 : bi - q[i];
+      r[i] = rv[c];
+      x0[i] = 0.0;
+      r0[i] = rv[c];
+      rr += rv[c] * rv[c];
+      bb += bi * bi;
+    }
+    mg_minv(dinv, binv, v, rv, z);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) d0[3 * v + c] = z[c] / th;
   }
   block_sum2(rr, bb, sh);
   if (threadIdx.x == 0) {
@@ -842,7 +943,8 @@ __global__ __launch_bounds__(256) void k_mgcg_step(double* __restrict__ x, doubl
                                                    const double* __restrict__ p, const double* __restrict__ q,
                                                    long n, const double* __restrict__ part_pq, int n_pq,
                                                    double* __restrict__ scal, int it,
-                                                   const double* __restrict__ dinv, const double* __restrict__ s0,
+                                                   const double* __restrict__ dinv, const double* __restrict__ binv,
+                                                   const double* __restrict__ s0,
                                                    double* __restrict__ x0, double* __restrict__ r0,
                                                    double* __restrict__ d0) {
   __shared__ double sh[16];
@@ -855,13 +957,22 @@ __global__ __launch_bounds__(256) void k_mgcg_step(double* __restrict__ x, doubl
     return;
   }
   const double alpha = rz / pq, th = s0[MS_THETA];
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * q[i];
-    r[i] = ri;
-    x0[i] = 0.0;
-    r0[i] = ri;
-    d0[i] = dinv[i] * ri / th;
+  // per node (n = 3 nn): the smoother's start needs the node's three residual
+  // components together when it smooths with node blocks
+  for (long v = blockIdx.x * (long)blockDim.x + threadIdx.x; v < n / 3; v += (long)gridDim.x * blockDim.x) {
+    double rv[3], z[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const long i = 3 * v + c;
+      x[i] += alpha * p[i];
+      rv[c] = r[i] - alpha * q[i];
+      r[i] = rv[c];
+      x0[i] = 0.0;
+      r0[i] = rv[c];
+    }
+    mg_minv(dinv, binv, v, rv, z);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) d0[3 * v + c] = z[c] / th;
   }
 }
 
@@ -941,7 +1052,7 @@ int pass(amrto_ctx* ctx, int k, const double* in, const MgUpd& u) {
     // octree level 0: the smoothing update runs in the operator pass itself;
     // the next direction goes to the other buffer of the pair (d, q)
     const int mode = u.mode == MG_CHEB ? 1 : (u.mode == MG_CHEB_LAST ? 2 : 3);
-    const int rc = apply_cheb(ctx, L.d, L.q, mode, u.step, L.scal, L.dinv, L.x, L.r);
+    const int rc = apply_cheb(ctx, L.d, L.q, mode, u.step, L.scal, L.dinv, L.x, L.r, L.binv);
     if (rc) return rc;
     if (mode != 2) std::swap(L.d, L.q);
     return AMRTO_OK;
@@ -963,6 +1074,7 @@ MgUpd upd(MgLevel& L, int mode, int step = 0) {
   u.step = step;
   u.scal = L.scal;
   u.dinv = L.dinv;
+  u.binv = L.binv;
   u.x = L.x;
   u.r = L.r;
   u.d = L.d;
@@ -998,25 +1110,32 @@ int vcycle_from(amrto_ctx* ctx, int k) {
   return hipGetLastError() == hipSuccess ? AMRTO_OK : ctx->fail(AMRTO_EHIP, "multigrid V-cycle");
 }
 
-// level-0 smoother start from the right-hand side b (device): x = 0, r = b, d = D^-1 b / theta
+// level-0 smoother start from the right-hand side b (device): x = 0, r = b, d = M^-1 b / theta
 __global__ __launch_bounds__(256) void k_mg_start0(const double* __restrict__ b, const uint8_t* __restrict__ flag,
-                                                   const double* __restrict__ dinv, const double* __restrict__ scal,
-                                                   double* __restrict__ x, double* __restrict__ r,
-                                                   double* __restrict__ d, long n) {
-  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double bi = mg_cons(flag[i / 3], (int)(i % 3)) ? 0.0 : b[i];
-  x[i] = 0.0;
-  r[i] = bi;
-  d[i] = dinv[i] * bi / scal[MS_THETA];
+                                                   const double* __restrict__ dinv, const double* __restrict__ binv,
+                                                   const double* __restrict__ scal, double* __restrict__ x,
+                                                   double* __restrict__ r, double* __restrict__ d, long nn) {
+  const long v = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (v >= nn) return;
+  double bv[3], z[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    bv[c] = mg_cons(flag[v], c) ? 0.0 : b[3 * v + c];
+    x[3 * v + c] = 0.0;
+    r[3 * v + c] = bv[c];
+  }
+  mg_minv(dinv, binv, v, bv, z);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) d[3 * v + c] = z[c] / scal[MS_THETA];
 }
 
 int vcycle(amrto_ctx* ctx, const double* b) {
   MgData* g = ctx->mg;
   MgLevel& L = g->lv[0];
   const long n = 3L * L.nn;
-  hipLaunchKernelGGL(k_mg_start0, dim3(blocks_for(n)), dim3(256), 0, ctx->stream, b, L.flag, L.dinv, L.scal, L.x,
-                     L.r, L.d, n);
+  (void)n;
+  hipLaunchKernelGGL(k_mg_start0, dim3(blocks_for(L.nn)), dim3(256), 0, ctx->stream, b, L.flag, L.dinv, L.binv,
+                     L.scal, L.x, L.r, L.d, (long)L.nn);
   return vcycle_from(ctx, 0);
 }
 
@@ -1025,6 +1144,12 @@ int vcycle(amrto_ctx* ctx, const double* b) {
 int mg_numeric(amrto_ctx* ctx) {
   MgData* g = ctx->mg;
   g->lv[0].dinv = ctx->d_dinv;
+  g->lv[0].binv = nullptr;
+  if (g->blocks0) {  // the inverse node blocks of the current density
+    const int rc = block3_setup(ctx);
+    if (rc) return rc;
+    g->lv[0].binv = ctx->d_binv;
+  }
   for (int k = 1; k < g->nlev; ++k) {
     MgLevel& L = g->lv[k];
     MgLevel& F = g->lv[k - 1];
@@ -1430,11 +1555,11 @@ int amrto_mg_setup(amrto_ctx* ctx, const amrto_octree* tree, const amrto_mg_opts
   if (!ctx) return AMRTO_EINVAL;
   if (!ctx->has_mesh) return ctx->fail(AMRTO_ESTATE, "amrto_mg_setup: no mesh uploaded");
   if (!tree) return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: NULL tree");
-  amrto_mg_opts o{2, 10.0, 20, 1.1, 200, 1, 0};
+  amrto_mg_opts o{2, 10.0, 20, 1.1, 200, 1, 0, 0};
   if (opts) o = *opts;
   if (o.degree < 1 || o.degree > 8 || o.coarse_degree < 0 || o.coarse_degree > 8 || !(o.ratio > 1.0) ||
       o.power_its < 1 || o.power_its > 200 || !(o.hi_factor >= 1.0) || o.coarse_dofs < 3 || o.first < 1 ||
-      o.first > 2)
+      o.first > 2 || o.blocks0 < 0 || o.blocks0 > 1)
     return ctx->fail(AMRTO_EINVAL, "amrto_mg_setup: bad options");
   AMRTO_HIP(hipSetDevice(ctx->device));
   AMRTO_HIP(hipStreamSynchronize(ctx->stream));
@@ -1451,6 +1576,7 @@ int amrto_mg_setup(amrto_ctx* ctx, const amrto_octree* tree, const amrto_mg_opts
   g->ratio = o.ratio;
   g->power_its = o.power_its;
   g->hi_factor = o.hi_factor;
+  g->blocks0 = o.blocks0 != 0;
   for (int k = 0; k < g->nlev; ++k)
     if ((rc = upload_level(ctx, g, H, k))) {
       mg_free(ctx);
@@ -1633,8 +1759,8 @@ int amrto_mg_pcg(amrto_ctx* ctx, const double* b, double* u, double rtol, int32_
   AMRTO_HIP(hipMemcpyAsync(u, g->qv, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
   hipLaunchKernelGGL(k_mg_zero, dim3(blocks_for(n)), dim3(256), 0, ctx->stream, p0, p1, n);
   if ((rc = launch_apply(ctx, u, g->qv, AMRTO_FP64))) return rc;
-  hipLaunchKernelGGL(k_mgcg_start, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, b, g->qv, L0.flag, r, n, L0.dinv,
-                     L0.scal, L0.x, L0.r, L0.d, g->cpart);
+  hipLaunchKernelGGL(k_mgcg_start, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, b, g->qv, L0.flag, r, (long)L0.nn,
+                     L0.dinv, L0.binv, L0.scal, L0.x, L0.r, L0.d, g->cpart);
   hipLaunchKernelGGL(k_mgcg_start_scal, dim3(1), dim3(256), 0, ctx->stream, g->cpart, g->cs, tol2);
   AMRTO_HIP(hipGetLastError());
   int it = 0, status = AMRTO_NOT_CONVERGED;
@@ -1664,7 +1790,7 @@ int amrto_mg_pcg(amrto_ctx* ctx, const double* b, double* u, double rtol, int32_
       CgArgs cg{g->cs, g->cpart, ctx->d_partpq, 0, k, tol2, 0};
       if ((rc = apply_fused(ctx, g->z, pold, pnew, g->qv, AMRTO_FP64, cg))) return rc;
       hipLaunchKernelGGL(k_mgcg_step, dim3(RED_BLOCKS), dim3(256), 0, ctx->stream, u, r, pnew, g->qv, n,
-                         ctx->d_partpq, ctx->n_partpq, g->cs, k, L0.dinv, L0.scal, L0.x, L0.r, L0.d);
+                         ctx->d_partpq, ctx->n_partpq, g->cs, k, L0.dinv, L0.binv, L0.scal, L0.x, L0.r, L0.d);
     }
     AMRTO_HIP(hipGetLastError());
     it += batch;
