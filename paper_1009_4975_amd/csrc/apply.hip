@@ -78,21 +78,26 @@ struct UArgs {
 // around UT x UT owned node columns and marches upwards through a range of
 // node layers.  Per element layer each wave contracts four rows of 16
 // elements, one v_mfma_f32_16x16x32_bf16 tile per row (lane n + 16 q holds
-// DOFs 8q..8q+7 of element n; the element mean per component, summed across
-// the four lanes of an element, is removed before the hi + lo split), and
-// writes the element outputs scaled by c_e to LDS.  After a barrier the thread
+// nodes 2q and 2q + 1 of element n, shifted by the element's node-0 values
+// before the hi + lo split), and writes the element outputs scaled by c_e to
+// LDS.  After a barrier the thread
 // owning a node column adds, in fixed order, the bottom-face rows of the four
 // elements of this layer around its node and the top-face rows of the layer
 // below (carried in registers).  Node layers rotate through three LDS
-// buffers and are fetched two layers ahead.
+// buffers and are fetched two layers ahead; no load waited on inside a step is
+// issued after that step's prefetch (waits count loads in issue order, so such
+// a wait would also wait for the prefetch).
 template <bool FUSED>
 __global__ __launch_bounds__(256, FUSED ? 3 : 4) void k_apply_uniform_bf16(UArgs a, CgArgs cg) {
   using VT = float;
   constexpr int NL = UN * UN * 3;  // values of one staged node layer
-  constexpr int YS = 25;           // LDS stride of one element's 24 outputs (padded)
+  // element outputs, row-major: output DOF d of element e at d * YR + e; a
+  // stride of 4 mod 16 puts the 64 lanes of a row write (16 elements x 4 lane
+  // groups, rows 4q + r) on 64 distinct banks
+  constexpr int YR = UE * UE + 4;
   __shared__ VT xs[3][NL];
   __shared__ VT cs[3][UE * UE];  // element coefficients of the staged layers
-  __shared__ VT yel[UE * UE * YS + 256 * 4];  // + a slot per thread for the padding rows 24..31
+  __shared__ VT yel[24 * YR];
   __shared__ double sh[16];
   double beta = 0.0;
   if (FUSED) {
@@ -205,8 +210,23 @@ __global__ __launch_bounds__(256, FUSED ? 3 : 4) void k_apply_uniform_bf16(UArgs
 
   const int kbeg = max(z0 - 1, 0);
   const int kend = min(z1 - 1, nz - 1);
+  // A operand: K0 hi / lo rows 16 t + (lane & 15); slot i of lane group q is
+  // column 6 q + i (slots 6, 7 and rows 24..31 zero)
   bf16x8 ka[2][2];
-  load_k0_bf16((const uint16_t*)a.kb, ka);
+  {
+    const uint16_t* __restrict__ kb = (const uint16_t*)a.kb;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int part = 0; part < 2; ++part) {
+        const int m = n + 16 * t;
+        bf16x8 w;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          w[i] = bits_to_bf16((m < 24 && i < 6) ? kb[part * 576 + m * 24 + 6 * q + i] : (uint16_t)0);
+        ka[t][part] = w;
+      }
+  }
   Slot S0, S1;
   load(S0, kbeg);
   stage(S0, kbeg);
@@ -217,84 +237,93 @@ __global__ __launch_bounds__(256, FUSED ? 3 : 4) void k_apply_uniform_bf16(UArgs
 
   VT carry[3] = {0, 0, 0};
   double dot = 0.0;
-  // the DOFs this lane's group holds: d = 8 q + i (q = 3: padding, zeros);
-  // DOF d is component (c0 + i) mod 3 with c0 = 2q mod 3, so the lane keeps
-  // its per-component sums rotated by c0 (compile-time register indices)
-  const int c0 = (2 * q) % 3;
-  const float qv = q < 3 ? 1.f : 0.f;
-  int loff[8];     // LDS offset of DOF i within a staged layer pair (element at the tile origin)
-  bool ltop[8];    // DOF i lies on the element's top face
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    // padding lanes (q = 3) read the addresses of q = 2 (an LDS broadcast,
-    // no extra bank cycles) and scale the values by zero
-    const int d = 8 * min(q, 2) + i;
-    const int aa = d / 3, c = d % 3;
-    ltop[i] = (aa >> 2) != 0;
-    loff[i] = (((aa >> 1) & 1) * UN + n + (aa & 1)) * 3 + c;
-  }
+  // B operand: lane n + 16 q holds element n's nodes 2q and 2q + 1 (slots
+  // 0..5: six consecutive values of one staged layer, component = slot mod 3;
+  // slots 6, 7: zero, against zero K0 columns).  Nodes 0..3 lie on the bottom
+  // face (layer k), 4..7 on the top face (layer k + 1); the lane's base offset
+  // includes this wave's first element row, and a row adds a compile-time
+  // offset.
+  const int wrow = 4 * wave * UN * 3;
+  const int lane_off = wrow + ((q & 1) * UN + n) * 3;
+  const int ref_off = wrow + n * 3;  // node 0 of the element (bottom face)
+  const VT* __restrict__ xsb = &xs[0][0];
+  const int ceoff = 4 * wave * UE + n;
+  VT* __restrict__ yeb = yel + 4 * q * YR + 4 * wave * UE + n;
   // element layer k: contract, finish node layer k, stage layer k + 2
   auto step = [&](int k, Slot& Rst, Slot& Rld) {
-    if (k + 3 <= nz) load(Rld, k + 3);
-    const VT* bot = xs[k % 3];
-    const VT* top = xs[(k + 1) % 3];
-#pragma unroll 2
-    for (int r = 0; r < 4; ++r) {
-      const int jj = 4 * wave + r;
-      float u[8];
-      float t3[3] = {0.f, 0.f, 0.f};  // t3[j]: component (c0 + j) mod 3
+    // plain apply: x of the owned node (rows of fixed DOFs copy it), requested
+    // before the prefetch; the prefetch itself is unconditional (layers past
+    // the top are clamped and never staged)
+    VT xo[3];
+    if (!FUSED) {
+      const VT* Xk = X + 3 * (sxy * k + onode);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const float v = (ltop[i] ? top : bot)[jj * UN * 3 + loff[i]] * qv;
-        u[i] = v;
-        t3[i % 3] += v;
-      }
-      // back to component order (the lane groups rotate differently), then
-      // summed over the element's four lanes
-      float s3[3];
+      for (int c = 0; c < 3; ++c) xo[c] = Xk[c];
+    }
+    load(Rld, k + 3);
+    const int bsl = (k % 3) * NL;
+    const VT* __restrict__ xl = xsb + (q >= 2 ? ((k + 1) % 3) * NL : bsl) + lane_off;
+    const VT* __restrict__ xr = xsb + bsl + ref_off;
+    const VT* __restrict__ csk = cs[k % 3] + ceoff;
+    // one element row: operands (K0 annihilates a translation, so any
+    // per-component shift of the element's values leaves its product
+    // unchanged; taking off node 0's values makes the split relative to the
+    // variation within the element), products, and the scaled output rows
+    auto prep = [&](int r, bf16x8& bh, bf16x8& bl, float& ce) {
+      const int ro = r * UN * 3;
+      float sft[3], v[6];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int j = (c - c0 + 3) % 3;
-        s3[c] = j == 0 ? t3[0] : (j == 1 ? t3[1] : t3[2]);
-      }
-      float m3[3];
+      for (int j = 0; j < 3; ++j) sft[j] = xr[ro + j];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        float t = s3[c] + __shfl_xor(s3[c], 16, 64);
-        t += __shfl_xor(t, 32, 64);
-        m3[c] = 0.125f * t;
-      }
-      float mr[3];  // mr[j] = mean of component (c0 + j) mod 3
+      for (int i = 0; i < 6; ++i) v[i] = xl[ro + i];
+      ce = csk[r * UE];
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const int c = (c0 + j) % 3;
-        mr[j] = c == 0 ? m3[0] : (c == 1 ? m3[1] : m3[2]);
-      }
-      bf16x8 bh, bl;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const float v = (u[i] - mr[i % 3]) * qv;
-        const __bf16 h = (__bf16)v;
+      for (int i = 0; i < 6; ++i) {
+        const float t = v[i] - sft[i % 3];
+        const __bf16 h = (__bf16)t;
         bh[i] = h;
-        bl[i] = (__bf16)(v - (float)h);
+        bl[i] = (__bf16)(t - (float)h);
       }
-      // the two row tiles' accumulation chains interleaved
+      bh[6] = bh[7] = bl[6] = bl[7] = (__bf16)0.f;
+    };
+    auto mm = [&](const bf16x8& bh, const bf16x8& bl, f32x4& d0, f32x4& d1) {
       const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-      f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[0][0], bh, z, 0, 0, 0);
-      f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[1][0], bh, z, 0, 0, 0);
+      d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[0][0], bh, z, 0, 0, 0);
+      d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[1][0], bh, z, 0, 0, 0);
       d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[0][1], bh, d0, 0, 0, 0);
       d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[1][1], bh, d1, 0, 0, 0);
       d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[0][0], bl, d0, 0, 0, 0);
       d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[1][0], bl, d1, 0, 0, 0);
-      const float ce = cs[k % 3][jj * UE + n];
-      VT* ye = yel + (jj * UE + n) * YS;
-      VT* ye1 = q < 2 ? ye + 16 + 4 * q : yel + UE * UE * YS + 4 * tid;  // rows 24..31: the thread's spare slot
+    };
+    auto put = [&](int r, float ce, const f32x4& d0, const f32x4& d1) {
+      VT* ye = yeb + r * UE;
 #pragma unroll
-      for (int r4 = 0; r4 < 4; ++r4) {
-        ye[4 * q + r4] = ce * d0[r4];
-        ye1[r4] = ce * d1[r4];
+      for (int r4 = 0; r4 < 4; ++r4) ye[r4 * YR] = ce * d0[r4];
+      if (q < 2) {  // rows 24..31 of the second tile are padding
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4) ye[(16 + r4) * YR] = ce * d1[r4];
       }
-    }
+    };
+    // rows in pairs, in an order that keeps LDS reads ahead of the writes
+    // (the compiler keeps LDS accesses in program order): the operands of
+    // rows 2 and 3 are read while the products of rows 0 and 1 run
+    bf16x8 bh0, bl0, bh1, bl1;
+    float ce0, ce1;
+    f32x4 d00, d01, d10, d11;
+    prep(0, bh0, bl0, ce0);
+    prep(1, bh1, bl1, ce1);
+    mm(bh0, bl0, d00, d01);
+    mm(bh1, bl1, d10, d11);
+    bf16x8 bh2, bl2, bh3, bl3;
+    float ce2, ce3;
+    prep(2, bh2, bl2, ce2);
+    prep(3, bh3, bl3, ce3);
+    put(0, ce0, d00, d01);
+    put(1, ce1, d10, d11);
+    mm(bh2, bl2, d00, d01);
+    mm(bh3, bl3, d10, d11);
+    put(2, ce2, d00, d01);
+    put(3, ce3, d10, d11);
     __syncthreads();
     // node layer k: carried top rows of element layer k - 1 plus the bottom
     // rows of element layer k, four elements in fixed order
@@ -304,11 +333,11 @@ __global__ __launch_bounds__(256, FUSED ? 3 : 4) void k_apply_uniform_bf16(UArgs
       for (int e = 0; e < 4; ++e) {
         const int ii = oli - 1 + (e & 1), jj = olj - 1 + (e >> 1);
         const int av = (oli - ii) + 2 * (olj - jj);
-        const VT* ye = yel + (jj * UE + ii) * YS;
+        const VT* ye = yel + jj * UE + ii;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          yb[c] += ye[3 * av + c];
-          yt[c] += ye[3 * (av + 4) + c];
+          yb[c] += ye[(3 * av + c) * YR];
+          yt[c] += ye[(3 * (av + 4) + c) * YR];
         }
       }
       if (k >= z0) {
@@ -325,7 +354,7 @@ __global__ __launch_bounds__(256, FUSED ? 3 : 4) void k_apply_uniform_bf16(UArgs
             Y[g + c] = qv;
             dot += (double)pn * (double)qv;
           } else {
-            Y[g + c] = fc ? X[g + c] : acc;
+            Y[g + c] = fc ? xo[c] : acc;
           }
         }
       }

@@ -2,7 +2,7 @@
 
 Tolerances: FP64 operator results within 1e-12 of max |y| (sums of 576
 products per node; rounding order differs); FP32 within 5e-6; BF16 operands
-(K0 and the element-mean-shifted displacements each split hi + lo in BF16,
+(K0 and the shifted element displacements each split hi + lo in BF16,
 three MFMA products, FP32 accumulation) within 1e-4 of max |y|.  Solutions are compared at 1e-8 relative
 error after solves to a 1e-12 relative residual.
 """
@@ -111,7 +111,7 @@ def test_pcg_uniform_edge_shapes_match_direct(lib, dims):
 @pytest.mark.parametrize("prec,tol", [(1, 5e-6), (2, 1e-4)])
 def test_apply_reduced_precision(pair_rho, prec, tol):
     """FP32 and BF16 contractions against the FP64 oracle.  BF16 bound: K0 and
-    the mean-free element displacement are each split hi + lo in BF16 (three
+    the shifted element displacement are each split hi + lo in BF16 (three
     MFMA products, FP32 accumulation), good to about 1.3e-5 of an element's
     product and at most eight products per node, so 1e-4 of max |y|; a
     hi-only contraction (about 2^-9) misses it by an order of magnitude
