@@ -79,14 +79,14 @@ struct UArgs {
 // node layers.  Per element layer each wave contracts four rows of 16
 // elements, one v_mfma_f32_16x16x32_bf16 tile per row (lane n + 16 q holds
 // nodes 2q and 2q + 1 of element n, shifted by the element's node-0 values
-// before the hi + lo split), and writes the element outputs scaled by c_e to
-// LDS.  After a barrier the thread
-// owning a node column adds, in fixed order, the bottom-face rows of the four
-// elements of this layer around its node and the top-face rows of the layer
-// below (carried in registers).  Node layers rotate through three LDS
-// buffers and are fetched two layers ahead; no load waited on inside a step is
-// issued after that step's prefetch (waits count loads in issue order, so such
-// a wait would also wait for the prefetch).
+// before the hi + lo split), and writes the element outputs K0 u_e to LDS.
+// After a barrier the thread owning a node column adds, in fixed order, the
+// bottom-face rows of the four elements of this layer around its node, each
+// scaled by its c_e, and the top-face rows of the layer below (carried in
+// registers).  Node layers rotate through three LDS buffers and are fetched
+// two layers ahead; no load waited on inside a step is issued after that
+// step's prefetch (waits count loads in issue order, so such a wait would
+// also wait for the prefetch).
 template <bool FUSED>
 __global__ __launch_bounds__(256, FUSED ? 3 : 4) void k_apply_uniform_bf16(UArgs a, CgArgs cg) {
   using VT = float;
@@ -247,7 +247,6 @@ __global__ __launch_bounds__(256, FUSED ? 3 : 4) void k_apply_uniform_bf16(UArgs
   const int lane_off = wrow + ((q & 1) * UN + n) * 3;
   const int ref_off = wrow + n * 3;  // node 0 of the element (bottom face)
   const VT* __restrict__ xsb = &xs[0][0];
-  const int ceoff = 4 * wave * UE + n;
   VT* __restrict__ yeb = yel + 4 * q * YR + 4 * wave * UE + n;
   // element layer k: contract, finish node layer k, stage layer k + 2
   auto step = [&](int k, Slot& Rst, Slot& Rld) {
@@ -264,27 +263,33 @@ __global__ __launch_bounds__(256, FUSED ? 3 : 4) void k_apply_uniform_bf16(UArgs
     const int bsl = (k % 3) * NL;
     const VT* __restrict__ xl = xsb + (q >= 2 ? ((k + 1) % 3) * NL : bsl) + lane_off;
     const VT* __restrict__ xr = xsb + bsl + ref_off;
-    const VT* __restrict__ csk = cs[k % 3] + ceoff;
     // one element row: operands (K0 annihilates a translation, so any
     // per-component shift of the element's values leaves its product
     // unchanged; taking off node 0's values makes the split relative to the
     // variation within the element), products, and the scaled output rows
-    auto prep = [&](int r, bf16x8& bh, bf16x8& bl, float& ce) {
+    // hi = t with the low 16 bits cleared (truncation: t - hi is exact in
+    // FP32 and below 2^-7 |t|), lo = t - hi rounded to BF16; two hi parts
+    // pack into one register from their high halves
+    auto prep = [&](int r, bf16x8& bh, bf16x8& bl) {
       const int ro = r * UN * 3;
       float sft[3], v[6];
 #pragma unroll
       for (int j = 0; j < 3; ++j) sft[j] = xr[ro + j];
 #pragma unroll
       for (int i = 0; i < 6; ++i) v[i] = xl[ro + i];
-      ce = csk[r * UE];
+      uint32_t tb[6];
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
         const float t = v[i] - sft[i % 3];
-        const __bf16 h = (__bf16)t;
-        bh[i] = h;
-        bl[i] = (__bf16)(t - (float)h);
+        tb[i] = __float_as_uint(t);
+        bl[i] = (__bf16)(t - __uint_as_float(tb[i] & 0xffff0000u));
       }
-      bh[6] = bh[7] = bl[6] = bl[7] = (__bf16)0.f;
+      bl[6] = bl[7] = (__bf16)0.f;
+      uint32_t hp[4];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) hp[i] = (tb[2 * i] >> 16) | (tb[2 * i + 1] & 0xffff0000u);
+      hp[3] = 0u;
+      bh = __builtin_bit_cast(bf16x8, hp);
     };
     auto mm = [&](const bf16x8& bh, const bf16x8& bl, f32x4& d0, f32x4& d1) {
       const f32x4 z = {0.f, 0.f, 0.f, 0.f};
@@ -295,35 +300,24 @@ __global__ __launch_bounds__(256, FUSED ? 3 : 4) void k_apply_uniform_bf16(UArgs
       d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[0][0], bl, d0, 0, 0, 0);
       d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[1][0], bl, d1, 0, 0, 0);
     };
-    auto put = [&](int r, float ce, const f32x4& d0, const f32x4& d1) {
+    // unscaled K0 u_e rows (c_e is applied by the node owner)
+    auto put = [&](int r, const f32x4& d0, const f32x4& d1) {
       VT* ye = yeb + r * UE;
 #pragma unroll
-      for (int r4 = 0; r4 < 4; ++r4) ye[r4 * YR] = ce * d0[r4];
+      for (int r4 = 0; r4 < 4; ++r4) ye[r4 * YR] = d0[r4];
       if (q < 2) {  // rows 24..31 of the second tile are padding
 #pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4) ye[(16 + r4) * YR] = ce * d1[r4];
+        for (int r4 = 0; r4 < 4; ++r4) ye[(16 + r4) * YR] = d1[r4];
       }
     };
-    // rows in pairs, in an order that keeps LDS reads ahead of the writes
-    // (the compiler keeps LDS accesses in program order): the operands of
-    // rows 2 and 3 are read while the products of rows 0 and 1 run
-    bf16x8 bh0, bl0, bh1, bl1;
-    float ce0, ce1;
-    f32x4 d00, d01, d10, d11;
-    prep(0, bh0, bl0, ce0);
-    prep(1, bh1, bl1, ce1);
-    mm(bh0, bl0, d00, d01);
-    mm(bh1, bl1, d10, d11);
-    bf16x8 bh2, bl2, bh3, bl3;
-    float ce2, ce3;
-    prep(2, bh2, bl2, ce2);
-    prep(3, bh3, bl3, ce3);
-    put(0, ce0, d00, d01);
-    put(1, ce1, d10, d11);
-    mm(bh2, bl2, d00, d01);
-    mm(bh3, bl3, d10, d11);
-    put(2, ce2, d00, d01);
-    put(3, ce3, d10, d11);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      bf16x8 bh, bl;
+      f32x4 d0, d1;
+      prep(r, bh, bl);
+      mm(bh, bl, d0, d1);
+      put(r, d0, d1);
+    }
     __syncthreads();
     // node layer k: carried top rows of element layer k - 1 plus the bottom
     // rows of element layer k, four elements in fixed order
@@ -334,10 +328,11 @@ __global__ __launch_bounds__(256, FUSED ? 3 : 4) void k_apply_uniform_bf16(UArgs
         const int ii = oli - 1 + (e & 1), jj = olj - 1 + (e >> 1);
         const int av = (oli - ii) + 2 * (olj - jj);
         const VT* ye = yel + jj * UE + ii;
+        const VT ce = cs[k % 3][jj * UE + ii];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          yb[c] += ye[(3 * av + c) * YR];
-          yt[c] += ye[(3 * (av + 4) + c) * YR];
+          yb[c] = fmaf(ce, ye[(3 * av + c) * YR], yb[c]);
+          yt[c] = fmaf(ce, ye[(3 * (av + 4) + c) * YR], yt[c]);
         }
       }
       if (k >= z0) {
