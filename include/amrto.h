@@ -557,8 +557,12 @@ int amrto_mg_restrict(amrto_ctx* ctx, int32_t k, const double* rf, double* rc);
 int amrto_mg_pass_times(amrto_ctx* ctx, int32_t reps, double* us);
 /* CG in FP64 on A~ u~ = b preconditioned by one V-cycle per iteration, from
  * the initial guess in u (constrained entries ignored), to ||r|| <= rtol
- * ||b||; the numeric set-up runs first after a density change.  On exit
- * u = T u~ with hanging DOFs recovered (Eq. (9)), as from amrto_pcg.
+ * ||b||; the numeric set-up runs first after a density change.  check_every
+ * (>= 1) is the shortest run of iterations between host convergence checks;
+ * runs grow to at most 8x this while the residual's convergence rate says
+ * the target is further away (iterations queued past convergence leave u,
+ * the iteration count and the residual as they were).  On exit u = T u~
+ * with hanging DOFs recovered (Eq. (9)), as from amrto_pcg.
  * Returns AMRTO_OK, AMRTO_NOT_CONVERGED or AMRTO_EBREAKDOWN. */
 int amrto_mg_pcg(amrto_ctx* ctx, const double* b, double* u, double rtol, int32_t max_it,
                  int32_t check_every, amrto_solve_stats* stats);

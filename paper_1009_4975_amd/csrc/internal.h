@@ -285,6 +285,12 @@ int apply_fused_coarse(amrto_ctx* ctx, const void* r, const void* minv, const vo
                        int prec, const CgArgs& cg, bool block3 = false, double* zq_part = nullptr);
 int apply_blocks(const amrto_ctx* ctx);
 void uniform_grid(const amrto_ctx* ctx, int& tiles_x, int& tiles_y, int& zchunk, int& n_tiles, int& grid);
+// iterations a Krylov solve enqueues before its next host convergence check,
+// from r.r at the start (rr0), at the previous check (rr_prev, last
+// iterations ago) and now (rr, its iterations in): check_every while nothing
+// is known, then 3/4 of the iterations the residual still needs to reach
+// target, between check_every and 8 check_every, at most left
+int next_batch(double rr0, double rr_prev, double rr, int its, int last, double target, int check_every, int left);
 
 // helpers
 void k0_unit_cube(double nu, double* K);  // 24 x 24, E = 1

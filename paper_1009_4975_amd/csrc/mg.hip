@@ -1763,7 +1763,12 @@ int amrto_mg_pcg(amrto_ctx* ctx, const double* b, double* u, double rtol, int32_
                      L0.dinv, L0.binv, L0.scal, L0.x, L0.r, L0.d, g->cpart);
   hipLaunchKernelGGL(k_mgcg_start_scal, dim3(1), dim3(256), 0, ctx->stream, g->cpart, g->cs, tol2);
   AMRTO_HIP(hipGetLastError());
-  int it = 0, status = AMRTO_NOT_CONVERGED;
+  // every check drains the stream, so runs between checks grow with the
+  // predicted distance to the target (next_batch); iterations queued past
+  // convergence still run their V-cycle but leave u and the CG state as they
+  // are (the CG kernels test the device's finished flag)
+  int it = 0, last = 0, status = AMRTO_NOT_CONVERGED;
+  double rr0 = 0.0, rr_prev = 0.0;
   while (true) {
     AMRTO_HIP(hipMemcpyAsync(g->h_cg, g->cs, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     AMRTO_HIP(hipStreamSynchronize(ctx->stream));
@@ -1779,7 +1784,11 @@ int amrto_mg_pcg(amrto_ctx* ctx, const double* b, double* u, double rtol, int32_
       break;
     }
     if (it >= max_it) break;
-    const int batch = std::min(check_every, max_it - it);
+    const double rr = g->h_cg[S_RR];
+    if (it == 0) rr0 = rr;
+    const int batch = next_batch(rr0, rr_prev, rr, it, last, tol2 * g->h_cg[S_BB], check_every, max_it - it);
+    rr_prev = rr;
+    last = batch;
     for (int k = it; k < it + batch; ++k) {
       // z = V-cycle(r); p = z + beta p_old, q = A~ p and p.q in one fused pass; update
       if ((rc = vcycle_from(ctx, 0))) return rc;

@@ -1043,8 +1043,8 @@ int apply_precond(amrto_ctx* ctx, const double* s, double* u, bool block3, bool 
 // the residual still needs to reach `target`, at the faster of its mean rate
 // since rr0 (its iterations ago) and its rate over the last batch (log r.r
 // falls about linearly in CG), between check_every and 8 check_every.
-static int next_batch(double rr0, double rr_prev, double rr, int its, int last, double target, int check_every,
-                      int left) {
+int next_batch(double rr0, double rr_prev, double rr, int its, int last, double target, int check_every,
+               int left) {
   int n = check_every;
   if (its > 0 && last > 0 && rr0 > 0.0 && rr_prev > 0.0 && target > 0.0 && rr > target && rr < rr0) {
     double rate = std::log(rr / rr0) / its;
