@@ -275,3 +275,31 @@ def test_vcycle_deterministic_symmetric_at_full_size(first, coarse):
     u = torch.zeros_like(b)
     st = ctx.mg_pcg(b, u, rtol=1e-8, max_it=400, check_every=4)
     assert st["status"] == "OK" and st["iters"] <= 110, st
+
+
+def test_mg_pcg_result_independent_of_check_interval():
+    """How often the host reads the convergence state (runs of iterations
+    sized from the residual's rate, between check_every and 8 check_every)
+    changes only how many iterations are queued past convergence, and those
+    leave u and the CG state as they were: on the full-size octree, in
+    deterministic mode, every interval gives the same iteration count and the
+    same solution bit for bit."""
+    t, mesh, rho = _c2_library_only()
+    ctx = binding.Context(0)
+    ctx.upload_mesh(mesh)
+    ctx.set_deterministic(True)
+    ctx.set_density(_t(rho))
+    ctx.mg_setup(t, first=2, ratio=50.0, degree=1, coarse_degree=2, coarse_dofs=700)
+    f = _t(mesh.f_load)
+    b = torch.empty_like(f)
+    ctx.project_rhs(f, b)
+    runs = {}
+    for ce in (1, 2, 5, 64):
+        u = torch.zeros_like(b)
+        st = ctx.mg_pcg(b, u, rtol=1e-8, max_it=400, check_every=ce)
+        assert st["status"] == "OK" and st["rel_res"] <= 1e-8, (ce, st)
+        runs[ce] = (st["iters"], u)
+    its = {ce: r[0] for ce, r in runs.items()}
+    assert len(set(its.values())) == 1, its
+    for ce in (2, 5, 64):
+        assert torch.equal(runs[ce][1], runs[1][1]), ce
