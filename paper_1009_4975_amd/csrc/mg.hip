@@ -492,19 +492,22 @@ __global__ __launch_bounds__(256) void k_mg_galerkin(const int32_t* __restrict__
                                                      const int32_t* __restrict__ pure_f,
                                                      const double* __restrict__ coef, const double* __restrict__ K0,
                                                      double* __restrict__ Kd) {
-  __shared__ double Kc[576], T1[576];
+  __shared__ double Kc[576], T1[576], Pw[64];
   const int e = blockIdx.x;
   if (e >= nd) return;
   double acc[3] = {0.0, 0.0, 0.0};
   for (int k = cptr[e]; k < cptr[e + 1]; ++k) {
     const int ch = celem[k], o = coct[k];
     __syncthreads();
+    // the child's matrix (stored transposed: read in order, placed by the
+    // transpose) and its 8 x 8 corner weights Pw[a2][a] = mg_pw(o, a2, a)
     if (ch < nd_f) {
-      for (int i = threadIdx.x; i < 576; i += blockDim.x) Kc[i] = Kd_f[576L * ch + (i % 24) * 24 + i / 24];
+      for (int j = threadIdx.x; j < 576; j += blockDim.x) Kc[(j % 24) * 24 + j / 24] = Kd_f[576L * ch + j];
     } else {
       const double c = coef[pure_f[ch - nd_f]];
       for (int i = threadIdx.x; i < 576; i += blockDim.x) Kc[i] = c * K0[i];
     }
+    if (o != 0 && threadIdx.x < 64) Pw[threadIdx.x] = mg_pw(o, threadIdx.x >> 3, threadIdx.x & 7);
     __syncthreads();
     if (o == 0) {  // the same box
       for (int i = threadIdx.x, t = 0; i < 576; i += blockDim.x, ++t) acc[t] += Kc[i];
@@ -514,7 +517,7 @@ __global__ __launch_bounds__(256) void k_mg_galerkin(const int32_t* __restrict__
     for (int i = threadIdx.x; i < 576; i += blockDim.x) {
       const int row = i / 24, col = i % 24, b = col / 3, dd = col % 3;
       double s = 0.0;
-      for (int b2 = 0; b2 < 8; ++b2) s = fma(Kc[row * 24 + 3 * b2 + dd], mg_pw(o, b2, b), s);
+      for (int b2 = 0; b2 < 8; ++b2) s = fma(Kc[row * 24 + 3 * b2 + dd], Pw[b2 * 8 + b], s);
       T1[i] = s;
     }
     __syncthreads();
@@ -522,7 +525,7 @@ __global__ __launch_bounds__(256) void k_mg_galerkin(const int32_t* __restrict__
     for (int i = threadIdx.x, t = 0; i < 576; i += blockDim.x, ++t) {
       const int row = i / 24, col = i % 24, a = row / 3, c = row % 3;
       double s = 0.0;
-      for (int a2 = 0; a2 < 8; ++a2) s = fma(mg_pw(o, a2, a), T1[(3 * a2 + c) * 24 + col], s);
+      for (int a2 = 0; a2 < 8; ++a2) s = fma(Pw[a2 * 8 + a], T1[(3 * a2 + c) * 24 + col], s);
       acc[t] += s;
     }
   }
