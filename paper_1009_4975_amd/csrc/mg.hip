@@ -81,6 +81,11 @@ struct MgData {
   double *z = nullptr, *p = nullptr, *z2 = nullptr, *qv = nullptr;  // PCG vectors (p and z2: direction pair)
   double* cpart = nullptr;  // 2 x RED_BLOCKS partials of the fused CG
   double* cs = nullptr;     // S_COUNT scalars of the fused CG
+  // P_o^T K0 P_o for every placement code o (256 x 576, row-major), the
+  // Galerkin matrix of a unit-coefficient leaf placed by o; built for the
+  // Poisson ratio in G_nu
+  double* G = nullptr;
+  double G_nu = -2.0;
   std::vector<void*> owned;
 };
 
@@ -483,14 +488,42 @@ __device__ __forceinline__ double mg_pw(int code, int a2, int a) {
   return w;
 }
 
+// (P_o (x) I3)^T K0 (P_o (x) I3) for the placement code o = blockIdx.x (codes
+// that place no child, a ratio field of 3 or an offset beyond the ratio, give
+// zeros); the same two products as k_mg_galerkin
+__global__ __launch_bounds__(256) void k_mg_gtable(const double* __restrict__ K0, double* __restrict__ G) {
+  __shared__ double Kc[576], T1[576], Pw[64];
+  const int o = blockIdx.x, r = 1 << (o & 3);
+  bool valid = (o & 3) != 3;
+  for (int ax = 0; ax < 3; ++ax) valid = valid && ((o >> (2 + 2 * ax)) & 3) < r;
+  for (int i = threadIdx.x; i < 576; i += blockDim.x) Kc[i] = K0[i];
+  if (threadIdx.x < 64) Pw[threadIdx.x] = mg_pw(o, threadIdx.x >> 3, threadIdx.x & 7);
+  __syncthreads();
+  for (int i = threadIdx.x; i < 576; i += blockDim.x) {
+    const int row = i / 24, col = i % 24, b = col / 3, dd = col % 3;
+    double s = 0.0;
+    for (int b2 = 0; b2 < 8; ++b2) s = fma(Kc[row * 24 + 3 * b2 + dd], Pw[b2 * 8 + b], s);
+    T1[i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 576; i += blockDim.x) {
+    const int row = i / 24, col = i % 24, a = row / 3, c = row % 3;
+    double s = 0.0;
+    for (int a2 = 0; a2 < 8; ++a2) s = fma(Pw[a2 * 8 + a], T1[(3 * a2 + c) * 24 + col], s);
+    G[576L * o + i] = valid ? s : 0.0;
+  }
+}
+
 // dense Galerkin matrix of each merged element: sum over children j of
-// (P_j (x) I3)^T K_j (P_j (x) I3); K_j dense (previous level) or c K0
+// (P_j (x) I3)^T K_j (P_j (x) I3); K_j dense (previous level) or, for a leaf
+// of the finer level, c_j K0, whose product is c_j times the tabulated
+// P^T K0 P of its placement
 __global__ __launch_bounds__(256) void k_mg_galerkin(const int32_t* __restrict__ cptr,
                                                      const int32_t* __restrict__ celem,
                                                      const uint8_t* __restrict__ coct, int nd,
                                                      const double* __restrict__ Kd_f, int nd_f,
                                                      const int32_t* __restrict__ pure_f,
-                                                     const double* __restrict__ coef, const double* __restrict__ K0,
+                                                     const double* __restrict__ coef, const double* __restrict__ G,
                                                      double* __restrict__ Kd) {
   __shared__ double Kc[576], T1[576], Pw[64];
   const int e = blockIdx.x;
@@ -498,15 +531,15 @@ __global__ __launch_bounds__(256) void k_mg_galerkin(const int32_t* __restrict__
   double acc[3] = {0.0, 0.0, 0.0};
   for (int k = cptr[e]; k < cptr[e + 1]; ++k) {
     const int ch = celem[k], o = coct[k];
+    if (ch >= nd_f) {  // a leaf: no shared memory, the same for every thread
+      const double c = coef[pure_f[ch - nd_f]];
+      for (int i = threadIdx.x, t = 0; i < 576; i += blockDim.x, ++t) acc[t] += c * G[576L * o + i];
+      continue;
+    }
     __syncthreads();
     // the child's matrix (stored transposed: read in order, placed by the
     // transpose) and its 8 x 8 corner weights Pw[a2][a] = mg_pw(o, a2, a)
-    if (ch < nd_f) {
-      for (int j = threadIdx.x; j < 576; j += blockDim.x) Kc[(j % 24) * 24 + j / 24] = Kd_f[576L * ch + j];
-    } else {
-      const double c = coef[pure_f[ch - nd_f]];
-      for (int i = threadIdx.x; i < 576; i += blockDim.x) Kc[i] = c * K0[i];
-    }
+    for (int j = threadIdx.x; j < 576; j += blockDim.x) Kc[(j % 24) * 24 + j / 24] = Kd_f[576L * ch + j];
     if (o != 0 && threadIdx.x < 64) Pw[threadIdx.x] = mg_pw(o, threadIdx.x >> 3, threadIdx.x & 7);
     __syncthreads();
     if (o == 0) {  // the same box
@@ -1153,12 +1186,16 @@ int mg_numeric(amrto_ctx* ctx) {
     if (rc) return rc;
     g->lv[0].binv = ctx->d_binv;
   }
+  if (g->G_nu != ctx->nu) {  // K0 changes with the Poisson ratio only
+    hipLaunchKernelGGL(k_mg_gtable, dim3(256), dim3(256), 0, ctx->stream, ctx->d_K0, g->G);
+    g->G_nu = ctx->nu;
+  }
   for (int k = 1; k < g->nlev; ++k) {
     MgLevel& L = g->lv[k];
     MgLevel& F = g->lv[k - 1];
     if (L.nd > 0)
       hipLaunchKernelGGL(k_mg_galerkin, dim3(L.nd), dim3(256), 0, ctx->stream, L.cptr, L.celem, L.coct, L.nd, F.Kd,
-                         F.nd, F.pure_src, ctx->d_coef, ctx->d_K0, L.Kd);
+                         F.nd, F.pure_src, ctx->d_coef, g->G, L.Kd);
     hipLaunchKernelGGL(k_mg_bsr_values, dim3(blocks_for(L.nnzb)), dim3(256), 0, ctx->stream, L.kptr, L.ke, L.kab,
                        L.kw, L.bcol, L.flag, L.Kd, L.nd, L.pure_src, ctx->d_coef, ctx->d_K0, L.bval, L.nnzb);
     hipLaunchKernelGGL(k_mg_bsr_diag, dim3(blocks_for(L.nn)), dim3(256), 0, ctx->stream, L.bdiag, L.bval, L.flag,
@@ -1590,6 +1627,7 @@ int amrto_mg_setup(amrto_ctx* ctx, const amrto_octree* tree, const amrto_mg_opts
       mg_alloc(g->owned, g->z, n0) != hipSuccess || mg_alloc(g->owned, g->p, n0) != hipSuccess ||
       mg_alloc(g->owned, g->qv, n0) != hipSuccess || mg_alloc(g->owned, g->z2, n0) != hipSuccess ||
       mg_alloc(g->owned, g->cpart, 2 * RED_BLOCKS) != hipSuccess || mg_alloc(g->owned, g->cs, S_COUNT) != hipSuccess ||
+      mg_alloc(g->owned, g->G, 256L * 576) != hipSuccess ||
       hipHostMalloc((void**)&g->h_cg, std::max<int>(MC_COUNT, S_COUNT) * sizeof(double)) != hipSuccess) {
     mg_free(ctx);
     return ctx->fail(AMRTO_ENOMEM, "amrto_mg_setup: out of device memory");
