@@ -303,3 +303,38 @@ def test_mg_pcg_result_independent_of_check_interval():
     assert len(set(its.values())) == 1, its
     for ce in (2, 5, 64):
         assert torch.equal(runs[ce][1], runs[1][1]), ce
+
+
+def test_level_operators_follow_a_material_change():
+    """The Galerkin set-up takes a leaf's product from a table of P^T K0 P per
+    placement, and K0 depends on the Poisson ratio: after set_material the
+    coarse operators must be those of the new ratio (equal, bit for bit, to a
+    context built with it from the start), not the old table's."""
+    p = octree_pair((8, 4, 4), 2)
+    rho = _t(p.to_lib_elems(np.clip(centre_density(p, p.case["field"]), 0.05, 1.0)))
+
+    def build(nu_first, nu_then=None):
+        ctx = binding.Context(0)
+        ctx.set_material(nu=nu_first)
+        ctx.upload_mesh(p.lib_mesh)
+        ctx.set_density(rho)
+        ctx.mg_setup(p.case["tree"], coarse_dofs=COARSE, first=2)
+        if nu_then is not None:
+            x = _t(np.random.default_rng(4).standard_normal(ctx.mg_info()["dofs"][1]))
+            y_old = torch.empty_like(x)
+            ctx.mg_level_apply(1, x, y_old)
+            ctx.set_material(nu=nu_then)
+            ctx.set_density(rho)
+            return ctx, y_old
+        return ctx, None
+
+    changed, y_old = build(0.3, 0.25)
+    fresh, _ = build(0.25)
+    for k in range(1, len(fresh.mg_info()["dofs"]) - 1):
+        x = _t(np.random.default_rng(4 + k).standard_normal(fresh.mg_info()["dofs"][k]))
+        ya, yb = torch.empty_like(x), torch.empty_like(x)
+        changed.mg_level_apply(k, x, ya)
+        fresh.mg_level_apply(k, x, yb)
+        assert torch.equal(ya, yb), k
+        if k == 1:
+            assert not torch.equal(ya, y_old)
