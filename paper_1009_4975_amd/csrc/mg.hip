@@ -86,6 +86,10 @@ struct MgData {
   // Poisson ratio in G_nu
   double* G = nullptr;
   double G_nu = -2.0;
+  // the coarsest inverse runs beside the power iterations: a second stream
+  // (default priority) forked from and joined to the context's by events
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<void*> owned;
 };
 
@@ -1202,6 +1206,17 @@ int mg_numeric(amrto_ctx* ctx) {
                        L.dinv, L.nn);
   }
   if (hipGetLastError() != hipSuccess) return ctx->fail(AMRTO_EHIP, "multigrid Galerkin set-up");
+  // the coarsest level's dense matrix and its inverse need only its block
+  // rows: they run on the second stream while the power iterations below
+  // (smoothed levels only) run on the context's
+  MgLevel& C = g->lv[g->nlev - 1];
+  const int n = 3 * C.nn;
+  AMRTO_HIP(hipEventRecord(g->ev_fork, ctx->stream));
+  AMRTO_HIP(hipStreamWaitEvent(g->aux, g->ev_fork, 0));
+  hipLaunchKernelGGL(k_mg_coarse_assemble, dim3(C.nn), dim3(256), 0, g->aux, C.bptr, C.bcol, C.bval, C.flag,
+                     C.nn, C.Ainv);
+  bgj_invert(g->aux, C.Ainv, n);
+  AMRTO_HIP(hipEventRecord(g->ev_join, g->aux));
   // lambda_max of D^-1 A on every smoothed level by power iteration
   for (int k = 0; k < g->nlev - 1; ++k) {
     MgLevel& L = g->lv[k];
@@ -1222,11 +1237,7 @@ int mg_numeric(amrto_ctx* ctx) {
     hipLaunchKernelGGL(k_mg_lambda, dim3(1), dim3(256), 0, ctx->stream, g->part, L.scal,
                        g->user_bounds ? g->lam_user[k] : 0.0, g->hi_factor, g->ratio);
   }
-  MgLevel& C = g->lv[g->nlev - 1];
-  const int n = 3 * C.nn;
-  hipLaunchKernelGGL(k_mg_coarse_assemble, dim3(C.nn), dim3(256), 0, ctx->stream, C.bptr, C.bcol, C.bval, C.flag,
-                     C.nn, C.Ainv);
-  bgj_invert(ctx->stream, C.Ainv, n);
+  AMRTO_HIP(hipStreamWaitEvent(ctx->stream, g->ev_join, 0));
   if (hipGetLastError() != hipSuccess) return ctx->fail(AMRTO_EHIP, "multigrid coarse set-up");
   ctx->mg_valid = true;
   return AMRTO_OK;
@@ -1243,6 +1254,9 @@ void mg_free(amrto_ctx* ctx) {
     for (void* p : g->lv[k].owned) (void)hipFree(p);
   for (void* p : g->owned) (void)hipFree(p);
   if (g->h_cg) (void)hipHostFree(g->h_cg);
+  if (g->ev_fork) (void)hipEventDestroy(g->ev_fork);
+  if (g->ev_join) (void)hipEventDestroy(g->ev_join);
+  if (g->aux) (void)hipStreamDestroy(g->aux);
   delete g;
   ctx->mg = nullptr;
   ctx->mg_valid = false;
@@ -1628,6 +1642,9 @@ int amrto_mg_setup(amrto_ctx* ctx, const amrto_octree* tree, const amrto_mg_opts
       mg_alloc(g->owned, g->qv, n0) != hipSuccess || mg_alloc(g->owned, g->z2, n0) != hipSuccess ||
       mg_alloc(g->owned, g->cpart, 2 * RED_BLOCKS) != hipSuccess || mg_alloc(g->owned, g->cs, S_COUNT) != hipSuccess ||
       mg_alloc(g->owned, g->G, 256L * 576) != hipSuccess ||
+      hipStreamCreateWithFlags(&g->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming) != hipSuccess ||
       hipHostMalloc((void**)&g->h_cg, std::max<int>(MC_COUNT, S_COUNT) * sizeof(double)) != hipSuccess) {
     mg_free(ctx);
     return ctx->fail(AMRTO_ENOMEM, "amrto_mg_setup: out of device memory");
